@@ -1,0 +1,128 @@
+"""Linear-method matrices, energy centring, eigenproblem and update (dense FP64).
+
+Methods, "From SR to a Stable Eigenvalue Problem":
+
+* tangent basis chi_0 = psi, chi_i = d psi / d theta_i; H~_ij = <chi_i|H|chi_j>,
+  S~_ij = <chi_i|chi_j> (Eq. rayleigh_quotient), both (p+1) x (p+1);
+* normalisation <psi|psi> = 1, realised here by D^ = D~ / sqrt(Z), Z = psi^T psi;
+* energy E = psi^T H psi / Z; centred operator H' = H - E;
+* H_eff = <d psi|H'|d psi> (Eq. heff) and the standard Hermitian problem
+  H_eff v = lambda v obtained from S ~ I (Eq. standard_evp);
+* the full problem H~ c = lambda S~ c (Eq. full_gevp) with c = [1, v].
+
+Readings (the paper is not explicit):
+* mode "A" (default): the S ~ I problem on the (p+1)-dimensional centred matrix
+  H~' = H~ - E S~ = [[0, g^T / 2], [g / 2, H_eff]] (identity metric); the lowest
+  eigenpair (lambda, c) gives the update dtheta = c[1:] / c[0], the reading of
+  c = [1, v] under which the eigenvector alone fixes direction and length.
+* mode "P": the literal p x p problem H_eff v = lambda v; direction only
+  (step length parity unpinned).
+* mode "G": the exact generalised problem H~' c = lambda S~ c, solved after
+  canonical orthogonalisation of S~.
+
+Pins: tests/test_oracle_lm.py (identities, D~ = I reduction to exact
+diagonalisation, zero update at an exact wavefunction, exact GEVP, ARPACK's
+implicitly restarted Lanczos, finite-difference gradient, predicted decrease).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+import scipy.linalg as sla
+import scipy.sparse as sp
+
+
+def exact_sum(x: np.ndarray) -> float:
+    """Correctly rounded sum (math.fsum)."""
+    return math.fsum(np.asarray(x, dtype=np.float64).tolist())
+
+
+def energy(psi: np.ndarray, Hmat: sp.spmatrix, e_core: float = 0.0):
+    """(Z, E_el, E) with Z = psi^T psi and E_el = psi^T H psi / Z (electronic),
+    E = E_el + e_core.  Sums are correctly rounded."""
+    r = Hmat @ psi
+    Z = exact_sum(psi * psi)
+    E_el = exact_sum(psi * r) / Z
+    return Z, E_el, E_el + e_core
+
+
+def gradient(Dt: np.ndarray, Hmat: sp.spmatrix) -> np.ndarray:
+    """g = dE/dtheta = 2 J^T (H psi - E psi) / Z (real wavefunction)."""
+    psi = Dt[:, 0]
+    Z, E_el, _ = energy(psi, Hmat)
+    r = Hmat @ psi
+    return 2.0 * (Dt[:, 1:].T @ (r - E_el * psi)) / Z
+
+
+def apply_lm_operator(Dt: np.ndarray, Hmat: sp.spmatrix, v: np.ndarray):
+    """Raw, unnormalised operator pair for one vector (matrix-free):
+    y_H = D~^T H D~ v, y_S = D~^T D~ v."""
+    w = Dt @ v
+    u = Hmat @ w
+    return Dt.T @ u, Dt.T @ w
+
+
+def dense_matrices(Dt: np.ndarray, Hmat: sp.spmatrix):
+    """Normalised H~ = D^T H D^, S~ = D^T D^ with D^ = D~ / sqrt(Z)."""
+    psi = Dt[:, 0]
+    Z = exact_sum(psi * psi)
+    Dh = Dt / math.sqrt(Z)
+    St = Dh.T @ Dh
+    Ht = Dh.T @ np.asarray(Hmat @ Dh)
+    return Ht, St
+
+
+def centred(Ht: np.ndarray, St: np.ndarray, E_el: float) -> np.ndarray:
+    """H~' = H~ - E S~, symmetrised."""
+    Hp = Ht - E_el * St
+    return 0.5 * (Hp + Hp.T)
+
+
+@dataclass
+class LMResult:
+    E: float            # energy at theta (including e_core)
+    E_el: float
+    Z: float
+    lam: float          # lowest eigenvalue of the chosen problem
+    c: np.ndarray       # its eigenvector (unit norm, or S-normalised in mode G)
+    dtheta: np.ndarray | None
+    gap: float          # lambda_2 - lambda_1
+    Hp: np.ndarray      # the centred matrix H~'
+    St: np.ndarray
+
+
+def solve(Dt: np.ndarray, Hmat: sp.spmatrix, mode: str = "A", e_core: float = 0.0,
+          s_cut: float = 1e-12) -> LMResult:
+    """Dense solve of the LM eigenproblem for the basis D~ (N_s x (p+1))."""
+    psi = Dt[:, 0]
+    Z, E_el, E = energy(psi, Hmat, e_core)
+    Ht, St = dense_matrices(Dt, Hmat)
+    Hp = centred(Ht, St, E_el)
+    if mode == "A":
+        w, U = np.linalg.eigh(Hp)
+        c = U[:, 0]
+        dtheta = c[1:] / c[0]
+        gap = w[1] - w[0] if w.size > 1 else np.inf
+        return LMResult(E, E_el, Z, w[0], c, dtheta, gap, Hp, St)
+    if mode == "P":
+        w, U = np.linalg.eigh(Hp[1:, 1:])
+        gap = w[1] - w[0] if w.size > 1 else np.inf
+        return LMResult(E, E_el, Z, w[0], U[:, 0], None, gap, Hp, St)
+    if mode == "G":
+        s, Us = np.linalg.eigh(0.5 * (St + St.T))
+        keep = s > s_cut * s.max()
+        X = Us[:, keep] / np.sqrt(s[keep])       # canonical orthogonalisation
+        w, Y = np.linalg.eigh(X.T @ Hp @ X)
+        c = X @ Y[:, 0]
+        dtheta = c[1:] / c[0]
+        gap = w[1] - w[0] if w.size > 1 else np.inf
+        return LMResult(E, E_el, Z, w[0], c, dtheta, gap, Hp, St)
+    raise ValueError(mode)
+
+
+def eigh_lowest(A: np.ndarray):
+    """Lowest eigenpair of a dense symmetric matrix (scipy)."""
+    w, U = sla.eigh(A, subset_by_index=[0, 0])
+    return w[0], U[:, 0]

@@ -1,0 +1,154 @@
+"""Pins for the oracle's LM matrices, centring, eigenproblem and update.
+
+* operator identities of the raw pair (y_H, y_S);
+* D~ = I reduces H~ to the Hamiltonian: mode A gives lambda + E = E_exact;
+* an exact eigenvector as psi gives g = 0, lambda = 0, dtheta = 0;
+* a square full-rank D~ makes the generalised problem exact: lambda + E = E_exact;
+* ARPACK's implicitly restarted Lanczos (scipy eigsh) on H~' gives the same
+  lowest eigenvalue as the dense solver;
+* g = 2 H~'[1:, 0] equals a central finite difference of E(theta);
+* mode G's lambda equals E_new - E for the linearised wavefunction;
+* planted mistakes (no centring) are caught.
+"""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+import synth
+from oracle import hamiltonian, lm, nqs, space, step
+
+
+@pytest.fixture(scope="module")
+def small():
+    n, na, nb, V, H = 6, 3, 3, 12, 8
+    h, g = synth.integrals(n, 1)
+    keys = space.full_space(n, na, nb)
+    Hm = hamiltonian.build(keys, n, h, g)
+    theta = synth.nqs_theta(V, H, 1, scale=0.3)
+    Dt = nqs.dtilde(keys, n, V, H, theta)
+    e_exact, psi0 = np.linalg.eigh(Hm.toarray())
+    return dict(n=n, V=V, H=H, keys=keys, Hm=Hm, theta=theta, Dt=Dt, e=e_exact, psi0=psi0[:, 0])
+
+
+def test_operator_identities(small):
+    Dt, Hm = small["Dt"], small["Hm"]
+    rng = np.random.default_rng(0)
+    v, u = rng.normal(size=Dt.shape[1]), rng.normal(size=Dt.shape[1])
+    yH, yS = lm.apply_lm_operator(Dt, Hm, v)
+    uH, uS = lm.apply_lm_operator(Dt, Hm, u)
+    assert abs(v @ yS - np.linalg.norm(Dt @ v) ** 2) < 1e-10 * abs(v @ yS)
+    assert abs(u @ yH - v @ uH) < 1e-10 * abs(u @ yH)
+    e0 = np.zeros(Dt.shape[1])
+    e0[0] = 1.0
+    yH, yS = lm.apply_lm_operator(Dt, Hm, e0)
+    Z, E_el, _ = lm.energy(Dt[:, 0], Hm)
+    assert abs(yS[0] - Z) < 1e-12 * Z
+    assert abs(yH[0] / yS[0] - E_el) < 1e-12
+
+
+def test_identity_dtilde_reduces_to_ed(small):
+    Hm, e = small["Hm"], small["e"]
+    N = Hm.shape[0]
+    Dt = np.eye(N)
+    Ht, St = lm.dense_matrices(Dt, Hm)
+    assert np.array_equal(St, np.eye(N))
+    assert np.max(np.abs(Ht - Hm.toarray())) < 1e-14
+    res = lm.solve(Dt, Hm, mode="A")
+    assert abs(res.E - Hm[0, 0]) < 1e-14
+    assert abs(res.lam + res.E - e[0]) < 1e-11
+
+
+def test_exact_psi_gives_zero_update(small):
+    Hm, psi0 = small["Hm"], small["psi0"]
+    rng = np.random.default_rng(3)
+    Dt = np.concatenate([psi0[:, None], rng.normal(size=(psi0.size, 40))], axis=1)
+    Ht, St = lm.dense_matrices(Dt, Hm)
+    Z, E_el, _ = lm.energy(psi0, Hm)
+    g = 2.0 * lm.centred(Ht, St, E_el)[1:, 0]
+    assert np.max(np.abs(g)) < 1e-12
+    assert np.max(np.abs(lm.gradient(Dt, Hm))) < 1e-12
+    res = lm.solve(Dt, Hm, mode="A")
+    assert abs(res.lam) < 1e-12
+    assert np.max(np.abs(res.dtheta)) < 1e-12
+
+
+def test_planted_missing_centring_is_caught(small, monkeypatch):
+    monkeypatch.setattr(lm, "centred", lambda Ht, St, E: 0.5 * (Ht + Ht.T))
+    Hm, psi0 = small["Hm"], small["psi0"]
+    rng = np.random.default_rng(3)
+    Dt = np.concatenate([psi0[:, None], rng.normal(size=(psi0.size, 40))], axis=1)
+    res = lm.solve(Dt, Hm, mode="A")
+    assert abs(res.lam) > 1e-3
+
+
+def test_square_full_rank_generalised_is_exact(small):
+    Hm, e = small["Hm"], small["e"]
+    N = Hm.shape[0]
+    rng = np.random.default_rng(4)
+    Dt = rng.normal(size=(N, N))
+    res = lm.solve(Dt, Hm, mode="G")
+    assert abs(res.lam + res.E - e[0]) < 1e-9
+
+
+def test_arpack_irl_agrees_with_dense(small):
+    res = lm.solve(small["Dt"], small["Hm"], mode="A")
+    Hp = res.Hp
+    op = spla.LinearOperator(Hp.shape, matvec=lambda x: Hp @ x, dtype=np.float64)
+    lam = spla.eigsh(op, k=1, which="SA", ncv=20, tol=1e-13)[0][0]
+    assert abs(lam - res.lam) <= 1e-10 * max(abs(res.lam), np.linalg.norm(Hp, 2))
+
+
+def test_gradient_matches_finite_difference(small):
+    n, V, H, keys, Hm, theta = (small[k] for k in ("n", "V", "H", "keys", "Hm", "theta"))
+    res = lm.solve(small["Dt"], Hm, mode="A")
+    g = 2.0 * res.Hp[1:, 0]
+    assert np.allclose(g, lm.gradient(small["Dt"], Hm), rtol=0, atol=1e-12 * np.abs(g).max())
+
+    def E(t):
+        psi, _ = nqs.psi_and_jacobian(keys, n, V, H, t)
+        return lm.energy(psi, Hm)[2]
+
+    hstep = 1e-5
+    for i in list(range(0, theta.size, 7)) + [theta.size - 1]:
+        tp, tm = theta.copy(), theta.copy()
+        tp[i] += hstep
+        tm[i] -= hstep
+        fd = (E(tp) - E(tm)) / (2 * hstep)
+        assert abs(fd - g[i]) <= 1e-7 * max(1.0, np.abs(g).max())
+
+
+def test_generalised_lambda_is_predicted_decrease(small):
+    Dt, Hm = small["Dt"], small["Hm"]
+    res = lm.solve(Dt, Hm, mode="G")
+    psi_new = Dt[:, 0] + Dt[:, 1:] @ res.dtheta
+    _, E_new, _ = lm.energy(psi_new, Hm)
+    assert abs(res.lam - (E_new - res.E)) < 1e-9
+
+
+def test_mode_a_is_augmented_hessian_step(small):
+    res = lm.solve(small["Dt"], small["Hm"], mode="A")
+    Heff, g = res.Hp[1:, 1:], 2.0 * res.Hp[1:, 0]
+    v = res.dtheta
+    assert abs(res.lam - 0.5 * g @ v) < 1e-9 * max(1.0, abs(res.lam))
+    r = Heff @ v - res.lam * v + 0.5 * g
+    assert np.linalg.norm(r) < 1e-8 * max(1.0, np.linalg.norm(Heff @ v))
+    assert res.lam <= 1e-14                   # c = e_0 gives 0, so the minimum is <= 0
+
+
+def test_mode_p_is_heff_lowest(small):
+    res = lm.solve(small["Dt"], small["Hm"], mode="P")
+    resA = lm.solve(small["Dt"], small["Hm"], mode="A")
+    assert abs(res.lam - np.linalg.eigvalsh(resA.Hp[1:, 1:])[0]) < 1e-12 * np.linalg.norm(resA.Hp)
+    # interlacing: the bordered matrix's lowest eigenvalue is below H_eff's
+    assert resA.lam <= res.lam + 1e-12
+
+
+def test_c1_step_runs(c1_problem):
+    p = c1_problem
+    w = p["w"]
+    res, th_new, E_after = step.lm_step(p["keys"], w.n, w.V, w.H, p["theta"], p["H"])
+    assert res.Hp.shape == (w.P + 1, w.P + 1)
+    assert np.max(np.abs(res.Hp - res.Hp.T)) == 0.0
+    s = np.linalg.eigvalsh(res.St)
+    assert s[0] >= -1e-12 * s[-1]                  # S~ is positive semidefinite
+    assert np.isfinite(E_after)
