@@ -1,0 +1,269 @@
+#!/usr/bin/env python3
+"""Benchmark of the IRL optimisation step on one MI355X.
+
+Workload (default): 12 spatial orbitals, 6 alpha + 6 beta electrons, the full
+853,776-determinant space; random molecule-like integrals (seed 0); network
+V = 24, H = 64 (P = 1624), so D~ is 853,776 x 1625 FP64 (11.1 GB); Krylov
+dimension 40, 10 vectors kept per restart, tolerance 1e-12; FP64.
+
+A timed step is one optimisation step: network evaluation (D~, Z, E,
+gradient), the implicitly restarted Lanczos solve (operator applies,
+recurrence, restarts) and the parameter update.  W warm-up steps run from
+theta_0; theta is then reset to theta_0 and K steps are timed, so the timed
+region is the first K steps of the trajectory.  Inputs are resident in HBM
+before timing starts.
+
+Prints one JSON line (stdout); progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+METRIC = "time per IRL step & operator HBM GB/s vs roofline; solves/s, p99 step latency"
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_bytes(kind, ns, ncols, sD):
+    """Algorithmic HBM bytes of one launch (reads + writes the kernel must do)."""
+    if kind == "gemv":        # read D~, read v, write w
+        return ns * ncols * sD + ncols * 8 + ns * 8
+    if kind == "gemv_t":      # read D~, read the two row vectors
+        return ns * ncols * sD + 2 * ns * 8
+    if kind == "dtilde_build":  # write D~ (and psi)
+        return ns * ncols * sD + ns * 8
+    return None
+
+
+def source_hash(paths):
+    h = hashlib.sha256()
+    for p in paths:
+        h.update(open(p, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(kernel, workload, src_hash):
+    """HBM traffic per launch from a committed rocprofv3 counter summary, if it
+    was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_counters.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m_hash = re.search(r"source_hash:\s*([0-9a-f]+)", text)
+    m_val = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not m_hash or not m_val or m_hash.group(1) != src_hash:
+        return None
+    return float(m_val.group(1))
+
+
+def cpu_baseline(wl, keys_fn, applies_per_step, sample_rows=100_000, chunk=20_000):
+    """The oracle's matrix-free apply (oracle.nqs rows, oracle C Slater-Condon
+    rows, numpy products) timed on a row sample and scaled to one step."""
+    import numpy as np
+
+    from oracle import capply, nqs
+    keys = keys_fn()
+    ns = keys.size
+    h, g = wl.integrals()
+    theta = wl.theta()
+    rng = np.random.default_rng(0)
+    rows = np.sort(rng.choice(ns, size=min(sample_rows, ns), replace=False))
+    v = rng.normal(size=wl.P + 1)
+    wfull = rng.normal(size=ns)       # Slater-Condon cost does not depend on w's values
+    t_build = t_dv = t_h = t_dt = 0.0
+    for c0 in range(0, rows.size, chunk):
+        rs = rows[c0:c0 + chunk]
+        t = time.perf_counter()
+        D = nqs.dtilde(keys[rs], wl.n, wl.V, wl.H, theta)
+        t_build += time.perf_counter() - t
+        t = time.perf_counter()
+        w = D @ v
+        t_dv += time.perf_counter() - t
+        t = time.perf_counter()
+        u = capply.apply(wl.n, h, g, keys, wfull, rows=rs)
+        t_h += time.perf_counter() - t
+        t = time.perf_counter()
+        _ = D.T @ np.stack([w, u], axis=1)
+        t_dt += time.perf_counter() - t
+        del D
+    scale = ns / rows.size
+    per_apply = (t_dv + t_h + t_dt) * scale
+    per_eval = (t_build + t_h + t_dt) * scale          # D~, H psi, gradient pass
+    per_step = applies_per_step * per_apply + per_eval
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {
+        "value": 1.0 / per_step,
+        "unit": "IRL steps/s",
+        "cores": cores,
+        "kind": "oracle",
+        "sample": (f"{rows.size} of {ns} rows: oracle network rows, oracle C Slater-Condon rows "
+                   f"and numpy D~ products timed ({t_build + t_dv + t_h + t_dt:.1f} s) and scaled "
+                   f"by {scale:.2f} to {applies_per_step:.1f} operator applies + 1 evaluation "
+                   f"per step (apply count from the GPU run)"),
+        "ms_per_apply": per_apply * 1e3,
+        "ms_per_step": per_step * 1e3,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="c2", choices=["c1", "c2"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--force-hash", action="store_true", help="general hashed Hamiltonian kernel")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(--gpus must be 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2601_01437_amd import binding as B
+    from paper_2601_01437_amd import System
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a HIP device", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    wl = synth.WORKLOADS[args.config]
+    h, g = wl.integrals()
+    log(f"workload {wl.name}: n={wl.n} {wl.na}a+{wl.nb}b V={wl.V} H={wl.H} P={wl.P} m={wl.m} k={wl.k}")
+    t = time.perf_counter()
+    sysm = System(wl.n, wl.na, wl.nb, h, g, flags=B.IRL_SYS_FORCE_HASH if args.force_hash else 0)
+    torch.cuda.synchronize()
+    setup_ms = (time.perf_counter() - t) * 1e3
+    ns = sysm.ns
+    log(f"system ready: {ns} determinants, ham kernel {sysm.info.ham_kernel}, {setup_ms:.1f} ms")
+    theta0 = torch.tensor(wl.theta(), dtype=torch.float64, device="cuda")
+    theta = theta0.clone()
+    ws_flags = B.IRL_WS_FP64
+    sysm.workspace(wl.P + 1, ws_flags)
+    log(f"workspace {sysm.ws.numel() / 2**30:.2f} GiB")
+
+    def one_step():
+        rc, r, _, _ = sysm.step(theta, wl.V, wl.H, m=wl.m, k_keep=wl.k, tol=1e-12,
+                                flags=B.IRL_STEP_NO_EVAL_AFTER, ws_flags=ws_flags,
+                                want_dtheta=False)
+        return rc, r
+
+    for i in range(args.warmup):
+        rc, r = one_step()
+        log(f"warmup {i}: E={r.E_before:.12f} lambda={r.lambda_min:.3e} applies={r.n_apply} "
+            f"restarts={r.n_restart} conv={r.converged} {r.ms_eval + r.ms_solve + r.ms_after:.1f} ms")
+    theta.copy_(theta0)
+    torch.cuda.synchronize()
+    B.irl_stats_enable(sysm.handle, True)
+    steps = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ts = time.perf_counter()
+        rc, r = one_step()
+        step_ms = (time.perf_counter() - ts) * 1e3
+        steps.append({"E": r.E_before, "lambda_min": r.lambda_min, "applies": r.n_apply,
+                      "restarts": r.n_restart, "converged": r.converged,
+                      "residual_est": r.residual_est, "residual_explicit": r.residual_explicit,
+                      "status": rc, "ms": step_ms})
+        log(f"step {i}: E={r.E_before:.12f} lambda={r.lambda_min:.3e} applies={r.n_apply} "
+            f"restarts={r.n_restart} conv={r.converged} {step_ms:.1f} ms")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    stats = B.irl_stats_get(sysm.handle)
+    B.irl_stats_enable(sysm.handle, False)
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    applies = sum(s["applies"] for s in steps)
+    # final energy after the last update
+    Zf, Ef, _ = sysm.evaluate(wl.V, wl.H, theta, ws_flags=ws_flags, want_grad=False)
+
+    # dominant kernel and its roofline
+    ncols = wl.P + 1
+    kern = {k: {"ms_total": v[0], "launches": v[1], "ms_avg": v[0] / v[1] if v[1] else None}
+            for k, v in stats.items()}
+    dominant = max(kern, key=lambda k: kern[k]["ms_total"])
+    src = [os.path.join(ROOT, "paper_2601_01437_amd", "csrc", f) for f in ("dtilde.hip",)]
+    src_hash = source_hash(src)
+    roof = None
+    hbm_kinds = ("gemv", "gemv_t", "dtilde_build")
+    roof_kernel = dominant if dominant in hbm_kinds else max(hbm_kinds, key=lambda k: kern[k]["ms_total"])
+    nbytes = kernel_bytes(roof_kernel, ns, ncols, 8)
+    avg = kern[roof_kernel]["ms_avg"]
+    if avg:
+        achieved = nbytes / (avg * 1e-3) / 1e9
+        traffic = read_traffic(roof_kernel, wl.name, src_hash)
+        roof = {"kernel": roof_kernel, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS,
+                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
+                "bytes_per_launch": nbytes, "ms_avg": avg, "source_hash": src_hash}
+    # whole operator apply
+    op_ms = sum(kern[k]["ms_total"] for k in ("gemv", "gemv_t", "reduce", "ham_apply"))
+    per_apply_bytes = 2 * ns * ncols * 8 + 6 * 8 * ns
+    n_op = kern["gemv"]["launches"]
+    operator = None
+    if n_op:
+        apply_ms = (kern["gemv"]["ms_total"] + kern["ham_apply"]["ms_total"] * n_op / max(1, kern["ham_apply"]["launches"])
+                    + kern["gemv_t"]["ms_total"] * n_op / max(1, kern["gemv_t"]["launches"])
+                    + kern["reduce"]["ms_total"] * n_op / max(1, kern["reduce"]["launches"])) / n_op
+        operator = {"ms_per_apply": apply_ms, "GBps": per_apply_bytes / (apply_ms * 1e-3) / 1e9,
+                    "frac_hbm": per_apply_bytes / (apply_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS,
+                    "bytes_per_apply": per_apply_bytes,
+                    "ham_elements_per_s": ns * sysm.info.max_connections /
+                    (kern["ham_apply"]["ms_avg"] * 1e-3) if kern["ham_apply"]["ms_avg"] else None}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle on a row sample)")
+        from oracle import space
+        cpu = cpu_baseline(wl, lambda: space.full_space(wl.n, wl.na, wl.nb),
+                           applies_per_step=applies / args.steps)
+        log(f"cpu baseline: {cpu['ms_per_step']:.0f} ms per step")
+
+    out = {
+        "metric": METRIC,
+        "value": 1000.0 / ms_per_step,
+        "unit": "IRL steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": (f"{wl.name}: {wl.n} orbitals {wl.na}a+{wl.nb}b full space "
+                                f"({ns} determinants), random molecule-like integrals seed {wl.seed}, "
+                                f"one-hidden-layer tanh network V={wl.V} H={wl.H} (P={wl.P}), "
+                                f"D~ {ns}x{ncols} FP64, IRL m={wl.m} k_keep={wl.k} tol=1e-12"),
+                   "n_dets": ns, "P": wl.P, "m": wl.m, "k_keep": wl.k,
+                   "ham_kernel": ["hashed-pull", "rank-pull", "string-product"][sysm.info.ham_kernel]},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "operator": operator,
+        "kernels": kern,
+        "applies_per_step": applies / args.steps,
+        "setup_ms": setup_ms,
+        "trajectory": steps,
+        "E_final": Ef,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

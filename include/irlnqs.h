@@ -1,0 +1,320 @@
+/*
+ * irlnqs.h -- C ABI of the MI355X (gfx950) linear-method operator library.
+ *
+ * The library applies the linear-method (LM) operator pair of the paper's
+ * Methods section "From SR to a Stable Eigenvalue Problem",
+ *
+ *     v  ->  ( D~^T H D~ v ,  D~^T D~ v ),
+ *
+ * where D~ = [psi, d psi / d theta] is the N_s x (P+1) amplitude/Jacobian matrix
+ * of a one-hidden-layer network over a determinant set (tangent basis
+ * chi_0 = psi, chi_i = d psi / d theta_i; H~ and S~ of Eq. rayleigh_quotient)
+ * and H is the second-quantised Hamiltonian of Methods, "Wave Function
+ * Ansatz", applied matrix-free by Slater-Condon single and double excitations
+ * restricted to the set.  On top of the apply it runs the implicitly
+ * restarted Lanczos solve of Algorithm 1 (Lanczos recurrence of Algorithm 2
+ * with full reorthogonalisation, Ritz pairs, exact-shift implicit QR restarts;
+ * Methods, "The Standard Lanczos Process and Implicit Restart") for the lowest
+ * eigenpair of the centred S ~ I problem (Eq. standard_evp), and the
+ * parameter update taken from that eigenvector.
+ *
+ * Conventions
+ *  - Determinant key: uint64, alpha orbital p at bit p, beta orbital p at bit
+ *    32 + p (n_orb <= 32).  A determinant set is stored in ascending key order;
+ *    row r of D~ is the r-th key.
+ *  - Integrals: h is n x n row-major; g is n^4 row-major with
+ *    g[((p*n + q)*n + r)*n + s] = (pq|rs) (chemists' notation),
+ *    H = sum h_pq a+_p a_q + 1/2 sum (pq|rs) a+_p a+_r a_s a_q over spin-orbitals,
+ *    alpha spin-orbitals ordered before beta ones for the fermionic sign.
+ *  - Network: x_v = occupation of spin-orbital v (alpha v < n, beta v >= n),
+ *    V = 2 n, psi = sum_v a_v x_v + sum_h tanh(b_h + sum_v W_hv x_v);
+ *    theta = [a (V), b (H), W (H x V row-major)], P = V*H + H + V.
+ *  - Every pointer documented "device" belongs to the HIP device that was
+ *    current when the system was created.  Streams are hipStream_t passed as
+ *    void* (NULL = the default stream).  All work is enqueued on the given
+ *    stream; calls that return host scalars synchronise that stream.
+ *  - A handle is not thread-safe.  Several handles may be used concurrently
+ *    from different threads or streams.
+ *  - No exception crosses the ABI.  Negative return values are errors,
+ *    positive ones are warnings with a valid result; irl_last_error() returns
+ *    a message for the last failing call on a handle.
+ */
+#ifndef IRLNQS_H
+#define IRLNQS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------- */
+enum irl_status {
+    IRL_OK = 0,
+    IRL_ENOTCONV = 1,   /* IRL stopped at max_restarts; result valid, not converged */
+    IRL_ESTEP = 2,      /* |c_0| too small to form an update; theta left unchanged */
+    IRL_EINVAL = -1,    /* invalid argument (sizes, popcounts, duplicates, symmetry) */
+    IRL_ENOMEM = -2,    /* device allocation failed or workspace too small */
+    IRL_EDEVICE = -3,   /* a HIP runtime call failed (message in irl_last_error) */
+    IRL_ESTATE = -4     /* workspace holds no D~ for this call (evaluate/set first) */
+};
+
+/* operator precision of the D~ products */
+enum irl_precision { IRL_FP64 = 0, IRL_FP32 = 1 };
+
+/* eigenproblem form (Eq. standard_evp):
+ *  IRL_MODE_A: (P+1)-dimensional centred matrix H~' = H~ - E S~ with identity
+ *              metric; the update is dtheta = c[1:] / c[0].
+ *  IRL_MODE_P: the P x P matrix H_eff (Eq. heff) with identity metric; returns
+ *              the direction only (no update is defined). */
+enum irl_mode { IRL_MODE_A = 0, IRL_MODE_P = 1 };
+
+/* workspace flags (irl_workspace_query) */
+enum irl_ws_flags {
+    IRL_WS_FP64 = 1u,   /* hold an FP64 copy of D~ (required for IRL_FP64 applies) */
+    IRL_WS_FP32 = 2u    /* hold an FP32 copy of D~ (required for IRL_FP32 applies) */
+};
+
+/* irl_step flags */
+enum irl_step_flags {
+    IRL_STEP_WS_CURRENT = 1u,    /* ws already holds D~, Z, E, g for *theta; skip evaluation */
+    IRL_STEP_NO_EVAL_AFTER = 2u, /* do not evaluate E(theta + dtheta) after the update */
+    IRL_STEP_NO_UPDATE = 4u      /* solve only; leave theta unchanged */
+};
+
+/* K4 variant selection (irl_system_desc.flags) */
+enum irl_system_flags {
+    IRL_SYS_FORCE_HASH = 1u      /* use the general hashed per-determinant Hamiltonian
+                                    apply even for a full space (testing) */
+};
+
+typedef struct irl_system irl_system;
+
+typedef struct {
+    int32_t n_orb;          /* spatial orbitals n, 1 <= n <= 32 (n <= 20 for a full space) */
+    int32_t n_alpha;        /* alpha electrons, 0 <= n_alpha <= n */
+    int32_t n_beta;         /* beta electrons, 0 <= n_beta <= n */
+    const double *h;        /* host, n*n, symmetric to 1e-12 */
+    const double *g;        /* host, n^4, 8-fold symmetric to 1e-12 */
+    double e_core;          /* constant added to every reported energy */
+    const uint64_t *dets;   /* host, n_dets keys (any order, no duplicates);
+                               NULL = the full (n_alpha, n_beta) space */
+    int64_t n_dets;         /* ignored when dets == NULL */
+    uint32_t flags;         /* irl_system_flags */
+} irl_system_desc;
+
+typedef struct {
+    int64_t n_dets;         /* N_s */
+    int32_t n_orb, n_alpha, n_beta;
+    int32_t full_space;     /* 1 if the set is the full (n_alpha, n_beta) space */
+    int64_t n_alpha_strings, n_beta_strings;   /* distinct strings in the set */
+    int64_t max_connections;  /* singles + doubles per determinant (before projection) */
+    size_t device_bytes;    /* device memory owned by the handle */
+    int32_t ham_kernel;     /* 0: hashed per-determinant, 1: string-product */
+} irl_system_info;
+
+typedef struct {
+    int32_t V;              /* visible units, must equal 2 * n_orb */
+    int32_t H;              /* hidden units, 1 <= H <= 1024 */
+    double *theta;          /* device, P doubles, order [a, b, W] */
+} irl_nqs_desc;
+
+typedef struct {
+    double Z;               /* psi^T psi */
+    double E;               /* psi^T H psi / Z + e_core */
+    double *grad;           /* device, P doubles, dE/dtheta = 2 J^T (H psi - E psi) / Z;
+                               NULL: not copied out (it stays in the workspace) */
+} irl_eval_out;
+
+typedef struct {
+    int32_t m;              /* Krylov dimension, 2 <= m <= 64 (default 20) */
+    int32_t k_keep;         /* vectors kept at a restart, 1 <= k_keep < m (default 1) */
+    double tol;             /* residual tolerance on ||H~'y - lambda y|| (default 1e-12) */
+    int32_t max_restarts;   /* default 300 */
+    int32_t precision;      /* irl_precision of the D~ products */
+    int32_t mode;           /* irl_mode */
+    uint64_t seed;          /* start vector: splitmix64(seed, index) -> U(-1, 1) */
+    uint32_t flags;         /* irl_step_flags */
+} irl_solver_opts;
+
+typedef struct {
+    double E_before;        /* E(theta) */
+    double E_after;         /* E(theta + dtheta) (NaN when not evaluated) */
+    double lambda_min;      /* lowest eigenvalue found */
+    double residual_est;    /* |beta_m e_m^T u_1| of the accepted cycle */
+    double residual_explicit;  /* ||H~'y - lambda y|| with one more operator apply */
+    double tol_used;        /* max(tol, 64 u_op ||T_m||) */
+    double c0;              /* first component of the unit Ritz vector (mode A) */
+    double gap;             /* second-lowest minus lowest Ritz value */
+    double norm_T;          /* max |Ritz value| of the last cycle */
+    int32_t n_apply;        /* operator applies used by the solve */
+    int32_t n_restart;      /* restart cycles */
+    int32_t converged;      /* 1 if the residual test passed */
+    int32_t reserved;
+    double ms_eval, ms_solve, ms_after;   /* host wall time of each phase */
+} irl_step_result;
+
+/* ---- system --------------------------------------------------------------- */
+
+/* Build the device tables of one system: the determinant set (enumerated when
+ * dets == NULL: every alpha string with n_alpha bits times every beta string
+ * with n_beta bits, Methods "Wave Function Ansatz" and Eq. constraint), the
+ * key -> row lookup, the integrals and the diagonal H_xx.  Inputs are copied;
+ * the library owns the device tables until irl_system_destroy.
+ * Errors: IRL_EINVAL (n out of range, wrong popcount or orbital outside n,
+ * duplicate keys, non-symmetric h or g beyond 1e-12, empty set), IRL_ENOMEM,
+ * IRL_EDEVICE.  *out is NULL on error. */
+int irl_system_create(const irl_system_desc *desc, void *stream, irl_system **out);
+
+/* Release a system (NULL is ignored). */
+void irl_system_destroy(irl_system *sys);
+
+/* Sizes of a system (host call, no device work). */
+int irl_system_info_get(const irl_system *sys, irl_system_info *out);
+
+/* Message for the last error on sys ("" if none); for a NULL sys, the last
+ * error of a failed irl_system_create on this thread. */
+const char *irl_last_error(const irl_system *sys);
+
+/* ---- workspace -------------------------------------------------------------- */
+
+/* Bytes of caller-owned device workspace for a D~ with ncols = P + 1 columns
+ * and the D~ copies named by ws_flags (irl_ws_flags).  The workspace holds D~
+ * (row-major, rows padded to a multiple of 128 bytes), psi, H psi, the
+ * gradient, the operator vectors, the split reduction partials and the
+ * double-buffered Krylov basis (room for m <= 64).  The caller allocates it
+ * (any 256-byte aligned device buffer) and keeps it alive while it is in use;
+ * its contents persist between calls.  A system remembers the last workspace
+ * it evaluated into; applies and steps must pass that same workspace.
+ * Errors: IRL_EINVAL (ncols < 1, no precision flag). */
+int irl_workspace_query(const irl_system *sys, int64_t ncols, uint32_t ws_flags,
+                        size_t *bytes);
+
+/* ---- network evaluation --------------------------------------------------- */
+
+/* Evaluate the network on every determinant and build D~ = [psi, d psi/d theta]
+ * (Methods, "From SR to a Stable Eigenvalue Problem", linearised wavefunction)
+ * into ws, then Z = psi^T psi, E = psi^T H psi / Z (compensated sums) and the
+ * energy gradient g = 2 J^T (H psi - E psi) / Z (Methods, "Practical
+ * Matrix-Free Implementation", definition of F for a real wavefunction).
+ * ws_flags must match the irl_workspace_query call that sized ws.  Writes
+ * out->Z, out->E and, if out->grad != NULL, P doubles to out->grad (device).
+ * Synchronises the stream.  Errors: IRL_EINVAL (V != 2 n, H out of range,
+ * NULL theta), IRL_ENOMEM (ws_bytes too small), IRL_EDEVICE. */
+int irl_nqs_evaluate(irl_system *sys, const irl_nqs_desc *nqs, void *ws, size_t ws_bytes,
+                     uint32_t ws_flags, irl_eval_out *out, void *stream);
+
+/* Load an arbitrary D~ (device, n_dets x ncols, leading dimension ld >= ncols
+ * elements, dtype IRL_FP64 = double or IRL_FP32 = float) into ws in place of
+ * a network evaluation; column 0 plays the role of psi.  Every copy named in
+ * ws_flags is filled (converted as needed).  Z, E and g = 2 D~[:,1:]^T
+ * (H psi - E psi) / Z are computed from it as in irl_nqs_evaluate, from the
+ * FP64 copy when present.  ws must have been sized for this ncols and
+ * ws_flags.  Synchronises the stream.
+ * Errors: IRL_EINVAL, IRL_ENOMEM, IRL_EDEVICE. */
+int irl_dtilde_set(irl_system *sys, const void *D, int64_t ld, int64_t ncols, int32_t dtype,
+                   void *ws, size_t ws_bytes, uint32_t ws_flags, void *stream);
+
+/* ---- the operator ------------------------------------------------------------ */
+
+/* The LM operator apply (Eq. rayleigh_quotient matrices applied to a vector,
+ * matrix-free as in Methods, "Practical Matrix-Free Implementation"):
+ *     w = D~ v,  u = H w  (restricted to the set),
+ *     yH = D~^T u = D~^T H D~ v,   yS = D~^T w = D~^T D~ v,
+ * raw and unnormalised (divide by Z for the <psi|psi> = 1 convention).
+ * v, yH, yS: device, P+1 doubles each, caller-owned, must not overlap.
+ * precision selects the FP64 or FP32 copy of D~ (FP32 products accumulate in
+ * FP32 per row block; the Hamiltonian apply is always FP64).  Asynchronous on
+ * stream.  Errors: IRL_ESTATE (no D~ in ws for the requested precision),
+ * IRL_EINVAL, IRL_EDEVICE. */
+int irl_apply_lm_operator(irl_system *sys, void *ws, size_t ws_bytes, const double *v,
+                          double *yH, double *yS, int32_t precision, void *stream);
+
+/* u = H w on the determinant set (device vectors of n_dets doubles). */
+int irl_apply_hamiltonian(irl_system *sys, const double *w, double *u, void *stream);
+
+/* ---- one optimisation step ---------------------------------------------- */
+
+/* One optimisation step (Algorithm 1 around the operator apply):
+ *  1. unless IRL_STEP_WS_CURRENT: irl_nqs_evaluate at theta;
+ *  2. implicitly restarted Lanczos for the lowest eigenpair of the centred
+ *     operator (mode A: H~'; mode P: H_eff), Krylov dimension m, k_keep kept
+ *     vectors per restart, exact shifts = the m - k_keep largest Ritz values,
+ *     full (two-pass classical Gram-Schmidt) reorthogonalisation, convergence
+ *     when the Ritz residual estimate is below max(tol, 64 u_op ||T_m||),
+ *     confirmed by one explicit apply;
+ *  3. mode A: dtheta = c[1:] / c[0]; unless IRL_STEP_NO_UPDATE theta += dtheta;
+ *  4. unless IRL_STEP_NO_EVAL_AFTER: evaluate at the new theta (ws then holds
+ *     D~ for the new theta, so the next call may pass IRL_STEP_WS_CURRENT).
+ * nqs may be NULL when ws holds a D~ from irl_dtilde_set (no update then).
+ * dtheta: device, P doubles, or NULL.  ritz: device, P+1 doubles (mode A) or
+ * P doubles (mode P), unit-norm eigenvector, or NULL.
+ * Returns IRL_OK, IRL_ENOTCONV (r filled with the last cycle's values),
+ * IRL_ESTEP (|c_0| < 1e-8: theta unchanged) or an error. */
+int irl_step(irl_system *sys, irl_nqs_desc *nqs, const irl_solver_opts *opts, void *ws,
+             size_t ws_bytes, uint32_t ws_flags, double *dtheta, double *ritz,
+             irl_step_result *r, void *stream);
+
+/* Default solver options (m 20, k_keep 1, tol 1e-12, max_restarts 300, FP64,
+ * mode A, seed 0, flags 0). */
+void irl_solver_opts_default(irl_solver_opts *o);
+
+/* ---- per-kernel timing -------------------------------------------------- */
+
+/* Kernel classes timed by irl_stats_*. */
+enum irl_stat_kind {
+    IRL_STAT_DTILDE_BUILD = 0,   /* network forward + Jacobian rows written to D~ */
+    IRL_STAT_HAM_APPLY = 1,      /* u = H w */
+    IRL_STAT_GEMV = 2,           /* w = D~ v */
+    IRL_STAT_GEMV_T = 3,         /* [ya, yb] = D~^T [a, b] (stream part) */
+    IRL_STAT_REDUCE = 4,         /* fixed-order reduction of the D~^T partial sums */
+    IRL_STAT_ENERGY = 5,         /* compensated Z and psi^T H psi reductions */
+    IRL_STAT_LANCZOS = 6,        /* Lanczos recurrence + reorthogonalisation step */
+    IRL_STAT_RITZ = 7,           /* Ritz pairs, restart shifts, basis compression, Ritz vector */
+    IRL_STAT_KINDS = 8
+};
+
+/* on != 0: from now on every kernel launch of this handle is bracketed by a
+ * pair of HIP events on its stream; on == 0 stops and clears.  Adds a few
+ * microseconds of host work per launch. */
+int irl_stats_enable(irl_system *sys, int32_t on);
+
+/* Synchronise `stream` and return, per irl_stat_kind, the summed kernel time
+ * in milliseconds (ms[IRL_STAT_KINDS]) and the launch count
+ * (count[IRL_STAT_KINDS]) since the last irl_stats_enable(sys, 1). */
+int irl_stats_get(irl_system *sys, double *ms, int64_t *count, void *stream);
+
+/* ---- bit-exact test surface ----------------------------------------------- */
+
+/* Copy the ascending key array (n_dets uint64) to host memory out. */
+int irl_debug_keys(const irl_system *sys, uint64_t *out);
+
+/* rows[i] = row of keys[i] in the set, or -1 if absent (host arrays of n). */
+int irl_debug_lookup(const irl_system *sys, const uint64_t *keys, int64_t n, int32_t *rows);
+
+/* Copy the diagonal H_xx (n_dets doubles) to host memory out. */
+int irl_debug_diagonal(const irl_system *sys, double *out);
+
+/* Off-diagonal connections of determinant `row` inside the set, sorted by
+ * target row, written to host arrays of capacity cap: target row, fermionic
+ * sign (+1/-1), kind (1 alpha single, 2 beta single, 3 alpha-alpha,
+ * 4 beta-beta, 5 alpha-beta double) and matrix element.  *count receives the
+ * number of connections; IRL_EINVAL if it exceeds cap. */
+int irl_debug_excitations(const irl_system *sys, int64_t row, int32_t *target, int8_t *sign,
+                          uint8_t *kind, double *hval, int64_t cap, int64_t *count);
+
+/* Run j_end Lanczos steps of the centred mode-A (or mode-P) operator from the
+ * unit vector v1 (device), no restart, and copy to host: the basis
+ * V (j_end+1 rows of length L = P+1 or P, row-major), alpha (j_end) and beta
+ * (j_end).  Tests the recurrence and the projection relation
+ * H~' V_m = V_m T_m + beta_m v_{m+1} e_m^T (Methods, "The Standard Lanczos
+ * Process and Implicit Restart"). */
+int irl_debug_lanczos(irl_system *sys, void *ws, size_t ws_bytes, const double *v1,
+                      int32_t j_end, int32_t precision, int32_t mode, double *V_host,
+                      double *alpha_host, double *beta_host, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IRLNQS_H */

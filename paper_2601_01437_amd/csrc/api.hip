@@ -1,0 +1,776 @@
+// C ABI of the LM-operator library: system set-up, network evaluation, the
+// operator apply and the implicitly restarted Lanczos optimisation step.
+// Host orchestration only; every arithmetic step runs in the HIP kernels of
+// system.hip, hamiltonian.hip, nqs.hip, dtilde.hip and lanczos.hip.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+using namespace irl;
+
+namespace {
+
+thread_local std::string g_create_err;
+
+int set_err(irl_system *s, int code, const std::string &msg)
+{
+    if (s)
+        s->err = msg;
+    else
+        g_create_err = msg;
+    return code;
+}
+
+#define CK(s, call)                                                                          \
+    do {                                                                                     \
+        hipError_t e_ = (call);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return set_err((s), IRL_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+int64_t binom_host(int n, int k)
+{
+    if (k < 0 || k > n) return 0;
+    int64_t r = 1;
+    for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
+    return r;
+}
+
+double now_ms()
+{
+    using namespace std::chrono;
+    return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+template <typename T>
+int dev_alloc(irl_system *s, T **p, size_t count)
+{
+    size_t bytes = count * sizeof(T);
+    if (bytes == 0) bytes = sizeof(T);
+    hipError_t e = hipMalloc((void **)p, bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return set_err(s, IRL_ENOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
+    }
+    s->dev_bytes += bytes;
+    return IRL_OK;
+}
+
+void free_system(irl_system *s)
+{
+    if (!s) return;
+    void *ptrs[] = {s->d.keys, s->d.h, s->d.g, s->d.diag, s->d.hkeys, s->d.hrows, s->d.rankA,
+                    s->d.rankB, s->d.strA, s->d.strB, s->d.sglA, s->d.sglB, s->d.fA, s->d.fB,
+                    s->d.dblA_rank, s->d.dblA_val, s->d.dblB_rank, s->d.dblB_val, s->d.jA};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    if (s->host_scal) (void)hipHostFree(s->host_scal);
+    for (hipEvent_t e : s->ev_pool) (void)hipEventDestroy(e);
+    delete s;
+}
+
+int stats_fold(irl_system *s);
+
+// read the scalar header of a workspace (synchronises the stream)
+int read_scalars(irl_system *s, void *ws, const WsLayout &L, hipStream_t st)
+{
+    const size_t n = offsetof(WsScalars, alpha) + 4 * kMaxKrylov * sizeof(double);
+    CK(s, hipMemcpyAsync(s->host_scal, ws_ptr<char>(ws, L.off_scal), n, hipMemcpyDeviceToHost, st));
+    CK(s, hipStreamSynchronize(st));
+    return stats_fold(s);
+}
+
+int check_ws(irl_system *s, void *ws, size_t ws_bytes, const WsLayout &L)
+{
+    if (!ws) return set_err(s, IRL_EINVAL, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(ws) % 256 != 0)
+        return set_err(s, IRL_EINVAL, "workspace must be 256-byte aligned");
+    if (ws_bytes < L.total)
+        return set_err(s, IRL_ENOMEM, "workspace too small: need " + std::to_string(L.total) +
+                                          " bytes, got " + std::to_string(ws_bytes));
+    return IRL_OK;
+}
+
+// ---- per-kernel timing: event pairs around launches, folded after syncs ----
+int stats_fold(irl_system *s)
+{
+    for (size_t i = 0; i < s->ev_used; ++i) {
+        float ms = 0.f;
+        CK(s, hipEventSynchronize(s->ev_pool[2 * i + 1]));
+        CK(s, hipEventElapsedTime(&ms, s->ev_pool[2 * i], s->ev_pool[2 * i + 1]));
+        s->stat_ms[s->ev_kind[i]] += ms;
+        s->stat_cnt[s->ev_kind[i]] += 1;
+    }
+    s->ev_used = 0;
+    return IRL_OK;
+}
+
+int stat_begin(irl_system *s, int kind, hipStream_t st)
+{
+    if (!s->stats_on) return IRL_OK;
+    const size_t cap = 4096;
+    if (s->ev_used == cap) {
+        int rc = stats_fold(s);
+        if (rc) return rc;
+    }
+    while (s->ev_pool.size() < 2 * (s->ev_used + 1)) {
+        hipEvent_t e;
+        CK(s, hipEventCreate(&e));
+        s->ev_pool.push_back(e);
+    }
+    if (s->ev_kind.size() < s->ev_used + 1) s->ev_kind.resize(s->ev_used + 1);
+    s->ev_kind[s->ev_used] = kind;
+    CK(s, hipEventRecord(s->ev_pool[2 * s->ev_used], st));
+    return IRL_OK;
+}
+
+int stat_end(irl_system *s, hipStream_t st)
+{
+    if (!s->stats_on) return IRL_OK;
+    CK(s, hipEventRecord(s->ev_pool[2 * s->ev_used + 1], st));
+    s->ev_used += 1;
+    return IRL_OK;
+}
+
+#define TIMED(s, kind, st, call)                       \
+    do {                                               \
+        int rc_ = stat_begin((s), (kind), (st));       \
+        if (rc_) return rc_;                           \
+        CK((s), (call));                               \
+        rc_ = stat_end((s), (st));                     \
+        if (rc_) return rc_;                           \
+    } while (0)
+
+// Z, E and the gradient from psi (and D~ in ws): H psi -> reductions -> D~^T (H psi - E psi)
+int energy_and_gradient(irl_system *s, void *ws, const WsLayout &L, hipStream_t st)
+{
+    double *psi = ws_ptr<double>(ws, L.off_psi), *hpsi = ws_ptr<double>(ws, L.off_hpsi);
+    TIMED(s, IRL_STAT_HAM_APPLY, st, launch_ham_apply(s, psi, hpsi, st));
+    TIMED(s, IRL_STAT_ENERGY, st, launch_energy_reduce(L, ws, st));
+    WsScalars *sc = ws_ptr<WsScalars>(ws, L.off_scal);
+    const int prec = (L.flags & IRL_WS_FP64) ? IRL_FP64 : IRL_FP32;
+    // y = D~^T psi (diagnostic), grad_full = 2 D~^T (H psi - E psi) / Z
+    int nblk = 1;
+    TIMED(s, IRL_STAT_GEMV_T, st, launch_gemv_t2(L, ws, prec, psi, hpsi, psi, &sc->E_el, &nblk, st));
+    TIMED(s, IRL_STAT_REDUCE, st, launch_t2_reduce(L, ws, nblk, ws_ptr<double>(ws, L.off_y),
+                                                   ws_ptr<double>(ws, L.off_grad), L.ncols, 2.0,
+                                                   &sc->Z, st));
+    int rc = read_scalars(s, ws, L, st);
+    if (rc) return rc;
+    s->Z = s->host_scal->Z;
+    s->E_el = s->host_scal->E_el;
+    if (!(s->Z > 0.0) || !std::isfinite(s->E_el))
+        return set_err(s, IRL_EINVAL, "psi^T psi is zero or the energy is not finite");
+    return IRL_OK;
+}
+
+// the operator pair into ws yH/yS (internal, ldv long)
+int apply_internal(irl_system *s, void *ws, const WsLayout &L, const double *v, double *yH,
+                   double *yS, int prec, hipStream_t st)
+{
+    double *w = ws_ptr<double>(ws, L.off_w), *u = ws_ptr<double>(ws, L.off_u);
+    TIMED(s, IRL_STAT_GEMV, st, launch_gemv_rows(L, ws, prec, v, w, st));
+    TIMED(s, IRL_STAT_HAM_APPLY, st, launch_ham_apply(s, w, u, st));
+    int nblk = 1;
+    TIMED(s, IRL_STAT_GEMV_T, st, launch_gemv_t2(L, ws, prec, w, u, nullptr, nullptr, &nblk, st));
+    TIMED(s, IRL_STAT_REDUCE, st, launch_t2_reduce(L, ws, nblk, yS, yH, L.ncols, 1.0, nullptr, st));
+    return IRL_OK;
+}
+
+int check_prec(irl_system *s, int prec)
+{
+    if (prec == IRL_FP64 && !s->ws_has64)
+        return set_err(s, IRL_ESTATE, "workspace holds no FP64 copy of D~");
+    if (prec == IRL_FP32 && !s->ws_has32)
+        return set_err(s, IRL_ESTATE, "workspace holds no FP32 copy of D~");
+    if (prec != IRL_FP64 && prec != IRL_FP32) return set_err(s, IRL_EINVAL, "bad precision");
+    return IRL_OK;
+}
+
+}  // namespace
+
+namespace irl {
+
+WsLayout make_layout(int64_t ns, int64_t ncols, uint32_t flags)
+{
+    WsLayout L;
+    L.ns = ns;
+    L.ncols = ncols;
+    L.flags = flags;
+    const int64_t ld = (int64_t)align_up((size_t)ncols, 32);
+    L.ld64 = L.ld32 = L.ldv = ld;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align_up(off + bytes, 256);
+        return o;
+    };
+    L.off_scal = take(sizeof(WsScalars));
+    L.off_d64 = take((flags & IRL_WS_FP64) ? (size_t)ns * ld * sizeof(double) : 0);
+    L.off_d32 = take((flags & IRL_WS_FP32) ? (size_t)ns * ld * sizeof(float) : 0);
+    L.off_psi = take((size_t)ns * 8);
+    L.off_hpsi = take((size_t)ns * 8);
+    L.off_w = take((size_t)ns * 8);
+    L.off_u = take((size_t)ns * 8);
+    L.off_grad = take((size_t)ld * 8);
+    L.off_yh = take((size_t)ld * 8);
+    L.off_ys = take((size_t)ld * 8);
+    L.off_y = take((size_t)ld * 8);
+    L.off_r = take((size_t)ld * 8);
+    L.off_vconv = take((size_t)ld * 8);
+    L.off_part = take((size_t)kStreamBlocks * 2 * ld * 8);
+    L.off_part2 = take((size_t)kReduceGroups * 2 * ld * 8);
+    L.off_red = take((size_t)kScalarParts * 4 * 8);
+    L.off_kry0 = take((size_t)(kMaxKrylov + 1) * ld * 8);
+    L.off_kry1 = take((size_t)(kMaxKrylov + 1) * ld * 8);
+    L.total = off;
+    return L;
+}
+
+}  // namespace irl
+
+extern "C" {
+
+const char *irl_last_error(const irl_system *sys)
+{
+    return sys ? sys->err.c_str() : g_create_err.c_str();
+}
+
+void irl_solver_opts_default(irl_solver_opts *o)
+{
+    if (!o) return;
+    o->m = 20;
+    o->k_keep = 1;
+    o->tol = 1e-12;
+    o->max_restarts = 300;
+    o->precision = IRL_FP64;
+    o->mode = IRL_MODE_A;
+    o->seed = 0;
+    o->flags = 0;
+}
+
+int irl_system_create(const irl_system_desc *d, void *stream, irl_system **out)
+{
+    if (!out) return set_err(nullptr, IRL_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!d) return set_err(nullptr, IRL_EINVAL, "desc is NULL");
+    const int n = d->n_orb, na = d->n_alpha, nb = d->n_beta;
+    if (n < 1 || n > 32) return set_err(nullptr, IRL_EINVAL, "n_orb must be in [1, 32]");
+    if (na < 0 || na > n || nb < 0 || nb > n)
+        return set_err(nullptr, IRL_EINVAL, "electron counts out of range");
+    if (!d->h || !d->g) return set_err(nullptr, IRL_EINVAL, "integrals are NULL");
+    // symmetry of the integrals
+    double gmax = 1.0;
+    const size_t n2 = (size_t)n * n, n4 = n2 * n2;
+    for (size_t i = 0; i < n2; ++i) gmax = std::max(gmax, std::fabs(d->h[i]));
+    for (size_t i = 0; i < n4; ++i) {
+        if (!std::isfinite(d->g[i])) return set_err(nullptr, IRL_EINVAL, "g is not finite");
+        gmax = std::max(gmax, std::fabs(d->g[i]));
+    }
+    const double stol = 1e-12 * gmax;
+    for (int p = 0; p < n; ++p)
+        for (int q = 0; q < n; ++q)
+            if (!(std::fabs(d->h[p * n + q] - d->h[q * n + p]) <= stol))
+                return set_err(nullptr, IRL_EINVAL, "h is not symmetric");
+    auto G = [&](int p, int q, int r, int s_) { return d->g[(((size_t)p * n + q) * n + r) * n + s_]; };
+    for (int p = 0; p < n; ++p)
+        for (int q = 0; q < n; ++q)
+            for (int r = 0; r < n; ++r)
+                for (int s_ = 0; s_ < n; ++s_) {
+                    double v = G(p, q, r, s_);
+                    if (!(std::fabs(v - G(q, p, r, s_)) <= stol && std::fabs(v - G(p, q, s_, r)) <= stol &&
+                          std::fabs(v - G(r, s_, p, q)) <= stol))
+                        return set_err(nullptr, IRL_EINVAL, "g is not 8-fold symmetric");
+                }
+
+    irl_system *s = new irl_system();
+    s->n = n;
+    s->na = na;
+    s->nb = nb;
+    s->e_core = d->e_core;
+    hipStream_t st = (hipStream_t)stream;
+    (void)hipGetDevice(&s->device);
+    const int64_t cA = binom_host(n, na), cB = binom_host(n, nb);
+    std::vector<uint64_t> keys;
+    bool full = (d->dets == nullptr);
+    if (!full) {
+        if (d->n_dets <= 0) { free_system(s); return set_err(nullptr, IRL_EINVAL, "empty determinant set"); }
+        keys.assign(d->dets, d->dets + d->n_dets);
+        std::sort(keys.begin(), keys.end());
+        for (size_t i = 0; i < keys.size(); ++i) {
+            uint32_t al = (uint32_t)keys[i], be = (uint32_t)(keys[i] >> 32);
+            if (i > 0 && keys[i] == keys[i - 1]) { free_system(s); return set_err(nullptr, IRL_EINVAL, "duplicate determinant keys"); }
+            if ((n < 32 && ((al >> n) || (be >> n))) || __builtin_popcount(al) != na ||
+                __builtin_popcount(be) != nb) {
+                free_system(s);
+                return set_err(nullptr, IRL_EINVAL, "determinant with wrong electron count or orbital outside n");
+            }
+        }
+        if ((int64_t)keys.size() == cA * cB && n <= 24) full = true;   // the set is the full space
+    }
+    if (full && n > 24) { free_system(s); return set_err(nullptr, IRL_EINVAL, "full space needs n_orb <= 24"); }
+    s->ns = full ? cA * cB : (int64_t)keys.size();
+    if (s->ns >= (int64_t)1 << 31) { free_system(s); return set_err(nullptr, IRL_EINVAL, "more than 2^31 - 1 determinants"); }
+    s->full = full;
+    s->nA = full ? cA : 0;
+    s->nB = full ? cB : 0;
+    const bool want_hash = !full || (d->flags & IRL_SYS_FORCE_HASH);
+    s->ham_kernel = want_hash ? 0 : 1;
+
+    int rc = IRL_OK;
+#define AL(ptr, cnt) \
+    if ((rc = dev_alloc(s, &(ptr), (cnt))) != IRL_OK) { std::string m_ = s->err; free_system(s); return set_err(nullptr, rc, m_); }
+    AL(s->d.keys, (size_t)s->ns);
+    AL(s->d.h, n2);
+    AL(s->d.g, n4);
+    AL(s->d.diag, (size_t)s->ns);
+    if (full) {
+        AL(s->d.rankA, (size_t)1 << n);
+        AL(s->d.rankB, (size_t)1 << n);
+        AL(s->d.strA, (size_t)cA);
+        AL(s->d.strB, (size_t)cB);
+    }
+    if (want_hash) {
+        uint64_t cap = 64;
+        while (cap < 2 * (uint64_t)s->ns) cap <<= 1;
+        s->d.hcap = cap;
+        AL(s->d.hkeys, cap);
+        AL(s->d.hrows, cap);
+    }
+#undef AL
+    auto fail_dev = [&](hipError_t e, const char *what) {
+        std::string m_ = std::string(what) + ": " + hipGetErrorString(e);
+        free_system(s);
+        return set_err(nullptr, IRL_EDEVICE, m_);
+    };
+    hipError_t e;
+    if ((e = hipMemcpyAsync(s->d.h, d->h, n2 * 8, hipMemcpyHostToDevice, st)) != hipSuccess) return fail_dev(e, "copy h");
+    if ((e = hipMemcpyAsync(s->d.g, d->g, n4 * 8, hipMemcpyHostToDevice, st)) != hipSuccess) return fail_dev(e, "copy g");
+    if (full) {
+        if ((e = launch_enumerate_full(s->d.keys, s->d.strA, s->d.strB, s->d.rankA, s->d.rankB, n, na, nb, cA, cB, st)) != hipSuccess)
+            return fail_dev(e, "enumerate");
+    } else {
+        if ((e = hipMemcpyAsync(s->d.keys, keys.data(), keys.size() * 8, hipMemcpyHostToDevice, st)) != hipSuccess)
+            return fail_dev(e, "copy keys");
+    }
+    if (want_hash)
+        if ((e = launch_hash_build(s->d.keys, s->ns, s->d.hkeys, s->d.hrows, s->d.hcap, st)) != hipSuccess)
+            return fail_dev(e, "hash build");
+    if ((e = launch_diagonal(s->d.keys, s->ns, n, s->d.h, s->d.g, s->d.diag, st)) != hipSuccess)
+        return fail_dev(e, "diagonal");
+    if ((e = launch_product_tables(s, st)) != hipSuccess) return fail_dev(e, "product tables");
+    if ((e = hipHostMalloc((void **)&s->host_scal, sizeof(WsScalars))) != hipSuccess) return fail_dev(e, "pinned scalars");
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return fail_dev(e, "system create");
+    *out = s;
+    return IRL_OK;
+}
+
+void irl_system_destroy(irl_system *sys) { free_system(sys); }
+
+int irl_system_info_get(const irl_system *s, irl_system_info *o)
+{
+    if (!s || !o) return IRL_EINVAL;
+    o->n_dets = s->ns;
+    o->n_orb = s->n;
+    o->n_alpha = s->na;
+    o->n_beta = s->nb;
+    o->full_space = s->full ? 1 : 0;
+    o->n_alpha_strings = s->full ? s->nA : -1;
+    o->n_beta_strings = s->full ? s->nB : -1;
+    const int va = s->n - s->na, vb = s->n - s->nb;
+    o->max_connections = (int64_t)s->na * va + (int64_t)s->nb * vb +
+                         binom_host(s->na, 2) * binom_host(va, 2) + binom_host(s->nb, 2) * binom_host(vb, 2) +
+                         (int64_t)s->na * va * s->nb * vb;
+    o->device_bytes = s->dev_bytes;
+    o->ham_kernel = s->ham_kernel;
+    return IRL_OK;
+}
+
+int irl_workspace_query(const irl_system *s, int64_t ncols, uint32_t ws_flags, size_t *bytes)
+{
+    if (!s || !bytes || ncols < 2 || !(ws_flags & (IRL_WS_FP64 | IRL_WS_FP32)) ||
+        (ws_flags & ~(uint32_t)(IRL_WS_FP64 | IRL_WS_FP32)))
+        return IRL_EINVAL;
+    *bytes = make_layout(s->ns, ncols, ws_flags).total;
+    return IRL_OK;
+}
+
+int irl_nqs_evaluate(irl_system *s, const irl_nqs_desc *nqs, void *ws, size_t ws_bytes,
+                     uint32_t ws_flags, irl_eval_out *out, void *stream)
+{
+    if (!s) return IRL_EINVAL;
+    if (!nqs || !nqs->theta) return set_err(s, IRL_EINVAL, "network descriptor or theta is NULL");
+    if (nqs->V != 2 * s->n) return set_err(s, IRL_EINVAL, "V must equal 2 * n_orb");
+    if (nqs->H < 1 || nqs->H > 1024) return set_err(s, IRL_EINVAL, "H must be in [1, 1024]");
+    if (!(ws_flags & (IRL_WS_FP64 | IRL_WS_FP32))) return set_err(s, IRL_EINVAL, "ws_flags names no D~ copy");
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t P = (int64_t)nqs->V * nqs->H + nqs->H + nqs->V;
+    WsLayout L = make_layout(s->ns, P + 1, ws_flags);
+    int rc = check_ws(s, ws, ws_bytes, L);
+    if (rc) return rc;
+    s->ws_valid = false;
+    TIMED(s, IRL_STAT_DTILDE_BUILD, st, launch_nqs_dtilde(s, nqs->V, nqs->H, nqs->theta, L, ws, st));
+    rc = energy_and_gradient(s, ws, L, st);
+    if (rc) return rc;
+    s->ws = ws;
+    s->lay = L;
+    s->ws_valid = true;
+    s->ws_has64 = (ws_flags & IRL_WS_FP64) != 0;
+    s->ws_has32 = (ws_flags & IRL_WS_FP32) != 0;
+    if (out) {
+        out->Z = s->Z;
+        out->E = s->E_el + s->e_core;
+        if (out->grad) {
+            CK(s, hipMemcpyAsync(out->grad, ws_ptr<double>(ws, L.off_grad) + 1, P * 8,
+                                 hipMemcpyDeviceToDevice, st));
+            CK(s, hipStreamSynchronize(st));
+        }
+    }
+    return IRL_OK;
+}
+
+int irl_dtilde_set(irl_system *s, const void *D, int64_t ld, int64_t ncols, int32_t dtype,
+                   void *ws, size_t ws_bytes, uint32_t ws_flags, void *stream)
+{
+    if (!s) return IRL_EINVAL;
+    if (!D || ncols < 2 || ld < ncols || (dtype != IRL_FP64 && dtype != IRL_FP32))
+        return set_err(s, IRL_EINVAL, "bad D~ arguments");
+    if (!(ws_flags & (IRL_WS_FP64 | IRL_WS_FP32))) return set_err(s, IRL_EINVAL, "ws_flags names no D~ copy");
+    hipStream_t st = (hipStream_t)stream;
+    WsLayout L = make_layout(s->ns, ncols, ws_flags);
+    int rc = check_ws(s, ws, ws_bytes, L);
+    if (rc) return rc;
+    s->ws_valid = false;
+    TIMED(s, IRL_STAT_DTILDE_BUILD, st, launch_dtilde_import(D, ld, ncols, dtype, L, ws, st));
+    rc = energy_and_gradient(s, ws, L, st);
+    if (rc) return rc;
+    s->ws = ws;
+    s->lay = L;
+    s->ws_valid = true;
+    s->ws_has64 = (ws_flags & IRL_WS_FP64) != 0;
+    s->ws_has32 = (ws_flags & IRL_WS_FP32) != 0;
+    return IRL_OK;
+}
+
+int irl_apply_lm_operator(irl_system *s, void *ws, size_t ws_bytes, const double *v, double *yH,
+                          double *yS, int32_t precision, void *stream)
+{
+    if (!s) return IRL_EINVAL;
+    if (!s->ws_valid || ws != s->ws) return set_err(s, IRL_ESTATE, "workspace holds no evaluation for this system");
+    if (ws_bytes < s->lay.total) return set_err(s, IRL_ENOMEM, "workspace too small");
+    if (!v || !yH || !yS) return set_err(s, IRL_EINVAL, "NULL vector");
+    int rc = check_prec(s, precision);
+    if (rc) return rc;
+    return apply_internal(s, ws, s->lay, v, yH, yS, precision, (hipStream_t)stream);
+}
+
+int irl_apply_hamiltonian(irl_system *s, const double *w, double *u, void *stream)
+{
+    if (!s || !w || !u) return IRL_EINVAL;
+    CK(s, launch_ham_apply(s, w, u, (hipStream_t)stream));
+    return IRL_OK;
+}
+
+int irl_step(irl_system *s, irl_nqs_desc *nqs, const irl_solver_opts *opts, void *ws,
+             size_t ws_bytes, uint32_t ws_flags, double *dtheta, double *ritz, irl_step_result *r,
+             void *stream)
+{
+    if (!s) return IRL_EINVAL;
+    irl_solver_opts o;
+    if (opts)
+        o = *opts;
+    else
+        irl_solver_opts_default(&o);
+    if (o.m < 2 || o.m > kMaxKrylov || o.k_keep < 1 || o.k_keep >= o.m || !(o.tol > 0.0) ||
+        o.max_restarts < 0 || (o.mode != IRL_MODE_A && o.mode != IRL_MODE_P))
+        return set_err(s, IRL_EINVAL, "bad solver options");
+    hipStream_t st = (hipStream_t)stream;
+    irl_step_result res;
+    std::memset(&res, 0, sizeof(res));
+    res.E_after = std::numeric_limits<double>::quiet_NaN();
+    double t0 = now_ms();
+    int rc;
+    if (nqs && !(o.flags & IRL_STEP_WS_CURRENT)) {
+        irl_eval_out ev{0, 0, nullptr};
+        rc = irl_nqs_evaluate(s, nqs, ws, ws_bytes, ws_flags, &ev, stream);
+        if (rc) return rc;
+    } else if (!s->ws_valid || s->ws != ws) {
+        return set_err(s, IRL_ESTATE, "workspace holds no evaluation for this system");
+    }
+    if (nqs) {
+        const int64_t P = (int64_t)nqs->V * nqs->H + nqs->H + nqs->V;
+        if (P + 1 != s->lay.ncols) return set_err(s, IRL_EINVAL, "network size does not match the workspace");
+    }
+    rc = check_prec(s, o.precision);
+    if (rc) return rc;
+    const WsLayout L = s->lay;
+    res.E_before = s->E_el + s->e_core;
+    double t1 = now_ms();
+    res.ms_eval = t1 - t0;
+
+    // ---- implicitly restarted Lanczos ----
+    const int64_t dim = (o.mode == IRL_MODE_A) ? L.ncols : L.ncols - 1;
+    int m = (int)std::min<int64_t>(o.m, dim);
+    int k = std::min(o.k_keep, m - 1);
+    if (m < 2 || k < 1) return set_err(s, IRL_EINVAL, "problem dimension too small for the Krylov space");
+    const double u_op = (o.precision == IRL_FP64) ? 1.1102230246251565e-16 : 5.960464477539063e-08;
+    double *Vb[2] = {ws_ptr<double>(ws, L.off_kry0), ws_ptr<double>(ws, L.off_kry1)};
+    int cur = 0;
+    double *yH = ws_ptr<double>(ws, L.off_yh), *yS = ws_ptr<double>(ws, L.off_ys);
+    double *y = ws_ptr<double>(ws, L.off_y), *rv = ws_ptr<double>(ws, L.off_r);
+    CK(s, launch_reset_solve(L, ws, st));
+    CK(s, launch_start_vector(Vb[0], L.ncols, L.ldv, o.mode, o.seed, st));
+    int j0 = 0, n_apply = 0, n_restart = 0;
+    bool converged = false;
+    double tol_eff = o.tol;
+    for (;;) {
+        for (int j = j0; j < m; ++j) {
+            rc = apply_internal(s, ws, L, Vb[cur] + (int64_t)j * L.ldv, yH, yS, o.precision, st);
+            if (rc) return rc;
+            ++n_apply;
+            TIMED(s, IRL_STAT_LANCZOS, st, launch_lanczos_step(L, ws, Vb[cur], j, o.mode, o.seed + 0x100000001b3ull * (uint64_t)(n_restart + 1), st));
+        }
+        TIMED(s, IRL_STAT_RITZ, st, launch_ritz(L, ws, m, k, st));
+        rc = read_scalars(s, ws, L, st);
+        if (rc) return rc;
+        const WsScalars &hs = *s->host_scal;
+        tol_eff = std::max(o.tol, 64.0 * u_op * hs.normT);
+        res.lambda_min = hs.lam;
+        res.residual_est = hs.resid_est;
+        res.gap = hs.gap;
+        res.norm_T = hs.normT;
+        if (!std::isfinite(hs.lam)) return set_err(s, IRL_EINVAL, "non-finite Ritz value (check theta and D~)");
+        if (hs.resid_est <= tol_eff) {
+            TIMED(s, IRL_STAT_RITZ, st, launch_ritz_vector(L, ws, Vb[cur], m, y, st));
+            rc = apply_internal(s, ws, L, y, yH, yS, o.precision, st);
+            if (rc) return rc;
+            ++n_apply;
+            TIMED(s, IRL_STAT_RITZ, st, launch_residual(L, ws, y, rv, o.mode, st));
+            rc = read_scalars(s, ws, L, st);
+            if (rc) return rc;
+            res.residual_explicit = std::sqrt(s->host_scal->resid2);
+            const double tol_explicit = std::max(tol_eff, 1024.0 * u_op * hs.normT);
+            if (res.residual_explicit <= tol_explicit) {
+                converged = true;
+                break;
+            }
+        }
+        if (n_restart >= o.max_restarts) break;
+        TIMED(s, IRL_STAT_RITZ, st,
+              launch_restart_basis(L, ws, Vb[cur], Vb[1 - cur], m, k, o.mode,
+                                   o.seed ^ (0x9e3779b97f4a7c15ull * (uint64_t)(n_restart + 7)), st));
+        cur = 1 - cur;
+        j0 = k;
+        ++n_restart;
+    }
+    if (!converged) {
+        // report the current Ritz pair
+        TIMED(s, IRL_STAT_RITZ, st, launch_ritz(L, ws, m, 0, st));
+        TIMED(s, IRL_STAT_RITZ, st, launch_ritz_vector(L, ws, Vb[cur], m, y, st));
+        rc = apply_internal(s, ws, L, y, yH, yS, o.precision, st);
+        if (rc) return rc;
+        ++n_apply;
+        TIMED(s, IRL_STAT_RITZ, st, launch_residual(L, ws, y, rv, o.mode, st));
+        rc = read_scalars(s, ws, L, st);
+        if (rc) return rc;
+        res.residual_explicit = std::sqrt(s->host_scal->resid2);
+    }
+    res.c0 = s->host_scal->c0;
+    res.n_apply = n_apply;
+    res.n_restart = n_restart;
+    res.converged = converged ? 1 : 0;
+    res.tol_used = tol_eff;
+    if (ritz) {
+        if (o.mode == IRL_MODE_A)
+            CK(s, hipMemcpyAsync(ritz, y, L.ncols * 8, hipMemcpyDeviceToDevice, st));
+        else
+            CK(s, hipMemcpyAsync(ritz, y + 1, (L.ncols - 1) * 8, hipMemcpyDeviceToDevice, st));
+    }
+    double t2 = now_ms();
+    res.ms_solve = t2 - t1;
+    int status = converged ? IRL_OK : IRL_ENOTCONV;
+    if (o.mode == IRL_MODE_A) {
+        if (!(std::fabs(res.c0) >= 1e-8)) {
+            status = IRL_ESTEP;
+        } else {
+            const bool upd = nqs && !(o.flags & IRL_STEP_NO_UPDATE);
+            CK(s, launch_update(L, ws, y, dtheta, upd ? nqs->theta : nullptr, L.ncols - 1, o.mode, st));
+            if (upd && !(o.flags & IRL_STEP_NO_EVAL_AFTER)) {
+                irl_eval_out ev{0, 0, nullptr};
+                rc = irl_nqs_evaluate(s, nqs, ws, ws_bytes, ws_flags, &ev, stream);
+                if (rc) return rc;
+                res.E_after = ev.E;
+            }
+        }
+    }
+    CK(s, hipStreamSynchronize(st));
+    res.ms_after = now_ms() - t2;
+    if (r) *r = res;
+    return status;
+}
+
+int irl_stats_enable(irl_system *s, int32_t on)
+{
+    if (!s) return IRL_EINVAL;
+    if (s->stats_on) {
+        int rc = stats_fold(s);
+        if (rc) return rc;
+    }
+    s->stats_on = on != 0;
+    s->ev_used = 0;
+    for (int k = 0; k < IRL_STAT_KINDS; ++k) {
+        s->stat_ms[k] = 0.0;
+        s->stat_cnt[k] = 0;
+    }
+    return IRL_OK;
+}
+
+int irl_stats_get(irl_system *s, double *ms, int64_t *count, void *stream)
+{
+    if (!s) return IRL_EINVAL;
+    CK(s, hipStreamSynchronize((hipStream_t)stream));
+    int rc = stats_fold(s);
+    if (rc) return rc;
+    for (int k = 0; k < IRL_STAT_KINDS; ++k) {
+        if (ms) ms[k] = s->stat_ms[k];
+        if (count) count[k] = s->stat_cnt[k];
+    }
+    return IRL_OK;
+}
+
+int irl_debug_keys(const irl_system *s, uint64_t *out)
+{
+    if (!s || !out) return IRL_EINVAL;
+    if (hipMemcpy(out, s->d.keys, (size_t)s->ns * 8, hipMemcpyDeviceToHost) != hipSuccess) return IRL_EDEVICE;
+    return IRL_OK;
+}
+
+int irl_debug_diagonal(const irl_system *s, double *out)
+{
+    if (!s || !out) return IRL_EINVAL;
+    if (hipMemcpy(out, s->d.diag, (size_t)s->ns * 8, hipMemcpyDeviceToHost) != hipSuccess) return IRL_EDEVICE;
+    return IRL_OK;
+}
+
+int irl_debug_lookup(const irl_system *cs, const uint64_t *keys, int64_t n, int32_t *rows)
+{
+    irl_system *s = const_cast<irl_system *>(cs);
+    if (!s || n < 0 || (n > 0 && (!keys || !rows))) return IRL_EINVAL;
+    if (n == 0) return IRL_OK;
+    uint64_t *dq = nullptr;
+    int32_t *dr = nullptr;
+    if (hipMalloc((void **)&dq, n * 8) != hipSuccess) return IRL_ENOMEM;
+    if (hipMalloc((void **)&dr, n * 4) != hipSuccess) { (void)hipFree(dq); return IRL_ENOMEM; }
+    int rc = IRL_OK;
+    if (hipMemcpy(dq, keys, n * 8, hipMemcpyHostToDevice) != hipSuccess ||
+        launch_lookup_any(s, dq, n, dr, nullptr) != hipSuccess ||
+        hipMemcpy(rows, dr, n * 4, hipMemcpyDeviceToHost) != hipSuccess)
+        rc = IRL_EDEVICE;
+    (void)hipFree(dq);
+    (void)hipFree(dr);
+    return rc;
+}
+
+int irl_debug_excitations(const irl_system *cs, int64_t row, int32_t *target, int8_t *sign,
+                          uint8_t *kind, double *hval, int64_t cap, int64_t *count)
+{
+    irl_system *s = const_cast<irl_system *>(cs);
+    if (!s || row < 0 || row >= s->ns || !count || cap < 0) return IRL_EINVAL;
+    const int64_t maxc = 4096 + 16 * 16 * 16 * 16;
+    int32_t *dt = nullptr, *dc = nullptr;
+    int8_t *ds = nullptr;
+    uint8_t *dk = nullptr;
+    double *dv = nullptr;
+    int rc = IRL_OK;
+    if (hipMalloc((void **)&dt, maxc * 4) != hipSuccess || hipMalloc((void **)&ds, maxc) != hipSuccess ||
+        hipMalloc((void **)&dk, maxc) != hipSuccess || hipMalloc((void **)&dv, maxc * 8) != hipSuccess ||
+        hipMalloc((void **)&dc, 4) != hipSuccess) {
+        rc = IRL_ENOMEM;
+    } else if (launch_ham_row_list(s, row, dt, ds, dk, dv, dc, (int)maxc, nullptr) != hipSuccess) {
+        rc = IRL_EDEVICE;
+    } else {
+        int32_t c = 0;
+        if (hipMemcpy(&c, dc, 4, hipMemcpyDeviceToHost) != hipSuccess) {
+            rc = IRL_EDEVICE;
+        } else if (c > maxc) {
+            rc = IRL_EINVAL;
+        } else {
+            std::vector<int32_t> t(c);
+            std::vector<int8_t> sg(c);
+            std::vector<uint8_t> kd(c);
+            std::vector<double> v(c);
+            if (c && (hipMemcpy(t.data(), dt, c * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+                      hipMemcpy(sg.data(), ds, c, hipMemcpyDeviceToHost) != hipSuccess ||
+                      hipMemcpy(kd.data(), dk, c, hipMemcpyDeviceToHost) != hipSuccess ||
+                      hipMemcpy(v.data(), dv, c * 8, hipMemcpyDeviceToHost) != hipSuccess)) {
+                rc = IRL_EDEVICE;
+            } else {
+                std::vector<int32_t> idx(c);
+                for (int32_t i = 0; i < c; ++i) idx[i] = i;
+                std::sort(idx.begin(), idx.end(), [&](int32_t a, int32_t b) { return t[a] < t[b]; });
+                *count = c;
+                if (c > cap) {
+                    rc = IRL_EINVAL;
+                } else {
+                    for (int32_t i = 0; i < c; ++i) {
+                        if (target) target[i] = t[idx[i]];
+                        if (sign) sign[i] = sg[idx[i]];
+                        if (kind) kind[i] = kd[idx[i]];
+                        if (hval) hval[i] = v[idx[i]];
+                    }
+                }
+            }
+        }
+    }
+    if (dt) (void)hipFree(dt);
+    if (ds) (void)hipFree(ds);
+    if (dk) (void)hipFree(dk);
+    if (dv) (void)hipFree(dv);
+    if (dc) (void)hipFree(dc);
+    return rc;
+}
+
+int irl_debug_lanczos(irl_system *s, void *ws, size_t ws_bytes, const double *v1, int32_t j_end,
+                      int32_t precision, int32_t mode, double *V_host, double *alpha_host,
+                      double *beta_host, void *stream)
+{
+    if (!s) return IRL_EINVAL;
+    if (!s->ws_valid || ws != s->ws) return set_err(s, IRL_ESTATE, "workspace holds no evaluation");
+    if (ws_bytes < s->lay.total || !v1 || j_end < 1 || j_end > kMaxKrylov || (mode != IRL_MODE_A && mode != IRL_MODE_P))
+        return set_err(s, IRL_EINVAL, "bad arguments");
+    int rc = check_prec(s, precision);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    const WsLayout L = s->lay;
+    double *V = ws_ptr<double>(ws, L.off_kry0);
+    double *yH = ws_ptr<double>(ws, L.off_yh), *yS = ws_ptr<double>(ws, L.off_ys);
+    CK(s, launch_reset_solve(L, ws, st));
+    CK(s, hipMemsetAsync(V, 0, L.ldv * 8, st));
+    CK(s, hipMemcpyAsync(V, v1, L.ncols * 8, hipMemcpyDeviceToDevice, st));
+    for (int j = 0; j < j_end; ++j) {
+        rc = apply_internal(s, ws, L, V + (int64_t)j * L.ldv, yH, yS, precision, st);
+        if (rc) return rc;
+        CK(s, launch_lanczos_step(L, ws, V, j, mode, 12345, st));
+    }
+    rc = read_scalars(s, ws, L, st);
+    if (rc) return rc;
+    for (int j = 0; j < j_end; ++j) {
+        if (alpha_host) alpha_host[j] = s->host_scal->alpha[j];
+        if (beta_host) beta_host[j] = s->host_scal->beta[j];
+    }
+    if (V_host)
+        for (int j = 0; j <= j_end; ++j)
+            CK(s, hipMemcpy(V_host + (int64_t)j * L.ncols, V + (int64_t)j * L.ldv, L.ncols * 8,
+                            hipMemcpyDeviceToHost));
+    return IRL_OK;
+}
+
+}  // extern "C"

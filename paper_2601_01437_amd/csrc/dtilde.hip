@@ -1,0 +1,353 @@
+// Streams over D~ (HBM-bound) and the energy reductions, gfx950.
+//
+// The LM operator apply (Methods, "Practical Matrix-Free Implementation": the
+// eigen-solver only needs matrix-vector products) reads D~ twice per vector:
+//   K6  w = D~ v               one wavefront per row, v staged in LDS;
+//   K7  [ya, yb] = D~^T [a, b] column tiles x row blocks, two right-hand sides
+//                               per pass, per-block partial sums;
+// followed by a two-level fixed-order reduction of the partials (no float
+// atomics: results are bitwise reproducible).  D~ rows are read with 16-byte
+// non-temporal loads, 1 KiB per wavefront instruction.  FP32 copies are
+// multiplied and accumulated in FP32 inside a row block (the operator's
+// reduced-precision mode); block partials are combined in FP64.
+#include "internal.h"
+
+namespace irl {
+
+typedef double d2 __attribute__((ext_vector_type(2)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------- K6: w = D v
+template <typename T>
+struct Chunk;
+template <>
+struct Chunk<double> {
+    typedef d2 V;
+    static constexpr int E = 2;
+};
+template <>
+struct Chunk<float> {
+    typedef f4 V;
+    static constexpr int E = 4;
+};
+
+template <typename T>
+__device__ __forceinline__ T dot_chunk(typename Chunk<T>::V x, const T *v)
+{
+    if constexpr (Chunk<T>::E == 2) {
+        return x.x * v[0] + x.y * v[1];
+    } else {
+        return x.x * v[0] + x.y * v[1] + x.z * v[2] + x.w * v[3];
+    }
+}
+
+constexpr size_t kMaxLdsBytes = 64 * 1024;
+
+// VLDS: v staged in LDS (row length up to 64 KiB), else read through the caches
+template <typename T, bool VLDS>
+__global__ __launch_bounds__(256) void k_gemv_rows(const T *__restrict__ D, int64_t ld, int64_t ns,
+                                                   const double *__restrict__ v, int64_t nv,
+                                                   const T *__restrict__ vglob,
+                                                   double *__restrict__ w)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const T *vs = vglob;
+    if constexpr (VLDS) {
+        T *vl = reinterpret_cast<T *>(smem_raw);
+        for (int64_t c = threadIdx.x; c < ld; c += blockDim.x) vl[c] = c < nv ? (T)v[c] : (T)0;
+        __syncthreads();
+        vs = vl;
+    }
+    typedef typename Chunk<T>::V CV;
+    constexpr int E = Chunk<T>::E;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t nch = ld / E;               // chunks per row (ld is a multiple of E)
+    // contiguous row range per block, rows interleaved over the 4 waves
+    const int64_t per = (ns + gridDim.x - 1) / gridDim.x;
+    const int64_t r0 = (int64_t)blockIdx.x * per, r1 = min(ns, r0 + per);
+    for (int64_t r = r0 + wv; r < r1; r += 4) {
+        const CV *row = reinterpret_cast<const CV *>(D + r * ld);
+        T acc = 0;
+        int64_t k = lane;
+        for (; k + 3 * kWave < nch; k += 4 * kWave) {
+            CV x0 = __builtin_nontemporal_load(row + k);
+            CV x1 = __builtin_nontemporal_load(row + k + kWave);
+            CV x2 = __builtin_nontemporal_load(row + k + 2 * kWave);
+            CV x3 = __builtin_nontemporal_load(row + k + 3 * kWave);
+            acc += dot_chunk<T>(x0, vs + k * E);
+            acc += dot_chunk<T>(x1, vs + (k + kWave) * E);
+            acc += dot_chunk<T>(x2, vs + (k + 2 * kWave) * E);
+            acc += dot_chunk<T>(x3, vs + (k + 3 * kWave) * E);
+        }
+        for (; k < nch; k += kWave) acc += dot_chunk<T>(__builtin_nontemporal_load(row + k), vs + k * E);
+        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kWave);
+        if (lane == 0) w[r] = (double)acc;
+    }
+}
+
+// vector v converted to the stream precision, zero padded to ld
+template <typename T>
+__global__ void k_vec_convert(const double *__restrict__ v, int64_t nv, int64_t ld, T *out)
+{
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < ld;
+         c += (int64_t)gridDim.x * blockDim.x)
+        out[c] = c < nv ? (T)v[c] : (T)0;
+}
+
+template <typename T>
+static hipError_t gemv_rows_typed(const T *D, int64_t ld, int64_t ns, const double *v, int64_t nv,
+                                  T *vtmp, double *w, hipStream_t st)
+{
+    const int64_t nblk = ns < 4096 ? (ns + 3) / 4 : 2048;
+    const size_t sh = (size_t)ld * sizeof(T);
+    if (sh <= kMaxLdsBytes) {
+        k_gemv_rows<T, true><<<(unsigned)nblk, 256, sh, st>>>(D, ld, ns, v, nv, nullptr, w);
+    } else {
+        k_vec_convert<T><<<(unsigned)((ld + 255) / 256), 256, 0, st>>>(v, nv, ld, vtmp);
+        k_gemv_rows<T, false><<<(unsigned)nblk, 256, 0, st>>>(D, ld, ns, v, nv, vtmp, w);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_gemv_rows(const WsLayout &L, void *ws, int prec, const double *v, double *w,
+                            hipStream_t st)
+{
+    // the residual slot doubles as the converted-vector buffer (ld doubles >= ld floats)
+    if (prec == IRL_FP64)
+        return gemv_rows_typed<double>(ws_ptr<double>(ws, L.off_d64), L.ld64, L.ns, v, L.ncols,
+                                       ws_ptr<double>(ws, L.off_vconv), w, st);
+    return gemv_rows_typed<float>(ws_ptr<float>(ws, L.off_d32), L.ld32, L.ns, v, L.ncols,
+                                  ws_ptr<float>(ws, L.off_vconv), w, st);
+}
+
+// ------------------------------------------------------ K7: [ya, yb] = D^T [a, b]
+// b_r = b[r] - coef * sub[r] when sub != nullptr (coef read from device memory).
+template <typename T, int NCH>
+__global__ __launch_bounds__(256) void k_gemv_t2(const T *__restrict__ D, int64_t ld, int64_t ns,
+                                                 const double *__restrict__ a,
+                                                 const double *__restrict__ b,
+                                                 const double *__restrict__ sub,
+                                                 const double *__restrict__ coefp,
+                                                 double *__restrict__ part, int64_t ldv,
+                                                 int nblk_rows)
+{
+    typedef typename Chunk<T>::V CV;
+    constexpr int E = Chunk<T>::E;
+    const int64_t nch = ld / E;
+    const int tile = blockIdx.x, rb = blockIdx.y;
+    const int64_t cbase = (int64_t)tile * 256 * NCH + threadIdx.x;
+    const int64_t per = (ns + nblk_rows - 1) / nblk_rows;
+    const int64_t r0 = (int64_t)rb * per, r1 = min(ns, r0 + per);
+    const double coef = sub ? *coefp : 0.0;
+    CV acc_a[NCH], acc_b[NCH];
+#pragma unroll
+    for (int q = 0; q < NCH; ++q) {
+        acc_a[q] = (CV)0;
+        acc_b[q] = (CV)0;
+    }
+    for (int64_t r = r0; r < r1; ++r) {
+        const double ad = a[r];
+        const double bd = sub ? b[r] - coef * sub[r] : b[r];
+        const T av = (T)ad, bv = (T)bd;
+        const CV *row = reinterpret_cast<const CV *>(D + r * ld);
+#pragma unroll
+        for (int q = 0; q < NCH; ++q) {
+            int64_t k = cbase + (int64_t)q * 256;
+            if (k < nch) {
+                CV x = __builtin_nontemporal_load(row + k);
+                acc_a[q] += av * x;
+                acc_b[q] += bv * x;
+            }
+        }
+    }
+    double *pa = part + (int64_t)rb * 2 * ldv;
+    double *pb = pa + ldv;
+#pragma unroll
+    for (int q = 0; q < NCH; ++q) {
+        int64_t k = cbase + (int64_t)q * 256;
+        if (k < nch) {
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                pa[k * E + e] = (double)acc_a[q][e];
+                pb[k * E + e] = (double)acc_b[q][e];
+            }
+        }
+    }
+}
+
+// stage 1: group g sums row blocks [g*per, (g+1)*per) of part -> part2[g]
+__global__ void k_reduce_stage1(const double *__restrict__ part, int nblk, int64_t len,
+                                double *__restrict__ part2, int groups)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int g = blockIdx.y;
+    if (c >= len) return;
+    const int per = (nblk + groups - 1) / groups;
+    const int b0 = g * per, b1 = min(nblk, b0 + per);
+    double s = 0.0;
+    for (int b = b0; b < b1; ++b) s += part[(int64_t)b * len + c];
+    part2[(int64_t)g * len + c] = s;
+}
+
+// stage 2: out = scale / (div ? *div : 1) * sum_g part2[g]; first half -> ya, second -> yb
+__global__ void k_reduce_stage2(const double *__restrict__ part2, int groups, int64_t ldv,
+                                double *ya, double *yb, int64_t nout, double scale,
+                                const double *divp)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= 2 * ldv) return;
+    const int64_t cc = c < ldv ? c : c - ldv;
+    if (cc >= nout) return;
+    double s = 0.0;
+    for (int g = 0; g < groups; ++g) s += part2[(int64_t)g * 2 * ldv + c];
+    const double f = divp ? scale / *divp : scale;
+    if (c < ldv) {
+        if (ya) ya[cc] = s * f;
+    } else {
+        if (yb) yb[cc] = s * f;
+    }
+}
+
+template <typename T, int NCH>
+static void launch_t2_inst(const T *D, int64_t ld, int64_t ns, const double *a, const double *b,
+                           const double *sub, const double *coef, double *part, int64_t ldv,
+                           int ntiles, int nblk, hipStream_t st)
+{
+    k_gemv_t2<T, NCH><<<dim3(ntiles, nblk), 256, 0, st>>>(D, ld, ns, a, b, sub, coef, part, ldv,
+                                                          nblk);
+}
+
+template <typename T>
+static hipError_t launch_t2_typed(const T *D, int64_t ld, int64_t ns, const double *a,
+                                  const double *b, const double *sub, const double *coef,
+                                  double *part, int64_t ldv, int &nblk_out, hipStream_t st)
+{
+    constexpr int E = Chunk<T>::E;
+    const int64_t nch = ld / E;
+    int nchp = (int)((nch + 255) / 256);   // chunks per lane for one tile
+    int NCH = nchp <= 1 ? 1 : nchp <= 2 ? 2 : nchp <= 3 ? 3 : nchp <= 4 ? 4 : 4;
+    int ntiles = (int)((nch + 256 * NCH - 1) / (256 * NCH));
+    int nblk = kStreamBlocks / ntiles;
+    if (nblk < 1) nblk = 1;
+    if (nblk > ns) nblk = (int)ns;
+    nblk_out = nblk;
+    switch (NCH) {
+    case 1: launch_t2_inst<T, 1>(D, ld, ns, a, b, sub, coef, part, ldv, ntiles, nblk, st); break;
+    case 2: launch_t2_inst<T, 2>(D, ld, ns, a, b, sub, coef, part, ldv, ntiles, nblk, st); break;
+    case 3: launch_t2_inst<T, 3>(D, ld, ns, a, b, sub, coef, part, ldv, ntiles, nblk, st); break;
+    default: launch_t2_inst<T, 4>(D, ld, ns, a, b, sub, coef, part, ldv, ntiles, nblk, st); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_gemv_t2(const WsLayout &L, void *ws, int prec, const double *a,
+                          const double *b, const double *b_sub, const double *b_coef,
+                          int *nblk, hipStream_t st)
+{
+    double *part = ws_ptr<double>(ws, L.off_part);
+    if (prec == IRL_FP64)
+        return launch_t2_typed<double>(ws_ptr<double>(ws, L.off_d64), L.ld64, L.ns, a, b, b_sub,
+                                       b_coef, part, L.ldv, *nblk, st);
+    return launch_t2_typed<float>(ws_ptr<float>(ws, L.off_d32), L.ld32, L.ns, a, b, b_sub, b_coef,
+                                  part, L.ldv, *nblk, st);
+}
+
+hipError_t launch_t2_reduce(const WsLayout &L, void *ws, int nblk, double *ya, double *yb,
+                            int64_t nout, double out_scale, const double *out_div, hipStream_t st)
+{
+    double *part = ws_ptr<double>(ws, L.off_part);
+    double *part2 = ws_ptr<double>(ws, L.off_part2);
+    const int64_t len = 2 * L.ldv;
+    const int groups = nblk < kReduceGroups ? nblk : kReduceGroups;
+    k_reduce_stage1<<<dim3((unsigned)((len + 255) / 256), groups), 256, 0, st>>>(part, nblk, len,
+                                                                                 part2, groups);
+    k_reduce_stage2<<<(unsigned)((len + 255) / 256), 256, 0, st>>>(part2, groups, L.ldv, ya, yb,
+                                                                   nout, out_scale, out_div);
+    return hipGetLastError();
+}
+
+// ------------------------------------------- energy: Z = psi.psi, N = psi.(H psi)
+struct Neu {
+    double s, c;
+};
+__device__ __forceinline__ Neu neu_add(Neu a, double x)
+{
+    double t = a.s + x;
+    double bp = t - a.s;
+    double err = (a.s - (t - bp)) + (x - bp);
+    return Neu{t, a.c + err};
+}
+__device__ __forceinline__ Neu neu_merge(Neu a, Neu b)
+{
+    Neu r = neu_add(a, b.s);
+    r.c += b.c;
+    return r;
+}
+
+__global__ __launch_bounds__(256) void k_energy_stage1(const double *__restrict__ psi,
+                                                       const double *__restrict__ hpsi, int64_t ns,
+                                                       double *__restrict__ red)
+{
+    __shared__ double sh[4][256];
+    const int64_t per = (ns + gridDim.x - 1) / gridDim.x;
+    const int64_t r0 = (int64_t)blockIdx.x * per, r1 = min(ns, r0 + per);
+    Neu z{0, 0}, e{0, 0};
+    for (int64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
+        double p = psi[r];
+        z = neu_add(z, p * p);
+        e = neu_add(e, p * hpsi[r]);
+    }
+    sh[0][threadIdx.x] = z.s;
+    sh[1][threadIdx.x] = z.c;
+    sh[2][threadIdx.x] = e.s;
+    sh[3][threadIdx.x] = e.c;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            Neu a{sh[0][threadIdx.x], sh[1][threadIdx.x]}, b{sh[0][threadIdx.x + w], sh[1][threadIdx.x + w]};
+            Neu c{sh[2][threadIdx.x], sh[3][threadIdx.x]}, d{sh[2][threadIdx.x + w], sh[3][threadIdx.x + w]};
+            a = neu_merge(a, b);
+            c = neu_merge(c, d);
+            sh[0][threadIdx.x] = a.s;
+            sh[1][threadIdx.x] = a.c;
+            sh[2][threadIdx.x] = c.s;
+            sh[3][threadIdx.x] = c.c;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        red[blockIdx.x * 4 + 0] = sh[0][0];
+        red[blockIdx.x * 4 + 1] = sh[1][0];
+        red[blockIdx.x * 4 + 2] = sh[2][0];
+        red[blockIdx.x * 4 + 3] = sh[3][0];
+    }
+}
+
+__global__ void k_energy_stage2(const double *__restrict__ red, int nparts, WsScalars *sc)
+{
+    if (threadIdx.x != 0) return;
+    Neu z{0, 0}, e{0, 0};
+    for (int i = 0; i < nparts; ++i) {
+        z = neu_merge(z, Neu{red[i * 4 + 0], red[i * 4 + 1]});
+        e = neu_merge(e, Neu{red[i * 4 + 2], red[i * 4 + 3]});
+    }
+    sc->sum_psi2[0] = z.s;
+    sc->sum_psi2[1] = z.c;
+    sc->sum_psih[0] = e.s;
+    sc->sum_psih[1] = e.c;
+    const double Z = z.s + z.c, N = e.s + e.c;
+    sc->Z = Z;
+    sc->E_el = N / Z;
+}
+
+hipError_t launch_energy_reduce(const WsLayout &L, void *ws, hipStream_t st)
+{
+    int parts = L.ns < (int64_t)kScalarParts * 256 ? (int)((L.ns + 255) / 256) : kScalarParts;
+    double *red = ws_ptr<double>(ws, L.off_red);
+    k_energy_stage1<<<parts, 256, 0, st>>>(ws_ptr<double>(ws, L.off_psi),
+                                           ws_ptr<double>(ws, L.off_hpsi), L.ns, red);
+    k_energy_stage2<<<1, 64, 0, st>>>(red, parts, ws_ptr<WsScalars>(ws, L.off_scal));
+    return hipGetLastError();
+}
+
+}  // namespace irl

@@ -1,0 +1,179 @@
+// Internal declarations of the gfx950 LM-operator library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "irlnqs.h"
+
+namespace irl {
+
+constexpr int kMaxKrylov = 64;          // m <= 64
+constexpr int kWave = 64;               // CDNA wavefront width
+constexpr int kStreamBlocks = 512;      // row blocks of the D~^T stream kernel
+constexpr int kReduceGroups = 16;       // first-level groups of the partial reduction
+constexpr int kScalarParts = 1024;      // blocks of the scalar (energy) reductions
+constexpr uint64_t kEmptyKey = ~0ull;   // empty hash slot
+
+// Device scalars kept in the first bytes of a workspace.
+struct WsScalars {
+    double Z;            // psi^T psi
+    double E_el;         // psi^T H psi / Z (electronic)
+    double sum_psi2[2];  // compensated (sum, compensation)
+    double sum_psih[2];
+    double resid2;       // squared norm of an explicit residual
+    double rnorm;        // scratch norm
+    double normT;        // running max |alpha|, |beta| of the current T
+    double lam;          // selected Ritz value
+    double resid_est;    // |beta_m u_1[m-1]|
+    double gap;
+    double c0;
+    int32_t breakdowns;  // Lanczos breakdowns in the current solve
+    int32_t pad0;
+    double alpha[kMaxKrylov];
+    double beta[kMaxKrylov];
+    double ritz[kMaxKrylov];
+    double talpha[kMaxKrylov];   // T after restart (leading k)
+    double tbeta[kMaxKrylov];
+    double Q[kMaxKrylov * kMaxKrylov];   // restart rotations, column-major Q[l + m*i]
+    double U[kMaxKrylov * kMaxKrylov];   // Ritz vectors of T, column-major
+    double h[kMaxKrylov + 1];            // Gram-Schmidt coefficients
+};
+
+// Workspace layout for one (N_s, ncols, flags).
+struct WsLayout {
+    int64_t ns = 0, ncols = 0;
+    int64_t ld64 = 0, ld32 = 0, ldv = 0;   // row strides (elements) and vector length
+    uint32_t flags = 0;
+    size_t off_scal = 0, off_d64 = 0, off_d32 = 0, off_psi = 0, off_hpsi = 0, off_w = 0,
+           off_u = 0, off_grad = 0, off_yh = 0, off_ys = 0, off_y = 0, off_r = 0,
+           off_part = 0, off_part2 = 0, off_red = 0, off_kry0 = 0, off_kry1 = 0, off_vconv = 0;
+    size_t total = 0;
+};
+
+WsLayout make_layout(int64_t ns, int64_t ncols, uint32_t flags);
+
+template <typename T>
+inline T *ws_ptr(void *ws, size_t off) { return reinterpret_cast<T *>(static_cast<char *>(ws) + off); }
+
+// Device tables owned by a system handle.
+struct SystemDev {
+    uint64_t *keys = nullptr;   // ascending, n_dets
+    double *h = nullptr;        // n*n
+    double *g = nullptr;        // n^4
+    double *diag = nullptr;     // n_dets
+    // hashed lookup (any set)
+    uint64_t *hkeys = nullptr;  // capacity
+    int32_t *hrows = nullptr;   // capacity
+    uint64_t hcap = 0;
+    // string tables (full space)
+    int32_t *rankA = nullptr;   // 2^n, -1 for strings not of popcount n_alpha
+    int32_t *rankB = nullptr;
+    uint32_t *strA = nullptr;   // alpha strings by rank
+    uint32_t *strB = nullptr;
+    // product-kernel tables (full space)
+    uint32_t *sglA = nullptr;   // nA x (na*va): rank<<10 | sign<<9 | i<<5 | a
+    uint32_t *sglB = nullptr;
+    double *fA = nullptr;       // nA x (na*va): h_ia + sum_{j in alpha}[(ia|jj)-(ij|ja)]
+    double *fB = nullptr;
+    int32_t *dblA_rank = nullptr;   // nA x (C(na,2) C(va,2))
+    double *dblA_val = nullptr;
+    int32_t *dblB_rank = nullptr;
+    double *dblB_val = nullptr;
+    double *jA = nullptr;       // nA x n*n: sum_{i in alpha} (pq|ii)
+};
+
+}  // namespace irl
+
+struct irl_system {
+    int32_t n = 0, na = 0, nb = 0;
+    double e_core = 0.0;
+    int64_t ns = 0;
+    int64_t nA = 0, nB = 0;   // string counts (full space) or distinct counts
+    bool full = false;
+    int ham_kernel = 0;       // 0 hashed, 1 product
+    int device = 0;
+    size_t dev_bytes = 0;
+    irl::SystemDev d;
+    std::string err;
+    // last workspace evaluated into
+    void *ws = nullptr;
+    irl::WsLayout lay;
+    bool ws_valid = false;
+    bool ws_has64 = false, ws_has32 = false;
+    double Z = 0.0, E_el = 0.0;   // host copies after the last evaluation
+    // pinned host staging for small readbacks
+    irl::WsScalars *host_scal = nullptr;
+    // per-kernel timing
+    bool stats_on = false;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<int> ev_kind;       // kind of pending pair i (events 2i, 2i+1)
+    size_t ev_used = 0;
+    double stat_ms[IRL_STAT_KINDS] = {0};
+    int64_t stat_cnt[IRL_STAT_KINDS] = {0};
+};
+
+namespace irl {
+
+// ---- kernels (launch wrappers; all enqueue on `st`) ----
+// system.hip
+hipError_t launch_enumerate_full(uint64_t *keys, uint32_t *strA, uint32_t *strB, int32_t *rankA,
+                                 int32_t *rankB, int n, int na, int nb, int64_t nA, int64_t nB,
+                                 hipStream_t st);
+hipError_t launch_hash_build(const uint64_t *keys, int64_t ns, uint64_t *hkeys, int32_t *hrows,
+                             uint64_t cap, hipStream_t st);
+hipError_t launch_hash_lookup(const uint64_t *hkeys, const int32_t *hrows, uint64_t cap,
+                              const uint64_t *q, int64_t nq, int32_t *rows, hipStream_t st);
+hipError_t launch_diagonal(const uint64_t *keys, int64_t ns, int n, const double *h,
+                           const double *g, double *diag, hipStream_t st);
+hipError_t launch_lookup_any(const irl_system *s, const uint64_t *q, int64_t nq, int32_t *rows,
+                             hipStream_t st);
+
+// hamiltonian.hip
+hipError_t launch_product_tables(irl_system *s, hipStream_t st);
+hipError_t launch_ham_apply(const irl_system *s, const double *w, double *u, hipStream_t st);
+hipError_t launch_ham_row_list(const irl_system *s, int64_t row, int32_t *tgt, int8_t *sign,
+                               uint8_t *kind, double *val, int32_t *count, int cap,
+                               hipStream_t st);
+
+// nqs.hip
+hipError_t launch_nqs_dtilde(const irl_system *s, int V, int H, const double *theta,
+                             const WsLayout &L, void *ws, hipStream_t st);
+hipError_t launch_dtilde_import(const void *D, int64_t ld, int64_t ncols, int dtype,
+                                const WsLayout &L, void *ws, hipStream_t st);
+
+// dtilde.hip
+hipError_t launch_gemv_rows(const WsLayout &L, void *ws, int prec, const double *v, double *w,
+                            hipStream_t st);
+// [yS, yH] = D~^T [a, b] where a = w (or nullptr), b = u - scale*psi form; see dtilde.hip
+// stream part: per-row-block partial sums; returns the number of row blocks
+hipError_t launch_gemv_t2(const WsLayout &L, void *ws, int prec, const double *a,
+                          const double *b, const double *b_sub, const double *b_coef,
+                          int *nblk, hipStream_t st);
+// fixed-order reduction of the partials: ya/yb[c] = out_scale / (*out_div) * sum
+hipError_t launch_t2_reduce(const WsLayout &L, void *ws, int nblk, double *ya, double *yb,
+                            int64_t nout, double out_scale, const double *out_div, hipStream_t st);
+hipError_t launch_energy_reduce(const WsLayout &L, void *ws, hipStream_t st);
+
+// lanczos.hip
+hipError_t launch_start_vector(double *v, int64_t L, int64_t ldv, int mode, uint64_t seed,
+                               hipStream_t st);
+hipError_t launch_lanczos_step(const WsLayout &L, void *ws, double *V, int j, int mode,
+                               uint64_t seed, hipStream_t st);
+hipError_t launch_ritz(const WsLayout &L, void *ws, int m, int k, hipStream_t st);
+hipError_t launch_restart_basis(const WsLayout &L, void *ws, const double *Vold, double *Vnew,
+                                int m, int k, int mode, uint64_t seed, hipStream_t st);
+hipError_t launch_ritz_vector(const WsLayout &L, void *ws, const double *V, int m, double *y,
+                              hipStream_t st);
+hipError_t launch_residual(const WsLayout &L, void *ws, const double *y, double *r, int mode,
+                           hipStream_t st);
+hipError_t launch_update(const WsLayout &L, void *ws, const double *y, double *dtheta,
+                         double *theta, int64_t P, int mode, hipStream_t st);
+hipError_t launch_copy(double *dst, const double *src, int64_t n, hipStream_t st);
+hipError_t launch_reset_solve(const WsLayout &L, void *ws, hipStream_t st);
+
+}  // namespace irl

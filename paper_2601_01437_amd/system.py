@@ -1,0 +1,112 @@
+"""Convenience owner of one system handle and its workspace (torch device memory).
+
+Marshalling only: every method forwards to one C entry point.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import binding as B
+
+
+class System:
+    """A determinant set with its Hamiltonian on the current HIP device."""
+
+    def __init__(self, n, n_alpha, n_beta, h, g, dets=None, e_core=0.0, flags=0, device=None):
+        self.device = torch.device(device or "cuda")
+        self.n, self.na, self.nb = n, n_alpha, n_beta
+        with torch.cuda.device(self.device):
+            self.handle = B.irl_system_create(n, n_alpha, n_beta, h, g, dets=dets, e_core=e_core,
+                                              flags=flags)
+        self.info = B.irl_system_info_get(self.handle)
+        self.ns = self.info.n_dets
+        self.ws = None
+        self.ws_flags = 0
+        self.ncols = 0
+
+    # -- lifetime --
+    def close(self):
+        if self.handle is not None:
+            B.irl_system_destroy(self.handle)
+            self.handle = None
+            self.ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- workspace --
+    def workspace(self, ncols, ws_flags=B.IRL_WS_FP64):
+        nbytes = B.irl_workspace_query(self.handle, ncols, ws_flags)
+        if self.ws is None or self.ws.numel() < nbytes or self.ws_flags != ws_flags or self.ncols != ncols:
+            self.ws = None
+            torch.cuda.empty_cache()
+            self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.ws_flags = ws_flags
+        self.ncols = ncols
+        return self.ws
+
+    # -- calls --
+    def keys(self):
+        return B.irl_debug_keys(self.handle, self.ns)
+
+    def diagonal(self):
+        return B.irl_debug_diagonal(self.handle, self.ns)
+
+    def lookup(self, keys):
+        return B.irl_debug_lookup(self.handle, keys)
+
+    def excitations(self, row):
+        return B.irl_debug_excitations(self.handle, row)
+
+    def evaluate(self, V, H, theta, ws_flags=B.IRL_WS_FP64, want_grad=True):
+        P = V * H + H + V
+        ws = self.workspace(P + 1, ws_flags)
+        grad = torch.empty(P, dtype=torch.float64, device=self.device) if want_grad else None
+        Z, E = B.irl_nqs_evaluate(self.handle, V, H, theta, ws, ws_flags, grad=grad)
+        return Z, E, grad
+
+    def set_dtilde(self, D, ws_flags=B.IRL_WS_FP64):
+        ws = self.workspace(D.shape[1], ws_flags)
+        B.irl_dtilde_set(self.handle, D, ws, ws_flags)
+
+    def apply(self, v, precision=B.IRL_FP64):
+        yH = torch.empty(self.ncols, dtype=torch.float64, device=self.device)
+        yS = torch.empty_like(yH)
+        B.irl_apply_lm_operator(self.handle, self.ws, v, yH, yS, precision)
+        return yH, yS
+
+    def apply_hamiltonian(self, w):
+        u = torch.empty_like(w)
+        B.irl_apply_hamiltonian(self.handle, w, u)
+        return u
+
+    def step(self, theta=None, V=None, H=None, m=20, k_keep=1, tol=1e-12, max_restarts=300,
+             precision=B.IRL_FP64, mode=B.IRL_MODE_A, seed=0, flags=0, ws_flags=None,
+             want_dtheta=True, want_ritz=False):
+        o = B.irl_solver_opts_default()
+        o.m, o.k_keep, o.tol, o.max_restarts = m, k_keep, tol, max_restarts
+        o.precision, o.mode, o.seed, o.flags = precision, mode, seed, flags
+        if ws_flags is None:
+            ws_flags = self.ws_flags or (B.IRL_WS_FP64 if precision == B.IRL_FP64 else B.IRL_WS_FP32)
+        if theta is not None:
+            P = V * H + H + V
+            ws = self.workspace(P + 1, ws_flags)
+        else:
+            ws = self.ws
+            P = self.ncols - 1
+        dth = torch.empty(P, dtype=torch.float64, device=self.device) if want_dtheta else None
+        ritz = None
+        if want_ritz:
+            ritz = torch.empty(P + 1 if mode == B.IRL_MODE_A else P, dtype=torch.float64,
+                               device=self.device)
+        rc, res = B.irl_step(self.handle, o, ws, ws_flags, V=V, H=H, theta=theta, dtheta=dth,
+                             ritz=ritz)
+        return rc, res, dth, ritz
+
+
+def to_device(x, device="cuda", dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=dtype).to(device)

@@ -1,0 +1,133 @@
+"""Parity of the IRL optimisation step (GPU through the C ABI) with the dense
+oracle: lowest eigenvalue within 1e-10 max(|lambda|, ||H~'||), energies within
+1e-12 Ha, and the pins that hold for any implementation (D~ = I reduces to
+exact diagonalisation, exact psi gives a zero update, Lanczos invariants)."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import hamiltonian, lm, nqs, space, step
+from tests.gpu_util import announce, dev, host, rel_err, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    require_gpu()
+
+
+def make_system(n, na, nb, seed=0, dets=None, flags=0):
+    from paper_2601_01437_amd import System
+    h, g = synth.integrals(n, seed)
+    return System(n, na, nb, h, g, dets=dets, flags=flags), h, g
+
+
+@pytest.fixture(scope="module")
+def c1_oracle_step(c1_problem):
+    p = c1_problem
+    w = p["w"]
+    res, th_new, E_after = step.lm_step(p["keys"], w.n, w.V, w.H, p["theta"], p["H"])
+    return res, th_new, E_after
+
+
+@pytest.mark.parametrize("m,k", [(20, 1), (20, 5), (12, 3)])
+def test_step_c1_mode_a(c1_problem, c1_oracle_step, m, k):
+    announce(f"irl step c1 m={m} k={k}")
+    p = c1_problem
+    w = p["w"]
+    res, th_new, E_after = c1_oracle_step
+    s, _, _ = make_system(8, 4, 4)
+    theta = dev(p["theta"])
+    rc, r, dth, ritz = s.step(theta, w.V, w.H, m=m, k_keep=k, want_ritz=True)
+    normH = np.linalg.norm(res.Hp, 2)
+    assert rc == 0 and r.converged == 1
+    assert abs(r.E_before - res.E) <= 1e-12
+    assert abs(r.lambda_min - res.lam) <= 1e-10 * max(abs(res.lam), normH)
+    assert rel_err(host(dth), res.dtheta) <= 1e-8
+    assert abs(r.E_after - E_after) <= 1e-12
+    assert rel_err(host(theta), th_new) <= 1e-10
+    c = host(ritz)
+    assert abs(abs(c @ res.c) - 1.0) <= 1e-10
+    assert r.residual_explicit <= max(1e-12, 1024 * 2.2e-16 * normH)
+
+
+def test_step_c1_mode_p(c1_problem):
+    from paper_2601_01437_amd import IRL_MODE_P
+    announce("irl step c1 mode P")
+    p = c1_problem
+    w = p["w"]
+    Dt = nqs.dtilde(p["keys"], w.n, w.V, w.H, p["theta"])
+    resP = lm.solve(Dt, p["H"], mode="P")
+    s, _, _ = make_system(8, 4, 4)
+    s.evaluate(w.V, w.H, dev(p["theta"]))
+    rc, r, _, ritz = s.step(None, m=20, k_keep=2, mode=IRL_MODE_P, flags=1, want_ritz=True,
+                            want_dtheta=False)
+    normH = np.linalg.norm(resP.Hp[1:, 1:], 2)
+    assert r.converged == 1
+    assert abs(r.lambda_min - resP.lam) <= 1e-10 * max(abs(resP.lam), normH)
+    assert abs(abs(host(ritz) @ resP.c) - 1.0) <= 1e-9
+
+
+def test_identity_dtilde_is_exact_diagonalisation():
+    """D~ = I: H~ equals the Hamiltonian, lambda + E = E_exact."""
+    announce("dtilde = I")
+    n, na, nb = 5, 2, 2
+    s, h, g = make_system(n, na, nb, seed=3)
+    keys = space.full_space(n, na, nb)
+    Hm = hamiltonian.build(keys, n, h, g).toarray()
+    e_exact = np.linalg.eigvalsh(Hm)[0]
+    s.set_dtilde(dev(np.eye(keys.size)))
+    rc, r, _, _ = s.step(None, m=40, k_keep=5, flags=1)
+    assert r.converged == 1
+    assert abs(r.E_before - Hm[0, 0]) <= 1e-12
+    assert abs(r.lambda_min + r.E_before - e_exact) <= 1e-10
+
+
+def test_exact_psi_gives_zero_update():
+    announce("exact psi")
+    n, na, nb = 5, 3, 2
+    s, h, g = make_system(n, na, nb, seed=4)
+    keys = space.full_space(n, na, nb)
+    Hm = hamiltonian.build(keys, n, h, g).toarray()
+    psi0 = np.linalg.eigh(Hm)[1][:, 0]
+    J = np.random.default_rng(5).normal(size=(keys.size, 30))
+    s.set_dtilde(dev(np.concatenate([psi0[:, None], J], axis=1)))
+    rc, r, dth, _ = s.step(None, m=20, k_keep=2, flags=1)
+    assert abs(r.lambda_min) <= 1e-12
+    assert np.max(np.abs(host(dth))) <= 1e-10
+
+
+def test_lanczos_invariants_c1(c1_problem):
+    from paper_2601_01437_amd import binding as B
+    announce("lanczos invariants")
+    p = c1_problem
+    w = p["w"]
+    res, _, _ = step.lm_step(p["keys"], w.n, w.V, w.H, p["theta"], p["H"])
+    s, _, _ = make_system(8, 4, 4)
+    s.evaluate(w.V, w.H, dev(p["theta"]))
+    v1 = np.random.default_rng(11).normal(size=w.P + 1)
+    v1 /= np.linalg.norm(v1)
+    m = 20
+    V, a, b = B.irl_debug_lanczos(s.handle, s.ws, dev(v1), m, w.P + 1)
+    Vm = V[:m].T
+    assert np.max(np.abs(Vm.T @ Vm - np.eye(m))) <= 1e-12
+    T = np.diag(a) + np.diag(b[:-1], 1) + np.diag(b[:-1], -1)
+    R = res.Hp @ Vm - Vm @ T - np.outer(V[m], np.eye(m)[m - 1]) * b[m - 1]
+    assert np.linalg.norm(R) <= 1e-11 * np.linalg.norm(res.Hp, 2)
+
+
+def test_selected_set_step():
+    """A selected (hashed) set with a network: step parity with the oracle."""
+    announce("selected-set step")
+    n, na, nb, V, H = 10, 5, 5, 20, 6
+    keys = synth.cisd_like_selected_set(n, na, nb, 2000, seed=3)
+    s, h, g = make_system(n, na, nb, seed=3, dets=keys)
+    Hm = hamiltonian.build(keys, n, h, g)
+    theta = synth.nqs_theta(V, H, 3, scale=0.2)
+    res, th_new, E_after = step.lm_step(keys, n, V, H, theta, Hm)
+    rc, r, dth, _ = s.step(dev(theta), V, H, m=20, k_keep=3)
+    assert r.converged == 1
+    assert abs(r.E_before - res.E) <= 1e-12
+    assert abs(r.lambda_min - res.lam) <= 1e-10 * max(abs(res.lam), np.linalg.norm(res.Hp, 2))
+    assert abs(r.E_after - E_after) <= 1e-12

@@ -1,0 +1,143 @@
+"""Parity of the Hamiltonian apply, network evaluation (Z, E, gradient) and the
+LM operator apply (GPU through the C ABI) with the oracle.
+
+Tolerances: operator applies ||y - y_ref|| <= 1e-10 ||y_ref|| per output;
+energies 1e-12 Ha absolute (FP64 path)."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import capply, hamiltonian, lm, nqs, space
+from tests.gpu_util import announce, dev, host, rel_err, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    require_gpu()
+
+
+def make_system(n, na, nb, seed=0, dets=None, flags=0):
+    from paper_2601_01437_amd import System
+    h, g = synth.integrals(n, seed)
+    return System(n, na, nb, h, g, dets=dets, flags=flags), h, g
+
+
+@pytest.mark.parametrize("flags", [0, 1])
+def test_hamiltonian_apply_c1(c1_problem, flags):
+    announce(f"H apply c1 flags={flags}")
+    s, _, _ = make_system(8, 4, 4, flags=flags)
+    w = np.random.default_rng(3).normal(size=s.ns)
+    u = host(s.apply_hamiltonian(dev(w)))
+    assert rel_err(u, c1_problem["H"] @ w) <= 1e-12
+
+
+@pytest.mark.parametrize("n,na,nb,count,seed", [(10, 5, 5, 3000, 2), (20, 10, 10, 1 << 14, 0),
+                                                 (9, 5, 4, 777, 5)])
+def test_hamiltonian_apply_selected(n, na, nb, count, seed):
+    announce(f"H apply selected n={n} count={count}")
+    keys = synth.cisd_like_selected_set(n, na, nb, count, seed=seed)
+    s, h, g = make_system(n, na, nb, seed=seed, dets=keys)
+    w = np.random.default_rng(4).normal(size=keys.size)
+    u = host(s.apply_hamiltonian(dev(w)))
+    assert rel_err(u, capply.apply(n, h, g, keys, w)) <= 1e-12
+
+
+def test_hamiltonian_apply_c2_sampled_rows():
+    """Full 853,776-determinant space: sampled rows against the oracle."""
+    announce("H apply c2 sampled")
+    s, h, g = make_system(12, 6, 6)
+    keys = space.full_space(12, 6, 6)
+    w = np.random.default_rng(5).normal(size=keys.size)
+    u = host(s.apply_hamiltonian(dev(w)))
+    rows = np.random.default_rng(6).choice(keys.size, 3000, replace=False)
+    rows = np.concatenate([rows, [0, keys.size - 1]])
+    ref = capply.apply(12, h, g, keys, w, rows=rows)
+    assert np.max(np.abs(u[rows] - ref)) <= 1e-12 * np.abs(ref).max()
+
+
+def _oracle_eval(p):
+    w = p["w"]
+    Dt = nqs.dtilde(p["keys"], w.n, w.V, w.H, p["theta"])
+    Z, E_el, E = lm.energy(Dt[:, 0], p["H"])
+    g = lm.gradient(Dt, p["H"])
+    return Dt, Z, E, g
+
+
+def test_evaluate_c1(c1_problem):
+    announce("evaluate c1")
+    p = c1_problem
+    w = p["w"]
+    Dt, Z, E, g = _oracle_eval(p)
+    s, _, _ = make_system(8, 4, 4)
+    Zg, Eg, grad = s.evaluate(w.V, w.H, dev(p["theta"]))
+    assert abs(Zg - Z) <= 1e-12 * Z
+    assert abs(Eg - E) <= 1e-12
+    assert rel_err(host(grad), g) <= 1e-10
+
+
+@pytest.mark.parametrize("flags", [0, 1])
+def test_apply_c1(c1_problem, flags):
+    announce(f"apply c1 flags={flags}")
+    p = c1_problem
+    w = p["w"]
+    Dt, _, _, _ = _oracle_eval(p)
+    s, _, _ = make_system(8, 4, 4, flags=flags)
+    s.evaluate(w.V, w.H, dev(p["theta"]))
+    rng = np.random.default_rng(7)
+    for t in range(3):
+        v = rng.normal(size=w.P + 1)
+        yH, yS = s.apply(dev(v))
+        rH, rS = lm.apply_lm_operator(Dt, p["H"], v)
+        assert rel_err(host(yH), rH) <= 1e-10
+        assert rel_err(host(yS), rS) <= 1e-10
+    # e_0 identities: y_S[0] = Z and y_H[0] / y_S[0] = E
+    e0 = np.zeros(w.P + 1)
+    e0[0] = 1.0
+    yH, yS = s.apply(dev(e0))
+    Z, E_el, _ = lm.energy(Dt[:, 0], p["H"])
+    assert abs(host(yS)[0] - Z) <= 1e-12 * Z
+    assert abs(host(yH)[0] / host(yS)[0] - E_el) <= 1e-12
+
+
+def test_apply_fp32_c1(c1_problem):
+    from paper_2601_01437_amd import IRL_FP32, IRL_WS_FP32, IRL_WS_FP64
+    announce("apply fp32 c1")
+    p = c1_problem
+    w = p["w"]
+    Dt, _, _, _ = _oracle_eval(p)
+    s, _, _ = make_system(8, 4, 4)
+    s.evaluate(w.V, w.H, dev(p["theta"]), ws_flags=IRL_WS_FP64 | IRL_WS_FP32)
+    v = np.random.default_rng(8).normal(size=w.P + 1)
+    yH, yS = s.apply(dev(v), precision=IRL_FP32)
+    rH, rS = lm.apply_lm_operator(Dt, p["H"], v)
+    assert rel_err(host(yH), rH) <= 1e-5
+    assert rel_err(host(yS), rS) <= 1e-5
+
+
+def test_dtilde_set_random_and_selected():
+    announce("dtilde_set")
+    n = 9
+    keys = synth.cisd_like_selected_set(n, 5, 4, 500, seed=1)
+    s, h, g = make_system(n, 5, 4, seed=1, dets=keys)
+    Hm = hamiltonian.build(keys, n, h, g)
+    rng = np.random.default_rng(9)
+    D = rng.normal(size=(keys.size, 37))
+    s.set_dtilde(dev(D))
+    v = rng.normal(size=37)
+    yH, yS = s.apply(dev(v))
+    rH, rS = lm.apply_lm_operator(D, Hm, v)
+    assert rel_err(host(yH), rH) <= 1e-10 and rel_err(host(yS), rS) <= 1e-10
+
+
+def test_apply_bitwise_reproducible(c1_problem):
+    p = c1_problem
+    w = p["w"]
+    s, _, _ = make_system(8, 4, 4)
+    s.evaluate(w.V, w.H, dev(p["theta"]))
+    v = dev(np.random.default_rng(10).normal(size=w.P + 1))
+    a = [host(x) for x in s.apply(v)]
+    b = [host(x) for x in s.apply(v)]
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
