@@ -85,8 +85,10 @@ enum irl_step_flags {
 
 /* K4 variant selection (irl_system_desc.flags) */
 enum irl_system_flags {
-    IRL_SYS_FORCE_HASH = 1u      /* use the general hashed per-determinant Hamiltonian
+    IRL_SYS_FORCE_HASH = 1u,     /* use the general hashed per-determinant Hamiltonian
                                     apply even for a full space (testing) */
+    IRL_SYS_FORCE_PULL = 2u      /* full space: per-determinant kernel with string-rank
+                                    lookup instead of the string-product kernel */
 };
 
 typedef struct irl_system irl_system;
@@ -111,7 +113,8 @@ typedef struct {
     int64_t n_alpha_strings, n_beta_strings;   /* distinct strings in the set */
     int64_t max_connections;  /* singles + doubles per determinant (before projection) */
     size_t device_bytes;    /* device memory owned by the handle */
-    int32_t ham_kernel;     /* 0: hashed per-determinant, 1: string-product */
+    int32_t ham_kernel;     /* 0: hashed per-determinant, 1: rank per-determinant,
+                               2: string-product (full space) */
 } irl_system_info;
 
 typedef struct {

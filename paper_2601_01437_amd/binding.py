@@ -28,6 +28,7 @@ IRL_MODE_A, IRL_MODE_P = 0, 1
 IRL_WS_FP64, IRL_WS_FP32 = 1, 2
 IRL_STEP_WS_CURRENT, IRL_STEP_NO_EVAL_AFTER, IRL_STEP_NO_UPDATE = 1, 2, 4
 IRL_SYS_FORCE_HASH = 1
+IRL_SYS_FORCE_PULL = 2
 STAT_KINDS = ("dtilde_build", "ham_apply", "gemv", "gemv_t", "reduce", "energy", "lanczos", "ritz")
 
 STATUS_NAMES = {0: "IRL_OK", 1: "IRL_ENOTCONV", 2: "IRL_ESTEP", -1: "IRL_EINVAL",

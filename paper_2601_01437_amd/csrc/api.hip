@@ -69,7 +69,8 @@ void free_system(irl_system *s)
     if (!s) return;
     void *ptrs[] = {s->d.keys, s->d.h, s->d.g, s->d.diag, s->d.hkeys, s->d.hrows, s->d.rankA,
                     s->d.rankB, s->d.strA, s->d.strB, s->d.sglA, s->d.sglB, s->d.fA, s->d.fB,
-                    s->d.dblA_rank, s->d.dblA_val, s->d.dblB_rank, s->d.dblB_val, s->d.jA};
+                    s->d.dblA_rank, s->d.dblA_val, s->d.dblB_rank, s->d.dblB_val, s->d.jA,
+                    s->d.jB, s->d.sglA_ia, s->d.sglB_ia};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (s->host_scal) (void)hipHostFree(s->host_scal);
@@ -366,7 +367,8 @@ int irl_system_create(const irl_system_desc *d, void *stream, irl_system **out)
             return fail_dev(e, "hash build");
     if ((e = launch_diagonal(s->d.keys, s->ns, n, s->d.h, s->d.g, s->d.diag, st)) != hipSuccess)
         return fail_dev(e, "diagonal");
-    if ((e = launch_product_tables(s, st)) != hipSuccess) return fail_dev(e, "product tables");
+    if (!(d->flags & IRL_SYS_FORCE_PULL))
+        if ((e = launch_product_tables(s, st)) != hipSuccess) return fail_dev(e, "product tables");
     if ((e = hipHostMalloc((void **)&s->host_scal, sizeof(WsScalars))) != hipSuccess) return fail_dev(e, "pinned scalars");
     if ((e = hipStreamSynchronize(st)) != hipSuccess) return fail_dev(e, "system create");
     *out = s;

@@ -122,6 +122,10 @@ hipError_t launch_gemv_rows(const WsLayout &L, void *ws, int prec, const double 
 
 // ------------------------------------------------------ K7: [ya, yb] = D^T [a, b]
 // b_r = b[r] - coef * sub[r] when sub != nullptr (coef read from device memory).
+// Grid (column tiles, row blocks).  Each wavefront takes whole rows of its
+// tile (lane owns chunks cbase + 64 q, q < NCH: every row issues NCH
+// independent 16-byte loads per lane), the 4 wavefronts of a block are summed
+// in LDS in a fixed order and the block writes one partial row.
 template <typename T, int NCH>
 __global__ __launch_bounds__(256) void k_gemv_t2(const T *__restrict__ D, int64_t ld, int64_t ns,
                                                  const double *__restrict__ a,
@@ -133,9 +137,11 @@ __global__ __launch_bounds__(256) void k_gemv_t2(const T *__restrict__ D, int64_
 {
     typedef typename Chunk<T>::V CV;
     constexpr int E = Chunk<T>::E;
+    __shared__ CV red[2][64 * NCH];
     const int64_t nch = ld / E;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int tile = blockIdx.x, rb = blockIdx.y;
-    const int64_t cbase = (int64_t)tile * 256 * NCH + threadIdx.x;
+    const int64_t cbase = (int64_t)tile * 64 * NCH + lane;
     const int64_t per = (ns + nblk_rows - 1) / nblk_rows;
     const int64_t r0 = (int64_t)rb * per, r1 = min(ns, r0 + per);
     const double coef = sub ? *coefp : 0.0;
@@ -145,26 +151,48 @@ __global__ __launch_bounds__(256) void k_gemv_t2(const T *__restrict__ D, int64_
         acc_a[q] = (CV)0;
         acc_b[q] = (CV)0;
     }
-    for (int64_t r = r0; r < r1; ++r) {
+    for (int64_t r = r0 + wv; r < r1; r += 4) {
         const double ad = a[r];
         const double bd = sub ? b[r] - coef * sub[r] : b[r];
         const T av = (T)ad, bv = (T)bd;
         const CV *row = reinterpret_cast<const CV *>(D + r * ld);
+        CV x[NCH];
 #pragma unroll
         for (int q = 0; q < NCH; ++q) {
-            int64_t k = cbase + (int64_t)q * 256;
-            if (k < nch) {
-                CV x = __builtin_nontemporal_load(row + k);
-                acc_a[q] += av * x;
-                acc_b[q] += bv * x;
+            const int64_t k = cbase + (int64_t)q * 64;
+            x[q] = k < nch ? __builtin_nontemporal_load(row + k) : (CV)0;
+        }
+#pragma unroll
+        for (int q = 0; q < NCH; ++q) {
+            acc_a[q] += av * x[q];
+            acc_b[q] += bv * x[q];
+        }
+    }
+    // fixed-order sum of the 4 wavefronts: ((w0 + w1) + w2) + w3
+    for (int src = 1; src < 4; ++src) {
+        __syncthreads();
+        if (wv == src) {
+#pragma unroll
+            for (int q = 0; q < NCH; ++q) {
+                red[0][q * 64 + lane] = acc_a[q];
+                red[1][q * 64 + lane] = acc_b[q];
+            }
+        }
+        __syncthreads();
+        if (wv == 0) {
+#pragma unroll
+            for (int q = 0; q < NCH; ++q) {
+                acc_a[q] += red[0][q * 64 + lane];
+                acc_b[q] += red[1][q * 64 + lane];
             }
         }
     }
+    if (wv != 0) return;
     double *pa = part + (int64_t)rb * 2 * ldv;
     double *pb = pa + ldv;
 #pragma unroll
     for (int q = 0; q < NCH; ++q) {
-        int64_t k = cbase + (int64_t)q * 256;
+        const int64_t k = cbase + (int64_t)q * 64;
         if (k < nch) {
 #pragma unroll
             for (int e = 0; e < E; ++e) {
@@ -224,19 +252,19 @@ static hipError_t launch_t2_typed(const T *D, int64_t ld, int64_t ns, const doub
 {
     constexpr int E = Chunk<T>::E;
     const int64_t nch = ld / E;
-    int nchp = (int)((nch + 255) / 256);   // chunks per lane for one tile
-    int NCH = nchp <= 1 ? 1 : nchp <= 2 ? 2 : nchp <= 3 ? 3 : nchp <= 4 ? 4 : 4;
-    int ntiles = (int)((nch + 256 * NCH - 1) / (256 * NCH));
+    const int ntiles = (int)((nch + 64 * 16 - 1) / (64 * 16));
+    const int NCH = (int)((nch + 64 * ntiles - 1) / (64 * ntiles));   // <= 16
     int nblk = kStreamBlocks / ntiles;
     if (nblk < 1) nblk = 1;
-    if (nblk > ns) nblk = (int)ns;
+    if (nblk > (ns + 3) / 4) nblk = (int)((ns + 3) / 4);
     nblk_out = nblk;
+#define T2CASE(c) case c: launch_t2_inst<T, c>(D, ld, ns, a, b, sub, coef, part, ldv, ntiles, nblk, st); break;
     switch (NCH) {
-    case 1: launch_t2_inst<T, 1>(D, ld, ns, a, b, sub, coef, part, ldv, ntiles, nblk, st); break;
-    case 2: launch_t2_inst<T, 2>(D, ld, ns, a, b, sub, coef, part, ldv, ntiles, nblk, st); break;
-    case 3: launch_t2_inst<T, 3>(D, ld, ns, a, b, sub, coef, part, ldv, ntiles, nblk, st); break;
-    default: launch_t2_inst<T, 4>(D, ld, ns, a, b, sub, coef, part, ldv, ntiles, nblk, st); break;
+        T2CASE(1) T2CASE(2) T2CASE(3) T2CASE(4) T2CASE(5) T2CASE(6) T2CASE(7) T2CASE(8)
+        T2CASE(9) T2CASE(10) T2CASE(11) T2CASE(12) T2CASE(13) T2CASE(14) T2CASE(15)
+        default: launch_t2_inst<T, 16>(D, ld, ns, a, b, sub, coef, part, ldv, ntiles, nblk, st); break;
     }
+#undef T2CASE
     return hipGetLastError();
 }
 

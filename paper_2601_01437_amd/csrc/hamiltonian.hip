@@ -257,14 +257,15 @@ static HamArgs ham_args(const irl_system *s)
     return A;
 }
 
+static hipError_t launch_ham_product(const irl_system *s, const double *w, double *u, hipStream_t st);
+
 hipError_t launch_ham_apply(const irl_system *s, const double *w, double *u, hipStream_t st)
 {
+    if (s->ham_kernel == 2) return launch_ham_product(s, w, u, st);
     HamArgs A = ham_args(s);
     int64_t blocks = (s->ns + 3) / 4;
     if (blocks > 65536) blocks = 65536;
-    if (s->full && s->ham_kernel == 0 && s->d.hkeys == nullptr)
-        k_ham_pull<true><<<(unsigned)blocks, 256, 0, st>>>(A, w, u);
-    else if (s->d.hkeys != nullptr)
+    if (s->d.hkeys != nullptr)
         k_ham_pull<false><<<(unsigned)blocks, 256, 0, st>>>(A, w, u);
     else
         k_ham_pull<true><<<(unsigned)blocks, 256, 0, st>>>(A, w, u);
@@ -310,6 +311,284 @@ hipError_t launch_ham_row_list(const irl_system *s, int64_t row, int32_t *tgt, i
     return hipGetLastError();
 }
 
-hipError_t launch_product_tables(irl_system *, hipStream_t) { return hipSuccess; }
+// ---------------------------------------------------------------------------
+// String-product kernel for a full (N_alpha, N_beta) space.
+//
+// Rows with the same beta string are contiguous (row = rank(beta) * nA +
+// rank(alpha)).  Per-string tables hold, for every alpha (beta) string, its
+// single moves (target rank, fermionic sign, orbitals), the same-spin part of
+// each single's matrix element, its same-spin double moves with their signed
+// elements, and J[pq] = sum_{j in string} (pq|jj).  One workgroup takes one
+// beta string and 256 alpha strings (one thread per determinant):
+//   alpha singles / alpha-alpha doubles gather w inside the beta row (L1),
+//   beta singles / beta-beta doubles read w coalesced across the threads,
+//   opposite-spin doubles loop over the beta moves (uniform) with the g slice
+//   (. . | j b) in LDS and the thread's alpha moves cached in registers.
+// The elements are the same Slater-Condon expressions as above, summed in a
+// different (fixed) order.
+// ---------------------------------------------------------------------------
+constexpr int kProdThreads = 256;
+constexpr int kProdMaxSingles = 64;     // n_e * (n - n_e) per spin
+constexpr int kProdMaxDoubles = 1024;   // C(n_e, 2) C(n - n_e, 2) per spin
+
+struct StrTables {
+    int32_t *srank;   // [e][s]  target rank
+    uint16_t *sia;    // [e][s]  i | a << 5 | (sign < 0) << 10
+    double *sf;       // [e][s]  h_ia + sum_{j in s}[(ia|jj) - (ij|ja)]
+    int32_t *drank;   // [d][s]
+    double *dval;     // [d][s]  signed element
+    double *J;        // [pq][s] sum_{j in s} (pq|jj)
+};
+
+__global__ void k_string_tables(const uint32_t *strs, const int32_t *rank, int64_t nstr, int n,
+                                int ne, const double *h, const double *g, StrTables T)
+{
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= nstr) return;
+    const uint32_t bits = strs[s];
+    const uint32_t full = (n == 32) ? 0xffffffffu : ((1u << n) - 1u);
+    const uint32_t vir = ~bits & full;
+    int e = 0;
+    for (uint32_t bi = bits; bi; bi &= bi - 1) {
+        const int i = __ffs(bi) - 1;
+        for (uint32_t ba = vir; ba; ba &= ba - 1) {
+            const int a = __ffs(ba) - 1;
+            const int sg = move_sign(bits, i, a);
+            const uint32_t nb = (bits & ~(1u << i)) | (1u << a);
+            double f = h[i * n + a];
+            for (uint32_t bj = bits; bj; bj &= bj - 1) {
+                const int j = __ffs(bj) - 1;
+                f += gint(g, n, i, a, j, j) - gint(g, n, i, j, j, a);
+            }
+            T.srank[(int64_t)e * nstr + s] = rank[nb];
+            T.sia[(int64_t)e * nstr + s] = (uint16_t)(i | (a << 5) | ((sg < 0 ? 1 : 0) << 10));
+            T.sf[(int64_t)e * nstr + s] = f;
+            ++e;
+        }
+    }
+    int d = 0;
+    for (uint32_t bi = bits; bi; bi &= bi - 1) {
+        const int i = __ffs(bi) - 1;
+        for (uint32_t bj = bi & (bi - 1); bj; bj &= bj - 1) {
+            const int j = __ffs(bj) - 1;
+            for (uint32_t ba = vir; ba; ba &= ba - 1) {
+                const int a = __ffs(ba) - 1;
+                for (uint32_t bb = ba & (ba - 1); bb; bb &= bb - 1) {
+                    const int b = __ffs(bb) - 1;
+                    const int s1 = move_sign(bits, i, a);
+                    const uint32_t b1 = (bits & ~(1u << i)) | (1u << a);
+                    const int s2 = move_sign(b1, j, b);
+                    const uint32_t b2 = (b1 & ~(1u << j)) | (1u << b);
+                    T.drank[(int64_t)d * nstr + s] = rank[b2];
+                    T.dval[(int64_t)d * nstr + s] =
+                        (s1 * s2) * (gint(g, n, i, a, j, b) - gint(g, n, i, b, j, a));
+                    ++d;
+                }
+            }
+        }
+    }
+    for (int p = 0; p < n; ++p)
+        for (int q = 0; q < n; ++q) {
+            double acc = 0.0;
+            for (uint32_t bj = bits; bj; bj &= bj - 1) {
+                const int j = __ffs(bj) - 1;
+                acc += gint(g, n, p, q, j, j);
+            }
+            T.J[(int64_t)(p * n + q) * nstr + s] = acc;
+        }
+}
+
+struct ProdArgs {
+    int n, nsa, nsb, nda, ndb;
+    int64_t nA, nB;
+    const double *diag, *g;
+    StrTables A, B;
+};
+
+template <int NSA>
+__global__ __launch_bounds__(kProdThreads) void k_ham_product(ProdArgs P, const double *__restrict__ w,
+                                                              double *__restrict__ u)
+{
+    __shared__ double gs[32 * 32];          // (p q | j_f b_f) for all p, q
+    __shared__ double jb[32 * 32];          // sum_{j in beta} (pq|jj)
+    __shared__ int32_t sb_rank[kProdMaxSingles];
+    __shared__ uint16_t sb_ia[kProdMaxSingles];
+    __shared__ double sb_f[kProdMaxSingles];
+    __shared__ int32_t db_rank[kProdMaxDoubles];
+    __shared__ double db_val[kProdMaxDoubles];
+    const int n = P.n, n2 = n * n;
+    const int64_t rb = blockIdx.y;
+    const int64_t ra = (int64_t)blockIdx.x * kProdThreads + threadIdx.x;
+    const bool valid = ra < P.nA;
+    const int64_t rac = valid ? ra : 0;
+    for (int p = threadIdx.x; p < n2; p += kProdThreads) jb[p] = P.B.J[(int64_t)p * P.nB + rb];
+    for (int f = threadIdx.x; f < P.nsb; f += kProdThreads) {
+        sb_rank[f] = P.B.srank[(int64_t)f * P.nB + rb];
+        sb_ia[f] = P.B.sia[(int64_t)f * P.nB + rb];
+        sb_f[f] = P.B.sf[(int64_t)f * P.nB + rb];
+    }
+    for (int d = threadIdx.x; d < P.ndb; d += kProdThreads) {
+        db_rank[d] = P.B.drank[(int64_t)d * P.nB + rb];
+        db_val[d] = P.B.dval[(int64_t)d * P.nB + rb];
+    }
+    __syncthreads();
+    const double *wrow = w + rb * P.nA;
+    double acc = P.diag[rb * P.nA + rac] * wrow[rac];
+    // alpha singles (moves cached in registers for the opposite-spin loop)
+    int32_t ar[NSA];
+    uint16_t aia[NSA];
+#pragma unroll
+    for (int e = 0; e < NSA; ++e) {
+        if (e < P.nsa) {
+            ar[e] = P.A.srank[(int64_t)e * P.nA + rac];
+            aia[e] = P.A.sia[(int64_t)e * P.nA + rac];
+            const int i = aia[e] & 31, a = (aia[e] >> 5) & 31;
+            const double v = P.A.sf[(int64_t)e * P.nA + rac] + jb[i * n + a];
+            acc += ((aia[e] >> 10) & 1 ? -v : v) * wrow[ar[e]];
+        } else {
+            ar[e] = 0;
+            aia[e] = 0;
+        }
+    }
+    // alpha-alpha doubles
+    for (int d = 0; d < P.nda; ++d)
+        acc += P.A.dval[(int64_t)d * P.nA + rac] * wrow[P.A.drank[(int64_t)d * P.nA + rac]];
+    // beta singles: opposite-spin part sum_{i in alpha} (jb|ii) from the alpha J table
+    for (int f = 0; f < P.nsb; ++f) {
+        const int j = sb_ia[f] & 31, b = (sb_ia[f] >> 5) & 31;
+        const double v = sb_f[f] + P.A.J[(int64_t)(j * n + b) * P.nA + rac];
+        acc += ((sb_ia[f] >> 10) & 1 ? -v : v) * w[(int64_t)sb_rank[f] * P.nA + rac];
+    }
+    // beta-beta doubles
+    for (int d = 0; d < P.ndb; ++d) acc += db_val[d] * w[(int64_t)db_rank[d] * P.nA + rac];
+    // opposite-spin doubles
+    for (int f = 0; f < P.nsb; ++f) {
+        const int j = sb_ia[f] & 31, b = (sb_ia[f] >> 5) & 31;
+        __syncthreads();
+        for (int p = threadIdx.x; p < n2; p += kProdThreads)
+            gs[p] = P.g[(int64_t)p * n2 + j * n + b];
+        __syncthreads();
+        const double *wb = w + (int64_t)sb_rank[f] * P.nA;
+        double part = 0.0;
+#pragma unroll
+        for (int e = 0; e < NSA; ++e) {
+            if (e < P.nsa) {
+                const int i = aia[e] & 31, a = (aia[e] >> 5) & 31;
+                const double v = gs[i * n + a] * wb[ar[e]];
+                part += (aia[e] >> 10) & 1 ? -v : v;
+            }
+        }
+        acc += (sb_ia[f] >> 10) & 1 ? -part : part;
+    }
+    if (valid) u[rb * P.nA + ra] = acc;
+}
+
+static bool product_fits(const irl_system *s, int &nsa, int &nsb, int &nda, int &ndb)
+{
+    const int n = s->n, na = s->na, nb = s->nb, va = n - na, vb = n - nb;
+    nsa = na * va;
+    nsb = nb * vb;
+    nda = na * (na - 1) / 2 * (va * (va - 1) / 2);
+    ndb = nb * (nb - 1) / 2 * (vb * (vb - 1) / 2);
+    if (!s->full || n > 20 || s->nB > 65535) return false;
+    if (nsa > kProdMaxSingles || nsb > kProdMaxSingles) return false;
+    if (nda > kProdMaxDoubles || ndb > kProdMaxDoubles) return false;
+    const double bytes = (double)(s->nA + s->nB) * ((nsa > nsb ? nsa : nsb) * 14.0 +
+                                                    (nda > ndb ? nda : ndb) * 12.0 + n * n * 8.0);
+    return bytes < 4e9;
+}
+
+hipError_t launch_product_tables(irl_system *s, hipStream_t st)
+{
+    int nsa, nsb, nda, ndb;
+    if (s->ham_kernel != 1 || !product_fits(s, nsa, nsb, nda, ndb)) return hipSuccess;
+    const int n = s->n;
+    auto alloc = [&](StrTables &T, int64_t nstr, int ns1, int nd) -> hipError_t {
+        hipError_t e;
+        if ((e = hipMalloc(&T.srank, (size_t)(ns1 ? ns1 : 1) * nstr * 4)) != hipSuccess) return e;
+        if ((e = hipMalloc(&T.sia, (size_t)(ns1 ? ns1 : 1) * nstr * 2)) != hipSuccess) return e;
+        if ((e = hipMalloc(&T.sf, (size_t)(ns1 ? ns1 : 1) * nstr * 8)) != hipSuccess) return e;
+        if ((e = hipMalloc(&T.drank, (size_t)(nd ? nd : 1) * nstr * 4)) != hipSuccess) return e;
+        if ((e = hipMalloc(&T.dval, (size_t)(nd ? nd : 1) * nstr * 8)) != hipSuccess) return e;
+        if ((e = hipMalloc(&T.J, (size_t)n * n * nstr * 8)) != hipSuccess) return e;
+        s->dev_bytes += (size_t)nstr * ((ns1 ? ns1 : 1) * 14 + (nd ? nd : 1) * 12 + n * n * 8);
+        return hipSuccess;
+    };
+    StrTables A{}, B{};
+    hipError_t e;
+    if ((e = alloc(A, s->nA, nsa, nda)) != hipSuccess) return e;
+    s->d.sglA = reinterpret_cast<uint32_t *>(A.srank);
+    s->d.sglA_ia = A.sia;
+    s->d.fA = A.sf;
+    s->d.dblA_rank = A.drank;
+    s->d.dblA_val = A.dval;
+    s->d.jA = A.J;
+    if ((e = alloc(B, s->nB, nsb, ndb)) != hipSuccess) return e;
+    s->d.sglB = reinterpret_cast<uint32_t *>(B.srank);
+    s->d.sglB_ia = B.sia;
+    s->d.fB = B.sf;
+    s->d.dblB_rank = B.drank;
+    s->d.dblB_val = B.dval;
+    s->d.jB = B.J;
+    k_string_tables<<<(unsigned)((s->nA + 127) / 128), 128, 0, st>>>(s->d.strA, s->d.rankA, s->nA, n,
+                                                                    s->na, s->d.h, s->d.g, A);
+    k_string_tables<<<(unsigned)((s->nB + 127) / 128), 128, 0, st>>>(s->d.strB, s->d.rankB, s->nB, n,
+                                                                    s->nb, s->d.h, s->d.g, B);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    s->ham_kernel = 2;
+    return hipSuccess;
+}
+
+static StrTables tables_of(const irl_system *s, bool alpha)
+{
+    StrTables T;
+    T.srank = reinterpret_cast<int32_t *>(alpha ? s->d.sglA : s->d.sglB);
+    T.sia = alpha ? s->d.sglA_ia : s->d.sglB_ia;
+    T.sf = alpha ? s->d.fA : s->d.fB;
+    T.drank = alpha ? s->d.dblA_rank : s->d.dblB_rank;
+    T.dval = alpha ? s->d.dblA_val : s->d.dblB_val;
+    T.J = alpha ? s->d.jA : s->d.jB;
+    return T;
+}
+
+template <int NSA>
+static void launch_prod_inst(const ProdArgs &P, const double *w, double *u, hipStream_t st)
+{
+    dim3 grid((unsigned)((P.nA + kProdThreads - 1) / kProdThreads), (unsigned)P.nB);
+    k_ham_product<NSA><<<grid, kProdThreads, 0, st>>>(P, w, u);
+}
+
+static hipError_t launch_ham_product(const irl_system *s, const double *w, double *u, hipStream_t st)
+{
+    ProdArgs P;
+    product_fits(s, P.nsa, P.nsb, P.nda, P.ndb);
+    P.n = s->n;
+    P.nA = s->nA;
+    P.nB = s->nB;
+    P.diag = s->d.diag;
+    P.g = s->d.g;
+    P.A = tables_of(s, true);
+    P.B = tables_of(s, false);
+    const int q = (P.nsa + 3) / 4;
+    switch (q) {
+    case 0: case 1: launch_prod_inst<4>(P, w, u, st); break;
+    case 2: launch_prod_inst<8>(P, w, u, st); break;
+    case 3: launch_prod_inst<12>(P, w, u, st); break;
+    case 4: launch_prod_inst<16>(P, w, u, st); break;
+    case 5: launch_prod_inst<20>(P, w, u, st); break;
+    case 6: launch_prod_inst<24>(P, w, u, st); break;
+    case 7: launch_prod_inst<28>(P, w, u, st); break;
+    case 8: launch_prod_inst<32>(P, w, u, st); break;
+    case 9: launch_prod_inst<36>(P, w, u, st); break;
+    case 10: launch_prod_inst<40>(P, w, u, st); break;
+    case 11: launch_prod_inst<44>(P, w, u, st); break;
+    case 12: launch_prod_inst<48>(P, w, u, st); break;
+    case 13: launch_prod_inst<52>(P, w, u, st); break;
+    case 14: launch_prod_inst<56>(P, w, u, st); break;
+    case 15: launch_prod_inst<60>(P, w, u, st); break;
+    default: launch_prod_inst<64>(P, w, u, st); break;
+    }
+    return hipGetLastError();
+}
 
 }  // namespace irl

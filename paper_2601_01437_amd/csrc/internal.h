@@ -78,6 +78,9 @@ struct SystemDev {
     // product-kernel tables (full space)
     uint32_t *sglA = nullptr;   // nA x (na*va): rank<<10 | sign<<9 | i<<5 | a
     uint32_t *sglB = nullptr;
+    uint16_t *sglA_ia = nullptr;
+    uint16_t *sglB_ia = nullptr;
+    double *jB = nullptr;
     double *fA = nullptr;       // nA x (na*va): h_ia + sum_{j in alpha}[(ia|jj)-(ij|ja)]
     double *fB = nullptr;
     int32_t *dblA_rank = nullptr;   // nA x (C(na,2) C(va,2))
@@ -95,7 +98,7 @@ struct irl_system {
     int64_t ns = 0;
     int64_t nA = 0, nB = 0;   // string counts (full space) or distinct counts
     bool full = false;
-    int ham_kernel = 0;       // 0 hashed, 1 product
+    int ham_kernel = 0;       // 0 hashed pull, 1 rank pull, 2 string product
     int device = 0;
     size_t dev_bytes = 0;
     irl::SystemDev d;

@@ -25,7 +25,7 @@ def make_system(n, na, nb, seed=0, dets=None, flags=0):
     return System(n, na, nb, h, g, dets=dets, flags=flags), h, g
 
 
-@pytest.mark.parametrize("flags", [0, 1])
+@pytest.mark.parametrize("flags", [0, 1, 2])
 def test_hamiltonian_apply_c1(c1_problem, flags):
     announce(f"H apply c1 flags={flags}")
     s, _, _ = make_system(8, 4, 4, flags=flags)
@@ -45,10 +45,12 @@ def test_hamiltonian_apply_selected(n, na, nb, count, seed):
     assert rel_err(u, capply.apply(n, h, g, keys, w)) <= 1e-12
 
 
-def test_hamiltonian_apply_c2_sampled_rows():
+@pytest.mark.parametrize("flags", [0, 2])
+def test_hamiltonian_apply_c2_sampled_rows(flags):
     """Full 853,776-determinant space: sampled rows against the oracle."""
-    announce("H apply c2 sampled")
-    s, h, g = make_system(12, 6, 6)
+    announce(f"H apply c2 sampled flags={flags}")
+    s, h, g = make_system(12, 6, 6, flags=flags)
+    assert s.info.ham_kernel == (2 if flags == 0 else 1)
     keys = space.full_space(12, 6, 6)
     w = np.random.default_rng(5).normal(size=keys.size)
     u = host(s.apply_hamiltonian(dev(w)))
@@ -78,7 +80,7 @@ def test_evaluate_c1(c1_problem):
     assert rel_err(host(grad), g) <= 1e-10
 
 
-@pytest.mark.parametrize("flags", [0, 1])
+@pytest.mark.parametrize("flags", [0, 1, 2])
 def test_apply_c1(c1_problem, flags):
     announce(f"apply c1 flags={flags}")
     p = c1_problem
@@ -141,3 +143,14 @@ def test_apply_bitwise_reproducible(c1_problem):
     a = [host(x) for x in s.apply(v)]
     b = [host(x) for x in s.apply(v)]
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+@pytest.mark.parametrize("n,na,nb", [(10, 5, 5), (11, 6, 5), (9, 2, 6), (8, 1, 7), (6, 0, 3)])
+def test_product_kernel_matches_oracle_shapes(n, na, nb):
+    """String-product kernel over uneven fillings (the batched solves' shapes)."""
+    announce(f"product kernel n={n} {na}+{nb}")
+    s, h, g = make_system(n, na, nb, seed=n)
+    keys = space.full_space(n, na, nb)
+    w = np.random.default_rng(12).normal(size=keys.size)
+    u = host(s.apply_hamiltonian(dev(w)))
+    assert rel_err(u, capply.apply(n, h, g, keys, w)) <= 1e-12
