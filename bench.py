@@ -69,7 +69,7 @@ def read_traffic(kernel, workload, src_hash):
     return float(m_val.group(1))
 
 
-def cpu_baseline(wl, keys_fn, applies_per_step, sample_rows=100_000, chunk=20_000):
+def cpu_baseline(wl, keys_fn, applies_per_step, sample_rows=1_000_000, chunk=20_000):
     """The oracle's matrix-free apply (oracle.nqs rows, oracle C Slater-Condon
     rows, numpy products) timed on a row sample and scaled to one step."""
     import numpy as np
@@ -126,6 +126,8 @@ def main():
     ap.add_argument("--config", default="c2", choices=["c1", "c2"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--force-hash", action="store_true", help="general hashed Hamiltonian kernel")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only copy MIB MiB device-to-device (HBM counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -143,6 +145,15 @@ def main():
         print("bench.py needs a HIP device", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        nbytes = args.copy_calibration << 20
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": nbytes}), flush=True)
+        return
     wl = synth.WORKLOADS[args.config]
     h, g = wl.integrals()
     log(f"workload {wl.name}: n={wl.n} {wl.na}a+{wl.nb}b V={wl.V} H={wl.H} P={wl.P} m={wl.m} k={wl.k}")
@@ -198,7 +209,7 @@ def main():
     kern = {k: {"ms_total": v[0], "launches": v[1], "ms_avg": v[0] / v[1] if v[1] else None}
             for k, v in stats.items()}
     dominant = max(kern, key=lambda k: kern[k]["ms_total"])
-    src = [os.path.join(ROOT, "paper_2601_01437_amd", "csrc", f) for f in ("dtilde.hip",)]
+    src = [os.path.join(ROOT, "paper_2601_01437_amd", "csrc", f) for f in ("dtilde.hip", "internal.h")]
     src_hash = source_hash(src)
     roof = None
     hbm_kinds = ("gemv", "gemv_t", "dtilde_build")

@@ -483,6 +483,140 @@ __global__ __launch_bounds__(kProdThreads) void k_ham_product(ProdArgs P, const 
     if (valid) u[rb * P.nA + ra] = acc;
 }
 
+// LDS-staged variant (nA <= kProdLdsMaxA): the own beta row of w, the beta'
+// row of the current beta move and the g slice live in LDS (double-buffered
+// over the beta moves, one barrier per move); the thread's alpha moves are
+// packed one per register: rank | (i n + a) << 16 | sign << 31.
+constexpr int kProd2Threads = 512;
+constexpr int kProdLdsMaxA = 2048;
+
+template <int NSA>
+__global__ __launch_bounds__(kProd2Threads) void k_ham_product_lds(ProdArgs P,
+                                                                   const double *__restrict__ w,
+                                                                   double *__restrict__ u)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int n = P.n, n2 = n * n;
+    const int nA = (int)P.nA;
+    double *wself = reinterpret_cast<double *>(smem);
+    double *wb0 = wself + nA;
+    double *wb1 = wb0 + nA;
+    double *gs0 = wb1 + nA;
+    double *gs1 = gs0 + n2;
+    double *jbl = gs1 + n2;
+    double *sb_f = jbl + n2;
+    double *db_val = sb_f + P.nsb;
+    int32_t *sb_rank = reinterpret_cast<int32_t *>(db_val + P.ndb);
+    int32_t *db_rank = sb_rank + P.nsb;
+    uint16_t *sb_ia = reinterpret_cast<uint16_t *>(db_rank + P.ndb);
+
+    const int64_t rb = blockIdx.y;
+    const int ra = blockIdx.x * kProd2Threads + threadIdx.x;
+    const bool valid = ra < nA;
+    const int rac = valid ? ra : 0;
+    const double *wrow = w + rb * P.nA;
+    for (int p = threadIdx.x; p < nA; p += kProd2Threads) wself[p] = wrow[p];
+    for (int p = threadIdx.x; p < n2; p += kProd2Threads) jbl[p] = P.B.J[(int64_t)p * P.nB + rb];
+    for (int f = threadIdx.x; f < P.nsb; f += kProd2Threads) {
+        sb_rank[f] = P.B.srank[(int64_t)f * P.nB + rb];
+        sb_ia[f] = P.B.sia[(int64_t)f * P.nB + rb];
+        sb_f[f] = P.B.sf[(int64_t)f * P.nB + rb];
+    }
+    for (int d = threadIdx.x; d < P.ndb; d += kProd2Threads) {
+        db_rank[d] = P.B.drank[(int64_t)d * P.nB + rb];
+        db_val[d] = P.B.dval[(int64_t)d * P.nB + rb];
+    }
+    __syncthreads();
+    // stage the first beta move
+    if (P.nsb > 0) {
+        const int j = sb_ia[0] & 31, b = (sb_ia[0] >> 5) & 31;
+        const double *src = w + (int64_t)sb_rank[0] * P.nA;
+        for (int p = threadIdx.x; p < nA; p += kProd2Threads) wb0[p] = src[p];
+        for (int p = threadIdx.x; p < n2; p += kProd2Threads) gs0[p] = P.g[(int64_t)p * n2 + j * n + b];
+    }
+    double acc = P.diag[rb * P.nA + rac] * wself[rac];
+    uint32_t pk[NSA];
+#pragma unroll
+    for (int e = 0; e < NSA; ++e) {
+        if (e < P.nsa) {
+            const int32_t rk = P.A.srank[(int64_t)e * P.nA + rac];
+            const uint16_t q = P.A.sia[(int64_t)e * P.nA + rac];
+            const int i = q & 31, a = (q >> 5) & 31;
+            const double v = P.A.sf[(int64_t)e * P.nA + rac] + jbl[i * n + a];
+            acc += ((q >> 10) & 1 ? -v : v) * wself[rk];
+            pk[e] = (uint32_t)rk | ((uint32_t)(i * n + a) << 16) | ((uint32_t)((q >> 10) & 1) << 31);
+        } else {
+            pk[e] = 0;
+        }
+    }
+    for (int d = 0; d < P.nda; ++d)
+        acc += P.A.dval[(int64_t)d * P.nA + rac] * wself[P.A.drank[(int64_t)d * P.nA + rac]];
+    for (int f = 0; f < P.nsb; ++f) {
+        const int j = sb_ia[f] & 31, b = (sb_ia[f] >> 5) & 31;
+        const double v = sb_f[f] + P.A.J[(int64_t)(j * n + b) * P.nA + rac];
+        acc += ((sb_ia[f] >> 10) & 1 ? -v : v) * w[(int64_t)sb_rank[f] * P.nA + rac];
+    }
+    for (int d = 0; d < P.ndb; ++d) acc += db_val[d] * w[(int64_t)db_rank[d] * P.nA + rac];
+    __syncthreads();
+    // opposite-spin doubles, double-buffered over the beta moves
+    constexpr int PFW = (kProdLdsMaxA + kProd2Threads - 1) / kProd2Threads;
+    constexpr int PFG = (32 * 32 + kProd2Threads - 1) / kProd2Threads;
+    for (int f = 0; f < P.nsb; ++f) {
+        const double *wb = (f & 1) ? wb1 : wb0;
+        const double *gs = (f & 1) ? gs1 : gs0;
+        double pw[PFW], pg[PFG];
+        const bool more = f + 1 < P.nsb;
+        if (more) {
+            const int j = sb_ia[f + 1] & 31, b = (sb_ia[f + 1] >> 5) & 31;
+            const double *src = w + (int64_t)sb_rank[f + 1] * P.nA;
+#pragma unroll
+            for (int t = 0; t < PFW; ++t) {
+                const int p = threadIdx.x + t * kProd2Threads;
+                pw[t] = p < nA ? src[p] : 0.0;
+            }
+#pragma unroll
+            for (int t = 0; t < PFG; ++t) {
+                const int p = threadIdx.x + t * kProd2Threads;
+                pg[t] = p < n2 ? P.g[(int64_t)p * n2 + j * n + b] : 0.0;
+            }
+        }
+        double part = 0.0;
+#pragma unroll
+        for (int e = 0; e < NSA; ++e) {
+            if (e < P.nsa) {
+                const uint32_t q = pk[e];
+                const double ge = gs[(q >> 16) & 1023];
+                const double v = ge * wb[q & 0xffffu];
+                part += (q >> 31) ? -v : v;
+            }
+        }
+        acc += (sb_ia[f] >> 10) & 1 ? -part : part;
+        if (more) {
+            double *wn = (f & 1) ? wb0 : wb1;
+            double *gn = (f & 1) ? gs0 : gs1;
+#pragma unroll
+            for (int t = 0; t < PFW; ++t) {
+                const int p = threadIdx.x + t * kProd2Threads;
+                if (p < nA) wn[p] = pw[t];
+            }
+#pragma unroll
+            for (int t = 0; t < PFG; ++t) {
+                const int p = threadIdx.x + t * kProd2Threads;
+                if (p < n2) gn[p] = pg[t];
+            }
+        }
+        __syncthreads();
+    }
+    if (valid) u[rb * P.nA + ra] = acc;
+}
+
+static size_t product_lds_bytes(const ProdArgs &P)
+{
+    const size_t n2 = (size_t)P.n * P.n;
+    return (3 * (size_t)P.nA + 3 * n2 + P.nsb + P.ndb) * 8 + (size_t)(P.nsb + P.ndb) * 4 +
+           (size_t)P.nsb * 2;
+}
+
 static bool product_fits(const irl_system *s, int &nsa, int &nsb, int &nda, int &ndb)
 {
     const int n = s->n, na = s->na, nb = s->nb, va = n - na, vb = n - nb;
@@ -554,8 +688,14 @@ static StrTables tables_of(const irl_system *s, bool alpha)
 template <int NSA>
 static void launch_prod_inst(const ProdArgs &P, const double *w, double *u, hipStream_t st)
 {
-    dim3 grid((unsigned)((P.nA + kProdThreads - 1) / kProdThreads), (unsigned)P.nB);
-    k_ham_product<NSA><<<grid, kProdThreads, 0, st>>>(P, w, u);
+    const size_t lds = product_lds_bytes(P);
+    if (P.nA <= kProdLdsMaxA && lds <= 64 * 1024) {
+        dim3 grid((unsigned)((P.nA + kProd2Threads - 1) / kProd2Threads), (unsigned)P.nB);
+        k_ham_product_lds<NSA><<<grid, kProd2Threads, lds, st>>>(P, w, u);
+    } else {
+        dim3 grid((unsigned)((P.nA + kProdThreads - 1) / kProdThreads), (unsigned)P.nB);
+        k_ham_product<NSA><<<grid, kProdThreads, 0, st>>>(P, w, u);
+    }
 }
 
 static hipError_t launch_ham_product(const irl_system *s, const double *w, double *u, hipStream_t st)
