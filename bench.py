@@ -123,7 +123,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", default="c2", choices=["c1", "c2"])
+    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c3s"])
+    ap.add_argument("--precision", default=None, choices=["fp64", "fp32"],
+                    help="operator precision (default: the workload's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--force-hash", action="store_true", help="general hashed Hamiltonian kernel")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -158,21 +160,26 @@ def main():
     h, g = wl.integrals()
     log(f"workload {wl.name}: n={wl.n} {wl.na}a+{wl.nb}b V={wl.V} H={wl.H} P={wl.P} m={wl.m} k={wl.k}")
     t = time.perf_counter()
-    sysm = System(wl.n, wl.na, wl.nb, h, g, flags=B.IRL_SYS_FORCE_HASH if args.force_hash else 0)
+    dets = wl.dets()
+    sysm = System(wl.n, wl.na, wl.nb, h, g, dets=dets,
+                  flags=B.IRL_SYS_FORCE_HASH if args.force_hash else 0)
     torch.cuda.synchronize()
     setup_ms = (time.perf_counter() - t) * 1e3
     ns = sysm.ns
     log(f"system ready: {ns} determinants, ham kernel {sysm.info.ham_kernel}, {setup_ms:.1f} ms")
     theta0 = torch.tensor(wl.theta(), dtype=torch.float64, device="cuda")
     theta = theta0.clone()
-    ws_flags = B.IRL_WS_FP64
+    prec_name = args.precision or wl.precision
+    precision = B.IRL_FP64 if prec_name == "fp64" else B.IRL_FP32
+    ws_flags = B.IRL_WS_FP64 | (B.IRL_WS_FP32 if precision == B.IRL_FP32 else 0)
+    sD = 8 if precision == B.IRL_FP64 else 4
     sysm.workspace(wl.P + 1, ws_flags)
     log(f"workspace {sysm.ws.numel() / 2**30:.2f} GiB")
 
     def one_step():
         rc, r, _, _ = sysm.step(theta, wl.V, wl.H, m=wl.m, k_keep=wl.k, tol=1e-12,
-                                flags=B.IRL_STEP_NO_EVAL_AFTER, ws_flags=ws_flags,
-                                want_dtheta=False)
+                                precision=precision, flags=B.IRL_STEP_NO_EVAL_AFTER,
+                                ws_flags=ws_flags, want_dtheta=False)
         return rc, r
 
     for i in range(args.warmup):
@@ -214,7 +221,8 @@ def main():
     roof = None
     hbm_kinds = ("gemv", "gemv_t", "dtilde_build")
     roof_kernel = dominant if dominant in hbm_kinds else max(hbm_kinds, key=lambda k: kern[k]["ms_total"])
-    nbytes = kernel_bytes(roof_kernel, ns, ncols, 8)
+    s_build = 8 + (4 if ws_flags & B.IRL_WS_FP32 else 0)    # both copies are written
+    nbytes = kernel_bytes(roof_kernel, ns, ncols, s_build if roof_kernel == "dtilde_build" else sD)
     avg = kern[roof_kernel]["ms_avg"]
     if avg:
         achieved = nbytes / (avg * 1e-3) / 1e9
@@ -224,7 +232,7 @@ def main():
                 "bytes_per_launch": nbytes, "ms_avg": avg, "source_hash": src_hash}
     # whole operator apply
     op_ms = sum(kern[k]["ms_total"] for k in ("gemv", "gemv_t", "reduce", "ham_apply"))
-    per_apply_bytes = 2 * ns * ncols * 8 + 6 * 8 * ns
+    per_apply_bytes = 2 * ns * ncols * sD + 6 * 8 * ns
     n_op = kern["gemv"]["launches"]
     operator = None
     if n_op:
@@ -241,8 +249,8 @@ def main():
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle on a row sample)")
         from oracle import space
-        cpu = cpu_baseline(wl, lambda: space.full_space(wl.n, wl.na, wl.nb),
-                           applies_per_step=applies / args.steps)
+        keys_fn = (lambda: space.full_space(wl.n, wl.na, wl.nb)) if dets is None else (lambda: dets)
+        cpu = cpu_baseline(wl, keys_fn, applies_per_step=applies / args.steps)
         log(f"cpu baseline: {cpu['ms_per_step']:.0f} ms per step")
 
     out = {
@@ -256,12 +264,14 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if precision == B.IRL_FP64 else "f32 operator / f64 solver",
         "data": "synthetic",
-        "config": {"workload": (f"{wl.name}: {wl.n} orbitals {wl.na}a+{wl.nb}b full space "
+        "config": {"workload": (f"{wl.name}: {wl.n} orbitals {wl.na}a+{wl.nb}b "
+                                f"{'full space' if dets is None else 'selected set'} "
                                 f"({ns} determinants), random molecule-like integrals seed {wl.seed}, "
                                 f"one-hidden-layer tanh network V={wl.V} H={wl.H} (P={wl.P}), "
-                                f"D~ {ns}x{ncols} FP64, IRL m={wl.m} k_keep={wl.k} tol=1e-12"),
+                                f"D~ {ns}x{ncols} {prec_name.upper()}, IRL m={wl.m} k_keep={wl.k} "
+                                f"tol=1e-12"),
                    "n_dets": ns, "P": wl.P, "m": wl.m, "k_keep": wl.k,
                    "ham_kernel": ["hashed-pull", "rank-pull", "string-product"][sysm.info.ham_kernel]},
         "roofline": roof,

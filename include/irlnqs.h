@@ -80,7 +80,10 @@ enum irl_ws_flags {
 enum irl_step_flags {
     IRL_STEP_WS_CURRENT = 1u,    /* ws already holds D~, Z, E, g for *theta; skip evaluation */
     IRL_STEP_NO_EVAL_AFTER = 2u, /* do not evaluate E(theta + dtheta) after the update */
-    IRL_STEP_NO_UPDATE = 4u      /* solve only; leave theta unchanged */
+    IRL_STEP_NO_UPDATE = 4u,     /* solve only; leave theta unchanged */
+    IRL_STEP_NO_POLISH = 8u,     /* FP32 solve: skip the FP64 polish (see irl_step) */
+    IRL_STEP_FULL_CYCLES = 16u   /* test convergence only at the end of each m-step cycle
+                                    (no early Ritz tests inside a cycle) */
 };
 
 /* K4 variant selection (irl_system_desc.flags) */
@@ -154,7 +157,7 @@ typedef struct {
     int32_t n_apply;        /* operator applies used by the solve */
     int32_t n_restart;      /* restart cycles */
     int32_t converged;      /* 1 if the residual test passed */
-    int32_t reserved;
+    int32_t n_apply_lo;     /* of n_apply, the reduced-precision (FP32) applies */
     double ms_eval, ms_solve, ms_after;   /* host wall time of each phase */
 } irl_step_result;
 
@@ -246,7 +249,14 @@ int irl_apply_hamiltonian(irl_system *sys, const double *w, double *u, void *str
  *     vectors per restart, exact shifts = the m - k_keep largest Ritz values,
  *     full (two-pass classical Gram-Schmidt) reorthogonalisation, convergence
  *     when the Ritz residual estimate is below max(tol, 64 u_op ||T_m||),
- *     confirmed by one explicit apply;
+ *     confirmed by one explicit apply; on operators that stream >= 256 MB per
+ *     apply the Ritz pair of T_j is also tested every 2 steps inside a cycle
+ *     (IRL_STEP_FULL_CYCLES disables this);
+ *     With precision IRL_FP32 the operator's D~ products use the FP32 copy and
+ *     the centred matrix takes its psi row and column from the FP64 gradient
+ *     (split form); if the workspace also holds the FP64 copy, the solve is
+ *     then polished in FP64 from the FP32 Ritz vector (unless
+ *     IRL_STEP_NO_POLISH), so the result meets the FP64 tolerance;
  *  3. mode A: dtheta = c[1:] / c[0]; unless IRL_STEP_NO_UPDATE theta += dtheta;
  *  4. unless IRL_STEP_NO_EVAL_AFTER: evaluate at the new theta (ws then holds
  *     D~ for the new theta, so the next call may pass IRL_STEP_WS_CURRENT).

@@ -81,3 +81,34 @@ class Operator:
             return apply(self.n, self.h, self.g, self.keys, w)
         return np.stack([apply(self.n, self.h, self.g, self.keys, w[:, j])
                          for j in range(w.shape[1])], axis=1)
+
+
+def csr(n: int, h: np.ndarray, g: np.ndarray, keys: np.ndarray):
+    """Hamiltonian projected on the set as scipy CSR, row by row through the C
+    rules (same elements as ``hamiltonian.build``)."""
+    import scipy.sparse as sp
+    lib = _load()
+    if not hasattr(lib, "_row_ready"):
+        lib.oracle_sc_row.restype = ctypes.c_int64
+        lib.oracle_sc_row.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                      ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
+                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64]
+        lib._row_ready = True
+    h = np.ascontiguousarray(h, dtype=np.float64)
+    g = np.ascontiguousarray(g, dtype=np.float64)
+    keys = np.ascontiguousarray(keys, dtype=np.uint64)
+    cap = 1 << 17
+    cols = np.empty(cap, dtype=np.int64)
+    vals = np.empty(cap, dtype=np.float64)
+    indptr = [0]
+    all_c, all_v = [], []
+    for r in range(keys.size):
+        c = lib.oracle_sc_row(n, h.ctypes.data, g.ctypes.data, keys.ctypes.data, keys.size, r,
+                              cols.ctypes.data, vals.ctypes.data, cap)
+        assert c <= cap
+        order = np.argsort(cols[:c], kind="stable")
+        all_c.append(cols[:c][order].copy())
+        all_v.append(vals[:c][order].copy())
+        indptr.append(indptr[-1] + c)
+    return sp.csr_matrix((np.concatenate(all_v), np.concatenate(all_c), np.array(indptr)),
+                         shape=(keys.size, keys.size))

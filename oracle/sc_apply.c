@@ -129,3 +129,82 @@ void oracle_sc_apply(int n, const double *h, const double *g, const uint64_t *ke
         u[k] = row_apply(n, h, g, keys, ns, w, keys[r]);
     }
 }
+
+/* Connections of one row inside the set (diagonal first, then every single
+ * and double that lands in the set, in enumeration order; duplicates cannot
+ * occur).  Writes up to cap (col, value) pairs, returns the count. */
+int64_t oracle_sc_row(int n, const double *h, const double *g, const uint64_t *keys, int64_t ns,
+                      int64_t row, int64_t *cols, double *vals, int64_t cap)
+{
+    uint64_t key = keys[row];
+    uint32_t al = (uint32_t)(key & 0xffffffffu), be = (uint32_t)(key >> 32);
+    int oa[32], ob[32], va[32], vb[32], noa = 0, nob = 0, nva = 0, nvb = 0;
+    for (int p = 0; p < n; ++p) {
+        if (al >> p & 1u) oa[noa++] = p; else va[nva++] = p;
+        if (be >> p & 1u) ob[nob++] = p; else vb[nvb++] = p;
+    }
+    int64_t c = 0;
+#define EMIT(col, val) do { if (c < cap) { cols[c] = (col); vals[c] = (val); } ++c; } while (0)
+    double d = 0.0;
+    for (int x = 0; x < noa; ++x) d += h[oa[x] * n + oa[x]];
+    for (int x = 0; x < nob; ++x) d += h[ob[x] * n + ob[x]];
+    for (int x = 0; x < noa; ++x)
+        for (int y = 0; y < noa; ++y)
+            d += 0.5 * (G(oa[x], oa[x], oa[y], oa[y]) - G(oa[x], oa[y], oa[y], oa[x]));
+    for (int x = 0; x < nob; ++x)
+        for (int y = 0; y < nob; ++y)
+            d += 0.5 * (G(ob[x], ob[x], ob[y], ob[y]) - G(ob[x], ob[y], ob[y], ob[x]));
+    for (int x = 0; x < noa; ++x)
+        for (int y = 0; y < nob; ++y)
+            d += G(oa[x], oa[x], ob[y], ob[y]);
+    EMIT(row, d);
+    for (int spin = 0; spin < 2; ++spin) {
+        const int *os = spin ? ob : oa, *oo = spin ? oa : ob, *vs = spin ? vb : va;
+        int nos = spin ? nob : noa, noo = spin ? noa : nob, nvs = spin ? nvb : nva;
+        uint32_t bits = spin ? be : al;
+        for (int x = 0; x < nos; ++x)
+            for (int u = 0; u < nvs; ++u) {
+                int i = os[x], a = vs[u];
+                uint32_t nb = (bits & ~(1u << i)) | (1u << a);
+                uint64_t t = spin ? ((uint64_t)al | ((uint64_t)nb << 32))
+                                  : ((uint64_t)nb | ((uint64_t)be << 32));
+                int64_t r = find_key(keys, ns, t);
+                if (r < 0) continue;
+                double v = h[i * n + a];
+                for (int y = 0; y < nos; ++y) v += G(i, a, os[y], os[y]) - G(i, os[y], os[y], a);
+                for (int y = 0; y < noo; ++y) v += G(i, a, oo[y], oo[y]);
+                EMIT(r, parity_between(bits, i, a) * v);
+            }
+        for (int x = 0; x < nos; ++x)
+            for (int y = x + 1; y < nos; ++y)
+                for (int u = 0; u < nvs; ++u)
+                    for (int z = u + 1; z < nvs; ++z) {
+                        int i = os[x], j = os[y], a = vs[u], b = vs[z];
+                        int s1 = parity_between(bits, i, a);
+                        uint32_t b1 = (bits & ~(1u << i)) | (1u << a);
+                        int s2 = parity_between(b1, j, b);
+                        uint32_t b2 = (b1 & ~(1u << j)) | (1u << b);
+                        uint64_t t = spin ? ((uint64_t)al | ((uint64_t)b2 << 32))
+                                          : ((uint64_t)b2 | ((uint64_t)be << 32));
+                        int64_t r = find_key(keys, ns, t);
+                        if (r >= 0) EMIT(r, s1 * s2 * (G(i, a, j, b) - G(i, b, j, a)));
+                    }
+    }
+    for (int x = 0; x < noa; ++x)
+        for (int u = 0; u < nva; ++u) {
+            int i = oa[x], a = va[u];
+            int s1 = parity_between(al, i, a);
+            uint32_t a1 = (al & ~(1u << i)) | (1u << a);
+            for (int y = 0; y < nob; ++y)
+                for (int z = 0; z < nvb; ++z) {
+                    int j = ob[y], b = vb[z];
+                    int s2 = parity_between(be, j, b);
+                    uint32_t b1 = (be & ~(1u << j)) | (1u << b);
+                    int64_t r = find_key(keys, ns, (uint64_t)a1 | ((uint64_t)b1 << 32));
+                    if (r >= 0) EMIT(r, s1 * s2 * G(i, a, j, b));
+                }
+        }
+#undef EMIT
+    (void)0;
+    return c;
+}

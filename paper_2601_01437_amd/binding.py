@@ -26,7 +26,8 @@ IRL_EINVAL, IRL_ENOMEM, IRL_EDEVICE, IRL_ESTATE = -1, -2, -3, -4
 IRL_FP64, IRL_FP32 = 0, 1
 IRL_MODE_A, IRL_MODE_P = 0, 1
 IRL_WS_FP64, IRL_WS_FP32 = 1, 2
-IRL_STEP_WS_CURRENT, IRL_STEP_NO_EVAL_AFTER, IRL_STEP_NO_UPDATE = 1, 2, 4
+IRL_STEP_WS_CURRENT, IRL_STEP_NO_EVAL_AFTER, IRL_STEP_NO_UPDATE, IRL_STEP_NO_POLISH = 1, 2, 4, 8
+IRL_STEP_FULL_CYCLES = 16
 IRL_SYS_FORCE_HASH = 1
 IRL_SYS_FORCE_PULL = 2
 STAT_KINDS = ("dtilde_build", "ham_apply", "gemv", "gemv_t", "reduce", "energy", "lanczos", "ritz")
@@ -73,11 +74,11 @@ class irl_step_result(ctypes.Structure):
                 ("residual_est", c_double), ("residual_explicit", c_double),
                 ("tol_used", c_double), ("c0", c_double), ("gap", c_double),
                 ("norm_T", c_double), ("n_apply", c_int32), ("n_restart", c_int32),
-                ("converged", c_int32), ("reserved", c_int32), ("ms_eval", c_double),
+                ("converged", c_int32), ("n_apply_lo", c_int32), ("ms_eval", c_double),
                 ("ms_solve", c_double), ("ms_after", c_double)]
 
     def as_dict(self):
-        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 _SYS = c_void_p

@@ -70,7 +70,7 @@ void free_system(irl_system *s)
     void *ptrs[] = {s->d.keys, s->d.h, s->d.g, s->d.diag, s->d.hkeys, s->d.hrows, s->d.rankA,
                     s->d.rankB, s->d.strA, s->d.strB, s->d.sglA, s->d.sglB, s->d.fA, s->d.fB,
                     s->d.dblA_rank, s->d.dblA_val, s->d.dblB_rank, s->d.dblB_val, s->d.jA,
-                    s->d.jB, s->d.sglA_ia, s->d.sglB_ia};
+                    s->d.jB, s->d.sglA_ia, s->d.sglB_ia, s->d.hfilter};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (s->host_scal) (void)hipHostFree(s->host_scal);
@@ -173,12 +173,12 @@ int energy_and_gradient(irl_system *s, void *ws, const WsLayout &L, hipStream_t 
     return IRL_OK;
 }
 
-// the operator pair into ws yH/yS (internal, ldv long)
+// the operator pair into ws yH/yS (internal, ldv long); zero_v0: apply to (0, v[1:])
 int apply_internal(irl_system *s, void *ws, const WsLayout &L, const double *v, double *yH,
-                   double *yS, int prec, hipStream_t st)
+                   double *yS, int prec, hipStream_t st, int zero_v0 = 0)
 {
     double *w = ws_ptr<double>(ws, L.off_w), *u = ws_ptr<double>(ws, L.off_u);
-    TIMED(s, IRL_STAT_GEMV, st, launch_gemv_rows(L, ws, prec, v, w, st));
+    TIMED(s, IRL_STAT_GEMV, st, launch_gemv_rows(L, ws, prec, v, w, zero_v0, st));
     TIMED(s, IRL_STAT_HAM_APPLY, st, launch_ham_apply(s, w, u, st));
     int nblk = 1;
     TIMED(s, IRL_STAT_GEMV_T, st, launch_gemv_t2(L, ws, prec, w, u, nullptr, nullptr, &nblk, st));
@@ -237,6 +237,128 @@ WsLayout make_layout(int64_t ns, int64_t ncols, uint32_t flags)
 }
 
 }  // namespace irl
+
+namespace {
+
+// One implicitly restarted Lanczos solve of the centred operator at precision
+// prec, from a random start vector or from start (device, ldv doubles).  On
+// return the unit Ritz vector is in ws y.
+struct SolveOut {
+    double lam = 0, resid_est = 0, resid_explicit = 0, gap = 0, normT = 0, c0 = 0, tol_used = 0;
+    int n_apply = 0, n_restart = 0, converged = 0;
+};
+
+int irl_solve(irl_system *s, void *ws, const WsLayout &L, const irl_solver_opts &o, int prec,
+              const double *start, SolveOut &out, hipStream_t st)
+{
+    const int64_t dim = (o.mode == IRL_MODE_A) ? L.ncols : L.ncols - 1;
+    const int m = (int)std::min<int64_t>(o.m, dim);
+    const int k = std::min(o.k_keep, m - 1);
+    if (m < 2 || k < 1) return set_err(s, IRL_EINVAL, "problem dimension too small for the Krylov space");
+    const double u_op = (prec == IRL_FP64) ? 1.1102230246251565e-16 : 5.960464477539063e-08;
+    // reduced-precision operator: psi row/column of H~' from the FP64 gradient (split form)
+    const int split = (prec == IRL_FP32) ? 1 : 0;
+    double *Vb[2] = {ws_ptr<double>(ws, L.off_kry0), ws_ptr<double>(ws, L.off_kry1)};
+    int cur = 0;
+    double *yH = ws_ptr<double>(ws, L.off_yh), *yS = ws_ptr<double>(ws, L.off_ys);
+    double *y = ws_ptr<double>(ws, L.off_y), *rv = ws_ptr<double>(ws, L.off_r);
+    int rc;
+    TIMED(s, IRL_STAT_RITZ, st, launch_reset_solve(L, ws, st));
+    if (start) {
+        TIMED(s, IRL_STAT_RITZ, st, launch_copy(Vb[0], start, L.ldv, st));
+    } else {
+        TIMED(s, IRL_STAT_RITZ, st, launch_start_vector(Vb[0], L.ncols, L.ldv, o.mode, o.seed, st));
+    }
+    int j0 = 0, n_apply = 0, n_restart = 0;
+    bool converged = false;
+    double tol_eff = o.tol;
+    // Early checks: on large operators the Ritz pair of T_j is also tested every
+    // `stride` Lanczos steps inside a cycle (an m-step cycle otherwise runs to the
+    // end before its convergence test).  A check costs one small kernel and one
+    // stream synchronisation, negligible next to an apply that streams >= 256 MB.
+    const double apply_bytes = 2.0 * (double)L.ns * (double)L.ldv * (prec == IRL_FP64 ? 8.0 : 4.0);
+    const int stride = (o.flags & IRL_STEP_FULL_CYCLES) ? 0 : (apply_bytes >= 2.56e8 ? 2 : 0);
+    for (;;) {
+        int mc = m;   // size of the tridiagonal tested at the end of this pass
+        bool early = false;
+        for (int j = j0; j < m; ++j) {
+            rc = apply_internal(s, ws, L, Vb[cur] + (int64_t)j * L.ldv, yH, yS, prec, st, split);
+            if (rc) return rc;
+            ++n_apply;
+            TIMED(s, IRL_STAT_LANCZOS, st,
+                  launch_lanczos_step(L, ws, Vb[cur], j, o.mode, split,
+                                      o.seed + 0x100000001b3ull * (uint64_t)(n_restart + 1), st));
+            if (stride && j + 1 < m && j + 1 >= 2 && (j + 1 - j0) % stride == 0) {
+                TIMED(s, IRL_STAT_RITZ, st, launch_ritz(L, ws, j + 1, 0, st));
+                rc = read_scalars(s, ws, L, st);
+                if (rc) return rc;
+                const double tq = std::max(o.tol, 64.0 * u_op * s->host_scal->normT);
+                if (s->host_scal->resid_est <= tq && std::isfinite(s->host_scal->lam)) {
+                    mc = j + 1;
+                    early = true;
+                    break;
+                }
+            }
+        }
+        if (!early) TIMED(s, IRL_STAT_RITZ, st, launch_ritz(L, ws, m, k, st));
+        rc = read_scalars(s, ws, L, st);
+        if (rc) return rc;
+        const WsScalars &hs = *s->host_scal;
+        tol_eff = std::max(o.tol, 64.0 * u_op * hs.normT);
+        out.lam = hs.lam;
+        out.resid_est = hs.resid_est;
+        out.gap = hs.gap;
+        out.normT = hs.normT;
+        if (!std::isfinite(hs.lam)) return set_err(s, IRL_EINVAL, "non-finite Ritz value (check theta and D~)");
+        if (hs.resid_est <= tol_eff) {
+            TIMED(s, IRL_STAT_RITZ, st, launch_ritz_vector(L, ws, Vb[cur], mc, y, st));
+            rc = apply_internal(s, ws, L, y, yH, yS, prec, st, split);
+            if (rc) return rc;
+            ++n_apply;
+            TIMED(s, IRL_STAT_RITZ, st, launch_residual(L, ws, y, rv, o.mode, split, st));
+            rc = read_scalars(s, ws, L, st);
+            if (rc) return rc;
+            out.resid_explicit = std::sqrt(s->host_scal->resid2);
+            const double tol_explicit = std::max(tol_eff, 1024.0 * u_op * hs.normT);
+            if (out.resid_explicit <= tol_explicit) {
+                converged = true;
+                break;
+            }
+        }
+        if (early) {
+            // explicit test failed on an early candidate: continue the cycle
+            j0 = mc;
+            continue;
+        }
+        if (n_restart >= o.max_restarts) break;
+        TIMED(s, IRL_STAT_RITZ, st,
+              launch_restart_basis(L, ws, Vb[cur], Vb[1 - cur], m, k, o.mode,
+                                   o.seed ^ (0x9e3779b97f4a7c15ull * (uint64_t)(n_restart + 7)), st));
+        cur = 1 - cur;
+        j0 = k;
+        ++n_restart;
+    }
+    if (!converged) {
+        // report the current Ritz pair
+        TIMED(s, IRL_STAT_RITZ, st, launch_ritz(L, ws, m, 0, st));
+        TIMED(s, IRL_STAT_RITZ, st, launch_ritz_vector(L, ws, Vb[cur], m, y, st));
+        rc = apply_internal(s, ws, L, y, yH, yS, prec, st, split);
+        if (rc) return rc;
+        ++n_apply;
+        TIMED(s, IRL_STAT_RITZ, st, launch_residual(L, ws, y, rv, o.mode, split, st));
+        rc = read_scalars(s, ws, L, st);
+        if (rc) return rc;
+        out.resid_explicit = std::sqrt(s->host_scal->resid2);
+    }
+    out.c0 = s->host_scal->c0;
+    out.n_apply = n_apply;
+    out.n_restart = n_restart;
+    out.converged = converged ? 1 : 0;
+    out.tol_used = tol_eff;
+    return IRL_OK;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -345,6 +467,11 @@ int irl_system_create(const irl_system_desc *d, void *stream, irl_system **out)
         s->d.hcap = cap;
         AL(s->d.hkeys, cap);
         AL(s->d.hrows, cap);
+        // membership filter: ~16 bits per key, 2^16 .. 2^25 bits
+        int fb = 16;
+        while (fb < 25 && ((uint64_t)1 << fb) < 16 * (uint64_t)s->ns) ++fb;
+        s->d.hfbits = fb;
+        AL(s->d.hfilter, ((size_t)1 << fb) / 32);
     }
 #undef AL
     auto fail_dev = [&](hipError_t e, const char *what) {
@@ -363,7 +490,8 @@ int irl_system_create(const irl_system_desc *d, void *stream, irl_system **out)
             return fail_dev(e, "copy keys");
     }
     if (want_hash)
-        if ((e = launch_hash_build(s->d.keys, s->ns, s->d.hkeys, s->d.hrows, s->d.hcap, st)) != hipSuccess)
+        if ((e = launch_hash_build(s->d.keys, s->ns, s->d.hkeys, s->d.hrows, s->d.hcap, s->d.hfilter,
+                                   s->d.hfbits, st)) != hipSuccess)
             return fail_dev(e, "hash build");
     if ((e = launch_diagonal(s->d.keys, s->ns, n, s->d.h, s->d.g, s->d.diag, st)) != hipSuccess)
         return fail_dev(e, "diagonal");
@@ -519,77 +647,33 @@ int irl_step(irl_system *s, irl_nqs_desc *nqs, const irl_solver_opts *opts, void
     res.ms_eval = t1 - t0;
 
     // ---- implicitly restarted Lanczos ----
-    const int64_t dim = (o.mode == IRL_MODE_A) ? L.ncols : L.ncols - 1;
-    int m = (int)std::min<int64_t>(o.m, dim);
-    int k = std::min(o.k_keep, m - 1);
-    if (m < 2 || k < 1) return set_err(s, IRL_EINVAL, "problem dimension too small for the Krylov space");
-    const double u_op = (o.precision == IRL_FP64) ? 1.1102230246251565e-16 : 5.960464477539063e-08;
-    double *Vb[2] = {ws_ptr<double>(ws, L.off_kry0), ws_ptr<double>(ws, L.off_kry1)};
-    int cur = 0;
-    double *yH = ws_ptr<double>(ws, L.off_yh), *yS = ws_ptr<double>(ws, L.off_ys);
-    double *y = ws_ptr<double>(ws, L.off_y), *rv = ws_ptr<double>(ws, L.off_r);
-    CK(s, launch_reset_solve(L, ws, st));
-    CK(s, launch_start_vector(Vb[0], L.ncols, L.ldv, o.mode, o.seed, st));
-    int j0 = 0, n_apply = 0, n_restart = 0;
-    bool converged = false;
-    double tol_eff = o.tol;
-    for (;;) {
-        for (int j = j0; j < m; ++j) {
-            rc = apply_internal(s, ws, L, Vb[cur] + (int64_t)j * L.ldv, yH, yS, o.precision, st);
-            if (rc) return rc;
-            ++n_apply;
-            TIMED(s, IRL_STAT_LANCZOS, st, launch_lanczos_step(L, ws, Vb[cur], j, o.mode, o.seed + 0x100000001b3ull * (uint64_t)(n_restart + 1), st));
-        }
-        TIMED(s, IRL_STAT_RITZ, st, launch_ritz(L, ws, m, k, st));
-        rc = read_scalars(s, ws, L, st);
+    SolveOut so;
+    rc = irl_solve(s, ws, L, o, o.precision, nullptr, so, st);
+    if (rc) return rc;
+    int n_apply_lo = 0;
+    if (o.precision == IRL_FP32 && s->ws_has64 && !(o.flags & IRL_STEP_NO_POLISH)) {
+        // FP64 polish from the reduced-precision Ritz vector
+        n_apply_lo = so.n_apply;
+        SolveOut sp;
+        rc = irl_solve(s, ws, L, o, IRL_FP64, ws_ptr<double>(ws, L.off_y), sp, st);
         if (rc) return rc;
-        const WsScalars &hs = *s->host_scal;
-        tol_eff = std::max(o.tol, 64.0 * u_op * hs.normT);
-        res.lambda_min = hs.lam;
-        res.residual_est = hs.resid_est;
-        res.gap = hs.gap;
-        res.norm_T = hs.normT;
-        if (!std::isfinite(hs.lam)) return set_err(s, IRL_EINVAL, "non-finite Ritz value (check theta and D~)");
-        if (hs.resid_est <= tol_eff) {
-            TIMED(s, IRL_STAT_RITZ, st, launch_ritz_vector(L, ws, Vb[cur], m, y, st));
-            rc = apply_internal(s, ws, L, y, yH, yS, o.precision, st);
-            if (rc) return rc;
-            ++n_apply;
-            TIMED(s, IRL_STAT_RITZ, st, launch_residual(L, ws, y, rv, o.mode, st));
-            rc = read_scalars(s, ws, L, st);
-            if (rc) return rc;
-            res.residual_explicit = std::sqrt(s->host_scal->resid2);
-            const double tol_explicit = std::max(tol_eff, 1024.0 * u_op * hs.normT);
-            if (res.residual_explicit <= tol_explicit) {
-                converged = true;
-                break;
-            }
-        }
-        if (n_restart >= o.max_restarts) break;
-        TIMED(s, IRL_STAT_RITZ, st,
-              launch_restart_basis(L, ws, Vb[cur], Vb[1 - cur], m, k, o.mode,
-                                   o.seed ^ (0x9e3779b97f4a7c15ull * (uint64_t)(n_restart + 7)), st));
-        cur = 1 - cur;
-        j0 = k;
-        ++n_restart;
+        sp.n_apply += so.n_apply;
+        sp.n_restart += so.n_restart;
+        so = sp;
     }
-    if (!converged) {
-        // report the current Ritz pair
-        TIMED(s, IRL_STAT_RITZ, st, launch_ritz(L, ws, m, 0, st));
-        TIMED(s, IRL_STAT_RITZ, st, launch_ritz_vector(L, ws, Vb[cur], m, y, st));
-        rc = apply_internal(s, ws, L, y, yH, yS, o.precision, st);
-        if (rc) return rc;
-        ++n_apply;
-        TIMED(s, IRL_STAT_RITZ, st, launch_residual(L, ws, y, rv, o.mode, st));
-        rc = read_scalars(s, ws, L, st);
-        if (rc) return rc;
-        res.residual_explicit = std::sqrt(s->host_scal->resid2);
-    }
-    res.c0 = s->host_scal->c0;
-    res.n_apply = n_apply;
-    res.n_restart = n_restart;
-    res.converged = converged ? 1 : 0;
-    res.tol_used = tol_eff;
+    double *y = ws_ptr<double>(ws, L.off_y);
+    res.lambda_min = so.lam;
+    res.residual_est = so.resid_est;
+    res.residual_explicit = so.resid_explicit;
+    res.gap = so.gap;
+    res.norm_T = so.normT;
+    res.c0 = so.c0;
+    res.n_apply = so.n_apply;
+    res.n_restart = so.n_restart;
+    res.converged = so.converged;
+    res.tol_used = so.tol_used;
+    res.n_apply_lo = n_apply_lo;
+    const bool converged = so.converged != 0;
     if (ritz) {
         if (o.mode == IRL_MODE_A)
             CK(s, hipMemcpyAsync(ritz, y, L.ncols * 8, hipMemcpyDeviceToDevice, st));
@@ -757,10 +841,11 @@ int irl_debug_lanczos(irl_system *s, void *ws, size_t ws_bytes, const double *v1
     CK(s, launch_reset_solve(L, ws, st));
     CK(s, hipMemsetAsync(V, 0, L.ldv * 8, st));
     CK(s, hipMemcpyAsync(V, v1, L.ncols * 8, hipMemcpyDeviceToDevice, st));
+    const int split = (precision == IRL_FP32) ? 1 : 0;
     for (int j = 0; j < j_end; ++j) {
-        rc = apply_internal(s, ws, L, V + (int64_t)j * L.ldv, yH, yS, precision, st);
+        rc = apply_internal(s, ws, L, V + (int64_t)j * L.ldv, yH, yS, precision, st, split);
         if (rc) return rc;
-        CK(s, launch_lanczos_step(L, ws, V, j, mode, 12345, st));
+        CK(s, launch_lanczos_step(L, ws, V, j, mode, split, 12345, st));
     }
     rc = read_scalars(s, ws, L, st);
     if (rc) return rc;

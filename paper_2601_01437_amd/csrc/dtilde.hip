@@ -47,14 +47,15 @@ constexpr size_t kMaxLdsBytes = 64 * 1024;
 template <typename T, bool VLDS>
 __global__ __launch_bounds__(256) void k_gemv_rows(const T *__restrict__ D, int64_t ld, int64_t ns,
                                                    const double *__restrict__ v, int64_t nv,
-                                                   const T *__restrict__ vglob,
+                                                   const T *__restrict__ vglob, int c0,
                                                    double *__restrict__ w)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const T *vs = vglob;
     if constexpr (VLDS) {
         T *vl = reinterpret_cast<T *>(smem_raw);
-        for (int64_t c = threadIdx.x; c < ld; c += blockDim.x) vl[c] = c < nv ? (T)v[c] : (T)0;
+        for (int64_t c = threadIdx.x; c < ld; c += blockDim.x)
+            vl[c] = (c < nv && c >= c0) ? (T)v[c] : (T)0;
         __syncthreads();
         vs = vl;
     }
@@ -87,36 +88,37 @@ __global__ __launch_bounds__(256) void k_gemv_rows(const T *__restrict__ D, int6
 
 // vector v converted to the stream precision, zero padded to ld
 template <typename T>
-__global__ void k_vec_convert(const double *__restrict__ v, int64_t nv, int64_t ld, T *out)
+__global__ void k_vec_convert(const double *__restrict__ v, int64_t nv, int64_t ld, int c0, T *out)
 {
     for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < ld;
          c += (int64_t)gridDim.x * blockDim.x)
-        out[c] = c < nv ? (T)v[c] : (T)0;
+        out[c] = (c < nv && c >= c0) ? (T)v[c] : (T)0;
 }
 
 template <typename T>
 static hipError_t gemv_rows_typed(const T *D, int64_t ld, int64_t ns, const double *v, int64_t nv,
-                                  T *vtmp, double *w, hipStream_t st)
+                                  int c0, T *vtmp, double *w, hipStream_t st)
 {
     const int64_t nblk = ns < 4096 ? (ns + 3) / 4 : 2048;
     const size_t sh = (size_t)ld * sizeof(T);
     if (sh <= kMaxLdsBytes) {
-        k_gemv_rows<T, true><<<(unsigned)nblk, 256, sh, st>>>(D, ld, ns, v, nv, nullptr, w);
+        k_gemv_rows<T, true><<<(unsigned)nblk, 256, sh, st>>>(D, ld, ns, v, nv, nullptr, c0, w);
     } else {
-        k_vec_convert<T><<<(unsigned)((ld + 255) / 256), 256, 0, st>>>(v, nv, ld, vtmp);
-        k_gemv_rows<T, false><<<(unsigned)nblk, 256, 0, st>>>(D, ld, ns, v, nv, vtmp, w);
+        k_vec_convert<T><<<(unsigned)((ld + 255) / 256), 256, 0, st>>>(v, nv, ld, c0, vtmp);
+        k_gemv_rows<T, false><<<(unsigned)nblk, 256, 0, st>>>(D, ld, ns, v, nv, vtmp, c0, w);
     }
     return hipGetLastError();
 }
 
 hipError_t launch_gemv_rows(const WsLayout &L, void *ws, int prec, const double *v, double *w,
-                            hipStream_t st)
+                            int zero_v0, hipStream_t st)
 {
-    // the residual slot doubles as the converted-vector buffer (ld doubles >= ld floats)
+    // vconv holds the vector converted to the stream precision when it is too long for LDS
+    const int c0 = zero_v0 ? 1 : 0;
     if (prec == IRL_FP64)
-        return gemv_rows_typed<double>(ws_ptr<double>(ws, L.off_d64), L.ld64, L.ns, v, L.ncols,
+        return gemv_rows_typed<double>(ws_ptr<double>(ws, L.off_d64), L.ld64, L.ns, v, L.ncols, c0,
                                        ws_ptr<double>(ws, L.off_vconv), w, st);
-    return gemv_rows_typed<float>(ws_ptr<float>(ws, L.off_d32), L.ld32, L.ns, v, L.ncols,
+    return gemv_rows_typed<float>(ws_ptr<float>(ws, L.off_d32), L.ld32, L.ns, v, L.ncols, c0,
                                   ws_ptr<float>(ws, L.off_vconv), w, st);
 }
 

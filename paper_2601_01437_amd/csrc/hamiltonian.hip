@@ -30,6 +30,8 @@ struct HamArgs {
     const uint64_t *hkeys;
     const int32_t *hrows;
     uint64_t hmask;
+    const uint32_t *hfilter;
+    int hfbits;
     const int32_t *rankA, *rankB;
 };
 
@@ -78,7 +80,11 @@ __device__ __forceinline__ int64_t find_row(const HamArgs &A, uint32_t al, uint3
         return (int64_t)A.rankB[be] * A.nA + A.rankA[al];
     } else {
         uint64_t key = (uint64_t)al | ((uint64_t)be << 32);
-        uint64_t slot = mix64h(key) & A.hmask;
+        const uint64_t hm = mix64h(key);
+        // membership bitmap (a few MB, cache-resident) rejects most absent targets
+        const uint64_t bit = hm >> (64 - A.hfbits);
+        if (!((A.hfilter[bit >> 5] >> (bit & 31)) & 1u)) return -1;
+        uint64_t slot = hm & A.hmask;
         for (uint64_t probe = 0; probe <= A.hmask; ++probe) {
             uint64_t k = A.hkeys[slot];
             if (k == key) return A.hrows[slot];
@@ -252,6 +258,8 @@ static HamArgs ham_args(const irl_system *s)
     A.hkeys = s->d.hkeys;
     A.hrows = s->d.hrows;
     A.hmask = s->d.hcap ? s->d.hcap - 1 : 0;
+    A.hfilter = s->d.hfilter;
+    A.hfbits = s->d.hfbits;
     A.rankA = s->d.rankA;
     A.rankB = s->d.rankB;
     return A;

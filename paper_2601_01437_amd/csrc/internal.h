@@ -70,6 +70,8 @@ struct SystemDev {
     uint64_t *hkeys = nullptr;  // capacity
     int32_t *hrows = nullptr;   // capacity
     uint64_t hcap = 0;
+    uint32_t *hfilter = nullptr;  // membership bitmap, 2^hfbits bits, indexed by the top hash bits
+    int hfbits = 0;
     // string tables (full space)
     int32_t *rankA = nullptr;   // 2^n, -1 for strings not of popcount n_alpha
     int32_t *rankB = nullptr;
@@ -128,7 +130,7 @@ hipError_t launch_enumerate_full(uint64_t *keys, uint32_t *strA, uint32_t *strB,
                                  int32_t *rankB, int n, int na, int nb, int64_t nA, int64_t nB,
                                  hipStream_t st);
 hipError_t launch_hash_build(const uint64_t *keys, int64_t ns, uint64_t *hkeys, int32_t *hrows,
-                             uint64_t cap, hipStream_t st);
+                             uint64_t cap, uint32_t *filter, int fbits, hipStream_t st);
 hipError_t launch_hash_lookup(const uint64_t *hkeys, const int32_t *hrows, uint64_t cap,
                               const uint64_t *q, int64_t nq, int32_t *rows, hipStream_t st);
 hipError_t launch_diagonal(const uint64_t *keys, int64_t ns, int n, const double *h,
@@ -150,8 +152,9 @@ hipError_t launch_dtilde_import(const void *D, int64_t ld, int64_t ncols, int dt
                                 const WsLayout &L, void *ws, hipStream_t st);
 
 // dtilde.hip
+// zero_v0: treat v[0] as zero (split form: the psi column is handled in FP64 through g)
 hipError_t launch_gemv_rows(const WsLayout &L, void *ws, int prec, const double *v, double *w,
-                            hipStream_t st);
+                            int zero_v0, hipStream_t st);
 // [yS, yH] = D~^T [a, b] where a = w (or nullptr), b = u - scale*psi form; see dtilde.hip
 // stream part: per-row-block partial sums; returns the number of row blocks
 hipError_t launch_gemv_t2(const WsLayout &L, void *ws, int prec, const double *a,
@@ -165,7 +168,9 @@ hipError_t launch_energy_reduce(const WsLayout &L, void *ws, hipStream_t st);
 // lanczos.hip
 hipError_t launch_start_vector(double *v, int64_t L, int64_t ldv, int mode, uint64_t seed,
                                hipStream_t st);
-hipError_t launch_lanczos_step(const WsLayout &L, void *ws, double *V, int j, int mode,
+// split: w = H~'v assembled as [g.v[1:]/2 ; g v0/2 + H_eff v[1:]] with g in FP64 (the
+// operator pair then comes from an apply of (0, v[1:]))
+hipError_t launch_lanczos_step(const WsLayout &L, void *ws, double *V, int j, int mode, int split,
                                uint64_t seed, hipStream_t st);
 hipError_t launch_ritz(const WsLayout &L, void *ws, int m, int k, hipStream_t st);
 hipError_t launch_restart_basis(const WsLayout &L, void *ws, const double *Vold, double *Vnew,
@@ -173,7 +178,7 @@ hipError_t launch_restart_basis(const WsLayout &L, void *ws, const double *Vold,
 hipError_t launch_ritz_vector(const WsLayout &L, void *ws, const double *V, int m, double *y,
                               hipStream_t st);
 hipError_t launch_residual(const WsLayout &L, void *ws, const double *y, double *r, int mode,
-                           hipStream_t st);
+                           int split, hipStream_t st);
 hipError_t launch_update(const WsLayout &L, void *ws, const double *y, double *dtheta,
                          double *theta, int64_t P, int mode, hipStream_t st);
 hipError_t launch_copy(double *dst, const double *src, int64_t n, hipStream_t st);

@@ -116,6 +116,28 @@ __device__ double fresh_vector(const double *V, int64_t ldv, int nd, double *w, 
     return nrm;
 }
 
+// (H~' v)_i from the raw operator pair.  Plain form: (yH_i - E yS_i) / Z.  Split
+// form (pair computed from (0, v[1:])): component 0 is g.v[1:] / 2 and
+// components i >= 1 add g_i v_0 / 2, with g = grad[1:] in FP64.
+__device__ __forceinline__ double centred_component(int64_t i, const double *yH, const double *yS,
+                                                    const double *grad, double v0, double gdotv,
+                                                    double Z, double E, int split)
+{
+    if (split) {
+        if (i == 0) return 0.5 * gdotv;
+        return (yH[i] - E * yS[i]) / Z + 0.5 * grad[i] * v0;
+    }
+    return (yH[i] - E * yS[i]) / Z;
+}
+
+// g.v[1:] over the block (only needed in split form)
+__device__ double grad_dot(const double *grad, const double *v, int64_t ncols, double *sh)
+{
+    double p = 0.0;
+    for (int64_t i = 1 + threadIdx.x; i < ncols; i += kVecThreads) p += grad[i] * v[i];
+    return block_sum(p, sh);
+}
+
 __global__ __launch_bounds__(kVecThreads) void k_start_vector(double *v, int64_t ncols, int64_t ldv,
                                                              int mode, uint64_t seed)
 {
@@ -133,8 +155,8 @@ hipError_t launch_start_vector(double *v, int64_t ncols, int64_t ldv, int mode, 
 
 // One Lanczos step j: w = H~' v_j from (yH, yS), recurrence, CGS2, normalise.
 __global__ __launch_bounds__(kVecThreads) void k_lanczos_step(
-    const double *__restrict__ yH, const double *__restrict__ yS, WsScalars *sc, double *V,
-    int64_t ldv, int64_t ncols, int j, int mode, uint64_t seed)
+    const double *__restrict__ yH, const double *__restrict__ yS, const double *__restrict__ grad,
+    WsScalars *sc, double *V, int64_t ldv, int64_t ncols, int j, int mode, int split, uint64_t seed)
 {
     __shared__ double sh[kVecWaves * (kMaxKrylov + 1)];
     __shared__ double hsh[kMaxKrylov + 1];
@@ -142,9 +164,11 @@ __global__ __launch_bounds__(kVecThreads) void k_lanczos_step(
     const double *vj = V + (int64_t)j * ldv;
     double *w = V + (int64_t)(j + 1) * ldv;
     const int64_t L = ldv;
+    const double gdotv = split ? grad_dot(grad, vj, ncols, sh) : 0.0;
+    const double v0 = vj[0];
     double pa = 0.0;
     for (int64_t i = threadIdx.x; i < L; i += kVecThreads) {
-        double x = (i < ncols) ? (yH[i] - E * yS[i]) / Z : 0.0;
+        double x = (i < ncols) ? centred_component(i, yH, yS, grad, v0, gdotv, Z, E, split) : 0.0;
         if (mode == IRL_MODE_P && i == 0) x = 0.0;
         w[i] = x;
         pa += vj[i] * x;
@@ -177,12 +201,13 @@ __global__ __launch_bounds__(kVecThreads) void k_lanczos_step(
     }
 }
 
-hipError_t launch_lanczos_step(const WsLayout &L, void *ws, double *V, int j, int mode,
+hipError_t launch_lanczos_step(const WsLayout &L, void *ws, double *V, int j, int mode, int split,
                                uint64_t seed, hipStream_t st)
 {
     k_lanczos_step<<<1, kVecThreads, 0, st>>>(ws_ptr<double>(ws, L.off_yh), ws_ptr<double>(ws, L.off_ys),
+                                               ws_ptr<double>(ws, L.off_grad),
                                                ws_ptr<WsScalars>(ws, L.off_scal), V, L.ldv, L.ncols,
-                                               j, mode, seed);
+                                               j, mode, split, seed);
     return hipGetLastError();
 }
 
@@ -405,15 +430,18 @@ hipError_t launch_ritz_vector(const WsLayout &L, void *ws, const double *V, int 
 
 // r = H~'y - lam y from (yH, yS); resid2 = ||r||^2
 __global__ __launch_bounds__(kVecThreads) void k_residual(WsScalars *sc, const double *yH,
-                                                         const double *yS, const double *y,
-                                                         double *r, int64_t ldv, int64_t ncols,
-                                                         int mode)
+                                                         const double *yS, const double *grad,
+                                                         const double *y, double *r, int64_t ldv,
+                                                         int64_t ncols, int mode, int split)
 {
     __shared__ double sh[kVecWaves * (kMaxKrylov + 1)];
     const double Z = sc->Z, E = sc->E_el, lam = sc->lam;
+    const double gdotv = split ? grad_dot(grad, y, ncols, sh) : 0.0;
+    const double v0 = y[0];
     double p = 0.0;
     for (int64_t c = threadIdx.x; c < ldv; c += kVecThreads) {
-        double x = c < ncols ? (yH[c] - E * yS[c]) / Z - lam * y[c] : 0.0;
+        double x = c < ncols ? centred_component(c, yH, yS, grad, v0, gdotv, Z, E, split) - lam * y[c]
+                             : 0.0;
         if (mode == IRL_MODE_P && c == 0) x = 0.0;
         r[c] = x;
         p += x * x;
@@ -423,11 +451,12 @@ __global__ __launch_bounds__(kVecThreads) void k_residual(WsScalars *sc, const d
 }
 
 hipError_t launch_residual(const WsLayout &L, void *ws, const double *y, double *r, int mode,
-                           hipStream_t st)
+                           int split, hipStream_t st)
 {
     k_residual<<<1, kVecThreads, 0, st>>>(ws_ptr<WsScalars>(ws, L.off_scal),
-                                          ws_ptr<double>(ws, L.off_yh), ws_ptr<double>(ws, L.off_ys), y,
-                                          r, L.ldv, L.ncols, mode);
+                                          ws_ptr<double>(ws, L.off_yh), ws_ptr<double>(ws, L.off_ys),
+                                          ws_ptr<double>(ws, L.off_grad), y, r, L.ldv, L.ncols, mode,
+                                          split);
     return hipGetLastError();
 }
 

@@ -78,12 +78,17 @@ __global__ void k_fill_u64(uint64_t *p, uint64_t n, uint64_t v)
 }
 
 __global__ void k_hash_insert(const uint64_t *keys, int64_t ns, uint64_t *hkeys, int32_t *hrows,
-                              uint64_t mask)
+                              uint64_t mask, uint32_t *filter, int fbits)
 {
     int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= ns) return;
     uint64_t key = keys[r];
-    uint64_t slot = mix64(key) & mask;
+    const uint64_t hm = mix64(key);
+    if (filter) {
+        const uint64_t bit = hm >> (64 - fbits);
+        atomicOr(&filter[bit >> 5], 1u << (bit & 31));
+    }
+    uint64_t slot = hm & mask;
     for (uint64_t probe = 0; probe <= mask; ++probe) {
         unsigned long long prev = atomicCAS((unsigned long long *)&hkeys[slot],
                                             (unsigned long long)kEmptyKey,
@@ -96,12 +101,23 @@ __global__ void k_hash_insert(const uint64_t *keys, int64_t ns, uint64_t *hkeys,
     }
 }
 
+__global__ void k_fill_u32(uint32_t *p, uint64_t n, uint32_t v)
+{
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
 hipError_t launch_hash_build(const uint64_t *keys, int64_t ns, uint64_t *hkeys, int32_t *hrows,
-                             uint64_t cap, hipStream_t st)
+                             uint64_t cap, uint32_t *filter, int fbits, hipStream_t st)
 {
     const int bs = 256;
     k_fill_u64<<<(unsigned)((cap + bs - 1) / bs), bs, 0, st>>>(hkeys, cap, kEmptyKey);
-    k_hash_insert<<<(unsigned)((ns + bs - 1) / bs), bs, 0, st>>>(keys, ns, hkeys, hrows, cap - 1);
+    if (filter) {
+        const uint64_t words = (1ull << fbits) / 32;
+        k_fill_u32<<<(unsigned)((words + bs - 1) / bs), bs, 0, st>>>(filter, words, 0u);
+    }
+    k_hash_insert<<<(unsigned)((ns + bs - 1) / bs), bs, 0, st>>>(keys, ns, hkeys, hrows, cap - 1,
+                                                                filter, fbits);
     return hipGetLastError();
 }
 
