@@ -273,6 +273,34 @@ int irl_step(irl_system *sys, irl_nqs_desc *nqs, const irl_solver_opts *opts, vo
  * mode A, seed 0, flags 0). */
 void irl_solver_opts_default(irl_solver_opts *o);
 
+/* ---- batches of independent solves ------------------------------------- */
+
+/* A batch groups `count` independent optimisations (systems, networks,
+ * workspaces) that are stepped together: every kernel launch of a batch step
+ * covers all members that are still active (grouped kernels over per-member
+ * work lists), the members advance through the Lanczos steps in lockstep, and
+ * the host reads back all members' scalars with one copy per check point.
+ * Each member follows exactly the arithmetic of irl_step on a system created
+ * with IRL_SYS_FORCE_PULL (same row blocks, reduction order, seeds and
+ * tolerances), so its result equals that solo result bit for bit.  Members use
+ * the per-determinant Hamiltonian kernels (string-rank or hashed lookup).
+ * systems[i], nqs[i] and ws[i] (sized by irl_workspace_query for P_i + 1
+ * columns and ws_flags) are borrowed and must stay alive while the batch
+ * exists; a system must not be used by two members.  Requires
+ * (P_i + 1) <= 8192.  Errors: IRL_EINVAL, IRL_ENOMEM, IRL_EDEVICE. */
+typedef struct irl_batch irl_batch;
+int irl_batch_create(int32_t count, irl_system *const *systems, const irl_nqs_desc *nqs,
+                     void *const *ws, const size_t *ws_bytes, uint32_t ws_flags,
+                     irl_batch **out);
+void irl_batch_destroy(irl_batch *batch);
+
+/* One optimisation step for every member (irl_step semantics, same options for
+ * all members).  dtheta: NULL or an array of count device pointers (each NULL
+ * or P_i doubles).  results and status: host arrays of count entries; status[i]
+ * is IRL_OK, IRL_ENOTCONV or IRL_ESTEP.  Returns IRL_OK or an error. */
+int irl_batch_step(irl_batch *batch, const irl_solver_opts *opts, double *const *dtheta,
+                   irl_step_result *results, int32_t *status, void *stream);
+
 /* ---- per-kernel timing -------------------------------------------------- */
 
 /* Kernel classes timed by irl_stats_*. */

@@ -7,4 +7,4 @@ convenience class.  Importing it without the built library raises ImportError.
 """
 from .binding import *  # noqa: F401,F403
 from .binding import EXPORTED, IrlError, LIB_PATH  # noqa: F401
-from .system import System  # noqa: F401
+from .system import Batch, System  # noqa: F401

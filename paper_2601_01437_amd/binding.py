@@ -101,6 +101,11 @@ _sigs = {
     "irl_solver_opts_default": (None, [POINTER(irl_solver_opts)]),
     "irl_stats_enable": (c_int32, [_SYS, c_int32]),
     "irl_stats_get": (c_int32, [_SYS, c_void_p, c_void_p, c_void_p]),
+    "irl_batch_create": (c_int32, [c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_uint32,
+                                   POINTER(c_void_p)]),
+    "irl_batch_destroy": (None, [c_void_p]),
+    "irl_batch_step": (c_int32, [c_void_p, POINTER(irl_solver_opts), c_void_p, c_void_p, c_void_p,
+                                 c_void_p]),
     "irl_debug_keys": (c_int32, [_SYS, c_void_p]),
     "irl_debug_lookup": (c_int32, [_SYS, c_void_p, c_int64, c_void_p]),
     "irl_debug_diagonal": (c_int32, [_SYS, c_void_p]),
@@ -230,6 +235,35 @@ def irl_stats_get(sys, stream=None):
     cnt = np.zeros(len(STAT_KINDS), dtype=np.int64)
     _check(_lib.irl_stats_get(sys, ms.ctypes.data, cnt.ctypes.data, _stream(stream)), sys)
     return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(STAT_KINDS)}
+
+
+def irl_batch_create(systems, nqs, ws, ws_flags):
+    """systems: handles; nqs: list of (V, H, theta tensor); ws: list of device uint8 tensors."""
+    n = len(systems)
+    sys_arr = (c_void_p * n)(*[s.value if isinstance(s, c_void_p) else s for s in systems])
+    nqs_arr = (irl_nqs_desc * n)(*[irl_nqs_desc(V, H, th.data_ptr()) for V, H, th in nqs])
+    ws_arr = (c_void_p * n)(*[w.data_ptr() for w in ws])
+    sizes = (c_size_t * n)(*[w.numel() * w.element_size() for w in ws])
+    out = c_void_p()
+    _check(_lib.irl_batch_create(n, sys_arr, nqs_arr, ws_arr, sizes, ws_flags, ctypes.byref(out)),
+           systems[0])
+    return out
+
+
+def irl_batch_destroy(batch):
+    _lib.irl_batch_destroy(batch)
+
+
+def irl_batch_step(batch, opts, count, dtheta=None, first_system=None, stream=None):
+    """Returns (list of irl_step_result, list of status codes)."""
+    res = (irl_step_result * count)()
+    status = (c_int32 * count)()
+    dth = None
+    if dtheta is not None:
+        dth = (c_void_p * count)(*[None if t is None else t.data_ptr() for t in dtheta])
+    _check(_lib.irl_batch_step(batch, ctypes.byref(opts), dth, res, status, _stream(stream)),
+           first_system)
+    return list(res), list(status)
 
 
 def irl_debug_keys(sys, n_dets):

@@ -861,3 +861,542 @@ int irl_debug_lanczos(irl_system *s, void *ws, size_t ws_bytes, const double *v1
 }
 
 }  // extern "C"
+
+// ============================================================================
+// Batches: independent solves stepped in lockstep with grouped kernels
+// ============================================================================
+struct irl_batch {
+    int B = 0;
+    std::vector<irl_system *> sys;
+    std::vector<WsLayout> lay;
+    std::vector<void *> ws;
+    std::vector<size_t> ws_bytes;
+    std::vector<irl_nqs_desc> nqs;
+    std::vector<Member> hm;
+    uint32_t ws_flags = 0;
+    Member *dm = nullptr;
+    // two device work-list regions (0: active set, 1: check / candidate set)
+    WorkItem *ditems[2] = {nullptr, nullptr};
+    size_t dcap[2] = {0, 0};
+    WorkItem *hitems = nullptr;   // pinned staging
+    size_t hcap = 0;
+    MemberScalars *dscal = nullptr, *hscal = nullptr;
+};
+
+namespace {
+
+enum { LS_ROWS6, LS_ROWS4, LS_ROWS5, LS_T2, LS_RED, LS_E1, LS_VEC, LS_KINDS };
+
+struct ListSet {
+    int region = 0;
+    int off[LS_KINDS] = {0}, cnt[LS_KINDS] = {0};
+    size_t lds6 = 0;   // dynamic LDS of the grouped D~ v launch
+    const WorkItem *ptr(const irl_batch *b, int kind) const { return b->ditems[region] + off[kind]; }
+};
+
+int t2_blocks(int64_t ns, int64_t ld, int prec)   // row blocks of the solo D~^T launch
+{
+    const int64_t nch = ld / (prec == IRL_FP64 ? 2 : 4);
+    const int ntiles = (int)((nch + 64 * 16 - 1) / (64 * 16));
+    int nblk = kStreamBlocks / ntiles;
+    if (nblk < 1) nblk = 1;
+    if (nblk > (ns + 3) / 4) nblk = (int)((ns + 3) / 4);
+    return nblk;
+}
+
+int energy_parts(int64_t ns)
+{
+    return ns < (int64_t)kScalarParts * 256 ? (int)((ns + 255) / 256) : kScalarParts;
+}
+
+// Build the work lists of `subset` into device region `region` (synchronises
+// the stream first: the pinned staging buffer is reused).
+int build_lists(irl_batch *b, const std::vector<int> &subset, int region, int prec, ListSet &ls,
+                hipStream_t st)
+{
+    irl_system *s0 = b->sys[0];
+    std::vector<WorkItem> v;
+    ls.region = region;
+    auto rows = [&](int m, int64_t R) {
+        const int64_t ns = b->hm[m].ns;
+        for (int64_t r0 = 0; r0 < ns; r0 += R) v.push_back(WorkItem{m, 0, 0, 0, r0, std::min(ns, r0 + R)});
+    };
+    ls.lds6 = 0;
+    for (int kind = 0; kind < LS_KINDS; ++kind) {
+        ls.off[kind] = (int)v.size();
+        for (int m : subset) {
+            const Member &mb = b->hm[m];
+            switch (kind) {
+            case LS_ROWS6: rows(m, 512); ls.lds6 = std::max(ls.lds6, (size_t)mb.ld * (prec == IRL_FP64 ? 8 : 4)); break;
+            case LS_ROWS4: rows(m, 256); break;
+            case LS_ROWS5: rows(m, 256); break;
+            case LS_T2: {
+                const int64_t nch = mb.ld / (prec == IRL_FP64 ? 2 : 4);
+                const int ntiles = (int)((nch + 64 * kGroupedT2Chunks - 1) / (64 * kGroupedT2Chunks));
+                const int nblk = mb.nblk_t2;
+                const int64_t per = (mb.ns + nblk - 1) / nblk;
+                for (int rb = 0; rb < nblk; ++rb)
+                    for (int t = 0; t < ntiles; ++t) {
+                        const int64_t r0 = (int64_t)rb * per;
+                        v.push_back(WorkItem{m, t, rb, 0, std::min(r0, mb.ns), std::min(mb.ns, r0 + per)});
+                    }
+                break;
+            }
+            case LS_RED: {
+                const int64_t len = 2 * mb.ld;
+                for (int64_t a = 0; a < (len + 255) / 256; ++a) v.push_back(WorkItem{m, (int)a, 0, 0, 0, 0});
+                break;
+            }
+            case LS_E1: {
+                const int parts = mb.nparts_e;
+                const int64_t per = (mb.ns + parts - 1) / parts;
+                for (int p = 0; p < parts; ++p) {
+                    const int64_t r0 = (int64_t)p * per;
+                    v.push_back(WorkItem{m, p, 0, 0, std::min(r0, mb.ns), std::min(mb.ns, r0 + per)});
+                }
+                break;
+            }
+            case LS_VEC: v.push_back(WorkItem{m, 0, 0, 0, 0, 0}); break;
+            }
+        }
+        ls.cnt[kind] = (int)v.size() - ls.off[kind];
+    }
+    if (ls.lds6 > 64 * 1024) return set_err(s0, IRL_EINVAL, "batch member row longer than 8192 columns");
+    CK(s0, hipStreamSynchronize(st));
+    if (v.size() > b->hcap) {
+        if (b->hitems) (void)hipHostFree(b->hitems);
+        b->hitems = nullptr;
+        b->hcap = 0;
+        CK(s0, hipHostMalloc((void **)&b->hitems, v.size() * sizeof(WorkItem)));
+        b->hcap = v.size();
+    }
+    if (v.size() > b->dcap[region]) {
+        if (b->ditems[region]) (void)hipFree(b->ditems[region]);
+        b->ditems[region] = nullptr;
+        b->dcap[region] = 0;
+        CK(s0, hipMalloc((void **)&b->ditems[region], v.size() * sizeof(WorkItem)));
+        b->dcap[region] = v.size();
+    }
+    std::memcpy(b->hitems, v.data(), v.size() * sizeof(WorkItem));
+    CK(s0, hipMemcpyAsync(b->ditems[region], b->hitems, v.size() * sizeof(WorkItem),
+                          hipMemcpyHostToDevice, st));
+    return IRL_OK;
+}
+
+int upload_members(irl_batch *b, hipStream_t st)
+{
+    CK(b->sys[0], hipStreamSynchronize(st));
+    CK(b->sys[0], hipMemcpy(b->dm, b->hm.data(), b->B * sizeof(Member), hipMemcpyHostToDevice));
+    return IRL_OK;
+}
+
+int gather(irl_batch *b, const ListSet &ls, hipStream_t st)
+{
+    irl_system *s0 = b->sys[0];
+    CK(s0, launch_lanczos_grouped(kGrpGather, b->dm, ls.ptr(b, LS_VEC), ls.cnt[LS_VEC], 0, 0, 0, 0, 0,
+                                  b->dscal, st));
+    CK(s0, hipMemcpyAsync(b->hscal, b->dscal, b->B * sizeof(MemberScalars), hipMemcpyDeviceToHost, st));
+    CK(s0, hipStreamSynchronize(st));
+    return IRL_OK;
+}
+
+int batch_apply(irl_batch *b, const ListSet &ls, int vsel, int j, int cur, int split, int prec,
+                hipStream_t st)
+{
+    irl_system *s0 = b->sys[0];
+    CK(s0, launch_gemv_rows_grouped(b->dm, ls.ptr(b, LS_ROWS6), ls.cnt[LS_ROWS6], prec, vsel, j, cur,
+                                    split, ls.lds6, st));
+    CK(s0, launch_ham_pull_grouped(b->dm, ls.ptr(b, LS_ROWS4), ls.cnt[LS_ROWS4], 0, st));
+    CK(s0, launch_gemv_t2_grouped(b->dm, ls.ptr(b, LS_T2), ls.cnt[LS_T2], prec, 0, st));
+    CK(s0, launch_reduce_grouped(b->dm, ls.ptr(b, LS_RED), ls.cnt[LS_RED], 0, st));
+    return IRL_OK;
+}
+
+// the D~^T launches of a phase use the row blocks of the solo launch at that precision
+int set_stream_precision(irl_batch *b, int prec, hipStream_t st)
+{
+    bool changed = false;
+    for (int i = 0; i < b->B; ++i) {
+        const int nb = t2_blocks(b->hm[i].ns, b->hm[i].ld, prec);
+        if (nb != b->hm[i].nblk_t2) {
+            b->hm[i].nblk_t2 = nb;
+            changed = true;
+        }
+    }
+    return changed ? upload_members(b, st) : IRL_OK;
+}
+
+int batch_evaluate(irl_batch *b, const std::vector<int> &subset, hipStream_t st)
+{
+    irl_system *s0 = b->sys[0];
+    ListSet ls;
+    const int prec = (b->ws_flags & IRL_WS_FP64) ? IRL_FP64 : IRL_FP32;
+    int rc = set_stream_precision(b, prec, st);
+    if (rc) return rc;
+    rc = build_lists(b, subset, 0, prec, ls, st);
+    if (rc) return rc;
+    CK(s0, launch_nqs_dtilde_grouped(b->dm, ls.ptr(b, LS_ROWS5), ls.cnt[LS_ROWS5], 0, 0, st));
+    CK(s0, launch_ham_pull_grouped(b->dm, ls.ptr(b, LS_ROWS4), ls.cnt[LS_ROWS4], 1, st));
+    CK(s0, launch_energy_grouped(b->dm, ls.ptr(b, LS_E1), ls.cnt[LS_E1], 1, st));
+    CK(s0, launch_energy_grouped(b->dm, ls.ptr(b, LS_VEC), ls.cnt[LS_VEC], 2, st));
+    CK(s0, launch_gemv_t2_grouped(b->dm, ls.ptr(b, LS_T2), ls.cnt[LS_T2], prec, 1, st));
+    CK(s0, launch_reduce_grouped(b->dm, ls.ptr(b, LS_RED), ls.cnt[LS_RED], 1, st));
+    rc = gather(b, ls, st);
+    if (rc) return rc;
+    for (int m : subset) {
+        irl_system *s = b->sys[m];
+        s->Z = b->hscal[m].Z;
+        s->E_el = b->hscal[m].E_el;
+        s->ws = b->ws[m];
+        s->lay = b->lay[m];
+        s->ws_valid = true;
+        s->ws_has64 = (b->ws_flags & IRL_WS_FP64) != 0;
+        s->ws_has32 = (b->ws_flags & IRL_WS_FP32) != 0;
+        if (!(s->Z > 0.0) || !std::isfinite(s->E_el))
+            return set_err(s0, IRL_EINVAL, "batch member " + std::to_string(m) + ": psi^T psi is zero or the energy is not finite");
+    }
+    return IRL_OK;
+}
+
+struct MemberSolve {
+    double lam = 0, resid_est = 0, resid_explicit = 0, gap = 0, normT = 0, c0 = 0, tol_used = 0;
+    int n_apply = 0, n_restart = 0, converged = 0, done = 0;
+};
+
+// Lockstep IRL over all members (irl_solve semantics per member).
+int batch_solve(irl_batch *b, const irl_solver_opts &o, int prec, bool from_y,
+                std::vector<MemberSolve> &out, hipStream_t st)
+{
+    irl_system *s0 = b->sys[0];
+    const int B = b->B;
+    int m = o.m, k = o.k_keep;
+    for (int i = 0; i < B; ++i) {
+        const int64_t dim = (o.mode == IRL_MODE_A) ? b->hm[i].ncols : b->hm[i].ncols - 1;
+        if (dim < m) return set_err(s0, IRL_EINVAL, "batch member too small for the Krylov dimension");
+    }
+    const double u_op = (prec == IRL_FP64) ? 1.1102230246251565e-16 : 5.960464477539063e-08;
+    const int split = (prec == IRL_FP32) ? 1 : 0;
+    std::vector<int> stride(B);
+    for (int i = 0; i < B; ++i) {
+        const double apply_bytes = 2.0 * (double)b->hm[i].ns * (double)b->hm[i].ld * (prec == IRL_FP64 ? 8.0 : 4.0);
+        stride[i] = (o.flags & IRL_STEP_FULL_CYCLES) ? 0 : (apply_bytes >= 2.56e8 ? 2 : 0);
+    }
+    out.assign(B, MemberSolve());
+    std::vector<int> active(B);
+    for (int i = 0; i < B; ++i) active[i] = i;
+    ListSet la, lc;
+    int rc = set_stream_precision(b, prec, st);
+    if (rc) return rc;
+    rc = build_lists(b, active, 0, prec, la, st);
+    if (rc) return rc;
+    CK(s0, launch_lanczos_grouped(kGrpReset, b->dm, la.ptr(b, LS_VEC), la.cnt[LS_VEC], 0, 0, 0, 0, 0, nullptr, st));
+    CK(s0, launch_lanczos_grouped(kGrpStart, b->dm, la.ptr(b, LS_VEC), la.cnt[LS_VEC], o.mode, from_y ? 1 : 0, 0, 0, o.seed, nullptr, st));
+    int j0 = 0, cur = 0, n_restart = 0;
+    // test candidates: Ritz vector of T_mc, one explicit apply, residual
+    auto finalize = [&](const std::vector<int> &cand, int mc, bool accept_all) -> int {
+        if (cand.empty()) return IRL_OK;
+        int r2 = build_lists(b, cand, 1, prec, lc, st);
+        if (r2) return r2;
+        CK(s0, launch_lanczos_grouped(kGrpRitzVector, b->dm, lc.ptr(b, LS_VEC), lc.cnt[LS_VEC], cur, mc, 0, 0, 0, nullptr, st));
+        r2 = batch_apply(b, lc, 1, 0, cur, split, prec, st);
+        if (r2) return r2;
+        CK(s0, launch_lanczos_grouped(kGrpResidual, b->dm, lc.ptr(b, LS_VEC), lc.cnt[LS_VEC], o.mode, split, 0, 0, 0, nullptr, st));
+        r2 = gather(b, lc, st);
+        if (r2) return r2;
+        std::vector<int> still;
+        for (int i : cand) {
+            MemberSolve &ms = out[i];
+            ms.n_apply += 1;
+            ms.resid_explicit = std::sqrt(b->hscal[i].resid2);
+            ms.c0 = b->hscal[i].c0;
+            const double tol_explicit = std::max(ms.tol_used, 1024.0 * u_op * ms.normT);
+            if (accept_all || ms.resid_explicit <= tol_explicit) {
+                ms.converged = accept_all ? 0 : 1;
+                ms.done = 1;
+                ms.n_restart = n_restart;
+            }
+        }
+        std::vector<int> na;
+        for (int i : active)
+            if (!out[i].done) na.push_back(i);
+        if (na.size() != active.size()) {
+            active.swap(na);
+            if (!active.empty()) {
+                int r3 = build_lists(b, active, 0, prec, la, st);
+                if (r3) return r3;
+            }
+        }
+        return IRL_OK;
+    };
+    auto check = [&](const std::vector<int> &who, int mt, int kk, bool end_of_cycle, std::vector<int> &cand) -> int {
+        cand.clear();
+        if (who.empty()) return IRL_OK;
+        int r2 = build_lists(b, who, 1, prec, lc, st);
+        if (r2) return r2;
+        CK(s0, launch_lanczos_grouped(kGrpRitz, b->dm, lc.ptr(b, LS_VEC), lc.cnt[LS_VEC], mt, kk, 0, 0, 0, nullptr, st));
+        r2 = gather(b, lc, st);
+        if (r2) return r2;
+        for (int i : who) {
+            const MemberScalars &hs = b->hscal[i];
+            if (!std::isfinite(hs.lam)) return set_err(s0, IRL_EINVAL, "non-finite Ritz value in batch member " + std::to_string(i));
+            const double tq = std::max(o.tol, 64.0 * u_op * hs.normT);
+            MemberSolve &ms = out[i];
+            if (end_of_cycle || hs.resid_est <= tq) {
+                ms.lam = hs.lam;
+                ms.resid_est = hs.resid_est;
+                ms.gap = hs.gap;
+                ms.normT = hs.normT;
+                ms.tol_used = tq;
+            }
+            if (hs.resid_est <= tq) cand.push_back(i);
+        }
+        return IRL_OK;
+    };
+    std::vector<int> cand;
+    while (!active.empty()) {
+        bool cycle_done = true;
+        for (int j = j0; j < m && !active.empty(); ++j) {
+            rc = batch_apply(b, la, 0, j, cur, split, prec, st);
+            if (rc) return rc;
+            for (int i : active) out[i].n_apply += 1;
+            CK(s0, launch_lanczos_grouped(kGrpLanczos, b->dm, la.ptr(b, LS_VEC), la.cnt[LS_VEC], j, cur, o.mode, split,
+                                          o.seed + 0x100000001b3ull * (uint64_t)(n_restart + 1), nullptr, st));
+            if (j + 1 < m && j + 1 >= 2 && (j + 1 - j0) % 2 == 0) {
+                std::vector<int> who;
+                for (int i : active)
+                    if (stride[i]) who.push_back(i);
+                rc = check(who, j + 1, 0, false, cand);
+                if (rc) return rc;
+                rc = finalize(cand, j + 1, false);
+                if (rc) return rc;
+            }
+            if (active.empty()) cycle_done = false;
+        }
+        if (!cycle_done || active.empty()) break;
+        rc = check(active, m, k, true, cand);
+        if (rc) return rc;
+        rc = finalize(cand, m, false);
+        if (rc) return rc;
+        if (active.empty()) break;
+        if (n_restart >= o.max_restarts) {
+            std::vector<int> rest = active;
+            rc = check(rest, m, 0, true, cand);
+            if (rc) return rc;
+            rc = finalize(rest, m, true);
+            if (rc) return rc;
+            break;
+        }
+        CK(s0, launch_lanczos_grouped(kGrpRestart, b->dm, la.ptr(b, LS_VEC), la.cnt[LS_VEC], cur, m, k, o.mode,
+                                      o.seed ^ (0x9e3779b97f4a7c15ull * (uint64_t)(n_restart + 7)), nullptr, st));
+        cur = 1 - cur;
+        j0 = k;
+        ++n_restart;
+    }
+    return IRL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int irl_batch_create(int32_t count, irl_system *const *systems, const irl_nqs_desc *nqs,
+                     void *const *ws, const size_t *ws_bytes, uint32_t ws_flags, irl_batch **out)
+{
+    if (!out) return IRL_EINVAL;
+    *out = nullptr;
+    if (count < 1 || !systems || !nqs || !ws || !ws_bytes) return set_err(nullptr, IRL_EINVAL, "bad batch arguments");
+    if (!(ws_flags & (IRL_WS_FP64 | IRL_WS_FP32))) return set_err(nullptr, IRL_EINVAL, "ws_flags names no D~ copy");
+    irl_batch *b = new irl_batch();
+    b->B = count;
+    b->ws_flags = ws_flags;
+    for (int i = 0; i < count; ++i) {
+        irl_system *s = systems[i];
+        if (!s || !nqs[i].theta) { delete b; return set_err(nullptr, IRL_EINVAL, "NULL batch member"); }
+        for (int k = 0; k < i; ++k)
+            if (systems[k] == s) { delete b; return set_err(nullptr, IRL_EINVAL, "a system appears twice in a batch"); }
+        if (nqs[i].V != 2 * s->n || nqs[i].H < 1 || nqs[i].H > 1024) { delete b; return set_err(nullptr, IRL_EINVAL, "bad network size in batch member " + std::to_string(i)); }
+        const int64_t P = (int64_t)nqs[i].V * nqs[i].H + nqs[i].H + nqs[i].V;
+        WsLayout L = make_layout(s->ns, P + 1, ws_flags);
+        if (L.ldv > 8192) { delete b; return set_err(nullptr, IRL_EINVAL, "batch members need P + 1 <= 8192"); }
+        if (!ws[i] || reinterpret_cast<uintptr_t>(ws[i]) % 256 || ws_bytes[i] < L.total) { delete b; return set_err(nullptr, IRL_ENOMEM, "batch workspace missing or too small for member " + std::to_string(i)); }
+        b->sys.push_back(s);
+        b->lay.push_back(L);
+        b->ws.push_back(ws[i]);
+        b->ws_bytes.push_back(ws_bytes[i]);
+        b->nqs.push_back(nqs[i]);
+        Member mb;
+        std::memset(&mb, 0, sizeof(mb));
+        mb.ham = ham_view(s);
+        mb.D64 = (ws_flags & IRL_WS_FP64) ? ws_ptr<double>(ws[i], L.off_d64) : nullptr;
+        mb.D32 = (ws_flags & IRL_WS_FP32) ? ws_ptr<float>(ws[i], L.off_d32) : nullptr;
+        mb.ld = L.ldv;
+        mb.ncols = L.ncols;
+        mb.ns = L.ns;
+        mb.psi = ws_ptr<double>(ws[i], L.off_psi);
+        mb.hpsi = ws_ptr<double>(ws[i], L.off_hpsi);
+        mb.w = ws_ptr<double>(ws[i], L.off_w);
+        mb.u = ws_ptr<double>(ws[i], L.off_u);
+        mb.grad = ws_ptr<double>(ws[i], L.off_grad);
+        mb.yH = ws_ptr<double>(ws[i], L.off_yh);
+        mb.yS = ws_ptr<double>(ws[i], L.off_ys);
+        mb.y = ws_ptr<double>(ws[i], L.off_y);
+        mb.r = ws_ptr<double>(ws[i], L.off_r);
+        mb.part = ws_ptr<double>(ws[i], L.off_part);
+        mb.part2 = ws_ptr<double>(ws[i], L.off_part2);
+        mb.red = ws_ptr<double>(ws[i], L.off_red);
+        mb.vconv = ws_ptr<double>(ws[i], L.off_vconv);
+        mb.kry[0] = ws_ptr<double>(ws[i], L.off_kry0);
+        mb.kry[1] = ws_ptr<double>(ws[i], L.off_kry1);
+        mb.sc = ws_ptr<WsScalars>(ws[i], L.off_scal);
+        mb.V = nqs[i].V;
+        mb.H = nqs[i].H;
+        mb.theta = nqs[i].theta;
+        mb.dtheta = nullptr;
+        mb.nblk_t2 = t2_blocks(L.ns, L.ldv, (ws_flags & IRL_WS_FP64) ? IRL_FP64 : IRL_FP32);
+        mb.nparts_e = energy_parts(L.ns);
+        b->hm.push_back(mb);
+    }
+    irl_system *s0 = b->sys[0];
+    if (hipMalloc((void **)&b->dm, count * sizeof(Member)) != hipSuccess ||
+        hipMalloc((void **)&b->dscal, count * sizeof(MemberScalars)) != hipSuccess ||
+        hipHostMalloc((void **)&b->hscal, count * sizeof(MemberScalars)) != hipSuccess) {
+        irl_batch_destroy(b);
+        return set_err(s0, IRL_ENOMEM, "batch descriptors");
+    }
+    if (hipMemcpy(b->dm, b->hm.data(), count * sizeof(Member), hipMemcpyHostToDevice) != hipSuccess) {
+        irl_batch_destroy(b);
+        return set_err(s0, IRL_EDEVICE, "batch descriptor upload");
+    }
+    *out = b;
+    return IRL_OK;
+}
+
+void irl_batch_destroy(irl_batch *b)
+{
+    if (!b) return;
+    if (b->dm) (void)hipFree(b->dm);
+    for (int r = 0; r < 2; ++r)
+        if (b->ditems[r]) (void)hipFree(b->ditems[r]);
+    if (b->hitems) (void)hipHostFree(b->hitems);
+    if (b->dscal) (void)hipFree(b->dscal);
+    if (b->hscal) (void)hipHostFree(b->hscal);
+    delete b;
+}
+
+int irl_batch_step(irl_batch *b, const irl_solver_opts *opts, double *const *dtheta,
+                   irl_step_result *results, int32_t *status, void *stream)
+{
+    if (!b) return IRL_EINVAL;
+    irl_system *s0 = b->sys[0];
+    irl_solver_opts o;
+    if (opts)
+        o = *opts;
+    else
+        irl_solver_opts_default(&o);
+    if (o.m < 2 || o.m > kMaxKrylov || o.k_keep < 1 || o.k_keep >= o.m || !(o.tol > 0.0) ||
+        o.max_restarts < 0 || (o.mode != IRL_MODE_A && o.mode != IRL_MODE_P))
+        return set_err(s0, IRL_EINVAL, "bad solver options");
+    if ((o.precision == IRL_FP64 && !(b->ws_flags & IRL_WS_FP64)) ||
+        (o.precision == IRL_FP32 && !(b->ws_flags & IRL_WS_FP32)))
+        return set_err(s0, IRL_ESTATE, "batch workspaces hold no D~ copy for this precision");
+    hipStream_t st = (hipStream_t)stream;
+    const int B = b->B;
+    std::vector<int> all(B);
+    for (int i = 0; i < B; ++i) all[i] = i;
+    std::vector<irl_step_result> res(B);
+    for (auto &r : res) {
+        std::memset(&r, 0, sizeof(r));
+        r.E_after = std::numeric_limits<double>::quiet_NaN();
+    }
+    for (int i = 0; i < B; ++i) {
+        b->hm[i].theta = b->nqs[i].theta;
+        b->hm[i].dtheta = nullptr;
+    }
+    int rc = upload_members(b, st);
+    if (rc) return rc;
+    const double t0 = now_ms();
+    if (!(o.flags & IRL_STEP_WS_CURRENT)) {
+        rc = batch_evaluate(b, all, st);
+        if (rc) return rc;
+    } else {
+        for (int i = 0; i < B; ++i)
+            if (!b->sys[i]->ws_valid || b->sys[i]->ws != b->ws[i])
+                return set_err(s0, IRL_ESTATE, "batch member " + std::to_string(i) + " holds no evaluation");
+    }
+    for (int i = 0; i < B; ++i) res[i].E_before = b->sys[i]->E_el + b->sys[i]->e_core;
+    const double t1 = now_ms();
+    std::vector<MemberSolve> ms;
+    rc = batch_solve(b, o, o.precision, false, ms, st);
+    if (rc) return rc;
+    std::vector<int> lo(B, 0);
+    if (o.precision == IRL_FP32 && (b->ws_flags & IRL_WS_FP64) && !(o.flags & IRL_STEP_NO_POLISH)) {
+        std::vector<MemberSolve> mp;
+        rc = batch_solve(b, o, IRL_FP64, true, mp, st);
+        if (rc) return rc;
+        for (int i = 0; i < B; ++i) {
+            lo[i] = ms[i].n_apply;
+            mp[i].n_apply += ms[i].n_apply;
+            mp[i].n_restart += ms[i].n_restart;
+        }
+        ms.swap(mp);
+    }
+    const double t2 = now_ms();
+    std::vector<int> upd;
+    for (int i = 0; i < B; ++i) {
+        irl_step_result &r = res[i];
+        r.lambda_min = ms[i].lam;
+        r.residual_est = ms[i].resid_est;
+        r.residual_explicit = ms[i].resid_explicit;
+        r.gap = ms[i].gap;
+        r.norm_T = ms[i].normT;
+        r.c0 = ms[i].c0;
+        r.n_apply = ms[i].n_apply;
+        r.n_restart = ms[i].n_restart;
+        r.converged = ms[i].converged;
+        r.tol_used = ms[i].tol_used;
+        r.n_apply_lo = lo[i];
+        int stt = ms[i].converged ? IRL_OK : IRL_ENOTCONV;
+        if (o.mode == IRL_MODE_A) {
+            if (!(std::fabs(r.c0) >= 1e-8))
+                stt = IRL_ESTEP;
+            else
+                upd.push_back(i);
+        }
+        if (status) status[i] = stt;
+    }
+    if (!upd.empty()) {
+        const bool move = !(o.flags & IRL_STEP_NO_UPDATE);
+        for (int i : upd) {
+            b->hm[i].dtheta = dtheta ? dtheta[i] : nullptr;
+            b->hm[i].theta = move ? b->nqs[i].theta : nullptr;
+        }
+        rc = upload_members(b, st);
+        if (rc) return rc;
+        ListSet lu;
+        rc = build_lists(b, upd, 1, o.precision, lu, st);
+        if (rc) return rc;
+        CK(s0, launch_lanczos_grouped(kGrpUpdate, b->dm, lu.ptr(b, LS_VEC), lu.cnt[LS_VEC], 0, 0, 0, 0, 0, nullptr, st));
+        for (int i = 0; i < B; ++i) {
+            b->hm[i].theta = b->nqs[i].theta;
+            b->hm[i].dtheta = nullptr;
+        }
+        rc = upload_members(b, st);
+        if (rc) return rc;
+        if (move && !(o.flags & IRL_STEP_NO_EVAL_AFTER)) {
+            rc = batch_evaluate(b, upd, st);
+            if (rc) return rc;
+            for (int i : upd) res[i].E_after = b->sys[i]->E_el + b->sys[i]->e_core;
+        }
+    }
+    CK(s0, hipStreamSynchronize(st));
+    const double t3 = now_ms();
+    for (int i = 0; i < B; ++i) {
+        res[i].ms_eval = t1 - t0;
+        res[i].ms_solve = t2 - t1;
+        res[i].ms_after = t3 - t2;
+        if (results) results[i] = res[i];
+    }
+    return IRL_OK;
+}
+
+}  // extern "C"

@@ -43,29 +43,16 @@ __device__ __forceinline__ T dot_chunk(typename Chunk<T>::V x, const T *v)
 
 constexpr size_t kMaxLdsBytes = 64 * 1024;
 
-// VLDS: v staged in LDS (row length up to 64 KiB), else read through the caches
-template <typename T, bool VLDS>
-__global__ __launch_bounds__(256) void k_gemv_rows(const T *__restrict__ D, int64_t ld, int64_t ns,
-                                                   const double *__restrict__ v, int64_t nv,
-                                                   const T *__restrict__ vglob, int c0,
-                                                   double *__restrict__ w)
+// rows [r0, r1) of D (row stride ld), interleaved over the 4 waves of a block:
+// w[r] = D[r, :] . v, one wavefront per row, 4 x 16-byte loads in flight per lane
+template <typename T>
+__device__ __forceinline__ void gemv_rows_range(const T *__restrict__ D, int64_t ld, int64_t r0,
+                                                int64_t r1, const T *vs, double *__restrict__ w,
+                                                int lane, int wv)
 {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    const T *vs = vglob;
-    if constexpr (VLDS) {
-        T *vl = reinterpret_cast<T *>(smem_raw);
-        for (int64_t c = threadIdx.x; c < ld; c += blockDim.x)
-            vl[c] = (c < nv && c >= c0) ? (T)v[c] : (T)0;
-        __syncthreads();
-        vs = vl;
-    }
     typedef typename Chunk<T>::V CV;
     constexpr int E = Chunk<T>::E;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t nch = ld / E;               // chunks per row (ld is a multiple of E)
-    // contiguous row range per block, rows interleaved over the 4 waves
-    const int64_t per = (ns + gridDim.x - 1) / gridDim.x;
-    const int64_t r0 = (int64_t)blockIdx.x * per, r1 = min(ns, r0 + per);
     for (int64_t r = r0 + wv; r < r1; r += 4) {
         const CV *row = reinterpret_cast<const CV *>(D + r * ld);
         T acc = 0;
@@ -84,6 +71,29 @@ __global__ __launch_bounds__(256) void k_gemv_rows(const T *__restrict__ D, int6
         for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kWave);
         if (lane == 0) w[r] = (double)acc;
     }
+}
+
+// VLDS: v staged in LDS (row length up to 64 KiB), else read through the caches
+template <typename T, bool VLDS>
+__global__ __launch_bounds__(256) void k_gemv_rows(const T *__restrict__ D, int64_t ld, int64_t ns,
+                                                   const double *__restrict__ v, int64_t nv,
+                                                   const T *__restrict__ vglob, int c0,
+                                                   double *__restrict__ w)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const T *vs = vglob;
+    if constexpr (VLDS) {
+        T *vl = reinterpret_cast<T *>(smem_raw);
+        for (int64_t c = threadIdx.x; c < ld; c += blockDim.x)
+            vl[c] = (c < nv && c >= c0) ? (T)v[c] : (T)0;
+        __syncthreads();
+        vs = vl;
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    // contiguous row range per block, rows interleaved over the 4 waves
+    const int64_t per = (ns + gridDim.x - 1) / gridDim.x;
+    const int64_t r0 = (int64_t)blockIdx.x * per, r1 = min(ns, r0 + per);
+    gemv_rows_range<T>(D, ld, r0, r1, vs, w, lane, wv);
 }
 
 // vector v converted to the stream precision, zero padded to ld
@@ -128,25 +138,24 @@ hipError_t launch_gemv_rows(const WsLayout &L, void *ws, int prec, const double 
 // tile (lane owns chunks cbase + 64 q, q < NCH: every row issues NCH
 // independent 16-byte loads per lane), the 4 wavefronts of a block are summed
 // in LDS in a fixed order and the block writes one partial row.
+// Rows [r0, r1) of column tile `tile` (lane owns chunks tile*64*NCH + lane +
+// 64 q): acc_a += a_r D[r, :], acc_b += b_r D[r, :], b_r = b[r] - coef sub[r].
+// Each column is summed by one lane over the wave's rows (r0 + wv + 4 t) and the
+// 4 waves are combined ((w0 + w1) + w2) + w3, so the order per column does not
+// depend on NCH.  Wave 0 writes the block's partial row (pa, pb).
 template <typename T, int NCH>
-__global__ __launch_bounds__(256) void k_gemv_t2(const T *__restrict__ D, int64_t ld, int64_t ns,
-                                                 const double *__restrict__ a,
-                                                 const double *__restrict__ b,
-                                                 const double *__restrict__ sub,
-                                                 const double *__restrict__ coefp,
-                                                 double *__restrict__ part, int64_t ldv,
-                                                 int nblk_rows)
+__device__ __forceinline__ void gemv_t2_range(const T *__restrict__ D, int64_t ld, int64_t r0,
+                                              int64_t r1, int tile, const double *__restrict__ a,
+                                              const double *__restrict__ b,
+                                              const double *__restrict__ sub, double coef,
+                                              double *__restrict__ pa, double *__restrict__ pb,
+                                              typename Chunk<T>::V (*red)[64 * NCH])
 {
     typedef typename Chunk<T>::V CV;
     constexpr int E = Chunk<T>::E;
-    __shared__ CV red[2][64 * NCH];
     const int64_t nch = ld / E;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int tile = blockIdx.x, rb = blockIdx.y;
     const int64_t cbase = (int64_t)tile * 64 * NCH + lane;
-    const int64_t per = (ns + nblk_rows - 1) / nblk_rows;
-    const int64_t r0 = (int64_t)rb * per, r1 = min(ns, r0 + per);
-    const double coef = sub ? *coefp : 0.0;
     CV acc_a[NCH], acc_b[NCH];
 #pragma unroll
     for (int q = 0; q < NCH; ++q) {
@@ -170,7 +179,6 @@ __global__ __launch_bounds__(256) void k_gemv_t2(const T *__restrict__ D, int64_
             acc_b[q] += bv * x[q];
         }
     }
-    // fixed-order sum of the 4 wavefronts: ((w0 + w1) + w2) + w3
     for (int src = 1; src < 4; ++src) {
         __syncthreads();
         if (wv == src) {
@@ -190,8 +198,6 @@ __global__ __launch_bounds__(256) void k_gemv_t2(const T *__restrict__ D, int64_
         }
     }
     if (wv != 0) return;
-    double *pa = part + (int64_t)rb * 2 * ldv;
-    double *pb = pa + ldv;
 #pragma unroll
     for (int q = 0; q < NCH; ++q) {
         const int64_t k = cbase + (int64_t)q * 64;
@@ -203,6 +209,26 @@ __global__ __launch_bounds__(256) void k_gemv_t2(const T *__restrict__ D, int64_
             }
         }
     }
+}
+
+// K7 launch: grid (column tiles, row blocks); rows per block = ceil(ns / nblk)
+template <typename T, int NCH>
+__global__ __launch_bounds__(256) void k_gemv_t2(const T *__restrict__ D, int64_t ld, int64_t ns,
+                                                 const double *__restrict__ a,
+                                                 const double *__restrict__ b,
+                                                 const double *__restrict__ sub,
+                                                 const double *__restrict__ coefp,
+                                                 double *__restrict__ part, int64_t ldv,
+                                                 int nblk_rows)
+{
+    typedef typename Chunk<T>::V CV;
+    __shared__ CV red[2][64 * NCH];
+    const int tile = blockIdx.x, rb = blockIdx.y;
+    const int64_t per = (ns + nblk_rows - 1) / nblk_rows;
+    const int64_t r0 = (int64_t)rb * per, r1 = min(ns, r0 + per);
+    const double coef = sub ? *coefp : 0.0;
+    double *pa = part + (int64_t)rb * 2 * ldv;
+    gemv_t2_range<T, NCH>(D, ld, r0, r1, tile, a, b, sub, coef, pa, pa + ldv, red);
 }
 
 // stage 1: group g sums row blocks [g*per, (g+1)*per) of part -> part2[g]
@@ -314,13 +340,11 @@ __device__ __forceinline__ Neu neu_merge(Neu a, Neu b)
     return r;
 }
 
-__global__ __launch_bounds__(256) void k_energy_stage1(const double *__restrict__ psi,
-                                                       const double *__restrict__ hpsi, int64_t ns,
-                                                       double *__restrict__ red)
+// compensated sums of psi_r^2 and psi_r (H psi)_r over rows [r0, r1) -> red[0..3]
+__device__ void energy_stage1_body(const double *__restrict__ psi, const double *__restrict__ hpsi,
+                                   int64_t r0, int64_t r1, double *__restrict__ red)
 {
     __shared__ double sh[4][256];
-    const int64_t per = (ns + gridDim.x - 1) / gridDim.x;
-    const int64_t r0 = (int64_t)blockIdx.x * per, r1 = min(ns, r0 + per);
     Neu z{0, 0}, e{0, 0};
     for (int64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
         double p = psi[r];
@@ -346,14 +370,23 @@ __global__ __launch_bounds__(256) void k_energy_stage1(const double *__restrict_
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        red[blockIdx.x * 4 + 0] = sh[0][0];
-        red[blockIdx.x * 4 + 1] = sh[1][0];
-        red[blockIdx.x * 4 + 2] = sh[2][0];
-        red[blockIdx.x * 4 + 3] = sh[3][0];
+        red[0] = sh[0][0];
+        red[1] = sh[1][0];
+        red[2] = sh[2][0];
+        red[3] = sh[3][0];
     }
 }
 
-__global__ void k_energy_stage2(const double *__restrict__ red, int nparts, WsScalars *sc)
+__global__ __launch_bounds__(256) void k_energy_stage1(const double *__restrict__ psi,
+                                                       const double *__restrict__ hpsi, int64_t ns,
+                                                       double *__restrict__ red)
+{
+    const int64_t per = (ns + gridDim.x - 1) / gridDim.x;
+    const int64_t r0 = (int64_t)blockIdx.x * per, r1 = min(ns, r0 + per);
+    energy_stage1_body(psi, hpsi, r0, r1, red + blockIdx.x * 4);
+}
+
+__device__ void energy_stage2_body(const double *__restrict__ red, int nparts, WsScalars *sc)
 {
     if (threadIdx.x != 0) return;
     Neu z{0, 0}, e{0, 0};
@@ -370,6 +403,11 @@ __global__ void k_energy_stage2(const double *__restrict__ red, int nparts, WsSc
     sc->E_el = N / Z;
 }
 
+__global__ void k_energy_stage2(const double *__restrict__ red, int nparts, WsScalars *sc)
+{
+    energy_stage2_body(red, nparts, sc);
+}
+
 hipError_t launch_energy_reduce(const WsLayout &L, void *ws, hipStream_t st)
 {
     int parts = L.ns < (int64_t)kScalarParts * 256 ? (int)((L.ns + 255) / 256) : kScalarParts;
@@ -377,6 +415,146 @@ hipError_t launch_energy_reduce(const WsLayout &L, void *ws, hipStream_t st)
     k_energy_stage1<<<parts, 256, 0, st>>>(ws_ptr<double>(ws, L.off_psi),
                                            ws_ptr<double>(ws, L.off_hpsi), L.ns, red);
     k_energy_stage2<<<1, 64, 0, st>>>(red, parts, ws_ptr<WsScalars>(ws, L.off_scal));
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Grouped launches (batch): work item (member, indices, rows) per block, with
+// the per-member arithmetic of the solo launches (same row blocks, same
+// reduction order), so a batched result equals the solo result bit for bit.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ const T *member_D(const Member &mb)
+{
+    if constexpr (sizeof(T) == 8)
+        return reinterpret_cast<const T *>(mb.D64);
+    else
+        return reinterpret_cast<const T *>(mb.D32);
+}
+
+// vsel 0: v = Krylov row j of buffer cur; vsel 1: v = the Ritz vector y
+template <typename T>
+__global__ __launch_bounds__(256) void k_gemv_rows_grouped(const Member *__restrict__ M,
+                                                           const WorkItem *__restrict__ items,
+                                                           int vsel, int j, int cur, int c0)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const WorkItem it = items[blockIdx.x];
+    const Member &mb = M[it.m];
+    const double *v = vsel ? mb.y : mb.kry[cur] + (int64_t)j * mb.ld;
+    T *vl = reinterpret_cast<T *>(smem_raw);
+    for (int64_t c = threadIdx.x; c < mb.ld; c += blockDim.x)
+        vl[c] = (c < mb.ncols && c >= c0) ? (T)v[c] : (T)0;
+    __syncthreads();
+    gemv_rows_range<T>(member_D<T>(mb), mb.ld, it.r0, it.r1, vl, mb.w, threadIdx.x & 63,
+                       threadIdx.x >> 6);
+}
+
+hipError_t launch_gemv_rows_grouped(const Member *M, const WorkItem *items, int nitems, int prec,
+                                    int vsel, int j, int cur, int zero_v0, size_t lds_bytes,
+                                    hipStream_t st)
+{
+    if (nitems <= 0) return hipSuccess;
+    if (prec == IRL_FP64)
+        k_gemv_rows_grouped<double><<<nitems, 256, lds_bytes, st>>>(M, items, vsel, j, cur, zero_v0);
+    else
+        k_gemv_rows_grouped<float><<<nitems, 256, lds_bytes, st>>>(M, items, vsel, j, cur, zero_v0);
+    return hipGetLastError();
+}
+
+// which 0: [yS, yH] partials of D~^T [w, u]; which 1: gradient partials of D~^T [psi, H psi - E psi]
+template <typename T>
+__global__ __launch_bounds__(256) void k_gemv_t2_grouped(const Member *__restrict__ M,
+                                                         const WorkItem *__restrict__ items,
+                                                         int which)
+{
+    typedef typename Chunk<T>::V CV;
+    __shared__ CV red[2][64 * kGroupedT2Chunks];
+    const WorkItem it = items[blockIdx.x];
+    const Member &mb = M[it.m];
+    const double *a = which ? mb.psi : mb.w;
+    const double *b = which ? mb.hpsi : mb.u;
+    const double *sub = which ? mb.psi : nullptr;
+    const double coef = which ? mb.sc->E_el : 0.0;
+    double *pa = mb.part + (int64_t)it.b * 2 * mb.ld;
+    gemv_t2_range<T, kGroupedT2Chunks>(member_D<T>(mb), mb.ld, it.r0, it.r1, it.a, a, b, sub, coef,
+                                       pa, pa + mb.ld, red);
+}
+
+hipError_t launch_gemv_t2_grouped(const Member *M, const WorkItem *items, int nitems, int prec,
+                                  int which, hipStream_t st)
+{
+    if (nitems <= 0) return hipSuccess;
+    if (prec == IRL_FP64)
+        k_gemv_t2_grouped<double><<<nitems, 256, 0, st>>>(M, items, which);
+    else
+        k_gemv_t2_grouped<float><<<nitems, 256, 0, st>>>(M, items, which);
+    return hipGetLastError();
+}
+
+// item: member m, column chunk a (256 of the 2 ld partial columns); the two
+// reduction levels of the solo launch, in the same order
+__global__ void k_reduce_grouped(const Member *__restrict__ M, const WorkItem *__restrict__ items,
+                                 int which)
+{
+    const WorkItem it = items[blockIdx.x];
+    const Member &mb = M[it.m];
+    const int64_t len = 2 * mb.ld;
+    const int64_t c = (int64_t)it.a * blockDim.x + threadIdx.x;
+    if (c >= len) return;
+    const int64_t cc = c < mb.ld ? c : c - mb.ld;
+    if (cc >= mb.ncols) return;
+    const int nblk = mb.nblk_t2;
+    const int groups = nblk < kReduceGroups ? nblk : kReduceGroups;
+    const int per = (nblk + groups - 1) / groups;
+    double tot = 0.0;
+    for (int g = 0; g < groups; ++g) {
+        const int b0 = g * per, b1 = min(nblk, b0 + per);
+        double s = 0.0;
+        for (int b = b0; b < b1; ++b) s += mb.part[(int64_t)b * len + c];
+        tot += s;
+    }
+    if (which == 0) {
+        if (c < mb.ld) mb.yS[cc] = tot * 1.0;
+        else mb.yH[cc] = tot * 1.0;
+    } else {
+        const double f = 2.0 / mb.sc->Z;
+        if (c < mb.ld) mb.y[cc] = tot * f;
+        else mb.grad[cc] = tot * f;
+    }
+}
+
+hipError_t launch_reduce_grouped(const Member *M, const WorkItem *items, int nitems, int which,
+                                 hipStream_t st)
+{
+    if (nitems <= 0) return hipSuccess;
+    k_reduce_grouped<<<nitems, 256, 0, st>>>(M, items, which);
+    return hipGetLastError();
+}
+
+// stage 1 item: member m, part a, rows [r0, r1); stage 2 item: member m
+__global__ __launch_bounds__(256) void k_energy_grouped1(const Member *__restrict__ M,
+                                                         const WorkItem *__restrict__ items)
+{
+    const WorkItem it = items[blockIdx.x];
+    const Member &mb = M[it.m];
+    energy_stage1_body(mb.psi, mb.hpsi, it.r0, it.r1, mb.red + (int64_t)it.a * 4);
+}
+
+__global__ void k_energy_grouped2(const Member *__restrict__ M, const WorkItem *__restrict__ items)
+{
+    const Member &mb = M[items[blockIdx.x].m];
+    energy_stage2_body(mb.red, mb.nparts_e, mb.sc);
+}
+
+hipError_t launch_energy_grouped(const Member *M, const WorkItem *items, int nitems, int stage,
+                                 hipStream_t st)
+{
+    if (nitems <= 0) return hipSuccess;
+    if (stage == 1)
+        k_energy_grouped1<<<nitems, 256, 0, st>>>(M, items);
+    else
+        k_energy_grouped2<<<nitems, 64, 0, st>>>(M, items);
     return hipGetLastError();
 }
 

@@ -22,18 +22,7 @@
 
 namespace irl {
 
-struct HamArgs {
-    int n, na, nb;
-    int64_t ns, nA;
-    const uint64_t *keys;
-    const double *diag, *h, *g;
-    const uint64_t *hkeys;
-    const int32_t *hrows;
-    uint64_t hmask;
-    const uint32_t *hfilter;
-    int hfbits;
-    const int32_t *rankA, *rankB;
-};
+typedef HamView HamArgs;
 
 __device__ __forceinline__ uint64_t mix64h(uint64_t x)
 {
@@ -216,36 +205,72 @@ __device__ __forceinline__ void visit_row(const HamArgs &A, const WaveLists &L, 
     }
 }
 
+// one determinant row on one wavefront: u[row] = H_rr w[row] + sum of the row's connections
+template <bool FULL>
+__device__ __forceinline__ void pull_row(const HamArgs &A, WaveLists &L, int64_t row, int lane,
+                                         const double *__restrict__ w, double *__restrict__ u)
+{
+    uint64_t key = A.keys[row];
+    uint32_t al = (uint32_t)key, be = (uint32_t)(key >> 32);
+    build_lists(al, A.n, A.na, L.sA, L.sAstr, L.poA, L.pvA, lane);
+    build_lists(be, A.n, A.nb, L.sB, L.sBstr, L.poB, L.pvB, lane);
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    double acc = 0.0;
+    visit_row<FULL>(A, L, al, be, lane, kWave,
+                    [&](int64_t r, int, int, double v) { acc += v * w[r]; });
+    acc = wave_sum(acc);
+    if (lane == 0) u[row] = A.diag[row] * w[row] + acc;
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <bool FULL>
 __global__ __launch_bounds__(256) void k_ham_pull(HamArgs A, const double *__restrict__ w,
                                                   double *__restrict__ u)
 {
     __shared__ WaveLists lists[4];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    WaveLists &L = lists[wv];
     const int64_t nwaves = (int64_t)gridDim.x * 4;
-    for (int64_t row = (int64_t)blockIdx.x * 4 + wv; row < A.ns; row += nwaves) {
-        uint64_t key = A.keys[row];
-        uint32_t al = (uint32_t)key, be = (uint32_t)(key >> 32);
-        build_lists(al, A.n, A.na, L.sA, L.sAstr, L.poA, L.pvA, lane);
-        build_lists(be, A.n, A.nb, L.sB, L.sBstr, L.poB, L.pvB, lane);
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        double acc = 0.0;
-        visit_row<FULL>(A, L, al, be, lane, kWave,
-                        [&](int64_t r, int, int, double v) { acc += v * w[r]; });
-        acc = wave_sum(acc);
-        if (lane == 0) u[row] = A.diag[row] * w[row] + acc;
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int64_t row = (int64_t)blockIdx.x * 4 + wv; row < A.ns; row += nwaves)
+        pull_row<FULL>(A, lists[wv], row, lane, w, u);
+}
+
+// grouped: one work item = rows [r0, r1) of member m; which = 0: w -> u, 1: psi -> H psi
+__global__ __launch_bounds__(256) void k_ham_pull_grouped(const Member *__restrict__ M,
+                                                          const WorkItem *__restrict__ items,
+                                                          int which)
+{
+    __shared__ WaveLists lists[4];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const WorkItem it = items[blockIdx.x];
+    const Member &mb = M[it.m];
+    const HamArgs A = mb.ham;
+    const double *w = which ? mb.psi : mb.w;
+    double *u = which ? mb.hpsi : mb.u;
+    const bool ranks = A.hkeys == nullptr;
+    for (int64_t row = it.r0 + wv; row < it.r1; row += 4) {
+        if (ranks)
+            pull_row<true>(A, lists[wv], row, lane, w, u);
+        else
+            pull_row<false>(A, lists[wv], row, lane, w, u);
     }
 }
 
-static HamArgs ham_args(const irl_system *s)
+hipError_t launch_ham_pull_grouped(const Member *M, const WorkItem *items, int nitems, int which,
+                                   hipStream_t st)
+{
+    if (nitems <= 0) return hipSuccess;
+    k_ham_pull_grouped<<<nitems, 256, 0, st>>>(M, items, which);
+    return hipGetLastError();
+}
+
+HamView ham_view(const irl_system *s)
 {
     HamArgs A;
+    A.full = s->full ? 1 : 0;
     A.n = s->n;
     A.na = s->na;
     A.nb = s->nb;
@@ -270,7 +295,7 @@ static hipError_t launch_ham_product(const irl_system *s, const double *w, doubl
 hipError_t launch_ham_apply(const irl_system *s, const double *w, double *u, hipStream_t st)
 {
     if (s->ham_kernel == 2) return launch_ham_product(s, w, u, st);
-    HamArgs A = ham_args(s);
+    HamArgs A = ham_view(s);
     int64_t blocks = (s->ns + 3) / 4;
     if (blocks > 65536) blocks = 65536;
     if (s->d.hkeys != nullptr)
@@ -311,7 +336,7 @@ hipError_t launch_ham_row_list(const irl_system *s, int64_t row, int32_t *tgt, i
                                uint8_t *kind, double *val, int32_t *count, int cap,
                                hipStream_t st)
 {
-    HamArgs A = ham_args(s);
+    HamArgs A = ham_view(s);
     if (s->d.hkeys != nullptr)
         k_ham_row_list<false><<<1, 64, 0, st>>>(A, row, tgt, sign, kind, val, count, cap);
     else

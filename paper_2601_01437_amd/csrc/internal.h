@@ -92,6 +92,48 @@ struct SystemDev {
     double *jA = nullptr;       // nA x n*n: sum_{i in alpha} (pq|ii)
 };
 
+// Read-only view of a system's Hamiltonian tables (pull kernels, solo and grouped).
+struct HamView {
+    int n, na, nb, full;
+    int64_t ns, nA;
+    const uint64_t *keys;
+    const double *diag, *h, *g;
+    const uint64_t *hkeys;
+    const int32_t *hrows;
+    uint64_t hmask;
+    const uint32_t *hfilter;
+    int hfbits;
+    const int32_t *rankA, *rankB;
+};
+
+// One member of a grouped (batched) launch: its system view, workspace
+// pointers and network.  Lives in device memory; grouped kernels index it.
+struct Member {
+    HamView ham;
+    const double *D64;
+    const float *D32;
+    int64_t ld, ncols, ns;
+    double *psi, *hpsi, *w, *u, *grad, *yH, *yS, *y, *r, *part, *part2, *red, *vconv;
+    double *kry[2];
+    WsScalars *sc;
+    int32_t V, H;
+    double *theta;
+    double *dtheta;
+    int32_t nblk_t2;     // row blocks of the D~^T stream (same as the solo launch)
+    int32_t nparts_e;    // blocks of the energy reduction (same as the solo launch)
+};
+
+// A unit of grouped work: member m, kernel-specific indices a, b, rows [r0, r1).
+struct WorkItem {
+    int32_t m, a, b, pad;
+    int64_t r0, r1;
+};
+
+// Scalars gathered from every member after a grouped phase (one readback).
+struct MemberScalars {
+    double Z, E_el, lam, resid_est, gap, normT, c0, resid2;
+};
+
 }  // namespace irl
 
 struct irl_system {
@@ -140,6 +182,9 @@ hipError_t launch_lookup_any(const irl_system *s, const uint64_t *q, int64_t nq,
 
 // hamiltonian.hip
 hipError_t launch_product_tables(irl_system *s, hipStream_t st);
+HamView ham_view(const irl_system *s);
+hipError_t launch_ham_pull_grouped(const Member *M, const WorkItem *items, int nitems, int which,
+                                   hipStream_t st);
 hipError_t launch_ham_apply(const irl_system *s, const double *w, double *u, hipStream_t st);
 hipError_t launch_ham_row_list(const irl_system *s, int64_t row, int32_t *tgt, int8_t *sign,
                                uint8_t *kind, double *val, int32_t *count, int cap,
@@ -183,5 +228,30 @@ hipError_t launch_update(const WsLayout &L, void *ws, const double *y, double *d
                          double *theta, int64_t P, int mode, hipStream_t st);
 hipError_t launch_copy(double *dst, const double *src, int64_t n, hipStream_t st);
 hipError_t launch_reset_solve(const WsLayout &L, void *ws, hipStream_t st);
+
+// grouped launches (batch): one work item per member for the vector kernels
+enum GroupedOp {
+    kGrpReset, kGrpStart, kGrpLanczos, kGrpRitz, kGrpRestart, kGrpRitzVector, kGrpResidual,
+    kGrpUpdate, kGrpGather
+};
+// op-specific integer arguments: Start(mode, from_y), Lanczos(j, cur, mode, split),
+// Ritz(m, k), Restart(cur, m, k, mode), RitzVector(cur, m), Residual(mode, split)
+hipError_t launch_lanczos_grouped(int op, const Member *M, const WorkItem *items, int nitems,
+                                  int i0, int i1, int i2, int i3, uint64_t seed,
+                                  MemberScalars *out, hipStream_t st);
+// row/tile work items: which = 0 apply (w -> u, [yS, yH] = D~^T [w, u]),
+// which = 1 evaluation (psi -> H psi, gradient)
+hipError_t launch_gemv_rows_grouped(const Member *M, const WorkItem *items, int nitems, int prec,
+                                    int vsel, int j, int cur, int zero_v0, size_t lds_bytes,
+                                    hipStream_t st);
+hipError_t launch_gemv_t2_grouped(const Member *M, const WorkItem *items, int nitems, int prec,
+                                  int which, hipStream_t st);
+hipError_t launch_reduce_grouped(const Member *M, const WorkItem *items, int nitems, int which,
+                                 hipStream_t st);
+hipError_t launch_energy_grouped(const Member *M, const WorkItem *items, int nitems, int stage,
+                                 hipStream_t st);
+hipError_t launch_nqs_dtilde_grouped(const Member *M, const WorkItem *items, int nitems, int n,
+                                     uint32_t flags, hipStream_t st);
+constexpr int kGroupedT2Chunks = 8;   // chunks per lane of a grouped D~^T column tile
 
 }  // namespace irl

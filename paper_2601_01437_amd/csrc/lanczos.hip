@@ -154,7 +154,7 @@ hipError_t launch_start_vector(double *v, int64_t ncols, int64_t ldv, int mode, 
 }
 
 // One Lanczos step j: w = H~' v_j from (yH, yS), recurrence, CGS2, normalise.
-__global__ __launch_bounds__(kVecThreads) void k_lanczos_step(
+__device__ void lanczos_step_body(
     const double *__restrict__ yH, const double *__restrict__ yS, const double *__restrict__ grad,
     WsScalars *sc, double *V, int64_t ldv, int64_t ncols, int j, int mode, int split, uint64_t seed)
 {
@@ -199,6 +199,13 @@ __global__ __launch_bounds__(kVecThreads) void k_lanczos_step(
         sc->beta[j] = beta;
         sc->normT = normT;
     }
+}
+
+__global__ __launch_bounds__(kVecThreads) void k_lanczos_step(
+    const double *__restrict__ yH, const double *__restrict__ yS, const double *__restrict__ grad,
+    WsScalars *sc, double *V, int64_t ldv, int64_t ncols, int j, int mode, int split, uint64_t seed)
+{
+    lanczos_step_body(yH, yS, grad, sc, V, ldv, ncols, j, mode, split, seed);
 }
 
 hipError_t launch_lanczos_step(const WsLayout &L, void *ws, double *V, int j, int mode, int split,
@@ -279,7 +286,7 @@ __device__ void tridiag_eig(double *d, double *e, double *Zm, int m)
     }
 }
 
-__global__ __launch_bounds__(64) void k_ritz(WsScalars *sc, int m, int k)
+__device__ void ritz_body(WsScalars *sc, int m, int k)
 {
     __shared__ double d[kMaxKrylov], e[kMaxKrylov], Zm[kMaxKrylov * kMaxKrylov];
     __shared__ int rank[kMaxKrylov];
@@ -340,6 +347,11 @@ __global__ __launch_bounds__(64) void k_ritz(WsScalars *sc, int m, int k)
     }
 }
 
+__global__ __launch_bounds__(64) void k_ritz(WsScalars *sc, int m, int k)
+{
+    ritz_body(sc, m, k);
+}
+
 hipError_t launch_ritz(const WsLayout &L, void *ws, int m, int k, hipStream_t st)
 {
     k_ritz<<<1, 64, 0, st>>>(ws_ptr<WsScalars>(ws, L.off_scal), m, k);
@@ -348,7 +360,7 @@ hipError_t launch_ritz(const WsLayout &L, void *ws, int m, int k, hipStream_t st
 
 // V+ = V Q[:, :k], f = V Q[:, k] * T+[k][k-1] + beta_m Q[m-1][k-1] v_{m+1},
 // v_{k+1} = f / ||f|| (reorthogonalised), T <- leading k x k of Q^T T Q.
-__global__ __launch_bounds__(kVecThreads) void k_restart_basis(WsScalars *sc, const double *Vold,
+__device__ void restart_basis_body(WsScalars *sc, const double *Vold,
                                                               double *Vnew, int64_t ldv,
                                                               int64_t ncols, int m, int k, int mode,
                                                               uint64_t seed)
@@ -395,6 +407,14 @@ __global__ __launch_bounds__(kVecThreads) void k_restart_basis(WsScalars *sc, co
     }
 }
 
+__global__ __launch_bounds__(kVecThreads) void k_restart_basis(WsScalars *sc, const double *Vold,
+                                                              double *Vnew, int64_t ldv,
+                                                              int64_t ncols, int m, int k, int mode,
+                                                              uint64_t seed)
+{
+    restart_basis_body(sc, Vold, Vnew, ldv, ncols, m, k, mode, seed);
+}
+
 hipError_t launch_restart_basis(const WsLayout &L, void *ws, const double *Vold, double *Vnew,
                                 int m, int k, int mode, uint64_t seed, hipStream_t st)
 {
@@ -404,7 +424,7 @@ hipError_t launch_restart_basis(const WsLayout &L, void *ws, const double *Vold,
 }
 
 // y = V U[:, 0] normalised; c0 = y[0]
-__global__ __launch_bounds__(kVecThreads) void k_ritz_vector(WsScalars *sc, const double *V,
+__device__ void ritz_vector_body(WsScalars *sc, const double *V,
                                                             int64_t ldv, int m, double *y)
 {
     __shared__ double sh[kVecWaves * (kMaxKrylov + 1)];
@@ -421,6 +441,12 @@ __global__ __launch_bounds__(kVecThreads) void k_ritz_vector(WsScalars *sc, cons
     if (threadIdx.x == 0) sc->c0 = y[0];
 }
 
+__global__ __launch_bounds__(kVecThreads) void k_ritz_vector(WsScalars *sc, const double *V,
+                                                            int64_t ldv, int m, double *y)
+{
+    ritz_vector_body(sc, V, ldv, m, y);
+}
+
 hipError_t launch_ritz_vector(const WsLayout &L, void *ws, const double *V, int m, double *y,
                               hipStream_t st)
 {
@@ -429,7 +455,7 @@ hipError_t launch_ritz_vector(const WsLayout &L, void *ws, const double *V, int 
 }
 
 // r = H~'y - lam y from (yH, yS); resid2 = ||r||^2
-__global__ __launch_bounds__(kVecThreads) void k_residual(WsScalars *sc, const double *yH,
+__device__ void residual_body(WsScalars *sc, const double *yH,
                                                          const double *yS, const double *grad,
                                                          const double *y, double *r, int64_t ldv,
                                                          int64_t ncols, int mode, int split)
@@ -448,6 +474,14 @@ __global__ __launch_bounds__(kVecThreads) void k_residual(WsScalars *sc, const d
     }
     double s = block_sum(p, sh);
     if (threadIdx.x == 0) sc->resid2 = s;
+}
+
+__global__ __launch_bounds__(kVecThreads) void k_residual(WsScalars *sc, const double *yH,
+                                                         const double *yS, const double *grad,
+                                                         const double *y, double *r, int64_t ldv,
+                                                         int64_t ncols, int mode, int split)
+{
+    residual_body(sc, yH, yS, grad, y, r, ldv, ncols, mode, split);
 }
 
 hipError_t launch_residual(const WsLayout &L, void *ws, const double *y, double *r, int mode,
@@ -513,6 +547,126 @@ __global__ void k_reset_solve(WsScalars *sc)
 hipError_t launch_reset_solve(const WsLayout &L, void *ws, hipStream_t st)
 {
     k_reset_solve<<<1, 64, 0, st>>>(ws_ptr<WsScalars>(ws, L.off_scal));
+    return hipGetLastError();
+}
+
+}  // namespace irl
+
+// ---------------------------------------------------------------------------
+// Grouped launches for a batch of independent systems advancing in lockstep:
+// block b works on member items[b].m with exactly the per-member arithmetic of
+// the solo kernels above.
+// ---------------------------------------------------------------------------
+namespace irl {
+
+__global__ void k_reset_grouped(const Member *__restrict__ M, const WorkItem *__restrict__ items)
+{
+    if (threadIdx.x == 0) {
+        WsScalars *sc = M[items[blockIdx.x].m].sc;
+        sc->normT = 0.0;
+        sc->breakdowns = 0;
+        sc->resid2 = 0.0;
+    }
+}
+
+__global__ __launch_bounds__(kVecThreads) void k_start_vector_grouped(
+    const Member *__restrict__ M, const WorkItem *__restrict__ items, int mode, uint64_t seed,
+    int from_y)
+{
+    __shared__ double sh[kVecWaves * (kMaxKrylov + 1)];
+    __shared__ double hsh[kMaxKrylov + 1];
+    const Member &mb = M[items[blockIdx.x].m];
+    if (from_y) {
+        for (int64_t i = threadIdx.x; i < mb.ld; i += kVecThreads) mb.kry[0][i] = mb.y[i];
+        return;
+    }
+    fresh_vector(nullptr, mb.ld, 0, mb.kry[0], mb.ld, mb.ncols, mode, seed, sh, hsh);
+}
+
+__global__ __launch_bounds__(kVecThreads) void k_lanczos_step_grouped(
+    const Member *__restrict__ M, const WorkItem *__restrict__ items, int j, int cur, int mode,
+    int split, uint64_t seed)
+{
+    const Member &mb = M[items[blockIdx.x].m];
+    lanczos_step_body(mb.yH, mb.yS, mb.grad, mb.sc, mb.kry[cur], mb.ld, mb.ncols, j, mode, split,
+                      seed);
+}
+
+__global__ __launch_bounds__(64) void k_ritz_grouped(const Member *__restrict__ M,
+                                                     const WorkItem *__restrict__ items, int m,
+                                                     int k)
+{
+    ritz_body(M[items[blockIdx.x].m].sc, m, k);
+}
+
+__global__ __launch_bounds__(kVecThreads) void k_restart_basis_grouped(
+    const Member *__restrict__ M, const WorkItem *__restrict__ items, int cur, int m, int k,
+    int mode, uint64_t seed)
+{
+    const Member &mb = M[items[blockIdx.x].m];
+    restart_basis_body(mb.sc, mb.kry[cur], mb.kry[1 - cur], mb.ld, mb.ncols, m, k, mode, seed);
+}
+
+__global__ __launch_bounds__(kVecThreads) void k_ritz_vector_grouped(
+    const Member *__restrict__ M, const WorkItem *__restrict__ items, int cur, int m)
+{
+    const Member &mb = M[items[blockIdx.x].m];
+    ritz_vector_body(mb.sc, mb.kry[cur], mb.ld, m, mb.y);
+}
+
+__global__ __launch_bounds__(kVecThreads) void k_residual_grouped(
+    const Member *__restrict__ M, const WorkItem *__restrict__ items, int mode, int split)
+{
+    const Member &mb = M[items[blockIdx.x].m];
+    residual_body(mb.sc, mb.yH, mb.yS, mb.grad, mb.y, mb.r, mb.ld, mb.ncols, mode, split);
+}
+
+__global__ void k_update_grouped(const Member *__restrict__ M, const WorkItem *__restrict__ items)
+{
+    const Member &mb = M[items[blockIdx.x].m];
+    const double c0 = mb.y[0];
+    for (int64_t i = threadIdx.x; i < mb.ncols - 1; i += blockDim.x) {
+        const double d = mb.y[i + 1] / c0;
+        if (mb.dtheta) mb.dtheta[i] = d;
+        if (mb.theta) mb.theta[i] += d;
+    }
+}
+
+__global__ void k_gather_scalars(const Member *__restrict__ M, const WorkItem *__restrict__ items,
+                                 MemberScalars *out)
+{
+    if (threadIdx.x != 0) return;
+    const int m = items[blockIdx.x].m;
+    const WsScalars *sc = M[m].sc;
+    MemberScalars o;
+    o.Z = sc->Z;
+    o.E_el = sc->E_el;
+    o.lam = sc->lam;
+    o.resid_est = sc->resid_est;
+    o.gap = sc->gap;
+    o.normT = sc->normT;
+    o.c0 = sc->c0;
+    o.resid2 = sc->resid2;
+    out[m] = o;
+}
+
+hipError_t launch_lanczos_grouped(int op, const Member *M, const WorkItem *items, int nitems,
+                                  int i0, int i1, int i2, int i3, uint64_t seed,
+                                  MemberScalars *out, hipStream_t st)
+{
+    if (nitems <= 0) return hipSuccess;
+    switch (op) {
+    case kGrpReset: k_reset_grouped<<<nitems, 64, 0, st>>>(M, items); break;
+    case kGrpStart: k_start_vector_grouped<<<nitems, kVecThreads, 0, st>>>(M, items, i0, seed, i1); break;
+    case kGrpLanczos: k_lanczos_step_grouped<<<nitems, kVecThreads, 0, st>>>(M, items, i0, i1, i2, i3, seed); break;
+    case kGrpRitz: k_ritz_grouped<<<nitems, 64, 0, st>>>(M, items, i0, i1); break;
+    case kGrpRestart: k_restart_basis_grouped<<<nitems, kVecThreads, 0, st>>>(M, items, i0, i1, i2, i3, seed); break;
+    case kGrpRitzVector: k_ritz_vector_grouped<<<nitems, kVecThreads, 0, st>>>(M, items, i0, i1); break;
+    case kGrpResidual: k_residual_grouped<<<nitems, kVecThreads, 0, st>>>(M, items, i0, i1); break;
+    case kGrpUpdate: k_update_grouped<<<nitems, 256, 0, st>>>(M, items); break;
+    case kGrpGather: k_gather_scalars<<<nitems, 64, 0, st>>>(M, items, out); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

@@ -110,3 +110,40 @@ class System:
 
 def to_device(x, device="cuda", dtype=torch.float64):
     return torch.as_tensor(np.ascontiguousarray(x), dtype=dtype).to(device)
+
+
+class Batch:
+    """Independent optimisations stepped together with grouped kernels."""
+
+    def __init__(self, systems, thetas, Vs, Hs, ws_flags=B.IRL_WS_FP64):
+        self.systems = list(systems)
+        self.thetas = list(thetas)
+        self.ws = [s.workspace(V * H + H + V + 1, ws_flags) for s, V, H in zip(self.systems, Vs, Hs)]
+        self.Ps = [V * H + H + V for V, H in zip(Vs, Hs)]
+        self.ws_flags = ws_flags
+        self.handle = B.irl_batch_create([s.handle for s in self.systems],
+                                         list(zip(Vs, Hs, self.thetas)), self.ws, ws_flags)
+
+    def step(self, m=20, k_keep=1, tol=1e-12, max_restarts=300, precision=B.IRL_FP64,
+             mode=B.IRL_MODE_A, seed=0, flags=0, want_dtheta=False):
+        o = B.irl_solver_opts_default()
+        o.m, o.k_keep, o.tol, o.max_restarts = m, k_keep, tol, max_restarts
+        o.precision, o.mode, o.seed, o.flags = precision, mode, seed, flags
+        dth = None
+        if want_dtheta:
+            dth = [torch.empty(P, dtype=torch.float64, device=s.device)
+                   for s, P in zip(self.systems, self.Ps)]
+        res, status = B.irl_batch_step(self.handle, o, len(self.systems), dtheta=dth,
+                                       first_system=self.systems[0].handle)
+        return res, status, dth
+
+    def close(self):
+        if self.handle is not None:
+            B.irl_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
