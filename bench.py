@@ -31,6 +31,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
 METRIC = "time per IRL step & operator HBM GB/s vs roofline; solves/s, p99 step latency"
+HAM_KERNELS = ["hashed-pull", "rank-pull", "string-product", "beta-blocked-pull"]
 
 
 def log(msg):
@@ -118,12 +119,108 @@ def cpu_baseline(wl, keys_fn, applies_per_step, sample_rows=1_000_000, chunk=20_
     }
 
 
+def run_batch_bench(args):
+    """64 independent solves (n ~ U{8..16}, half filled, full space capped at
+    2^18 determinants, H ~ U{16..128}, FP64, m = 20, k = 1): one optimisation
+    step each, (a) one after another with the solo path, (b) as batches of
+    grouped kernels admitted in waves by workspace footprint."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2601_01437_amd import binding as B
+    from paper_2601_01437_amd import Batch, System
+
+    wls = synth.batch_workloads(args.solves)
+    log(f"building {len(wls)} systems")
+    systems, thetas0 = [], []
+    for w in wls:
+        h, g = w.integrals()
+        systems.append(System(w.n, w.na, w.nb, h, g, dets=w.dets()))
+        thetas0.append(torch.tensor(w.theta(), dtype=torch.float64, device="cuda"))
+    fl = B.IRL_WS_FP64
+    sizes = [B.irl_workspace_query(s.handle, w.P + 1, fl) for s, w in zip(systems, wls)]
+    for s, w in zip(systems, wls):
+        s.workspace(w.P + 1, fl)
+    torch.cuda.synchronize()
+    log(f"workspaces: {sum(sizes) / 1e9:.1f} GB")
+    opts = dict(m=20, k_keep=1, tol=1e-12)
+
+    def solo_pass():
+        out = []
+        t0 = time.perf_counter()
+        for s, w, th0 in zip(systems, wls, thetas0):
+            th = th0.clone()
+            rc, r, _, _ = s.step(th, w.V, w.H, ws_flags=fl, want_dtheta=False, **opts)
+            out.append((rc, r.lambda_min, r.E_after, r.n_apply))
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, out
+
+    # admission waves by footprint (first fit, input order)
+    budget = args.hbm_budget_gb * 1e9
+    waves, cur, used = [], [], 0.0
+    for i, sz in enumerate(sizes):
+        if cur and used + sz > budget:
+            waves.append(cur)
+            cur, used = [], 0.0
+        cur.append(i)
+        used += sz
+    if cur:
+        waves.append(cur)
+
+    def batch_pass():
+        out = [None] * len(wls)
+        t0 = time.perf_counter()
+        for wave in waves:
+            ths = [thetas0[i].clone() for i in wave]
+            bt = Batch([systems[i] for i in wave], ths, [wls[i].V for i in wave],
+                       [wls[i].H for i in wave], ws_flags=fl)
+            res, status, _ = bt.step(**opts)
+            for j, i in enumerate(wave):
+                out[i] = (status[j], res[j].lambda_min, res[j].E_after, res[j].n_apply)
+            bt.close()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, out
+
+    solo_pass()                          # warm-up (module load, allocator)
+    batch_pass()
+    t_solo, r_solo = solo_pass()
+    log(f"sequential: {t_solo * 1e3:.1f} ms")
+    t_batch, r_batch = batch_pass()
+    log(f"batched: {t_batch * 1e3:.1f} ms in {len(waves)} wave(s)")
+    dlam = max(abs(a[1] - b_[1]) / max(1.0, abs(a[1])) for a, b_ in zip(r_solo, r_batch))
+    dE = max(abs(a[2] - b_[2]) for a, b_ in zip(r_solo, r_batch))
+    out = {
+        "metric": METRIC,
+        "value": len(wls) / t_batch,
+        "unit": "solves/s",
+        "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": t_batch * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": (f"c4: {len(wls)} independent solves, n ~ U{{8..16}} half filled, "
+                                f"full space capped at 2^18 determinants, H ~ U{{16..128}}, "
+                                f"seeds 0..{len(wls) - 1}, one IRL step each (m=20, k=1, tol=1e-12), FP64"),
+                   "waves": len(waves), "workspace_GB": sum(sizes) / 1e9},
+        "sequential_solves_per_s": len(wls) / t_solo,
+        "speedup_vs_sequential": t_solo / t_batch,
+        "max_rel_dlambda_batched_vs_sequential": dlam,
+        "max_abs_dE_after_batched_vs_sequential": dE,
+        "applies": [r[3] for r in r_batch],
+        "converged": sum(1 for r in r_batch if r[0] in (0, 2)),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c3s"])
+    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c3s", "c4"])
+    ap.add_argument("--solves", type=int, default=64, help="c4: number of independent solves")
+    ap.add_argument("--hbm-budget-gb", type=float, default=240.0,
+                    help="c4: device memory admitted per wave of batched solves")
     ap.add_argument("--precision", default=None, choices=["fp64", "fp32"],
                     help="operator precision (default: the workload's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -155,6 +252,9 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": nbytes}), flush=True)
+        return
+    if args.config == "c4":
+        run_batch_bench(args)
         return
     wl = synth.WORKLOADS[args.config]
     h, g = wl.integrals()
@@ -273,7 +373,7 @@ def main():
                                 f"D~ {ns}x{ncols} {prec_name.upper()}, IRL m={wl.m} k_keep={wl.k} "
                                 f"tol=1e-12"),
                    "n_dets": ns, "P": wl.P, "m": wl.m, "k_keep": wl.k,
-                   "ham_kernel": ["hashed-pull", "rank-pull", "string-product"][sysm.info.ham_kernel]},
+                   "ham_kernel": HAM_KERNELS[sysm.info.ham_kernel]},
         "roofline": roof,
         "cpu_baseline": cpu,
         "operator": operator,

@@ -89,7 +89,8 @@ enum irl_step_flags {
 /* K4 variant selection (irl_system_desc.flags) */
 enum irl_system_flags {
     IRL_SYS_FORCE_HASH = 1u,     /* use the general hashed per-determinant Hamiltonian
-                                    apply even for a full space (testing) */
+                                    apply for every set (full spaces and selected sets
+                                    that would otherwise take the beta-blocked kernel) */
     IRL_SYS_FORCE_PULL = 2u      /* full space: per-determinant kernel with string-rank
                                     lookup instead of the string-product kernel */
 };
@@ -117,7 +118,8 @@ typedef struct {
     int64_t max_connections;  /* singles + doubles per determinant (before projection) */
     size_t device_bytes;    /* device memory owned by the handle */
     int32_t ham_kernel;     /* 0: hashed per-determinant, 1: rank per-determinant,
-                               2: string-product (full space) */
+                               2: string-product (full space), 3: beta-blocked
+                               per-determinant (selected sets with n_orb <= 24) */
 } irl_system_info;
 
 typedef struct {

@@ -70,7 +70,7 @@ void free_system(irl_system *s)
     void *ptrs[] = {s->d.keys, s->d.h, s->d.g, s->d.diag, s->d.hkeys, s->d.hrows, s->d.rankA,
                     s->d.rankB, s->d.strA, s->d.strB, s->d.sglA, s->d.sglB, s->d.fA, s->d.fB,
                     s->d.dblA_rank, s->d.dblA_val, s->d.dblB_rank, s->d.dblB_val, s->d.jA,
-                    s->d.jB, s->d.sglA_ia, s->d.sglB_ia, s->d.hfilter};
+                    s->d.jB, s->d.sglA_ia, s->d.sglB_ia, s->d.hfilter, s->d.bidx, s->d.bstart};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (s->host_scal) (void)hipHostFree(s->host_scal);
@@ -446,7 +446,24 @@ int irl_system_create(const irl_system_desc *d, void *stream, irl_system **out)
     s->nA = full ? cA : 0;
     s->nB = full ? cB : 0;
     const bool want_hash = !full || (d->flags & IRL_SYS_FORCE_HASH);
-    s->ham_kernel = want_hash ? 0 : 1;
+    // selected sets: rows sharing a beta string form one contiguous block of the
+    // sorted keys (beta-major order); a direct beta -> block table plus a binary
+    // search over the block's alpha strings replaces the hash on the apply path
+    const bool want_blocks = !full && n <= 24 && !(d->flags & IRL_SYS_FORCE_HASH);
+    s->ham_kernel = want_blocks ? 3 : (want_hash ? 0 : 1);
+    std::vector<int32_t> bidx, bstart;
+    if (want_blocks) {
+        bidx.assign((size_t)1 << n, -1);
+        for (size_t i = 0; i < keys.size(); ++i) {
+            uint32_t be = (uint32_t)(keys[i] >> 32);
+            if (i == 0 || be != (uint32_t)(keys[i - 1] >> 32)) {
+                bidx[be] = (int32_t)bstart.size();
+                bstart.push_back((int32_t)i);
+            }
+        }
+        s->d.nblocks = (int64_t)bstart.size();
+        bstart.push_back((int32_t)keys.size());
+    }
 
     int rc = IRL_OK;
 #define AL(ptr, cnt) \
@@ -473,6 +490,10 @@ int irl_system_create(const irl_system_desc *d, void *stream, irl_system **out)
         s->d.hfbits = fb;
         AL(s->d.hfilter, ((size_t)1 << fb) / 32);
     }
+    if (want_blocks) {
+        AL(s->d.bidx, bidx.size());
+        AL(s->d.bstart, bstart.size());
+    }
 #undef AL
     auto fail_dev = [&](hipError_t e, const char *what) {
         std::string m_ = std::string(what) + ": " + hipGetErrorString(e);
@@ -488,6 +509,12 @@ int irl_system_create(const irl_system_desc *d, void *stream, irl_system **out)
     } else {
         if ((e = hipMemcpyAsync(s->d.keys, keys.data(), keys.size() * 8, hipMemcpyHostToDevice, st)) != hipSuccess)
             return fail_dev(e, "copy keys");
+    }
+    if (want_blocks) {
+        if ((e = hipMemcpyAsync(s->d.bidx, bidx.data(), bidx.size() * 4, hipMemcpyHostToDevice, st)) != hipSuccess)
+            return fail_dev(e, "copy block index");
+        if ((e = hipMemcpyAsync(s->d.bstart, bstart.data(), bstart.size() * 4, hipMemcpyHostToDevice, st)) != hipSuccess)
+            return fail_dev(e, "copy block starts");
     }
     if (want_hash)
         if ((e = launch_hash_build(s->d.keys, s->ns, s->d.hkeys, s->d.hrows, s->d.hcap, s->d.hfilter,

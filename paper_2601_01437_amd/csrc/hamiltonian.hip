@@ -62,11 +62,33 @@ __device__ __forceinline__ double single_value(const double *h, const double *g,
     return v;
 }
 
-template <bool FULL>
+// key -> row lookup modes of the per-determinant kernels
+constexpr int kLkRanks = 0;    // full space: rank(beta) * nA + rank(alpha)
+constexpr int kLkHash = 1;     // any set: membership bitmap, then open-addressing hash
+constexpr int kLkBlocks = 2;   // selected set: beta -> contiguous row block, binary search on alpha
+
+// row of alpha string `al` inside the rows [lo, hi) that share one beta string
+__device__ __forceinline__ int64_t search_block(const uint64_t *keys, int64_t lo, int64_t hi,
+                                                uint32_t al)
+{
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        const uint32_t a = (uint32_t)keys[mid];
+        if (a == al) return mid;
+        if (a < al) lo = mid + 1; else hi = mid;
+    }
+    return -1;
+}
+
+template <int LK>
 __device__ __forceinline__ int64_t find_row(const HamArgs &A, uint32_t al, uint32_t be)
 {
-    if (FULL) {
+    if constexpr (LK == kLkRanks) {
         return (int64_t)A.rankB[be] * A.nA + A.rankA[al];
+    } else if constexpr (LK == kLkBlocks) {
+        const int32_t b = A.bidx[be];
+        if (b < 0) return -1;
+        return search_block(A.keys, A.bstart[b], A.bstart[b + 1], al);
     } else {
         uint64_t key = (uint64_t)al | ((uint64_t)be << 32);
         const uint64_t hm = mix64h(key);
@@ -93,7 +115,25 @@ struct WaveLists {
     uint32_t sB[kMaxSingles];
     uint32_t sBstr[kMaxSingles];
     uint16_t poA[kMaxPairs], pvA[kMaxPairs], poB[kMaxPairs], pvB[kMaxPairs];  // i | j << 8
+    int32_t sBlo[kMaxSingles], sBhi[kMaxSingles];   // blocked lookup: rows of each beta single's target
+    int32_t own_lo, own_hi;                         // blocked lookup: rows sharing this row's beta
 };
+
+// blocked lookup: row ranges of the beta-single targets and of the row's own beta
+__device__ void build_block_ranges(const HamArgs &A, WaveLists &L, uint32_t be, int lane)
+{
+    const int cnt = A.nb * (A.n - A.nb);
+    for (int f = lane; f < cnt; f += kWave) {
+        const int32_t b = A.bidx[L.sBstr[f]];
+        L.sBlo[f] = b < 0 ? 0 : A.bstart[b];
+        L.sBhi[f] = b < 0 ? 0 : A.bstart[b + 1];
+    }
+    if (lane == 0) {
+        const int32_t b = A.bidx[be];
+        L.own_lo = A.bstart[b];
+        L.own_hi = A.bstart[b + 1];
+    }
+}
 
 // k-th set bit (0-based) of x
 __device__ __forceinline__ int nth_bit(uint32_t x, int k)
@@ -141,7 +181,7 @@ __device__ __forceinline__ double wave_sum(double v)
 
 // Evaluate the candidates of one determinant on one lane (stride 64).  OP is
 // called with (target row, sign, kind, value) for every target inside the set.
-template <bool FULL, typename OP>
+template <int LK, typename OP>
 __device__ __forceinline__ void visit_row(const HamArgs &A, const WaveLists &L, uint32_t al,
                                           uint32_t be, int lane, int stride, OP op)
 {
@@ -155,7 +195,12 @@ __device__ __forceinline__ void visit_row(const HamArgs &A, const WaveLists &L, 
         for (int e = lane; e < cnt; e += stride) {
             uint32_t p = s[e];
             int i = p & 31, a = (p >> 5) & 31, sg = (p >> 10) & 1 ? -1 : 1;
-            int64_t r = spin ? find_row<FULL>(A, al, ss[e]) : find_row<FULL>(A, ss[e], be);
+            int64_t r;
+            if constexpr (LK == kLkBlocks)
+                r = spin ? search_block(A.keys, L.sBlo[e], L.sBhi[e], al)
+                         : search_block(A.keys, L.own_lo, L.own_hi, ss[e]);
+            else
+                r = spin ? find_row<LK>(A, al, ss[e]) : find_row<LK>(A, ss[e], be);
             if (r >= 0) op(r, sg, spin ? 2 : 1, sg * single_value(A.h, A.g, n, same, other, i, a));
         }
     }
@@ -175,7 +220,11 @@ __device__ __forceinline__ void visit_row(const HamArgs &A, const WaveLists &L, 
             uint32_t b1 = (bits & ~(1u << i)) | (1u << a);
             int s2 = move_sign(b1, j, b);
             uint32_t b2 = (b1 & ~(1u << j)) | (1u << b);
-            int64_t r = spin ? find_row<FULL>(A, al, b2) : find_row<FULL>(A, b2, be);
+            int64_t r;
+            if constexpr (LK == kLkBlocks)
+                r = spin ? find_row<LK>(A, al, b2) : search_block(A.keys, L.own_lo, L.own_hi, b2);
+            else
+                r = spin ? find_row<LK>(A, al, b2) : find_row<LK>(A, b2, be);
             if (r >= 0) {
                 double v = gint(A.g, n, i, a, j, b) - gint(A.g, n, i, b, j, a);
                 op(r, s1 * s2, spin ? 4 : 3, (s1 * s2) * v);
@@ -195,7 +244,11 @@ __device__ __forceinline__ void visit_row(const HamArgs &A, const WaveLists &L, 
                 uint32_t pa = L.sA[xa], pb = L.sB[xb];
                 int i = pa & 31, a = (pa >> 5) & 31, j = pb & 31, b = (pb >> 5) & 31;
                 int sg = (((pa >> 10) ^ (pb >> 10)) & 1) ? -1 : 1;
-                int64_t r = find_row<FULL>(A, L.sAstr[xa], L.sBstr[xb]);
+                int64_t r;
+                if constexpr (LK == kLkBlocks)
+                    r = L.sBhi[xb] > L.sBlo[xb] ? search_block(A.keys, L.sBlo[xb], L.sBhi[xb], L.sAstr[xa]) : -1;
+                else
+                    r = find_row<LK>(A, L.sAstr[xa], L.sBstr[xb]);
                 if (r >= 0) op(r, sg, 5, sg * gint(A.g, n, i, a, j, b));
                 xb += step_b;
                 xa += step_a;
@@ -206,7 +259,7 @@ __device__ __forceinline__ void visit_row(const HamArgs &A, const WaveLists &L, 
 }
 
 // one determinant row on one wavefront: u[row] = H_rr w[row] + sum of the row's connections
-template <bool FULL>
+template <int LK>
 __device__ __forceinline__ void pull_row(const HamArgs &A, WaveLists &L, int64_t row, int lane,
                                          const double *__restrict__ w, double *__restrict__ u)
 {
@@ -217,8 +270,14 @@ __device__ __forceinline__ void pull_row(const HamArgs &A, WaveLists &L, int64_t
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if constexpr (LK == kLkBlocks) {
+        build_block_ranges(A, L, be, lane);
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
     double acc = 0.0;
-    visit_row<FULL>(A, L, al, be, lane, kWave,
+    visit_row<LK>(A, L, al, be, lane, kWave,
                     [&](int64_t r, int, int, double v) { acc += v * w[r]; });
     acc = wave_sum(acc);
     if (lane == 0) u[row] = A.diag[row] * w[row] + acc;
@@ -227,7 +286,7 @@ __device__ __forceinline__ void pull_row(const HamArgs &A, WaveLists &L, int64_t
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <bool FULL>
+template <int LK>
 __global__ __launch_bounds__(256) void k_ham_pull(HamArgs A, const double *__restrict__ w,
                                                   double *__restrict__ u)
 {
@@ -235,7 +294,12 @@ __global__ __launch_bounds__(256) void k_ham_pull(HamArgs A, const double *__res
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t nwaves = (int64_t)gridDim.x * 4;
     for (int64_t row = (int64_t)blockIdx.x * 4 + wv; row < A.ns; row += nwaves)
-        pull_row<FULL>(A, lists[wv], row, lane, w, u);
+        pull_row<LK>(A, lists[wv], row, lane, w, u);
+}
+
+__device__ __forceinline__ int lookup_mode(const HamArgs &A)
+{
+    return A.bidx ? kLkBlocks : (A.hkeys ? kLkHash : kLkRanks);
 }
 
 // grouped: one work item = rows [r0, r1) of member m; which = 0: w -> u, 1: psi -> H psi
@@ -250,12 +314,14 @@ __global__ __launch_bounds__(256) void k_ham_pull_grouped(const Member *__restri
     const HamArgs A = mb.ham;
     const double *w = which ? mb.psi : mb.w;
     double *u = which ? mb.hpsi : mb.u;
-    const bool ranks = A.hkeys == nullptr;
+    const int lk = lookup_mode(A);
     for (int64_t row = it.r0 + wv; row < it.r1; row += 4) {
-        if (ranks)
-            pull_row<true>(A, lists[wv], row, lane, w, u);
+        if (lk == kLkRanks)
+            pull_row<kLkRanks>(A, lists[wv], row, lane, w, u);
+        else if (lk == kLkBlocks)
+            pull_row<kLkBlocks>(A, lists[wv], row, lane, w, u);
         else
-            pull_row<false>(A, lists[wv], row, lane, w, u);
+            pull_row<kLkHash>(A, lists[wv], row, lane, w, u);
     }
 }
 
@@ -285,6 +351,8 @@ HamView ham_view(const irl_system *s)
     A.hmask = s->d.hcap ? s->d.hcap - 1 : 0;
     A.hfilter = s->d.hfilter;
     A.hfbits = s->d.hfbits;
+    A.bidx = s->ham_kernel == 3 ? s->d.bidx : nullptr;
+    A.bstart = s->ham_kernel == 3 ? s->d.bstart : nullptr;
     A.rankA = s->d.rankA;
     A.rankB = s->d.rankB;
     return A;
@@ -298,16 +366,18 @@ hipError_t launch_ham_apply(const irl_system *s, const double *w, double *u, hip
     HamArgs A = ham_view(s);
     int64_t blocks = (s->ns + 3) / 4;
     if (blocks > 65536) blocks = 65536;
-    if (s->d.hkeys != nullptr)
-        k_ham_pull<false><<<(unsigned)blocks, 256, 0, st>>>(A, w, u);
+    if (s->ham_kernel == 3)
+        k_ham_pull<kLkBlocks><<<(unsigned)blocks, 256, 0, st>>>(A, w, u);
+    else if (s->d.hkeys != nullptr)
+        k_ham_pull<kLkHash><<<(unsigned)blocks, 256, 0, st>>>(A, w, u);
     else
-        k_ham_pull<true><<<(unsigned)blocks, 256, 0, st>>>(A, w, u);
+        k_ham_pull<kLkRanks><<<(unsigned)blocks, 256, 0, st>>>(A, w, u);
     return hipGetLastError();
 }
 
 // Connections of one row (debug surface): same candidate enumeration as the
 // apply kernel, one lane, written in enumeration order.
-template <bool FULL>
+template <int LK>
 __global__ void k_ham_row_list(HamArgs A, int64_t row, int32_t *tgt, int8_t *sign, uint8_t *kind,
                                double *val, int32_t *count, int cap)
 {
@@ -318,9 +388,13 @@ __global__ void k_ham_row_list(HamArgs A, int64_t row, int32_t *tgt, int8_t *sig
     build_lists(al, A.n, A.na, L.sA, L.sAstr, L.poA, L.pvA, lane);
     build_lists(be, A.n, A.nb, L.sB, L.sBstr, L.poB, L.pvB, lane);
     __syncthreads();
+    if constexpr (LK == kLkBlocks) {
+        build_block_ranges(A, L, be, lane);
+        __syncthreads();
+    }
     if (lane != 0) return;
     int c = 0;
-    visit_row<FULL>(A, L, al, be, 0, 1, [&](int64_t r, int sg, int k, double v) {
+    visit_row<LK>(A, L, al, be, 0, 1, [&](int64_t r, int sg, int k, double v) {
         if (c < cap) {
             tgt[c] = (int32_t)r;
             sign[c] = (int8_t)sg;
@@ -337,10 +411,12 @@ hipError_t launch_ham_row_list(const irl_system *s, int64_t row, int32_t *tgt, i
                                hipStream_t st)
 {
     HamArgs A = ham_view(s);
-    if (s->d.hkeys != nullptr)
-        k_ham_row_list<false><<<1, 64, 0, st>>>(A, row, tgt, sign, kind, val, count, cap);
+    if (s->ham_kernel == 3)
+        k_ham_row_list<kLkBlocks><<<1, 64, 0, st>>>(A, row, tgt, sign, kind, val, count, cap);
+    else if (s->d.hkeys != nullptr)
+        k_ham_row_list<kLkHash><<<1, 64, 0, st>>>(A, row, tgt, sign, kind, val, count, cap);
     else
-        k_ham_row_list<true><<<1, 64, 0, st>>>(A, row, tgt, sign, kind, val, count, cap);
+        k_ham_row_list<kLkRanks><<<1, 64, 0, st>>>(A, row, tgt, sign, kind, val, count, cap);
     return hipGetLastError();
 }
 

@@ -72,6 +72,10 @@ struct SystemDev {
     uint64_t hcap = 0;
     uint32_t *hfilter = nullptr;  // membership bitmap, 2^hfbits bits, indexed by the top hash bits
     int hfbits = 0;
+    // blocked lookup (selected sets, n <= 24): rows sharing a beta string are contiguous
+    int32_t *bidx = nullptr;      // 2^n: beta string -> block index, -1 if absent
+    int32_t *bstart = nullptr;    // nblocks + 1 row offsets
+    int64_t nblocks = 0;
     // string tables (full space)
     int32_t *rankA = nullptr;   // 2^n, -1 for strings not of popcount n_alpha
     int32_t *rankB = nullptr;
@@ -104,6 +108,8 @@ struct HamView {
     const uint32_t *hfilter;
     int hfbits;
     const int32_t *rankA, *rankB;
+    const int32_t *bidx;     // blocked lookup: beta string -> block, -1 if absent (or nullptr)
+    const int32_t *bstart;   // blocked lookup: first row of each block, plus the end
 };
 
 // One member of a grouped (batched) launch: its system view, workspace
@@ -142,7 +148,7 @@ struct irl_system {
     int64_t ns = 0;
     int64_t nA = 0, nB = 0;   // string counts (full space) or distinct counts
     bool full = false;
-    int ham_kernel = 0;       // 0 hashed pull, 1 rank pull, 2 string product
+    int ham_kernel = 0;       // 0 hashed pull, 1 rank pull, 2 string product, 3 blocked pull
     int device = 0;
     size_t dev_bytes = 0;
     irl::SystemDev d;

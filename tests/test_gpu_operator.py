@@ -34,15 +34,46 @@ def test_hamiltonian_apply_c1(c1_problem, flags):
     assert rel_err(u, c1_problem["H"] @ w) <= 1e-12
 
 
+@pytest.mark.parametrize("flags", [0, 1])
 @pytest.mark.parametrize("n,na,nb,count,seed", [(10, 5, 5, 3000, 2), (20, 10, 10, 1 << 14, 0),
-                                                 (9, 5, 4, 777, 5)])
-def test_hamiltonian_apply_selected(n, na, nb, count, seed):
-    announce(f"H apply selected n={n} count={count}")
+                                                 (9, 5, 4, 777, 5), (24, 4, 3, 5000, 1)])
+def test_hamiltonian_apply_selected(n, na, nb, count, seed, flags):
+    """Selected sets: beta-blocked lookup (default) and hashed lookup (flag 1)."""
+    announce(f"H apply selected n={n} count={count} flags={flags}")
     keys = synth.cisd_like_selected_set(n, na, nb, count, seed=seed)
-    s, h, g = make_system(n, na, nb, seed=seed, dets=keys)
+    s, h, g = make_system(n, na, nb, seed=seed, dets=keys, flags=flags)
+    assert s.info.ham_kernel == (3 if flags == 0 else 0)
     w = np.random.default_rng(4).normal(size=keys.size)
     u = host(s.apply_hamiltonian(dev(w)))
     assert rel_err(u, capply.apply(n, h, g, keys, w)) <= 1e-12
+
+
+@pytest.mark.parametrize("shape", ["one_beta", "distinct_betas", "single_det"])
+def test_hamiltonian_apply_selected_block_shapes(shape):
+    """Degenerate block structures of the beta-blocked lookup: every row in one
+    beta block, every row in its own block, and a one-determinant set."""
+    announce(f"H apply selected block shape {shape}")
+    n, na, nb = 10, 4, 3
+    full = space.full_space(n, na, nb)
+    al, be = full & 0xFFFFFFFF, full >> 32
+    if shape == "one_beta":
+        keys = full[be == be[len(be) // 2]]
+    elif shape == "distinct_betas":
+        _, first = np.unique(be, return_index=True)
+        keys = full[first]
+    else:
+        keys = full[[123]]
+    s, h, g = make_system(n, na, nb, seed=7, dets=keys)
+    assert s.info.ham_kernel == 3
+    w = np.random.default_rng(8).normal(size=keys.size)
+    u = host(s.apply_hamiltonian(dev(w)))
+    assert rel_err(u, capply.apply(n, h, g, np.sort(keys), w)) <= 1e-12
+    for r in sorted({0, keys.size // 2, keys.size - 1}):
+        rows, signs, kinds, vals = s.excitations(r)
+        orow, osig, okind, oval = hamiltonian.excitation_list(int(np.sort(keys)[r]), np.sort(keys),
+                                                              n, h, g)
+        assert np.array_equal(rows, orow) and np.array_equal(signs, osig)
+        assert np.array_equal(kinds, okind)
 
 
 @pytest.mark.parametrize("flags", [0, 2])

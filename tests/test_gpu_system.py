@@ -89,10 +89,11 @@ def test_excitation_lists_bit_exact_c1(c1_problem, flags):
         assert np.max(np.abs(vals - oval)) <= 1e-12, r
 
 
-def test_excitation_lists_selected_set():
+@pytest.mark.parametrize("flags", [0, 1])
+def test_excitation_lists_selected_set(flags):
     n = 10
     keys = synth.cisd_like_selected_set(n, 5, 5, 3000, seed=0)
-    s, h, g = make_system(n, 5, 5, seed=2, dets=keys)
+    s, h, g = make_system(n, 5, 5, seed=2, dets=keys, flags=flags)
     for r in (0, 1, 77, 1500, 2999):
         rows, signs, kinds, vals = s.excitations(r)
         orow, osig, okind, oval = hamiltonian.excitation_list(int(keys[r]), keys, n, h, g)
