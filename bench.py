@@ -31,7 +31,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
 METRIC = "time per IRL step & operator HBM GB/s vs roofline; solves/s, p99 step latency"
-HAM_KERNELS = ["hashed-pull", "rank-pull", "string-product", "beta-blocked-pull"]
+HAM_KERNELS = ["hashed-pull", "rank-pull", "string-product", "beta-blocked-pull", "stored-rows"]
 
 
 def log(msg):
@@ -144,6 +144,19 @@ def run_batch_bench(args):
         s.workspace(w.P + 1, fl)
     torch.cuda.synchronize()
     log(f"workspaces: {sum(sizes) / 1e9:.1f} GB")
+    # selected (capped) sets: store H's rows while they fit beside the workspaces
+    n_stored, stored_bytes, t = 0, 0, time.perf_counter()
+    if not args.matrix_free:
+        for s in systems:
+            if s.info.full_space:
+                continue
+            free = torch.cuda.mem_get_info()[0]
+            ok, need = s.store_hamiltonian(max(0, free - (8 << 30)))
+            n_stored += ok
+            stored_bytes += need if ok else 0
+    log(f"stored rows for {n_stored} selected sets: {stored_bytes / 1e9:.1f} GB, "
+        f"{(time.perf_counter() - t) * 1e3:.0f} ms")
+    kernels = [s.info.ham_kernel for s in systems]
     opts = dict(m=20, k_keep=1, tol=1e-12)
 
     def solo_pass():
@@ -182,12 +195,31 @@ def run_batch_bench(args):
         torch.cuda.synchronize()
         return time.perf_counter() - t0, out
 
+    def kernel_totals(handles):
+        tot = {k: [0.0, 0] for k in B.STAT_KINDS}
+        for hnd in handles:
+            for k, (ms, cnt) in B.irl_stats_get(hnd).items():
+                tot[k][0] += ms
+                tot[k][1] += cnt
+            B.irl_stats_enable(hnd, False)
+        return {k: {"ms_total": v[0], "launches": v[1]} for k, v in tot.items() if v[1]}
+
     solo_pass()                          # warm-up (module load, allocator)
     batch_pass()
     t_solo, r_solo = solo_pass()
     log(f"sequential: {t_solo * 1e3:.1f} ms")
     t_batch, r_batch = batch_pass()
     log(f"batched: {t_batch * 1e3:.1f} ms in {len(waves)} wave(s)")
+    # kernel-time breakdown of each pass (separate, untimed runs: events add host work)
+    for s in systems:
+        B.irl_stats_enable(s.handle, True)
+    solo_pass()
+    k_solo = kernel_totals([s.handle for s in systems])
+    B.irl_stats_enable(systems[0].handle, True)
+    batch_pass()
+    k_batch = kernel_totals([systems[0].handle])
+    log("kernel ms sequential: " + ", ".join(f"{k} {v['ms_total']:.0f}" for k, v in k_solo.items()))
+    log("kernel ms batched:    " + ", ".join(f"{k} {v['ms_total']:.0f}" for k, v in k_batch.items()))
     dlam = max(abs(a[1] - b_[1]) / max(1.0, abs(a[1])) for a, b_ in zip(r_solo, r_batch))
     dE = max(abs(a[2] - b_[2]) for a, b_ in zip(r_solo, r_batch))
     out = {
@@ -201,11 +233,15 @@ def run_batch_bench(args):
         "config": {"workload": (f"c4: {len(wls)} independent solves, n ~ U{{8..16}} half filled, "
                                 f"full space capped at 2^18 determinants, H ~ U{{16..128}}, "
                                 f"seeds 0..{len(wls) - 1}, one IRL step each (m=20, k=1, tol=1e-12), FP64"),
-                   "waves": len(waves), "workspace_GB": sum(sizes) / 1e9},
+                   "waves": len(waves), "workspace_GB": sum(sizes) / 1e9,
+                   "ham_kernels": {HAM_KERNELS[k]: kernels.count(k) for k in sorted(set(kernels))},
+                   "stored_rows_GB": stored_bytes / 1e9},
         "sequential_solves_per_s": len(wls) / t_solo,
         "speedup_vs_sequential": t_solo / t_batch,
         "max_rel_dlambda_batched_vs_sequential": dlam,
         "max_abs_dE_after_batched_vs_sequential": dE,
+        "kernels_sequential": k_solo,
+        "kernels_batched": k_batch,
         "applies": [r[3] for r in r_batch],
         "converged": sum(1 for r in r_batch if r[0] in (0, 2)),
     }
@@ -225,6 +261,9 @@ def main():
                     help="operator precision (default: the workload's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--force-hash", action="store_true", help="general hashed Hamiltonian kernel")
+    ap.add_argument("--matrix-free", action="store_true",
+                    help="selected sets: enumerate excitations on every apply instead of "
+                         "streaming stored rows")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -275,6 +314,13 @@ def main():
     sD = 8 if precision == B.IRL_FP64 else 4
     sysm.workspace(wl.P + 1, ws_flags)
     log(f"workspace {sysm.ws.numel() / 2**30:.2f} GiB")
+    store = None
+    if not sysm.info.full_space and not args.matrix_free:
+        free = torch.cuda.mem_get_info()[0]
+        t = time.perf_counter()
+        stored, need = sysm.store_hamiltonian(max(0, free - (4 << 30)))
+        store = {"stored": stored, "bytes": need, "ms": (time.perf_counter() - t) * 1e3}
+        log(f"stored rows: {stored}, {need / 2**30:.2f} GiB, {store['ms']:.1f} ms")
 
     def one_step():
         rc, r, _, _ = sysm.step(theta, wl.V, wl.H, m=wl.m, k_keep=wl.k, tol=1e-12,
@@ -380,6 +426,7 @@ def main():
         "kernels": kern,
         "applies_per_step": applies / args.steps,
         "setup_ms": setup_ms,
+        "stored_rows": store,
         "trajectory": steps,
         "E_final": Ef,
     }

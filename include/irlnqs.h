@@ -119,7 +119,8 @@ typedef struct {
     size_t device_bytes;    /* device memory owned by the handle */
     int32_t ham_kernel;     /* 0: hashed per-determinant, 1: rank per-determinant,
                                2: string-product (full space), 3: beta-blocked
-                               per-determinant (selected sets with n_orb <= 24) */
+                               per-determinant (selected sets with n_orb <= 24),
+                               4: stored rows (irl_system_store_hamiltonian) */
 } irl_system_info;
 
 typedef struct {
@@ -180,6 +181,22 @@ void irl_system_destroy(irl_system *sys);
 
 /* Sizes of a system (host call, no device work). */
 int irl_system_info_get(const irl_system *sys, irl_system_info *out);
+
+/* Store the off-diagonal elements of H inside the set (Methods, "Wave Function
+ * Ansatz": the second-quantised electronic Hamiltonian, whose elements between
+ * determinants follow from the Slater-Condon rules) as
+ * compressed rows: row offsets int64[n_dets + 1], targets int32[nnz], values
+ * FP64[nnz], device memory owned by the system.  Later applies stream these
+ * rows instead of enumerating excitations (ham_kernel becomes 4); results agree
+ * with the enumerating kernels to rounding (summation order differs).  Two
+ * enumeration passes count and fill the rows; the call synchronises stream.
+ * max_bytes: device bytes the caller allows for the stored rows.
+ * bytes_needed (may be NULL): receives (n_dets + 1) * 8 + nnz * 12.
+ * Errors: IRL_ENOMEM when the rows need more than max_bytes or allocation
+ * fails (the system is unchanged and stays usable), IRL_EDEVICE, IRL_EINVAL.
+ * Calling it again after success does nothing. */
+int irl_system_store_hamiltonian(irl_system *sys, size_t max_bytes, size_t *bytes_needed,
+                                 void *stream);
 
 /* Message for the last error on sys ("" if none); for a NULL sys, the last
  * error of a failed irl_system_create on this thread. */
@@ -282,14 +299,18 @@ void irl_solver_opts_default(irl_solver_opts *o);
  * covers all members that are still active (grouped kernels over per-member
  * work lists), the members advance through the Lanczos steps in lockstep, and
  * the host reads back all members' scalars with one copy per check point.
- * Each member follows exactly the arithmetic of irl_step on a system created
- * with IRL_SYS_FORCE_PULL (same row blocks, reduction order, seeds and
- * tolerances), so its result equals that solo result bit for bit.  Members use
- * the per-determinant Hamiltonian kernels (string-rank or hashed lookup).
+ * Each member follows exactly the arithmetic of irl_step on its system (same
+ * row blocks, reduction order, seeds and tolerances), so its result equals
+ * that solo result bit for bit.  The Hamiltonian apply of each member is the
+ * kernel its system uses when the batch is created: string-product members
+ * get their own launch, stored-row and per-determinant members share grouped
+ * launches (rows stored after batch create are not used by the batch).
  * systems[i], nqs[i] and ws[i] (sized by irl_workspace_query for P_i + 1
  * columns and ws_flags) are borrowed and must stay alive while the batch
  * exists; a system must not be used by two members.  Requires
- * (P_i + 1) <= 8192.  Errors: IRL_EINVAL, IRL_ENOMEM, IRL_EDEVICE. */
+ * (P_i + 1) <= 8192, and at most 2^26 determinant rows over the members that
+ * share one Hamiltonian kernel kind (checked at each step: IRL_EINVAL).
+ * Errors: IRL_EINVAL, IRL_ENOMEM, IRL_EDEVICE. */
 typedef struct irl_batch irl_batch;
 int irl_batch_create(int32_t count, irl_system *const *systems, const irl_nqs_desc *nqs,
                      void *const *ws, const size_t *ws_bytes, uint32_t ws_flags,
@@ -320,7 +341,8 @@ enum irl_stat_kind {
 
 /* on != 0: from now on every kernel launch of this handle is bracketed by a
  * pair of HIP events on its stream; on == 0 stops and clears.  Adds a few
- * microseconds of host work per launch. */
+ * microseconds of host work per launch.  A batch step records its launches
+ * (which cover all members) in the stats of the first member's system. */
 int irl_stats_enable(irl_system *sys, int32_t on);
 
 /* Synchronise `stream` and return, per irl_stat_kind, the summed kernel time

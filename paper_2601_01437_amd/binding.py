@@ -86,6 +86,7 @@ _sigs = {
     "irl_system_create": (c_int32, [POINTER(irl_system_desc), c_void_p, POINTER(_SYS)]),
     "irl_system_destroy": (None, [_SYS]),
     "irl_system_info_get": (c_int32, [_SYS, POINTER(irl_system_info)]),
+    "irl_system_store_hamiltonian": (c_int32, [_SYS, c_size_t, POINTER(c_size_t), c_void_p]),
     "irl_last_error": (c_char_p, [_SYS]),
     "irl_workspace_query": (c_int32, [_SYS, c_int64, c_uint32, POINTER(c_size_t)]),
     "irl_nqs_evaluate": (c_int32, [_SYS, POINTER(irl_nqs_desc), c_void_p, c_size_t, c_uint32,
@@ -166,6 +167,15 @@ def irl_system_info_get(sys):
     info = irl_system_info()
     _check(_lib.irl_system_info_get(sys, ctypes.byref(info)), sys)
     return info
+
+
+def irl_system_store_hamiltonian(sys, max_bytes, stream=None):
+    """Returns (stored: bool, bytes_needed).  Over budget is not an error here:
+    the system stays matrix-free and stored is False."""
+    need = c_size_t()
+    rc = _lib.irl_system_store_hamiltonian(sys, int(max_bytes), ctypes.byref(need), _stream(stream))
+    _check(rc, sys, ok=(IRL_OK, IRL_ENOMEM))
+    return rc == IRL_OK, need.value
 
 
 def irl_last_error(sys=None):

@@ -70,7 +70,8 @@ void free_system(irl_system *s)
     void *ptrs[] = {s->d.keys, s->d.h, s->d.g, s->d.diag, s->d.hkeys, s->d.hrows, s->d.rankA,
                     s->d.rankB, s->d.strA, s->d.strB, s->d.sglA, s->d.sglB, s->d.fA, s->d.fB,
                     s->d.dblA_rank, s->d.dblA_val, s->d.dblB_rank, s->d.dblB_val, s->d.jA,
-                    s->d.jB, s->d.sglA_ia, s->d.sglB_ia, s->d.hfilter, s->d.bidx, s->d.bstart};
+                    s->d.jB, s->d.sglA_ia, s->d.sglB_ia, s->d.hfilter, s->d.bidx, s->d.bstart,
+                    s->d.hptr, s->d.hcol, s->d.hval};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (s->host_scal) (void)hipHostFree(s->host_scal);
@@ -451,6 +452,7 @@ int irl_system_create(const irl_system_desc *d, void *stream, irl_system **out)
     // search over the block's alpha strings replaces the hash on the apply path
     const bool want_blocks = !full && n <= 24 && !(d->flags & IRL_SYS_FORCE_HASH);
     s->ham_kernel = want_blocks ? 3 : (want_hash ? 0 : 1);
+    s->lookup = want_blocks ? kLkBlocks : (want_hash ? kLkHash : kLkRanks);
     std::vector<int32_t> bidx, bstart;
     if (want_blocks) {
         bidx.assign((size_t)1 << n, -1);
@@ -531,6 +533,62 @@ int irl_system_create(const irl_system_desc *d, void *stream, irl_system **out)
 }
 
 void irl_system_destroy(irl_system *sys) { free_system(sys); }
+
+int irl_system_store_hamiltonian(irl_system *s, size_t max_bytes, size_t *bytes_needed, void *stream)
+{
+    if (!s) return set_err(nullptr, IRL_EINVAL, "system is NULL");
+    const int64_t ns = s->ns;
+    if (s->ham_kernel == 4) {
+        if (bytes_needed) *bytes_needed = (size_t)(ns + 1) * 8 + (size_t)s->d.hnnz * 12;
+        return IRL_OK;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    int32_t *dcount = nullptr;
+    CK(s, hipMalloc((void **)&dcount, (size_t)ns * 4));
+    std::vector<int32_t> count((size_t)ns);
+    hipError_t e = launch_ham_count(s, dcount, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(count.data(), dcount, (size_t)ns * 4, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipFree(dcount);
+    if (e != hipSuccess) return set_err(s, IRL_EDEVICE, std::string("row counts: ") + hipGetErrorString(e));
+    std::vector<int64_t> ptr((size_t)ns + 1);
+    ptr[0] = 0;
+    for (int64_t r = 0; r < ns; ++r) ptr[r + 1] = ptr[r] + count[r];
+    const int64_t nnz = ptr[ns];
+    const size_t bytes = (size_t)(ns + 1) * 8 + (size_t)nnz * 12;
+    if (bytes_needed) *bytes_needed = bytes;
+    if (bytes > max_bytes)
+        return set_err(s, IRL_ENOMEM, "stored rows need " + std::to_string(bytes) +
+                                          " bytes, more than max_bytes = " + std::to_string(max_bytes));
+    int rc;
+    const size_t bytes_before = s->dev_bytes;
+    auto release = [&]() {
+        s->dev_bytes = bytes_before;
+        for (void *p : {(void *)s->d.hptr, (void *)s->d.hcol, (void *)s->d.hval})
+            if (p) (void)hipFree(p);
+        s->d.hptr = nullptr;
+        s->d.hcol = nullptr;
+        s->d.hval = nullptr;
+    };
+    if ((rc = dev_alloc(s, &s->d.hptr, (size_t)ns + 1)) != IRL_OK ||
+        (rc = dev_alloc(s, &s->d.hcol, (size_t)nnz)) != IRL_OK ||
+        (rc = dev_alloc(s, &s->d.hval, (size_t)nnz)) != IRL_OK) {
+        release();
+        return rc;
+    }
+    e = hipMemcpyAsync(s->d.hptr, ptr.data(), ptr.size() * 8, hipMemcpyHostToDevice, st);
+    // targets start at row 0, so a slot the fill did not reach still gathers in bounds
+    if (e == hipSuccess) e = hipMemsetAsync(s->d.hcol, 0, (size_t)std::max<int64_t>(nnz, 1) * 4, st);
+    if (e == hipSuccess) e = launch_ham_fill(s, s->d.hptr, s->d.hcol, s->d.hval, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        release();
+        return set_err(s, IRL_EDEVICE, std::string("stored rows: ") + hipGetErrorString(e));
+    }
+    s->d.hnnz = nnz;
+    s->ham_kernel = 4;
+    return IRL_OK;
+}
 
 int irl_system_info_get(const irl_system *s, irl_system_info *o)
 {
@@ -912,11 +970,17 @@ struct irl_batch {
 
 namespace {
 
-enum { LS_ROWS6, LS_ROWS4, LS_ROWS5, LS_T2, LS_RED, LS_E1, LS_VEC, LS_KINDS };
+// work-list kinds: D~ v rows; H rows of enumerating members by lookup (string
+// ranks, hash, beta blocks) and of stored-row members; D~ build rows, D~^T
+// tiles, reductions, energy parts, one item per member
+enum { LS_ROWS6, LS_ROWS4R, LS_ROWS4H, LS_ROWS4B, LS_ROWS4S, LS_ROWS5, LS_T2, LS_RED, LS_E1, LS_VEC,
+       LS_KINDS };
 
 struct ListSet {
     int region = 0;
     int off[LS_KINDS] = {0}, cnt[LS_KINDS] = {0};
+    std::vector<int> product;   // members whose H apply is the solo string-product launch
+    int64_t blocks[LS_KINDS] = {0};   // H-row kinds: blocks of the launch (one per 4-row group)
     size_t lds6 = 0;   // dynamic LDS of the grouped D~ v launch
     const WorkItem *ptr(const irl_batch *b, int kind) const { return b->ditems[region] + off[kind]; }
 };
@@ -938,6 +1002,12 @@ int energy_parts(int64_t ns)
 
 // Build the work lists of `subset` into device region `region` (synchronises
 // the stream first: the pinned staging buffer is reused).
+// lookup a member's enumerating H kernel uses (from its view taken at batch create)
+int lookup_of(const Member &mb)
+{
+    return mb.ham.bidx ? kLkBlocks : (mb.ham.hkeys ? kLkHash : kLkRanks);
+}
+
 int build_lists(irl_batch *b, const std::vector<int> &subset, int region, int prec, ListSet &ls,
                 hipStream_t st)
 {
@@ -948,14 +1018,43 @@ int build_lists(irl_batch *b, const std::vector<int> &subset, int region, int pr
         const int64_t ns = b->hm[m].ns;
         for (int64_t r0 = 0; r0 < ns; r0 += R) v.push_back(WorkItem{m, 0, 0, 0, r0, std::min(ns, r0 + R)});
     };
+    // H rows: one item per member, (m, first block, row groups of 4 rows)
+    int64_t nblk = 0;
+    auto row_groups = [&](int m) {
+        const int64_t ng = (b->hm[m].ns + 3) / 4;
+        v.push_back(WorkItem{m, (int)nblk, (int)ng, 0, 0, 0});
+        nblk += ng;
+    };
     ls.lds6 = 0;
+    ls.product.clear();
+    // enumerating H rows: most expensive members first, in short items, so the
+    // launch does not end on a few long work items
+    std::vector<int> by_cost(subset);
+    auto row_cost = [&](int m) {
+        const irl_system *s = b->sys[m];
+        const int64_t va = s->n - s->na, vb = s->n - s->nb;
+        return (int64_t)s->na * va * s->nb * vb + binom_host(s->na, 2) * binom_host((int)va, 2) +
+               binom_host(s->nb, 2) * binom_host((int)vb, 2);
+    };
+    std::stable_sort(by_cost.begin(), by_cost.end(), [&](int x, int y) { return row_cost(x) > row_cost(y); });
     for (int kind = 0; kind < LS_KINDS; ++kind) {
         ls.off[kind] = (int)v.size();
-        for (int m : subset) {
+        const bool hrows = kind == LS_ROWS4R || kind == LS_ROWS4H || kind == LS_ROWS4B;
+        nblk = 0;
+        for (int m : (hrows ? by_cost : subset)) {
             const Member &mb = b->hm[m];
+            // the stored rows a member uses are those in its view taken at batch create
+            const bool stored = mb.ham.hptr != nullptr;
+            const bool product = !stored && b->sys[m]->ham_kernel == 2;
             switch (kind) {
             case LS_ROWS6: rows(m, 512); ls.lds6 = std::max(ls.lds6, (size_t)mb.ld * (prec == IRL_FP64 ? 8 : 4)); break;
-            case LS_ROWS4: rows(m, 256); break;
+            case LS_ROWS4R:
+                if (product) ls.product.push_back(m);
+                else if (!stored && lookup_of(mb) == kLkRanks) row_groups(m);
+                break;
+            case LS_ROWS4H: if (!stored && !product && lookup_of(mb) == kLkHash) row_groups(m); break;
+            case LS_ROWS4B: if (!stored && !product && lookup_of(mb) == kLkBlocks) row_groups(m); break;
+            case LS_ROWS4S: if (stored) row_groups(m); break;
             case LS_ROWS5: rows(m, 256); break;
             case LS_T2: {
                 const int64_t nch = mb.ld / (prec == IRL_FP64 ? 2 : 4);
@@ -987,6 +1086,10 @@ int build_lists(irl_batch *b, const std::vector<int> &subset, int region, int pr
             }
         }
         ls.cnt[kind] = (int)v.size() - ls.off[kind];
+        ls.blocks[kind] = nblk;
+        // one launch covers the kind: grid size in work-items must stay below 2^32
+        if (nblk > ((int64_t)1 << 24))
+            return set_err(s0, IRL_EINVAL, "batch has more than 2^26 determinant rows of one kernel kind");
     }
     if (ls.lds6 > 64 * 1024) return set_err(s0, IRL_EINVAL, "batch member row longer than 8192 columns");
     CK(s0, hipStreamSynchronize(st));
@@ -1020,7 +1123,7 @@ int upload_members(irl_batch *b, hipStream_t st)
 int gather(irl_batch *b, const ListSet &ls, hipStream_t st)
 {
     irl_system *s0 = b->sys[0];
-    CK(s0, launch_lanczos_grouped(kGrpGather, b->dm, ls.ptr(b, LS_VEC), ls.cnt[LS_VEC], 0, 0, 0, 0, 0,
+    TIMED(s0, IRL_STAT_RITZ, st, launch_lanczos_grouped(kGrpGather, b->dm, ls.ptr(b, LS_VEC), ls.cnt[LS_VEC], 0, 0, 0, 0, 0,
                                   b->dscal, st));
     CK(s0, hipMemcpyAsync(b->hscal, b->dscal, b->B * sizeof(MemberScalars), hipMemcpyDeviceToHost, st));
     CK(s0, hipStreamSynchronize(st));
@@ -1031,11 +1134,18 @@ int batch_apply(irl_batch *b, const ListSet &ls, int vsel, int j, int cur, int s
                 hipStream_t st)
 {
     irl_system *s0 = b->sys[0];
-    CK(s0, launch_gemv_rows_grouped(b->dm, ls.ptr(b, LS_ROWS6), ls.cnt[LS_ROWS6], prec, vsel, j, cur,
+    TIMED(s0, IRL_STAT_GEMV, st, launch_gemv_rows_grouped(b->dm, ls.ptr(b, LS_ROWS6), ls.cnt[LS_ROWS6], prec, vsel, j, cur,
                                     split, ls.lds6, st));
-    CK(s0, launch_ham_pull_grouped(b->dm, ls.ptr(b, LS_ROWS4), ls.cnt[LS_ROWS4], 0, st));
-    CK(s0, launch_gemv_t2_grouped(b->dm, ls.ptr(b, LS_T2), ls.cnt[LS_T2], prec, 0, st));
-    CK(s0, launch_reduce_grouped(b->dm, ls.ptr(b, LS_RED), ls.cnt[LS_RED], 0, st));
+    for (int k : {LS_ROWS4R, LS_ROWS4H, LS_ROWS4B})
+        if (ls.cnt[k])
+            TIMED(s0, IRL_STAT_HAM_APPLY, st,
+                  launch_ham_pull_grouped(b->dm, ls.ptr(b, k), ls.cnt[k], ls.blocks[k], 0,
+                                          k == LS_ROWS4R ? kLkRanks : (k == LS_ROWS4H ? kLkHash : kLkBlocks), st));
+    if (ls.cnt[LS_ROWS4S])
+        TIMED(s0, IRL_STAT_HAM_APPLY, st, launch_ham_stored_grouped(b->dm, ls.ptr(b, LS_ROWS4S), ls.cnt[LS_ROWS4S], ls.blocks[LS_ROWS4S], 0, st));
+    for (int m : ls.product) TIMED(s0, IRL_STAT_HAM_APPLY, st, launch_ham_apply(b->sys[m], b->hm[m].w, b->hm[m].u, st));
+    TIMED(s0, IRL_STAT_GEMV_T, st, launch_gemv_t2_grouped(b->dm, ls.ptr(b, LS_T2), ls.cnt[LS_T2], prec, 0, st));
+    TIMED(s0, IRL_STAT_REDUCE, st, launch_reduce_grouped(b->dm, ls.ptr(b, LS_RED), ls.cnt[LS_RED], 0, st));
     return IRL_OK;
 }
 
@@ -1062,12 +1172,19 @@ int batch_evaluate(irl_batch *b, const std::vector<int> &subset, hipStream_t st)
     if (rc) return rc;
     rc = build_lists(b, subset, 0, prec, ls, st);
     if (rc) return rc;
-    CK(s0, launch_nqs_dtilde_grouped(b->dm, ls.ptr(b, LS_ROWS5), ls.cnt[LS_ROWS5], 0, 0, st));
-    CK(s0, launch_ham_pull_grouped(b->dm, ls.ptr(b, LS_ROWS4), ls.cnt[LS_ROWS4], 1, st));
-    CK(s0, launch_energy_grouped(b->dm, ls.ptr(b, LS_E1), ls.cnt[LS_E1], 1, st));
-    CK(s0, launch_energy_grouped(b->dm, ls.ptr(b, LS_VEC), ls.cnt[LS_VEC], 2, st));
-    CK(s0, launch_gemv_t2_grouped(b->dm, ls.ptr(b, LS_T2), ls.cnt[LS_T2], prec, 1, st));
-    CK(s0, launch_reduce_grouped(b->dm, ls.ptr(b, LS_RED), ls.cnt[LS_RED], 1, st));
+    TIMED(s0, IRL_STAT_DTILDE_BUILD, st, launch_nqs_dtilde_grouped(b->dm, ls.ptr(b, LS_ROWS5), ls.cnt[LS_ROWS5], 0, 0, st));
+    for (int k : {LS_ROWS4R, LS_ROWS4H, LS_ROWS4B})
+        if (ls.cnt[k])
+            TIMED(s0, IRL_STAT_HAM_APPLY, st,
+                  launch_ham_pull_grouped(b->dm, ls.ptr(b, k), ls.cnt[k], ls.blocks[k], 1,
+                                          k == LS_ROWS4R ? kLkRanks : (k == LS_ROWS4H ? kLkHash : kLkBlocks), st));
+    if (ls.cnt[LS_ROWS4S])
+        TIMED(s0, IRL_STAT_HAM_APPLY, st, launch_ham_stored_grouped(b->dm, ls.ptr(b, LS_ROWS4S), ls.cnt[LS_ROWS4S], ls.blocks[LS_ROWS4S], 1, st));
+    for (int m : ls.product) TIMED(s0, IRL_STAT_HAM_APPLY, st, launch_ham_apply(b->sys[m], b->hm[m].psi, b->hm[m].hpsi, st));
+    TIMED(s0, IRL_STAT_ENERGY, st, launch_energy_grouped(b->dm, ls.ptr(b, LS_E1), ls.cnt[LS_E1], 1, st));
+    TIMED(s0, IRL_STAT_ENERGY, st, launch_energy_grouped(b->dm, ls.ptr(b, LS_VEC), ls.cnt[LS_VEC], 2, st));
+    TIMED(s0, IRL_STAT_GEMV_T, st, launch_gemv_t2_grouped(b->dm, ls.ptr(b, LS_T2), ls.cnt[LS_T2], prec, 1, st));
+    TIMED(s0, IRL_STAT_REDUCE, st, launch_reduce_grouped(b->dm, ls.ptr(b, LS_RED), ls.cnt[LS_RED], 1, st));
     rc = gather(b, ls, st);
     if (rc) return rc;
     for (int m : subset) {
@@ -1116,18 +1233,18 @@ int batch_solve(irl_batch *b, const irl_solver_opts &o, int prec, bool from_y,
     if (rc) return rc;
     rc = build_lists(b, active, 0, prec, la, st);
     if (rc) return rc;
-    CK(s0, launch_lanczos_grouped(kGrpReset, b->dm, la.ptr(b, LS_VEC), la.cnt[LS_VEC], 0, 0, 0, 0, 0, nullptr, st));
-    CK(s0, launch_lanczos_grouped(kGrpStart, b->dm, la.ptr(b, LS_VEC), la.cnt[LS_VEC], o.mode, from_y ? 1 : 0, 0, 0, o.seed, nullptr, st));
+    TIMED(s0, IRL_STAT_RITZ, st, launch_lanczos_grouped(kGrpReset, b->dm, la.ptr(b, LS_VEC), la.cnt[LS_VEC], 0, 0, 0, 0, 0, nullptr, st));
+    TIMED(s0, IRL_STAT_RITZ, st, launch_lanczos_grouped(kGrpStart, b->dm, la.ptr(b, LS_VEC), la.cnt[LS_VEC], o.mode, from_y ? 1 : 0, 0, 0, o.seed, nullptr, st));
     int j0 = 0, cur = 0, n_restart = 0;
     // test candidates: Ritz vector of T_mc, one explicit apply, residual
     auto finalize = [&](const std::vector<int> &cand, int mc, bool accept_all) -> int {
         if (cand.empty()) return IRL_OK;
         int r2 = build_lists(b, cand, 1, prec, lc, st);
         if (r2) return r2;
-        CK(s0, launch_lanczos_grouped(kGrpRitzVector, b->dm, lc.ptr(b, LS_VEC), lc.cnt[LS_VEC], cur, mc, 0, 0, 0, nullptr, st));
+        TIMED(s0, IRL_STAT_RITZ, st, launch_lanczos_grouped(kGrpRitzVector, b->dm, lc.ptr(b, LS_VEC), lc.cnt[LS_VEC], cur, mc, 0, 0, 0, nullptr, st));
         r2 = batch_apply(b, lc, 1, 0, cur, split, prec, st);
         if (r2) return r2;
-        CK(s0, launch_lanczos_grouped(kGrpResidual, b->dm, lc.ptr(b, LS_VEC), lc.cnt[LS_VEC], o.mode, split, 0, 0, 0, nullptr, st));
+        TIMED(s0, IRL_STAT_RITZ, st, launch_lanczos_grouped(kGrpResidual, b->dm, lc.ptr(b, LS_VEC), lc.cnt[LS_VEC], o.mode, split, 0, 0, 0, nullptr, st));
         r2 = gather(b, lc, st);
         if (r2) return r2;
         std::vector<int> still;
@@ -1160,7 +1277,7 @@ int batch_solve(irl_batch *b, const irl_solver_opts &o, int prec, bool from_y,
         if (who.empty()) return IRL_OK;
         int r2 = build_lists(b, who, 1, prec, lc, st);
         if (r2) return r2;
-        CK(s0, launch_lanczos_grouped(kGrpRitz, b->dm, lc.ptr(b, LS_VEC), lc.cnt[LS_VEC], mt, kk, 0, 0, 0, nullptr, st));
+        TIMED(s0, IRL_STAT_RITZ, st, launch_lanczos_grouped(kGrpRitz, b->dm, lc.ptr(b, LS_VEC), lc.cnt[LS_VEC], mt, kk, 0, 0, 0, nullptr, st));
         r2 = gather(b, lc, st);
         if (r2) return r2;
         for (int i : who) {
@@ -1186,7 +1303,7 @@ int batch_solve(irl_batch *b, const irl_solver_opts &o, int prec, bool from_y,
             rc = batch_apply(b, la, 0, j, cur, split, prec, st);
             if (rc) return rc;
             for (int i : active) out[i].n_apply += 1;
-            CK(s0, launch_lanczos_grouped(kGrpLanczos, b->dm, la.ptr(b, LS_VEC), la.cnt[LS_VEC], j, cur, o.mode, split,
+            TIMED(s0, IRL_STAT_LANCZOS, st, launch_lanczos_grouped(kGrpLanczos, b->dm, la.ptr(b, LS_VEC), la.cnt[LS_VEC], j, cur, o.mode, split,
                                           o.seed + 0x100000001b3ull * (uint64_t)(n_restart + 1), nullptr, st));
             if (j + 1 < m && j + 1 >= 2 && (j + 1 - j0) % 2 == 0) {
                 std::vector<int> who;
@@ -1213,7 +1330,7 @@ int batch_solve(irl_batch *b, const irl_solver_opts &o, int prec, bool from_y,
             if (rc) return rc;
             break;
         }
-        CK(s0, launch_lanczos_grouped(kGrpRestart, b->dm, la.ptr(b, LS_VEC), la.cnt[LS_VEC], cur, m, k, o.mode,
+        TIMED(s0, IRL_STAT_RITZ, st, launch_lanczos_grouped(kGrpRestart, b->dm, la.ptr(b, LS_VEC), la.cnt[LS_VEC], cur, m, k, o.mode,
                                       o.seed ^ (0x9e3779b97f4a7c15ull * (uint64_t)(n_restart + 7)), nullptr, st));
         cur = 1 - cur;
         j0 = k;
@@ -1402,7 +1519,7 @@ int irl_batch_step(irl_batch *b, const irl_solver_opts *opts, double *const *dth
         ListSet lu;
         rc = build_lists(b, upd, 1, o.precision, lu, st);
         if (rc) return rc;
-        CK(s0, launch_lanczos_grouped(kGrpUpdate, b->dm, lu.ptr(b, LS_VEC), lu.cnt[LS_VEC], 0, 0, 0, 0, 0, nullptr, st));
+        TIMED(s0, IRL_STAT_RITZ, st, launch_lanczos_grouped(kGrpUpdate, b->dm, lu.ptr(b, LS_VEC), lu.cnt[LS_VEC], 0, 0, 0, 0, 0, nullptr, st));
         for (int i = 0; i < B; ++i) {
             b->hm[i].theta = b->nqs[i].theta;
             b->hm[i].dtheta = nullptr;

@@ -62,10 +62,10 @@ __device__ __forceinline__ double single_value(const double *h, const double *g,
     return v;
 }
 
-// key -> row lookup modes of the per-determinant kernels
-constexpr int kLkRanks = 0;    // full space: rank(beta) * nA + rank(alpha)
-constexpr int kLkHash = 1;     // any set: membership bitmap, then open-addressing hash
-constexpr int kLkBlocks = 2;   // selected set: beta -> contiguous row block, binary search on alpha
+// key -> row lookup of the per-determinant kernels (LookupMode):
+//   kLkRanks   full space: rank(beta) * nA + rank(alpha)
+//   kLkHash    any set: membership bitmap, then open-addressing hash
+//   kLkBlocks  selected set: beta -> contiguous row block, binary search on alpha
 
 // row of alpha string `al` inside the rows [lo, hi) that share one beta string
 __device__ __forceinline__ int64_t search_block(const uint64_t *keys, int64_t lo, int64_t hi,
@@ -259,12 +259,12 @@ __device__ __forceinline__ void visit_row(const HamArgs &A, const WaveLists &L, 
 }
 
 // one determinant row on one wavefront: u[row] = H_rr w[row] + sum of the row's connections
+// lists of one row's single moves and pairs (and, for the blocked lookup, the
+// row ranges of its beta-single targets), written by the 64 lanes of its wave
 template <int LK>
-__device__ __forceinline__ void pull_row(const HamArgs &A, WaveLists &L, int64_t row, int lane,
-                                         const double *__restrict__ w, double *__restrict__ u)
+__device__ __forceinline__ void prepare_row(const HamArgs &A, WaveLists &L, uint32_t al, uint32_t be,
+                                            int lane)
 {
-    uint64_t key = A.keys[row];
-    uint32_t al = (uint32_t)key, be = (uint32_t)(key >> 32);
     build_lists(al, A.n, A.na, L.sA, L.sAstr, L.poA, L.pvA, lane);
     build_lists(be, A.n, A.nb, L.sB, L.sBstr, L.poB, L.pvB, lane);
     __builtin_amdgcn_wave_barrier();
@@ -276,14 +276,28 @@ __device__ __forceinline__ void pull_row(const HamArgs &A, WaveLists &L, int64_t
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
+}
+
+__device__ __forceinline__ void end_row()
+{
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int LK>
+__device__ __forceinline__ void pull_row(const HamArgs &A, WaveLists &L, int64_t row, int lane,
+                                         const double *__restrict__ w, double *__restrict__ u)
+{
+    uint64_t key = A.keys[row];
+    uint32_t al = (uint32_t)key, be = (uint32_t)(key >> 32);
+    prepare_row<LK>(A, L, al, be, lane);
     double acc = 0.0;
     visit_row<LK>(A, L, al, be, lane, kWave,
                     [&](int64_t r, int, int, double v) { acc += v * w[r]; });
     acc = wave_sum(acc);
     if (lane == 0) u[row] = A.diag[row] * w[row] + acc;
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    end_row();
 }
 
 template <int LK>
@@ -297,39 +311,156 @@ __global__ __launch_bounds__(256) void k_ham_pull(HamArgs A, const double *__res
         pull_row<LK>(A, lists[wv], row, lane, w, u);
 }
 
-__device__ __forceinline__ int lookup_mode(const HamArgs &A)
+// Stored rows: u[row] = diag * w[row] + sum_p val[p] w[col[p]], one wave per row.
+// The elements are streamed once per apply (non-temporal); each lane keeps four
+// gathers of w in flight.  Lane partial sums are combined by a fixed butterfly,
+// so the result does not depend on scheduling.
+__device__ __forceinline__ void stored_row(const HamArgs &A, int64_t row, int lane,
+                                           const double *__restrict__ w, double *__restrict__ u)
 {
-    return A.bidx ? kLkBlocks : (A.hkeys ? kLkHash : kLkRanks);
+    const int64_t p1 = A.hptr[row + 1];
+    int64_t p = A.hptr[row] + lane;
+    double acc = 0.0;
+    for (; p + 3 * kWave < p1; p += 4 * kWave) {
+        int32_t c[4];
+        double v[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            c[q] = __builtin_nontemporal_load(A.hcol + p + q * kWave);
+            v[q] = __builtin_nontemporal_load(A.hval + p + q * kWave);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc += v[q] * w[c[q]];
+    }
+    for (; p < p1; p += kWave)
+        acc += __builtin_nontemporal_load(A.hval + p) * w[__builtin_nontemporal_load(A.hcol + p)];
+    acc = wave_sum(acc);
+    if (lane == 0) u[row] = A.diag[row] * w[row] + acc;
 }
 
-// grouped: one work item = rows [r0, r1) of member m; which = 0: w -> u, 1: psi -> H psi
-__global__ __launch_bounds__(256) void k_ham_pull_grouped(const Member *__restrict__ M,
-                                                          const WorkItem *__restrict__ items,
-                                                          int which)
+__global__ __launch_bounds__(256) void k_ham_stored(HamArgs A, const double *__restrict__ w,
+                                                    double *__restrict__ u)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t nwaves = (int64_t)gridDim.x * 4;
+    for (int64_t row = (int64_t)blockIdx.x * 4 + wv; row < A.ns; row += nwaves)
+        stored_row(A, row, lane, w, u);
+}
+
+// Stored rows, first pass: number of connections of each row inside the set.
+template <int LK>
+__global__ __launch_bounds__(256) void k_ham_count(HamArgs A, int32_t *__restrict__ count)
 {
     __shared__ WaveLists lists[4];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const WorkItem it = items[blockIdx.x];
-    const Member &mb = M[it.m];
-    const HamArgs A = mb.ham;
-    const double *w = which ? mb.psi : mb.w;
-    double *u = which ? mb.hpsi : mb.u;
-    const int lk = lookup_mode(A);
-    for (int64_t row = it.r0 + wv; row < it.r1; row += 4) {
-        if (lk == kLkRanks)
-            pull_row<kLkRanks>(A, lists[wv], row, lane, w, u);
-        else if (lk == kLkBlocks)
-            pull_row<kLkBlocks>(A, lists[wv], row, lane, w, u);
-        else
-            pull_row<kLkHash>(A, lists[wv], row, lane, w, u);
+    const int64_t nwaves = (int64_t)gridDim.x * 4;
+    for (int64_t row = (int64_t)blockIdx.x * 4 + wv; row < A.ns; row += nwaves) {
+        uint64_t key = A.keys[row];
+        uint32_t al = (uint32_t)key, be = (uint32_t)(key >> 32);
+        prepare_row<LK>(A, lists[wv], al, be, lane);
+        int c = 0;
+        visit_row<LK>(A, lists[wv], al, be, lane, kWave, [&](int64_t, int, int, double) { ++c; });
+        for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, kWave);
+        if (lane == 0) count[row] = c;
+        end_row();
     }
 }
 
-hipError_t launch_ham_pull_grouped(const Member *M, const WorkItem *items, int nitems, int which,
-                                   hipStream_t st)
+// Stored rows, second pass: each lane counts its own connections again, an
+// exclusive scan over the lanes gives its first slot, and a third enumeration
+// writes them.  The layout inside a row is therefore fixed (lane-major), and
+// writes never leave [ptr[row], ptr[row + 1]).
+template <int LK>
+__global__ __launch_bounds__(256) void k_ham_fill(HamArgs A, const int64_t *__restrict__ ptr,
+                                                  int32_t *__restrict__ col, double *__restrict__ val)
 {
-    if (nitems <= 0) return hipSuccess;
-    k_ham_pull_grouped<<<nitems, 256, 0, st>>>(M, items, which);
+    __shared__ WaveLists lists[4];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t nwaves = (int64_t)gridDim.x * 4;
+    for (int64_t row = (int64_t)blockIdx.x * 4 + wv; row < A.ns; row += nwaves) {
+        uint64_t key = A.keys[row];
+        uint32_t al = (uint32_t)key, be = (uint32_t)(key >> 32);
+        prepare_row<LK>(A, lists[wv], al, be, lane);
+        int c = 0;
+        visit_row<LK>(A, lists[wv], al, be, lane, kWave, [&](int64_t, int, int, double) { ++c; });
+        int incl = c;
+        for (int off = 1; off < kWave; off <<= 1) {
+            int t = __shfl_up(incl, off, kWave);
+            if (lane >= off) incl += t;
+        }
+        int64_t pos = ptr[row] + (incl - c);
+        const int64_t end = ptr[row + 1];
+        visit_row<LK>(A, lists[wv], al, be, lane, kWave, [&](int64_t r, int, int, double v) {
+            if (pos < end) {
+                col[pos] = (int32_t)r;
+                val[pos] = v;
+            }
+            ++pos;
+        });
+        end_row();
+    }
+}
+
+// Grouped H rows: one block per 4-row group, as in the solo launch.  Item k
+// = (member m, first block a, b row groups); the items are in ascending a, and
+// each block finds its item by a binary search (uniform, scalar loads).
+// which = 0: w -> u, 1: psi -> H psi.
+__device__ __forceinline__ int find_item(const WorkItem *__restrict__ items, int nitems, int blk)
+{
+    int lo = 0, hi = nitems - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (items[mid].a <= blk) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <int LK>
+__global__ __launch_bounds__(256) void k_ham_pull_grouped(const Member *__restrict__ M,
+                                                          const WorkItem *__restrict__ items,
+                                                          int nitems, int which)
+{
+    __shared__ WaveLists lists[4];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const WorkItem it = items[find_item(items, nitems, (int)blockIdx.x)];
+    const Member &mb = M[it.m];
+    const double *w = which ? mb.psi : mb.w;
+    double *u = which ? mb.hpsi : mb.u;
+    const int64_t row = 4 * (int64_t)((int)blockIdx.x - it.a) + wv;
+    if (row < mb.ns) pull_row<LK>(mb.ham, lists[wv], row, lane, w, u);
+}
+
+__global__ __launch_bounds__(256) void k_ham_stored_grouped(const Member *__restrict__ M,
+                                                            const WorkItem *__restrict__ items,
+                                                            int nitems, int which)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const WorkItem it = items[find_item(items, nitems, (int)blockIdx.x)];
+    const Member &mb = M[it.m];
+    const double *w = which ? mb.psi : mb.w;
+    double *u = which ? mb.hpsi : mb.u;
+    const int64_t row = 4 * (int64_t)((int)blockIdx.x - it.a) + wv;
+    if (row < mb.ns) stored_row(mb.ham, row, lane, w, u);
+}
+
+hipError_t launch_ham_stored_grouped(const Member *M, const WorkItem *items, int nitems,
+                                     int64_t nblocks, int which, hipStream_t st)
+{
+    if (nitems <= 0 || nblocks <= 0) return hipSuccess;
+    k_ham_stored_grouped<<<(unsigned)nblocks, 256, 0, st>>>(M, items, nitems, which);
+    return hipGetLastError();
+}
+
+hipError_t launch_ham_pull_grouped(const Member *M, const WorkItem *items, int nitems,
+                                   int64_t nblocks, int which, int lookup, hipStream_t st)
+{
+    if (nitems <= 0 || nblocks <= 0) return hipSuccess;
+    if (lookup == kLkBlocks)
+        k_ham_pull_grouped<kLkBlocks><<<(unsigned)nblocks, 256, 0, st>>>(M, items, nitems, which);
+    else if (lookup == kLkHash)
+        k_ham_pull_grouped<kLkHash><<<(unsigned)nblocks, 256, 0, st>>>(M, items, nitems, which);
+    else
+        k_ham_pull_grouped<kLkRanks><<<(unsigned)nblocks, 256, 0, st>>>(M, items, nitems, which);
     return hipGetLastError();
 }
 
@@ -351,8 +482,11 @@ HamView ham_view(const irl_system *s)
     A.hmask = s->d.hcap ? s->d.hcap - 1 : 0;
     A.hfilter = s->d.hfilter;
     A.hfbits = s->d.hfbits;
-    A.bidx = s->ham_kernel == 3 ? s->d.bidx : nullptr;
-    A.bstart = s->ham_kernel == 3 ? s->d.bstart : nullptr;
+    A.bidx = s->lookup == kLkBlocks ? s->d.bidx : nullptr;
+    A.bstart = s->lookup == kLkBlocks ? s->d.bstart : nullptr;
+    A.hptr = s->ham_kernel == 4 ? s->d.hptr : nullptr;
+    A.hcol = s->ham_kernel == 4 ? s->d.hcol : nullptr;
+    A.hval = s->ham_kernel == 4 ? s->d.hval : nullptr;
     A.rankA = s->d.rankA;
     A.rankB = s->d.rankB;
     return A;
@@ -366,12 +500,43 @@ hipError_t launch_ham_apply(const irl_system *s, const double *w, double *u, hip
     HamArgs A = ham_view(s);
     int64_t blocks = (s->ns + 3) / 4;
     if (blocks > 65536) blocks = 65536;
-    if (s->ham_kernel == 3)
+    if (s->ham_kernel == 4)
+        k_ham_stored<<<(unsigned)blocks, 256, 0, st>>>(A, w, u);
+    else if (s->lookup == kLkBlocks)
         k_ham_pull<kLkBlocks><<<(unsigned)blocks, 256, 0, st>>>(A, w, u);
-    else if (s->d.hkeys != nullptr)
+    else if (s->lookup == kLkHash)
         k_ham_pull<kLkHash><<<(unsigned)blocks, 256, 0, st>>>(A, w, u);
     else
         k_ham_pull<kLkRanks><<<(unsigned)blocks, 256, 0, st>>>(A, w, u);
+    return hipGetLastError();
+}
+
+hipError_t launch_ham_count(const irl_system *s, int32_t *count, hipStream_t st)
+{
+    HamArgs A = ham_view(s);
+    int64_t blocks = (s->ns + 3) / 4;
+    if (blocks > 65536) blocks = 65536;
+    if (s->lookup == kLkBlocks)
+        k_ham_count<kLkBlocks><<<(unsigned)blocks, 256, 0, st>>>(A, count);
+    else if (s->lookup == kLkHash)
+        k_ham_count<kLkHash><<<(unsigned)blocks, 256, 0, st>>>(A, count);
+    else
+        k_ham_count<kLkRanks><<<(unsigned)blocks, 256, 0, st>>>(A, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_ham_fill(const irl_system *s, const int64_t *ptr, int32_t *col, double *val,
+                           hipStream_t st)
+{
+    HamArgs A = ham_view(s);
+    int64_t blocks = (s->ns + 3) / 4;
+    if (blocks > 65536) blocks = 65536;
+    if (s->lookup == kLkBlocks)
+        k_ham_fill<kLkBlocks><<<(unsigned)blocks, 256, 0, st>>>(A, ptr, col, val);
+    else if (s->lookup == kLkHash)
+        k_ham_fill<kLkHash><<<(unsigned)blocks, 256, 0, st>>>(A, ptr, col, val);
+    else
+        k_ham_fill<kLkRanks><<<(unsigned)blocks, 256, 0, st>>>(A, ptr, col, val);
     return hipGetLastError();
 }
 
@@ -411,9 +576,9 @@ hipError_t launch_ham_row_list(const irl_system *s, int64_t row, int32_t *tgt, i
                                hipStream_t st)
 {
     HamArgs A = ham_view(s);
-    if (s->ham_kernel == 3)
+    if (s->lookup == kLkBlocks)
         k_ham_row_list<kLkBlocks><<<1, 64, 0, st>>>(A, row, tgt, sign, kind, val, count, cap);
-    else if (s->d.hkeys != nullptr)
+    else if (s->lookup == kLkHash)
         k_ham_row_list<kLkHash><<<1, 64, 0, st>>>(A, row, tgt, sign, kind, val, count, cap);
     else
         k_ham_row_list<kLkRanks><<<1, 64, 0, st>>>(A, row, tgt, sign, kind, val, count, cap);

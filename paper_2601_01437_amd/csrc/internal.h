@@ -76,6 +76,11 @@ struct SystemDev {
     int32_t *bidx = nullptr;      // 2^n: beta string -> block index, -1 if absent
     int32_t *bstart = nullptr;    // nblocks + 1 row offsets
     int64_t nblocks = 0;
+    // stored rows (optional): off-diagonal elements inside the set, compressed by row
+    int64_t *hptr = nullptr;      // n_dets + 1
+    int32_t *hcol = nullptr;      // nnz target rows
+    double *hval = nullptr;       // nnz values
+    int64_t hnnz = 0;
     // string tables (full space)
     int32_t *rankA = nullptr;   // 2^n, -1 for strings not of popcount n_alpha
     int32_t *rankB = nullptr;
@@ -110,7 +115,13 @@ struct HamView {
     const int32_t *rankA, *rankB;
     const int32_t *bidx;     // blocked lookup: beta string -> block, -1 if absent (or nullptr)
     const int32_t *bstart;   // blocked lookup: first row of each block, plus the end
+    const int64_t *hptr;     // stored rows (or nullptr): row offsets
+    const int32_t *hcol;     // stored rows: targets
+    const double *hval;      // stored rows: values
 };
+
+// key -> row lookup used when excitations are enumerated
+enum LookupMode { kLkRanks = 0, kLkHash = 1, kLkBlocks = 2 };
 
 // One member of a grouped (batched) launch: its system view, workspace
 // pointers and network.  Lives in device memory; grouped kernels index it.
@@ -148,7 +159,9 @@ struct irl_system {
     int64_t ns = 0;
     int64_t nA = 0, nB = 0;   // string counts (full space) or distinct counts
     bool full = false;
-    int ham_kernel = 0;       // 0 hashed pull, 1 rank pull, 2 string product, 3 blocked pull
+    int ham_kernel = 0;       // 0 hashed pull, 1 rank pull, 2 string product, 3 blocked pull,
+                              // 4 stored rows
+    int lookup = 0;           // irl::LookupMode of the excitation enumeration
     int device = 0;
     size_t dev_bytes = 0;
     irl::SystemDev d;
@@ -189,9 +202,15 @@ hipError_t launch_lookup_any(const irl_system *s, const uint64_t *q, int64_t nq,
 // hamiltonian.hip
 hipError_t launch_product_tables(irl_system *s, hipStream_t st);
 HamView ham_view(const irl_system *s);
-hipError_t launch_ham_pull_grouped(const Member *M, const WorkItem *items, int nitems, int which,
-                                   hipStream_t st);
+hipError_t launch_ham_stored_grouped(const Member *M, const WorkItem *items, int nitems,
+                                     int64_t nblocks, int which, hipStream_t st);
+hipError_t launch_ham_pull_grouped(const Member *M, const WorkItem *items, int nitems,
+                                   int64_t nblocks, int which, int lookup, hipStream_t st);
 hipError_t launch_ham_apply(const irl_system *s, const double *w, double *u, hipStream_t st);
+// stored rows: per-row counts of connections inside the set, then the fill
+hipError_t launch_ham_count(const irl_system *s, int32_t *count, hipStream_t st);
+hipError_t launch_ham_fill(const irl_system *s, const int64_t *ptr, int32_t *col, double *val,
+                           hipStream_t st);
 hipError_t launch_ham_row_list(const irl_system *s, int64_t row, int32_t *tgt, int8_t *sign,
                                uint8_t *kind, double *val, int32_t *count, int cap,
                                hipStream_t st);

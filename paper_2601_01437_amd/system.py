@@ -38,6 +38,14 @@ class System:
         except Exception:
             pass
 
+    def store_hamiltonian(self, max_bytes):
+        """Store H's rows in device memory if they fit in max_bytes; returns
+        (stored, bytes_needed)."""
+        with torch.cuda.device(self.device):
+            stored, need = B.irl_system_store_hamiltonian(self.handle, max_bytes)
+        self.info = B.irl_system_info_get(self.handle)
+        return stored, need
+
     # -- workspace --
     def workspace(self, ncols, ws_flags=B.IRL_WS_FP64):
         nbytes = B.irl_workspace_query(self.handle, ncols, ws_flags)

@@ -1,6 +1,7 @@
 """Batched solves (grouped kernels, lockstep members) through the C ABI: every
-member's result equals the solo irl_step result on a system created with the
-same per-determinant Hamiltonian kernel, bit for bit, and matches the oracle."""
+member's result equals the solo irl_step result on a system that uses the same
+Hamiltonian kernel (per-determinant, string-product or stored rows), bit for
+bit, and matches the oracle."""
 import numpy as np
 import pytest
 
@@ -21,13 +22,15 @@ MEMBERS = [(6, 3, 3, 8, 1, None), (8, 4, 4, 16, 0, None), (7, 4, 3, 12, 2, None)
            (10, 5, 5, 6, 3, 2000), (9, 5, 4, 10, 4, 777), (8, 4, 4, 24, 5, 3000)]
 
 
-def _build(flags_full):
+def _build(flags_full, store=False, flags_sel=0):
     from paper_2601_01437_amd import System
     out = []
     for n, na, nb, H, seed, sel in MEMBERS:
         h, g = synth.integrals(n, seed)
         dets = None if sel is None else synth.cisd_like_selected_set(n, na, nb, sel, seed=seed)
-        s = System(n, na, nb, h, g, dets=dets, flags=flags_full if dets is None else 0)
+        s = System(n, na, nb, h, g, dets=dets, flags=flags_full if dets is None else flags_sel)
+        if store:
+            assert s.store_hamiltonian(1 << 32)[0]
         theta = synth.nqs_theta(2 * n, H, seed, scale=0.2)
         out.append((s, theta, 2 * n, H, h, g, dets))
     return out
@@ -38,17 +41,35 @@ def _fields(r):
             r.n_apply, r.n_restart, r.converged)
 
 
+# (flags for full spaces, store rows, flags for selected sets)
+KERNELS = {"pull": (2, False, 0), "default": (0, False, 0), "stored": (2, True, 0),
+           "hash": (1, False, 1)}
+
+
+@pytest.mark.parametrize("kernels", ["pull", "default", "stored", "hash"])
 @pytest.mark.parametrize("m,k", [(20, 1), (12, 4)])
-def test_batch_equals_solo_bitwise(m, k):
-    from paper_2601_01437_amd import IRL_SYS_FORCE_PULL, Batch
-    announce(f"batch vs solo m={m} k={k}")
-    solo = _build(IRL_SYS_FORCE_PULL)
+def test_batch_equals_solo_bitwise(m, k, kernels):
+    """pull: per-determinant kernels (string ranks, beta blocks); default:
+    string-product for full spaces and beta-blocked for selected sets; stored:
+    every member's rows stored; hash: hashed lookup for every member."""
+    from paper_2601_01437_amd import Batch
+    announce(f"batch vs solo m={m} k={k} kernels={kernels}")
+    flags_full, store, flags_sel = KERNELS[kernels]
+    solo = _build(flags_full, store, flags_sel)
     ref = []
     for s, theta, V, H, *_ in solo:
         th = dev(theta)
         rc, r, dth, _ = s.step(th, V, H, m=m, k_keep=k)
         ref.append((rc, r, host(dth), host(th)))
-    batch_sys = _build(IRL_SYS_FORCE_PULL)
+    batch_sys = _build(flags_full, store, flags_sel)
+    kinds = [x[0].info.ham_kernel for x in batch_sys]
+    assert kinds == [x[0].info.ham_kernel for x in solo]
+    if kernels == "stored":
+        assert set(kinds) == {4}
+    elif kernels == "default":
+        assert 2 in kinds and 3 in kinds
+    elif kernels == "hash":
+        assert set(kinds) == {0}
     thetas = [dev(t) for _, t, *_ in batch_sys]
     bt = Batch([x[0] for x in batch_sys], thetas, [x[2] for x in batch_sys], [x[3] for x in batch_sys])
     res, status, dth = bt.step(m=m, k_keep=k, want_dtheta=True)

@@ -1,0 +1,112 @@
+"""Stored Hamiltonian rows (irl_system_store_hamiltonian) through the C ABI.
+
+The number of stored elements is an integer fixed by the set: it must equal the
+oracle's count of off-diagonal connections inside the set (bit-exact, through
+the reported byte size).  Applies and whole steps that stream the stored rows
+are compared with the oracle at the FP64 tolerances of the enumerating kernels
+(||u - u_ref|| <= 1e-12 ||u_ref||; energies 1e-12 Ha)."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import capply, space
+from tests.gpu_util import announce, dev, host, rel_err, require_gpu
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "c3s_step.json")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    require_gpu()
+
+
+def _system(n, na, nb, seed, dets, flags=0):
+    from paper_2601_01437_amd import System
+    h, g = synth.integrals(n, seed)
+    return System(n, na, nb, h, g, dets=dets, flags=flags), h, g
+
+
+CASES = [  # (n, na, nb, selected count or None, seed, system flags)
+    (8, 4, 4, None, 0, 2),          # full space, rank lookup
+    (10, 5, 5, 3000, 2, 0),         # selected, beta-blocked lookup
+    (10, 5, 5, 3000, 2, 1),         # selected, hashed lookup
+    (20, 10, 10, 1 << 14, 0, 0),    # selected, 20 orbitals
+    (24, 4, 3, 5000, 1, 0),         # selected, 24 orbitals
+    (9, 5, 4, 1, 5, 0),             # one determinant: no off-diagonal elements
+]
+
+
+@pytest.mark.parametrize("n,na,nb,count,seed,flags", CASES)
+def test_stored_rows_count_and_apply(n, na, nb, count, seed, flags):
+    announce(f"stored rows n={n} count={count} flags={flags}")
+    keys = (space.full_space(n, na, nb) if count is None
+            else synth.cisd_like_selected_set(n, na, nb, count, seed=seed))
+    s, h, g = _system(n, na, nb, seed, None if count is None else keys, flags)
+    Href = capply.csr(n, h, g, keys)
+    nnz_off = Href.nnz - keys.size        # the oracle emits the diagonal once per row
+    stored, need = s.store_hamiltonian(1 << 40)
+    assert stored and s.info.ham_kernel == 4
+    assert need == (keys.size + 1) * 8 + 12 * nnz_off
+    w = np.random.default_rng(4).normal(size=keys.size)
+    u = host(s.apply_hamiltonian(dev(w)))
+    assert rel_err(u, Href @ w) <= 1e-12
+    again, need2 = s.store_hamiltonian(0)   # already stored: no-op
+    assert again and need2 == need
+
+
+def test_stored_rows_over_budget_leaves_system_unchanged():
+    announce("stored rows over budget")
+    keys = synth.cisd_like_selected_set(10, 5, 5, 2000, seed=3)
+    s, h, g = _system(10, 5, 5, 3, keys)
+    kernel, nbytes = s.info.ham_kernel, s.info.device_bytes
+    stored, need = s.store_hamiltonian(1000)
+    assert not stored and need > 1000
+    assert s.info.ham_kernel == kernel and s.info.device_bytes == nbytes
+    w = np.random.default_rng(5).normal(size=keys.size)
+    u = host(s.apply_hamiltonian(dev(w)))
+    assert rel_err(u, capply.apply(10, h, g, keys, w)) <= 1e-12
+    stored, need3 = s.store_hamiltonian(need)  # exactly the size needed fits
+    assert stored and need3 == need
+    assert s.info.device_bytes == nbytes + need
+    u2 = host(s.apply_hamiltonian(dev(w)))
+    assert rel_err(u2, u) <= 1e-13
+
+
+def test_stored_rows_apply_is_bitwise_reproducible():
+    keys = synth.cisd_like_selected_set(12, 6, 6, 20000, seed=1)
+    s, _, _ = _system(12, 6, 6, 1, keys)
+    assert s.store_hamiltonian(1 << 32)[0]
+    w = dev(np.random.default_rng(6).normal(size=keys.size))
+    u1 = host(s.apply_hamiltonian(w))
+    u2 = host(s.apply_hamiltonian(w))
+    assert np.array_equal(u1, u2)
+    # two systems built from the same set store identical rows
+    s2, _, _ = _system(12, 6, 6, 1, keys)
+    assert s2.store_hamiltonian(1 << 32)[0]
+    assert np.array_equal(host(s2.apply_hamiltonian(w)), u1)
+
+
+def test_stored_rows_c3s_step_matches_oracle():
+    """One FP64 step on the 2^14-determinant, 20-orbital selected set with V = 40,
+    H = 256 (P = 10,536), the Hamiltonian streamed from stored rows."""
+    if not os.path.exists(GOLDEN):
+        pytest.skip("tests/golden/c3s_step.json not generated")
+    from paper_2601_01437_amd import IRL_FP64, IRL_WS_FP64, System
+    announce("stored rows c3s step")
+    G = json.load(open(GOLDEN))
+    w = synth.WORKLOADS["c3s"]
+    h, g = w.integrals()
+    s = System(w.n, w.na, w.nb, h, g, dets=w.dets())
+    assert s.store_hamiltonian(1 << 34)[0]
+    rc, r, dth, _ = s.step(dev(w.theta()), w.V, w.H, m=w.m, k_keep=w.k, precision=IRL_FP64,
+                           ws_flags=IRL_WS_FP64)
+    assert r.converged == 1
+    assert abs(r.E_before - G["E"]) <= 1e-12
+    assert abs(r.lambda_min - G["lambda_min"]) <= 1e-10 * max(abs(G["lambda_min"]), G["norm_Hp"])
+    assert abs(r.E_after - G["E_after"]) <= 1e-12
+    d = host(dth)
+    assert abs(np.linalg.norm(d) - G["dtheta_norm"]) <= 1e-8 * G["dtheta_norm"]
