@@ -248,12 +248,147 @@ def run_batch_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def run_serving_bench(args):
+    """Serving: requests (one optimisation step of a fresh network on the c1, c2
+    or c3 system) arrive as a Poisson process (20/s, seed 0) over about
+    args.serve_seconds; the mix is chosen so the offered load is 0.7 of the
+    measured one-at-a-time capacity.  Served with resident slots per class and
+    one lane per class (FP32 operator, FP64 solver), then against the plain
+    sequential FP64 schedule of the same arrivals."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2601_01437_amd import binding as B
+    from paper_2601_01437_amd.serving import (ClassPool, ClassSpec, Request, Server,
+                                              latency_summary, run_sequential)
+
+    rate = 20.0
+    names = ("c1", "c2", "c3")
+    wl = {c: synth.WORKLOADS[c] for c in names}
+    ints = {c: wl[c].integrals() for c in names}
+    dets = {c: wl[c].dets() for c in names}
+    slots = {"c1": 16, "c2": 8, "c3": 1}
+
+    def make_pools(precision, nslots):
+        pools = {}
+        for c in names:
+            w = wl[c]
+            h, g = ints[c]
+            pools[c] = ClassPool(ClassSpec(c, w.n, w.na, w.nb, w.V, w.H, h, g, dets=dets[c], m=w.m,
+                                           k_keep=w.k, precision=precision, slots=nslots[c],
+                                           store_rows_bytes=32 << 30))
+        torch.cuda.synchronize()
+        return pools
+
+    def service_ms(pools, reps):
+        out = {}
+        for c in names:
+            r = Request(-1, c, 0.0, synth.nqs_theta(wl[c].V, wl[c].H, 999))
+            pools[c].step([r])                       # warm-up
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(reps[c]):
+                pools[c].step([r])
+            torch.cuda.synchronize()
+            out[c] = (time.perf_counter() - t) / reps[c] * 1e3
+        return out
+
+    t_setup = time.perf_counter()
+    pools = make_pools(B.IRL_FP32, slots)
+    log(f"resident pools ready in {time.perf_counter() - t_setup:.1f} s: "
+        + ", ".join(f"{c} {len(p.systems)} slots {p.device_bytes() / 1e9:.1f} GB" for c, p in pools.items()))
+    svc = service_ms(pools, {"c1": 5, "c2": 3, "c3": 1})
+    log("one-at-a-time FP32 service ms: " + ", ".join(f"{c} {v:.1f}" for c, v in svc.items()))
+    # mix c1 : c2 : c3 = (1 - 6x) : 5x : x with offered load rate * E[service] = 0.7
+    t1, t2, t3 = (svc[c] / 1e3 for c in names)
+    x = (0.7 / rate - t1) / (5 * t2 + t3 - 6 * t1)
+    x = float(min(max(x, 0.0), 1.0 / 6.0))
+    mix = {"c1": 1 - 6 * x, "c2": 5 * x, "c3": x}
+    offered = rate * sum(mix[c] * svc[c] / 1e3 for c in names)
+    n_req = int(rate * args.serve_seconds)
+    arr, picks = synth.serving_arrivals(n_req, rate, mix, seed=0)
+    log(f"mix {', '.join(f'{c} {mix[c]:.3f}' for c in names)}; offered load {offered:.2f}; "
+        f"{n_req} requests over {arr[-1]:.1f} s")
+
+    def requests():
+        return [Request(i, picks[i], float(arr[i]), synth.nqs_theta(wl[picks[i]].V, wl[picks[i]].H, 1000 + i))
+                for i in range(n_req)]
+
+    served = requests()
+    makespan = Server(pools).run(served)
+    lat = {"all": latency_summary(served)}
+    for c in names:
+        lat[c] = latency_summary([r for r in served if r.cls == c])
+    log(f"served {n_req} in {makespan:.1f} s: p50 {lat['all']['p50_ms']:.1f} ms, "
+        f"p99 {lat['all']['p99_ms']:.1f} ms")
+    # a result in the mix equals the result alone (solo path, slot 0)
+    checked = equal = 0
+    c3_left = 2
+    for r in served:
+        if r.cls == "c3":
+            if c3_left == 0:
+                continue
+            c3_left -= 1
+        alone = Request(r.rid, r.cls, 0.0, r.theta)
+        pools[r.cls].step([alone])
+        checked += 1
+        equal += (alone.lambda_min == r.lambda_min and alone.E_after == r.E_after
+                  and alone.n_apply == r.n_apply and alone.status == r.status)
+    torch.cuda.synchronize()
+    log(f"mix vs alone: {equal}/{checked} bitwise equal")
+    batch_sizes = [r.batch_size for r in served]
+    for p in pools.values():
+        p.close()
+    pools = None
+    torch.cuda.empty_cache()
+
+    pools64 = make_pools(B.IRL_FP64, {c: 1 for c in names})
+    svc64 = service_ms(pools64, {"c1": 5, "c2": 3, "c3": 1})
+    log("sequential FP64 service ms: " + ", ".join(f"{c} {v:.1f}" for c, v in svc64.items()))
+    seq = requests()
+    makespan64 = run_sequential(pools64, seq)
+    lat64 = {"all": latency_summary(seq)}
+    for c in names:
+        lat64[c] = latency_summary([r for r in seq if r.cls == c])
+    log(f"sequential FP64: {n_req} in {makespan64:.1f} s: p50 {lat64['all']['p50_ms']:.1f} ms, "
+        f"p99 {lat64['all']['p99_ms']:.1f} ms")
+    dE = [abs(a.E_after - b_.E_after) for a, b_ in zip(served, seq) if np.isfinite(a.E_after)]
+    for p in pools64.values():
+        p.close()
+    out = {
+        "metric": METRIC,
+        "value": n_req / makespan,
+        "unit": "solves/s",
+        "n_gpus": 1, "steps": n_req, "warmup": 1,
+        "ms_per_step": lat["all"]["p50_ms"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 operator, f64 solver", "data": "synthetic",
+        "config": {"workload": (f"c5: Poisson arrivals {rate:g}/s seed 0, {n_req} requests, each one IRL "
+                                f"step of a fresh network (theta seed 1000 + request) on the c1 (4,900 "
+                                f"full), c2 (853,776 full) or c3 (2^20 selected, stored rows) system; "
+                                f"continuous admission into resident slots, one lane per class"),
+                   "mix": mix, "offered_load": offered, "slots": slots,
+                   "service_ms_fp32": svc, "service_ms_fp64": svc64},
+        "latency_ms": lat,
+        "mean_batch_size": float(np.mean(batch_sizes)),
+        "makespan_s": makespan,
+        "sequential_fp64": {"solves_per_s": n_req / makespan64, "makespan_s": makespan64,
+                            "latency_ms": lat64},
+        "mix_equals_alone": {"checked": checked, "bitwise_equal": equal},
+        "max_abs_dE_after_fp32_vs_fp64": float(max(dE)) if dE else None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c3s", "c4"])
+    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c3s", "c4", "c5"])
+    ap.add_argument("--serve-seconds", type=float, default=20.0,
+                    help="c5: length of the arrival window in seconds")
     ap.add_argument("--solves", type=int, default=64, help="c4: number of independent solves")
     ap.add_argument("--hbm-budget-gb", type=float, default=240.0,
                     help="c4: device memory admitted per wave of batched solves")
@@ -294,6 +429,9 @@ def main():
         return
     if args.config == "c4":
         run_batch_bench(args)
+        return
+    if args.config == "c5":
+        run_serving_bench(args)
         return
     wl = synth.WORKLOADS[args.config]
     h, g = wl.integrals()
