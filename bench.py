@@ -38,14 +38,17 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def kernel_bytes(kind, ns, ncols, sD):
-    """Algorithmic HBM bytes of one launch (reads + writes the kernel must do)."""
-    if kind == "gemv":        # read D~, read v, write w
-        return ns * ncols * sD + ncols * 8 + ns * 8
-    if kind == "gemv_t":      # read D~, read the two row vectors
+def kernel_bytes(kind, ns, ncols, s_build):
+    """Algorithmic HBM bytes of one launch (reads + writes the kernel must do).
+    The stream kernels read the FP64 copy of D~ (8 B per element) or, for the
+    *_fp32 kinds, the FP32 copy; the build writes every copy (s_build B)."""
+    sD = 4 if kind.endswith("_fp32") else 8
+    if kind.startswith("gemv_t"):   # read D~, read the two row vectors
         return ns * ncols * sD + 2 * ns * 8
-    if kind == "dtilde_build":  # write D~ (and psi)
-        return ns * ncols * sD + ns * 8
+    if kind.startswith("gemv"):     # read D~, read v, write w
+        return ns * ncols * sD + ncols * 8 + ns * 8
+    if kind == "dtilde_build":      # write D~ (and psi)
+        return ns * ncols * s_build + ns * 8
     return None
 
 
@@ -395,6 +398,10 @@ def main():
     ap.add_argument("--precision", default=None, choices=["fp64", "fp32"],
                     help="operator precision (default: the workload's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--polish", action="store_true",
+                    help="FP32 operator: keep an FP64 copy of D~ and refine the Ritz pair in FP64")
+    ap.add_argument("--no-fp64-reference", dest="fp64_reference", action="store_false",
+                    help="FP32 operator: skip the FP64 step used to report the precision gap")
     ap.add_argument("--force-hash", action="store_true", help="general hashed Hamiltonian kernel")
     ap.add_argument("--matrix-free", action="store_true",
                     help="selected sets: enumerate excitations on every apply instead of "
@@ -448,8 +455,12 @@ def main():
     theta = theta0.clone()
     prec_name = args.precision or wl.precision
     precision = B.IRL_FP64 if prec_name == "fp64" else B.IRL_FP32
-    ws_flags = B.IRL_WS_FP64 | (B.IRL_WS_FP32 if precision == B.IRL_FP32 else 0)
-    sD = 8 if precision == B.IRL_FP64 else 4
+    # FP32 operator: FP32 copy of D~ only, unless the FP64 polish of the Ritz pair is asked for
+    if precision == B.IRL_FP64:
+        ws_flags = B.IRL_WS_FP64
+    else:
+        ws_flags = B.IRL_WS_FP32 | (B.IRL_WS_FP64 if args.polish else 0)
+    step_flags = B.IRL_STEP_NO_EVAL_AFTER | (0 if args.polish else B.IRL_STEP_NO_POLISH)
     sysm.workspace(wl.P + 1, ws_flags)
     log(f"workspace {sysm.ws.numel() / 2**30:.2f} GiB")
     store = None
@@ -462,7 +473,7 @@ def main():
 
     def one_step():
         rc, r, _, _ = sysm.step(theta, wl.V, wl.H, m=wl.m, k_keep=wl.k, tol=1e-12,
-                                precision=precision, flags=B.IRL_STEP_NO_EVAL_AFTER,
+                                precision=precision, flags=step_flags,
                                 ws_flags=ws_flags, want_dtheta=False)
         return rc, r
 
@@ -481,6 +492,7 @@ def main():
         rc, r = one_step()
         step_ms = (time.perf_counter() - ts) * 1e3
         steps.append({"E": r.E_before, "lambda_min": r.lambda_min, "applies": r.n_apply,
+                      "applies_fp32": r.n_apply_lo,
                       "restarts": r.n_restart, "converged": r.converged,
                       "residual_est": r.residual_est, "residual_explicit": r.residual_explicit,
                       "status": rc, "ms": step_ms})
@@ -498,36 +510,57 @@ def main():
     # dominant kernel and its roofline
     ncols = wl.P + 1
     kern = {k: {"ms_total": v[0], "launches": v[1], "ms_avg": v[0] / v[1] if v[1] else None}
-            for k, v in stats.items()}
-    dominant = max(kern, key=lambda k: kern[k]["ms_total"])
+            for k, v in stats.items() if v[1]}
     src = [os.path.join(ROOT, "paper_2601_01437_amd", "csrc", f) for f in ("dtilde.hip", "internal.h")]
     src_hash = source_hash(src)
     roof = None
-    hbm_kinds = ("gemv", "gemv_t", "dtilde_build")
-    roof_kernel = dominant if dominant in hbm_kinds else max(hbm_kinds, key=lambda k: kern[k]["ms_total"])
-    s_build = 8 + (4 if ws_flags & B.IRL_WS_FP32 else 0)    # both copies are written
-    nbytes = kernel_bytes(roof_kernel, ns, ncols, s_build if roof_kernel == "dtilde_build" else sD)
+    s_build = (8 if ws_flags & B.IRL_WS_FP64 else 0) + (4 if ws_flags & B.IRL_WS_FP32 else 0)
+    hbm_kinds = [k for k in ("gemv", "gemv_t", "gemv_fp32", "gemv_t_fp32", "dtilde_build") if k in kern]
+    roof_kernel = max(hbm_kinds, key=lambda k: kern[k]["ms_total"])
+    nbytes = kernel_bytes(roof_kernel, ns, ncols, s_build)
     avg = kern[roof_kernel]["ms_avg"]
-    if avg:
-        achieved = nbytes / (avg * 1e-3) / 1e9
-        traffic = read_traffic(roof_kernel, wl.name, src_hash)
-        roof = {"kernel": roof_kernel, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS,
-                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
-                "bytes_per_launch": nbytes, "ms_avg": avg, "source_hash": src_hash}
-    # whole operator apply
-    op_ms = sum(kern[k]["ms_total"] for k in ("gemv", "gemv_t", "reduce", "ham_apply"))
-    per_apply_bytes = 2 * ns * ncols * sD + 6 * 8 * ns
-    n_op = kern["gemv"]["launches"]
-    operator = None
-    if n_op:
-        apply_ms = (kern["gemv"]["ms_total"] + kern["ham_apply"]["ms_total"] * n_op / max(1, kern["ham_apply"]["launches"])
-                    + kern["gemv_t"]["ms_total"] * n_op / max(1, kern["gemv_t"]["launches"])
-                    + kern["reduce"]["ms_total"] * n_op / max(1, kern["reduce"]["launches"])) / n_op
-        operator = {"ms_per_apply": apply_ms, "GBps": per_apply_bytes / (apply_ms * 1e-3) / 1e9,
-                    "frac_hbm": per_apply_bytes / (apply_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS,
-                    "bytes_per_apply": per_apply_bytes,
-                    "ham_elements_per_s": ns * sysm.info.max_connections /
-                    (kern["ham_apply"]["ms_avg"] * 1e-3) if kern["ham_apply"]["ms_avg"] else None}
+    achieved = nbytes / (avg * 1e-3) / 1e9
+    traffic = read_traffic(roof_kernel, wl.name, src_hash)
+    roof = {"kernel": roof_kernel, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS,
+            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
+            "bytes_per_launch": nbytes, "ms_avg": avg, "source_hash": src_hash}
+    # whole operator apply, per D~ copy streamed: K6 + K4 + K7 + reduction averages
+    operator = {}
+    ham_avg = kern["ham_apply"]["ms_avg"]
+    red_avg = kern.get("reduce", {}).get("ms_avg") or 0.0
+    for tag, g6, g7, sDo in (("fp64", "gemv", "gemv_t", 8), ("fp32", "gemv_fp32", "gemv_t_fp32", 4)):
+        if g6 not in kern or g7 not in kern:
+            continue
+        apply_ms = kern[g6]["ms_avg"] + ham_avg + kern[g7]["ms_avg"] + red_avg
+        per_apply_bytes = 2 * ns * ncols * sDo + 6 * 8 * ns
+        operator[tag] = {"applies": kern[g6]["launches"], "ms_per_apply": apply_ms,
+                         "GBps": per_apply_bytes / (apply_ms * 1e-3) / 1e9,
+                         "frac_hbm": per_apply_bytes / (apply_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS,
+                         "stream_frac_hbm": (2 * ns * ncols * sDo) / ((kern[g6]["ms_avg"] + kern[g7]["ms_avg"]) * 1e-3)
+                         / 1e9 / HBM_PEAK_GBPS,
+                         "bytes_per_apply": per_apply_bytes}
+    operator["ham_ms_per_apply"] = ham_avg
+    operator["ham_candidates_per_s"] = ns * sysm.info.max_connections / (ham_avg * 1e-3)
+
+    fp64_ref = None
+    if precision == B.IRL_FP32 and args.fp64_reference:
+        # the same first step from theta0 on the FP32 path and on the FP64 path
+        def first_step(prec, fl, flags):
+            th = theta0.clone()
+            rc, r, _, _ = sysm.step(th, wl.V, wl.H, m=wl.m, k_keep=wl.k, tol=1e-12, precision=prec,
+                                    flags=flags, ws_flags=fl, want_dtheta=False)
+            return r
+        r32 = first_step(precision, ws_flags, step_flags & ~B.IRL_STEP_NO_EVAL_AFTER)
+        sysm.ws = None
+        torch.cuda.empty_cache()
+        t = time.perf_counter()
+        r64 = first_step(B.IRL_FP64, B.IRL_WS_FP64, 0)
+        ms64 = (time.perf_counter() - t) * 1e3
+        fp64_ref = {"ms_fp64_step": ms64, "applies_fp64": r64.n_apply,
+                    "lambda_fp64": r64.lambda_min, "E_after_fp64": r64.E_after,
+                    "dlambda": r32.lambda_min - r64.lambda_min, "dE_after": r32.E_after - r64.E_after}
+        log(f"fp64 reference step: {ms64:.1f} ms, dlambda {fp64_ref['dlambda']:.3e}, "
+            f"dE_after {fp64_ref['dE_after']:.3e}")
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -548,7 +581,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if precision == B.IRL_FP64 else "f32 operator / f64 solver",
+        "dtype": ("f64" if precision == B.IRL_FP64 else
+                  "f32 operator / f64 solver" + (" + f64 polish" if args.polish else "")),
         "data": "synthetic",
         "config": {"workload": (f"{wl.name}: {wl.n} orbitals {wl.na}a+{wl.nb}b "
                                 f"{'full space' if dets is None else 'selected set'} "
@@ -565,6 +599,7 @@ def main():
         "applies_per_step": applies / args.steps,
         "setup_ms": setup_ms,
         "stored_rows": store,
+        "fp64_reference": fp64_ref,
         "trajectory": steps,
         "E_final": Ef,
     }

@@ -330,13 +330,16 @@ int irl_batch_step(irl_batch *batch, const irl_solver_opts *opts, double *const 
 enum irl_stat_kind {
     IRL_STAT_DTILDE_BUILD = 0,   /* network forward + Jacobian rows written to D~ */
     IRL_STAT_HAM_APPLY = 1,      /* u = H w */
-    IRL_STAT_GEMV = 2,           /* w = D~ v */
-    IRL_STAT_GEMV_T = 3,         /* [ya, yb] = D~^T [a, b] (stream part) */
+    IRL_STAT_GEMV = 2,           /* w = D~ v (FP64 copy) */
+    IRL_STAT_GEMV_T = 3,         /* [ya, yb] = D~^T [a, b] (stream part, FP64 copy) */
     IRL_STAT_REDUCE = 4,         /* fixed-order reduction of the D~^T partial sums */
-    IRL_STAT_ENERGY = 5,         /* compensated Z and psi^T H psi reductions */
+    IRL_STAT_ENERGY = 5,         /* compensated Z and psi^T H psi reductions; the FP64
+                                    gradient recomputed from theta (FP32-only workspace) */
     IRL_STAT_LANCZOS = 6,        /* Lanczos recurrence + reorthogonalisation step */
     IRL_STAT_RITZ = 7,           /* Ritz pairs, restart shifts, basis compression, Ritz vector */
-    IRL_STAT_KINDS = 8
+    IRL_STAT_GEMV_LO = 8,        /* w = D~ v on the FP32 copy (IRL_STAT_GEMV: FP64 copy) */
+    IRL_STAT_GEMV_T_LO = 9,      /* D~^T stream on the FP32 copy (IRL_STAT_GEMV_T: FP64 copy) */
+    IRL_STAT_KINDS = 10
 };
 
 /* on != 0: from now on every kernel launch of this handle is bracketed by a

@@ -30,7 +30,8 @@ IRL_STEP_WS_CURRENT, IRL_STEP_NO_EVAL_AFTER, IRL_STEP_NO_UPDATE, IRL_STEP_NO_POL
 IRL_STEP_FULL_CYCLES = 16
 IRL_SYS_FORCE_HASH = 1
 IRL_SYS_FORCE_PULL = 2
-STAT_KINDS = ("dtilde_build", "ham_apply", "gemv", "gemv_t", "reduce", "energy", "lanczos", "ritz")
+STAT_KINDS = ("dtilde_build", "ham_apply", "gemv", "gemv_t", "reduce", "energy", "lanczos", "ritz",
+              "gemv_fp32", "gemv_t_fp32")
 
 STATUS_NAMES = {0: "IRL_OK", 1: "IRL_ENOTCONV", 2: "IRL_ESTEP", -1: "IRL_EINVAL",
                 -2: "IRL_ENOMEM", -3: "IRL_EDEVICE", -4: "IRL_ESTATE"}

@@ -151,20 +151,41 @@ int stat_end(irl_system *s, hipStream_t st)
         if (rc_) return rc_;                           \
     } while (0)
 
-// Z, E and the gradient from psi (and D~ in ws): H psi -> reductions -> D~^T (H psi - E psi)
-int energy_and_gradient(irl_system *s, void *ws, const WsLayout &L, hipStream_t st)
+// row blocks of the D~^T stream launch (and of the partial rows it leaves)
+int t2_blocks(int64_t ns, int64_t ld, int prec)
+{
+    const int64_t nch = ld / (prec == IRL_FP64 ? 2 : 4);
+    const int ntiles = (int)((nch + 64 * 16 - 1) / (64 * 16));
+    int nblk = kStreamBlocks / ntiles;
+    if (nblk < 1) nblk = 1;
+    if (nblk > (ns + 3) / 4) nblk = (int)((ns + 3) / 4);
+    return nblk;
+}
+
+// Z, E and the gradient from psi: H psi -> reductions -> grad_full = 2 D~^T (H psi - E psi) / Z.
+// With an FP64 copy of D~ the gradient streams it (and leaves D~^T psi in y as a
+// diagnostic); without one, and with the network at hand (nqs), it is recomputed
+// from theta in FP64; only a caller-set FP32 D~ falls back to the FP32 stream.
+int energy_and_gradient(irl_system *s, void *ws, const WsLayout &L, hipStream_t st,
+                        const irl_nqs_desc *nqs = nullptr)
 {
     double *psi = ws_ptr<double>(ws, L.off_psi), *hpsi = ws_ptr<double>(ws, L.off_hpsi);
     TIMED(s, IRL_STAT_HAM_APPLY, st, launch_ham_apply(s, psi, hpsi, st));
     TIMED(s, IRL_STAT_ENERGY, st, launch_energy_reduce(L, ws, st));
     WsScalars *sc = ws_ptr<WsScalars>(ws, L.off_scal);
     const int prec = (L.flags & IRL_WS_FP64) ? IRL_FP64 : IRL_FP32;
-    // y = D~^T psi (diagnostic), grad_full = 2 D~^T (H psi - E psi) / Z
     int nblk = 1;
-    TIMED(s, IRL_STAT_GEMV_T, st, launch_gemv_t2(L, ws, prec, psi, hpsi, psi, &sc->E_el, &nblk, st));
-    TIMED(s, IRL_STAT_REDUCE, st, launch_t2_reduce(L, ws, nblk, ws_ptr<double>(ws, L.off_y),
-                                                   ws_ptr<double>(ws, L.off_grad), L.ncols, 2.0,
-                                                   &sc->Z, st));
+    double *y = ws_ptr<double>(ws, L.off_y);
+    if (prec == IRL_FP32 && nqs) {
+        nblk = t2_blocks(L.ns, L.ld32, IRL_FP32);
+        TIMED(s, IRL_STAT_ENERGY, st, launch_nqs_grad(s, nqs->V, nqs->H, nqs->theta, L, ws, nblk, st));
+        y = nullptr;
+    } else {
+        TIMED(s, prec == IRL_FP64 ? IRL_STAT_GEMV_T : IRL_STAT_GEMV_T_LO, st,
+              launch_gemv_t2(L, ws, prec, psi, hpsi, psi, &sc->E_el, &nblk, st));
+    }
+    TIMED(s, IRL_STAT_REDUCE, st, launch_t2_reduce(L, ws, nblk, y, ws_ptr<double>(ws, L.off_grad),
+                                                   L.ncols, 2.0, &sc->Z, st));
     int rc = read_scalars(s, ws, L, st);
     if (rc) return rc;
     s->Z = s->host_scal->Z;
@@ -179,10 +200,10 @@ int apply_internal(irl_system *s, void *ws, const WsLayout &L, const double *v, 
                    double *yS, int prec, hipStream_t st, int zero_v0 = 0)
 {
     double *w = ws_ptr<double>(ws, L.off_w), *u = ws_ptr<double>(ws, L.off_u);
-    TIMED(s, IRL_STAT_GEMV, st, launch_gemv_rows(L, ws, prec, v, w, zero_v0, st));
+    TIMED(s, prec == IRL_FP64 ? IRL_STAT_GEMV : IRL_STAT_GEMV_LO, st, launch_gemv_rows(L, ws, prec, v, w, zero_v0, st));
     TIMED(s, IRL_STAT_HAM_APPLY, st, launch_ham_apply(s, w, u, st));
     int nblk = 1;
-    TIMED(s, IRL_STAT_GEMV_T, st, launch_gemv_t2(L, ws, prec, w, u, nullptr, nullptr, &nblk, st));
+    TIMED(s, prec == IRL_FP64 ? IRL_STAT_GEMV_T : IRL_STAT_GEMV_T_LO, st, launch_gemv_t2(L, ws, prec, w, u, nullptr, nullptr, &nblk, st));
     TIMED(s, IRL_STAT_REDUCE, st, launch_t2_reduce(L, ws, nblk, yS, yH, L.ncols, 1.0, nullptr, st));
     return IRL_OK;
 }
@@ -633,7 +654,7 @@ int irl_nqs_evaluate(irl_system *s, const irl_nqs_desc *nqs, void *ws, size_t ws
     if (rc) return rc;
     s->ws_valid = false;
     TIMED(s, IRL_STAT_DTILDE_BUILD, st, launch_nqs_dtilde(s, nqs->V, nqs->H, nqs->theta, L, ws, st));
-    rc = energy_and_gradient(s, ws, L, st);
+    rc = energy_and_gradient(s, ws, L, st, nqs);
     if (rc) return rc;
     s->ws = ws;
     s->lay = L;
@@ -735,10 +756,9 @@ int irl_step(irl_system *s, irl_nqs_desc *nqs, const irl_solver_opts *opts, void
     SolveOut so;
     rc = irl_solve(s, ws, L, o, o.precision, nullptr, so, st);
     if (rc) return rc;
-    int n_apply_lo = 0;
+    const int n_apply_lo = o.precision == IRL_FP32 ? so.n_apply : 0;
     if (o.precision == IRL_FP32 && s->ws_has64 && !(o.flags & IRL_STEP_NO_POLISH)) {
         // FP64 polish from the reduced-precision Ritz vector
-        n_apply_lo = so.n_apply;
         SolveOut sp;
         rc = irl_solve(s, ws, L, o, IRL_FP64, ws_ptr<double>(ws, L.off_y), sp, st);
         if (rc) return rc;
@@ -985,16 +1005,6 @@ struct ListSet {
     const WorkItem *ptr(const irl_batch *b, int kind) const { return b->ditems[region] + off[kind]; }
 };
 
-int t2_blocks(int64_t ns, int64_t ld, int prec)   // row blocks of the solo D~^T launch
-{
-    const int64_t nch = ld / (prec == IRL_FP64 ? 2 : 4);
-    const int ntiles = (int)((nch + 64 * 16 - 1) / (64 * 16));
-    int nblk = kStreamBlocks / ntiles;
-    if (nblk < 1) nblk = 1;
-    if (nblk > (ns + 3) / 4) nblk = (int)((ns + 3) / 4);
-    return nblk;
-}
-
 int energy_parts(int64_t ns)
 {
     return ns < (int64_t)kScalarParts * 256 ? (int)((ns + 255) / 256) : kScalarParts;
@@ -1134,7 +1144,7 @@ int batch_apply(irl_batch *b, const ListSet &ls, int vsel, int j, int cur, int s
                 hipStream_t st)
 {
     irl_system *s0 = b->sys[0];
-    TIMED(s0, IRL_STAT_GEMV, st, launch_gemv_rows_grouped(b->dm, ls.ptr(b, LS_ROWS6), ls.cnt[LS_ROWS6], prec, vsel, j, cur,
+    TIMED(s0, prec == IRL_FP64 ? IRL_STAT_GEMV : IRL_STAT_GEMV_LO, st, launch_gemv_rows_grouped(b->dm, ls.ptr(b, LS_ROWS6), ls.cnt[LS_ROWS6], prec, vsel, j, cur,
                                     split, ls.lds6, st));
     for (int k : {LS_ROWS4R, LS_ROWS4H, LS_ROWS4B})
         if (ls.cnt[k])
@@ -1144,7 +1154,7 @@ int batch_apply(irl_batch *b, const ListSet &ls, int vsel, int j, int cur, int s
     if (ls.cnt[LS_ROWS4S])
         TIMED(s0, IRL_STAT_HAM_APPLY, st, launch_ham_stored_grouped(b->dm, ls.ptr(b, LS_ROWS4S), ls.cnt[LS_ROWS4S], ls.blocks[LS_ROWS4S], 0, st));
     for (int m : ls.product) TIMED(s0, IRL_STAT_HAM_APPLY, st, launch_ham_apply(b->sys[m], b->hm[m].w, b->hm[m].u, st));
-    TIMED(s0, IRL_STAT_GEMV_T, st, launch_gemv_t2_grouped(b->dm, ls.ptr(b, LS_T2), ls.cnt[LS_T2], prec, 0, st));
+    TIMED(s0, prec == IRL_FP64 ? IRL_STAT_GEMV_T : IRL_STAT_GEMV_T_LO, st, launch_gemv_t2_grouped(b->dm, ls.ptr(b, LS_T2), ls.cnt[LS_T2], prec, 0, st));
     TIMED(s0, IRL_STAT_REDUCE, st, launch_reduce_grouped(b->dm, ls.ptr(b, LS_RED), ls.cnt[LS_RED], 0, st));
     return IRL_OK;
 }
@@ -1183,8 +1193,21 @@ int batch_evaluate(irl_batch *b, const std::vector<int> &subset, hipStream_t st)
     for (int m : ls.product) TIMED(s0, IRL_STAT_HAM_APPLY, st, launch_ham_apply(b->sys[m], b->hm[m].psi, b->hm[m].hpsi, st));
     TIMED(s0, IRL_STAT_ENERGY, st, launch_energy_grouped(b->dm, ls.ptr(b, LS_E1), ls.cnt[LS_E1], 1, st));
     TIMED(s0, IRL_STAT_ENERGY, st, launch_energy_grouped(b->dm, ls.ptr(b, LS_VEC), ls.cnt[LS_VEC], 2, st));
-    TIMED(s0, IRL_STAT_GEMV_T, st, launch_gemv_t2_grouped(b->dm, ls.ptr(b, LS_T2), ls.cnt[LS_T2], prec, 1, st));
-    TIMED(s0, IRL_STAT_REDUCE, st, launch_reduce_grouped(b->dm, ls.ptr(b, LS_RED), ls.cnt[LS_RED], 1, st));
+    if (prec == IRL_FP64) {
+        TIMED(s0, IRL_STAT_GEMV_T, st, launch_gemv_t2_grouped(b->dm, ls.ptr(b, LS_T2), ls.cnt[LS_T2], prec, 1, st));
+        TIMED(s0, IRL_STAT_REDUCE, st, launch_reduce_grouped(b->dm, ls.ptr(b, LS_RED), ls.cnt[LS_RED], 1, st));
+    } else {
+        // no FP64 copy: each member's FP64 gradient is recomputed from its theta (solo launches)
+        for (int m : subset) {
+            const WsLayout &L = b->lay[m];
+            const int nblk = t2_blocks(L.ns, L.ld32, IRL_FP32);
+            TIMED(s0, IRL_STAT_ENERGY, st, launch_nqs_grad(b->sys[m], b->nqs[m].V, b->nqs[m].H, b->nqs[m].theta,
+                                                            L, b->ws[m], nblk, st));
+            TIMED(s0, IRL_STAT_REDUCE, st,
+                  launch_t2_reduce(L, b->ws[m], nblk, nullptr, ws_ptr<double>(b->ws[m], L.off_grad), L.ncols,
+                                   2.0, &ws_ptr<WsScalars>(b->ws[m], L.off_scal)->Z, st));
+        }
+    }
     rc = gather(b, ls, st);
     if (rc) return rc;
     for (int m : subset) {
@@ -1473,12 +1496,13 @@ int irl_batch_step(irl_batch *b, const irl_solver_opts *opts, double *const *dth
     rc = batch_solve(b, o, o.precision, false, ms, st);
     if (rc) return rc;
     std::vector<int> lo(B, 0);
+    if (o.precision == IRL_FP32)
+        for (int i = 0; i < B; ++i) lo[i] = ms[i].n_apply;
     if (o.precision == IRL_FP32 && (b->ws_flags & IRL_WS_FP64) && !(o.flags & IRL_STEP_NO_POLISH)) {
         std::vector<MemberSolve> mp;
         rc = batch_solve(b, o, IRL_FP64, true, mp, st);
         if (rc) return rc;
         for (int i = 0; i < B; ++i) {
-            lo[i] = ms[i].n_apply;
             mp[i].n_apply += ms[i].n_apply;
             mp[i].n_restart += ms[i].n_restart;
         }

@@ -216,6 +216,9 @@ hipError_t launch_ham_row_list(const irl_system *s, int64_t row, int32_t *tgt, i
                                hipStream_t st);
 
 // nqs.hip
+// FP64 D~^T (H psi - E psi) recomputed from theta into the D~^T partial rows (nblk row blocks)
+hipError_t launch_nqs_grad(const irl_system *s, int V, int H, const double *theta, const WsLayout &L,
+                           void *ws, int nblk, hipStream_t st);
 hipError_t launch_nqs_dtilde(const irl_system *s, int V, int H, const double *theta,
                              const WsLayout &L, void *ws, hipStream_t st);
 hipError_t launch_dtilde_import(const void *D, int64_t ld, int64_t ncols, int dtype,

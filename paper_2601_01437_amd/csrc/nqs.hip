@@ -137,6 +137,129 @@ hipError_t launch_nqs_dtilde(const irl_system *s, int V, int H, const double *th
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// FP64 gradient without an FP64 copy of D~ (Methods, "From SR to a Stable
+// Eigenvalue Problem": the energy gradient is the Jacobian transposed applied to
+// the local-energy residual).  With c_x = (H psi)_x - E psi_x, the entries of
+// D~^T c are, per column block of D~:
+//   psi column:   sum_x c_x psi_x
+//   a_v:          sum_x c_x x_v
+//   b_h:          sum_x c_x (1 - t_xh^2)
+//   W_hv:         sum_x c_x (1 - t_xh^2) x_v
+// recomputed from theta in FP64 (the network pass costs far less than a D~
+// stream).  Grid (hidden tiles of 64, row blocks): lane = hidden unit of the
+// tile, W rows of the tile in LDS; every row's occupation mask is uniform over
+// the wave, so the W_h. accumulators are updated with a static loop over v.
+// The 4 waves are combined in a fixed order and wave 0 writes the block's
+// partial row into the second half of part (the first half is zeroed), the
+// layout the two-level D~^T reduction reads.
+constexpr int kGradVmax = 64;
+
+__device__ __forceinline__ void nqs_grad_block(const uint64_t *__restrict__ keys, int64_t r0,
+                                               int64_t r1, int n, int V, int H, int ht,
+                                               const double *__restrict__ theta,
+                                               const double *__restrict__ psi,
+                                               const double *__restrict__ hpsi, double E,
+                                               double *__restrict__ pa, double *__restrict__ pb,
+                                               int64_t ldv, double *Wt, double *red)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int h = ht * 64 + lane;
+    const bool hv = h < H;
+    const double *b = theta + V, *W = theta + V + H;
+    constexpr int kWs = kGradVmax + 1;   // odd LDS row stride: lanes read distinct banks
+    for (int i = threadIdx.x; i < 64 * kWs; i += blockDim.x) {
+        const int hh = i / kWs, v = i - hh * kWs;
+        Wt[i] = (v < V && ht * 64 + hh < H) ? W[(size_t)(ht * 64 + hh) * V + v] : 0.0;
+    }
+    __syncthreads();
+    const double bh = hv ? b[h] : 0.0;
+    double accW[kGradVmax];
+#pragma unroll
+    for (int v = 0; v < kGradVmax; ++v) accW[v] = 0.0;
+    double accB = 0.0, accA = 0.0, acc0 = 0.0;
+    for (int64_t r = r0 + wv; r < r1; r += 4) {
+        const uint64_t key = keys[r];
+        const uint64_t xm = (key & 0xffffffffull) | ((key >> 32) << n);
+        const double c = hpsi[r] - E * psi[r];
+        double z = bh;
+        for (uint64_t m = xm; m; m &= m - 1) z += Wt[lane * kWs + (__ffsll((unsigned long long)m) - 1)];
+        const double t = tanh(z);
+        const double d = c * (1.0 - t * t);
+        accB += d;
+#pragma unroll
+        for (int v = 0; v < kGradVmax; ++v) accW[v] += ((xm >> v) & 1ull) ? d : 0.0;
+        if (ht == 0) {
+            accA += ((xm >> lane) & 1ull) ? c : 0.0;
+            acc0 += c * psi[r];
+        }
+    }
+    // fixed-order combination of the 4 waves: ((w0 + w1) + w2) + w3
+    constexpr int kRs = kGradVmax + 3;
+    for (int src = 1; src < 4; ++src) {
+        __syncthreads();
+        if (wv == src) {
+#pragma unroll
+            for (int v = 0; v < kGradVmax; ++v) red[lane * kRs + v] = accW[v];
+            red[lane * kRs + kGradVmax] = accB;
+            red[lane * kRs + kGradVmax + 1] = accA;
+            red[lane * kRs + kGradVmax + 2] = acc0;
+        }
+        __syncthreads();
+        if (wv == 0) {
+#pragma unroll
+            for (int v = 0; v < kGradVmax; ++v) accW[v] += red[lane * kRs + v];
+            accB += red[lane * kRs + kGradVmax];
+            accA += red[lane * kRs + kGradVmax + 1];
+            acc0 += red[lane * kRs + kGradVmax + 2];
+        }
+    }
+    if (ht == 0)   // the first half of the partial row (D~^T psi) is not formed here
+        for (int64_t c = threadIdx.x; c < ldv; c += blockDim.x) pa[c] = 0.0;
+    if (wv != 0) return;
+    const int64_t P1 = (int64_t)V * H + H + V + 1;
+    if (hv) {
+        pb[1 + V + h] = accB;
+#pragma unroll
+        for (int v = 0; v < kGradVmax; ++v)
+            if (v < V) pb[1 + V + H + (int64_t)h * V + v] = accW[v];
+    }
+    if (ht == 0) {
+        if (lane < V) pb[1 + lane] = accA;
+        if (lane == 0) pb[0] = acc0;
+        for (int64_t c = P1 + lane; c < ldv; c += 64) pb[c] = 0.0;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_nqs_grad(const uint64_t *__restrict__ keys, int64_t ns, int n,
+                                                  int V, int H, const double *__restrict__ theta,
+                                                  const double *__restrict__ psi,
+                                                  const double *__restrict__ hpsi,
+                                                  const WsScalars *__restrict__ sc,
+                                                  double *__restrict__ part, int64_t ldv, int nblk)
+{
+    __shared__ double Wt[64 * (kGradVmax + 1)];
+    __shared__ double red[64 * (kGradVmax + 3)];
+    const int ht = blockIdx.x, rb = blockIdx.y;
+    const int64_t per = (ns + nblk - 1) / nblk;
+    const int64_t r0 = (int64_t)rb * per, r1 = min(ns, r0 + per);
+    double *pa = part + (int64_t)rb * 2 * ldv;
+    nqs_grad_block(keys, r0, r1, n, V, H, ht, theta, psi, hpsi, sc->E_el, pa, pa + ldv, ldv, Wt, red);
+}
+
+hipError_t launch_nqs_grad(const irl_system *s, int V, int H, const double *theta, const WsLayout &L,
+                           void *ws, int nblk, hipStream_t st)
+{
+    if (V > kGradVmax) return hipErrorInvalidValue;
+    const int htiles = (H + 63) / 64;
+    k_nqs_grad<<<dim3(htiles, nblk), 256, 0, st>>>(s->d.keys, L.ns, s->n, V, H, theta,
+                                                   ws_ptr<double>(ws, L.off_psi),
+                                                   ws_ptr<double>(ws, L.off_hpsi),
+                                                   ws_ptr<WsScalars>(ws, L.off_scal),
+                                                   ws_ptr<double>(ws, L.off_part), L.ldv, nblk);
+    return hipGetLastError();
+}
+
 // Copy a caller-provided D~ into the workspace copies (zero padding), and
 // column 0 into psi.
 template <typename TS>

@@ -123,3 +123,25 @@ def test_batch_three_steps_equal_solo():
             got[i].append((r.E_before, r.E_after, r.lambda_min))
     assert got == ref
     bt.close()
+
+
+def test_batch_fp32_only_equals_solo_bitwise():
+    """FP32 copy of D~ only (FP32 products, gradient recomputed from theta in
+    FP64): batched members equal their solo steps bit for bit."""
+    from paper_2601_01437_amd import IRL_FP32, IRL_WS_FP32, Batch
+    announce("batch fp32-only vs solo")
+    solo = _build(0)
+    ref = []
+    for s, theta, V, H, *_ in solo:
+        th = dev(theta)
+        rc, r, dth, _ = s.step(th, V, H, m=20, k_keep=1, precision=IRL_FP32, ws_flags=IRL_WS_FP32)
+        ref.append((rc, r, host(dth)))
+    mem = _build(0)
+    thetas = [dev(t) for _, t, *_ in mem]
+    bt = Batch([x[0] for x in mem], thetas, [x[2] for x in mem], [x[3] for x in mem], ws_flags=IRL_WS_FP32)
+    res, status, dth = bt.step(m=20, k_keep=1, precision=IRL_FP32, want_dtheta=True)
+    for i, (rc, r, d_ref) in enumerate(ref):
+        assert status[i] == rc, i
+        assert _fields(res[i]) == _fields(r), (i, _fields(res[i]), _fields(r))
+        assert np.array_equal(host(dth[i]), d_ref), i
+    bt.close()

@@ -99,16 +99,38 @@ def _oracle_eval(p):
     return Dt, Z, E, g
 
 
-def test_evaluate_c1(c1_problem):
-    announce("evaluate c1")
+@pytest.mark.parametrize("fp32_only", [False, True])
+def test_evaluate_c1(c1_problem, fp32_only):
+    """Energy and gradient in FP64: streamed from the FP64 copy of D~, or, with
+    only an FP32 copy, recomputed from theta (same FP64 tolerance)."""
+    from paper_2601_01437_amd import IRL_WS_FP32, IRL_WS_FP64
+    announce(f"evaluate c1 fp32_only={fp32_only}")
     p = c1_problem
     w = p["w"]
     Dt, Z, E, g = _oracle_eval(p)
     s, _, _ = make_system(8, 4, 4)
-    Zg, Eg, grad = s.evaluate(w.V, w.H, dev(p["theta"]))
+    Zg, Eg, grad = s.evaluate(w.V, w.H, dev(p["theta"]),
+                              ws_flags=IRL_WS_FP32 if fp32_only else IRL_WS_FP64)
     assert abs(Zg - Z) <= 1e-12 * Z
     assert abs(Eg - E) <= 1e-12
     assert rel_err(host(grad), g) <= 1e-10
+
+
+@pytest.mark.parametrize("n,na,nb,V,H,count", [(12, 6, 6, 24, 100, 20000), (32, 3, 2, 64, 70, 3000),
+                                               (20, 10, 10, 40, 256, 1 << 14)])
+def test_gradient_from_theta_matches_fp64_stream(n, na, nb, V, H, count):
+    """The FP64 gradient recomputed from theta equals the one streamed from the
+    FP64 copy of D~ to rounding, over hidden-tile and row-block shapes
+    (H not a multiple of 64, V = 64, several row blocks)."""
+    from paper_2601_01437_amd import IRL_WS_FP32, IRL_WS_FP64
+    announce(f"gradient from theta n={n} H={H} count={count}")
+    keys = synth.cisd_like_selected_set(n, na, nb, count, seed=3)
+    s, h, g = make_system(n, na, nb, seed=3, dets=keys)
+    theta = dev(synth.nqs_theta(V, H, 3, scale=0.2))
+    Z64, E64, g64 = s.evaluate(V, H, theta, ws_flags=IRL_WS_FP64)
+    Z32, E32, g32 = s.evaluate(V, H, theta, ws_flags=IRL_WS_FP32)
+    assert Z32 == Z64 and E32 == E64         # psi and H psi are FP64 in both layouts
+    assert rel_err(host(g32), host(g64)) <= 1e-12
 
 
 @pytest.mark.parametrize("flags", [0, 1, 2])

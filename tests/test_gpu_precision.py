@@ -135,3 +135,25 @@ def test_c3s_fp32_step(c3s_golden, polish):
     else:
         assert dlam <= 1e-5 * G["norm_Hp"]
         assert dE <= 1e-5 * max(1.0, abs(G["E_after"]))
+
+
+def test_c3s_fp32_only_workspace(c3s_golden):
+    """FP32 copy of D~ only: energy and gradient stay FP64 (the gradient is
+    recomputed from theta), the solve runs on FP32 products without polish."""
+    from paper_2601_01437_amd import IRL_FP32, IRL_STEP_NO_POLISH, IRL_WS_FP32
+    announce("c3s fp32-only workspace")
+    G = c3s_golden
+    w, s = _c3s_system()
+    theta = dev(w.theta())
+    Z, E, grad = s.evaluate(w.V, w.H, theta, ws_flags=IRL_WS_FP32)
+    assert abs(E - G["E"]) <= 1e-12
+    assert abs(np.linalg.norm(host(grad)) - G["grad_norm"]) <= 1e-10 * G["grad_norm"]
+    assert rel_err(host(grad)[:32], np.array(G["grad_head"])) <= 1e-10
+    rc, r, dth, _ = s.step(theta, w.V, w.H, m=w.m, k_keep=w.k, precision=IRL_FP32,
+                           ws_flags=IRL_WS_FP32, flags=IRL_STEP_NO_POLISH)
+    assert r.converged == 1 and r.n_apply_lo == r.n_apply
+    dlam = abs(r.lambda_min - G["lambda_min"])
+    dE = abs(r.E_after - G["E_after"])
+    announce(f"c3s fp32-only: |dlambda|={dlam:.3e} |dE_after|={dE:.3e} applies={r.n_apply}")
+    assert dlam <= 1e-5 * G["norm_Hp"]
+    assert dE <= 1e-5 * max(1.0, abs(G["E_after"]))
