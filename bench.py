@@ -398,6 +398,8 @@ def main():
     ap.add_argument("--precision", default=None, choices=["fp64", "fp32"],
                     help="operator precision (default: the workload's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--block", type=int, default=0,
+                    help="vectors per operator pass: 0/1 implicitly restarted Lanczos, 2..8 block Lanczos")
     ap.add_argument("--polish", action="store_true",
                     help="FP32 operator: keep an FP64 copy of D~ and refine the Ritz pair in FP64")
     ap.add_argument("--no-fp64-reference", dest="fp64_reference", action="store_false",
@@ -461,6 +463,8 @@ def main():
     else:
         ws_flags = B.IRL_WS_FP32 | (B.IRL_WS_FP64 if args.polish else 0)
     step_flags = B.IRL_STEP_NO_EVAL_AFTER | (0 if args.polish else B.IRL_STEP_NO_POLISH)
+    if args.block > 1:
+        ws_flags |= B.IRL_WS_BLOCK
     sysm.workspace(wl.P + 1, ws_flags)
     log(f"workspace {sysm.ws.numel() / 2**30:.2f} GiB")
     store = None
@@ -474,7 +478,7 @@ def main():
     def one_step():
         rc, r, _, _ = sysm.step(theta, wl.V, wl.H, m=wl.m, k_keep=wl.k, tol=1e-12,
                                 precision=precision, flags=step_flags,
-                                ws_flags=ws_flags, want_dtheta=False)
+                                ws_flags=ws_flags, want_dtheta=False, block=args.block)
         return rc, r
 
     for i in range(args.warmup):
@@ -548,13 +552,13 @@ def main():
         def first_step(prec, fl, flags):
             th = theta0.clone()
             rc, r, _, _ = sysm.step(th, wl.V, wl.H, m=wl.m, k_keep=wl.k, tol=1e-12, precision=prec,
-                                    flags=flags, ws_flags=fl, want_dtheta=False)
+                                    flags=flags, ws_flags=fl, want_dtheta=False, block=args.block)
             return r
         r32 = first_step(precision, ws_flags, step_flags & ~B.IRL_STEP_NO_EVAL_AFTER)
         sysm.ws = None
         torch.cuda.empty_cache()
         t = time.perf_counter()
-        r64 = first_step(B.IRL_FP64, B.IRL_WS_FP64, 0)
+        r64 = first_step(B.IRL_FP64, B.IRL_WS_FP64 | (ws_flags & B.IRL_WS_BLOCK), 0)
         ms64 = (time.perf_counter() - t) * 1e3
         fp64_ref = {"ms_fp64_step": ms64, "applies_fp64": r64.n_apply,
                     "lambda_fp64": r64.lambda_min, "E_after_fp64": r64.E_after,
@@ -589,8 +593,9 @@ def main():
                                 f"({ns} determinants), random molecule-like integrals seed {wl.seed}, "
                                 f"one-hidden-layer tanh network V={wl.V} H={wl.H} (P={wl.P}), "
                                 f"D~ {ns}x{ncols} {prec_name.upper()}, IRL m={wl.m} k_keep={wl.k} "
-                                f"tol=1e-12"),
-                   "n_dets": ns, "P": wl.P, "m": wl.m, "k_keep": wl.k,
+                                f"tol=1e-12" + (f", block Lanczos with {args.block} vectors per pass"
+                                                if args.block > 1 else "")),
+                   "n_dets": ns, "P": wl.P, "m": wl.m, "k_keep": wl.k, "block": args.block,
                    "ham_kernel": HAM_KERNELS[sysm.info.ham_kernel]},
         "roofline": roof,
         "cpu_baseline": cpu,

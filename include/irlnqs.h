@@ -73,7 +73,10 @@ enum irl_mode { IRL_MODE_A = 0, IRL_MODE_P = 1 };
 /* workspace flags (irl_workspace_query) */
 enum irl_ws_flags {
     IRL_WS_FP64 = 1u,   /* hold an FP64 copy of D~ (required for IRL_FP64 applies) */
-    IRL_WS_FP32 = 2u    /* hold an FP32 copy of D~ (required for IRL_FP32 applies) */
+    IRL_WS_FP32 = 2u,   /* hold an FP32 copy of D~ (required for IRL_FP32 applies) */
+    IRL_WS_BLOCK = 4u   /* room for multi-vector applies and block solves of up to 8
+                           vectors (8 vectors of n_dets for w and u, 8 of P+1 for the
+                           outputs and larger reduction partials) */
 };
 
 /* irl_step flags */
@@ -145,6 +148,10 @@ typedef struct {
     int32_t mode;           /* irl_mode */
     uint64_t seed;          /* start vector: splitmix64(seed, index) -> U(-1, 1) */
     uint32_t flags;         /* irl_step_flags */
+    int32_t block;          /* 0 or 1: implicitly restarted Lanczos (Algorithm 1); 2..8:
+                               thick-restart block Lanczos with this many vectors per
+                               operator pass (needs IRL_WS_BLOCK; m counts basis columns,
+                               2 * block <= m <= 64, k_keep <= m - block) */
 } irl_solver_opts;
 
 typedef struct {
@@ -256,6 +263,21 @@ int irl_dtilde_set(irl_system *sys, const void *D, int64_t ld, int64_t ncols, in
 int irl_apply_lm_operator(irl_system *sys, void *ws, size_t ws_bytes, const double *v,
                           double *yH, double *yS, int32_t precision, void *stream);
 
+/* The LM operator on nb <= 8 vectors with one pass over D~ per direction (the
+ * multi-vector form behind block Lanczos, which the paper names as its next
+ * step in the Discussion):  for q < nb,
+ *     YH[:, q] = D~^T H D~ V[:, q],   YS[:, q] = D~^T D~ V[:, q]   (raw, as above).
+ * V: device, nb columns of ncols = P + 1 doubles, column q at V + q * ldv
+ * (ldv >= ncols).  YH, YS: device, nb columns at stride ldy >= ncols (entries
+ * >= ncols are not written).  Needs a workspace evaluated with IRL_WS_BLOCK.
+ * Bytes per call are those of one vector; each column equals
+ * irl_apply_lm_operator on that column to rounding (the D~^T partial sums use
+ * other row blocks).  Asynchronous on stream.  Errors: IRL_ESTATE, IRL_EINVAL,
+ * IRL_ENOMEM, IRL_EDEVICE. */
+int irl_apply_lm_operator_block(irl_system *sys, void *ws, size_t ws_bytes, const double *V, int64_t ldv,
+                                int32_t nb, double *YH, double *YS, int64_t ldy, int32_t precision,
+                                void *stream);
+
 /* u = H w on the determinant set (device vectors of n_dets doubles). */
 int irl_apply_hamiltonian(irl_system *sys, const double *w, double *u, void *stream);
 
@@ -289,7 +311,7 @@ int irl_step(irl_system *sys, irl_nqs_desc *nqs, const irl_solver_opts *opts, vo
              irl_step_result *r, void *stream);
 
 /* Default solver options (m 20, k_keep 1, tol 1e-12, max_restarts 300, FP64,
- * mode A, seed 0, flags 0). */
+ * mode A, seed 0, flags 0, block 0). */
 void irl_solver_opts_default(irl_solver_opts *o);
 
 /* ---- batches of independent solves ------------------------------------- */

@@ -25,7 +25,7 @@ IRL_OK, IRL_ENOTCONV, IRL_ESTEP = 0, 1, 2
 IRL_EINVAL, IRL_ENOMEM, IRL_EDEVICE, IRL_ESTATE = -1, -2, -3, -4
 IRL_FP64, IRL_FP32 = 0, 1
 IRL_MODE_A, IRL_MODE_P = 0, 1
-IRL_WS_FP64, IRL_WS_FP32 = 1, 2
+IRL_WS_FP64, IRL_WS_FP32, IRL_WS_BLOCK = 1, 2, 4
 IRL_STEP_WS_CURRENT, IRL_STEP_NO_EVAL_AFTER, IRL_STEP_NO_UPDATE, IRL_STEP_NO_POLISH = 1, 2, 4, 8
 IRL_STEP_FULL_CYCLES = 16
 IRL_SYS_FORCE_HASH = 1
@@ -67,7 +67,7 @@ class irl_eval_out(ctypes.Structure):
 class irl_solver_opts(ctypes.Structure):
     _fields_ = [("m", c_int32), ("k_keep", c_int32), ("tol", c_double),
                 ("max_restarts", c_int32), ("precision", c_int32), ("mode", c_int32),
-                ("seed", c_uint64), ("flags", c_uint32)]
+                ("seed", c_uint64), ("flags", c_uint32), ("block", c_int32)]
 
 
 class irl_step_result(ctypes.Structure):
@@ -96,6 +96,8 @@ _sigs = {
                                  c_uint32, c_void_p]),
     "irl_apply_lm_operator": (c_int32, [_SYS, c_void_p, c_size_t, c_void_p, c_void_p, c_void_p,
                                         c_int32, c_void_p]),
+    "irl_apply_lm_operator_block": (c_int32, [_SYS, c_void_p, c_size_t, c_void_p, c_int64, c_int32,
+                                              c_void_p, c_void_p, c_int64, c_int32, c_void_p]),
     "irl_apply_hamiltonian": (c_int32, [_SYS, c_void_p, c_void_p, c_void_p]),
     "irl_step": (c_int32, [_SYS, POINTER(irl_nqs_desc), POINTER(irl_solver_opts), c_void_p,
                            c_size_t, c_uint32, c_void_p, c_void_p, POINTER(irl_step_result),
@@ -210,6 +212,15 @@ def irl_dtilde_set(sys, D, ws, ws_flags, stream=None):
 def irl_apply_lm_operator(sys, ws, v, yH, yS, precision=IRL_FP64, stream=None):
     _check(_lib.irl_apply_lm_operator(sys, _ptr(ws), ws.numel() * ws.element_size(), _ptr(v),
                                       _ptr(yH), _ptr(yS), precision, _stream(stream)), sys)
+
+
+def irl_apply_lm_operator_block(sys, ws, V, YH, YS, precision=IRL_FP64, stream=None):
+    """V, YH, YS: device float64 tensors of shape (nb, ldv) / (nb, ldy), one vector per row."""
+    nb = V.shape[0]
+    assert V.stride(1) == 1 and YH.stride(1) == 1 and YS.stride(1) == 1 and YH.stride(0) == YS.stride(0)
+    _check(_lib.irl_apply_lm_operator_block(sys, _ptr(ws), ws.numel() * ws.element_size(), _ptr(V), V.stride(0),
+                                            nb, _ptr(YH), _ptr(YS), YH.stride(0), precision, _stream(stream)),
+           sys)
 
 
 def irl_apply_hamiltonian(sys, w, u, stream=None):

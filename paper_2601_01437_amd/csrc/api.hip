@@ -208,6 +208,23 @@ int apply_internal(irl_system *s, void *ws, const WsLayout &L, const double *v, 
     return IRL_OK;
 }
 
+// nb operator pairs at once: W = D~ V (one D~ pass), U_q = H W_q, (YS, YH) = D~^T (W, U)
+// (one D~ pass); V columns stride ldv_in, outputs stride ldy
+int apply_block_internal(irl_system *s, void *ws, const WsLayout &L, const double *V, int64_t ldv_in, int nb,
+                         double *YH, double *YS, int64_t ldy, int prec, hipStream_t st, int zero_v0 = 0)
+{
+    double *W = ws_ptr<double>(ws, L.off_w), *U = ws_ptr<double>(ws, L.off_u);
+    TIMED(s, prec == IRL_FP64 ? IRL_STAT_GEMV : IRL_STAT_GEMV_LO, st,
+          launch_gemv_rows_multi(L, ws, prec, V, ldv_in, nb, zero_v0, W, st));
+    for (int q = 0; q < nb; ++q)
+        TIMED(s, IRL_STAT_HAM_APPLY, st, launch_ham_apply(s, W + (int64_t)q * L.ns, U + (int64_t)q * L.ns, st));
+    int nblk = 1;
+    TIMED(s, prec == IRL_FP64 ? IRL_STAT_GEMV_T : IRL_STAT_GEMV_T_LO, st,
+          launch_gemv_t2_multi(L, ws, prec, nb, W, U, &nblk, st));
+    TIMED(s, IRL_STAT_REDUCE, st, launch_t2_reduce_multi(L, ws, nblk, nb, YS, YH, ldy, st));
+    return IRL_OK;
+}
+
 int check_prec(irl_system *s, int prec)
 {
     if (prec == IRL_FP64 && !s->ws_has64)
@@ -239,21 +256,22 @@ WsLayout make_layout(int64_t ns, int64_t ncols, uint32_t flags)
     L.off_scal = take(sizeof(WsScalars));
     L.off_d64 = take((flags & IRL_WS_FP64) ? (size_t)ns * ld * sizeof(double) : 0);
     L.off_d32 = take((flags & IRL_WS_FP32) ? (size_t)ns * ld * sizeof(float) : 0);
+    const size_t nvec = (size_t)layout_vectors(L);   // vectors per w/u/yH/yS region
     L.off_psi = take((size_t)ns * 8);
     L.off_hpsi = take((size_t)ns * 8);
-    L.off_w = take((size_t)ns * 8);
-    L.off_u = take((size_t)ns * 8);
+    L.off_w = take((size_t)ns * 8 * nvec);
+    L.off_u = take((size_t)ns * 8 * nvec);
     L.off_grad = take((size_t)ld * 8);
-    L.off_yh = take((size_t)ld * 8);
-    L.off_ys = take((size_t)ld * 8);
+    L.off_yh = take((size_t)ld * 8 * nvec);
+    L.off_ys = take((size_t)ld * 8 * nvec);
     L.off_y = take((size_t)ld * 8);
     L.off_r = take((size_t)ld * 8);
-    L.off_vconv = take((size_t)ld * 8);
+    L.off_vconv = take((size_t)ld * 8 * nvec);
     L.off_part = take((size_t)kStreamBlocks * 2 * ld * 8);
-    L.off_part2 = take((size_t)kReduceGroups * 2 * ld * 8);
+    L.off_part2 = take((size_t)kReduceGroups * 2 * ld * 8 * nvec);
     L.off_red = take((size_t)kScalarParts * 4 * 8);
-    L.off_kry0 = take((size_t)(kMaxKrylov + 1) * ld * 8);
-    L.off_kry1 = take((size_t)(kMaxKrylov + 1) * ld * 8);
+    L.off_kry0 = take((size_t)kBasisCols * ld * 8);
+    L.off_kry1 = take((size_t)kBasisCols * ld * 8);
     L.total = off;
     return L;
 }
@@ -380,6 +398,91 @@ int irl_solve(irl_system *s, void *ws, const WsLayout &L, const irl_solver_opts 
     return IRL_OK;
 }
 
+// Thick-restart block Lanczos solve (opts.block = nb >= 2 vectors per operator
+// pass); same outputs and convergence test as irl_solve.  m counts basis columns.
+int irl_solve_block(irl_system *s, void *ws, const WsLayout &L, const irl_solver_opts &o, int prec,
+                    SolveOut &out, hipStream_t st)
+{
+    const int nb = o.block;
+    if (!(L.flags & IRL_WS_BLOCK)) return set_err(s, IRL_EINVAL, "block solves need a workspace with IRL_WS_BLOCK");
+    if (nb < 2 || nb > kMaxBlock) return set_err(s, IRL_EINVAL, "block must be in [2, 8]");
+    const int64_t dim = (o.mode == IRL_MODE_A) ? L.ncols : L.ncols - 1;
+    const int m = (int)std::min<int64_t>(std::min(o.m, kMaxKrylov), dim);
+    const int k = std::min(o.k_keep, m - nb);
+    if (m < 2 * nb || k < 1) return set_err(s, IRL_EINVAL, "block solve needs 2 * block <= m and 1 <= k_keep <= m - block");
+    const double u_op = (prec == IRL_FP64) ? 1.1102230246251565e-16 : 5.960464477539063e-08;
+    const int split = (prec == IRL_FP32) ? 1 : 0;
+    double *Vb[2] = {ws_ptr<double>(ws, L.off_kry0), ws_ptr<double>(ws, L.off_kry1)};
+    int cur = 0;
+    double *yH = ws_ptr<double>(ws, L.off_yh), *yS = ws_ptr<double>(ws, L.off_ys);
+    double *y = ws_ptr<double>(ws, L.off_y), *rv = ws_ptr<double>(ws, L.off_r);
+    int rc;
+    TIMED(s, IRL_STAT_RITZ, st, launch_reset_solve(L, ws, st));
+    TIMED(s, IRL_STAT_RITZ, st, launch_block_start(L, ws, Vb[0], nb, o.mode, o.seed, st));
+    int sz = 0, n_apply = 0, n_restart = 0;
+    bool converged = false;
+    double tol_eff = o.tol;
+    for (;;) {
+        // operator on the pending block, then one block step: basis grows to sz + nb
+        rc = apply_block_internal(s, ws, L, Vb[cur] + (int64_t)sz * L.ldv, L.ldv, nb, yH, yS, L.ldv, prec, st,
+                                  split);
+        if (rc) return rc;
+        n_apply += nb;
+        TIMED(s, IRL_STAT_LANCZOS, st,
+              launch_block_step(L, ws, Vb[cur], sz, nb, o.mode, split,
+                                o.seed + 0x100000001b3ull * (uint64_t)(n_restart + 1), st));
+        sz += nb;
+        TIMED(s, IRL_STAT_RITZ, st, launch_block_ritz(L, ws, sz, nb, st));
+        rc = read_scalars(s, ws, L, st);
+        if (rc) return rc;
+        const WsScalars &hs = *s->host_scal;
+        tol_eff = std::max(o.tol, 64.0 * u_op * hs.normT);
+        out.lam = hs.lam;
+        out.resid_est = hs.resid_est;
+        out.gap = hs.gap;
+        out.normT = hs.normT;
+        if (!std::isfinite(hs.lam)) return set_err(s, IRL_EINVAL, "non-finite Ritz value (check theta and D~)");
+        if (hs.resid_est <= tol_eff) {
+            TIMED(s, IRL_STAT_RITZ, st, launch_ritz_vector(L, ws, Vb[cur], sz, y, st));
+            rc = apply_internal(s, ws, L, y, yH, yS, prec, st, split);
+            if (rc) return rc;
+            ++n_apply;
+            TIMED(s, IRL_STAT_RITZ, st, launch_residual(L, ws, y, rv, o.mode, split, st));
+            rc = read_scalars(s, ws, L, st);
+            if (rc) return rc;
+            out.resid_explicit = std::sqrt(s->host_scal->resid2);
+            if (out.resid_explicit <= std::max(tol_eff, 1024.0 * u_op * hs.normT)) {
+                converged = true;
+                break;
+            }
+        }
+        if (sz + nb > m) {
+            if (n_restart >= o.max_restarts) break;
+            TIMED(s, IRL_STAT_RITZ, st, launch_block_restart(L, ws, Vb[cur], Vb[1 - cur], sz, k, nb, st));
+            cur = 1 - cur;
+            sz = k;
+            ++n_restart;
+        }
+    }
+    if (!converged) {
+        TIMED(s, IRL_STAT_RITZ, st, launch_block_ritz(L, ws, sz, nb, st));
+        TIMED(s, IRL_STAT_RITZ, st, launch_ritz_vector(L, ws, Vb[cur], sz, y, st));
+        rc = apply_internal(s, ws, L, y, yH, yS, prec, st, split);
+        if (rc) return rc;
+        ++n_apply;
+        TIMED(s, IRL_STAT_RITZ, st, launch_residual(L, ws, y, rv, o.mode, split, st));
+        rc = read_scalars(s, ws, L, st);
+        if (rc) return rc;
+        out.resid_explicit = std::sqrt(s->host_scal->resid2);
+    }
+    out.c0 = s->host_scal->c0;
+    out.n_apply = n_apply;
+    out.n_restart = n_restart;
+    out.converged = converged ? 1 : 0;
+    out.tol_used = tol_eff;
+    return IRL_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -400,6 +503,7 @@ void irl_solver_opts_default(irl_solver_opts *o)
     o->mode = IRL_MODE_A;
     o->seed = 0;
     o->flags = 0;
+    o->block = 0;
 }
 
 int irl_system_create(const irl_system_desc *d, void *stream, irl_system **out)
@@ -633,7 +737,7 @@ int irl_system_info_get(const irl_system *s, irl_system_info *o)
 int irl_workspace_query(const irl_system *s, int64_t ncols, uint32_t ws_flags, size_t *bytes)
 {
     if (!s || !bytes || ncols < 2 || !(ws_flags & (IRL_WS_FP64 | IRL_WS_FP32)) ||
-        (ws_flags & ~(uint32_t)(IRL_WS_FP64 | IRL_WS_FP32)))
+        (ws_flags & ~(uint32_t)(IRL_WS_FP64 | IRL_WS_FP32 | IRL_WS_BLOCK)))
         return IRL_EINVAL;
     *bytes = make_layout(s->ns, ncols, ws_flags).total;
     return IRL_OK;
@@ -708,6 +812,22 @@ int irl_apply_lm_operator(irl_system *s, void *ws, size_t ws_bytes, const double
     return apply_internal(s, ws, s->lay, v, yH, yS, precision, (hipStream_t)stream);
 }
 
+int irl_apply_lm_operator_block(irl_system *s, void *ws, size_t ws_bytes, const double *V, int64_t ldv_in,
+                                int32_t nb, double *YH, double *YS, int64_t ldy, int32_t precision, void *stream)
+{
+    if (!s) return IRL_EINVAL;
+    if (!s->ws_valid || s->ws != ws) return set_err(s, IRL_ESTATE, "workspace holds no evaluation");
+    const WsLayout &L = s->lay;
+    if (!(L.flags & IRL_WS_BLOCK)) return set_err(s, IRL_EINVAL, "multi-vector applies need IRL_WS_BLOCK");
+    if (ws_bytes < L.total) return set_err(s, IRL_ENOMEM, "workspace too small");
+    if (nb < 1 || nb > kMaxBlock) return set_err(s, IRL_EINVAL, "nb must be in [1, 8]");
+    if (!V || !YH || !YS || ldv_in < L.ncols || ldy < L.ncols) return set_err(s, IRL_EINVAL, "bad vector arguments");
+    int rc = check_prec(s, precision);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    return apply_block_internal(s, ws, L, V, ldv_in, nb, YH, YS, ldy, precision, st);
+}
+
 int irl_apply_hamiltonian(irl_system *s, const double *w, double *u, void *stream)
 {
     if (!s || !w || !u) return IRL_EINVAL;
@@ -726,7 +846,8 @@ int irl_step(irl_system *s, irl_nqs_desc *nqs, const irl_solver_opts *opts, void
     else
         irl_solver_opts_default(&o);
     if (o.m < 2 || o.m > kMaxKrylov || o.k_keep < 1 || o.k_keep >= o.m || !(o.tol > 0.0) ||
-        o.max_restarts < 0 || (o.mode != IRL_MODE_A && o.mode != IRL_MODE_P))
+        o.max_restarts < 0 || (o.mode != IRL_MODE_A && o.mode != IRL_MODE_P) || o.block < 0 ||
+        o.block > kMaxBlock)
         return set_err(s, IRL_EINVAL, "bad solver options");
     hipStream_t st = (hipStream_t)stream;
     irl_step_result res;
@@ -754,7 +875,8 @@ int irl_step(irl_system *s, irl_nqs_desc *nqs, const irl_solver_opts *opts, void
 
     // ---- implicitly restarted Lanczos ----
     SolveOut so;
-    rc = irl_solve(s, ws, L, o, o.precision, nullptr, so, st);
+    rc = o.block > 1 ? irl_solve_block(s, ws, L, o, o.precision, so, st)
+                     : irl_solve(s, ws, L, o, o.precision, nullptr, so, st);
     if (rc) return rc;
     const int n_apply_lo = o.precision == IRL_FP32 ? so.n_apply : 0;
     if (o.precision == IRL_FP32 && s->ws_has64 && !(o.flags & IRL_STEP_NO_POLISH)) {
@@ -1463,6 +1585,7 @@ int irl_batch_step(irl_batch *b, const irl_solver_opts *opts, double *const *dth
     if (o.m < 2 || o.m > kMaxKrylov || o.k_keep < 1 || o.k_keep >= o.m || !(o.tol > 0.0) ||
         o.max_restarts < 0 || (o.mode != IRL_MODE_A && o.mode != IRL_MODE_P))
         return set_err(s0, IRL_EINVAL, "bad solver options");
+    if (o.block > 1) return set_err(s0, IRL_EINVAL, "batches step with single-vector Lanczos (block must be 0 or 1)");
     if ((o.precision == IRL_FP64 && !(b->ws_flags & IRL_WS_FP64)) ||
         (o.precision == IRL_FP32 && !(b->ws_flags & IRL_WS_FP32)))
         return set_err(s0, IRL_ESTATE, "batch workspaces hold no D~ copy for this precision");

@@ -10,6 +10,8 @@
 // non-temporal loads, 1 KiB per wavefront instruction.  FP32 copies are
 // multiplied and accumulated in FP32 inside a row block (the operator's
 // reduced-precision mode); block partials are combined in FP64.
+#include <algorithm>
+
 #include "internal.h"
 
 namespace irl {
@@ -319,6 +321,290 @@ hipError_t launch_t2_reduce(const WsLayout &L, void *ws, int nblk, double *ya, d
                                                                                  part2, groups);
     k_reduce_stage2<<<(unsigned)((len + 255) / 256), 256, 0, st>>>(part2, groups, L.ldv, ya, yb,
                                                                    nout, out_scale, out_div);
+    return hipGetLastError();
+}
+
+// ------------------------------------------- multi-vector streams (nb <= 8)
+// One pass over D~ serves nb vectors (the block operator of a block Lanczos
+// step): K6 computes nb dot products per row from one set of 16-byte loads, K7
+// carries 2 nb right-hand sides.  Bytes per pass stay those of one vector;
+// arithmetic grows nb times and stays far below the HBM ridge for nb <= 8.
+
+// W[q * ns + r] = D[r, :] . v_q (v_q staged in LDS, or converted vectors in global memory)
+template <typename T, int NB, bool VLDS>
+__global__ __launch_bounds__(256) void k_gemv_rows_multi(const T *__restrict__ D, int64_t ld, int64_t ns,
+                                                         const double *__restrict__ V, int64_t ldv_in,
+                                                         int64_t nv, const T *__restrict__ vglob, int c0,
+                                                         double *__restrict__ W)
+{
+    typedef typename Chunk<T>::V CV;
+    constexpr int E = Chunk<T>::E;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const T *vs = vglob;
+    if constexpr (VLDS) {
+        T *vl = reinterpret_cast<T *>(smem_raw);
+        for (int64_t i = threadIdx.x; i < NB * ld; i += blockDim.x) {
+            const int q = (int)(i / ld);
+            const int64_t c = i - (int64_t)q * ld;
+            vl[i] = (c < nv && c >= c0) ? (T)V[q * ldv_in + c] : (T)0;
+        }
+        __syncthreads();
+        vs = vl;
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t nch = ld / E;
+    const int64_t per = (ns + gridDim.x - 1) / gridDim.x;
+    const int64_t r0 = (int64_t)blockIdx.x * per, r1 = min(ns, r0 + per);
+    for (int64_t r = r0 + wv; r < r1; r += 4) {
+        const CV *row = reinterpret_cast<const CV *>(D + r * ld);
+        T acc[NB];
+#pragma unroll
+        for (int q = 0; q < NB; ++q) acc[q] = 0;
+        int64_t k = lane;
+        for (; k + kWave < nch; k += 2 * kWave) {
+            const CV x0 = __builtin_nontemporal_load(row + k);
+            const CV x1 = __builtin_nontemporal_load(row + k + kWave);
+#pragma unroll
+            for (int q = 0; q < NB; ++q) {
+                acc[q] += dot_chunk<T>(x0, vs + q * ld + k * E);
+                acc[q] += dot_chunk<T>(x1, vs + q * ld + (k + kWave) * E);
+            }
+        }
+        for (; k < nch; k += kWave) {
+            const CV x0 = __builtin_nontemporal_load(row + k);
+#pragma unroll
+            for (int q = 0; q < NB; ++q) acc[q] += dot_chunk<T>(x0, vs + q * ld + k * E);
+        }
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+            T a = acc[q];
+            for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off, kWave);
+            if (lane == 0) W[q * ns + r] = (double)a;
+        }
+    }
+}
+
+// nb vectors converted to the stream precision, zero padded to ld (stride ld)
+template <typename T>
+__global__ void k_vec_convert_multi(const double *__restrict__ V, int64_t ldv_in, int nb, int64_t nv,
+                                    int64_t ld, int c0, T *out)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nb * ld;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int q = (int)(i / ld);
+        const int64_t c = i - (int64_t)q * ld;
+        out[i] = (c < nv && c >= c0) ? (T)V[q * ldv_in + c] : (T)0;
+    }
+}
+
+template <typename T, int NB>
+static void gemv_rows_multi_inst(const T *D, int64_t ld, int64_t ns, const double *V, int64_t ldv_in,
+                                 int64_t nv, int c0, T *vtmp, double *W, hipStream_t st)
+{
+    const int64_t nblk = ns < 4096 ? (ns + 3) / 4 : 2048;
+    const size_t sh = (size_t)NB * ld * sizeof(T);
+    if (sh <= kMaxLdsBytes) {
+        k_gemv_rows_multi<T, NB, true><<<(unsigned)nblk, 256, sh, st>>>(D, ld, ns, V, ldv_in, nv, nullptr,
+                                                                         c0, W);
+    } else {
+        k_vec_convert_multi<T><<<(unsigned)((NB * ld + 255) / 256), 256, 0, st>>>(V, ldv_in, NB, nv, ld, c0,
+                                                                                  vtmp);
+        k_gemv_rows_multi<T, NB, false><<<(unsigned)nblk, 256, 0, st>>>(D, ld, ns, V, ldv_in, nv, vtmp,
+                                                                        c0, W);
+    }
+}
+
+template <typename T>
+static hipError_t gemv_rows_multi_typed(const T *D, int64_t ld, int64_t ns, const double *V,
+                                        int64_t ldv_in, int nb, int64_t nv, int c0, T *vtmp, double *W,
+                                        hipStream_t st)
+{
+    switch (nb) {
+    case 1: gemv_rows_multi_inst<T, 1>(D, ld, ns, V, ldv_in, nv, c0, vtmp, W, st); break;
+    case 2: gemv_rows_multi_inst<T, 2>(D, ld, ns, V, ldv_in, nv, c0, vtmp, W, st); break;
+    case 3: gemv_rows_multi_inst<T, 3>(D, ld, ns, V, ldv_in, nv, c0, vtmp, W, st); break;
+    case 4: gemv_rows_multi_inst<T, 4>(D, ld, ns, V, ldv_in, nv, c0, vtmp, W, st); break;
+    case 5: gemv_rows_multi_inst<T, 5>(D, ld, ns, V, ldv_in, nv, c0, vtmp, W, st); break;
+    case 6: gemv_rows_multi_inst<T, 6>(D, ld, ns, V, ldv_in, nv, c0, vtmp, W, st); break;
+    case 7: gemv_rows_multi_inst<T, 7>(D, ld, ns, V, ldv_in, nv, c0, vtmp, W, st); break;
+    case 8: gemv_rows_multi_inst<T, 8>(D, ld, ns, V, ldv_in, nv, c0, vtmp, W, st); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_gemv_rows_multi(const WsLayout &L, void *ws, int prec, const double *V, int64_t ldv_in,
+                                  int nb, int zero_v0, double *W, hipStream_t st)
+{
+    if (nb < 1 || nb > layout_vectors(L)) return hipErrorInvalidValue;
+    const int c0 = zero_v0 ? 1 : 0;
+    if (prec == IRL_FP64)
+        return gemv_rows_multi_typed<double>(ws_ptr<double>(ws, L.off_d64), L.ld64, L.ns, V, ldv_in, nb,
+                                             L.ncols, c0, ws_ptr<double>(ws, L.off_vconv), W, st);
+    return gemv_rows_multi_typed<float>(ws_ptr<float>(ws, L.off_d32), L.ld32, L.ns, V, ldv_in, nb, L.ncols,
+                                        c0, ws_ptr<float>(ws, L.off_vconv), W, st);
+}
+
+// K7 with 2 NB right-hand sides: acc[2q] += W[q][r] D[r, :], acc[2q+1] += U[q][r] D[r, :].
+// Rows [r0, r1) per block, NCH chunks per lane per column tile, the 4 waves combined
+// ((w0 + w1) + w2) + w3; the block writes 2 NB partial rows: part[(rb*2NB + j) * ldv].
+template <typename T, int NCH, int NB>
+__global__ __launch_bounds__(256) void k_gemv_t2_multi(const T *__restrict__ D, int64_t ld, int64_t ns,
+                                                       const double *__restrict__ W,
+                                                       const double *__restrict__ U,
+                                                       double *__restrict__ part, int64_t ldv, int nblk)
+{
+    typedef typename Chunk<T>::V CV;
+    constexpr int E = Chunk<T>::E;
+    __shared__ CV red[2 * NB][64 * NCH];
+    const int tile = blockIdx.x, rb = blockIdx.y;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t nch = ld / E;
+    const int64_t per = (ns + nblk - 1) / nblk;
+    const int64_t r0 = (int64_t)rb * per, r1 = min(ns, r0 + per);
+    const int64_t cbase = (int64_t)tile * 64 * NCH + lane;
+    CV acc[2 * NB][NCH];
+#pragma unroll
+    for (int j = 0; j < 2 * NB; ++j)
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) acc[j][c] = (CV)0;
+    for (int64_t r = r0 + wv; r < r1; r += 4) {
+        const CV *row = reinterpret_cast<const CV *>(D + r * ld);
+        CV x[NCH];
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            const int64_t k = cbase + (int64_t)c * 64;
+            x[c] = k < nch ? __builtin_nontemporal_load(row + k) : (CV)0;
+        }
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+            const T aq = (T)W[q * ns + r], bq = (T)U[q * ns + r];
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) {
+                acc[2 * q][c] += aq * x[c];
+                acc[2 * q + 1][c] += bq * x[c];
+            }
+        }
+    }
+    for (int src = 1; src < 4; ++src) {
+        __syncthreads();
+        if (wv == src) {
+#pragma unroll
+            for (int j = 0; j < 2 * NB; ++j)
+#pragma unroll
+                for (int c = 0; c < NCH; ++c) red[j][c * 64 + lane] = acc[j][c];
+        }
+        __syncthreads();
+        if (wv == 0) {
+#pragma unroll
+            for (int j = 0; j < 2 * NB; ++j)
+#pragma unroll
+                for (int c = 0; c < NCH; ++c) acc[j][c] += red[j][c * 64 + lane];
+        }
+    }
+    if (wv != 0) return;
+    double *prow = part + (int64_t)rb * 2 * NB * ldv;
+#pragma unroll
+    for (int j = 0; j < 2 * NB; ++j)
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            const int64_t k = cbase + (int64_t)c * 64;
+            if (k < nch) {
+#pragma unroll
+                for (int e = 0; e < E; ++e) prow[j * ldv + k * E + e] = (double)acc[j][c][e];
+            }
+        }
+}
+
+// chunks per lane per column tile for NB vectors (accumulators ~ 2 NB NCH chunks)
+template <int NB>
+constexpr int multi_nch() { return NB == 1 ? 16 : (NB == 2 ? 8 : (NB <= 4 ? 4 : 2)); }
+
+// row blocks of the multi launch: about kStreamBlocks blocks in all, and at most
+// kStreamBlocks * 2 partial rows (the size of the partial buffer)
+static int multi_blocks(int64_t ns, int ntiles, int nb)
+{
+    int nblk = kStreamBlocks / ntiles;
+    nblk = std::min(nblk, kStreamBlocks / nb);
+    if (nblk < 1) nblk = 1;
+    if (nblk > (ns + 3) / 4) nblk = (int)((ns + 3) / 4);
+    return nblk;
+}
+
+template <typename T, int NB>
+static void gemv_t2_multi_inst(const T *D, int64_t ld, int64_t ns, const double *W, const double *U,
+                               double *part, int64_t ldv, int &nblk_out, hipStream_t st)
+{
+    constexpr int E = Chunk<T>::E;
+    constexpr int NCH = multi_nch<NB>();
+    const int64_t nch = ld / E;
+    const int ntiles = (int)((nch + 64 * NCH - 1) / (64 * NCH));
+    const int nblk = multi_blocks(ns, ntiles, NB);
+    nblk_out = nblk;
+    k_gemv_t2_multi<T, NCH, NB><<<dim3(ntiles, nblk), 256, 0, st>>>(D, ld, ns, W, U, part, ldv, nblk);
+}
+
+template <typename T>
+static hipError_t gemv_t2_multi_typed(const T *D, int64_t ld, int64_t ns, int nb, const double *W,
+                                      const double *U, double *part, int64_t ldv, int &nblk, hipStream_t st)
+{
+    switch (nb) {
+    case 1: gemv_t2_multi_inst<T, 1>(D, ld, ns, W, U, part, ldv, nblk, st); break;
+    case 2: gemv_t2_multi_inst<T, 2>(D, ld, ns, W, U, part, ldv, nblk, st); break;
+    case 3: gemv_t2_multi_inst<T, 3>(D, ld, ns, W, U, part, ldv, nblk, st); break;
+    case 4: gemv_t2_multi_inst<T, 4>(D, ld, ns, W, U, part, ldv, nblk, st); break;
+    case 5: gemv_t2_multi_inst<T, 5>(D, ld, ns, W, U, part, ldv, nblk, st); break;
+    case 6: gemv_t2_multi_inst<T, 6>(D, ld, ns, W, U, part, ldv, nblk, st); break;
+    case 7: gemv_t2_multi_inst<T, 7>(D, ld, ns, W, U, part, ldv, nblk, st); break;
+    case 8: gemv_t2_multi_inst<T, 8>(D, ld, ns, W, U, part, ldv, nblk, st); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_gemv_t2_multi(const WsLayout &L, void *ws, int prec, int nb, const double *W,
+                                const double *U, int *nblk, hipStream_t st)
+{
+    if (nb < 1 || nb > layout_vectors(L)) return hipErrorInvalidValue;
+    double *part = ws_ptr<double>(ws, L.off_part);
+    if (prec == IRL_FP64)
+        return gemv_t2_multi_typed<double>(ws_ptr<double>(ws, L.off_d64), L.ld64, L.ns, nb, W, U, part,
+                                           L.ldv, *nblk, st);
+    return gemv_t2_multi_typed<float>(ws_ptr<float>(ws, L.off_d32), L.ld32, L.ns, nb, W, U, part, L.ldv,
+                                      *nblk, st);
+}
+
+// stage 2 of the multi reduction: partial row j = 2q (a-sums, -> YS[:, q]) or
+// 2q + 1 (b-sums, -> YH[:, q]); columns >= nout are not written
+__global__ void k_reduce_stage2_multi(const double *__restrict__ part2, int groups, int64_t ldv, int nb,
+                                      double *YS, double *YH, int64_t ldy, int64_t nout)
+{
+    const int64_t len = 2 * (int64_t)nb * ldv;
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= len) return;
+    const int j = (int)(c / ldv);
+    const int64_t i = c - (int64_t)j * ldv;
+    if (i >= nout) return;
+    double s = 0.0;
+    for (int g = 0; g < groups; ++g) s += part2[(int64_t)g * len + c];
+    if (j & 1)
+        YH[(int64_t)(j >> 1) * ldy + i] = s;
+    else
+        YS[(int64_t)(j >> 1) * ldy + i] = s;
+}
+
+hipError_t launch_t2_reduce_multi(const WsLayout &L, void *ws, int nblk, int nb, double *YS, double *YH,
+                                  int64_t ldy, hipStream_t st)
+{
+    if (nb < 1 || nb > layout_vectors(L)) return hipErrorInvalidValue;
+    double *part = ws_ptr<double>(ws, L.off_part);
+    double *part2 = ws_ptr<double>(ws, L.off_part2);
+    const int64_t len = 2 * (int64_t)nb * L.ldv;
+    const int groups = nblk < kReduceGroups ? nblk : kReduceGroups;
+    k_reduce_stage1<<<dim3((unsigned)((len + 255) / 256), groups), 256, 0, st>>>(part, nblk, len, part2,
+                                                                                 groups);
+    k_reduce_stage2_multi<<<(unsigned)((len + 255) / 256), 256, 0, st>>>(part2, groups, L.ldv, nb, YS, YH,
+                                                                         ldy, L.ncols);
     return hipGetLastError();
 }
 

@@ -13,6 +13,8 @@
 namespace irl {
 
 constexpr int kMaxKrylov = 64;          // m <= 64
+constexpr int kMaxBlock = 8;            // vectors per multi-vector apply / block Lanczos step
+constexpr int kBasisCols = kMaxKrylov + kMaxBlock;   // Krylov basis columns held per buffer
 constexpr int kWave = 64;               // CDNA wavefront width
 constexpr int kStreamBlocks = 512;      // row blocks of the D~^T stream kernel
 constexpr int kReduceGroups = 16;       // first-level groups of the partial reduction
@@ -42,6 +44,9 @@ struct WsScalars {
     double Q[kMaxKrylov * kMaxKrylov];   // restart rotations, column-major Q[l + m*i]
     double U[kMaxKrylov * kMaxKrylov];   // Ritz vectors of T, column-major
     double h[kMaxKrylov + 1];            // Gram-Schmidt coefficients
+    // block Lanczos: projected matrix T = Q^T H~' Q over the basis and the next
+    // block (row-major, leading dimension kBasisCols)
+    double T[kBasisCols * kBasisCols];
 };
 
 // Workspace layout for one (N_s, ncols, flags).
@@ -56,6 +61,9 @@ struct WsLayout {
 };
 
 WsLayout make_layout(int64_t ns, int64_t ncols, uint32_t flags);
+
+// vectors the w/u, yH/yS and conversion regions of a layout hold (1, or kMaxBlock with IRL_WS_BLOCK)
+inline int layout_vectors(const WsLayout &L) { return (L.flags & IRL_WS_BLOCK) ? kMaxBlock : 1; }
 
 template <typename T>
 inline T *ws_ptr(void *ws, size_t off) { return reinterpret_cast<T *>(static_cast<char *>(ws) + off); }
@@ -207,6 +215,22 @@ hipError_t launch_ham_stored_grouped(const Member *M, const WorkItem *items, int
 hipError_t launch_ham_pull_grouped(const Member *M, const WorkItem *items, int nitems,
                                    int64_t nblocks, int which, int lookup, hipStream_t st);
 hipError_t launch_ham_apply(const irl_system *s, const double *w, double *u, hipStream_t st);
+// multi-vector D~ streams: W[:, q] = D~ V[:, q] (q < nb, W column stride ns) and the
+// 2 nb right-hand-side D~^T pass over (W, U); reduction into YS[:, q], YH[:, q] (stride ldy)
+hipError_t launch_gemv_rows_multi(const WsLayout &L, void *ws, int prec, const double *V, int64_t ldv_in,
+                                  int nb, int zero_v0, double *W, hipStream_t st);
+hipError_t launch_gemv_t2_multi(const WsLayout &L, void *ws, int prec, int nb, const double *W,
+                                const double *U, int *nblk, hipStream_t st);
+hipError_t launch_t2_reduce_multi(const WsLayout &L, void *ws, int nblk, int nb, double *YS, double *YH,
+                                  int64_t ldy, hipStream_t st);
+// block Lanczos (one workgroup each): start block, step, Ritz pairs of T, thick restart
+hipError_t launch_block_start(const WsLayout &L, void *ws, double *V, int nb, int mode, uint64_t seed,
+                              hipStream_t st);
+hipError_t launch_block_step(const WsLayout &L, void *ws, double *V, int s0, int nb, int mode, int split,
+                             uint64_t seed, hipStream_t st);
+hipError_t launch_block_ritz(const WsLayout &L, void *ws, int s, int nb, hipStream_t st);
+hipError_t launch_block_restart(const WsLayout &L, void *ws, const double *Vold, double *Vnew, int s,
+                                int k, int nb, hipStream_t st);
 // stored rows: per-row counts of connections inside the set, then the fill
 hipError_t launch_ham_count(const irl_system *s, int32_t *count, hipStream_t st);
 hipError_t launch_ham_fill(const irl_system *s, const int64_t *ptr, int32_t *col, double *val,

@@ -550,6 +550,348 @@ hipError_t launch_reset_solve(const WsLayout &L, void *ws, hipStream_t st)
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Thick-restart block Lanczos (the block variant the paper names as its future
+// direction, Discussion): nb vectors per operator pass.  Basis Q (orthonormal
+// columns), projected matrix T = Q^T H~' Q kept in full (row-major, leading
+// dimension kBasisCols) so that T stays exact after thick restarts:
+//   step:     Z = H~' Q_J for the newest block J; T[:, J] = Q^T Z (two passes of
+//             classical Gram-Schmidt against all columns); Z = Q_next R by
+//             modified Gram-Schmidt (two passes) inside the block; T[next, J] = R;
+//   Ritz:     T_s = Y Theta Y^T (Householder tridiagonalisation + the implicit
+//             QR of the single-vector path); residual of pair i = ||C y_i|| with
+//             C = T[next, 0:s], the coupling of the pending block;
+//   restart:  Q <- [Q Y_k, Q_next], T <- [[Theta_k, E^T], [E, .]], E = C Y_k
+//             (equivalent to exact-shift implicit restarts, Algorithm 1, for nb = 1).
+constexpr int kTld = kBasisCols;
+constexpr int kBSh = kBasisCols + 1;
+
+// h[d] = V[d] . w for d < nd (fixed order), into shared hsh[nd]; nd <= kBasisCols
+__device__ void bdots(const double *V, int64_t ldv, int nd, const double *w, int64_t L, double *sh,
+                      double *hsh)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    __syncthreads();
+    for (int d = 0; d < nd; ++d) {
+        double p = 0.0;
+        for (int64_t i = threadIdx.x; i < L; i += kVecThreads) p += V[d * ldv + i] * w[i];
+        for (int off = 32; off > 0; off >>= 1) p += __shfl_xor(p, off, kWave);
+        if (lane == 0) sh[wv * kBSh + d] = p;
+    }
+    __syncthreads();
+    if (threadIdx.x < nd) {
+        double s = 0.0;
+        for (int i = 0; i < kVecWaves; ++i) s += sh[i * kBSh + threadIdx.x];
+        hsh[threadIdx.x] = s;
+    }
+    __syncthreads();
+}
+
+// two passes of classical Gram-Schmidt of w against V[0..nd); coef[d] += both passes
+__device__ void bcgs2(const double *V, int64_t ldv, int nd, double *w, int64_t L, double *sh, double *hsh,
+                      double *coef)
+{
+    for (int pass = 0; pass < 2; ++pass) {
+        bdots(V, ldv, nd, w, L, sh, hsh);
+        if (coef && threadIdx.x < nd) coef[threadIdx.x] += hsh[threadIdx.x];
+        block_sub(V, ldv, nd, hsh, w, L);
+    }
+}
+
+__device__ double bnorm(const double *w, int64_t L, double *sh)
+{
+    double p = 0.0;
+    for (int64_t i = threadIdx.x; i < L; i += kVecThreads) p += w[i] * w[i];
+    return sqrt(block_sum(p, sh));
+}
+
+// random unit vector orthogonal to V[0..nd) into w (component 0 zero in mode P)
+__device__ void bfresh(const double *V, int64_t ldv, int nd, double *w, int64_t L, int64_t ncols, int mode,
+                       uint64_t seed, double *sh, double *hsh)
+{
+    for (int64_t i = threadIdx.x; i < L; i += kVecThreads)
+        w[i] = (i < ncols && !(mode == IRL_MODE_P && i == 0)) ? uniform_pm1(seed, (uint64_t)i) : 0.0;
+    __syncthreads();
+    bcgs2(V, ldv, nd, w, L, sh, hsh, nullptr);
+    const double nrm = bnorm(w, L, sh);
+    for (int64_t i = threadIdx.x; i < L; i += kVecThreads) w[i] = nrm > 0.0 ? w[i] / nrm : 0.0;
+    __syncthreads();
+}
+
+// start block: nb orthonormal random vectors in columns [0, nb); T cleared
+__global__ __launch_bounds__(kVecThreads) void k_block_start(WsScalars *sc, double *V, int64_t ldv,
+                                                            int64_t ncols, int nb, int mode, uint64_t seed)
+{
+    __shared__ double sh[kVecWaves * kBSh];
+    __shared__ double hsh[kBSh];
+    for (int i = threadIdx.x; i < kTld * kTld; i += kVecThreads) sc->T[i] = 0.0;
+    if (threadIdx.x == 0) {
+        sc->normT = 0.0;
+        sc->breakdowns = 0;
+        sc->resid2 = 0.0;
+    }
+    __syncthreads();
+    for (int q = 0; q < nb; ++q)
+        bfresh(V, ldv, q, V + (int64_t)q * ldv, ldv, ncols, mode, seed + 0x9E3779B97F4A7C15ull * (uint64_t)q,
+               sh, hsh);
+}
+
+hipError_t launch_block_start(const WsLayout &L, void *ws, double *V, int nb, int mode, uint64_t seed,
+                              hipStream_t st)
+{
+    if (nb < 1 || nb > kMaxBlock) return hipErrorInvalidValue;
+    k_block_start<<<1, kVecThreads, 0, st>>>(ws_ptr<WsScalars>(ws, L.off_scal), V, L.ldv, L.ncols, nb, mode,
+                                             seed);
+    return hipGetLastError();
+}
+
+// One block step on the block in columns [s0, s0 + nb): (yH, yS) hold the raw
+// operator pairs of those columns (stride ldy); the next block is written to
+// columns [s0 + nb, s0 + 2 nb).
+__global__ __launch_bounds__(kVecThreads) void k_block_step(
+    const double *__restrict__ yH, const double *__restrict__ yS, int64_t ldy,
+    const double *__restrict__ grad, WsScalars *sc, double *V, int64_t ldv, int64_t ncols, int s0, int nb,
+    int mode, int split, uint64_t seed)
+{
+    __shared__ double sh[kVecWaves * kBSh];
+    __shared__ double hsh[kBSh];
+    __shared__ double coef[kBSh];
+    __shared__ double R[kMaxBlock * kMaxBlock];
+    const int64_t L = ldv;
+    const double Z = sc->Z, E = sc->E_el;
+    // 1. centred images H~' q into the next block's columns
+    for (int q = 0; q < nb; ++q) {
+        const double *vq = V + (int64_t)(s0 + q) * ldv;
+        double *z = V + (int64_t)(s0 + nb + q) * ldv;
+        const double gdotv = split ? grad_dot(grad, vq, ncols, sh) : 0.0;
+        const double v0 = vq[0];
+        for (int64_t i = threadIdx.x; i < L; i += kVecThreads) {
+            double x = (i < ncols) ? centred_component(i, yH + q * ldy, yS + q * ldy, grad, v0, gdotv, Z, E,
+                                                       split)
+                                   : 0.0;
+            if (mode == IRL_MODE_P && i == 0) x = 0.0;
+            z[i] = x;
+        }
+        __syncthreads();
+    }
+    // 2. projection on all columns [0, s0 + nb): T[:, s0 + q]
+    const int nd = s0 + nb;
+    for (int q = 0; q < nb; ++q) {
+        double *z = V + (int64_t)(s0 + nb + q) * ldv;
+        if (threadIdx.x < nd) coef[threadIdx.x] = 0.0;
+        __syncthreads();
+        bcgs2(V, ldv, nd, z, L, sh, hsh, coef);
+        __syncthreads();
+        if (threadIdx.x < nd) sc->T[threadIdx.x * kTld + (s0 + q)] = coef[threadIdx.x];
+        __syncthreads();
+    }
+    double normT = sc->normT;
+    for (int d = 0; d < nd; ++d)
+        for (int q = 0; q < nb; ++q) normT = fmax(normT, fabs(sc->T[d * kTld + s0 + q]));
+    // 3. orthonormalise the new block in place (two passes of modified Gram-Schmidt)
+    for (int q = 0; q < nb; ++q) {
+        double *z = V + (int64_t)(s0 + nb + q) * ldv;
+        if (threadIdx.x < kMaxBlock) coef[threadIdx.x] = 0.0;
+        __syncthreads();
+        if (q > 0) bcgs2(V + (int64_t)(s0 + nb) * ldv, ldv, q, z, L, sh, hsh, coef);
+        const double nrm = bnorm(z, L, sh);
+        double rqq;
+        if (nrm <= 1e3 * 1.1102230246251565e-16 * normT) {
+            // invariant subspace: continue with a fresh direction, T decouples
+            bfresh(V, ldv, s0 + nb + q, z, L, ncols, mode,
+                   seed ^ (0x5bd1e995ull * (uint64_t)(s0 + nb + q + 1 + 97 * sc->breakdowns)), sh, hsh);
+            rqq = 0.0;
+            if (threadIdx.x == 0) sc->breakdowns += 1;
+        } else {
+            for (int64_t i = threadIdx.x; i < L; i += kVecThreads) z[i] /= nrm;
+            rqq = nrm;
+        }
+        if (threadIdx.x == 0) {
+            for (int c = 0; c < kMaxBlock; ++c) R[c * kMaxBlock + q] = c < q ? coef[c] : (c == q ? rqq : 0.0);
+        }
+        __syncthreads();
+    }
+    // 4. coupling of the next block (R, upper triangular) and symmetry of T
+    for (int idx = threadIdx.x; idx < nb * nb; idx += kVecThreads) {
+        const int r = idx / nb, c = idx - r * nb;
+        const double val = r <= c ? R[r * kMaxBlock + c] : 0.0;
+        sc->T[(s0 + nb + r) * kTld + s0 + c] = val;
+        sc->T[(s0 + c) * kTld + s0 + nb + r] = val;
+    }
+    for (int idx = threadIdx.x; idx < s0 * nb; idx += kVecThreads) {
+        const int d = idx / nb, q = idx - d * nb;
+        sc->T[(s0 + q) * kTld + d] = sc->T[d * kTld + s0 + q];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 0; i < nb; ++i)
+            for (int j = i + 1; j < nb; ++j) {
+                const double a = 0.5 * (sc->T[(s0 + i) * kTld + s0 + j] + sc->T[(s0 + j) * kTld + s0 + i]);
+                sc->T[(s0 + i) * kTld + s0 + j] = a;
+                sc->T[(s0 + j) * kTld + s0 + i] = a;
+            }
+        for (int r = 0; r < nb; ++r)
+            for (int c = 0; c < nb; ++c) normT = fmax(normT, fabs(R[r * kMaxBlock + c]));
+        sc->normT = normT;
+    }
+}
+
+hipError_t launch_block_step(const WsLayout &L, void *ws, double *V, int s0, int nb, int mode, int split,
+                             uint64_t seed, hipStream_t st)
+{
+    if (nb < 1 || nb > kMaxBlock || s0 < 0 || s0 + 2 * nb > kBasisCols || s0 + nb > kMaxKrylov)
+        return hipErrorInvalidValue;
+    k_block_step<<<1, kVecThreads, 0, st>>>(ws_ptr<double>(ws, L.off_yh), ws_ptr<double>(ws, L.off_ys), L.ldv,
+                                            ws_ptr<double>(ws, L.off_grad), ws_ptr<WsScalars>(ws, L.off_scal),
+                                            V, L.ldv, L.ncols, s0, nb, mode, split, seed);
+    return hipGetLastError();
+}
+
+// Ritz pairs of T[0:s, 0:s] (one wavefront): Householder reduction to
+// tridiagonal form with the reflections accumulated, the tridiagonal QR of the
+// single-vector path, back-transformation; ascending order into ritz / U
+// (column-major, leading dimension s); residual estimate of the lowest pair.
+__global__ __launch_bounds__(64) void k_block_ritz(WsScalars *sc, int s, int nb)
+{
+    __shared__ double A[kMaxKrylov * kMaxKrylov];   // T (row-major, ld s), then the QR eigenvectors
+    __shared__ double Qh[kMaxKrylov * kMaxKrylov];  // accumulated reflections (row-major, ld s)
+    __shared__ double v[kMaxKrylov], p[kMaxKrylov], d[kMaxKrylov], e[kMaxKrylov];
+    __shared__ int rank[kMaxKrylov];
+    __shared__ double red[kMaxBlock];
+    const int lane = threadIdx.x;
+    for (int idx = lane; idx < s * s; idx += 64) {
+        const int i = idx / s, j = idx - i * s;
+        A[idx] = sc->T[i * kTld + j];
+        Qh[idx] = (i == j) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    for (int k = 0; k + 2 < s; ++k) {
+        if (lane == 0) {
+            double nrm2 = 0.0;
+            for (int i = k + 1; i < s; ++i) nrm2 += A[i * s + k] * A[i * s + k];
+            const double nrm = sqrt(nrm2);
+            const double x0 = A[(k + 1) * s + k];
+            const double alpha = x0 >= 0.0 ? -nrm : nrm;
+            double vn2 = 0.0;
+            for (int i = 0; i < s; ++i) {
+                double vi = i > k ? A[i * s + k] : 0.0;
+                if (i == k + 1) vi -= alpha;
+                v[i] = vi;
+                vn2 += vi * vi;
+            }
+            const double vn = sqrt(vn2);
+            for (int i = 0; i < s; ++i) v[i] = vn > 0.0 ? v[i] / vn : 0.0;
+        }
+        __syncthreads();
+        if (lane < s) {
+            double acc = 0.0;
+            for (int j = k + 1; j < s; ++j) acc += A[lane * s + j] * v[j];
+            p[lane] = acc;
+        }
+        __syncthreads();
+        double K = 0.0;
+        for (int j = k + 1; j < s; ++j) K += v[j] * p[j];
+        // w = 2p - 2K v (into p); A <- A - v w^T - w v^T
+        __syncthreads();
+        if (lane < s) p[lane] = 2.0 * p[lane] - 2.0 * K * v[lane];
+        __syncthreads();
+        if (lane < s) {
+            for (int j = 0; j < s; ++j) A[lane * s + j] -= v[lane] * p[j] + p[lane] * v[j];
+            double t = 0.0;
+            for (int l = k + 1; l < s; ++l) t += Qh[lane * s + l] * v[l];
+            for (int j = k + 1; j < s; ++j) Qh[lane * s + j] -= 2.0 * t * v[j];
+        }
+        __syncthreads();
+    }
+    if (lane < s) {
+        d[lane] = A[lane * s + lane];
+        e[lane] = lane + 1 < s ? 0.5 * (A[lane * s + lane + 1] + A[(lane + 1) * s + lane]) : 0.0;
+    }
+    __syncthreads();
+    tridiag_eig(d, e, A, s);   // A <- eigenvectors of the tridiagonal (column-major, ld s)
+    if (lane < s) {
+        int rk = 0;
+        for (int t = 0; t < s; ++t) rk += (d[t] < d[lane]) || (d[t] == d[lane] && t < lane);
+        rank[lane] = rk;
+    }
+    __syncthreads();
+    if (lane < s) {
+        sc->ritz[rank[lane]] = d[lane];
+        for (int c = 0; c < s; ++c) {
+            double acc = 0.0;
+            for (int j = 0; j < s; ++j) acc += Qh[lane * s + j] * A[j + s * c];
+            sc->U[lane + s * rank[c]] = acc;
+        }
+    }
+    __syncthreads();
+    if (lane < nb) {
+        double acc = 0.0;
+        for (int j = 0; j < s; ++j) acc += sc->T[(s + lane) * kTld + j] * sc->U[j];
+        red[lane] = acc * acc;
+    }
+    __syncthreads();
+    if (lane == 0) {
+        double r2 = 0.0;
+        for (int q = 0; q < nb; ++q) r2 += red[q];
+        double nrm = 0.0;
+        for (int i = 0; i < s; ++i) nrm = fmax(nrm, fabs(sc->ritz[i]));
+        sc->lam = sc->ritz[0];
+        sc->gap = s > 1 ? sc->ritz[1] - sc->ritz[0] : 0.0;
+        sc->resid_est = sqrt(r2);
+        sc->normT = fmax(sc->normT, nrm);
+    }
+}
+
+hipError_t launch_block_ritz(const WsLayout &L, void *ws, int s, int nb, hipStream_t st)
+{
+    if (s < 1 || s > kMaxKrylov || nb < 1 || nb > kMaxBlock || s + nb > kBasisCols) return hipErrorInvalidValue;
+    k_block_ritz<<<1, 64, 0, st>>>(ws_ptr<WsScalars>(ws, L.off_scal), s, nb);
+    return hipGetLastError();
+}
+
+// Thick restart from the Ritz pairs of k_block_ritz: Vnew = [Vold Y_k, Vold[:, s:s+nb)],
+// T = [[Theta_k, E^T], [E, 0]] with E = T[s:s+nb, 0:s] Y_k.
+__global__ __launch_bounds__(kVecThreads) void k_block_restart(WsScalars *sc, const double *Vold, double *Vnew,
+                                                              int64_t ldv, int s, int k, int nb)
+{
+    __shared__ double Ys[kMaxKrylov * kMaxKrylov];
+    __shared__ double Es[kMaxBlock * kMaxKrylov];
+    for (int idx = threadIdx.x; idx < s * k; idx += kVecThreads) Ys[idx] = sc->U[idx];
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < nb * k; idx += kVecThreads) {
+        const int r = idx / k, c = idx - r * k;
+        double acc = 0.0;
+        for (int dd = 0; dd < s; ++dd) acc += sc->T[(s + r) * kTld + dd] * Ys[dd + s * c];
+        Es[idx] = acc;
+    }
+    for (int64_t i = threadIdx.x; i < ldv; i += kVecThreads) {
+        for (int c = 0; c < k; ++c) {
+            double acc = 0.0;
+            for (int dd = 0; dd < s; ++dd) acc += Vold[(int64_t)dd * ldv + i] * Ys[dd + s * c];
+            Vnew[(int64_t)c * ldv + i] = acc;
+        }
+        for (int r = 0; r < nb; ++r) Vnew[(int64_t)(k + r) * ldv + i] = Vold[(int64_t)(s + r) * ldv + i];
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < kTld * kTld; idx += kVecThreads) sc->T[idx] = 0.0;
+    __syncthreads();
+    if (threadIdx.x < k) sc->T[threadIdx.x * kTld + threadIdx.x] = sc->ritz[threadIdx.x];
+    for (int idx = threadIdx.x; idx < nb * k; idx += kVecThreads) {
+        const int r = idx / k, c = idx - r * k;
+        sc->T[(k + r) * kTld + c] = Es[idx];
+        sc->T[c * kTld + k + r] = Es[idx];
+    }
+}
+
+hipError_t launch_block_restart(const WsLayout &L, void *ws, const double *Vold, double *Vnew, int s, int k,
+                                int nb, hipStream_t st)
+{
+    if (s < 1 || s > kMaxKrylov || k < 1 || k >= s || nb < 1 || nb > kMaxBlock || s + nb > kBasisCols)
+        return hipErrorInvalidValue;
+    k_block_restart<<<1, kVecThreads, 0, st>>>(ws_ptr<WsScalars>(ws, L.off_scal), Vold, Vnew, L.ldv, s, k, nb);
+    return hipGetLastError();
+}
+
 }  // namespace irl
 
 // ---------------------------------------------------------------------------

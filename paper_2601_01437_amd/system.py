@@ -87,6 +87,13 @@ class System:
         B.irl_apply_lm_operator(self.handle, self.ws, v, yH, yS, precision)
         return yH, yS
 
+    def apply_block(self, V, precision=B.IRL_FP64):
+        """V: (nb, P+1) device float64; returns (YH, YS) of the same shape."""
+        YH = torch.empty_like(V)
+        YS = torch.empty_like(V)
+        B.irl_apply_lm_operator_block(self.handle, self.ws, V, YH, YS, precision)
+        return YH, YS
+
     def apply_hamiltonian(self, w):
         u = torch.empty_like(w)
         B.irl_apply_hamiltonian(self.handle, w, u)
@@ -94,10 +101,10 @@ class System:
 
     def step(self, theta=None, V=None, H=None, m=20, k_keep=1, tol=1e-12, max_restarts=300,
              precision=B.IRL_FP64, mode=B.IRL_MODE_A, seed=0, flags=0, ws_flags=None,
-             want_dtheta=True, want_ritz=False):
+             want_dtheta=True, want_ritz=False, block=0):
         o = B.irl_solver_opts_default()
         o.m, o.k_keep, o.tol, o.max_restarts = m, k_keep, tol, max_restarts
-        o.precision, o.mode, o.seed, o.flags = precision, mode, seed, flags
+        o.precision, o.mode, o.seed, o.flags, o.block = precision, mode, seed, flags, block
         if ws_flags is None:
             ws_flags = self.ws_flags or (B.IRL_WS_FP64 if precision == B.IRL_FP64 else B.IRL_WS_FP32)
         if theta is not None:
