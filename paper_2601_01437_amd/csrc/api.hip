@@ -272,6 +272,9 @@ WsLayout make_layout(int64_t ns, int64_t ncols, uint32_t flags)
     L.off_red = take((size_t)kScalarParts * 4 * 8);
     L.off_kry0 = take((size_t)kBasisCols * ld * 8);
     L.off_kry1 = take((size_t)kBasisCols * ld * 8);
+    L.off_img0 = take((size_t)kBasisCols * ld * 8);
+    L.off_img1 = take((size_t)kBasisCols * ld * 8);
+    L.off_hy = take((size_t)ld * 8);
     L.total = off;
     return L;
 }
@@ -299,9 +302,11 @@ int irl_solve(irl_system *s, void *ws, const WsLayout &L, const irl_solver_opts 
     // reduced-precision operator: psi row/column of H~' from the FP64 gradient (split form)
     const int split = (prec == IRL_FP32) ? 1 : 0;
     double *Vb[2] = {ws_ptr<double>(ws, L.off_kry0), ws_ptr<double>(ws, L.off_kry1)};
+    double *Ib[2] = {ws_ptr<double>(ws, L.off_img0), ws_ptr<double>(ws, L.off_img1)};
     int cur = 0;
     double *yH = ws_ptr<double>(ws, L.off_yh), *yS = ws_ptr<double>(ws, L.off_ys);
     double *y = ws_ptr<double>(ws, L.off_y), *rv = ws_ptr<double>(ws, L.off_r);
+    double *hy = ws_ptr<double>(ws, L.off_hy);
     int rc;
     TIMED(s, IRL_STAT_RITZ, st, launch_reset_solve(L, ws, st));
     if (start) {
@@ -312,12 +317,12 @@ int irl_solve(irl_system *s, void *ws, const WsLayout &L, const irl_solver_opts 
     int j0 = 0, n_apply = 0, n_restart = 0;
     bool converged = false;
     double tol_eff = o.tol;
-    // Early checks: on large operators the Ritz pair of T_j is also tested every
-    // `stride` Lanczos steps inside a cycle (an m-step cycle otherwise runs to the
-    // end before its convergence test).  A check costs one small kernel and one
+    // Early checks: on large operators the Ritz pair of T_j is also tested after
+    // every Lanczos step inside a cycle (an m-step cycle otherwise runs to the end
+    // before its convergence test).  A check costs a few small kernels and one
     // stream synchronisation, negligible next to an apply that streams >= 256 MB.
     const double apply_bytes = 2.0 * (double)L.ns * (double)L.ldv * (prec == IRL_FP64 ? 8.0 : 4.0);
-    const int stride = (o.flags & IRL_STEP_FULL_CYCLES) ? 0 : (apply_bytes >= 2.56e8 ? 2 : 0);
+    const int stride = (o.flags & IRL_STEP_FULL_CYCLES) ? 0 : (apply_bytes >= 2.56e8 ? kCheckStride : 0);
     for (;;) {
         int mc = m;   // size of the tridiagonal tested at the end of this pass
         bool early = false;
@@ -326,7 +331,7 @@ int irl_solve(irl_system *s, void *ws, const WsLayout &L, const irl_solver_opts 
             if (rc) return rc;
             ++n_apply;
             TIMED(s, IRL_STAT_LANCZOS, st,
-                  launch_lanczos_step(L, ws, Vb[cur], j, o.mode, split,
+                  launch_lanczos_step(L, ws, Vb[cur], Ib[cur], j, o.mode, split,
                                       o.seed + 0x100000001b3ull * (uint64_t)(n_restart + 1), st));
             if (stride && j + 1 < m && j + 1 >= 2 && (j + 1 - j0) % stride == 0) {
                 TIMED(s, IRL_STAT_RITZ, st, launch_ritz(L, ws, j + 1, 0, st));
@@ -351,11 +356,10 @@ int irl_solve(irl_system *s, void *ws, const WsLayout &L, const irl_solver_opts 
         out.normT = hs.normT;
         if (!std::isfinite(hs.lam)) return set_err(s, IRL_EINVAL, "non-finite Ritz value (check theta and D~)");
         if (hs.resid_est <= tol_eff) {
-            TIMED(s, IRL_STAT_RITZ, st, launch_ritz_vector(L, ws, Vb[cur], mc, y, st));
-            rc = apply_internal(s, ws, L, y, yH, yS, prec, st, split);
-            if (rc) return rc;
-            ++n_apply;
-            TIMED(s, IRL_STAT_RITZ, st, launch_residual(L, ws, y, rv, o.mode, split, st));
+            // explicit residual: the Ritz vector's image is the same combination of
+            // the stored images H~' v_j, so no further operator apply is needed
+            TIMED(s, IRL_STAT_RITZ, st, launch_ritz_vector(L, ws, Vb[cur], Ib[cur], mc, y, hy, st));
+            TIMED(s, IRL_STAT_RITZ, st, launch_residual_image(L, ws, y, hy, rv, o.mode, st));
             rc = read_scalars(s, ws, L, st);
             if (rc) return rc;
             out.resid_explicit = std::sqrt(s->host_scal->resid2);
@@ -372,7 +376,7 @@ int irl_solve(irl_system *s, void *ws, const WsLayout &L, const irl_solver_opts 
         }
         if (n_restart >= o.max_restarts) break;
         TIMED(s, IRL_STAT_RITZ, st,
-              launch_restart_basis(L, ws, Vb[cur], Vb[1 - cur], m, k, o.mode,
+              launch_restart_basis(L, ws, Vb[cur], Vb[1 - cur], Ib[cur], Ib[1 - cur], m, k, o.mode,
                                    o.seed ^ (0x9e3779b97f4a7c15ull * (uint64_t)(n_restart + 7)), st));
         cur = 1 - cur;
         j0 = k;
@@ -381,11 +385,8 @@ int irl_solve(irl_system *s, void *ws, const WsLayout &L, const irl_solver_opts 
     if (!converged) {
         // report the current Ritz pair
         TIMED(s, IRL_STAT_RITZ, st, launch_ritz(L, ws, m, 0, st));
-        TIMED(s, IRL_STAT_RITZ, st, launch_ritz_vector(L, ws, Vb[cur], m, y, st));
-        rc = apply_internal(s, ws, L, y, yH, yS, prec, st, split);
-        if (rc) return rc;
-        ++n_apply;
-        TIMED(s, IRL_STAT_RITZ, st, launch_residual(L, ws, y, rv, o.mode, split, st));
+        TIMED(s, IRL_STAT_RITZ, st, launch_ritz_vector(L, ws, Vb[cur], Ib[cur], m, y, hy, st));
+        TIMED(s, IRL_STAT_RITZ, st, launch_residual_image(L, ws, y, hy, rv, o.mode, st));
         rc = read_scalars(s, ws, L, st);
         if (rc) return rc;
         out.resid_explicit = std::sqrt(s->host_scal->resid2);
@@ -413,9 +414,11 @@ int irl_solve_block(irl_system *s, void *ws, const WsLayout &L, const irl_solver
     const double u_op = (prec == IRL_FP64) ? 1.1102230246251565e-16 : 5.960464477539063e-08;
     const int split = (prec == IRL_FP32) ? 1 : 0;
     double *Vb[2] = {ws_ptr<double>(ws, L.off_kry0), ws_ptr<double>(ws, L.off_kry1)};
+    double *Ib[2] = {ws_ptr<double>(ws, L.off_img0), ws_ptr<double>(ws, L.off_img1)};
     int cur = 0;
     double *yH = ws_ptr<double>(ws, L.off_yh), *yS = ws_ptr<double>(ws, L.off_ys);
     double *y = ws_ptr<double>(ws, L.off_y), *rv = ws_ptr<double>(ws, L.off_r);
+    double *hy = ws_ptr<double>(ws, L.off_hy);
     int rc;
     TIMED(s, IRL_STAT_RITZ, st, launch_reset_solve(L, ws, st));
     TIMED(s, IRL_STAT_RITZ, st, launch_block_start(L, ws, Vb[0], nb, o.mode, o.seed, st));
@@ -429,7 +432,7 @@ int irl_solve_block(irl_system *s, void *ws, const WsLayout &L, const irl_solver
         if (rc) return rc;
         n_apply += nb;
         TIMED(s, IRL_STAT_LANCZOS, st,
-              launch_block_step(L, ws, Vb[cur], sz, nb, o.mode, split,
+              launch_block_step(L, ws, Vb[cur], Ib[cur], sz, nb, o.mode, split,
                                 o.seed + 0x100000001b3ull * (uint64_t)(n_restart + 1), st));
         sz += nb;
         TIMED(s, IRL_STAT_RITZ, st, launch_block_ritz(L, ws, sz, nb, st));
@@ -443,11 +446,8 @@ int irl_solve_block(irl_system *s, void *ws, const WsLayout &L, const irl_solver
         out.normT = hs.normT;
         if (!std::isfinite(hs.lam)) return set_err(s, IRL_EINVAL, "non-finite Ritz value (check theta and D~)");
         if (hs.resid_est <= tol_eff) {
-            TIMED(s, IRL_STAT_RITZ, st, launch_ritz_vector(L, ws, Vb[cur], sz, y, st));
-            rc = apply_internal(s, ws, L, y, yH, yS, prec, st, split);
-            if (rc) return rc;
-            ++n_apply;
-            TIMED(s, IRL_STAT_RITZ, st, launch_residual(L, ws, y, rv, o.mode, split, st));
+            TIMED(s, IRL_STAT_RITZ, st, launch_ritz_vector(L, ws, Vb[cur], Ib[cur], sz, y, hy, st));
+            TIMED(s, IRL_STAT_RITZ, st, launch_residual_image(L, ws, y, hy, rv, o.mode, st));
             rc = read_scalars(s, ws, L, st);
             if (rc) return rc;
             out.resid_explicit = std::sqrt(s->host_scal->resid2);
@@ -458,7 +458,8 @@ int irl_solve_block(irl_system *s, void *ws, const WsLayout &L, const irl_solver
         }
         if (sz + nb > m) {
             if (n_restart >= o.max_restarts) break;
-            TIMED(s, IRL_STAT_RITZ, st, launch_block_restart(L, ws, Vb[cur], Vb[1 - cur], sz, k, nb, st));
+            TIMED(s, IRL_STAT_RITZ, st,
+                  launch_block_restart(L, ws, Vb[cur], Vb[1 - cur], Ib[cur], Ib[1 - cur], sz, k, nb, st));
             cur = 1 - cur;
             sz = k;
             ++n_restart;
@@ -466,11 +467,8 @@ int irl_solve_block(irl_system *s, void *ws, const WsLayout &L, const irl_solver
     }
     if (!converged) {
         TIMED(s, IRL_STAT_RITZ, st, launch_block_ritz(L, ws, sz, nb, st));
-        TIMED(s, IRL_STAT_RITZ, st, launch_ritz_vector(L, ws, Vb[cur], sz, y, st));
-        rc = apply_internal(s, ws, L, y, yH, yS, prec, st, split);
-        if (rc) return rc;
-        ++n_apply;
-        TIMED(s, IRL_STAT_RITZ, st, launch_residual(L, ws, y, rv, o.mode, split, st));
+        TIMED(s, IRL_STAT_RITZ, st, launch_ritz_vector(L, ws, Vb[cur], Ib[cur], sz, y, hy, st));
+        TIMED(s, IRL_STAT_RITZ, st, launch_residual_image(L, ws, y, hy, rv, o.mode, st));
         rc = read_scalars(s, ws, L, st);
         if (rc) return rc;
         out.resid_explicit = std::sqrt(s->host_scal->resid2);
@@ -1072,7 +1070,7 @@ int irl_debug_lanczos(irl_system *s, void *ws, size_t ws_bytes, const double *v1
     for (int j = 0; j < j_end; ++j) {
         rc = apply_internal(s, ws, L, V + (int64_t)j * L.ldv, yH, yS, precision, st, split);
         if (rc) return rc;
-        CK(s, launch_lanczos_step(L, ws, V, j, mode, split, 12345, st));
+        CK(s, launch_lanczos_step(L, ws, V, ws_ptr<double>(ws, L.off_img0), j, mode, split, 12345, st));
     }
     rc = read_scalars(s, ws, L, st);
     if (rc) return rc;
@@ -1368,7 +1366,7 @@ int batch_solve(irl_batch *b, const irl_solver_opts &o, int prec, bool from_y,
     std::vector<int> stride(B);
     for (int i = 0; i < B; ++i) {
         const double apply_bytes = 2.0 * (double)b->hm[i].ns * (double)b->hm[i].ld * (prec == IRL_FP64 ? 8.0 : 4.0);
-        stride[i] = (o.flags & IRL_STEP_FULL_CYCLES) ? 0 : (apply_bytes >= 2.56e8 ? 2 : 0);
+        stride[i] = (o.flags & IRL_STEP_FULL_CYCLES) ? 0 : (apply_bytes >= 2.56e8 ? kCheckStride : 0);
     }
     out.assign(B, MemberSolve());
     std::vector<int> active(B);
@@ -1387,15 +1385,12 @@ int batch_solve(irl_batch *b, const irl_solver_opts &o, int prec, bool from_y,
         int r2 = build_lists(b, cand, 1, prec, lc, st);
         if (r2) return r2;
         TIMED(s0, IRL_STAT_RITZ, st, launch_lanczos_grouped(kGrpRitzVector, b->dm, lc.ptr(b, LS_VEC), lc.cnt[LS_VEC], cur, mc, 0, 0, 0, nullptr, st));
-        r2 = batch_apply(b, lc, 1, 0, cur, split, prec, st);
-        if (r2) return r2;
-        TIMED(s0, IRL_STAT_RITZ, st, launch_lanczos_grouped(kGrpResidual, b->dm, lc.ptr(b, LS_VEC), lc.cnt[LS_VEC], o.mode, split, 0, 0, 0, nullptr, st));
+        TIMED(s0, IRL_STAT_RITZ, st, launch_lanczos_grouped(kGrpResidual, b->dm, lc.ptr(b, LS_VEC), lc.cnt[LS_VEC], o.mode, 0, 0, 0, 0, nullptr, st));
         r2 = gather(b, lc, st);
         if (r2) return r2;
         std::vector<int> still;
         for (int i : cand) {
             MemberSolve &ms = out[i];
-            ms.n_apply += 1;
             ms.resid_explicit = std::sqrt(b->hscal[i].resid2);
             ms.c0 = b->hscal[i].c0;
             const double tol_explicit = std::max(ms.tol_used, 1024.0 * u_op * ms.normT);
@@ -1450,7 +1445,7 @@ int batch_solve(irl_batch *b, const irl_solver_opts &o, int prec, bool from_y,
             for (int i : active) out[i].n_apply += 1;
             TIMED(s0, IRL_STAT_LANCZOS, st, launch_lanczos_grouped(kGrpLanczos, b->dm, la.ptr(b, LS_VEC), la.cnt[LS_VEC], j, cur, o.mode, split,
                                           o.seed + 0x100000001b3ull * (uint64_t)(n_restart + 1), nullptr, st));
-            if (j + 1 < m && j + 1 >= 2 && (j + 1 - j0) % 2 == 0) {
+            if (j + 1 < m && j + 1 >= 2 && (j + 1 - j0) % kCheckStride == 0) {
                 std::vector<int> who;
                 for (int i : active)
                     if (stride[i]) who.push_back(i);
@@ -1529,6 +1524,9 @@ int irl_batch_create(int32_t count, irl_system *const *systems, const irl_nqs_de
         mb.yH = ws_ptr<double>(ws[i], L.off_yh);
         mb.yS = ws_ptr<double>(ws[i], L.off_ys);
         mb.y = ws_ptr<double>(ws[i], L.off_y);
+        mb.hy = ws_ptr<double>(ws[i], L.off_hy);
+        mb.img[0] = ws_ptr<double>(ws[i], L.off_img0);
+        mb.img[1] = ws_ptr<double>(ws[i], L.off_img1);
         mb.r = ws_ptr<double>(ws[i], L.off_r);
         mb.part = ws_ptr<double>(ws[i], L.off_part);
         mb.part2 = ws_ptr<double>(ws[i], L.off_part2);

@@ -15,6 +15,7 @@ namespace irl {
 constexpr int kMaxKrylov = 64;          // m <= 64
 constexpr int kMaxBlock = 8;            // vectors per multi-vector apply / block Lanczos step
 constexpr int kBasisCols = kMaxKrylov + kMaxBlock;   // Krylov basis columns held per buffer
+constexpr int kCheckStride = 1;         // Lanczos steps between in-cycle convergence tests (large operators)
 constexpr int kWave = 64;               // CDNA wavefront width
 constexpr int kStreamBlocks = 512;      // row blocks of the D~^T stream kernel
 constexpr int kReduceGroups = 16;       // first-level groups of the partial reduction
@@ -56,7 +57,8 @@ struct WsLayout {
     uint32_t flags = 0;
     size_t off_scal = 0, off_d64 = 0, off_d32 = 0, off_psi = 0, off_hpsi = 0, off_w = 0,
            off_u = 0, off_grad = 0, off_yh = 0, off_ys = 0, off_y = 0, off_r = 0,
-           off_part = 0, off_part2 = 0, off_red = 0, off_kry0 = 0, off_kry1 = 0, off_vconv = 0;
+           off_part = 0, off_part2 = 0, off_red = 0, off_kry0 = 0, off_kry1 = 0, off_vconv = 0,
+           off_img0 = 0, off_img1 = 0, off_hy = 0;   // operator images of the basis; of y
     size_t total = 0;
 };
 
@@ -140,6 +142,8 @@ struct Member {
     int64_t ld, ncols, ns;
     double *psi, *hpsi, *w, *u, *grad, *yH, *yS, *y, *r, *part, *part2, *red, *vconv;
     double *kry[2];
+    double *img[2];   // operator images of the basis vectors
+    double *hy;       // operator image of the Ritz vector
     WsScalars *sc;
     int32_t V, H;
     double *theta;
@@ -226,11 +230,11 @@ hipError_t launch_t2_reduce_multi(const WsLayout &L, void *ws, int nblk, int nb,
 // block Lanczos (one workgroup each): start block, step, Ritz pairs of T, thick restart
 hipError_t launch_block_start(const WsLayout &L, void *ws, double *V, int nb, int mode, uint64_t seed,
                               hipStream_t st);
-hipError_t launch_block_step(const WsLayout &L, void *ws, double *V, int s0, int nb, int mode, int split,
-                             uint64_t seed, hipStream_t st);
+hipError_t launch_block_step(const WsLayout &L, void *ws, double *V, double *img, int s0, int nb, int mode,
+                             int split, uint64_t seed, hipStream_t st);
 hipError_t launch_block_ritz(const WsLayout &L, void *ws, int s, int nb, hipStream_t st);
-hipError_t launch_block_restart(const WsLayout &L, void *ws, const double *Vold, double *Vnew, int s,
-                                int k, int nb, hipStream_t st);
+hipError_t launch_block_restart(const WsLayout &L, void *ws, const double *Vold, double *Vnew,
+                                const double *Iold, double *Inew, int s, int k, int nb, hipStream_t st);
 // stored rows: per-row counts of connections inside the set, then the fill
 hipError_t launch_ham_count(const irl_system *s, int32_t *count, hipStream_t st);
 hipError_t launch_ham_fill(const irl_system *s, const int64_t *ptr, int32_t *col, double *val,
@@ -267,15 +271,16 @@ hipError_t launch_start_vector(double *v, int64_t L, int64_t ldv, int mode, uint
                                hipStream_t st);
 // split: w = H~'v assembled as [g.v[1:]/2 ; g v0/2 + H_eff v[1:]] with g in FP64 (the
 // operator pair then comes from an apply of (0, v[1:]))
-hipError_t launch_lanczos_step(const WsLayout &L, void *ws, double *V, int j, int mode, int split,
-                               uint64_t seed, hipStream_t st);
+hipError_t launch_lanczos_step(const WsLayout &L, void *ws, double *V, double *img, int j, int mode,
+                               int split, uint64_t seed, hipStream_t st);
 hipError_t launch_ritz(const WsLayout &L, void *ws, int m, int k, hipStream_t st);
 hipError_t launch_restart_basis(const WsLayout &L, void *ws, const double *Vold, double *Vnew,
-                                int m, int k, int mode, uint64_t seed, hipStream_t st);
-hipError_t launch_ritz_vector(const WsLayout &L, void *ws, const double *V, int m, double *y,
-                              hipStream_t st);
-hipError_t launch_residual(const WsLayout &L, void *ws, const double *y, double *r, int mode,
-                           int split, hipStream_t st);
+                                const double *Iold, double *Inew, int m, int k, int mode, uint64_t seed,
+                                hipStream_t st);
+hipError_t launch_ritz_vector(const WsLayout &L, void *ws, const double *V, const double *img, int m,
+                              double *y, double *hy, hipStream_t st);
+hipError_t launch_residual_image(const WsLayout &L, void *ws, const double *y, const double *hy, double *r,
+                                 int mode, hipStream_t st);
 hipError_t launch_update(const WsLayout &L, void *ws, const double *y, double *dtheta,
                          double *theta, int64_t P, int mode, hipStream_t st);
 hipError_t launch_copy(double *dst, const double *src, int64_t n, hipStream_t st);

@@ -154,9 +154,12 @@ hipError_t launch_start_vector(double *v, int64_t ncols, int64_t ldv, int mode, 
 }
 
 // One Lanczos step j: w = H~' v_j from (yH, yS), recurrence, CGS2, normalise.
+// img (column j of the image basis): a copy of H~' v_j, so that the image of any
+// combination of basis vectors (a Ritz vector) is the same combination of images.
 __device__ void lanczos_step_body(
     const double *__restrict__ yH, const double *__restrict__ yS, const double *__restrict__ grad,
-    WsScalars *sc, double *V, int64_t ldv, int64_t ncols, int j, int mode, int split, uint64_t seed)
+    WsScalars *sc, double *V, double *img, int64_t ldv, int64_t ncols, int j, int mode, int split,
+    uint64_t seed)
 {
     __shared__ double sh[kVecWaves * (kMaxKrylov + 1)];
     __shared__ double hsh[kMaxKrylov + 1];
@@ -171,6 +174,7 @@ __device__ void lanczos_step_body(
         double x = (i < ncols) ? centred_component(i, yH, yS, grad, v0, gdotv, Z, E, split) : 0.0;
         if (mode == IRL_MODE_P && i == 0) x = 0.0;
         w[i] = x;
+        img[(int64_t)j * ldv + i] = x;
         pa += vj[i] * x;
     }
     double alpha = block_sum(pa, sh);
@@ -203,17 +207,18 @@ __device__ void lanczos_step_body(
 
 __global__ __launch_bounds__(kVecThreads) void k_lanczos_step(
     const double *__restrict__ yH, const double *__restrict__ yS, const double *__restrict__ grad,
-    WsScalars *sc, double *V, int64_t ldv, int64_t ncols, int j, int mode, int split, uint64_t seed)
+    WsScalars *sc, double *V, double *img, int64_t ldv, int64_t ncols, int j, int mode, int split,
+    uint64_t seed)
 {
-    lanczos_step_body(yH, yS, grad, sc, V, ldv, ncols, j, mode, split, seed);
+    lanczos_step_body(yH, yS, grad, sc, V, img, ldv, ncols, j, mode, split, seed);
 }
 
-hipError_t launch_lanczos_step(const WsLayout &L, void *ws, double *V, int j, int mode, int split,
-                               uint64_t seed, hipStream_t st)
+hipError_t launch_lanczos_step(const WsLayout &L, void *ws, double *V, double *img, int j, int mode,
+                               int split, uint64_t seed, hipStream_t st)
 {
     k_lanczos_step<<<1, kVecThreads, 0, st>>>(ws_ptr<double>(ws, L.off_yh), ws_ptr<double>(ws, L.off_ys),
                                                ws_ptr<double>(ws, L.off_grad),
-                                               ws_ptr<WsScalars>(ws, L.off_scal), V, L.ldv, L.ncols,
+                                               ws_ptr<WsScalars>(ws, L.off_scal), V, img, L.ldv, L.ncols,
                                                j, mode, split, seed);
     return hipGetLastError();
 }
@@ -360,10 +365,9 @@ hipError_t launch_ritz(const WsLayout &L, void *ws, int m, int k, hipStream_t st
 
 // V+ = V Q[:, :k], f = V Q[:, k] * T+[k][k-1] + beta_m Q[m-1][k-1] v_{m+1},
 // v_{k+1} = f / ||f|| (reorthogonalised), T <- leading k x k of Q^T T Q.
-__device__ void restart_basis_body(WsScalars *sc, const double *Vold,
-                                                              double *Vnew, int64_t ldv,
-                                                              int64_t ncols, int m, int k, int mode,
-                                                              uint64_t seed)
+__device__ void restart_basis_body(WsScalars *sc, const double *Vold, double *Vnew,
+                                   const double *Iold, double *Inew, int64_t ldv, int64_t ncols,
+                                   int m, int k, int mode, uint64_t seed)
 {
     __shared__ double sh[kVecWaves * (kMaxKrylov + 1)];
     __shared__ double hsh[kMaxKrylov + 1];
@@ -381,6 +385,12 @@ __device__ void restart_basis_body(WsScalars *sc, const double *Vold,
                 Vnew[(int64_t)i * ldv + c] = acc;
             else
                 f[c] = acc * bk + sig * Vold[(int64_t)m * ldv + c];
+        }
+        // images of the kept vectors: the same combinations of the old images
+        for (int i = 0; i < k; ++i) {
+            double acc = 0.0;
+            for (int l = 0; l < m; ++l) acc += Iold[(int64_t)l * ldv + c] * Qs[l + m * i];
+            Inew[(int64_t)i * ldv + c] = acc;
         }
     }
     __syncthreads();
@@ -408,89 +418,90 @@ __device__ void restart_basis_body(WsScalars *sc, const double *Vold,
 }
 
 __global__ __launch_bounds__(kVecThreads) void k_restart_basis(WsScalars *sc, const double *Vold,
-                                                              double *Vnew, int64_t ldv,
-                                                              int64_t ncols, int m, int k, int mode,
-                                                              uint64_t seed)
+                                                              double *Vnew, const double *Iold,
+                                                              double *Inew, int64_t ldv, int64_t ncols,
+                                                              int m, int k, int mode, uint64_t seed)
 {
-    restart_basis_body(sc, Vold, Vnew, ldv, ncols, m, k, mode, seed);
+    restart_basis_body(sc, Vold, Vnew, Iold, Inew, ldv, ncols, m, k, mode, seed);
 }
 
 hipError_t launch_restart_basis(const WsLayout &L, void *ws, const double *Vold, double *Vnew,
-                                int m, int k, int mode, uint64_t seed, hipStream_t st)
+                                const double *Iold, double *Inew, int m, int k, int mode, uint64_t seed,
+                                hipStream_t st)
 {
-    k_restart_basis<<<1, kVecThreads, 0, st>>>(ws_ptr<WsScalars>(ws, L.off_scal), Vold, Vnew, L.ldv,
-                                               L.ncols, m, k, mode, seed);
+    k_restart_basis<<<1, kVecThreads, 0, st>>>(ws_ptr<WsScalars>(ws, L.off_scal), Vold, Vnew, Iold, Inew,
+                                               L.ldv, L.ncols, m, k, mode, seed);
     return hipGetLastError();
 }
 
-// y = V U[:, 0] normalised; c0 = y[0]
-__device__ void ritz_vector_body(WsScalars *sc, const double *V,
-                                                            int64_t ldv, int m, double *y)
+// y = V U[:, 0] normalised, c0 = y[0]; hy = img U[:, 0] with the same scale:
+// the operator image of y, formed from the images of the basis vectors
+__device__ void ritz_vector_body(WsScalars *sc, const double *V, const double *img, int64_t ldv,
+                                 int m, double *y, double *hy)
 {
     __shared__ double sh[kVecWaves * (kMaxKrylov + 1)];
     double p = 0.0;
     for (int64_t c = threadIdx.x; c < ldv; c += kVecThreads) {
-        double acc = 0.0;
-        for (int l = 0; l < m; ++l) acc += V[(int64_t)l * ldv + c] * sc->U[l];
+        double acc = 0.0, acch = 0.0;
+        for (int l = 0; l < m; ++l) {
+            acc += V[(int64_t)l * ldv + c] * sc->U[l];
+            acch += img[(int64_t)l * ldv + c] * sc->U[l];
+        }
         y[c] = acc;
+        hy[c] = acch;
         p += acc * acc;
     }
     double nrm = sqrt(block_sum(p, sh));
-    for (int64_t c = threadIdx.x; c < ldv; c += kVecThreads) y[c] /= nrm;
+    for (int64_t c = threadIdx.x; c < ldv; c += kVecThreads) {
+        y[c] /= nrm;
+        hy[c] /= nrm;
+    }
     __syncthreads();
     if (threadIdx.x == 0) sc->c0 = y[0];
 }
 
 __global__ __launch_bounds__(kVecThreads) void k_ritz_vector(WsScalars *sc, const double *V,
-                                                            int64_t ldv, int m, double *y)
+                                                            const double *img, int64_t ldv, int m,
+                                                            double *y, double *hy)
 {
-    ritz_vector_body(sc, V, ldv, m, y);
+    ritz_vector_body(sc, V, img, ldv, m, y, hy);
 }
 
-hipError_t launch_ritz_vector(const WsLayout &L, void *ws, const double *V, int m, double *y,
-                              hipStream_t st)
+hipError_t launch_ritz_vector(const WsLayout &L, void *ws, const double *V, const double *img, int m,
+                              double *y, double *hy, hipStream_t st)
 {
-    k_ritz_vector<<<1, kVecThreads, 0, st>>>(ws_ptr<WsScalars>(ws, L.off_scal), V, L.ldv, m, y);
+    k_ritz_vector<<<1, kVecThreads, 0, st>>>(ws_ptr<WsScalars>(ws, L.off_scal), V, img, L.ldv, m, y, hy);
     return hipGetLastError();
 }
 
-// r = H~'y - lam y from (yH, yS); resid2 = ||r||^2
-__device__ void residual_body(WsScalars *sc, const double *yH,
-                                                         const double *yS, const double *grad,
-                                                         const double *y, double *r, int64_t ldv,
-                                                         int64_t ncols, int mode, int split)
+// r = hy - lam y with hy = H~' y; resid2 = ||r||^2
+__device__ void residual_image_body(WsScalars *sc, const double *y, const double *hy, double *r,
+                                    int64_t ldv, int mode)
 {
     __shared__ double sh[kVecWaves * (kMaxKrylov + 1)];
-    const double Z = sc->Z, E = sc->E_el, lam = sc->lam;
-    const double gdotv = split ? grad_dot(grad, y, ncols, sh) : 0.0;
-    const double v0 = y[0];
+    const double lam = sc->lam;
     double p = 0.0;
     for (int64_t c = threadIdx.x; c < ldv; c += kVecThreads) {
-        double x = c < ncols ? centred_component(c, yH, yS, grad, v0, gdotv, Z, E, split) - lam * y[c]
-                             : 0.0;
+        double x = hy[c] - lam * y[c];
         if (mode == IRL_MODE_P && c == 0) x = 0.0;
         r[c] = x;
         p += x * x;
     }
-    double s = block_sum(p, sh);
+    const double s = block_sum(p, sh);
     if (threadIdx.x == 0) sc->resid2 = s;
 }
 
-__global__ __launch_bounds__(kVecThreads) void k_residual(WsScalars *sc, const double *yH,
-                                                         const double *yS, const double *grad,
-                                                         const double *y, double *r, int64_t ldv,
-                                                         int64_t ncols, int mode, int split)
+__global__ __launch_bounds__(kVecThreads) void k_residual_image(WsScalars *sc, const double *y,
+                                                               const double *hy, double *r, int64_t ldv,
+                                                               int mode)
 {
-    residual_body(sc, yH, yS, grad, y, r, ldv, ncols, mode, split);
+    residual_image_body(sc, y, hy, r, ldv, mode);
 }
 
-hipError_t launch_residual(const WsLayout &L, void *ws, const double *y, double *r, int mode,
-                           int split, hipStream_t st)
+hipError_t launch_residual_image(const WsLayout &L, void *ws, const double *y, const double *hy, double *r,
+                                 int mode, hipStream_t st)
 {
-    k_residual<<<1, kVecThreads, 0, st>>>(ws_ptr<WsScalars>(ws, L.off_scal),
-                                          ws_ptr<double>(ws, L.off_yh), ws_ptr<double>(ws, L.off_ys),
-                                          ws_ptr<double>(ws, L.off_grad), y, r, L.ldv, L.ncols, mode,
-                                          split);
+    k_residual_image<<<1, kVecThreads, 0, st>>>(ws_ptr<WsScalars>(ws, L.off_scal), y, hy, r, L.ldv, mode);
     return hipGetLastError();
 }
 
@@ -650,8 +661,8 @@ hipError_t launch_block_start(const WsLayout &L, void *ws, double *V, int nb, in
 // columns [s0 + nb, s0 + 2 nb).
 __global__ __launch_bounds__(kVecThreads) void k_block_step(
     const double *__restrict__ yH, const double *__restrict__ yS, int64_t ldy,
-    const double *__restrict__ grad, WsScalars *sc, double *V, int64_t ldv, int64_t ncols, int s0, int nb,
-    int mode, int split, uint64_t seed)
+    const double *__restrict__ grad, WsScalars *sc, double *V, double *img, int64_t ldv, int64_t ncols,
+    int s0, int nb, int mode, int split, uint64_t seed)
 {
     __shared__ double sh[kVecWaves * kBSh];
     __shared__ double hsh[kBSh];
@@ -671,6 +682,7 @@ __global__ __launch_bounds__(kVecThreads) void k_block_step(
                                    : 0.0;
             if (mode == IRL_MODE_P && i == 0) x = 0.0;
             z[i] = x;
+            img[(int64_t)(s0 + q) * ldv + i] = x;
         }
         __syncthreads();
     }
@@ -736,14 +748,14 @@ __global__ __launch_bounds__(kVecThreads) void k_block_step(
     }
 }
 
-hipError_t launch_block_step(const WsLayout &L, void *ws, double *V, int s0, int nb, int mode, int split,
-                             uint64_t seed, hipStream_t st)
+hipError_t launch_block_step(const WsLayout &L, void *ws, double *V, double *img, int s0, int nb, int mode,
+                             int split, uint64_t seed, hipStream_t st)
 {
     if (nb < 1 || nb > kMaxBlock || s0 < 0 || s0 + 2 * nb > kBasisCols || s0 + nb > kMaxKrylov)
         return hipErrorInvalidValue;
     k_block_step<<<1, kVecThreads, 0, st>>>(ws_ptr<double>(ws, L.off_yh), ws_ptr<double>(ws, L.off_ys), L.ldv,
                                             ws_ptr<double>(ws, L.off_grad), ws_ptr<WsScalars>(ws, L.off_scal),
-                                            V, L.ldv, L.ncols, s0, nb, mode, split, seed);
+                                            V, img, L.ldv, L.ncols, s0, nb, mode, split, seed);
     return hipGetLastError();
 }
 
@@ -852,7 +864,8 @@ hipError_t launch_block_ritz(const WsLayout &L, void *ws, int s, int nb, hipStre
 // Thick restart from the Ritz pairs of k_block_ritz: Vnew = [Vold Y_k, Vold[:, s:s+nb)],
 // T = [[Theta_k, E^T], [E, 0]] with E = T[s:s+nb, 0:s] Y_k.
 __global__ __launch_bounds__(kVecThreads) void k_block_restart(WsScalars *sc, const double *Vold, double *Vnew,
-                                                              int64_t ldv, int s, int k, int nb)
+                                                              const double *Iold, double *Inew, int64_t ldv,
+                                                              int s, int k, int nb)
 {
     __shared__ double Ys[kMaxKrylov * kMaxKrylov];
     __shared__ double Es[kMaxBlock * kMaxKrylov];
@@ -866,9 +879,13 @@ __global__ __launch_bounds__(kVecThreads) void k_block_restart(WsScalars *sc, co
     }
     for (int64_t i = threadIdx.x; i < ldv; i += kVecThreads) {
         for (int c = 0; c < k; ++c) {
-            double acc = 0.0;
-            for (int dd = 0; dd < s; ++dd) acc += Vold[(int64_t)dd * ldv + i] * Ys[dd + s * c];
+            double acc = 0.0, acci = 0.0;
+            for (int dd = 0; dd < s; ++dd) {
+                acc += Vold[(int64_t)dd * ldv + i] * Ys[dd + s * c];
+                acci += Iold[(int64_t)dd * ldv + i] * Ys[dd + s * c];
+            }
             Vnew[(int64_t)c * ldv + i] = acc;
+            Inew[(int64_t)c * ldv + i] = acci;
         }
         for (int r = 0; r < nb; ++r) Vnew[(int64_t)(k + r) * ldv + i] = Vold[(int64_t)(s + r) * ldv + i];
     }
@@ -883,12 +900,13 @@ __global__ __launch_bounds__(kVecThreads) void k_block_restart(WsScalars *sc, co
     }
 }
 
-hipError_t launch_block_restart(const WsLayout &L, void *ws, const double *Vold, double *Vnew, int s, int k,
-                                int nb, hipStream_t st)
+hipError_t launch_block_restart(const WsLayout &L, void *ws, const double *Vold, double *Vnew,
+                                const double *Iold, double *Inew, int s, int k, int nb, hipStream_t st)
 {
     if (s < 1 || s > kMaxKrylov || k < 1 || k >= s || nb < 1 || nb > kMaxBlock || s + nb > kBasisCols)
         return hipErrorInvalidValue;
-    k_block_restart<<<1, kVecThreads, 0, st>>>(ws_ptr<WsScalars>(ws, L.off_scal), Vold, Vnew, L.ldv, s, k, nb);
+    k_block_restart<<<1, kVecThreads, 0, st>>>(ws_ptr<WsScalars>(ws, L.off_scal), Vold, Vnew, Iold, Inew, L.ldv,
+                                               s, k, nb);
     return hipGetLastError();
 }
 
@@ -930,8 +948,8 @@ __global__ __launch_bounds__(kVecThreads) void k_lanczos_step_grouped(
     int split, uint64_t seed)
 {
     const Member &mb = M[items[blockIdx.x].m];
-    lanczos_step_body(mb.yH, mb.yS, mb.grad, mb.sc, mb.kry[cur], mb.ld, mb.ncols, j, mode, split,
-                      seed);
+    lanczos_step_body(mb.yH, mb.yS, mb.grad, mb.sc, mb.kry[cur], mb.img[cur], mb.ld, mb.ncols, j, mode,
+                      split, seed);
 }
 
 __global__ __launch_bounds__(64) void k_ritz_grouped(const Member *__restrict__ M,
@@ -946,21 +964,22 @@ __global__ __launch_bounds__(kVecThreads) void k_restart_basis_grouped(
     int mode, uint64_t seed)
 {
     const Member &mb = M[items[blockIdx.x].m];
-    restart_basis_body(mb.sc, mb.kry[cur], mb.kry[1 - cur], mb.ld, mb.ncols, m, k, mode, seed);
+    restart_basis_body(mb.sc, mb.kry[cur], mb.kry[1 - cur], mb.img[cur], mb.img[1 - cur], mb.ld, mb.ncols, m,
+                       k, mode, seed);
 }
 
 __global__ __launch_bounds__(kVecThreads) void k_ritz_vector_grouped(
     const Member *__restrict__ M, const WorkItem *__restrict__ items, int cur, int m)
 {
     const Member &mb = M[items[blockIdx.x].m];
-    ritz_vector_body(mb.sc, mb.kry[cur], mb.ld, m, mb.y);
+    ritz_vector_body(mb.sc, mb.kry[cur], mb.img[cur], mb.ld, m, mb.y, mb.hy);
 }
 
 __global__ __launch_bounds__(kVecThreads) void k_residual_grouped(
-    const Member *__restrict__ M, const WorkItem *__restrict__ items, int mode, int split)
+    const Member *__restrict__ M, const WorkItem *__restrict__ items, int mode)
 {
     const Member &mb = M[items[blockIdx.x].m];
-    residual_body(mb.sc, mb.yH, mb.yS, mb.grad, mb.y, mb.r, mb.ld, mb.ncols, mode, split);
+    residual_image_body(mb.sc, mb.y, mb.hy, mb.r, mb.ld, mode);
 }
 
 __global__ void k_update_grouped(const Member *__restrict__ M, const WorkItem *__restrict__ items)
@@ -1004,7 +1023,7 @@ hipError_t launch_lanczos_grouped(int op, const Member *M, const WorkItem *items
     case kGrpRitz: k_ritz_grouped<<<nitems, 64, 0, st>>>(M, items, i0, i1); break;
     case kGrpRestart: k_restart_basis_grouped<<<nitems, kVecThreads, 0, st>>>(M, items, i0, i1, i2, i3, seed); break;
     case kGrpRitzVector: k_ritz_vector_grouped<<<nitems, kVecThreads, 0, st>>>(M, items, i0, i1); break;
-    case kGrpResidual: k_residual_grouped<<<nitems, kVecThreads, 0, st>>>(M, items, i0, i1); break;
+    case kGrpResidual: k_residual_grouped<<<nitems, kVecThreads, 0, st>>>(M, items, i0); break;
     case kGrpUpdate: k_update_grouped<<<nitems, 256, 0, st>>>(M, items); break;
     case kGrpGather: k_gather_scalars<<<nitems, 64, 0, st>>>(M, items, out); break;
     default: return hipErrorInvalidValue;
