@@ -108,6 +108,32 @@ def cpu_baseline(wl, keys_fn, applies_per_step, sample_rows=1_000_000, chunk=20_
     per_eval = (t_build + t_h + t_dt) * scale          # D~, H psi, gradient pass
     per_step = applies_per_step * per_apply + per_eval
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    # the same apply on one thread (OpenMP and BLAS limited), on a smaller sample
+    one = None
+    try:
+        from threadpoolctl import threadpool_limits
+        rs = rows[: max(1, min(rows.size, 20_000))]
+        with threadpool_limits(limits=1):
+            t = time.perf_counter()
+            D = nqs.dtilde(keys[rs], wl.n, wl.V, wl.H, theta)
+            t_b1 = time.perf_counter() - t
+            t = time.perf_counter()
+            w = D @ v
+            u = capply.apply(wl.n, h, g, keys, wfull, rows=rs)
+            _ = D.T @ np.stack([w, u], axis=1)
+            t_a1 = time.perf_counter() - t
+        one = {"ms_per_apply": t_a1 * ns / rs.size * 1e3, "ms_dtilde_build": t_b1 * ns / rs.size * 1e3,
+               "sample_rows": int(rs.size)}
+    except ImportError:
+        pass
+    cpu_model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu_model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {
         "value": 1.0 / per_step,
         "unit": "IRL steps/s",
@@ -119,6 +145,8 @@ def cpu_baseline(wl, keys_fn, applies_per_step, sample_rows=1_000_000, chunk=20_
                    f"per step (apply count from the GPU run)"),
         "ms_per_apply": per_apply * 1e3,
         "ms_per_step": per_step * 1e3,
+        "one_thread": one,
+        "host": {"cpu_model": cpu_model, "logical_cpus": os.cpu_count()},
     }
 
 

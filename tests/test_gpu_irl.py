@@ -131,3 +131,25 @@ def test_selected_set_step():
     assert abs(r.E_before - res.E) <= 1e-12
     assert abs(r.lambda_min - res.lam) <= 1e-10 * max(abs(res.lam), np.linalg.norm(res.Hp, 2))
     assert abs(r.E_after - E_after) <= 1e-12
+
+
+@pytest.mark.parametrize("block", [0, 4])
+def test_trajectory_c1_matches_oracle(c1_problem, block):
+    """Four consecutive optimisation steps (theta updated in place on the GPU)
+    follow the oracle's trajectory: energies and eigenvalues of every step within
+    1e-9 (differences of 1e-12 per step compound through the updates)."""
+    from paper_2601_01437_amd import IRL_WS_BLOCK, IRL_WS_FP64
+    announce(f"trajectory c1 block={block}")
+    p = c1_problem
+    w = p["w"]
+    energies, lams, thetas = step.trajectory(p["keys"], w.n, w.V, w.H, p["theta"], p["H"], steps=4)
+    s, _, _ = make_system(8, 4, 4)
+    theta = dev(p["theta"])
+    fl = IRL_WS_FP64 | (IRL_WS_BLOCK if block else 0)
+    for t in range(4):
+        rc, r, _, _ = s.step(theta, w.V, w.H, m=20, k_keep=4, block=block, ws_flags=fl)
+        assert r.converged == 1
+        assert abs(r.E_before - energies[t]) <= 1e-9, t
+        assert abs(r.lambda_min - lams[t]) <= 1e-9 * max(1.0, abs(lams[t])), t
+        assert abs(r.E_after - energies[t + 1]) <= 1e-9, t
+    assert rel_err(host(theta), thetas[-1]) <= 1e-8

@@ -152,3 +152,25 @@ def test_c1_step_runs(c1_problem):
     s = np.linalg.eigvalsh(res.St)
     assert s[0] >= -1e-12 * s[-1]                  # S~ is positive semidefinite
     assert np.isfinite(E_after)
+
+
+def test_trajectory_towards_fci_small():
+    """End-to-end report on a tiny system (4 orbitals, 2+2 electrons, 36
+    determinants, V = 8, H = 8): consecutive mode-A steps lower the energy
+    towards the exact ground state.  Reported, gated only on a decrease; a
+    shallow network may stop short of E_FCI at a local minimum."""
+    import scipy.sparse.linalg  # noqa: F401
+    from oracle import hamiltonian, space, step
+    import synth
+    n, na, nb, V, H = 4, 2, 2, 8, 8
+    h, g = synth.integrals(n, 11)
+    keys = space.full_space(n, na, nb)
+    Hm = hamiltonian.build(keys, n, h, g)
+    e_fci = np.linalg.eigvalsh(Hm.toarray())[0]
+    theta = synth.nqs_theta(V, H, 11, scale=0.3)
+    energies, lams, _ = step.trajectory(keys, n, V, H, theta, Hm, steps=12)
+    print(f"E - E_FCI per step: {np.array2string(energies - e_fci, precision=3)}")
+    assert np.all(energies >= e_fci - 1e-10)          # variational
+    assert energies[-1] < energies[0]
+    assert energies[-1] - e_fci < 0.5 * (energies[0] - e_fci)
+    assert np.all(lams <= 1e-12)                       # mode A: predicted decrease is never positive
