@@ -15,6 +15,93 @@ namespace irl {
 
 constexpr int kMaxHidden = 1024;
 
+// Row write of D~ = [psi, x, 1 - t^2, (1 - t^2) (x) x]: each lane owns CPL
+// consecutive columns per pass, so every store instruction of the wave covers
+// 64 * 16 contiguous bytes (CPL = 2: FP64 copy, plus the FP32 copy when present;
+// CPL = 4: FP32 copy only).  Inside the W block (column 1 + V + H + h V + v) the
+// lane tracks (h, v) incrementally.
+template <int CPL>
+__device__ __forceinline__ void write_row(uint64_t xm, int64_t row, int V, int H, double psi,
+                                          const double *dsh, double *__restrict__ D64, int64_t ld64,
+                                          float *__restrict__ D32, int64_t ld32, int lane)
+{
+    const int64_t P1 = (int64_t)V * H + H + V + 1;
+    const int baseW = V + H + 1;
+    const int64_t ldw = D64 ? ld64 : ld32;
+    constexpr int kStep = CPL * kWave;
+    const int qh = kStep / V, rv = kStep - qh * V;   // (h, v) advance per pass
+    int64_t c0 = CPL * lane;
+    int hh = 0, vv = 0;
+    if (c0 >= baseW) {
+        const int idx = (int)(c0 - baseW);
+        hh = idx / V;
+        vv = idx - hh * V;
+    }
+    for (; c0 < ldw; c0 += kStep) {
+        double val[CPL];
+        if (c0 >= baseW && c0 + CPL - 1 < P1) {
+            int h2 = hh, v2 = vv;
+#pragma unroll
+            for (int q = 0; q < CPL; ++q) {
+                val[q] = ((xm >> v2) & 1ull) ? dsh[h2] : 0.0;
+                if (++v2 == V) {
+                    v2 = 0;
+                    ++h2;
+                }
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < CPL; ++q) {
+                const int64_t c = c0 + q;
+                double x;
+                if (c == 0) {
+                    x = psi;
+                } else if (c <= V) {
+                    x = (double)((xm >> (c - 1)) & 1ull);
+                } else if (c < baseW) {
+                    x = dsh[c - V - 1];
+                } else if (c < P1) {
+                    const int idx = (int)(c - baseW);
+                    const int h2 = idx / V;
+                    x = ((xm >> (idx - h2 * V)) & 1ull) ? dsh[h2] : 0.0;
+                } else {
+                    x = 0.0;
+                }
+                val[q] = x;
+            }
+        }
+        // (h, v) of the next pass's first column
+        if (c0 + kStep >= baseW) {
+            if (c0 < baseW) {
+                const int idx = (int)(c0 + kStep - baseW);
+                hh = idx / V;
+                vv = idx - hh * V;
+            } else {
+                hh += qh;
+                vv += rv;
+                if (vv >= V) {
+                    vv -= V;
+                    ++hh;
+                }
+            }
+        }
+        if constexpr (CPL == 2) {
+            typedef double d2 __attribute__((ext_vector_type(2)));
+            typedef float f2 __attribute__((ext_vector_type(2)));
+            d2 a = {val[0], val[1]};
+            __builtin_nontemporal_store(a, (d2 *)(D64 + row * ld64 + c0));
+            if (D32) {
+                f2 b2 = {(float)val[0], (float)val[1]};
+                __builtin_nontemporal_store(b2, (f2 *)(D32 + row * ld32 + c0));
+            }
+        } else {
+            typedef float f4 __attribute__((ext_vector_type(4)));
+            f4 v4 = {(float)val[0], (float)val[1], (float)val[2], (float)val[3]};
+            __builtin_nontemporal_store(v4, (f4 *)(D32 + row * ld32 + c0));
+        }
+    }
+}
+
 // one determinant row on one wavefront (dsh: the wave's H-long scratch in LDS)
 __device__ __forceinline__ void nqs_row(uint64_t key, int64_t row, int n, int V, int H,
                                         const double *__restrict__ theta, double *__restrict__ D64,
@@ -22,9 +109,6 @@ __device__ __forceinline__ void nqs_row(uint64_t key, int64_t row, int n, int V,
                                         double *__restrict__ psi_out, double *dsh, int lane)
 {
     const double *a = theta, *b = theta + V, *W = theta + V + H;
-    const int64_t P1 = (int64_t)V * H + H + V + 1;
-    const int baseW = V + H + 1;
-    const float invV = 1.0f / (float)V;
     // x as a bit mask over v: alpha orbitals at v < n, beta at v = n + p
     uint64_t xm = (key & 0xffffffffull) | ((key >> 32) << n);
     double tsum = 0.0;
@@ -45,42 +129,10 @@ __device__ __forceinline__ void nqs_row(uint64_t key, int64_t row, int n, int V,
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     if (lane == 0) psi_out[row] = psi;
-    const int64_t ldw = D64 ? ld64 : ld32;
-    for (int64_t c0 = 2 * lane; c0 < ldw; c0 += 2 * kWave) {
-        double val[2];
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            int64_t c = c0 + q;
-            double x;
-            if (c == 0) {
-                x = psi;
-            } else if (c <= V) {
-                x = (double)((xm >> (c - 1)) & 1ull);
-            } else if (c < baseW) {
-                x = dsh[c - V - 1];
-            } else if (c < P1) {
-                int idx = (int)(c - baseW);
-                int hh = (int)((float)idx * invV);
-                int vv = idx - hh * V;
-                if (vv < 0) { --hh; vv += V; }
-                if (vv >= V) { ++hh; vv -= V; }
-                x = ((xm >> vv) & 1ull) ? dsh[hh] : 0.0;
-            } else {
-                x = 0.0;
-            }
-            val[q] = x;
-        }
-        if (D64) {
-            typedef double d2 __attribute__((ext_vector_type(2)));
-            d2 v2 = {val[0], val[1]};
-            __builtin_nontemporal_store(v2, (d2 *)(D64 + row * ld64 + c0));
-        }
-        if (D32 && c0 < ld32) {
-            typedef float f2 __attribute__((ext_vector_type(2)));
-            f2 v2 = {(float)val[0], (float)val[1]};
-            __builtin_nontemporal_store(v2, (f2 *)(D32 + row * ld32 + c0));
-        }
-    }
+    if (D64)
+        write_row<2>(xm, row, V, H, psi, dsh, D64, ld64, D32, ld32, lane);
+    else
+        write_row<4>(xm, row, V, H, psi, dsh, nullptr, ld64, D32, ld32, lane);
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
