@@ -221,11 +221,11 @@ __global__ __launch_bounds__(256) void k_gemv_t2(const T *__restrict__ D, int64_
                                                  const double *__restrict__ sub,
                                                  const double *__restrict__ coefp,
                                                  double *__restrict__ part, int64_t ldv,
-                                                 int nblk_rows)
+                                                 int nblk_rows, int rb0)
 {
     typedef typename Chunk<T>::V CV;
     __shared__ CV red[2][64 * NCH];
-    const int tile = blockIdx.x, rb = blockIdx.y;
+    const int tile = blockIdx.x, rb = blockIdx.y + rb0;
     const int64_t per = (ns + nblk_rows - 1) / nblk_rows;
     const int64_t r0 = (int64_t)rb * per, r1 = min(ns, r0 + per);
     const double coef = sub ? *coefp : 0.0;
@@ -269,45 +269,74 @@ __global__ void k_reduce_stage2(const double *__restrict__ part2, int groups, in
 template <typename T, int NCH>
 static void launch_t2_inst(const T *D, int64_t ld, int64_t ns, const double *a, const double *b,
                            const double *sub, const double *coef, double *part, int64_t ldv,
-                           int ntiles, int nblk, hipStream_t st)
+                           int ntiles, int nblk, int rbA, int rbB, hipStream_t st)
 {
-    k_gemv_t2<T, NCH><<<dim3(ntiles, nblk), 256, 0, st>>>(D, ld, ns, a, b, sub, coef, part, ldv,
-                                                          nblk);
+    k_gemv_t2<T, NCH><<<dim3(ntiles, rbB - rbA), 256, 0, st>>>(D, ld, ns, a, b, sub, coef, part, ldv,
+                                                               nblk, rbA);
 }
 
+// row blocks of the D~^T launch for a row length ld (elements) and ns rows
 template <typename T>
-static hipError_t launch_t2_typed(const T *D, int64_t ld, int64_t ns, const double *a,
-                                  const double *b, const double *sub, const double *coef,
-                                  double *part, int64_t ldv, int &nblk_out, hipStream_t st)
+static int t2_row_blocks(int64_t ld, int64_t ns, int &ntiles, int &nch_lane)
 {
     constexpr int E = Chunk<T>::E;
     const int64_t nch = ld / E;
-    const int ntiles = (int)((nch + 64 * 16 - 1) / (64 * 16));
-    const int NCH = (int)((nch + 64 * ntiles - 1) / (64 * ntiles));   // <= 16
+    ntiles = (int)((nch + 64 * 16 - 1) / (64 * 16));
+    nch_lane = (int)((nch + 64 * ntiles - 1) / (64 * ntiles));   // <= 16
     int nblk = kStreamBlocks / ntiles;
     if (nblk < 1) nblk = 1;
     if (nblk > (ns + 3) / 4) nblk = (int)((ns + 3) / 4);
+    return nblk;
+}
+
+// row blocks [rbA, rbB) of the launch (rbB < 0: all); the partition into row
+// blocks, and hence every partial sum, does not depend on the range launched
+template <typename T>
+static hipError_t launch_t2_typed(const T *D, int64_t ld, int64_t ns, const double *a,
+                                  const double *b, const double *sub, const double *coef,
+                                  double *part, int64_t ldv, int &nblk_out, int rbA, int rbB,
+                                  hipStream_t st)
+{
+    int ntiles = 1, NCH = 16;
+    const int nblk = t2_row_blocks<T>(ld, ns, ntiles, NCH);
     nblk_out = nblk;
-#define T2CASE(c) case c: launch_t2_inst<T, c>(D, ld, ns, a, b, sub, coef, part, ldv, ntiles, nblk, st); break;
+    if (rbB < 0) rbB = nblk;
+    if (rbA < 0 || rbB > nblk || rbA > rbB) return hipErrorInvalidValue;
+    if (rbA == rbB) return hipSuccess;
+#define T2CASE(c) case c: launch_t2_inst<T, c>(D, ld, ns, a, b, sub, coef, part, ldv, ntiles, nblk, rbA, rbB, st); break;
     switch (NCH) {
         T2CASE(1) T2CASE(2) T2CASE(3) T2CASE(4) T2CASE(5) T2CASE(6) T2CASE(7) T2CASE(8)
         T2CASE(9) T2CASE(10) T2CASE(11) T2CASE(12) T2CASE(13) T2CASE(14) T2CASE(15)
-        default: launch_t2_inst<T, 16>(D, ld, ns, a, b, sub, coef, part, ldv, ntiles, nblk, st); break;
+        default: launch_t2_inst<T, 16>(D, ld, ns, a, b, sub, coef, part, ldv, ntiles, nblk, rbA, rbB, st); break;
     }
 #undef T2CASE
     return hipGetLastError();
+}
+
+int gemv_t2_row_blocks(const WsLayout &L, int prec)
+{
+    int ntiles, nch;
+    return prec == IRL_FP64 ? t2_row_blocks<double>(L.ld64, L.ns, ntiles, nch)
+                            : t2_row_blocks<float>(L.ld32, L.ns, ntiles, nch);
+}
+
+hipError_t launch_gemv_t2_blocks(const WsLayout &L, void *ws, int prec, const double *a,
+                                 const double *b, const double *b_sub, const double *b_coef,
+                                 int *nblk, int rbA, int rbB, hipStream_t st)
+{
+    double *part = ws_ptr<double>(ws, L.off_part);
+    if (prec == IRL_FP64)
+        return launch_t2_typed<double>(ws_ptr<double>(ws, L.off_d64), L.ld64, L.ns, a, b, b_sub,
+                                       b_coef, part, L.ldv, *nblk, rbA, rbB, st);
+    return launch_t2_typed<float>(ws_ptr<float>(ws, L.off_d32), L.ld32, L.ns, a, b, b_sub, b_coef,
+                                  part, L.ldv, *nblk, rbA, rbB, st);
 }
 
 hipError_t launch_gemv_t2(const WsLayout &L, void *ws, int prec, const double *a,
                           const double *b, const double *b_sub, const double *b_coef,
                           int *nblk, hipStream_t st)
 {
-    double *part = ws_ptr<double>(ws, L.off_part);
-    if (prec == IRL_FP64)
-        return launch_t2_typed<double>(ws_ptr<double>(ws, L.off_d64), L.ld64, L.ns, a, b, b_sub,
-                                       b_coef, part, L.ldv, *nblk, st);
-    return launch_t2_typed<float>(ws_ptr<float>(ws, L.off_d32), L.ld32, L.ns, a, b, b_sub, b_coef,
-                                  part, L.ldv, *nblk, st);
+    return launch_gemv_t2_blocks(L, ws, prec, a, b, b_sub, b_coef, nblk, 0, -1, st);
 }
 
 hipError_t launch_t2_reduce(const WsLayout &L, void *ws, int nblk, double *ya, double *yb,

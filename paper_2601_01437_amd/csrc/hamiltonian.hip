@@ -300,14 +300,15 @@ __device__ __forceinline__ void pull_row(const HamArgs &A, WaveLists &L, int64_t
     end_row();
 }
 
+// rows [r0, r1), one wavefront per row, grid-stride
 template <int LK>
 __global__ __launch_bounds__(256) void k_ham_pull(HamArgs A, const double *__restrict__ w,
-                                                  double *__restrict__ u)
+                                                  double *__restrict__ u, int64_t r0, int64_t r1)
 {
     __shared__ WaveLists lists[4];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t nwaves = (int64_t)gridDim.x * 4;
-    for (int64_t row = (int64_t)blockIdx.x * 4 + wv; row < A.ns; row += nwaves)
+    for (int64_t row = r0 + (int64_t)blockIdx.x * 4 + wv; row < r1; row += nwaves)
         pull_row<LK>(A, lists[wv], row, lane, w, u);
 }
 
@@ -339,11 +340,11 @@ __device__ __forceinline__ void stored_row(const HamArgs &A, int64_t row, int la
 }
 
 __global__ __launch_bounds__(256) void k_ham_stored(HamArgs A, const double *__restrict__ w,
-                                                    double *__restrict__ u)
+                                                    double *__restrict__ u, int64_t r0, int64_t r1)
 {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t nwaves = (int64_t)gridDim.x * 4;
-    for (int64_t row = (int64_t)blockIdx.x * 4 + wv; row < A.ns; row += nwaves)
+    for (int64_t row = r0 + (int64_t)blockIdx.x * 4 + wv; row < r1; row += nwaves)
         stored_row(A, row, lane, w, u);
 }
 
@@ -492,23 +493,38 @@ HamView ham_view(const irl_system *s)
     return A;
 }
 
-static hipError_t launch_ham_product(const irl_system *s, const double *w, double *u, hipStream_t st);
+static hipError_t launch_ham_product(const irl_system *s, const double *w, double *u, int64_t b0, int64_t b1,
+                                     hipStream_t st);
+
+int64_t ham_row_quantum(const irl_system *s) { return s->ham_kernel == 2 ? s->nA : 1; }
+
+hipError_t launch_ham_apply_rows(const irl_system *s, const double *w, double *u, int64_t r0, int64_t r1,
+                                 hipStream_t st)
+{
+    if (r0 < 0 || r1 > s->ns || r0 > r1) return hipErrorInvalidValue;
+    if (r0 == r1) return hipSuccess;
+    if (s->ham_kernel == 2) {
+        // the string-product kernel works on whole beta strings
+        if (r0 % s->nA || r1 % s->nA) return hipErrorInvalidValue;
+        return launch_ham_product(s, w, u, r0 / s->nA, r1 / s->nA, st);
+    }
+    HamArgs A = ham_view(s);
+    int64_t blocks = (r1 - r0 + 3) / 4;
+    if (blocks > 65536) blocks = 65536;
+    if (s->ham_kernel == 4)
+        k_ham_stored<<<(unsigned)blocks, 256, 0, st>>>(A, w, u, r0, r1);
+    else if (s->lookup == kLkBlocks)
+        k_ham_pull<kLkBlocks><<<(unsigned)blocks, 256, 0, st>>>(A, w, u, r0, r1);
+    else if (s->lookup == kLkHash)
+        k_ham_pull<kLkHash><<<(unsigned)blocks, 256, 0, st>>>(A, w, u, r0, r1);
+    else
+        k_ham_pull<kLkRanks><<<(unsigned)blocks, 256, 0, st>>>(A, w, u, r0, r1);
+    return hipGetLastError();
+}
 
 hipError_t launch_ham_apply(const irl_system *s, const double *w, double *u, hipStream_t st)
 {
-    if (s->ham_kernel == 2) return launch_ham_product(s, w, u, st);
-    HamArgs A = ham_view(s);
-    int64_t blocks = (s->ns + 3) / 4;
-    if (blocks > 65536) blocks = 65536;
-    if (s->ham_kernel == 4)
-        k_ham_stored<<<(unsigned)blocks, 256, 0, st>>>(A, w, u);
-    else if (s->lookup == kLkBlocks)
-        k_ham_pull<kLkBlocks><<<(unsigned)blocks, 256, 0, st>>>(A, w, u);
-    else if (s->lookup == kLkHash)
-        k_ham_pull<kLkHash><<<(unsigned)blocks, 256, 0, st>>>(A, w, u);
-    else
-        k_ham_pull<kLkRanks><<<(unsigned)blocks, 256, 0, st>>>(A, w, u);
-    return hipGetLastError();
+    return launch_ham_apply_rows(s, w, u, 0, s->ns, st);
 }
 
 hipError_t launch_ham_count(const irl_system *s, int32_t *count, hipStream_t st)
@@ -675,6 +691,7 @@ __global__ void k_string_tables(const uint32_t *strs, const int32_t *rank, int64
 struct ProdArgs {
     int n, nsa, nsb, nda, ndb;
     int64_t nA, nB;
+    int64_t rb0;              // first beta string of the launch (blockIdx.y + rb0)
     const double *diag, *g;
     StrTables A, B;
 };
@@ -691,7 +708,7 @@ __global__ __launch_bounds__(kProdThreads) void k_ham_product(ProdArgs P, const 
     __shared__ int32_t db_rank[kProdMaxDoubles];
     __shared__ double db_val[kProdMaxDoubles];
     const int n = P.n, n2 = n * n;
-    const int64_t rb = blockIdx.y;
+    const int64_t rb = blockIdx.y + P.rb0;
     const int64_t ra = (int64_t)blockIdx.x * kProdThreads + threadIdx.x;
     const bool valid = ra < P.nA;
     const int64_t rac = valid ? ra : 0;
@@ -761,13 +778,13 @@ __global__ __launch_bounds__(kProdThreads) void k_ham_product(ProdArgs P, const 
 // row of the current beta move and the g slice live in LDS (double-buffered
 // over the beta moves, one barrier per move); the thread's alpha moves are
 // packed one per register: rank | (i n + a) << 16 | sign << 31.
-constexpr int kProd2Threads = 512;
+// TPB threads per block (one thread per alpha string of the block's slice).
+constexpr int kProd2Threads = 256;
 constexpr int kProdLdsMaxA = 2048;
 
-template <int NSA>
-__global__ __launch_bounds__(kProd2Threads) void k_ham_product_lds(ProdArgs P,
-                                                                   const double *__restrict__ w,
-                                                                   double *__restrict__ u)
+template <int NSA, int TPB>
+__global__ __launch_bounds__(TPB) void k_ham_product_lds(ProdArgs P, const double *__restrict__ w,
+                                                         double *__restrict__ u)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int n = P.n, n2 = n * n;
@@ -784,19 +801,19 @@ __global__ __launch_bounds__(kProd2Threads) void k_ham_product_lds(ProdArgs P,
     int32_t *db_rank = sb_rank + P.nsb;
     uint16_t *sb_ia = reinterpret_cast<uint16_t *>(db_rank + P.ndb);
 
-    const int64_t rb = blockIdx.y;
-    const int ra = blockIdx.x * kProd2Threads + threadIdx.x;
+    const int64_t rb = blockIdx.y + P.rb0;
+    const int ra = blockIdx.x * TPB + threadIdx.x;
     const bool valid = ra < nA;
     const int rac = valid ? ra : 0;
     const double *wrow = w + rb * P.nA;
-    for (int p = threadIdx.x; p < nA; p += kProd2Threads) wself[p] = wrow[p];
-    for (int p = threadIdx.x; p < n2; p += kProd2Threads) jbl[p] = P.B.J[(int64_t)p * P.nB + rb];
-    for (int f = threadIdx.x; f < P.nsb; f += kProd2Threads) {
+    for (int p = threadIdx.x; p < nA; p += TPB) wself[p] = wrow[p];
+    for (int p = threadIdx.x; p < n2; p += TPB) jbl[p] = P.B.J[(int64_t)p * P.nB + rb];
+    for (int f = threadIdx.x; f < P.nsb; f += TPB) {
         sb_rank[f] = P.B.srank[(int64_t)f * P.nB + rb];
         sb_ia[f] = P.B.sia[(int64_t)f * P.nB + rb];
         sb_f[f] = P.B.sf[(int64_t)f * P.nB + rb];
     }
-    for (int d = threadIdx.x; d < P.ndb; d += kProd2Threads) {
+    for (int d = threadIdx.x; d < P.ndb; d += TPB) {
         db_rank[d] = P.B.drank[(int64_t)d * P.nB + rb];
         db_val[d] = P.B.dval[(int64_t)d * P.nB + rb];
     }
@@ -805,8 +822,8 @@ __global__ __launch_bounds__(kProd2Threads) void k_ham_product_lds(ProdArgs P,
     if (P.nsb > 0) {
         const int j = sb_ia[0] & 31, b = (sb_ia[0] >> 5) & 31;
         const double *src = w + (int64_t)sb_rank[0] * P.nA;
-        for (int p = threadIdx.x; p < nA; p += kProd2Threads) wb0[p] = src[p];
-        for (int p = threadIdx.x; p < n2; p += kProd2Threads) gs0[p] = P.g[(int64_t)p * n2 + j * n + b];
+        for (int p = threadIdx.x; p < nA; p += TPB) wb0[p] = src[p];
+        for (int p = threadIdx.x; p < n2; p += TPB) gs0[p] = P.g[(int64_t)p * n2 + j * n + b];
     }
     double acc = P.diag[rb * P.nA + rac] * wself[rac];
     uint32_t pk[NSA];
@@ -833,8 +850,8 @@ __global__ __launch_bounds__(kProd2Threads) void k_ham_product_lds(ProdArgs P,
     for (int d = 0; d < P.ndb; ++d) acc += db_val[d] * w[(int64_t)db_rank[d] * P.nA + rac];
     __syncthreads();
     // opposite-spin doubles, double-buffered over the beta moves
-    constexpr int PFW = (kProdLdsMaxA + kProd2Threads - 1) / kProd2Threads;
-    constexpr int PFG = (32 * 32 + kProd2Threads - 1) / kProd2Threads;
+    constexpr int PFW = (kProdLdsMaxA + TPB - 1) / TPB;
+    constexpr int PFG = (32 * 32 + TPB - 1) / TPB;
     for (int f = 0; f < P.nsb; ++f) {
         const double *wb = (f & 1) ? wb1 : wb0;
         const double *gs = (f & 1) ? gs1 : gs0;
@@ -845,12 +862,12 @@ __global__ __launch_bounds__(kProd2Threads) void k_ham_product_lds(ProdArgs P,
             const double *src = w + (int64_t)sb_rank[f + 1] * P.nA;
 #pragma unroll
             for (int t = 0; t < PFW; ++t) {
-                const int p = threadIdx.x + t * kProd2Threads;
+                const int p = threadIdx.x + t * TPB;
                 pw[t] = p < nA ? src[p] : 0.0;
             }
 #pragma unroll
             for (int t = 0; t < PFG; ++t) {
-                const int p = threadIdx.x + t * kProd2Threads;
+                const int p = threadIdx.x + t * TPB;
                 pg[t] = p < n2 ? P.g[(int64_t)p * n2 + j * n + b] : 0.0;
             }
         }
@@ -870,12 +887,12 @@ __global__ __launch_bounds__(kProd2Threads) void k_ham_product_lds(ProdArgs P,
             double *gn = (f & 1) ? gs0 : gs1;
 #pragma unroll
             for (int t = 0; t < PFW; ++t) {
-                const int p = threadIdx.x + t * kProd2Threads;
+                const int p = threadIdx.x + t * TPB;
                 if (p < nA) wn[p] = pw[t];
             }
 #pragma unroll
             for (int t = 0; t < PFG; ++t) {
-                const int p = threadIdx.x + t * kProd2Threads;
+                const int p = threadIdx.x + t * TPB;
                 if (p < n2) gn[p] = pg[t];
             }
         }
@@ -960,21 +977,25 @@ static StrTables tables_of(const irl_system *s, bool alpha)
 }
 
 template <int NSA>
-static void launch_prod_inst(const ProdArgs &P, const double *w, double *u, hipStream_t st)
+static void launch_prod_inst(const ProdArgs &P, int64_t nbeta, const double *w, double *u, hipStream_t st)
 {
     const size_t lds = product_lds_bytes(P);
     if (P.nA <= kProdLdsMaxA && lds <= 64 * 1024) {
-        dim3 grid((unsigned)((P.nA + kProd2Threads - 1) / kProd2Threads), (unsigned)P.nB);
-        k_ham_product_lds<NSA><<<grid, kProd2Threads, lds, st>>>(P, w, u);
+        dim3 grid((unsigned)((P.nA + kProd2Threads - 1) / kProd2Threads), (unsigned)nbeta);
+        k_ham_product_lds<NSA, kProd2Threads><<<grid, kProd2Threads, lds, st>>>(P, w, u);
     } else {
-        dim3 grid((unsigned)((P.nA + kProdThreads - 1) / kProdThreads), (unsigned)P.nB);
+        dim3 grid((unsigned)((P.nA + kProdThreads - 1) / kProdThreads), (unsigned)nbeta);
         k_ham_product<NSA><<<grid, kProdThreads, 0, st>>>(P, w, u);
     }
 }
 
-static hipError_t launch_ham_product(const irl_system *s, const double *w, double *u, hipStream_t st)
+// beta strings [b0, b1)
+static hipError_t launch_ham_product(const irl_system *s, const double *w, double *u, int64_t b0, int64_t b1,
+                                     hipStream_t st)
 {
     ProdArgs P;
+    P.rb0 = b0;
+    const int64_t nbeta = b1 - b0;
     product_fits(s, P.nsa, P.nsb, P.nda, P.ndb);
     P.n = s->n;
     P.nA = s->nA;
@@ -985,22 +1006,22 @@ static hipError_t launch_ham_product(const irl_system *s, const double *w, doubl
     P.B = tables_of(s, false);
     const int q = (P.nsa + 3) / 4;
     switch (q) {
-    case 0: case 1: launch_prod_inst<4>(P, w, u, st); break;
-    case 2: launch_prod_inst<8>(P, w, u, st); break;
-    case 3: launch_prod_inst<12>(P, w, u, st); break;
-    case 4: launch_prod_inst<16>(P, w, u, st); break;
-    case 5: launch_prod_inst<20>(P, w, u, st); break;
-    case 6: launch_prod_inst<24>(P, w, u, st); break;
-    case 7: launch_prod_inst<28>(P, w, u, st); break;
-    case 8: launch_prod_inst<32>(P, w, u, st); break;
-    case 9: launch_prod_inst<36>(P, w, u, st); break;
-    case 10: launch_prod_inst<40>(P, w, u, st); break;
-    case 11: launch_prod_inst<44>(P, w, u, st); break;
-    case 12: launch_prod_inst<48>(P, w, u, st); break;
-    case 13: launch_prod_inst<52>(P, w, u, st); break;
-    case 14: launch_prod_inst<56>(P, w, u, st); break;
-    case 15: launch_prod_inst<60>(P, w, u, st); break;
-    default: launch_prod_inst<64>(P, w, u, st); break;
+    case 0: case 1: launch_prod_inst<4>(P, nbeta, w, u, st); break;
+    case 2: launch_prod_inst<8>(P, nbeta, w, u, st); break;
+    case 3: launch_prod_inst<12>(P, nbeta, w, u, st); break;
+    case 4: launch_prod_inst<16>(P, nbeta, w, u, st); break;
+    case 5: launch_prod_inst<20>(P, nbeta, w, u, st); break;
+    case 6: launch_prod_inst<24>(P, nbeta, w, u, st); break;
+    case 7: launch_prod_inst<28>(P, nbeta, w, u, st); break;
+    case 8: launch_prod_inst<32>(P, nbeta, w, u, st); break;
+    case 9: launch_prod_inst<36>(P, nbeta, w, u, st); break;
+    case 10: launch_prod_inst<40>(P, nbeta, w, u, st); break;
+    case 11: launch_prod_inst<44>(P, nbeta, w, u, st); break;
+    case 12: launch_prod_inst<48>(P, nbeta, w, u, st); break;
+    case 13: launch_prod_inst<52>(P, nbeta, w, u, st); break;
+    case 14: launch_prod_inst<56>(P, nbeta, w, u, st); break;
+    case 15: launch_prod_inst<60>(P, nbeta, w, u, st); break;
+    default: launch_prod_inst<64>(P, nbeta, w, u, st); break;
     }
     return hipGetLastError();
 }

@@ -219,6 +219,11 @@ hipError_t launch_ham_stored_grouped(const Member *M, const WorkItem *items, int
 hipError_t launch_ham_pull_grouped(const Member *M, const WorkItem *items, int nitems,
                                    int64_t nblocks, int which, int lookup, hipStream_t st);
 hipError_t launch_ham_apply(const irl_system *s, const double *w, double *u, hipStream_t st);
+// rows [r0, r1) of u = H w (r0, r1 multiples of ham_row_quantum: whole beta strings
+// for the string-product kernel)
+hipError_t launch_ham_apply_rows(const irl_system *s, const double *w, double *u, int64_t r0, int64_t r1,
+                                 hipStream_t st);
+int64_t ham_row_quantum(const irl_system *s);
 // multi-vector D~ streams: W[:, q] = D~ V[:, q] (q < nb, W column stride ns) and the
 // 2 nb right-hand-side D~^T pass over (W, U); reduction into YS[:, q], YH[:, q] (stride ldy)
 hipError_t launch_gemv_rows_multi(const WsLayout &L, void *ws, int prec, const double *V, int64_t ldv_in,
@@ -258,6 +263,11 @@ hipError_t launch_gemv_rows(const WsLayout &L, void *ws, int prec, const double 
                             int zero_v0, hipStream_t st);
 // [yS, yH] = D~^T [a, b] where a = w (or nullptr), b = u - scale*psi form; see dtilde.hip
 // stream part: per-row-block partial sums; returns the number of row blocks
+// the D~^T launch restricted to its row blocks [rbA, rbB) (same partials as the full launch)
+hipError_t launch_gemv_t2_blocks(const WsLayout &L, void *ws, int prec, const double *a,
+                                 const double *b, const double *b_sub, const double *b_coef,
+                                 int *nblk, int rbA, int rbB, hipStream_t st);
+int gemv_t2_row_blocks(const WsLayout &L, int prec);
 hipError_t launch_gemv_t2(const WsLayout &L, void *ws, int prec, const double *a,
                           const double *b, const double *b_sub, const double *b_coef,
                           int *nblk, hipStream_t st);
