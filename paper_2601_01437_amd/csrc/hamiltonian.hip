@@ -107,6 +107,7 @@ __device__ __forceinline__ int64_t find_row(const HamArgs &A, uint32_t al, uint3
 }
 
 constexpr int kMaxSingles = 256;   // n <= 32: na * (n - na) <= 256
+constexpr int kScanFactor = 8;     // scan a block when it holds <= 8x the candidates it replaces
 constexpr int kMaxPairs = 496;     // C(32, 2)
 
 struct WaveLists {
@@ -186,8 +187,39 @@ __device__ __forceinline__ void visit_row(const HamArgs &A, const WaveLists &L, 
                                           uint32_t be, int lane, int stride, OP op)
 {
     const int n = A.n, na = A.na, nb = A.nb, va = n - na, vb = n - nb;
+    // Blocked lookup: a short own-beta block is scanned (its members that differ
+    // from the row's alpha string by one or two orbitals are exactly the alpha
+    // singles and alpha-alpha doubles inside the set) instead of probing every
+    // candidate; likewise a short beta' block for the opposite-spin doubles.
+    bool scan_own = false;
+    if constexpr (LK == kLkBlocks) {
+        const int cand = na * va + (na * (na - 1) / 2) * (va * (va - 1) / 2);
+        scan_own = (L.own_hi - L.own_lo) <= kScanFactor * cand;
+        if (scan_own) {
+            for (int64_t p = L.own_lo + lane; p < L.own_hi; p += stride) {
+                const uint32_t a2 = (uint32_t)A.keys[p];
+                const uint32_t x = al ^ a2;
+                const int pc = __popc(x);
+                if (pc == 2) {
+                    const int i = __ffs(al & x) - 1, a = __ffs(a2 & x) - 1;
+                    const int sg = move_sign(al, i, a);
+                    op(p, sg, 1, sg * single_value(A.h, A.g, n, al, be, i, a));
+                } else if (pc == 4) {
+                    const uint32_t out = al & x, in = a2 & x;
+                    const int i = __ffs(out) - 1, j = __ffs(out & (out - 1)) - 1;
+                    const int a = __ffs(in) - 1, b = __ffs(in & (in - 1)) - 1;
+                    const int s1 = move_sign(al, i, a);
+                    const uint32_t b1 = (al & ~(1u << i)) | (1u << a);
+                    const int s2 = move_sign(b1, j, b);
+                    const double v = gint(A.g, n, i, a, j, b) - gint(A.g, n, i, b, j, a);
+                    op(p, s1 * s2, 3, (s1 * s2) * v);
+                }
+            }
+        }
+    }
     // alpha and beta singles
     for (int spin = 0; spin < 2; ++spin) {
+        if (spin == 0 && scan_own) continue;
         const int cnt = spin ? nb * vb : na * va;
         const uint32_t *s = spin ? L.sB : L.sA;
         const uint32_t *ss = spin ? L.sBstr : L.sAstr;
@@ -206,6 +238,7 @@ __device__ __forceinline__ void visit_row(const HamArgs &A, const WaveLists &L, 
     }
     // same-spin doubles
     for (int spin = 0; spin < 2; ++spin) {
+        if (spin == 0 && scan_own) continue;
         const int ne = spin ? nb : na, nv = spin ? vb : va;
         const int npo = ne * (ne - 1) / 2, npv = nv * (nv - 1) / 2;
         const int cnt = npo * npv;
@@ -235,7 +268,35 @@ __device__ __forceinline__ void visit_row(const HamArgs &A, const WaveLists &L, 
         }
     }
     // opposite-spin doubles
-    {
+    if constexpr (LK == kLkBlocks) {
+        const int cA = na * va, cB = nb * vb;
+        for (int f = 0; f < cB && cA > 0; ++f) {
+            const int32_t lo = L.sBlo[f], hi = L.sBhi[f];
+            if (hi <= lo) continue;
+            const uint32_t pb = L.sB[f];
+            const int j = pb & 31, b = (pb >> 5) & 31, sgb = (pb >> 10) & 1 ? -1 : 1;
+            if (hi - lo <= kScanFactor * cA) {
+                for (int64_t p = lo + lane; p < hi; p += stride) {
+                    const uint32_t a2 = (uint32_t)A.keys[p];
+                    const uint32_t x = al ^ a2;
+                    if (__popc(x) != 2) continue;
+                    const int i = __ffs(al & x) - 1, a = __ffs(a2 & x) - 1;
+                    const int sg = move_sign(al, i, a) * sgb;
+                    op(p, sg, 5, sg * gint(A.g, n, i, a, j, b));
+                }
+            } else {
+                for (int xa = lane; xa < cA; xa += stride) {
+                    const int64_t r = search_block(A.keys, lo, hi, L.sAstr[xa]);
+                    if (r >= 0) {
+                        const uint32_t pa = L.sA[xa];
+                        const int i = pa & 31, a = (pa >> 5) & 31;
+                        const int sg = ((pa >> 10) & 1 ? -1 : 1) * sgb;
+                        op(r, sg, 5, sg * gint(A.g, n, i, a, j, b));
+                    }
+                }
+            }
+        }
+    } else {
         const int cA = na * va, cB = nb * vb, cnt = cA * cB;
         if (cnt > 0) {
             int xa = lane / cB, xb = lane - xa * cB;
@@ -244,11 +305,7 @@ __device__ __forceinline__ void visit_row(const HamArgs &A, const WaveLists &L, 
                 uint32_t pa = L.sA[xa], pb = L.sB[xb];
                 int i = pa & 31, a = (pa >> 5) & 31, j = pb & 31, b = (pb >> 5) & 31;
                 int sg = (((pa >> 10) ^ (pb >> 10)) & 1) ? -1 : 1;
-                int64_t r;
-                if constexpr (LK == kLkBlocks)
-                    r = L.sBhi[xb] > L.sBlo[xb] ? search_block(A.keys, L.sBlo[xb], L.sBhi[xb], L.sAstr[xa]) : -1;
-                else
-                    r = find_row<LK>(A, L.sAstr[xa], L.sBstr[xb]);
+                const int64_t r = find_row<LK>(A, L.sAstr[xa], L.sBstr[xb]);
                 if (r >= 0) op(r, sg, 5, sg * gint(A.g, n, i, a, j, b));
                 xb += step_b;
                 xa += step_a;
