@@ -426,6 +426,8 @@ def main():
     ap.add_argument("--precision", default=None, choices=["fp64", "fp32"],
                     help="operator precision (default: the workload's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--jacobian", default="dense", choices=["dense", "factored"],
+                    help="FP64 operator: stream the dense D~ or use the factored Jacobian of the network")
     ap.add_argument("--block", type=int, default=0,
                     help="vectors per operator pass: 0/1 implicitly restarted Lanczos, 2..8 block Lanczos")
     ap.add_argument("--polish", action="store_true",
@@ -487,7 +489,7 @@ def main():
     precision = B.IRL_FP64 if prec_name == "fp64" else B.IRL_FP32
     # FP32 operator: FP32 copy of D~ only, unless the FP64 polish of the Ritz pair is asked for
     if precision == B.IRL_FP64:
-        ws_flags = B.IRL_WS_FP64
+        ws_flags = B.IRL_WS_FACTORED if args.jacobian == "factored" else B.IRL_WS_FP64
     else:
         ws_flags = B.IRL_WS_FP32 | (B.IRL_WS_FP64 if args.polish else 0)
     step_flags = B.IRL_STEP_NO_EVAL_AFTER | (0 if args.polish else B.IRL_STEP_NO_POLISH)

@@ -74,9 +74,16 @@ enum irl_mode { IRL_MODE_A = 0, IRL_MODE_P = 1 };
 enum irl_ws_flags {
     IRL_WS_FP64 = 1u,   /* hold an FP64 copy of D~ (required for IRL_FP64 applies) */
     IRL_WS_FP32 = 2u,   /* hold an FP32 copy of D~ (required for IRL_FP32 applies) */
-    IRL_WS_BLOCK = 4u   /* room for multi-vector applies and block solves of up to 8
+    IRL_WS_BLOCK = 4u,  /* room for multi-vector applies and block solves of up to 8
                            vectors (8 vectors of n_dets for w and u, 8 of P+1 for the
                            outputs and larger reduction partials) */
+    IRL_WS_FACTORED = 8u  /* keep the Jacobian of the one-hidden-layer network in
+                           factored form (psi, d = 1 - t^2 of n_dets x H, and the
+                           occupations) instead of, or beside, the D~ copies: IRL_FP64
+                           applies and the gradient then use the network's forward and
+                           backward products, about 8 H bytes per determinant instead
+                           of 8 (P + 1).  Needs irl_nqs_evaluate (not irl_dtilde_set)
+                           and V <= 64. */
 };
 
 /* irl_step flags */

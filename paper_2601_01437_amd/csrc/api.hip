@@ -163,9 +163,10 @@ int t2_blocks(int64_t ns, int64_t ld, int prec)
 }
 
 // Z, E and the gradient from psi: H psi -> reductions -> grad_full = 2 D~^T (H psi - E psi) / Z.
-// With an FP64 copy of D~ the gradient streams it (and leaves D~^T psi in y as a
-// diagnostic); without one, and with the network at hand (nqs), it is recomputed
-// from theta in FP64; only a caller-set FP32 D~ falls back to the FP32 stream.
+// With the factored Jacobian the gradient is its backward product; with an FP64
+// copy of D~ it streams that copy (and leaves D~^T psi in y as a diagnostic);
+// without either, and with the network at hand (nqs), it is recomputed from
+// theta in FP64; only a caller-set FP32 D~ falls back to the FP32 stream.
 int energy_and_gradient(irl_system *s, void *ws, const WsLayout &L, hipStream_t st,
                         const irl_nqs_desc *nqs = nullptr)
 {
@@ -176,7 +177,11 @@ int energy_and_gradient(irl_system *s, void *ws, const WsLayout &L, hipStream_t 
     const int prec = (L.flags & IRL_WS_FP64) ? IRL_FP64 : IRL_FP32;
     int nblk = 1;
     double *y = ws_ptr<double>(ws, L.off_y);
-    if (prec == IRL_FP32 && nqs) {
+    if (L.flags & IRL_WS_FACTORED) {
+        nblk = fac_row_blocks(L);
+        TIMED(s, IRL_STAT_GEMV_T, st, launch_fac_vjp(s, L, ws, hpsi, &sc->E_el, 1, nblk, st));
+        y = nullptr;
+    } else if (prec == IRL_FP32 && nqs) {
         nblk = t2_blocks(L.ns, L.ld32, IRL_FP32);
         TIMED(s, IRL_STAT_ENERGY, st, launch_nqs_grad(s, nqs->V, nqs->H, nqs->theta, L, ws, nblk, st));
         y = nullptr;
@@ -200,6 +205,16 @@ int apply_internal(irl_system *s, void *ws, const WsLayout &L, const double *v, 
                    double *yS, int prec, hipStream_t st, int zero_v0 = 0)
 {
     double *w = ws_ptr<double>(ws, L.off_w), *u = ws_ptr<double>(ws, L.off_u);
+    if (prec == IRL_FP64 && (L.flags & IRL_WS_FACTORED)) {
+        // factored Jacobian: forward product, H, two backward products
+        TIMED(s, IRL_STAT_GEMV, st, launch_fac_jvp(s, L, ws, v, zero_v0, w, st));
+        TIMED(s, IRL_STAT_HAM_APPLY, st, launch_ham_apply(s, w, u, st));
+        const int nb = fac_row_blocks(L);
+        TIMED(s, IRL_STAT_GEMV_T, st, launch_fac_vjp(s, L, ws, w, nullptr, 0, nb, st));
+        TIMED(s, IRL_STAT_GEMV_T, st, launch_fac_vjp(s, L, ws, u, nullptr, 1, nb, st));
+        TIMED(s, IRL_STAT_REDUCE, st, launch_t2_reduce(L, ws, nb, yS, yH, L.ncols, 1.0, nullptr, st));
+        return IRL_OK;
+    }
     TIMED(s, prec == IRL_FP64 ? IRL_STAT_GEMV : IRL_STAT_GEMV_LO, st, launch_gemv_rows(L, ws, prec, v, w, zero_v0, st));
     TIMED(s, IRL_STAT_HAM_APPLY, st, launch_ham_apply(s, w, u, st));
     int nblk = 1;
@@ -228,7 +243,7 @@ int apply_block_internal(irl_system *s, void *ws, const WsLayout &L, const doubl
 int check_prec(irl_system *s, int prec)
 {
     if (prec == IRL_FP64 && !s->ws_has64)
-        return set_err(s, IRL_ESTATE, "workspace holds no FP64 copy of D~");
+        return set_err(s, IRL_ESTATE, "workspace holds neither an FP64 copy of D~ nor the factored Jacobian");
     if (prec == IRL_FP32 && !s->ws_has32)
         return set_err(s, IRL_ESTATE, "workspace holds no FP32 copy of D~");
     if (prec != IRL_FP64 && prec != IRL_FP32) return set_err(s, IRL_EINVAL, "bad precision");
@@ -239,12 +254,14 @@ int check_prec(irl_system *s, int prec)
 
 namespace irl {
 
-WsLayout make_layout(int64_t ns, int64_t ncols, uint32_t flags)
+WsLayout make_layout(int64_t ns, int64_t ncols, uint32_t flags, int V)
 {
     WsLayout L;
     L.ns = ns;
     L.ncols = ncols;
     L.flags = flags;
+    if ((flags & IRL_WS_FACTORED) && V > 0 && (ncols - 1 - V) > 0 && (ncols - 1 - V) % (V + 1) == 0)
+        L.hfac = (int)((ncols - 1 - V) / (V + 1));
     const int64_t ld = (int64_t)align_up((size_t)ncols, 32);
     L.ld64 = L.ld32 = L.ldv = ld;
     size_t off = 0;
@@ -275,6 +292,7 @@ WsLayout make_layout(int64_t ns, int64_t ncols, uint32_t flags)
     L.off_img0 = take((size_t)kBasisCols * ld * 8);
     L.off_img1 = take((size_t)kBasisCols * ld * 8);
     L.off_hy = take((size_t)ld * 8);
+    L.off_fac = take((flags & IRL_WS_FACTORED) ? (size_t)ns * (size_t)L.hfac * 8 : 0);
     L.total = off;
     return L;
 }
@@ -406,6 +424,8 @@ int irl_solve_block(irl_system *s, void *ws, const WsLayout &L, const irl_solver
 {
     const int nb = o.block;
     if (!(L.flags & IRL_WS_BLOCK)) return set_err(s, IRL_EINVAL, "block solves need a workspace with IRL_WS_BLOCK");
+    if (prec == IRL_FP64 && !(L.flags & IRL_WS_FP64))
+        return set_err(s, IRL_EINVAL, "block solves stream a D~ copy (IRL_WS_FP64 for FP64)");
     if (nb < 2 || nb > kMaxBlock) return set_err(s, IRL_EINVAL, "block must be in [2, 8]");
     const int64_t dim = (o.mode == IRL_MODE_A) ? L.ncols : L.ncols - 1;
     const int m = (int)std::min<int64_t>(std::min(o.m, kMaxKrylov), dim);
@@ -734,10 +754,12 @@ int irl_system_info_get(const irl_system *s, irl_system_info *o)
 
 int irl_workspace_query(const irl_system *s, int64_t ncols, uint32_t ws_flags, size_t *bytes)
 {
-    if (!s || !bytes || ncols < 2 || !(ws_flags & (IRL_WS_FP64 | IRL_WS_FP32)) ||
-        (ws_flags & ~(uint32_t)(IRL_WS_FP64 | IRL_WS_FP32 | IRL_WS_BLOCK)))
+    if (!s || !bytes || ncols < 2 || !(ws_flags & (IRL_WS_FP64 | IRL_WS_FP32 | IRL_WS_FACTORED)) ||
+        (ws_flags & ~(uint32_t)(IRL_WS_FP64 | IRL_WS_FP32 | IRL_WS_BLOCK | IRL_WS_FACTORED)))
         return IRL_EINVAL;
-    *bytes = make_layout(s->ns, ncols, ws_flags).total;
+    const WsLayout L = make_layout(s->ns, ncols, ws_flags, 2 * s->n);
+    if ((ws_flags & IRL_WS_FACTORED) && L.hfac < 1) return IRL_EINVAL;
+    *bytes = L.total;
     return IRL_OK;
 }
 
@@ -748,10 +770,12 @@ int irl_nqs_evaluate(irl_system *s, const irl_nqs_desc *nqs, void *ws, size_t ws
     if (!nqs || !nqs->theta) return set_err(s, IRL_EINVAL, "network descriptor or theta is NULL");
     if (nqs->V != 2 * s->n) return set_err(s, IRL_EINVAL, "V must equal 2 * n_orb");
     if (nqs->H < 1 || nqs->H > 1024) return set_err(s, IRL_EINVAL, "H must be in [1, 1024]");
-    if (!(ws_flags & (IRL_WS_FP64 | IRL_WS_FP32))) return set_err(s, IRL_EINVAL, "ws_flags names no D~ copy");
+    if (!(ws_flags & (IRL_WS_FP64 | IRL_WS_FP32 | IRL_WS_FACTORED)))
+        return set_err(s, IRL_EINVAL, "ws_flags names no D~ copy and no factored Jacobian");
+    if ((ws_flags & IRL_WS_FACTORED) && nqs->V > 64) return set_err(s, IRL_EINVAL, "the factored Jacobian needs V <= 64");
     hipStream_t st = (hipStream_t)stream;
     const int64_t P = (int64_t)nqs->V * nqs->H + nqs->H + nqs->V;
-    WsLayout L = make_layout(s->ns, P + 1, ws_flags);
+    WsLayout L = make_layout(s->ns, P + 1, ws_flags, nqs->V);
     int rc = check_ws(s, ws, ws_bytes, L);
     if (rc) return rc;
     s->ws_valid = false;
@@ -761,7 +785,7 @@ int irl_nqs_evaluate(irl_system *s, const irl_nqs_desc *nqs, void *ws, size_t ws
     s->ws = ws;
     s->lay = L;
     s->ws_valid = true;
-    s->ws_has64 = (ws_flags & IRL_WS_FP64) != 0;
+    s->ws_has64 = (ws_flags & (IRL_WS_FP64 | IRL_WS_FACTORED)) != 0;
     s->ws_has32 = (ws_flags & IRL_WS_FP32) != 0;
     if (out) {
         out->Z = s->Z;
@@ -782,8 +806,9 @@ int irl_dtilde_set(irl_system *s, const void *D, int64_t ld, int64_t ncols, int3
     if (!D || ncols < 2 || ld < ncols || (dtype != IRL_FP64 && dtype != IRL_FP32))
         return set_err(s, IRL_EINVAL, "bad D~ arguments");
     if (!(ws_flags & (IRL_WS_FP64 | IRL_WS_FP32))) return set_err(s, IRL_EINVAL, "ws_flags names no D~ copy");
+    if (ws_flags & IRL_WS_FACTORED) return set_err(s, IRL_EINVAL, "a caller-set D~ has no factored form");
     hipStream_t st = (hipStream_t)stream;
-    WsLayout L = make_layout(s->ns, ncols, ws_flags);
+    WsLayout L = make_layout(s->ns, ncols, ws_flags, 2 * s->n);
     int rc = check_ws(s, ws, ws_bytes, L);
     if (rc) return rc;
     s->ws_valid = false;
@@ -822,6 +847,8 @@ int irl_apply_lm_operator_block(irl_system *s, void *ws, size_t ws_bytes, const 
     if (!V || !YH || !YS || ldv_in < L.ncols || ldy < L.ncols) return set_err(s, IRL_EINVAL, "bad vector arguments");
     int rc = check_prec(s, precision);
     if (rc) return rc;
+    if (precision == IRL_FP64 && !(L.flags & IRL_WS_FP64))
+        return set_err(s, IRL_EINVAL, "multi-vector applies stream a D~ copy (IRL_WS_FP64 for FP64)");
     hipStream_t st = (hipStream_t)stream;
     return apply_block_internal(s, ws, L, V, ldv_in, nb, YH, YS, ldy, precision, st);
 }
@@ -1490,6 +1517,8 @@ int irl_batch_create(int32_t count, irl_system *const *systems, const irl_nqs_de
     *out = nullptr;
     if (count < 1 || !systems || !nqs || !ws || !ws_bytes) return set_err(nullptr, IRL_EINVAL, "bad batch arguments");
     if (!(ws_flags & (IRL_WS_FP64 | IRL_WS_FP32))) return set_err(nullptr, IRL_EINVAL, "ws_flags names no D~ copy");
+    if (ws_flags & IRL_WS_FACTORED)
+        return set_err(nullptr, IRL_EINVAL, "batches stream D~ copies (IRL_WS_FACTORED is not supported)");
     irl_batch *b = new irl_batch();
     b->B = count;
     b->ws_flags = ws_flags;
@@ -1500,7 +1529,7 @@ int irl_batch_create(int32_t count, irl_system *const *systems, const irl_nqs_de
             if (systems[k] == s) { delete b; return set_err(nullptr, IRL_EINVAL, "a system appears twice in a batch"); }
         if (nqs[i].V != 2 * s->n || nqs[i].H < 1 || nqs[i].H > 1024) { delete b; return set_err(nullptr, IRL_EINVAL, "bad network size in batch member " + std::to_string(i)); }
         const int64_t P = (int64_t)nqs[i].V * nqs[i].H + nqs[i].H + nqs[i].V;
-        WsLayout L = make_layout(s->ns, P + 1, ws_flags);
+        WsLayout L = make_layout(s->ns, P + 1, ws_flags, nqs[i].V);
         if (L.ldv > 8192) { delete b; return set_err(nullptr, IRL_EINVAL, "batch members need P + 1 <= 8192"); }
         if (!ws[i] || reinterpret_cast<uintptr_t>(ws[i]) % 256 || ws_bytes[i] < L.total) { delete b; return set_err(nullptr, IRL_ENOMEM, "batch workspace missing or too small for member " + std::to_string(i)); }
         b->sys.push_back(s);

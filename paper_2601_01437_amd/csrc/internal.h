@@ -58,11 +58,15 @@ struct WsLayout {
     size_t off_scal = 0, off_d64 = 0, off_d32 = 0, off_psi = 0, off_hpsi = 0, off_w = 0,
            off_u = 0, off_grad = 0, off_yh = 0, off_ys = 0, off_y = 0, off_r = 0,
            off_part = 0, off_part2 = 0, off_red = 0, off_kry0 = 0, off_kry1 = 0, off_vconv = 0,
-           off_img0 = 0, off_img1 = 0, off_hy = 0;   // operator images of the basis; of y
+           off_img0 = 0, off_img1 = 0, off_hy = 0,   // operator images of the basis; of y
+           off_fac = 0;                              // factored Jacobian d = 1 - t^2 (N_s x hfac)
+    int hfac = 0;                                    // hidden units of the factored Jacobian
     size_t total = 0;
 };
 
-WsLayout make_layout(int64_t ns, int64_t ncols, uint32_t flags);
+// V: visible units (2 n_orb); with IRL_WS_FACTORED the hidden width follows from
+// ncols = V H + H + V + 1 (hfac = 0 when ncols fits no network)
+WsLayout make_layout(int64_t ns, int64_t ncols, uint32_t flags, int V);
 
 // vectors the w/u, yH/yS and conversion regions of a layout hold (1, or kMaxBlock with IRL_WS_BLOCK)
 inline int layout_vectors(const WsLayout &L) { return (L.flags & IRL_WS_BLOCK) ? kMaxBlock : 1; }
@@ -252,6 +256,12 @@ hipError_t launch_ham_row_list(const irl_system *s, int64_t row, int32_t *tgt, i
 // FP64 D~^T (H psi - E psi) recomputed from theta into the D~^T partial rows (nblk row blocks)
 hipError_t launch_nqs_grad(const irl_system *s, int V, int H, const double *theta, const WsLayout &L,
                            void *ws, int nblk, hipStream_t st);
+// factored Jacobian: w = D~ v and partial rows of D~^T (y - coef psi) (half 0 or 1)
+hipError_t launch_fac_jvp(const irl_system *s, const WsLayout &L, void *ws, const double *v, int zero_v0,
+                          double *w, hipStream_t st);
+hipError_t launch_fac_vjp(const irl_system *s, const WsLayout &L, void *ws, const double *y,
+                          const double *coefp, int half, int nblk, hipStream_t st);
+int fac_row_blocks(const WsLayout &L);
 hipError_t launch_nqs_dtilde(const irl_system *s, int V, int H, const double *theta,
                              const WsLayout &L, void *ws, hipStream_t st);
 hipError_t launch_dtilde_import(const void *D, int64_t ld, int64_t ncols, int dtype,
