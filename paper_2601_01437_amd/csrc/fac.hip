@@ -1,0 +1,500 @@
+// Factored Jacobian of the one-hidden-layer network on gfx950 FP64 matrix cores.
+//
+// The rows of D~ are [psi, x, d, d (x) x] with d_h = 1 - t_h^2 (Methods, "From SR
+// to a Stable Eigenvalue Problem": the tangent vectors are psi and its parameter
+// derivatives), so every product with D~ reduces to contractions with the 0/1
+// occupation matrix X (N_s x V) and the stored d (N_s x H):
+//   forward   z = X W^T + b,  t = tanh z,  d = 1 - t^2,  psi = X a + sum_h t
+//   D~ v      w_r = psi_r v_0 + x_r . v_a + sum_h d_rh (v_b[h] + (X V_W^T)_rh)
+//   D~^T c    [sum c psi, X^T c, d^T c, ((c d)^T X)_hv]
+// X W^T and (c d)^T X run on v_mfma_f64_16x16x4f64 (the dense FP64 contraction of
+// the method: N_s V H multiply-adds per product); the rest is elementwise.
+//
+// Operand layout of the 16x16x4 FP64 MFMA (lane l, one wavefront): the lane
+// supplies A[l % 16][l / 16] and B[l / 16][l % 16] and receives D[4 r + l / 16][l % 16]
+// in register r.  Hidden units are relabelled inside a 64-wide chunk t so that
+// lane l owns the 4 consecutive units h = 64 t + 4 (l % 16) + q of its column or row
+// index: its d loads and stores are 32 contiguous bytes.
+#include "internal.h"
+
+namespace irl {
+
+typedef double d4v __attribute__((ext_vector_type(4)));
+typedef double d2v __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ d4v mfma_f64(double a, double b, d4v c)
+{
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// occupation bits over v: alpha orbitals at v < n, beta at v = n + p
+__device__ __forceinline__ uint64_t occ_bits(uint64_t key, int n)
+{
+    return (key & 0xffffffffull) | ((key >> 32) << n);
+}
+
+// d[row][h0 .. h0 + 3] (zero past H); H4: H % 4 == 0, so the 32 bytes are aligned
+template <bool H4>
+__device__ __forceinline__ void load_d4(const double *__restrict__ dfac, int64_t row, int H, int h0, double (&d)[4])
+{
+    const double *p = dfac + row * H + h0;
+    if (H4 && h0 < H) {
+        const d2v lo = *(const d2v *)p, hi = *(const d2v *)(p + 2);
+        d[0] = lo.x;
+        d[1] = lo.y;
+        d[2] = hi.x;
+        d[3] = hi.y;
+    } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) d[q] = h0 + q < H ? p[q] : 0.0;
+    }
+}
+
+template <bool H4>
+__device__ __forceinline__ void store_d4(double *__restrict__ dfac, int64_t row, int H, int h0, const double (&d)[4])
+{
+    double *p = dfac + row * H + h0;
+    if (H4 && h0 < H) {
+        *(d2v *)p = d2v{d[0], d[1]};
+        *(d2v *)(p + 2) = d2v{d[2], d[3]};
+    } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (h0 + q < H) p[q] = d[q];
+    }
+}
+
+// B operand of Z = X M^T for hidden chunk t (M: H x V, row-major): for k-step kk
+// and column tile q the lane holds M[h][v] at v = 4 kk + l / 16, h = 64 t + 4 (l % 16) + q
+// (zero outside v < V, h < H).
+template <int KS>
+__device__ __forceinline__ void load_bt(const double *__restrict__ M, int V, int H, int t, int lane,
+                                        double (&B)[KS][4])
+{
+    const int vs = lane >> 4, h0 = 64 * t + 4 * (lane & 15);
+#pragma unroll
+    for (int kk = 0; kk < KS; ++kk)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int v = 4 * kk + vs, h = h0 + q;
+            B[kk][q] = (v < V && h < H) ? M[(size_t)h * V + v] : 0.0;
+        }
+}
+
+// Z for the 16 rows of a tile (the lane's A row is l % 16, occupation bits xa)
+// and the 64 hidden units of the chunk: acc[q][r] = Z[4 r + l / 16][64 t + 4 (l % 16) + q]
+template <int KS>
+__device__ __forceinline__ void z_tile(uint64_t xa, int lane, const double (&B)[KS][4], d4v (&acc)[4])
+{
+    const int vs = lane >> 4;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[q] = d4v{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int kk = 0; kk < KS; ++kk) {
+        const double a = (double)(uint32_t)((xa >> (4 * kk + vs)) & 1ull);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[q] = mfma_f64(a, B[kk][q], acc[q]);
+    }
+}
+
+// x_r . u for the lane's A row (l % 16): partial over the lane's k-steps, then the
+// four lanes of the row are added (every lane of the row ends with the total)
+template <int KS>
+__device__ __forceinline__ double x_dot(uint64_t xa, int lane, const double (&uk)[KS])
+{
+    const int vs = lane >> 4;
+    double s = 0.0;
+#pragma unroll
+    for (int kk = 0; kk < KS; ++kk) s += ((xa >> (4 * kk + vs)) & 1ull) ? uk[kk] : 0.0;
+    s += __shfl_xor(s, 16, kWave);
+    s += __shfl_xor(s, 32, kWave);
+    return s;
+}
+
+// per-row sums p[r] (row 4 r + l / 16) over the 16 lanes of each quarter, handed to
+// lane j < 16 as the sum of row j
+__device__ __forceinline__ double rows_to_lanes(double (&p)[4], int lane)
+{
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+        for (int off = 1; off < 16; off <<= 1) p[r] += __shfl_xor(p[r], off, kWave);
+    const int j = lane & 15, src = 16 * (j & 3);
+    double out = 0.0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const double v = __shfl(p[r], src, kWave);
+        if ((j >> 2) == r) out = v;
+    }
+    return out;
+}
+
+// ---------------------------------------------------------------------------
+// forward pass: psi (N_s) and d (N_s x H) from theta = [a, b, W]
+template <int KS, bool H4>
+__global__ __launch_bounds__(256) void k_fac_forward(const uint64_t *__restrict__ keys, int64_t ns, int n,
+                                                     int V, int H, const double *__restrict__ theta,
+                                                     double *__restrict__ psi, double *__restrict__ dfac)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t ntile = (ns + 15) / 16, nw = (int64_t)gridDim.x * 4;
+    const double *a = theta, *b = theta + V, *W = theta + V + H;
+    double ak[KS];
+#pragma unroll
+    for (int kk = 0; kk < KS; ++kk) {
+        const int v = 4 * kk + (lane >> 4);
+        ak[kk] = v < V ? a[v] : 0.0;
+    }
+    const int htiles = (H + 63) / 64;
+    for (int t = 0; t < htiles; ++t) {
+        double B[KS][4], bh[4];
+        load_bt<KS>(W, V, H, t, lane, B);
+        const int h0 = 64 * t + 4 * (lane & 15);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) bh[q] = h0 + q < H ? b[h0 + q] : 0.0;
+        for (int64_t tile = (int64_t)blockIdx.x * 4 + wv; tile < ntile; tile += nw) {
+            const int64_t r0 = tile * 16, ra = r0 + (lane & 15);
+            const uint64_t xa = ra < ns ? occ_bits(keys[ra], n) : 0ull;
+            d4v acc[4];
+            z_tile<KS>(xa, lane, B, acc);
+            double ts[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t row = r0 + 4 * r + (lane >> 4);
+                double d[4], s = 0.0;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const double th = tanh(acc[q][r] + bh[q]);
+                    s += h0 + q < H ? th : 0.0;
+                    d[q] = 1.0 - th * th;
+                }
+                if (row < ns) store_d4<H4>(dfac, row, H, h0, d);
+                ts[r] = s;
+            }
+            double pj = rows_to_lanes(ts, lane);
+            if (t == 0) pj += x_dot<KS>(xa, lane, ak);
+            if (lane < 16 && ra < ns) psi[ra] = (t == 0 ? 0.0 : psi[ra]) + pj;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// w = D~ v with v = [v_0, v_a, v_b, V_W] (v_0 taken as 0 when zero_v0)
+template <int KS, bool H4>
+__global__ __launch_bounds__(256) void k_fac_jvp(const uint64_t *__restrict__ keys, int64_t ns, int n, int V,
+                                                 int H, const double *__restrict__ dfac,
+                                                 const double *__restrict__ psi, const double *__restrict__ v,
+                                                 int zero_v0, double *__restrict__ w)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t ntile = (ns + 15) / 16, nw = (int64_t)gridDim.x * 4;
+    const double *va = v + 1, *vb = v + 1 + V, *vW = v + 1 + V + H;
+    const double v0 = zero_v0 ? 0.0 : v[0];
+    double ak[KS];
+#pragma unroll
+    for (int kk = 0; kk < KS; ++kk) {
+        const int vv = 4 * kk + (lane >> 4);
+        ak[kk] = vv < V ? va[vv] : 0.0;
+    }
+    const int htiles = (H + 63) / 64;
+    for (int t = 0; t < htiles; ++t) {
+        double B[KS][4], bh[4];
+        load_bt<KS>(vW, V, H, t, lane, B);
+        const int h0 = 64 * t + 4 * (lane & 15);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) bh[q] = h0 + q < H ? vb[h0 + q] : 0.0;
+        for (int64_t tile = (int64_t)blockIdx.x * 4 + wv; tile < ntile; tile += nw) {
+            const int64_t r0 = tile * 16, ra = r0 + (lane & 15);
+            // d of the lane's 4 output rows, issued ahead of the matrix products
+            double d[4][4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t row = r0 + 4 * r + (lane >> 4);
+                if (row < ns) {
+                    load_d4<H4>(dfac, row, H, h0, d[r]);
+                } else {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) d[r][q] = 0.0;
+                }
+            }
+            const uint64_t xa = ra < ns ? occ_bits(keys[ra], n) : 0ull;
+            d4v acc[4];
+            z_tile<KS>(xa, lane, B, acc);
+            double p[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                double s = 0.0;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) s += d[r][q] * (acc[q][r] + bh[q]);
+                p[r] = s;
+            }
+            double pj = rows_to_lanes(p, lane);
+            if (t == 0) {
+                pj += x_dot<KS>(xa, lane, ak);
+                if (lane < 16 && ra < ns) pj += psi[ra] * v0;
+            }
+            if (lane < 16 && ra < ns) w[ra] = (t == 0 ? 0.0 : w[ra]) + pj;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// partial rows of D~^T c, c_r = y_r - coef psi_r, into half `half` of each row
+// block's pair of rows.  Grid (hidden chunks of 64, row blocks); each wave takes
+// groups of 4 rows (the K of the matrix product).  A[h][k] = c_k d_kh, B[k][v] = x_kv;
+// the b entries (sum c d), the a entries (sum c x) and the psi entry (sum c psi)
+// are lane-local sums beside the product.  The 4 waves are combined in a fixed
+// order and wave 0 writes the entries of the partial row that belong to its
+// chunk (chunk 0 also the psi, a and padding entries).
+template <int NT, bool H4>
+__global__ __launch_bounds__(256) void k_fac_vjp(const uint64_t *__restrict__ keys, int64_t ns, int n, int V,
+                                                 int H, const double *__restrict__ dfac,
+                                                 const double *__restrict__ psi, const double *__restrict__ y,
+                                                 const double *__restrict__ coefp, double *__restrict__ part,
+                                                 int64_t ldv, int nblk, int half)
+{
+    constexpr int kAcc = 16 * NT + 4 + NT + 1;   // doubles per lane in the wave combination
+    __shared__ double red[64 * kAcc];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int ht = blockIdx.x, rb = blockIdx.y;
+    const int64_t per = (ns + nblk - 1) / nblk;
+    const int64_t r0 = (int64_t)rb * per, r1 = min(ns, r0 + per);
+    const double coef = coefp ? *coefp : 0.0;
+    const int kq = lane >> 4, i = lane & 15, h0 = 64 * ht + 4 * i;
+    d4v acc[4][NT];
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int nn = 0; nn < NT; ++nn) acc[m][nn] = d4v{0.0, 0.0, 0.0, 0.0};
+    double accB[4] = {0.0, 0.0, 0.0, 0.0}, accA[NT], acc0 = 0.0;
+#pragma unroll
+    for (int nn = 0; nn < NT; ++nn) accA[nn] = 0.0;
+
+    for (int64_t g = r0 + 4 * wv; g < r1; g += 16) {
+        const int64_t row = g + kq;
+        double c = 0.0, ps = 0.0, d[4] = {0.0, 0.0, 0.0, 0.0};
+        uint64_t x = 0ull;
+        if (row < r1) {
+            load_d4<H4>(dfac, row, H, h0, d);
+            ps = psi[row];
+            c = y[row] - coef * ps;
+            x = occ_bits(keys[row], n);
+        }
+        double A[4], Bv[NT];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            A[m] = c * d[m];
+            accB[m] += A[m];
+        }
+#pragma unroll
+        for (int nn = 0; nn < NT; ++nn) Bv[nn] = (double)(uint32_t)((x >> (16 * nn + i)) & 1ull);
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int nn = 0; nn < NT; ++nn) acc[m][nn] = mfma_f64(A[m], Bv[nn], acc[m][nn]);
+        if (ht == 0) {
+#pragma unroll
+            for (int nn = 0; nn < NT; ++nn) accA[nn] += c * Bv[nn];
+            acc0 += c * ps;
+        }
+    }
+    // sums over the 4 rows of a group (the lane quarters)
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        accB[m] += __shfl_xor(accB[m], 16, kWave);
+        accB[m] += __shfl_xor(accB[m], 32, kWave);
+    }
+#pragma unroll
+    for (int nn = 0; nn < NT; ++nn) {
+        accA[nn] += __shfl_xor(accA[nn], 16, kWave);
+        accA[nn] += __shfl_xor(accA[nn], 32, kWave);
+    }
+    acc0 += __shfl_xor(acc0, 16, kWave);
+    acc0 += __shfl_xor(acc0, 32, kWave);
+
+    // fixed-order combination of the 4 waves: ((w0 + w1) + w2) + w3
+    for (int src = 1; src < 4; ++src) {
+        __syncthreads();
+        if (wv == src) {
+            double *o = red + lane;
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+#pragma unroll
+                for (int nn = 0; nn < NT; ++nn)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) o[64 * ((m * NT + nn) * 4 + r)] = acc[m][nn][r];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) o[64 * (16 * NT + m)] = accB[m];
+#pragma unroll
+            for (int nn = 0; nn < NT; ++nn) o[64 * (16 * NT + 4 + nn)] = accA[nn];
+            o[64 * (kAcc - 1)] = acc0;
+        }
+        __syncthreads();
+        if (wv == 0) {
+            const double *o = red + lane;
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+#pragma unroll
+                for (int nn = 0; nn < NT; ++nn)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) acc[m][nn][r] += o[64 * ((m * NT + nn) * 4 + r)];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) accB[m] += o[64 * (16 * NT + m)];
+#pragma unroll
+            for (int nn = 0; nn < NT; ++nn) accA[nn] += o[64 * (16 * NT + 4 + nn)];
+            acc0 += o[64 * (kAcc - 1)];
+        }
+    }
+    if (wv != 0) return;
+    double *out = part + ((int64_t)rb * 2 + half) * ldv;
+    const int64_t baseW = 1 + V + H;
+    // acc[m][nn][r] = sum c d_h x_v at h = 64 ht + 4 (4 r + l / 16) + m, v = 16 nn + l % 16
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const int h = 64 * ht + 16 * r + 4 * kq + m;
+            if (h < H)
+#pragma unroll
+                for (int nn = 0; nn < NT; ++nn) {
+                    const int vv = 16 * nn + i;
+                    if (vv < V) out[baseW + (int64_t)h * V + vv] = acc[m][nn][r];
+                }
+        }
+    if (lane < 16) {
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+            if (h0 + m < H) out[1 + V + h0 + m] = accB[m];
+        if (ht == 0) {
+#pragma unroll
+            for (int nn = 0; nn < NT; ++nn)
+                if (16 * nn + lane < V) out[1 + 16 * nn + lane] = accA[nn];
+        }
+    }
+    if (ht == 0) {
+        if (lane == 0) out[0] = acc0;
+        const int64_t P1 = (int64_t)V * H + H + V + 1;
+        for (int64_t col = P1 + lane; col < ldv; col += 64) out[col] = 0.0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launchers: KS = k-steps of 4 visible units (even, V <= 4 KS), NT = column tiles of
+// 16 visible units (V <= 16 NT)
+
+namespace {
+
+int fac_tile_blocks(int64_t ns)
+{
+    int64_t blocks = (ns + 63) / 64;   // 4 waves x one 16-row tile each
+    if (blocks > 1024) blocks = 1024;
+    return (int)(blocks < 1 ? 1 : blocks);
+}
+
+template <int KS>
+void forward_ks(const irl_system *s, const WsLayout &L, int V, int H, const double *theta, double *psi,
+                double *dfac, hipStream_t st)
+{
+    const int blocks = fac_tile_blocks(L.ns);
+    if (H % 4 == 0)
+        k_fac_forward<KS, true><<<blocks, 256, 0, st>>>(s->d.keys, L.ns, s->n, V, H, theta, psi, dfac);
+    else
+        k_fac_forward<KS, false><<<blocks, 256, 0, st>>>(s->d.keys, L.ns, s->n, V, H, theta, psi, dfac);
+}
+
+template <int KS>
+void jvp_ks(const irl_system *s, const WsLayout &L, int V, int H, const double *dfac, const double *psi,
+            const double *v, int zero_v0, double *w, hipStream_t st)
+{
+    const int blocks = fac_tile_blocks(L.ns);
+    if (H % 4 == 0)
+        k_fac_jvp<KS, true><<<blocks, 256, 0, st>>>(s->d.keys, L.ns, s->n, V, H, dfac, psi, v, zero_v0, w);
+    else
+        k_fac_jvp<KS, false><<<blocks, 256, 0, st>>>(s->d.keys, L.ns, s->n, V, H, dfac, psi, v, zero_v0, w);
+}
+
+template <int NT>
+void vjp_nt(const irl_system *s, const WsLayout &L, int V, int H, const double *dfac, const double *psi,
+            const double *y, const double *coefp, double *part, int nblk, int half, hipStream_t st)
+{
+    const dim3 grid((H + 63) / 64, nblk);
+    if (H % 4 == 0)
+        k_fac_vjp<NT, true><<<grid, 256, 0, st>>>(s->d.keys, L.ns, s->n, V, H, dfac, psi, y, coefp, part,
+                                                  L.ldv, nblk, half);
+    else
+        k_fac_vjp<NT, false><<<grid, 256, 0, st>>>(s->d.keys, L.ns, s->n, V, H, dfac, psi, y, coefp, part,
+                                                   L.ldv, nblk, half);
+}
+
+bool fac_shape_ok(const irl_system *s, const WsLayout &L)
+{
+    const int V = 2 * s->n;
+    return (L.flags & IRL_WS_FACTORED) && L.hfac >= 1 && V >= 1 && V <= 64 &&
+           (int64_t)V * L.hfac + L.hfac + V + 1 <= L.ldv;
+}
+
+}  // namespace
+
+hipError_t launch_fac_forward(const irl_system *s, const WsLayout &L, void *ws, const double *theta,
+                              hipStream_t st)
+{
+    if (!fac_shape_ok(s, L)) return hipErrorInvalidValue;
+    const int V = 2 * s->n, H = L.hfac;
+    double *psi = ws_ptr<double>(ws, L.off_psi), *dfac = ws_ptr<double>(ws, L.off_fac);
+    switch ((V + 7) / 8) {
+    case 1: forward_ks<2>(s, L, V, H, theta, psi, dfac, st); break;
+    case 2: forward_ks<4>(s, L, V, H, theta, psi, dfac, st); break;
+    case 3: forward_ks<6>(s, L, V, H, theta, psi, dfac, st); break;
+    case 4: forward_ks<8>(s, L, V, H, theta, psi, dfac, st); break;
+    case 5: forward_ks<10>(s, L, V, H, theta, psi, dfac, st); break;
+    case 6: forward_ks<12>(s, L, V, H, theta, psi, dfac, st); break;
+    case 7: forward_ks<14>(s, L, V, H, theta, psi, dfac, st); break;
+    default: forward_ks<16>(s, L, V, H, theta, psi, dfac, st); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_fac_jvp(const irl_system *s, const WsLayout &L, void *ws, const double *v, int zero_v0,
+                          double *w, hipStream_t st)
+{
+    if (!fac_shape_ok(s, L)) return hipErrorInvalidValue;
+    const int V = 2 * s->n, H = L.hfac;
+    const double *psi = ws_ptr<double>(ws, L.off_psi), *dfac = ws_ptr<double>(ws, L.off_fac);
+    switch ((V + 7) / 8) {
+    case 1: jvp_ks<2>(s, L, V, H, dfac, psi, v, zero_v0, w, st); break;
+    case 2: jvp_ks<4>(s, L, V, H, dfac, psi, v, zero_v0, w, st); break;
+    case 3: jvp_ks<6>(s, L, V, H, dfac, psi, v, zero_v0, w, st); break;
+    case 4: jvp_ks<8>(s, L, V, H, dfac, psi, v, zero_v0, w, st); break;
+    case 5: jvp_ks<10>(s, L, V, H, dfac, psi, v, zero_v0, w, st); break;
+    case 6: jvp_ks<12>(s, L, V, H, dfac, psi, v, zero_v0, w, st); break;
+    case 7: jvp_ks<14>(s, L, V, H, dfac, psi, v, zero_v0, w, st); break;
+    default: jvp_ks<16>(s, L, V, H, dfac, psi, v, zero_v0, w, st); break;
+    }
+    return hipGetLastError();
+}
+
+int fac_row_blocks(const WsLayout &L)
+{
+    const int htiles = (L.hfac + 63) / 64;
+    int nblk = kStreamBlocks / (htiles > 0 ? htiles : 1);
+    if (nblk < 1) nblk = 1;
+    if (nblk > (L.ns + 15) / 16) nblk = (int)((L.ns + 15) / 16);
+    return nblk < 1 ? 1 : nblk;
+}
+
+hipError_t launch_fac_vjp(const irl_system *s, const WsLayout &L, void *ws, const double *y,
+                          const double *coefp, int half, int nblk, hipStream_t st)
+{
+    if (!fac_shape_ok(s, L) || nblk < 1 || nblk > kStreamBlocks) return hipErrorInvalidValue;
+    const int V = 2 * s->n, H = L.hfac;
+    const double *psi = ws_ptr<double>(ws, L.off_psi), *dfac = ws_ptr<double>(ws, L.off_fac);
+    double *part = ws_ptr<double>(ws, L.off_part);
+    switch ((V + 15) / 16) {
+    case 1: vjp_nt<1>(s, L, V, H, dfac, psi, y, coefp, part, nblk, half, st); break;
+    case 2: vjp_nt<2>(s, L, V, H, dfac, psi, y, coefp, part, nblk, half, st); break;
+    case 3: vjp_nt<3>(s, L, V, H, dfac, psi, y, coefp, part, nblk, half, st); break;
+    default: vjp_nt<4>(s, L, V, H, dfac, psi, y, coefp, part, nblk, half, st); break;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace irl

@@ -257,6 +257,8 @@ hipError_t launch_ham_row_list(const irl_system *s, int64_t row, int32_t *tgt, i
 hipError_t launch_nqs_grad(const irl_system *s, int V, int H, const double *theta, const WsLayout &L,
                            void *ws, int nblk, hipStream_t st);
 // factored Jacobian: w = D~ v and partial rows of D~^T (y - coef psi) (half 0 or 1)
+hipError_t launch_fac_forward(const irl_system *s, const WsLayout &L, void *ws, const double *theta,
+                              hipStream_t st);
 hipError_t launch_fac_jvp(const irl_system *s, const WsLayout &L, void *ws, const double *v, int zero_v0,
                           double *w, hipStream_t st);
 hipError_t launch_fac_vjp(const irl_system *s, const WsLayout &L, void *ws, const double *y,

@@ -184,6 +184,7 @@ hipError_t launch_nqs_dtilde(const irl_system *s, int V, int H, const double *th
 {
     double *D64 = (L.flags & IRL_WS_FP64) ? ws_ptr<double>(ws, L.off_d64) : nullptr;
     float *D32 = (L.flags & IRL_WS_FP32) ? ws_ptr<float>(ws, L.off_d32) : nullptr;
+    if (!D64 && !D32 && (L.flags & IRL_WS_FACTORED)) return launch_fac_forward(s, L, ws, theta, st);
     int64_t blocks = (L.ns + 3) / 4;
     if (blocks > 16384) blocks = 16384;
     double *dfac = (L.flags & IRL_WS_FACTORED) ? ws_ptr<double>(ws, L.off_fac) : nullptr;
@@ -211,46 +212,38 @@ hipError_t launch_nqs_dtilde(const irl_system *s, int V, int H, const double *th
 // layout the two-level D~^T reduction reads.
 constexpr int kGradVmax = 64;
 
-// D~^T c over rows [r0, r1) for the hidden units of tile ht, c_r = y_r - coef psi_r.
-// RECOMPUTE: d = 1 - t^2 from theta (W rows of the tile staged in LDS); else d is
-// read from the factored Jacobian dfac (rows of H).  VMAX >= V bounds the static
-// loop over the visible units.  The 4 waves are combined in a fixed order and
-// wave 0 writes entries [0, ldv) of the partial row `out` that belong to this
-// tile (tile 0 also writes the psi, x and padding entries).
-template <bool RECOMPUTE, int VMAX>
+// D~^T c over rows [r0, r1) for the hidden units of tile ht, c_r = y_r - coef psi_r,
+// with d = 1 - t^2 recomputed from theta (W rows of the tile staged in LDS).  VMAX
+// >= V bounds the static loop over the visible units.  The 4 waves are combined in
+// a fixed order and wave 0 writes entries [0, ldv) of the partial row `out` that
+// belong to this tile (tile 0 also writes the psi, x and padding entries).
+template <int VMAX>
 __device__ __forceinline__ void vjp_block(const uint64_t *__restrict__ keys, int64_t r0, int64_t r1,
                                           int n, int V, int H, int ht, const double *__restrict__ theta,
-                                          const double *__restrict__ dfac, const double *__restrict__ psi,
-                                          const double *__restrict__ y, double coef,
-                                          double *__restrict__ out, int64_t ldv, double *Wt, double *red)
+                                          const double *__restrict__ psi, const double *__restrict__ y,
+                                          double coef, double *__restrict__ out, int64_t ldv, double *Wt,
+                                          double *red)
 {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int h = ht * 64 + lane;
     const bool hv = h < H;
     constexpr int kWs = kGradVmax + 1;   // odd LDS row stride: lanes read distinct banks
-    double bh = 0.0;
-    if constexpr (RECOMPUTE) {
-        const double *b = theta + V, *W = theta + V + H;
-        for (int i = threadIdx.x; i < 64 * kWs; i += blockDim.x) {
-            const int hh = i / kWs, v = i - hh * kWs;
-            Wt[i] = (v < V && ht * 64 + hh < H) ? W[(size_t)(ht * 64 + hh) * V + v] : 0.0;
-        }
-        __syncthreads();
-        bh = hv ? b[h] : 0.0;
+    const double *b = theta + V, *W = theta + V + H;
+    for (int i = threadIdx.x; i < 64 * kWs; i += blockDim.x) {
+        const int hh = i / kWs, v = i - hh * kWs;
+        Wt[i] = (v < V && ht * 64 + hh < H) ? W[(size_t)(ht * 64 + hh) * V + v] : 0.0;
     }
+    __syncthreads();
+    const double bh = hv ? b[h] : 0.0;
     double accW[VMAX];
 #pragma unroll
     for (int v = 0; v < VMAX; ++v) accW[v] = 0.0;
     double accB = 0.0, accA = 0.0, acc0 = 0.0;
-    auto row_d = [&](int64_t r, uint64_t xm) -> double {
-        if constexpr (RECOMPUTE) {
-            double z = bh;
-            for (uint64_t m = xm; m; m &= m - 1) z += Wt[lane * kWs + (__ffsll((unsigned long long)m) - 1)];
-            const double t = tanh(z);
-            return 1.0 - t * t;
-        } else {
-            return hv ? dfac[r * H + h] : 0.0;
-        }
+    auto row_d = [&](uint64_t xm) -> double {
+        double z = bh;
+        for (uint64_t m = xm; m; m &= m - 1) z += Wt[lane * kWs + (__ffsll((unsigned long long)m) - 1)];
+        const double t = tanh(z);
+        return 1.0 - t * t;
     };
     auto accumulate = [&](double c, double dh, double ps, uint64_t xm) {
         const double d = c * dh;
@@ -270,7 +263,7 @@ __device__ __forceinline__ void vjp_block(const uint64_t *__restrict__ keys, int
         const uint64_t x1 = (k1 & 0xffffffffull) | ((k1 >> 32) << n);
         const double p0 = psi[r], p1 = psi[r + 4];
         const double c0 = y[r] - coef * p0, c1 = y[r + 4] - coef * p1;
-        const double d0 = row_d(r, x0), d1 = row_d(r + 4, x1);
+        const double d0 = row_d(x0), d1 = row_d(x1);
         accumulate(c0, d0, p0, x0);
         accumulate(c1, d1, p1, x1);
     }
@@ -278,7 +271,7 @@ __device__ __forceinline__ void vjp_block(const uint64_t *__restrict__ keys, int
         const uint64_t k0 = keys[r];
         const uint64_t x0 = (k0 & 0xffffffffull) | ((k0 >> 32) << n);
         const double p0 = psi[r];
-        accumulate(y[r] - coef * p0, row_d(r, x0), p0, x0);
+        accumulate(y[r] - coef * p0, row_d(x0), p0, x0);
     }
     // fixed-order combination of the 4 waves: ((w0 + w1) + w2) + w3
     constexpr int kRs = kGradVmax + 3;
@@ -331,136 +324,9 @@ __global__ __launch_bounds__(256) void k_nqs_grad(const uint64_t *__restrict__ k
     // the first half of the partial row (D~^T psi) is not formed here
     if (ht == 0)
         for (int64_t c = threadIdx.x; c < ldv; c += blockDim.x) pa[c] = 0.0;
-    vjp_block<true, kGradVmax>(keys, r0, r1, n, V, H, ht, theta, nullptr, psi, hpsi, sc->E_el, pa + ldv, ldv,
-                               Wt, red);
+    vjp_block<kGradVmax>(keys, r0, r1, n, V, H, ht, theta, psi, hpsi, sc->E_el, pa + ldv, ldv, Wt, red);
 }
 
-// ---------------------------------------------------------------------------
-// Factored Jacobian (one hidden layer): the rows of D~ are [psi, x, d, d (x) x]
-// with d = 1 - t^2 (Methods, "From SR to a Stable Eigenvalue Problem": the
-// tangent vectors are the parameter derivatives of psi), so
-//   (D~ v)_r   = psi_r v_0 + x_r . v_a + sum_h d_rh (v_b[h] + sum_{v in x_r} V_W[h, v])
-//   (D~^T y)   = [sum y psi, sum y x, sum y d, sum_r y_r d_r (x) x_r]
-// need only psi, d (N_s x H) and the occupations: the forward and backward
-// products of the network, with no (P + 1)-wide rows in memory.
-
-// w = D~ v (v_0 taken as 0 when zero_v0): rows [r0, r1) per block, hidden tiles of
-// 64 (V_W rows of the tile in LDS), per-row partial sums added in tile order.
-// The psi and x terms join the first tile's butterfly (lane v < V adds v_a[v] when
-// orbital v is occupied, lane 0 adds psi v_0).  Two rows per pass.
-__global__ __launch_bounds__(256) void k_fac_jvp(const uint64_t *__restrict__ keys, int64_t ns, int n,
-                                                 int V, int H, const double *__restrict__ dfac,
-                                                 const double *__restrict__ psi,
-                                                 const double *__restrict__ v, int zero_v0,
-                                                 double *__restrict__ w)
-{
-    __shared__ double Wt[64 * (kGradVmax + 1)];
-    constexpr int kWs = kGradVmax + 1;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int64_t per = (ns + gridDim.x - 1) / gridDim.x;
-    const int64_t r0 = (int64_t)blockIdx.x * per, r1 = min(ns, r0 + per);
-    const double v0 = zero_v0 ? 0.0 : v[0];
-    const double *vb = v + 1 + V, *vW = v + 1 + V + H;
-    const double va_l = lane < V ? v[1 + lane] : 0.0;
-    const int htiles = (H + 63) / 64;
-    for (int t = 0; t < htiles; ++t) {
-        __syncthreads();
-        for (int i = threadIdx.x; i < 64 * kWs; i += blockDim.x) {
-            const int hh = i / kWs, vv = i - hh * kWs;
-            Wt[i] = (vv < V && t * 64 + hh < H) ? vW[(size_t)(t * 64 + hh) * V + vv] : 0.0;
-        }
-        __syncthreads();
-        const int h = t * 64 + lane;
-        const bool hv = h < H;
-        const double vbh = hv ? vb[h] : 0.0;
-        auto term = [&](int64_t r, uint64_t xm) -> double {
-            double z = vbh;
-            for (uint64_t m = xm; m; m &= m - 1) z += Wt[lane * kWs + (__ffsll((unsigned long long)m) - 1)];
-            double p = hv ? dfac[r * H + h] * z : 0.0;
-            if (t == 0) {
-                if ((xm >> lane) & 1ull) p += va_l;
-                if (lane == 0) p += psi[r] * v0;
-            }
-            return p;
-        };
-        auto finish = [&](int64_t r, double p) {
-            for (int off = 32; off > 0; off >>= 1) p += __shfl_xor(p, off, kWave);
-            if (lane == 0) w[r] = (t == 0) ? p : w[r] + p;
-        };
-        int64_t r = r0 + wv;
-        for (; r + 4 < r1; r += 8) {
-            const uint64_t k0 = keys[r], k1 = keys[r + 4];
-            const double p0 = term(r, (k0 & 0xffffffffull) | ((k0 >> 32) << n));
-            const double p1 = term(r + 4, (k1 & 0xffffffffull) | ((k1 >> 32) << n));
-            finish(r, p0);
-            finish(r + 4, p1);
-        }
-        for (; r < r1; r += 4) {
-            const uint64_t k0 = keys[r];
-            finish(r, term(r, (k0 & 0xffffffffull) | ((k0 >> 32) << n)));
-        }
-    }
-}
-
-hipError_t launch_fac_jvp(const irl_system *s, const WsLayout &L, void *ws, const double *v, int zero_v0,
-                          double *w, hipStream_t st)
-{
-    const int V = 2 * s->n, H = L.hfac;
-    if (V > kGradVmax || H < 1 || !(L.flags & IRL_WS_FACTORED)) return hipErrorInvalidValue;
-    int64_t blocks = (L.ns + 255) / 256;
-    if (blocks > 2048) blocks = 2048;
-    k_fac_jvp<<<(unsigned)blocks, 256, 0, st>>>(s->d.keys, L.ns, s->n, V, H, ws_ptr<double>(ws, L.off_fac),
-                                                ws_ptr<double>(ws, L.off_psi), v, zero_v0, w);
-    return hipGetLastError();
-}
-
-// partial rows of D~^T (y - coef psi) into half `half` (0 or 1) of each block's pair of rows
-template <int VMAX>
-__global__ __launch_bounds__(256) void k_fac_vjp(const uint64_t *__restrict__ keys, int64_t ns, int n, int V,
-                                                 int H, const double *__restrict__ dfac,
-                                                 const double *__restrict__ psi, const double *__restrict__ y,
-                                                 const double *__restrict__ coefp, double *__restrict__ part,
-                                                 int64_t ldv, int nblk, int half)
-{
-    __shared__ double red[64 * (kGradVmax + 3)];
-    const int ht = blockIdx.x, rb = blockIdx.y;
-    const int64_t per = (ns + nblk - 1) / nblk;
-    const int64_t r0 = (int64_t)rb * per, r1 = min(ns, r0 + per);
-    const double coef = coefp ? *coefp : 0.0;
-    vjp_block<false, VMAX>(keys, r0, r1, n, V, H, ht, nullptr, dfac, psi, y, coef,
-                           part + ((int64_t)rb * 2 + half) * ldv, ldv, nullptr, red);
-}
-
-int fac_row_blocks(const WsLayout &L)
-{
-    const int htiles = (L.hfac + 63) / 64;
-    int nblk = kStreamBlocks / (htiles > 0 ? htiles : 1);
-    if (nblk < 1) nblk = 1;
-    if (nblk > (L.ns + 3) / 4) nblk = (int)((L.ns + 3) / 4);
-    return nblk;
-}
-
-hipError_t launch_fac_vjp(const irl_system *s, const WsLayout &L, void *ws, const double *y,
-                          const double *coefp, int half, int nblk, hipStream_t st)
-{
-    const int V = 2 * s->n, H = L.hfac;
-    if (V > kGradVmax || H < 1 || !(L.flags & IRL_WS_FACTORED) || nblk < 1 || nblk > kStreamBlocks)
-        return hipErrorInvalidValue;
-    const int htiles = (H + 63) / 64;
-    const dim3 grid(htiles, nblk);
-    const uint64_t *keys = s->d.keys;
-    const double *dfac = ws_ptr<double>(ws, L.off_fac), *psi = ws_ptr<double>(ws, L.off_psi);
-    double *part = ws_ptr<double>(ws, L.off_part);
-    if (V <= 16)
-        k_fac_vjp<16><<<grid, 256, 0, st>>>(keys, L.ns, s->n, V, H, dfac, psi, y, coefp, part, L.ldv, nblk, half);
-    else if (V <= 32)
-        k_fac_vjp<32><<<grid, 256, 0, st>>>(keys, L.ns, s->n, V, H, dfac, psi, y, coefp, part, L.ldv, nblk, half);
-    else if (V <= 48)
-        k_fac_vjp<48><<<grid, 256, 0, st>>>(keys, L.ns, s->n, V, H, dfac, psi, y, coefp, part, L.ldv, nblk, half);
-    else
-        k_fac_vjp<64><<<grid, 256, 0, st>>>(keys, L.ns, s->n, V, H, dfac, psi, y, coefp, part, L.ldv, nblk, half);
-    return hipGetLastError();
-}
 
 hipError_t launch_nqs_grad(const irl_system *s, int V, int H, const double *theta, const WsLayout &L,
                            void *ws, int nblk, hipStream_t st)

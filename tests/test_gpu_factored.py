@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 import synth
-from oracle import lm, nqs, step
+from oracle import capply, lm, nqs, step
 from tests.gpu_util import announce, dev, host, rel_err, require_gpu
 
 pytestmark = pytest.mark.gpu
@@ -67,9 +67,44 @@ def test_factored_matches_dense_fp64(n, na, nb, V, H, count, seed):
     yH1, yS1 = s.apply(v)
     Z2, E2, g2 = s.evaluate(V, H, theta, ws_flags=_fl())
     yH2, yS2 = s.apply(v)
-    assert Z1 == Z2 and E1 == E2                 # psi and H psi are the same kernels
+    assert abs(Z2 - Z1) <= 1e-13 * Z1 and abs(E2 - E1) <= 1e-12
     assert rel_err(host(g2), host(g1)) <= 1e-12
     assert rel_err(host(yH2), host(yH1)) <= 1e-12 and rel_err(host(yS2), host(yS1)) <= 1e-12
+
+
+@pytest.mark.parametrize("n,na,nb,H,count,seed", [
+    (6, 3, 2, 5, 151, 3),       # V = 12 (one column tile, two k-steps padded), H = 5 (unaligned d rows)
+    (8, 4, 3, 64, 1001, 4),     # V = 16, exactly one hidden chunk, ragged 16-row tail
+    (10, 5, 4, 130, 2047, 5),   # three hidden chunks (the last one 2 wide), H % 4 != 0
+    (11, 3, 3, 33, 17, 6),      # 17 rows: one full tile plus one row
+    (9, 5, 4, 7, 1, 7),         # one determinant
+])
+def test_factored_shapes_vs_oracle(n, na, nb, H, count, seed):
+    """Tile edges of the matrix-core kernels against the oracle's dense D~:
+    psi (through Z and E), the gradient and the operator pair."""
+    announce(f"factored shapes n={n} H={H} rows={count}")
+    V = 2 * n
+    keys = synth.cisd_like_selected_set(n, na, nb, count, seed=seed)
+    s, h, g = _system(n, na, nb, seed=seed, dets=keys)
+    Hm = capply.csr(n, h, g, keys)
+    th = synth.nqs_theta(V, H, seed, scale=0.3)
+    Dt = nqs.dtilde(keys, n, V, H, th)
+    Z, _, E = lm.energy(Dt[:, 0], Hm)
+    Zg, Eg, grad = s.evaluate(V, H, dev(th), ws_flags=_fl())
+    assert abs(Zg - Z) <= 1e-12 * Z and abs(Eg - E) <= 1e-12 * max(1.0, abs(E))
+    g_ref = lm.gradient(Dt, Hm)
+    if keys.size == 1:                      # psi is an eigenvector: the gradient vanishes
+        assert np.max(np.abs(host(grad))) <= 1e-12 * max(1.0, abs(E))
+    else:
+        assert rel_err(host(grad), g_ref) <= 1e-10
+    rng = np.random.default_rng(seed)
+    for zero_v0 in (False, True):
+        v = rng.normal(size=V * H + H + V + 1)
+        if zero_v0:
+            v[0] = 0.0
+        yH, yS = s.apply(dev(v))
+        rH, rS = lm.apply_lm_operator(Dt, Hm, v)
+        assert rel_err(host(yH), rH) <= 1e-10 and rel_err(host(yS), rS) <= 1e-10
 
 
 @pytest.mark.parametrize("m,k", [(20, 1), (12, 3)])
