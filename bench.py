@@ -38,10 +38,13 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+FP64_PEAK_TFLOPS = 78.6          # vector FP64 FMA rate: 256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz
+
+
 def kernel_bytes(kind, ns, ncols, s_build):
-    """Algorithmic HBM bytes of one launch (reads + writes the kernel must do).
-    The stream kernels read the FP64 copy of D~ (8 B per element) or, for the
-    *_fp32 kinds, the FP32 copy; the build writes every copy (s_build B)."""
+    """Algorithmic HBM bytes of one launch of a dense-D~ kernel (reads + writes the
+    kernel must do).  The stream kernels read the FP64 copy of D~ (8 B per element)
+    or, for the *_fp32 kinds, the FP32 copy; the build writes every copy (s_build B)."""
     sD = 4 if kind.endswith("_fp32") else 8
     if kind.startswith("gemv_t"):   # read D~, read the two row vectors
         return ns * ncols * sD + 2 * ns * 8
@@ -49,6 +52,40 @@ def kernel_bytes(kind, ns, ncols, s_build):
         return ns * ncols * sD + ncols * 8 + ns * 8
     if kind == "dtilde_build":      # write D~ (and psi)
         return ns * ncols * s_build + ns * 8
+    return None
+
+
+CSRC = os.path.join(ROOT, "paper_2601_01437_amd", "csrc")
+
+
+def kernel_roofline(kind, ns, ncols, H, factored, s_build, info, stored_bytes):
+    """(name, bound, algorithmic work per launch, unit, peak, source files) of one
+    timed kernel kind, or None.
+
+    - Dense D~ streams and the dense build: HBM bytes (kernel_bytes).
+    - Factored Jacobian (d = 1 - t^2 stored, N_s x H): the forward pass writes d and
+      psi and reads the keys; D~ v reads d, keys, psi and writes w; the apply's
+      backward pass D~^T [w, u] reads d, keys, psi, w and u.  HBM bytes (their FP64
+      matrix-core work, 2 N_s V H flops per product, is below the byte time at
+      8 TB/s for these shapes).
+    - Hamiltonian apply: stored rows stream their bytes (HBM); the enumerating
+      kernels do one FP64 multiply-add per candidate excitation (2 flops against
+      the vector FP64 peak)."""
+    P1 = ncols
+    if kind in ("gemv", "gemv_t", "dtilde_build") and factored:
+        name = {"gemv": "fac_jvp", "gemv_t": "fac_vjp", "dtilde_build": "fac_forward"}[kind]
+        nbytes = {"gemv": ns * (8 * H + 24) + 8 * P1, "gemv_t": ns * (8 * H + 32) + 16 * P1,
+                  "dtilde_build": ns * (8 * H + 16)}[kind]
+        return name, "hbm", nbytes, "GB/s", HBM_PEAK_GBPS, ("fac.hip", "internal.h")
+    if kind in ("gemv", "gemv_t", "gemv_fp32", "gemv_t_fp32", "dtilde_build"):
+        src = ("dtilde.hip", "internal.h") if kind != "dtilde_build" else ("nqs.hip", "internal.h")
+        return kind, "hbm", kernel_bytes(kind, ns, ncols, s_build), "GB/s", HBM_PEAK_GBPS, src
+    if kind == "ham_apply":
+        if info.ham_kernel == 4:
+            return ("ham_apply", "hbm", stored_bytes + 2 * ns * 8, "GB/s", HBM_PEAK_GBPS,
+                    ("hamiltonian.hip", "internal.h"))
+        return ("ham_apply", "alu", 2.0 * ns * info.max_connections, "TFLOP/s", FP64_PEAK_TFLOPS,
+                ("hamiltonian.hip", "internal.h"))
     return None
 
 
@@ -426,8 +463,9 @@ def main():
     ap.add_argument("--precision", default=None, choices=["fp64", "fp32"],
                     help="operator precision (default: the workload's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--jacobian", default="dense", choices=["dense", "factored"],
-                    help="FP64 operator: stream the dense D~ or use the factored Jacobian of the network")
+    ap.add_argument("--jacobian", default="factored", choices=["dense", "factored"],
+                    help="FP64 operator: products with the factored Jacobian of the network "
+                         "(default) or streams of the dense D~")
     ap.add_argument("--block", type=int, default=0,
                     help="vectors per operator pass: 0/1 implicitly restarted Lanczos, 2..8 block Lanczos")
     ap.add_argument("--polish", action="store_true",
@@ -541,23 +579,30 @@ def main():
     # final energy after the last update
     Zf, Ef, _ = sysm.evaluate(wl.V, wl.H, theta, ws_flags=ws_flags, want_grad=False)
 
-    # dominant kernel and its roofline
+    # dominant kernel and its roofline (every kernel kind's beside it)
     ncols = wl.P + 1
     kern = {k: {"ms_total": v[0], "launches": v[1], "ms_avg": v[0] / v[1] if v[1] else None}
             for k, v in stats.items() if v[1]}
-    src = [os.path.join(ROOT, "paper_2601_01437_amd", "csrc", f) for f in ("dtilde.hip", "internal.h")]
-    src_hash = source_hash(src)
-    roof = None
+    factored = bool(ws_flags & B.IRL_WS_FACTORED) and precision == B.IRL_FP64
     s_build = (8 if ws_flags & B.IRL_WS_FP64 else 0) + (4 if ws_flags & B.IRL_WS_FP32 else 0)
-    hbm_kinds = [k for k in ("gemv", "gemv_t", "gemv_fp32", "gemv_t_fp32", "dtilde_build") if k in kern]
-    roof_kernel = max(hbm_kinds, key=lambda k: kern[k]["ms_total"])
-    nbytes = kernel_bytes(roof_kernel, ns, ncols, s_build)
-    avg = kern[roof_kernel]["ms_avg"]
-    achieved = nbytes / (avg * 1e-3) / 1e9
-    traffic = read_traffic(roof_kernel, wl.name, src_hash)
-    roof = {"kernel": roof_kernel, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS,
-            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
-            "bytes_per_launch": nbytes, "ms_avg": avg, "source_hash": src_hash}
+    stored_bytes = store["bytes"] if store and store["stored"] else 0
+    rooflines = {}
+    for k, v in kern.items():
+        spec = kernel_roofline(k, ns, ncols, wl.H, factored, s_build, sysm.info, stored_bytes)
+        if spec is None:
+            continue
+        name, bound, work, unit, peak, src = spec
+        scale = 1e9 if unit == "GB/s" else 1e12
+        achieved = work / (v["ms_avg"] * 1e-3) / scale
+        src_hash = source_hash([os.path.join(CSRC, f) for f in src])
+        rooflines[name] = {"kernel": name, "bound": bound, "achieved": achieved, "peak": peak,
+                           "unit": unit, "frac": achieved / peak,
+                           "traffic": read_traffic(name, wl.name, src_hash) if bound == "hbm" or
+                           name == "ham_apply" else None,
+                           ("bytes_per_launch" if unit == "GB/s" else "flops_per_launch"): work,
+                           "ms_avg": v["ms_avg"], "ms_total": v["ms_total"], "launches": v["launches"],
+                           "source_hash": src_hash}
+    roof = max(rooflines.values(), key=lambda r: r["ms_total"]) if rooflines else None
     # whole operator apply, per D~ copy streamed: K6 + K4 + K7 + reduction averages
     operator = {}
     ham_avg = kern["ham_apply"]["ms_avg"]
@@ -565,8 +610,20 @@ def main():
     for tag, g6, g7, sDo in (("fp64", "gemv", "gemv_t", 8), ("fp32", "gemv_fp32", "gemv_t_fp32", 4)):
         if g6 not in kern or g7 not in kern:
             continue
-        apply_ms = kern[g6]["ms_avg"] + ham_avg + kern[g7]["ms_avg"] + red_avg
+        # bytes of one apply as the dense method streams them (D~ read twice + vectors)
         per_apply_bytes = 2 * ns * ncols * sDo + 6 * 8 * ns
+        if tag == "fp64" and factored:
+            # D~ v, H w, then D~^T [w, u] in one backward pass
+            apply_ms = kern[g6]["ms_avg"] + ham_avg + kern[g7]["ms_avg"] + red_avg
+            operator["fp64_factored"] = {
+                "applies": kern[g6]["launches"], "ms_per_apply": apply_ms,
+                "dense_stream_ms_at_peak": per_apply_bytes / (HBM_PEAK_GBPS * 1e9) * 1e3,
+                "dense_equivalent_GBps": per_apply_bytes / (apply_ms * 1e-3) / 1e9,
+                "vs_dense_stream_roofline": per_apply_bytes / (apply_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS,
+                "factored_bytes_per_apply": ns * (8 * wl.H + 24) + ns * (8 * wl.H + 32) + 2 * 8 * ns,
+                "bytes_per_apply_dense": per_apply_bytes}
+            continue
+        apply_ms = kern[g6]["ms_avg"] + ham_avg + kern[g7]["ms_avg"] + red_avg
         operator[tag] = {"applies": kern[g6]["launches"], "ms_per_apply": apply_ms,
                          "GBps": per_apply_bytes / (apply_ms * 1e-3) / 1e9,
                          "frac_hbm": per_apply_bytes / (apply_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS,
@@ -622,12 +679,15 @@ def main():
                                 f"{'full space' if dets is None else 'selected set'} "
                                 f"({ns} determinants), random molecule-like integrals seed {wl.seed}, "
                                 f"one-hidden-layer tanh network V={wl.V} H={wl.H} (P={wl.P}), "
-                                f"D~ {ns}x{ncols} {prec_name.upper()}, IRL m={wl.m} k_keep={wl.k} "
+                                + (f"factored Jacobian (d {ns}x{wl.H} FP64, D~ {ns}x{ncols} never formed), "
+                                   if factored else f"D~ {ns}x{ncols} {prec_name.upper()}, ")
+                                + f"IRL m={wl.m} k_keep={wl.k} "
                                 f"tol=1e-12" + (f", block Lanczos with {args.block} vectors per pass"
                                                 if args.block > 1 else "")),
                    "n_dets": ns, "P": wl.P, "m": wl.m, "k_keep": wl.k, "block": args.block,
                    "ham_kernel": HAM_KERNELS[sysm.info.ham_kernel]},
         "roofline": roof,
+        "rooflines": rooflines,
         "cpu_baseline": cpu,
         "operator": operator,
         "kernels": kern,

@@ -131,6 +131,7 @@ typedef struct {
                                2: string-product (full space), 3: beta-blocked
                                per-determinant (selected sets with n_orb <= 24),
                                4: stored rows (irl_system_store_hamiltonian) */
+    int32_t stored_col_blocks;  /* column blocks of the stored rows (0 unless ham_kernel == 4) */
 } irl_system_info;
 
 typedef struct {
@@ -199,13 +200,17 @@ int irl_system_info_get(const irl_system *sys, irl_system_info *out);
 /* Store the off-diagonal elements of H inside the set (Methods, "Wave Function
  * Ansatz": the second-quantised electronic Hamiltonian, whose elements between
  * determinants follow from the Slater-Condon rules) as
- * compressed rows: row offsets int64[n_dets + 1], targets int32[nnz], values
- * FP64[nnz], device memory owned by the system.  Later applies stream these
- * rows instead of enumerating excitations (ham_kernel becomes 4); results agree
- * with the enumerating kernels to rounding (summation order differs).  Two
+ * compressed rows split into column blocks: the targets of block b are rows
+ * [b 2^s, (b + 1) 2^s), a slice of the amplitude vector of about 2 MiB (at most 8
+ * blocks), so the gathers of one block stay in the L2 cache.  Layout: row offsets
+ * int64[blocks][n_dets + 1] (block-major), targets int32[nnz], values FP64[nnz],
+ * device memory owned by the system.  Later applies stream these rows one block
+ * at a time instead of enumerating excitations (ham_kernel becomes 4,
+ * stored_col_blocks reports the block count); results agree with the enumerating
+ * kernels to rounding (summation order differs) and are reproducible.  Two
  * enumeration passes count and fill the rows; the call synchronises stream.
  * max_bytes: device bytes the caller allows for the stored rows.
- * bytes_needed (may be NULL): receives (n_dets + 1) * 8 + nnz * 12.
+ * bytes_needed (may be NULL): receives blocks * (n_dets + 1) * 8 + nnz * 12.
  * Errors: IRL_ENOMEM when the rows need more than max_bytes or allocation
  * fails (the system is unchanged and stays usable), IRL_EDEVICE, IRL_EINVAL.
  * Calling it again after success does nothing. */

@@ -67,6 +67,7 @@ int dev_alloc(irl_system *s, T **p, size_t count)
 void free_system(irl_system *s)
 {
     if (!s) return;
+    free_dense_doubles(s);
     void *ptrs[] = {s->d.keys, s->d.h, s->d.g, s->d.diag, s->d.hkeys, s->d.hrows, s->d.rankA,
                     s->d.rankB, s->d.strA, s->d.strB, s->d.sglA, s->d.sglB, s->d.fA, s->d.fB,
                     s->d.dblA_rank, s->d.dblA_val, s->d.dblB_rank, s->d.dblB_val, s->d.jA,
@@ -179,7 +180,7 @@ int energy_and_gradient(irl_system *s, void *ws, const WsLayout &L, hipStream_t 
     double *y = ws_ptr<double>(ws, L.off_y);
     if (L.flags & IRL_WS_FACTORED) {
         nblk = fac_row_blocks(L);
-        TIMED(s, IRL_STAT_GEMV_T, st, launch_fac_vjp(s, L, ws, hpsi, &sc->E_el, 1, nblk, st));
+        TIMED(s, IRL_STAT_ENERGY, st, launch_fac_vjp(s, L, ws, hpsi, nullptr, &sc->E_el, 1, nblk, st));
         y = nullptr;
     } else if (prec == IRL_FP32 && nqs) {
         nblk = t2_blocks(L.ns, L.ld32, IRL_FP32);
@@ -206,12 +207,11 @@ int apply_internal(irl_system *s, void *ws, const WsLayout &L, const double *v, 
 {
     double *w = ws_ptr<double>(ws, L.off_w), *u = ws_ptr<double>(ws, L.off_u);
     if (prec == IRL_FP64 && (L.flags & IRL_WS_FACTORED)) {
-        // factored Jacobian: forward product, H, two backward products
+        // factored Jacobian: forward product, H, both backward products in one pass
         TIMED(s, IRL_STAT_GEMV, st, launch_fac_jvp(s, L, ws, v, zero_v0, w, st));
         TIMED(s, IRL_STAT_HAM_APPLY, st, launch_ham_apply(s, w, u, st));
         const int nb = fac_row_blocks(L);
-        TIMED(s, IRL_STAT_GEMV_T, st, launch_fac_vjp(s, L, ws, w, nullptr, 0, nb, st));
-        TIMED(s, IRL_STAT_GEMV_T, st, launch_fac_vjp(s, L, ws, u, nullptr, 1, nb, st));
+        TIMED(s, IRL_STAT_GEMV_T, st, launch_fac_vjp(s, L, ws, w, u, nullptr, 0, nb, st));
         TIMED(s, IRL_STAT_REDUCE, st, launch_t2_reduce(L, ws, nb, yS, yH, L.ncols, 1.0, nullptr, st));
         return IRL_OK;
     }
@@ -682,27 +682,50 @@ int irl_system_store_hamiltonian(irl_system *s, size_t max_bytes, size_t *bytes_
     if (!s) return set_err(nullptr, IRL_EINVAL, "system is NULL");
     const int64_t ns = s->ns;
     if (s->ham_kernel == 4) {
-        if (bytes_needed) *bytes_needed = (size_t)(ns + 1) * 8 + (size_t)s->d.hnnz * 12;
+        if (bytes_needed) *bytes_needed = (size_t)s->d.hcb * (ns + 1) * 8 + (size_t)s->d.hnnz * 12;
         return IRL_OK;
     }
+    // column blocks: slices of w of about kColSliceBytes, a power of two rows wide
+    int hcs = 0;
+    while (hcs < 40 && ((int64_t)8 << hcs) < kColSliceBytes) ++hcs;
+    while (((ns + ((int64_t)1 << hcs) - 1) >> hcs) > kMaxColBlocks) ++hcs;
+    const int hcb = (int)((ns + ((int64_t)1 << hcs) - 1) >> hcs);
     hipStream_t st = (hipStream_t)stream;
     int32_t *dcount = nullptr;
-    CK(s, hipMalloc((void **)&dcount, (size_t)ns * 4));
-    std::vector<int32_t> count((size_t)ns);
+    CK(s, hipMalloc((void **)&dcount, (size_t)hcb * ns * 4));
+    std::vector<int32_t> count((size_t)hcb * ns);
+    s->d.hcb = hcb;               // read by the count and fill passes
+    s->d.hcs = hcs;
     hipError_t e = launch_ham_count(s, dcount, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(count.data(), dcount, (size_t)ns * 4, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(count.data(), dcount, (size_t)hcb * ns * 4, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     (void)hipFree(dcount);
-    if (e != hipSuccess) return set_err(s, IRL_EDEVICE, std::string("row counts: ") + hipGetErrorString(e));
-    std::vector<int64_t> ptr((size_t)ns + 1);
-    ptr[0] = 0;
-    for (int64_t r = 0; r < ns; ++r) ptr[r + 1] = ptr[r] + count[r];
-    const int64_t nnz = ptr[ns];
-    const size_t bytes = (size_t)(ns + 1) * 8 + (size_t)nnz * 12;
+    auto unset = [&]() {
+        s->d.hcb = 0;
+        s->d.hcs = 0;
+    };
+    if (e != hipSuccess) {
+        unset();
+        return set_err(s, IRL_EDEVICE, std::string("row counts: ") + hipGetErrorString(e));
+    }
+    // block-major offsets: all rows of block 0, then of block 1, ...
+    std::vector<int64_t> ptr((size_t)hcb * (ns + 1));
+    int64_t nnz = 0;
+    for (int b = 0; b < hcb; ++b) {
+        int64_t *pb = ptr.data() + (size_t)b * (ns + 1);
+        const int32_t *cb = count.data() + (size_t)b * ns;
+        pb[0] = nnz;
+        for (int64_t r = 0; r < ns; ++r) pb[r + 1] = pb[r] + cb[r];
+        nnz = pb[ns];
+    }
+    const size_t bytes = (size_t)hcb * (ns + 1) * 8 + (size_t)nnz * 12;
     if (bytes_needed) *bytes_needed = bytes;
-    if (bytes > max_bytes)
+    if (bytes > max_bytes) {
+        unset();
         return set_err(s, IRL_ENOMEM, "stored rows need " + std::to_string(bytes) +
                                           " bytes, more than max_bytes = " + std::to_string(max_bytes));
+    }
     int rc;
     const size_t bytes_before = s->dev_bytes;
     auto release = [&]() {
@@ -712,8 +735,9 @@ int irl_system_store_hamiltonian(irl_system *s, size_t max_bytes, size_t *bytes_
         s->d.hptr = nullptr;
         s->d.hcol = nullptr;
         s->d.hval = nullptr;
+        unset();
     };
-    if ((rc = dev_alloc(s, &s->d.hptr, (size_t)ns + 1)) != IRL_OK ||
+    if ((rc = dev_alloc(s, &s->d.hptr, (size_t)hcb * (ns + 1))) != IRL_OK ||
         (rc = dev_alloc(s, &s->d.hcol, (size_t)nnz)) != IRL_OK ||
         (rc = dev_alloc(s, &s->d.hval, (size_t)nnz)) != IRL_OK) {
         release();
@@ -749,6 +773,7 @@ int irl_system_info_get(const irl_system *s, irl_system_info *o)
                          (int64_t)s->na * va * s->nb * vb;
     o->device_bytes = s->dev_bytes;
     o->ham_kernel = s->ham_kernel;
+    o->stored_col_blocks = s->ham_kernel == 4 ? s->d.hcb : 0;
     return IRL_OK;
 }
 

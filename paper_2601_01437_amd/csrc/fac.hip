@@ -14,7 +14,8 @@
 // supplies A[l % 16][l / 16] and B[l / 16][l % 16] and receives D[4 r + l / 16][l % 16]
 // in register r.  Hidden units are relabelled inside a 64-wide chunk t so that
 // lane l owns the 4 consecutive units h = 64 t + 4 (l % 16) + q of its column or row
-// index: its d loads and stores are 32 contiguous bytes.
+// index: its d loads and stores are 32 contiguous bytes (chunks of 16 QT units with
+// QT units per lane where the operands of 64 units would not fit the registers).
 #include "internal.h"
 
 namespace irl {
@@ -33,67 +34,68 @@ __device__ __forceinline__ uint64_t occ_bits(uint64_t key, int n)
     return (key & 0xffffffffull) | ((key >> 32) << n);
 }
 
-// d[row][h0 .. h0 + 3] (zero past H); H4: H % 4 == 0, so the 32 bytes are aligned
-template <bool H4>
-__device__ __forceinline__ void load_d4(const double *__restrict__ dfac, int64_t row, int H, int h0, double (&d)[4])
+// d[row][h0 .. h0 + QT) (zero past H); VEC: H % QT == 0, so the 8 QT bytes are aligned
+template <int QT, bool VEC>
+__device__ __forceinline__ void load_dq(const double *__restrict__ dfac, int64_t row, int H, int h0, double (&d)[QT])
 {
     const double *p = dfac + row * H + h0;
-    if (H4 && h0 < H) {
-        const d2v lo = *(const d2v *)p, hi = *(const d2v *)(p + 2);
-        d[0] = lo.x;
-        d[1] = lo.y;
-        d[2] = hi.x;
-        d[3] = hi.y;
+    if (QT >= 2 && VEC && h0 < H) {
+#pragma unroll
+        for (int q = 0; q + 1 < QT; q += 2) {
+            const d2v t = *(const d2v *)(p + q);
+            d[q] = t.x;
+            d[q + 1] = t.y;
+        }
     } else {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) d[q] = h0 + q < H ? p[q] : 0.0;
+        for (int q = 0; q < QT; ++q) d[q] = h0 + q < H ? p[q] : 0.0;
     }
 }
 
-template <bool H4>
-__device__ __forceinline__ void store_d4(double *__restrict__ dfac, int64_t row, int H, int h0, const double (&d)[4])
+template <int QT, bool VEC>
+__device__ __forceinline__ void store_dq(double *__restrict__ dfac, int64_t row, int H, int h0, const double (&d)[QT])
 {
     double *p = dfac + row * H + h0;
-    if (H4 && h0 < H) {
-        *(d2v *)p = d2v{d[0], d[1]};
-        *(d2v *)(p + 2) = d2v{d[2], d[3]};
+    if (QT >= 2 && VEC && h0 < H) {
+#pragma unroll
+        for (int q = 0; q + 1 < QT; q += 2) *(d2v *)(p + q) = d2v{d[q], d[q + 1]};
     } else {
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
+        for (int q = 0; q < QT; ++q)
             if (h0 + q < H) p[q] = d[q];
     }
 }
 
-// B operand of Z = X M^T for hidden chunk t (M: H x V, row-major): for k-step kk
-// and column tile q the lane holds M[h][v] at v = 4 kk + l / 16, h = 64 t + 4 (l % 16) + q
-// (zero outside v < V, h < H).
-template <int KS>
+// B operand of Z = X M^T for hidden chunk t of 16 QT units (M: H x V, row-major):
+// for k-step kk and column tile q the lane holds M[h][v] at v = 4 kk + l / 16,
+// h = 16 QT t + QT (l % 16) + q (zero outside v < V, h < H).
+template <int KS, int QT>
 __device__ __forceinline__ void load_bt(const double *__restrict__ M, int V, int H, int t, int lane,
-                                        double (&B)[KS][4])
+                                        double (&B)[KS][QT])
 {
-    const int vs = lane >> 4, h0 = 64 * t + 4 * (lane & 15);
+    const int vs = lane >> 4, h0 = 16 * QT * t + QT * (lane & 15);
 #pragma unroll
     for (int kk = 0; kk < KS; ++kk)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < QT; ++q) {
             const int v = 4 * kk + vs, h = h0 + q;
             B[kk][q] = (v < V && h < H) ? M[(size_t)h * V + v] : 0.0;
         }
 }
 
 // Z for the 16 rows of a tile (the lane's A row is l % 16, occupation bits xa)
-// and the 64 hidden units of the chunk: acc[q][r] = Z[4 r + l / 16][64 t + 4 (l % 16) + q]
-template <int KS>
-__device__ __forceinline__ void z_tile(uint64_t xa, int lane, const double (&B)[KS][4], d4v (&acc)[4])
+// and the 16 QT hidden units of the chunk: acc[q][r] = Z[4 r + l / 16][16 QT t + QT (l % 16) + q]
+template <int KS, int QT>
+__device__ __forceinline__ void z_tile(uint64_t xa, int lane, const double (&B)[KS][QT], d4v (&acc)[QT])
 {
     const int vs = lane >> 4;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) acc[q] = d4v{0.0, 0.0, 0.0, 0.0};
+    for (int q = 0; q < QT; ++q) acc[q] = d4v{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int kk = 0; kk < KS; ++kk) {
         const double a = (double)(uint32_t)((xa >> (4 * kk + vs)) & 1ull);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) acc[q] = mfma_f64(a, B[kk][q], acc[q]);
+        for (int q = 0; q < QT; ++q) acc[q] = mfma_f64(a, B[kk][q], acc[q]);
     }
 }
 
@@ -129,8 +131,9 @@ __device__ __forceinline__ double rows_to_lanes(double (&p)[4], int lane)
 }
 
 // ---------------------------------------------------------------------------
-// forward pass: psi (N_s) and d (N_s x H) from theta = [a, b, W]
-template <int KS, bool H4>
+// forward pass: psi (N_s) and d (N_s x H) from theta = [a, b, W]; hidden chunks of
+// 16 QT units
+template <int KS, int QT, bool VEC>
 __global__ __launch_bounds__(256) void k_fac_forward(const uint64_t *__restrict__ keys, int64_t ns, int n,
                                                      int V, int H, const double *__restrict__ theta,
                                                      double *__restrict__ psi, double *__restrict__ dfac)
@@ -144,31 +147,31 @@ __global__ __launch_bounds__(256) void k_fac_forward(const uint64_t *__restrict_
         const int v = 4 * kk + (lane >> 4);
         ak[kk] = v < V ? a[v] : 0.0;
     }
-    const int htiles = (H + 63) / 64;
+    const int htiles = (H + 16 * QT - 1) / (16 * QT);
     for (int t = 0; t < htiles; ++t) {
-        double B[KS][4], bh[4];
-        load_bt<KS>(W, V, H, t, lane, B);
-        const int h0 = 64 * t + 4 * (lane & 15);
+        double B[KS][QT], bh[QT];
+        load_bt<KS, QT>(W, V, H, t, lane, B);
+        const int h0 = 16 * QT * t + QT * (lane & 15);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) bh[q] = h0 + q < H ? b[h0 + q] : 0.0;
+        for (int q = 0; q < QT; ++q) bh[q] = h0 + q < H ? b[h0 + q] : 0.0;
         for (int64_t tile = (int64_t)blockIdx.x * 4 + wv; tile < ntile; tile += nw) {
             const int64_t r0 = tile * 16, ra = r0 + (lane & 15);
             const uint64_t xa = ra < ns ? occ_bits(keys[ra], n) : 0ull;
-            d4v acc[4];
-            z_tile<KS>(xa, lane, B, acc);
+            d4v acc[QT];
+            z_tile<KS, QT>(xa, lane, B, acc);
             double ts[4];
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int64_t row = r0 + 4 * r + (lane >> 4);
-                double d[4], s = 0.0;
+                double d[QT], sum = 0.0;
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
+                for (int q = 0; q < QT; ++q) {
                     const double th = tanh(acc[q][r] + bh[q]);
-                    s += h0 + q < H ? th : 0.0;
+                    sum += h0 + q < H ? th : 0.0;
                     d[q] = 1.0 - th * th;
                 }
-                if (row < ns) store_d4<H4>(dfac, row, H, h0, d);
-                ts[r] = s;
+                if (row < ns) store_dq<QT, VEC>(dfac, row, H, h0, d);
+                ts[r] = sum;
             }
             double pj = rows_to_lanes(ts, lane);
             if (t == 0) pj += x_dot<KS>(xa, lane, ak);
@@ -178,8 +181,10 @@ __global__ __launch_bounds__(256) void k_fac_forward(const uint64_t *__restrict_
 }
 
 // ---------------------------------------------------------------------------
-// w = D~ v with v = [v_0, v_a, v_b, V_W] (v_0 taken as 0 when zero_v0)
-template <int KS, bool H4>
+// w = D~ v with v = [v_0, v_a, v_b, V_W] (v_0 taken as 0 when zero_v0); hidden
+// chunks of 16 QT units, the d rows and key of the next tile loaded while the
+// current one is multiplied
+template <int KS, int QT, bool VEC>
 __global__ __launch_bounds__(256) void k_fac_jvp(const uint64_t *__restrict__ keys, int64_t ns, int n, int V,
                                                  int H, const double *__restrict__ dfac,
                                                  const double *__restrict__ psi, const double *__restrict__ v,
@@ -195,37 +200,43 @@ __global__ __launch_bounds__(256) void k_fac_jvp(const uint64_t *__restrict__ ke
         const int vv = 4 * kk + (lane >> 4);
         ak[kk] = vv < V ? va[vv] : 0.0;
     }
-    const int htiles = (H + 63) / 64;
+    const int htiles = (H + 16 * QT - 1) / (16 * QT);
     for (int t = 0; t < htiles; ++t) {
-        double B[KS][4], bh[4];
-        load_bt<KS>(vW, V, H, t, lane, B);
-        const int h0 = 64 * t + 4 * (lane & 15);
+        double B[KS][QT], bh[QT];
+        load_bt<KS, QT>(vW, V, H, t, lane, B);
+        const int h0 = 16 * QT * t + QT * (lane & 15);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) bh[q] = h0 + q < H ? vb[h0 + q] : 0.0;
-        for (int64_t tile = (int64_t)blockIdx.x * 4 + wv; tile < ntile; tile += nw) {
+        for (int q = 0; q < QT; ++q) bh[q] = h0 + q < H ? vb[h0 + q] : 0.0;
+        auto fetch = [&](int64_t tile, double (&d)[4][QT], uint64_t &xa) {
             const int64_t r0 = tile * 16, ra = r0 + (lane & 15);
-            // d of the lane's 4 output rows, issued ahead of the matrix products
-            double d[4][4];
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int64_t row = r0 + 4 * r + (lane >> 4);
                 if (row < ns) {
-                    load_d4<H4>(dfac, row, H, h0, d[r]);
+                    load_dq<QT, VEC>(dfac, row, H, h0, d[r]);
                 } else {
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) d[r][q] = 0.0;
+                    for (int q = 0; q < QT; ++q) d[r][q] = 0.0;
                 }
             }
-            const uint64_t xa = ra < ns ? occ_bits(keys[ra], n) : 0ull;
-            d4v acc[4];
-            z_tile<KS>(xa, lane, B, acc);
+            xa = ra < ns ? occ_bits(keys[ra], n) : 0ull;
+        };
+        double d[4][QT], dn[4][QT];
+        uint64_t xa = 0ull, xn = 0ull;
+        int64_t tile = (int64_t)blockIdx.x * 4 + wv;
+        if (tile < ntile) fetch(tile, d, xa);
+        for (; tile < ntile; tile += nw) {
+            const int64_t r0 = tile * 16, ra = r0 + (lane & 15);
+            if (tile + nw < ntile) fetch(tile + nw, dn, xn);
+            d4v acc[QT];
+            z_tile<KS, QT>(xa, lane, B, acc);
             double p[4];
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                double s = 0.0;
+                double sum = 0.0;
 #pragma unroll
-                for (int q = 0; q < 4; ++q) s += d[r][q] * (acc[q][r] + bh[q]);
-                p[r] = s;
+                for (int q = 0; q < QT; ++q) sum += d[r][q] * (acc[q][r] + bh[q]);
+                p[r] = sum;
             }
             double pj = rows_to_lanes(p, lane);
             if (t == 0) {
@@ -233,147 +244,216 @@ __global__ __launch_bounds__(256) void k_fac_jvp(const uint64_t *__restrict__ ke
                 if (lane < 16 && ra < ns) pj += psi[ra] * v0;
             }
             if (lane < 16 && ra < ns) w[ra] = (t == 0 ? 0.0 : w[ra]) + pj;
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int q = 0; q < QT; ++q) d[r][q] = dn[r][q];
+            xa = xn;
         }
     }
 }
 
 // ---------------------------------------------------------------------------
-// partial rows of D~^T c, c_r = y_r - coef psi_r, into half `half` of each row
-// block's pair of rows.  Grid (hidden chunks of 64, row blocks); each wave takes
-// groups of 4 rows (the K of the matrix product).  A[h][k] = c_k d_kh, B[k][v] = x_kv;
+// partial rows of D~^T c for NR right-hand sides c_r = y_r - coef psi_r (coef = 0
+// without coefp): NR = 1 writes half `half` of each row block's pair of partial
+// rows, NR = 2 writes c = y0 into half 0 and c = y1 into half 1 from one pass over
+// d.  Grid (hidden chunks of CW = 16 MT units, row blocks); each wave takes
+// groups of 4 rows (the K of the matrix product), loading the next group while
+// the current one is multiplied.  A[h][k] = c_k d_kh (MT column tiles of 16 hidden
+// units, lane l owning units MT (l % 16) + m of the chunk), B[k][v] = x_kv;
 // the b entries (sum c d), the a entries (sum c x) and the psi entry (sum c psi)
 // are lane-local sums beside the product.  The 4 waves are combined in a fixed
-// order and wave 0 writes the entries of the partial row that belong to its
+// order and wave 0 writes the entries of the partial rows that belong to its
 // chunk (chunk 0 also the psi, a and padding entries).
-template <int NT, bool H4>
+template <int NT, int NR, int MT, bool VEC>
 __global__ __launch_bounds__(256) void k_fac_vjp(const uint64_t *__restrict__ keys, int64_t ns, int n, int V,
                                                  int H, const double *__restrict__ dfac,
-                                                 const double *__restrict__ psi, const double *__restrict__ y,
-                                                 const double *__restrict__ coefp, double *__restrict__ part,
-                                                 int64_t ldv, int nblk, int half)
+                                                 const double *__restrict__ psi, const double *__restrict__ y0,
+                                                 const double *__restrict__ y1, const double *__restrict__ coefp,
+                                                 double *__restrict__ part, int64_t ldv, int nblk, int half)
 {
-    constexpr int kAcc = 16 * NT + 4 + NT + 1;   // doubles per lane in the wave combination
+    constexpr int CW = 16 * MT;
+    static_assert(NR * MT * NT <= 8, "accumulator tiles per lane");
+    constexpr int kAcc = 4 * NR * MT * NT + NR * (MT + NT + 1);   // doubles per lane in the wave combination
     __shared__ double red[64 * kAcc];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int ht = blockIdx.x, rb = blockIdx.y;
     const int64_t per = (ns + nblk - 1) / nblk;
     const int64_t r0 = (int64_t)rb * per, r1 = min(ns, r0 + per);
     const double coef = coefp ? *coefp : 0.0;
-    const int kq = lane >> 4, i = lane & 15, h0 = 64 * ht + 4 * i;
-    d4v acc[4][NT];
+    const int kq = lane >> 4, i = lane & 15, h0 = CW * ht + MT * i;
+    const double *ys[2] = {y0, y1};
+    d4v acc[NR][MT][NT];
+    double accB[NR][MT], accA[NR][NT], acc0[NR];
 #pragma unroll
-    for (int m = 0; m < 4; ++m)
+    for (int r = 0; r < NR; ++r) {
+        acc0[r] = 0.0;
 #pragma unroll
-        for (int nn = 0; nn < NT; ++nn) acc[m][nn] = d4v{0.0, 0.0, 0.0, 0.0};
-    double accB[4] = {0.0, 0.0, 0.0, 0.0}, accA[NT], acc0 = 0.0;
+        for (int m = 0; m < MT; ++m) {
+            accB[r][m] = 0.0;
 #pragma unroll
-    for (int nn = 0; nn < NT; ++nn) accA[nn] = 0.0;
-
-    for (int64_t g = r0 + 4 * wv; g < r1; g += 16) {
+            for (int nn = 0; nn < NT; ++nn) acc[r][m][nn] = d4v{0.0, 0.0, 0.0, 0.0};
+        }
+#pragma unroll
+        for (int nn = 0; nn < NT; ++nn) accA[r][nn] = 0.0;
+    }
+    // one 4-row group: the lane's row is g + kq
+    struct Grp {
+        double d[MT], ps, y[NR];
+        uint64_t x;
+    };
+    auto fetch = [&](int64_t g, Grp &q) {
         const int64_t row = g + kq;
-        double c = 0.0, ps = 0.0, d[4] = {0.0, 0.0, 0.0, 0.0};
-        uint64_t x = 0ull;
+        q.ps = 0.0;
+        q.x = 0ull;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) q.y[r] = 0.0;
+#pragma unroll
+        for (int m = 0; m < MT; ++m) q.d[m] = 0.0;
         if (row < r1) {
-            load_d4<H4>(dfac, row, H, h0, d);
-            ps = psi[row];
-            c = y[row] - coef * ps;
-            x = occ_bits(keys[row], n);
+            load_dq<MT, VEC>(dfac, row, H, h0, q.d);
+            q.ps = psi[row];
+#pragma unroll
+            for (int r = 0; r < NR; ++r) q.y[r] = ys[r][row];
+            q.x = occ_bits(keys[row], n);
         }
-        double A[4], Bv[NT];
+    };
+    auto consume = [&](const Grp &cur) {
+        double Bv[NT];
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            A[m] = c * d[m];
-            accB[m] += A[m];
+        for (int nn = 0; nn < NT; ++nn) Bv[nn] = (double)(uint32_t)((cur.x >> (16 * nn + i)) & 1ull);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            const double c = cur.y[r] - coef * cur.ps;
+#pragma unroll
+            for (int m = 0; m < MT; ++m) {
+                const double A = c * cur.d[m];
+                accB[r][m] += A;
+#pragma unroll
+                for (int nn = 0; nn < NT; ++nn) acc[r][m][nn] = mfma_f64(A, Bv[nn], acc[r][m][nn]);
+            }
+            if (ht == 0) {
+#pragma unroll
+                for (int nn = 0; nn < NT; ++nn) accA[r][nn] += c * Bv[nn];
+                acc0[r] += c * cur.ps;
+            }
         }
+    };
+    // ring of PD groups in flight per wave: a group is consumed, then its slot is
+    // refilled with the group PD steps ahead (rows past r1 load as zeros)
+    constexpr int PD = 4;
+    Grp ring[PD];
+    const int64_t g0 = r0 + 4 * wv;
 #pragma unroll
-        for (int nn = 0; nn < NT; ++nn) Bv[nn] = (double)(uint32_t)((x >> (16 * nn + i)) & 1ull);
+    for (int p = 0; p < PD; ++p) fetch(g0 + 16 * p, ring[p]);
+    for (int64_t g = g0; g < r1; g += 16 * PD) {
 #pragma unroll
-        for (int m = 0; m < 4; ++m)
-#pragma unroll
-            for (int nn = 0; nn < NT; ++nn) acc[m][nn] = mfma_f64(A[m], Bv[nn], acc[m][nn]);
-        if (ht == 0) {
-#pragma unroll
-            for (int nn = 0; nn < NT; ++nn) accA[nn] += c * Bv[nn];
-            acc0 += c * ps;
+        for (int p = 0; p < PD; ++p) {
+            if (g + 16 * p < r1) consume(ring[p]);
+            fetch(g + 16 * (p + PD), ring[p]);
         }
     }
     // sums over the 4 rows of a group (the lane quarters)
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
-        accB[m] += __shfl_xor(accB[m], 16, kWave);
-        accB[m] += __shfl_xor(accB[m], 32, kWave);
-    }
+    for (int r = 0; r < NR; ++r) {
 #pragma unroll
-    for (int nn = 0; nn < NT; ++nn) {
-        accA[nn] += __shfl_xor(accA[nn], 16, kWave);
-        accA[nn] += __shfl_xor(accA[nn], 32, kWave);
+        for (int m = 0; m < MT; ++m) {
+            accB[r][m] += __shfl_xor(accB[r][m], 16, kWave);
+            accB[r][m] += __shfl_xor(accB[r][m], 32, kWave);
+        }
+#pragma unroll
+        for (int nn = 0; nn < NT; ++nn) {
+            accA[r][nn] += __shfl_xor(accA[r][nn], 16, kWave);
+            accA[r][nn] += __shfl_xor(accA[r][nn], 32, kWave);
+        }
+        acc0[r] += __shfl_xor(acc0[r], 16, kWave);
+        acc0[r] += __shfl_xor(acc0[r], 32, kWave);
     }
-    acc0 += __shfl_xor(acc0, 16, kWave);
-    acc0 += __shfl_xor(acc0, 32, kWave);
 
     // fixed-order combination of the 4 waves: ((w0 + w1) + w2) + w3
+    auto slot = [&](int k) -> double & { return red[64 * k + lane]; };
     for (int src = 1; src < 4; ++src) {
         __syncthreads();
-        if (wv == src) {
-            double *o = red + lane;
+        if (wv == src || wv == 0) {
+            const bool put = wv == src;
+            int k = 0;
 #pragma unroll
-            for (int m = 0; m < 4; ++m)
+            for (int r = 0; r < NR; ++r) {
 #pragma unroll
-                for (int nn = 0; nn < NT; ++nn)
+                for (int m = 0; m < MT; ++m)
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) o[64 * ((m * NT + nn) * 4 + r)] = acc[m][nn][r];
+                    for (int nn = 0; nn < NT; ++nn)
 #pragma unroll
-            for (int m = 0; m < 4; ++m) o[64 * (16 * NT + m)] = accB[m];
+                        for (int q = 0; q < 4; ++q, ++k) {
+                            if (put) slot(k) = acc[r][m][nn][q];
+                        }
+            }
 #pragma unroll
-            for (int nn = 0; nn < NT; ++nn) o[64 * (16 * NT + 4 + nn)] = accA[nn];
-            o[64 * (kAcc - 1)] = acc0;
+            for (int r = 0; r < NR; ++r) {
+#pragma unroll
+                for (int m = 0; m < MT; ++m, ++k)
+                    if (put) slot(k) = accB[r][m];
+#pragma unroll
+                for (int nn = 0; nn < NT; ++nn, ++k)
+                    if (put) slot(k) = accA[r][nn];
+                if (put) slot(k) = acc0[r];
+                ++k;
+            }
         }
         __syncthreads();
         if (wv == 0) {
-            const double *o = red + lane;
+            int k = 0;
 #pragma unroll
-            for (int m = 0; m < 4; ++m)
+            for (int r = 0; r < NR; ++r)
 #pragma unroll
-                for (int nn = 0; nn < NT; ++nn)
+                for (int m = 0; m < MT; ++m)
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) acc[m][nn][r] += o[64 * ((m * NT + nn) * 4 + r)];
+                    for (int nn = 0; nn < NT; ++nn)
 #pragma unroll
-            for (int m = 0; m < 4; ++m) accB[m] += o[64 * (16 * NT + m)];
+                        for (int q = 0; q < 4; ++q, ++k) acc[r][m][nn][q] += slot(k);
 #pragma unroll
-            for (int nn = 0; nn < NT; ++nn) accA[nn] += o[64 * (16 * NT + 4 + nn)];
-            acc0 += o[64 * (kAcc - 1)];
+            for (int r = 0; r < NR; ++r) {
+#pragma unroll
+                for (int m = 0; m < MT; ++m, ++k) accB[r][m] += slot(k);
+#pragma unroll
+                for (int nn = 0; nn < NT; ++nn, ++k) accA[r][nn] += slot(k);
+                acc0[r] += slot(k);
+                ++k;
+            }
         }
     }
     if (wv != 0) return;
-    double *out = part + ((int64_t)rb * 2 + half) * ldv;
-    const int64_t baseW = 1 + V + H;
-    // acc[m][nn][r] = sum c d_h x_v at h = 64 ht + 4 (4 r + l / 16) + m, v = 16 nn + l % 16
+    const int64_t baseW = 1 + V + H, P1 = (int64_t)V * H + H + V + 1;
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
+    for (int r = 0; r < NR; ++r) {
+        double *out = part + ((int64_t)rb * 2 + (NR == 2 ? r : half)) * ldv;
+        // acc[r][m][nn][q] = sum c d_h x_v at h = CW ht + MT (4 q + l / 16) + m, v = 16 nn + l % 16
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            const int h = 64 * ht + 16 * r + 4 * kq + m;
-            if (h < H)
+        for (int q = 0; q < 4; ++q)
 #pragma unroll
-                for (int nn = 0; nn < NT; ++nn) {
-                    const int vv = 16 * nn + i;
-                    if (vv < V) out[baseW + (int64_t)h * V + vv] = acc[m][nn][r];
-                }
+            for (int m = 0; m < MT; ++m) {
+                const int h = CW * ht + MT * (4 * q + kq) + m;
+                if (h < H)
+#pragma unroll
+                    for (int nn = 0; nn < NT; ++nn) {
+                        const int vv = 16 * nn + i;
+                        if (vv < V) out[baseW + (int64_t)h * V + vv] = acc[r][m][nn][q];
+                    }
+            }
+        if (lane < 16) {
+#pragma unroll
+            for (int m = 0; m < MT; ++m)
+                if (h0 + m < H) out[1 + V + h0 + m] = accB[r][m];
+            if (ht == 0) {
+#pragma unroll
+                for (int nn = 0; nn < NT; ++nn)
+                    if (16 * nn + lane < V) out[1 + 16 * nn + lane] = accA[r][nn];
+            }
         }
-    if (lane < 16) {
-#pragma unroll
-        for (int m = 0; m < 4; ++m)
-            if (h0 + m < H) out[1 + V + h0 + m] = accB[m];
         if (ht == 0) {
-#pragma unroll
-            for (int nn = 0; nn < NT; ++nn)
-                if (16 * nn + lane < V) out[1 + 16 * nn + lane] = accA[nn];
+            if (lane == 0) out[0] = acc0[r];
+            for (int64_t col = P1 + lane; col < ldv; col += 64) out[col] = 0.0;
         }
-    }
-    if (ht == 0) {
-        if (lane == 0) out[0] = acc0;
-        const int64_t P1 = (int64_t)V * H + H + V + 1;
-        for (int64_t col = P1 + lane; col < ldv; col += 64) out[col] = 0.0;
     }
 }
 
@@ -390,39 +470,45 @@ int fac_tile_blocks(int64_t ns)
     return (int)(blocks < 1 ? 1 : blocks);
 }
 
+// QT (hidden column tiles per wave): 4 while the B operand is small, else 2
 template <int KS>
 void forward_ks(const irl_system *s, const WsLayout &L, int V, int H, const double *theta, double *psi,
                 double *dfac, hipStream_t st)
 {
+    constexpr int QT = KS <= 6 ? 4 : 2;
     const int blocks = fac_tile_blocks(L.ns);
-    if (H % 4 == 0)
-        k_fac_forward<KS, true><<<blocks, 256, 0, st>>>(s->d.keys, L.ns, s->n, V, H, theta, psi, dfac);
+    if (H % QT == 0)
+        k_fac_forward<KS, QT, true><<<blocks, 256, 0, st>>>(s->d.keys, L.ns, s->n, V, H, theta, psi, dfac);
     else
-        k_fac_forward<KS, false><<<blocks, 256, 0, st>>>(s->d.keys, L.ns, s->n, V, H, theta, psi, dfac);
+        k_fac_forward<KS, QT, false><<<blocks, 256, 0, st>>>(s->d.keys, L.ns, s->n, V, H, theta, psi, dfac);
 }
 
 template <int KS>
 void jvp_ks(const irl_system *s, const WsLayout &L, int V, int H, const double *dfac, const double *psi,
             const double *v, int zero_v0, double *w, hipStream_t st)
 {
+    constexpr int QT = KS <= 6 ? 4 : 2;
     const int blocks = fac_tile_blocks(L.ns);
-    if (H % 4 == 0)
-        k_fac_jvp<KS, true><<<blocks, 256, 0, st>>>(s->d.keys, L.ns, s->n, V, H, dfac, psi, v, zero_v0, w);
+    if (H % QT == 0)
+        k_fac_jvp<KS, QT, true><<<blocks, 256, 0, st>>>(s->d.keys, L.ns, s->n, V, H, dfac, psi, v, zero_v0, w);
     else
-        k_fac_jvp<KS, false><<<blocks, 256, 0, st>>>(s->d.keys, L.ns, s->n, V, H, dfac, psi, v, zero_v0, w);
+        k_fac_jvp<KS, QT, false><<<blocks, 256, 0, st>>>(s->d.keys, L.ns, s->n, V, H, dfac, psi, v, zero_v0, w);
 }
 
-template <int NT>
+// MT (hidden column tiles per wave) keeps NR MT NT <= 8 accumulator tiles per lane
+template <int NT, int NR>
 void vjp_nt(const irl_system *s, const WsLayout &L, int V, int H, const double *dfac, const double *psi,
-            const double *y, const double *coefp, double *part, int nblk, int half, hipStream_t st)
+            const double *y0, const double *y1, const double *coefp, double *part, int nblk, int half,
+            hipStream_t st)
 {
-    const dim3 grid((H + 63) / 64, nblk);
-    if (H % 4 == 0)
-        k_fac_vjp<NT, true><<<grid, 256, 0, st>>>(s->d.keys, L.ns, s->n, V, H, dfac, psi, y, coefp, part,
-                                                  L.ldv, nblk, half);
+    constexpr int MT = (8 / (NR * NT)) >= 4 ? 4 : (8 / (NR * NT)) >= 2 ? 2 : 1;
+    const dim3 grid((H + 16 * MT - 1) / (16 * MT), nblk);
+    if (H % MT == 0)
+        k_fac_vjp<NT, NR, MT, true><<<grid, 256, 0, st>>>(s->d.keys, L.ns, s->n, V, H, dfac, psi, y0, y1,
+                                                          coefp, part, L.ldv, nblk, half);
     else
-        k_fac_vjp<NT, false><<<grid, 256, 0, st>>>(s->d.keys, L.ns, s->n, V, H, dfac, psi, y, coefp, part,
-                                                   L.ldv, nblk, half);
+        k_fac_vjp<NT, NR, MT, false><<<grid, 256, 0, st>>>(s->d.keys, L.ns, s->n, V, H, dfac, psi, y0, y1,
+                                                           coefp, part, L.ldv, nblk, half);
 }
 
 bool fac_shape_ok(const irl_system *s, const WsLayout &L)
@@ -481,18 +567,28 @@ int fac_row_blocks(const WsLayout &L)
     return nblk < 1 ? 1 : nblk;
 }
 
-hipError_t launch_fac_vjp(const irl_system *s, const WsLayout &L, void *ws, const double *y,
+hipError_t launch_fac_vjp(const irl_system *s, const WsLayout &L, void *ws, const double *y0, const double *y1,
                           const double *coefp, int half, int nblk, hipStream_t st)
 {
-    if (!fac_shape_ok(s, L) || nblk < 1 || nblk > kStreamBlocks) return hipErrorInvalidValue;
+    if (!fac_shape_ok(s, L) || nblk < 1 || nblk > kStreamBlocks || !y0) return hipErrorInvalidValue;
     const int V = 2 * s->n, H = L.hfac;
     const double *psi = ws_ptr<double>(ws, L.off_psi), *dfac = ws_ptr<double>(ws, L.off_fac);
     double *part = ws_ptr<double>(ws, L.off_part);
-    switch ((V + 15) / 16) {
-    case 1: vjp_nt<1>(s, L, V, H, dfac, psi, y, coefp, part, nblk, half, st); break;
-    case 2: vjp_nt<2>(s, L, V, H, dfac, psi, y, coefp, part, nblk, half, st); break;
-    case 3: vjp_nt<3>(s, L, V, H, dfac, psi, y, coefp, part, nblk, half, st); break;
-    default: vjp_nt<4>(s, L, V, H, dfac, psi, y, coefp, part, nblk, half, st); break;
+    const int nt = (V + 15) / 16;
+    if (y1) {
+        switch (nt) {
+        case 1: vjp_nt<1, 2>(s, L, V, H, dfac, psi, y0, y1, coefp, part, nblk, 0, st); break;
+        case 2: vjp_nt<2, 2>(s, L, V, H, dfac, psi, y0, y1, coefp, part, nblk, 0, st); break;
+        case 3: vjp_nt<3, 2>(s, L, V, H, dfac, psi, y0, y1, coefp, part, nblk, 0, st); break;
+        default: vjp_nt<4, 2>(s, L, V, H, dfac, psi, y0, y1, coefp, part, nblk, 0, st); break;
+        }
+    } else {
+        switch (nt) {
+        case 1: vjp_nt<1, 1>(s, L, V, H, dfac, psi, y0, nullptr, coefp, part, nblk, half, st); break;
+        case 2: vjp_nt<2, 1>(s, L, V, H, dfac, psi, y0, nullptr, coefp, part, nblk, half, st); break;
+        case 3: vjp_nt<3, 1>(s, L, V, H, dfac, psi, y0, nullptr, coefp, part, nblk, half, st); break;
+        default: vjp_nt<4, 1>(s, L, V, H, dfac, psi, y0, nullptr, coefp, part, nblk, half, st); break;
+        }
     }
     return hipGetLastError();
 }

@@ -20,6 +20,8 @@
 // reproducible.
 #include "internal.h"
 
+#include <rocblas/rocblas.h>
+
 namespace irl {
 
 typedef HamView HamArgs;
@@ -370,14 +372,18 @@ __global__ __launch_bounds__(256) void k_ham_pull(HamArgs A, const double *__res
 }
 
 // Stored rows: u[row] = diag * w[row] + sum_p val[p] w[col[p]], one wave per row.
-// The elements are streamed once per apply (non-temporal); each lane keeps four
-// gathers of w in flight.  Lane partial sums are combined by a fixed butterfly,
-// so the result does not depend on scheduling.
-__device__ __forceinline__ void stored_row(const HamArgs &A, int64_t row, int lane,
-                                           const double *__restrict__ w, double *__restrict__ u)
+// The elements of a row are split into column blocks (targets [b 2^hcs, (b + 1)
+// 2^hcs), a slice of w that stays in L2) and each block is its own launch, so the
+// random gathers of every XCD hit one resident slice; u accumulates over the
+// blocks in block order.  The elements are streamed once per apply (non-temporal);
+// each lane keeps four gathers of w in flight.  Lane partial sums are combined by
+// a fixed butterfly, so the result does not depend on scheduling.
+__device__ __forceinline__ double stored_block_sum(const HamArgs &A, int b, int64_t row, int lane,
+                                                   const double *__restrict__ w)
 {
-    const int64_t p1 = A.hptr[row + 1];
-    int64_t p = A.hptr[row] + lane;
+    const int64_t *ptr = A.hptr + (int64_t)b * (A.ns + 1);
+    const int64_t p1 = ptr[row + 1];
+    int64_t p = ptr[row] + lane;
     double acc = 0.0;
     for (; p + 3 * kWave < p1; p += 4 * kWave) {
         int32_t c[4];
@@ -392,20 +398,38 @@ __device__ __forceinline__ void stored_row(const HamArgs &A, int64_t row, int la
     }
     for (; p < p1; p += kWave)
         acc += __builtin_nontemporal_load(A.hval + p) * w[__builtin_nontemporal_load(A.hcol + p)];
-    acc = wave_sum(acc);
-    if (lane == 0) u[row] = A.diag[row] * w[row] + acc;
+    return wave_sum(acc);
+}
+
+// u[row] after column block b: fma(diag, w, S_0) for b = 0, then + S_b
+__device__ __forceinline__ double stored_accumulate(const HamArgs &A, int b, int64_t row, double prev,
+                                                    double acc, const double *__restrict__ w)
+{
+    return b == 0 ? fma(A.diag[row], w[row], acc) : prev + acc;
+}
+
+// all column blocks of one row in block order (the grouped launch)
+__device__ __forceinline__ void stored_row(const HamArgs &A, int64_t row, int lane, const double *__restrict__ w,
+                                           double *__restrict__ u)
+{
+    double t = 0.0;
+    for (int b = 0; b < A.hcb; ++b) t = stored_accumulate(A, b, row, t, stored_block_sum(A, b, row, lane, w), w);
+    if (lane == 0) u[row] = t;
 }
 
 __global__ __launch_bounds__(256) void k_ham_stored(HamArgs A, const double *__restrict__ w,
-                                                    double *__restrict__ u, int64_t r0, int64_t r1)
+                                                    double *__restrict__ u, int64_t r0, int64_t r1, int b)
 {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t nwaves = (int64_t)gridDim.x * 4;
-    for (int64_t row = r0 + (int64_t)blockIdx.x * 4 + wv; row < r1; row += nwaves)
-        stored_row(A, row, lane, w, u);
+    for (int64_t row = r0 + (int64_t)blockIdx.x * 4 + wv; row < r1; row += nwaves) {
+        const double acc = stored_block_sum(A, b, row, lane, w);
+        if (lane == 0) u[row] = stored_accumulate(A, b, row, b == 0 ? 0.0 : u[row], acc, w);
+    }
 }
 
-// Stored rows, first pass: number of connections of each row inside the set.
+// Stored rows, first pass: number of connections of each row inside the set, per
+// column block (count[b ns + row]).
 template <int LK>
 __global__ __launch_bounds__(256) void k_ham_count(HamArgs A, int32_t *__restrict__ count)
 {
@@ -416,18 +440,27 @@ __global__ __launch_bounds__(256) void k_ham_count(HamArgs A, int32_t *__restric
         uint64_t key = A.keys[row];
         uint32_t al = (uint32_t)key, be = (uint32_t)(key >> 32);
         prepare_row<LK>(A, lists[wv], al, be, lane);
-        int c = 0;
-        visit_row<LK>(A, lists[wv], al, be, lane, kWave, [&](int64_t, int, int, double) { ++c; });
-        for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, kWave);
-        if (lane == 0) count[row] = c;
+        int c[kMaxColBlocks];
+#pragma unroll
+        for (int bb = 0; bb < kMaxColBlocks; ++bb) c[bb] = 0;
+        visit_row<LK>(A, lists[wv], al, be, lane, kWave, [&](int64_t r, int, int, double) {
+            const int b = (int)(r >> A.hcs);
+#pragma unroll
+            for (int bb = 0; bb < kMaxColBlocks; ++bb) c[bb] += b == bb;
+        });
+#pragma unroll
+        for (int bb = 0; bb < kMaxColBlocks; ++bb) {
+            for (int off = 32; off > 0; off >>= 1) c[bb] += __shfl_xor(c[bb], off, kWave);
+            if (lane == 0 && bb < A.hcb) count[(int64_t)bb * A.ns + row] = c[bb];
+        }
         end_row();
     }
 }
 
-// Stored rows, second pass: each lane counts its own connections again, an
-// exclusive scan over the lanes gives its first slot, and a third enumeration
-// writes them.  The layout inside a row is therefore fixed (lane-major), and
-// writes never leave [ptr[row], ptr[row + 1]).
+// Stored rows, second pass: each lane counts its own connections per column block
+// again, an exclusive scan over the lanes gives its first slot in each block, and
+// a third enumeration writes them.  The layout inside a row's block is therefore
+// fixed (lane-major), and writes never leave [ptr_b[row], ptr_b[row + 1]).
 template <int LK>
 __global__ __launch_bounds__(256) void k_ham_fill(HamArgs A, const int64_t *__restrict__ ptr,
                                                   int32_t *__restrict__ col, double *__restrict__ val)
@@ -439,21 +472,38 @@ __global__ __launch_bounds__(256) void k_ham_fill(HamArgs A, const int64_t *__re
         uint64_t key = A.keys[row];
         uint32_t al = (uint32_t)key, be = (uint32_t)(key >> 32);
         prepare_row<LK>(A, lists[wv], al, be, lane);
-        int c = 0;
-        visit_row<LK>(A, lists[wv], al, be, lane, kWave, [&](int64_t, int, int, double) { ++c; });
-        int incl = c;
-        for (int off = 1; off < kWave; off <<= 1) {
-            int t = __shfl_up(incl, off, kWave);
-            if (lane >= off) incl += t;
-        }
-        int64_t pos = ptr[row] + (incl - c);
-        const int64_t end = ptr[row + 1];
-        visit_row<LK>(A, lists[wv], al, be, lane, kWave, [&](int64_t r, int, int, double v) {
-            if (pos < end) {
-                col[pos] = (int32_t)r;
-                val[pos] = v;
+        int c[kMaxColBlocks];
+#pragma unroll
+        for (int bb = 0; bb < kMaxColBlocks; ++bb) c[bb] = 0;
+        visit_row<LK>(A, lists[wv], al, be, lane, kWave, [&](int64_t r, int, int, double) {
+            const int b = (int)(r >> A.hcs);
+#pragma unroll
+            for (int bb = 0; bb < kMaxColBlocks; ++bb) c[bb] += b == bb;
+        });
+        int64_t pos[kMaxColBlocks], end[kMaxColBlocks];
+#pragma unroll
+        for (int bb = 0; bb < kMaxColBlocks; ++bb) {
+            int incl = c[bb];
+            for (int off = 1; off < kWave; off <<= 1) {
+                const int t = __shfl_up(incl, off, kWave);
+                if (lane >= off) incl += t;
             }
-            ++pos;
+            const int64_t *pb = ptr + (int64_t)(bb < A.hcb ? bb : 0) * (A.ns + 1);
+            pos[bb] = bb < A.hcb ? pb[row] + (incl - c[bb]) : 0;
+            end[bb] = bb < A.hcb ? pb[row + 1] : 0;
+        }
+        visit_row<LK>(A, lists[wv], al, be, lane, kWave, [&](int64_t r, int, int, double v) {
+            const int b = (int)(r >> A.hcs);
+#pragma unroll
+            for (int bb = 0; bb < kMaxColBlocks; ++bb) {
+                if (b == bb) {
+                    if (pos[bb] < end[bb]) {
+                        col[pos[bb]] = (int32_t)r;
+                        val[pos[bb]] = v;
+                    }
+                    ++pos[bb];
+                }
+            }
         });
         end_row();
     }
@@ -545,6 +595,8 @@ HamView ham_view(const irl_system *s)
     A.hptr = s->ham_kernel == 4 ? s->d.hptr : nullptr;
     A.hcol = s->ham_kernel == 4 ? s->d.hcol : nullptr;
     A.hval = s->ham_kernel == 4 ? s->d.hval : nullptr;
+    A.hcb = s->d.hcb;
+    A.hcs = s->d.hcs;
     A.rankA = s->d.rankA;
     A.rankB = s->d.rankB;
     return A;
@@ -568,9 +620,14 @@ hipError_t launch_ham_apply_rows(const irl_system *s, const double *w, double *u
     HamArgs A = ham_view(s);
     int64_t blocks = (r1 - r0 + 3) / 4;
     if (blocks > 65536) blocks = 65536;
-    if (s->ham_kernel == 4)
-        k_ham_stored<<<(unsigned)blocks, 256, 0, st>>>(A, w, u, r0, r1);
-    else if (s->lookup == kLkBlocks)
+    if (s->ham_kernel == 4) {
+        for (int b = 0; b < A.hcb; ++b) {
+            k_ham_stored<<<(unsigned)blocks, 256, 0, st>>>(A, w, u, r0, r1, b);
+            const hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    } else if (s->lookup == kLkBlocks)
         k_ham_pull<kLkBlocks><<<(unsigned)blocks, 256, 0, st>>>(A, w, u, r0, r1);
     else if (s->lookup == kLkHash)
         k_ham_pull<kLkHash><<<(unsigned)blocks, 256, 0, st>>>(A, w, u, r0, r1);
@@ -749,6 +806,7 @@ struct ProdArgs {
     int n, nsa, nsb, nda, ndb;
     int64_t nA, nB;
     int64_t rb0;              // first beta string of the launch (blockIdx.y + rb0)
+    int dense;                // same-spin doubles applied by dense products instead
     const double *diag, *g;
     StrTables A, B;
 };
@@ -799,8 +857,9 @@ __global__ __launch_bounds__(kProdThreads) void k_ham_product(ProdArgs P, const 
         }
     }
     // alpha-alpha doubles
-    for (int d = 0; d < P.nda; ++d)
-        acc += P.A.dval[(int64_t)d * P.nA + rac] * wrow[P.A.drank[(int64_t)d * P.nA + rac]];
+    if (!P.dense)
+        for (int d = 0; d < P.nda; ++d)
+            acc += P.A.dval[(int64_t)d * P.nA + rac] * wrow[P.A.drank[(int64_t)d * P.nA + rac]];
     // beta singles: opposite-spin part sum_{i in alpha} (jb|ii) from the alpha J table
     for (int f = 0; f < P.nsb; ++f) {
         const int j = sb_ia[f] & 31, b = (sb_ia[f] >> 5) & 31;
@@ -808,7 +867,8 @@ __global__ __launch_bounds__(kProdThreads) void k_ham_product(ProdArgs P, const 
         acc += ((sb_ia[f] >> 10) & 1 ? -v : v) * w[(int64_t)sb_rank[f] * P.nA + rac];
     }
     // beta-beta doubles
-    for (int d = 0; d < P.ndb; ++d) acc += db_val[d] * w[(int64_t)db_rank[d] * P.nA + rac];
+    if (!P.dense)
+        for (int d = 0; d < P.ndb; ++d) acc += db_val[d] * w[(int64_t)db_rank[d] * P.nA + rac];
     // opposite-spin doubles
     for (int f = 0; f < P.nsb; ++f) {
         const int j = sb_ia[f] & 31, b = (sb_ia[f] >> 5) & 31;
@@ -831,11 +891,15 @@ __global__ __launch_bounds__(kProdThreads) void k_ham_product(ProdArgs P, const 
     if (valid) u[rb * P.nA + ra] = acc;
 }
 
-// LDS-staged variant (nA <= kProdLdsMaxA): the own beta row of w, the beta'
-// row of the current beta move and the g slice live in LDS (double-buffered
-// over the beta moves, one barrier per move); the thread's alpha moves are
-// packed one per register: rank | (i n + a) << 16 | sign << 31.
-// TPB threads per block (one thread per alpha string of the block's slice).
+// LDS-staged variant (nA <= kProdLdsMaxA): the own beta row of w, the beta' row
+// of the current beta move and the g slice live in LDS.  The g slice is staged
+// multiplied by the beta move's sign, followed by its negation and one zero, so
+// every alpha move of a thread is two LDS byte offsets held in registers (its
+// w entry; its g entry with the alpha sign chosen by the copy, moves past nsa
+// pointing at the zero): an opposite-spin term is two LDS reads and one FMA,
+// with no branch.  Rows of the next beta move are loaded into registers while
+// the current one is summed (two barriers per move).  TPB threads per block
+// (one thread per alpha string of the block's slice).
 constexpr int kProd2Threads = 256;
 constexpr int kProdLdsMaxA = 2048;
 
@@ -847,11 +911,9 @@ __global__ __launch_bounds__(TPB) void k_ham_product_lds(ProdArgs P, const doubl
     const int n = P.n, n2 = n * n;
     const int nA = (int)P.nA;
     double *wself = reinterpret_cast<double *>(smem);
-    double *wb0 = wself + nA;
-    double *wb1 = wb0 + nA;
-    double *gs0 = wb1 + nA;
-    double *gs1 = gs0 + n2;
-    double *jbl = gs1 + n2;
+    double *wb = wself + nA;
+    double *gs = wb + nA;                  // [sign_f g | -sign_f g | 0]: 2 n2 + 1
+    double *jbl = gs + 2 * n2 + 1;
     double *sb_f = jbl + n2;
     double *db_val = sb_f + P.nsb;
     int32_t *sb_rank = reinterpret_cast<int32_t *>(db_val + P.ndb);
@@ -874,94 +936,93 @@ __global__ __launch_bounds__(TPB) void k_ham_product_lds(ProdArgs P, const doubl
         db_rank[d] = P.B.drank[(int64_t)d * P.nB + rb];
         db_val[d] = P.B.dval[(int64_t)d * P.nB + rb];
     }
+    if (threadIdx.x == 0) gs[2 * n2] = 0.0;
     __syncthreads();
-    // stage the first beta move
-    if (P.nsb > 0) {
-        const int j = sb_ia[0] & 31, b = (sb_ia[0] >> 5) & 31;
-        const double *src = w + (int64_t)sb_rank[0] * P.nA;
-        for (int p = threadIdx.x; p < nA; p += TPB) wb0[p] = src[p];
-        for (int p = threadIdx.x; p < n2; p += TPB) gs0[p] = P.g[(int64_t)p * n2 + j * n + b];
-    }
     double acc = P.diag[rb * P.nA + rac] * wself[rac];
-    uint32_t pk[NSA];
+    // alpha singles; their opposite-spin operand offsets
+    const uint32_t wb_off = (uint32_t)((unsigned char *)wb - smem);
+    const uint32_t gs_off = (uint32_t)((unsigned char *)gs - smem);
+    uint32_t ow[NSA], og[NSA];
 #pragma unroll
     for (int e = 0; e < NSA; ++e) {
         if (e < P.nsa) {
             const int32_t rk = P.A.srank[(int64_t)e * P.nA + rac];
             const uint16_t q = P.A.sia[(int64_t)e * P.nA + rac];
-            const int i = q & 31, a = (q >> 5) & 31;
+            const int i = q & 31, a = (q >> 5) & 31, neg = (q >> 10) & 1;
             const double v = P.A.sf[(int64_t)e * P.nA + rac] + jbl[i * n + a];
-            acc += ((q >> 10) & 1 ? -v : v) * wself[rk];
-            pk[e] = (uint32_t)rk | ((uint32_t)(i * n + a) << 16) | ((uint32_t)((q >> 10) & 1) << 31);
+            acc += (neg ? -v : v) * wself[rk];
+            ow[e] = wb_off + 8u * (uint32_t)rk;
+            og[e] = gs_off + 8u * (uint32_t)(i * n + a + (neg ? n2 : 0));
         } else {
-            pk[e] = 0;
+            ow[e] = wb_off;
+            og[e] = gs_off + 8u * (uint32_t)(2 * n2);
         }
     }
-    for (int d = 0; d < P.nda; ++d)
-        acc += P.A.dval[(int64_t)d * P.nA + rac] * wself[P.A.drank[(int64_t)d * P.nA + rac]];
+    if (!P.dense)
+        for (int d = 0; d < P.nda; ++d)
+            acc += P.A.dval[(int64_t)d * P.nA + rac] * wself[P.A.drank[(int64_t)d * P.nA + rac]];
     for (int f = 0; f < P.nsb; ++f) {
         const int j = sb_ia[f] & 31, b = (sb_ia[f] >> 5) & 31;
         const double v = sb_f[f] + P.A.J[(int64_t)(j * n + b) * P.nA + rac];
         acc += ((sb_ia[f] >> 10) & 1 ? -v : v) * w[(int64_t)sb_rank[f] * P.nA + rac];
     }
-    for (int d = 0; d < P.ndb; ++d) acc += db_val[d] * w[(int64_t)db_rank[d] * P.nA + rac];
-    __syncthreads();
-    // opposite-spin doubles, double-buffered over the beta moves
+    if (!P.dense)
+        for (int d = 0; d < P.ndb; ++d) acc += db_val[d] * w[(int64_t)db_rank[d] * P.nA + rac];
+
+    // opposite-spin doubles
     constexpr int PFW = (kProdLdsMaxA + TPB - 1) / TPB;
     constexpr int PFG = (32 * 32 + TPB - 1) / TPB;
+    double pw[PFW], pg[PFG];
+    auto fetch = [&](int f) {
+        const int j = sb_ia[f] & 31, b = (sb_ia[f] >> 5) & 31;
+        const double *src = w + (int64_t)sb_rank[f] * P.nA;
+#pragma unroll
+        for (int t = 0; t < PFW; ++t) {
+            const int p = threadIdx.x + t * TPB;
+            pw[t] = p < nA ? src[p] : 0.0;
+        }
+#pragma unroll
+        for (int t = 0; t < PFG; ++t) {
+            const int p = threadIdx.x + t * TPB;
+            pg[t] = p < n2 ? P.g[(int64_t)p * n2 + j * n + b] : 0.0;
+        }
+    };
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    if (P.nsb > 0) fetch(0);
     for (int f = 0; f < P.nsb; ++f) {
-        const double *wb = (f & 1) ? wb1 : wb0;
-        const double *gs = (f & 1) ? gs1 : gs0;
-        double pw[PFW], pg[PFG];
-        const bool more = f + 1 < P.nsb;
-        if (more) {
-            const int j = sb_ia[f + 1] & 31, b = (sb_ia[f + 1] >> 5) & 31;
-            const double *src = w + (int64_t)sb_rank[f + 1] * P.nA;
+        const double sg = (sb_ia[f] >> 10) & 1 ? -1.0 : 1.0;
+        __syncthreads();                   // every read of the previous move is done
 #pragma unroll
-            for (int t = 0; t < PFW; ++t) {
-                const int p = threadIdx.x + t * TPB;
-                pw[t] = p < nA ? src[p] : 0.0;
-            }
-#pragma unroll
-            for (int t = 0; t < PFG; ++t) {
-                const int p = threadIdx.x + t * TPB;
-                pg[t] = p < n2 ? P.g[(int64_t)p * n2 + j * n + b] : 0.0;
-            }
+        for (int t = 0; t < PFW; ++t) {
+            const int p = threadIdx.x + t * TPB;
+            if (p < nA) wb[p] = pw[t];
         }
-        double part = 0.0;
 #pragma unroll
-        for (int e = 0; e < NSA; ++e) {
-            if (e < P.nsa) {
-                const uint32_t q = pk[e];
-                const double ge = gs[(q >> 16) & 1023];
-                const double v = ge * wb[q & 0xffffu];
-                part += (q >> 31) ? -v : v;
-            }
-        }
-        acc += (sb_ia[f] >> 10) & 1 ? -part : part;
-        if (more) {
-            double *wn = (f & 1) ? wb0 : wb1;
-            double *gn = (f & 1) ? gs0 : gs1;
-#pragma unroll
-            for (int t = 0; t < PFW; ++t) {
-                const int p = threadIdx.x + t * TPB;
-                if (p < nA) wn[p] = pw[t];
-            }
-#pragma unroll
-            for (int t = 0; t < PFG; ++t) {
-                const int p = threadIdx.x + t * TPB;
-                if (p < n2) gn[p] = pg[t];
+        for (int t = 0; t < PFG; ++t) {
+            const int p = threadIdx.x + t * TPB;
+            if (p < n2) {
+                gs[p] = sg * pg[t];
+                gs[n2 + p] = -sg * pg[t];
             }
         }
         __syncthreads();
+        if (f + 1 < P.nsb) fetch(f + 1);
+#pragma unroll
+        for (int e = 0; e < NSA; e += 4) {
+            s0 = fma(*(const double *)(smem + og[e]), *(const double *)(smem + ow[e]), s0);
+            if (e + 1 < NSA) s1 = fma(*(const double *)(smem + og[e + 1]), *(const double *)(smem + ow[e + 1]), s1);
+            if (e + 2 < NSA) s2 = fma(*(const double *)(smem + og[e + 2]), *(const double *)(smem + ow[e + 2]), s2);
+            if (e + 3 < NSA) s3 = fma(*(const double *)(smem + og[e + 3]), *(const double *)(smem + ow[e + 3]), s3);
+        }
     }
+    acc += (s0 + s1) + (s2 + s3);
     if (valid) u[rb * P.nA + ra] = acc;
 }
 
 static size_t product_lds_bytes(const ProdArgs &P)
 {
     const size_t n2 = (size_t)P.n * P.n;
-    return (3 * (size_t)P.nA + 3 * n2 + P.nsb + P.ndb) * 8 + (size_t)(P.nsb + P.ndb) * 4 +
+    return (2 * (size_t)P.nA + 3 * n2 + 1 + P.nsb + P.ndb) * 8 + (size_t)(P.nsb + P.ndb) * 4 +
            (size_t)P.nsb * 2;
 }
 
@@ -978,6 +1039,56 @@ static bool product_fits(const irl_system *s, int &nsa, int &nsb, int &nda, int 
     const double bytes = (double)(s->nA + s->nB) * ((nsa > nsb ? nsa : nsb) * 14.0 +
                                                     (nda > ndb ? nda : ndb) * 12.0 + n * n * 8.0);
     return bytes < 4e9;
+}
+
+// Same-spin doubles of one spin as a dense symmetric matrix D[s][t] (row s = string
+// rank, t = target rank): the element of string s and its double t.
+__global__ void k_dense_doubles(const int32_t *__restrict__ drank, const double *__restrict__ dval, int64_t nstr,
+                                int nd, double *__restrict__ D)
+{
+    const int64_t str = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (str >= nstr) return;
+    for (int d = 0; d < nd; ++d) D[str * nstr + drank[(int64_t)d * nstr + str]] = dval[(int64_t)d * nstr + str];
+}
+
+// strings per spin up to which the same-spin doubles are dense products
+constexpr int64_t kDenseDoublesMax = 2048;
+
+void free_dense_doubles(irl_system *s)
+{
+    if (s->blas) (void)rocblas_destroy_handle((rocblas_handle)s->blas);
+    s->blas = nullptr;
+    for (double **p : {&s->d.denseA, &s->d.denseB}) {
+        if (*p) (void)hipFree(*p);
+        *p = nullptr;
+    }
+}
+
+// Dense same-spin doubles for a full space with few strings per spin: a DGEMM per
+// spin replaces 2 x C(N,2) C(n-N,2) gathered terms per determinant.
+static hipError_t build_dense_doubles(irl_system *s, int nda, int ndb, hipStream_t st)
+{
+    if (s->nA > kDenseDoublesMax || s->nB > kDenseDoublesMax) return hipSuccess;
+    hipError_t e;
+    const size_t bA = (size_t)s->nA * s->nA * 8, bB = (size_t)s->nB * s->nB * 8;
+    if ((e = hipMalloc(&s->d.denseA, bA)) != hipSuccess) return e;
+    if ((e = hipMalloc(&s->d.denseB, bB)) != hipSuccess) return e;
+    s->dev_bytes += bA + bB;
+    if ((e = hipMemsetAsync(s->d.denseA, 0, bA, st)) != hipSuccess) return e;
+    if ((e = hipMemsetAsync(s->d.denseB, 0, bB, st)) != hipSuccess) return e;
+    k_dense_doubles<<<(unsigned)((s->nA + 127) / 128), 128, 0, st>>>(s->d.dblA_rank, s->d.dblA_val, s->nA, nda,
+                                                                     s->d.denseA);
+    k_dense_doubles<<<(unsigned)((s->nB + 127) / 128), 128, 0, st>>>(s->d.dblB_rank, s->d.dblB_val, s->nB, ndb,
+                                                                     s->d.denseB);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    rocblas_handle hb = nullptr;
+    if (rocblas_create_handle(&hb) != rocblas_status_success) return hipErrorUnknown;
+    s->blas = hb;
+    // reproducible results: no split reductions with atomics
+    if (rocblas_set_atomics_mode(hb, rocblas_atomics_not_allowed) != rocblas_status_success ||
+        rocblas_set_pointer_mode(hb, rocblas_pointer_mode_host) != rocblas_status_success)
+        return hipErrorUnknown;
+    return hipSuccess;
 }
 
 hipError_t launch_product_tables(irl_system *s, hipStream_t st)
@@ -1017,6 +1128,7 @@ hipError_t launch_product_tables(irl_system *s, hipStream_t st)
     k_string_tables<<<(unsigned)((s->nB + 127) / 128), 128, 0, st>>>(s->d.strB, s->d.rankB, s->nB, n,
                                                                     s->nb, s->d.h, s->d.g, B);
     if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = build_dense_doubles(s, nda, ndb, st)) != hipSuccess) return e;
     s->ham_kernel = 2;
     return hipSuccess;
 }
@@ -1052,6 +1164,7 @@ static hipError_t launch_ham_product(const irl_system *s, const double *w, doubl
 {
     ProdArgs P;
     P.rb0 = b0;
+    P.dense = s->d.denseA != nullptr && s->blas != nullptr;
     const int64_t nbeta = b1 - b0;
     product_fits(s, P.nsa, P.nsb, P.nda, P.ndb);
     P.n = s->n;
@@ -1080,7 +1193,20 @@ static hipError_t launch_ham_product(const irl_system *s, const double *w, doubl
     case 15: launch_prod_inst<60>(P, nbeta, w, u, st); break;
     default: launch_prod_inst<64>(P, nbeta, w, u, st); break;
     }
-    return hipGetLastError();
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !P.dense) return e;
+    // same-spin doubles: with w as the column-major nA x nB matrix X (column = beta
+    // string), U[:, b0:b1] += D_A X[:, b0:b1] + X D_B[:, b0:b1] (D_A, D_B symmetric)
+    rocblas_handle hb = (rocblas_handle)s->blas;
+    const double one = 1.0;
+    const rocblas_int mA = (rocblas_int)s->nA, kB = (rocblas_int)s->nB, nb = (rocblas_int)nbeta;
+    if (rocblas_set_stream(hb, st) != rocblas_status_success ||
+        rocblas_dgemm(hb, rocblas_operation_none, rocblas_operation_none, mA, nb, mA, &one, s->d.denseA, mA,
+                      w + b0 * s->nA, mA, &one, u + b0 * s->nA, mA) != rocblas_status_success ||
+        rocblas_dgemm(hb, rocblas_operation_none, rocblas_operation_none, mA, nb, kB, &one, w, mA,
+                      s->d.denseB + b0 * s->nB, kB, &one, u + b0 * s->nA, mA) != rocblas_status_success)
+        return hipErrorUnknown;
+    return hipSuccess;
 }
 
 }  // namespace irl

@@ -18,6 +18,8 @@ constexpr int kBasisCols = kMaxKrylov + kMaxBlock;   // Krylov basis columns hel
 constexpr int kCheckStride = 1;         // Lanczos steps between in-cycle convergence tests (large operators)
 constexpr int kWave = 64;               // CDNA wavefront width
 constexpr int kStreamBlocks = 512;      // row blocks of the D~^T stream kernel
+constexpr int kMaxColBlocks = 8;        // column blocks of stored Hamiltonian rows
+constexpr int64_t kColSliceBytes = 2 << 20;   // w bytes per column block (an L2 share)
 constexpr int kReduceGroups = 16;       // first-level groups of the partial reduction
 constexpr int kScalarParts = 1024;      // blocks of the scalar (energy) reductions
 constexpr uint64_t kEmptyKey = ~0ull;   // empty hash slot
@@ -91,10 +93,12 @@ struct SystemDev {
     int32_t *bstart = nullptr;    // nblocks + 1 row offsets
     int64_t nblocks = 0;
     // stored rows (optional): off-diagonal elements inside the set, compressed by row
-    int64_t *hptr = nullptr;      // n_dets + 1
-    int32_t *hcol = nullptr;      // nnz target rows
+    int64_t *hptr = nullptr;      // hcb blocks of n_dets + 1 row offsets (block-major)
+    int32_t *hcol = nullptr;      // nnz target rows, block b's targets in [b 2^hcs, (b + 1) 2^hcs)
     double *hval = nullptr;       // nnz values
     int64_t hnnz = 0;
+    int32_t hcb = 0;              // column blocks of the stored rows
+    int32_t hcs = 0;              // log2 of the target rows per column block
     // string tables (full space)
     int32_t *rankA = nullptr;   // 2^n, -1 for strings not of popcount n_alpha
     int32_t *rankB = nullptr;
@@ -113,6 +117,8 @@ struct SystemDev {
     int32_t *dblB_rank = nullptr;
     double *dblB_val = nullptr;
     double *jA = nullptr;       // nA x n*n: sum_{i in alpha} (pq|ii)
+    double *denseA = nullptr;   // nA x nA same-spin alpha doubles as a dense symmetric matrix (or nullptr)
+    double *denseB = nullptr;   // nB x nB, beta
 };
 
 // Read-only view of a system's Hamiltonian tables (pull kernels, solo and grouped).
@@ -129,9 +135,10 @@ struct HamView {
     const int32_t *rankA, *rankB;
     const int32_t *bidx;     // blocked lookup: beta string -> block, -1 if absent (or nullptr)
     const int32_t *bstart;   // blocked lookup: first row of each block, plus the end
-    const int64_t *hptr;     // stored rows (or nullptr): row offsets
+    const int64_t *hptr;     // stored rows (or nullptr): row offsets, hcb blocks of ns + 1
     const int32_t *hcol;     // stored rows: targets
     const double *hval;      // stored rows: values
+    int hcb, hcs;            // stored rows: column blocks, log2 of their width in rows
 };
 
 // key -> row lookup used when excitations are enumerated
@@ -190,6 +197,8 @@ struct irl_system {
     double Z = 0.0, E_el = 0.0;   // host copies after the last evaluation
     // pinned host staging for small readbacks
     irl::WsScalars *host_scal = nullptr;
+    // dense BLAS handle (rocblas_handle) for the same-spin doubles of a full space
+    void *blas = nullptr;
     // per-kernel timing
     bool stats_on = false;
     std::vector<hipEvent_t> ev_pool;
@@ -217,6 +226,8 @@ hipError_t launch_lookup_any(const irl_system *s, const uint64_t *q, int64_t nq,
 
 // hamiltonian.hip
 hipError_t launch_product_tables(irl_system *s, hipStream_t st);
+// release the dense doubles and their BLAS handle
+void free_dense_doubles(irl_system *s);
 HamView ham_view(const irl_system *s);
 hipError_t launch_ham_stored_grouped(const Member *M, const WorkItem *items, int nitems,
                                      int64_t nblocks, int which, hipStream_t st);
@@ -245,6 +256,7 @@ hipError_t launch_block_ritz(const WsLayout &L, void *ws, int s, int nb, hipStre
 hipError_t launch_block_restart(const WsLayout &L, void *ws, const double *Vold, double *Vnew,
                                 const double *Iold, double *Inew, int s, int k, int nb, hipStream_t st);
 // stored rows: per-row counts of connections inside the set, then the fill
+// per column block b: count[b n_dets + row] = elements of row with targets in block b
 hipError_t launch_ham_count(const irl_system *s, int32_t *count, hipStream_t st);
 hipError_t launch_ham_fill(const irl_system *s, const int64_t *ptr, int32_t *col, double *val,
                            hipStream_t st);
@@ -261,7 +273,9 @@ hipError_t launch_fac_forward(const irl_system *s, const WsLayout &L, void *ws, 
                               hipStream_t st);
 hipError_t launch_fac_jvp(const irl_system *s, const WsLayout &L, void *ws, const double *v, int zero_v0,
                           double *w, hipStream_t st);
-hipError_t launch_fac_vjp(const irl_system *s, const WsLayout &L, void *ws, const double *y,
+// D~^T c into the partial rows: one right-hand side y0 (c = y0 - coef psi) into half
+// `half`, or two (y1 non-null: y0 into half 0, y1 into half 1) from one pass over d
+hipError_t launch_fac_vjp(const irl_system *s, const WsLayout &L, void *ws, const double *y0, const double *y1,
                           const double *coefp, int half, int nblk, hipStream_t st);
 int fac_row_blocks(const WsLayout &L);
 hipError_t launch_nqs_dtilde(const irl_system *s, int V, int H, const double *theta,

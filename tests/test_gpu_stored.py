@@ -50,12 +50,34 @@ def test_stored_rows_count_and_apply(n, na, nb, count, seed, flags):
     nnz_off = Href.nnz - keys.size        # the oracle emits the diagonal once per row
     stored, need = s.store_hamiltonian(1 << 40)
     assert stored and s.info.ham_kernel == 4
-    assert need == (keys.size + 1) * 8 + 12 * nnz_off
+    nb = s.info.stored_col_blocks
+    assert 1 <= nb <= 8 and nb == max(1, -(-keys.size // (1 << 18)))    # 2 MiB slices of w
+    assert need == nb * (keys.size + 1) * 8 + 12 * nnz_off
     w = np.random.default_rng(4).normal(size=keys.size)
     u = host(s.apply_hamiltonian(dev(w)))
     assert rel_err(u, Href @ w) <= 1e-12
     again, need2 = s.store_hamiltonian(0)   # already stored: no-op
     assert again and need2 == need
+
+
+def test_stored_rows_column_blocks_match_enumeration():
+    """300,000 determinants: the stored rows split into two column blocks (2^18
+    target rows each, the second ragged).  The blocked apply equals the
+    enumerating kernel of the same system (itself pinned to the oracle) to FP64
+    rounding, and is bitwise reproducible."""
+    announce("stored rows: two column blocks")
+    keys = synth.cisd_like_selected_set(14, 7, 7, 300000, seed=3)
+    s, _, _ = _system(14, 7, 7, 3, keys)
+    w = dev(np.random.default_rng(7).normal(size=keys.size))
+    u_enum = host(s.apply_hamiltonian(w))
+    stored, need = s.store_hamiltonian(1 << 40)
+    assert stored and s.info.ham_kernel == 4 and s.info.stored_col_blocks == 2
+    u1 = host(s.apply_hamiltonian(w))
+    assert rel_err(u1, u_enum) <= 1e-12
+    assert np.array_equal(host(s.apply_hamiltonian(w)), u1)
+    s2, _, _ = _system(14, 7, 7, 3, keys)
+    assert s2.store_hamiltonian(1 << 40) == (True, need)
+    assert np.array_equal(host(s2.apply_hamiltonian(w)), u1)
 
 
 def test_stored_rows_over_budget_leaves_system_unchanged():
