@@ -701,14 +701,24 @@ __global__ __launch_bounds__(256) void k_energy_stage1(const double *__restrict_
     energy_stage1_body(psi, hpsi, r0, r1, red + blockIdx.x * 4);
 }
 
+// one wavefront (64 threads): lane l merges parts l, l + 64, ... in order, then a
+// fixed halving tree (lane l takes lane l + off) leaves the total on lane 0
 __device__ void energy_stage2_body(const double *__restrict__ red, int nparts, WsScalars *sc)
 {
-    if (threadIdx.x != 0) return;
+    const int lane = threadIdx.x;
+    if (lane >= kWave) return;
     Neu z{0, 0}, e{0, 0};
-    for (int i = 0; i < nparts; ++i) {
+    for (int i = lane; i < nparts; i += kWave) {
         z = neu_merge(z, Neu{red[i * 4 + 0], red[i * 4 + 1]});
         e = neu_merge(e, Neu{red[i * 4 + 2], red[i * 4 + 3]});
     }
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        const Neu zo{__shfl_down(z.s, off, kWave), __shfl_down(z.c, off, kWave)};
+        const Neu eo{__shfl_down(e.s, off, kWave), __shfl_down(e.c, off, kWave)};
+        z = neu_merge(z, zo);
+        e = neu_merge(e, eo);
+    }
+    if (lane != 0) return;
     sc->sum_psi2[0] = z.s;
     sc->sum_psi2[1] = z.c;
     sc->sum_psih[0] = e.s;

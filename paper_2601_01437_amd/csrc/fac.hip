@@ -99,6 +99,17 @@ __device__ __forceinline__ void z_tile(uint64_t xa, int lane, const double (&B)[
     }
 }
 
+// t = tanh z and d = 1 - t^2 from one expm1 of 2|z|: with e = expm1(2 |z|) >= 0,
+// |t| = e / (e + 2) and 1 - t^2 = 4 (e + 1) / (e + 2)^2, which has no cancellation as
+// |t| -> 1; |z| is capped at 354, where e is still finite and d is below 2e-307
+__device__ __forceinline__ void tanh_and_d(double z, double &t, double &d)
+{
+    const double e = expm1(2.0 * fmin(fabs(z), 354.0));
+    const double r = 1.0 / (e + 2.0);
+    t = copysign(e * r, z);
+    d = 4.0 * ((e + 1.0) * r) * r;
+}
+
 // x_r . u for the lane's A row (l % 16): partial over the lane's k-steps, then the
 // four lanes of the row are added (every lane of the row ends with the total)
 template <int KS>
@@ -166,9 +177,9 @@ __global__ __launch_bounds__(256) void k_fac_forward(const uint64_t *__restrict_
                 double d[QT], sum = 0.0;
 #pragma unroll
                 for (int q = 0; q < QT; ++q) {
-                    const double th = tanh(acc[q][r] + bh[q]);
+                    double th;
+                    tanh_and_d(acc[q][r] + bh[q], th, d[q]);
                     sum += h0 + q < H ? th : 0.0;
-                    d[q] = 1.0 - th * th;
                 }
                 if (row < ns) store_dq<QT, VEC>(dfac, row, H, h0, d);
                 ts[r] = sum;

@@ -198,9 +198,13 @@ def test_apply_bitwise_reproducible(c1_problem):
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
 
 
-@pytest.mark.parametrize("n,na,nb", [(10, 5, 5), (11, 6, 5), (9, 2, 6), (8, 1, 7), (6, 0, 3)])
+@pytest.mark.parametrize("n,na,nb", [(10, 5, 5), (11, 6, 5), (9, 2, 6), (8, 1, 7), (6, 0, 3),
+                                     (14, 6, 1), (14, 1, 6)])
 def test_product_kernel_matches_oracle_shapes(n, na, nb):
-    """String-product kernel over uneven fillings (the batched solves' shapes)."""
+    """String-product kernel over uneven fillings (the batched solves' shapes).
+    Up to 2048 strings per spin the same-spin doubles are dense products; the
+    3003-string cases keep them in the kernel (3003 alpha strings also take the
+    variant without LDS staging)."""
     announce(f"product kernel n={n} {na}+{nb}")
     s, h, g = make_system(n, na, nb, seed=n)
     keys = space.full_space(n, na, nb)
