@@ -352,7 +352,7 @@ __global__ __launch_bounds__(256) void k_fac_vjp(const uint64_t *__restrict__ ke
     };
     // ring of PD groups in flight per wave: a group is consumed, then its slot is
     // refilled with the group PD steps ahead (rows past r1 load as zeros)
-    constexpr int PD = 4;
+    constexpr int PD = NT == 2 ? 8 : 4;   // deepest ring that keeps 2 or more waves per SIMD
     Grp ring[PD];
     const int64_t g0 = r0 + 4 * wv;
 #pragma unroll
