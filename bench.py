@@ -449,12 +449,136 @@ def run_serving_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def run_ablation_bench(args):
+    """Optimiser comparison (the shape of the paper's Fig. 2c): from the same theta_0
+    on one workload, implicitly restarted Lanczos (IRL, m = 20, k = 1 by default), standard
+    Lanczos (SL: one m = 20 Lanczos process per step, no restart, Algorithm 2) and
+    Adam (two step sizes).  E* is the energy where IRL's lowest eigenvalue reaches
+    |lambda| <= 1e-12 (a stationary point of this network); each method reports the
+    steps and seconds to E - E* <= 1e-3, 1e-6, 1e-9 and 1e-12 Ha, within its step
+    and time caps (if IRL does not reach |lambda| <= 1e-12 within its cap, E* is the
+    lowest energy any method reached).  FP64 factored Jacobian throughout."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2601_01437_amd import binding as B
+    from paper_2601_01437_amd import System
+
+    wl = synth.WORKLOADS[args.ablation_workload]
+    h, g = wl.integrals()
+    sysm = System(wl.n, wl.na, wl.nb, h, g, dets=wl.dets())
+    fl = B.IRL_WS_FACTORED
+    theta0 = torch.tensor(wl.theta(), dtype=torch.float64, device="cuda")
+    thresholds = (1e-3, 1e-6, 1e-9, 1e-12)
+
+    def lanczos_run(m, k, restarts, flags, cap, tcap, info):
+        th = theta0.clone()
+        Es, ts, lams = [], [], []
+        applies = restarts_done = not_conv = 0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for it in range(cap):
+            rc, r, _, _ = sysm.step(th, wl.V, wl.H, m=m, k_keep=k, tol=1e-12, max_restarts=restarts,
+                                    flags=flags, ws_flags=fl, want_dtheta=False)
+            torch.cuda.synchronize()
+            if not Es:
+                Es.append(r.E_before)
+                ts.append(0.0)
+            Es.append(r.E_after)
+            ts.append(time.perf_counter() - t0)
+            lams.append(r.lambda_min)
+            applies += r.n_apply
+            restarts_done += r.n_restart
+            not_conv += rc == B.IRL_ENOTCONV
+            if rc == B.IRL_ESTEP or abs(r.lambda_min) <= 1e-12 or ts[-1] > tcap:
+                break
+        info.update(applies_per_step=applies / max(1, len(lams)), restarts_per_step=restarts_done / max(1, len(lams)),
+                    steps_not_converged=not_conv, last_lambda=lams[-1] if lams else None)
+        return np.array(Es), np.array(ts), lams
+
+    def adam_run(lr, cap, tcap):
+        th = theta0.clone()
+        m = torch.zeros(wl.P, dtype=torch.float64, device="cuda")
+        v = torch.zeros_like(m)
+        Es, ts = [], []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for t in range(1, cap + 1):
+            _, E = sysm.adam_step(wl.V, wl.H, th, m, v, t, ws_flags=fl, lr=lr)
+            Es.append(E)
+            ts.append(time.perf_counter() - t0)
+            if ts[-1] > tcap:
+                break
+        return np.array(Es), np.array(ts)
+
+    log(f"ablation on {wl.name}: IRL reference")
+    lanczos_run(20, 1, 0, 0, 1, 1e9, {})                  # warm-up
+    mk = args.ablation_irl
+    irl_name = f"IRL (m={mk[0]}, k={mk[1]})"
+    info = {irl_name: {}, "SL (m=20, no restart)": {}}
+    E_irl, t_irl, lam_irl = lanczos_run(mk[0], mk[1], 300, 0, args.irl_steps, args.irl_seconds, info[irl_name])
+    irl_converged = abs(lam_irl[-1]) <= 1e-12
+    log(f"IRL: {len(E_irl) - 1} steps, E {E_irl[-1]:.12f}, lambda {lam_irl[-1]:.2e}, {info[irl_name]}")
+    E_sl, t_sl, lam_sl = lanczos_run(20, 1, 0, B.IRL_STEP_FULL_CYCLES, args.sl_steps, args.irl_seconds,
+                                     info["SL (m=20, no restart)"])
+    runs = {irl_name: (E_irl, t_irl), "SL (m=20, no restart)": (E_sl, t_sl)}
+    for lr in args.adam_lr:
+        E_a, t_a = adam_run(lr, args.adam_steps, args.adam_seconds)
+        runs[f"Adam (lr={lr:g})"] = (E_a, t_a)
+    # E*: IRL's stationary point, else the lowest energy any method reached
+    E_star = float(E_irl[-1]) if irl_converged else float(min(E.min() for E, _ in runs.values()))
+    log(f"E* = {E_star:.12f} ({'IRL stationary point' if irl_converged else 'lowest energy reached'})")
+    out_methods = {}
+    for name, (E, t) in runs.items():
+        err = E - E_star
+        reach = {}
+        for thr in thresholds:
+            idx = np.nonzero(err <= thr)[0]
+            reach[f"{thr:g}"] = None if idx.size == 0 else {"steps": int(idx[0]), "seconds": float(t[idx[0]])}
+        out_methods[name] = {"steps_run": int(len(E) - (1 if name.startswith(("IRL", "SL")) else 0)),
+                             "seconds": float(t[-1]), "ms_per_step": float(t[-1] / max(1, len(E) - 1) * 1e3),
+                             "final_error": float(err[-1]), "best_error": float(err.min()), "reach": reach,
+                             **info.get(name, {})}
+        log(f"{name}: {out_methods[name]['steps_run']} steps, {t[-1]:.3f} s, final E - E* = {err[-1]:.3e}")
+    irl_t = out_methods[irl_name]["reach"]["1e-12"]
+    out = {
+        "metric": "steps and time to E - E* <= 1e-12 Ha (IRL, standard Lanczos, Adam)",
+        "value": irl_t["seconds"] if irl_t else None,
+        "unit": "s (IRL to 1e-12 Ha)",
+        "n_gpus": 1, "steps": int(len(E_irl) - 1), "warmup": 1,
+        "ms_per_step": out_methods[irl_name]["ms_per_step"],
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": (f"optimiser comparison on {wl.name}: {wl.n} orbitals {wl.na}a+{wl.nb}b, "
+                                f"V={wl.V} H={wl.H} (P={wl.P}), same theta_0 (seed {wl.seed}); IRL m={mk[0]} k={mk[1]} "
+                                f"tol=1e-12; SL m=20 without restart; Adam beta=(0.9, 0.999) eps=1e-8, "
+                                f"at most {args.adam_steps} steps or {args.adam_seconds:g} s"),
+                   "E_star": E_star, "E_star_is_irl_stationary_point": bool(irl_converged)},
+        "methods": out_methods,
+        "trajectories": {name: [float(x) for x in (E[:60] if len(E) <= 60 else
+                                                     E[np.unique(np.geomspace(1, len(E) - 1, 60).astype(int))])]
+                         for name, (E, t) in runs.items()},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c3s", "c4", "c5"])
+    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c3s", "c4", "c5", "ablation"])
+    ap.add_argument("--ablation-workload", default="c1", choices=["c1", "c2", "c3s"],
+                    help="ablation: workload of the optimiser comparison")
+    ap.add_argument("--adam-lr", type=float, nargs="+", default=[1e-3, 1e-2], help="ablation: Adam step sizes")
+    ap.add_argument("--adam-steps", type=int, default=20000, help="ablation: Adam step cap")
+    ap.add_argument("--adam-seconds", type=float, default=20.0, help="ablation: Adam time cap per step size")
+    ap.add_argument("--sl-steps", type=int, default=400, help="ablation: standard Lanczos step cap")
+    ap.add_argument("--irl-steps", type=int, default=400, help="ablation: IRL step cap")
+    ap.add_argument("--irl-seconds", type=float, default=60.0, help="ablation: IRL and SL time cap")
+    ap.add_argument("--ablation-irl", type=int, nargs=2, default=[20, 1], metavar=("M", "K"),
+                    help="ablation: IRL Krylov dimension and vectors kept per restart")
     ap.add_argument("--serve-seconds", type=float, default=20.0,
                     help="c5: length of the arrival window in seconds")
     ap.add_argument("--solves", type=int, default=64, help="c4: number of independent solves")
@@ -509,6 +633,9 @@ def main():
         return
     if args.config == "c5":
         run_serving_bench(args)
+        return
+    if args.config == "ablation":
+        run_ablation_bench(args)
         return
     wl = synth.WORKLOADS[args.config]
     h, g = wl.integrals()

@@ -326,6 +326,32 @@ int irl_step(irl_system *sys, irl_nqs_desc *nqs, const irl_solver_opts *opts, vo
  * mode A, seed 0, flags 0, block 0). */
 void irl_solver_opts_default(irl_solver_opts *o);
 
+/* ---- first-order baseline (optimiser comparison) ---- */
+
+/* Adam step sizes: the first-order method the paper compares IRL and standard
+ * Lanczos against (Results, "Efficiency and Numerical Stability of IRL
+ * Optimization", Fig. 2); Methods, "Practical Matrix-Free Implementation", costs
+ * one such step as one gradient evaluation. */
+typedef struct {
+    double lr;              /* step size alpha */
+    double beta1, beta2;    /* decay rates of the first and second moment estimates */
+    double eps;             /* added to the square root of the second moment */
+} irl_adam_opts;
+
+/* One Adam step on theta (in place): evaluates psi, Z, E and the gradient g at
+ * theta exactly as irl_nqs_evaluate does (same workspace and flags), then with the
+ * step count t >= 1
+ *   m <- beta1 m + (1 - beta1) g,   v <- beta2 v + (1 - beta2) g^2,
+ *   theta <- theta - lr (m / (1 - beta1^t)) / (sqrt(v / (1 - beta2^t)) + eps)
+ * elementwise (the bias-corrected moments of the published algorithm).
+ * m, v: device FP64[P], caller-owned, all zero before the first step.
+ * out (may be NULL): Z and E at theta before the update; out->grad, if set,
+ * receives g.  Errors: as irl_nqs_evaluate, and IRL_EINVAL for t < 1, m or v NULL,
+ * or lr, beta1, beta2, eps out of [0, inf) x [0, 1) x [0, 1) x (0, inf). */
+int irl_adam_step(irl_system *sys, const irl_nqs_desc *nqs, void *ws, size_t ws_bytes, uint32_t ws_flags,
+                  const irl_adam_opts *opts, double *m, double *v, int64_t t, irl_eval_out *out,
+                  void *stream);
+
 /* ---- batches of independent solves ------------------------------------- */
 
 /* A batch groups `count` independent optimisations (systems, networks,

@@ -70,6 +70,10 @@ class irl_solver_opts(ctypes.Structure):
                 ("seed", c_uint64), ("flags", c_uint32), ("block", c_int32)]
 
 
+class irl_adam_opts(ctypes.Structure):
+    _fields_ = [("lr", c_double), ("beta1", c_double), ("beta2", c_double), ("eps", c_double)]
+
+
 class irl_step_result(ctypes.Structure):
     _fields_ = [("E_before", c_double), ("E_after", c_double), ("lambda_min", c_double),
                 ("residual_est", c_double), ("residual_explicit", c_double),
@@ -103,6 +107,9 @@ _sigs = {
                            c_size_t, c_uint32, c_void_p, c_void_p, POINTER(irl_step_result),
                            c_void_p]),
     "irl_solver_opts_default": (None, [POINTER(irl_solver_opts)]),
+    "irl_adam_step": (c_int32, [_SYS, POINTER(irl_nqs_desc), c_void_p, c_size_t, c_uint32,
+                                POINTER(irl_adam_opts), c_void_p, c_void_p, c_int64,
+                                POINTER(irl_eval_out), c_void_p]),
     "irl_stats_enable": (c_int32, [_SYS, c_int32]),
     "irl_stats_get": (c_int32, [_SYS, c_void_p, c_void_p, c_void_p]),
     "irl_batch_create": (c_int32, [c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_uint32,
@@ -197,6 +204,18 @@ def irl_nqs_evaluate(sys, V, H, theta, ws, ws_flags, grad=None, stream=None):
     out = irl_eval_out(0.0, 0.0, None if grad is None else grad.data_ptr())
     _check(_lib.irl_nqs_evaluate(sys, ctypes.byref(nqs), _ptr(ws), ws.numel() * ws.element_size(),
                                  ws_flags, ctypes.byref(out), _stream(stream)), sys)
+    return out.Z, out.E
+
+
+def irl_adam_step(sys, V, H, theta, ws, ws_flags, m, v, t, lr=1e-3, beta1=0.9, beta2=0.999,
+                  eps=1e-8, grad=None, stream=None):
+    """One Adam step on theta (device, in place); m, v: device moment tensors (P).
+    Returns (Z, E) at theta before the update."""
+    nqs = irl_nqs_desc(V, H, theta.data_ptr())
+    o = irl_adam_opts(lr, beta1, beta2, eps)
+    out = irl_eval_out(0.0, 0.0, None if grad is None else grad.data_ptr())
+    _check(_lib.irl_adam_step(sys, ctypes.byref(nqs), _ptr(ws), ws.numel() * ws.element_size(), ws_flags,
+                              ctypes.byref(o), _ptr(m), _ptr(v), t, ctypes.byref(out), _stream(stream)), sys)
     return out.Z, out.E
 
 

@@ -297,6 +297,10 @@ WsLayout make_layout(int64_t ns, int64_t ncols, uint32_t flags, int V)
     return L;
 }
 
+// Adam update of theta from the gradient (lanczos.hip)
+hipError_t launch_adam(double *theta, const double *g, double *m, double *v, int64_t P, double lr, double b1,
+                       double b2, double eps, int64_t t, hipStream_t st);
+
 }  // namespace irl
 
 namespace {
@@ -820,6 +824,28 @@ int irl_nqs_evaluate(irl_system *s, const irl_nqs_desc *nqs, void *ws, size_t ws
                                  hipMemcpyDeviceToDevice, st));
             CK(s, hipStreamSynchronize(st));
         }
+    }
+    return IRL_OK;
+}
+
+int irl_adam_step(irl_system *s, const irl_nqs_desc *nqs, void *ws, size_t ws_bytes, uint32_t ws_flags,
+                  const irl_adam_opts *o, double *m, double *v, int64_t t, irl_eval_out *out, void *stream)
+{
+    if (!s) return IRL_EINVAL;
+    if (!o || !m || !v || t < 1) return set_err(s, IRL_EINVAL, "Adam options, moments or step count invalid");
+    if (!(o->lr >= 0.0) || !(o->beta1 >= 0.0 && o->beta1 < 1.0) || !(o->beta2 >= 0.0 && o->beta2 < 1.0) ||
+        !(o->eps > 0.0) || !std::isfinite(o->lr) || !std::isfinite(o->eps))
+        return set_err(s, IRL_EINVAL, "Adam step sizes out of range");
+    irl_eval_out ev{0, 0, out ? out->grad : nullptr};
+    int rc = irl_nqs_evaluate(s, nqs, ws, ws_bytes, ws_flags, &ev, stream);
+    if (rc) return rc;
+    const int64_t P = (int64_t)nqs->V * nqs->H + nqs->H + nqs->V;
+    hipStream_t st = (hipStream_t)stream;
+    CK(s, launch_adam(nqs->theta, ws_ptr<double>(ws, s->lay.off_grad) + 1, m, v, P, o->lr, o->beta1, o->beta2,
+                      o->eps, t, st));
+    if (out) {
+        out->Z = ev.Z;
+        out->E = ev.E;
     }
     return IRL_OK;
 }

@@ -517,6 +517,29 @@ __global__ void k_update(const double *y, double *dtheta, double *theta, int64_t
     }
 }
 
+// Adam (bias-corrected first and second moments), elementwise over the P parameters
+__global__ void k_adam(double *__restrict__ theta, const double *__restrict__ g, double *__restrict__ m,
+                       double *__restrict__ v, int64_t P, double lr, double b1, double b2, double eps,
+                       double c1, double c2)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P) return;
+    const double gi = g[i];
+    const double mi = b1 * m[i] + (1.0 - b1) * gi;
+    const double vi = b2 * v[i] + (1.0 - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    theta[i] -= lr * (mi / c1) / (sqrt(vi / c2) + eps);
+}
+
+hipError_t launch_adam(double *theta, const double *g, double *m, double *v, int64_t P, double lr, double b1,
+                       double b2, double eps, int64_t t, hipStream_t st)
+{
+    const double c1 = 1.0 - pow(b1, (double)t), c2 = 1.0 - pow(b2, (double)t);
+    k_adam<<<(unsigned)((P + 255) / 256), 256, 0, st>>>(theta, g, m, v, P, lr, b1, b2, eps, c1, c2);
+    return hipGetLastError();
+}
+
 hipError_t launch_update(const WsLayout &, void *, const double *y, double *dtheta, double *theta,
                          int64_t P, int, hipStream_t st)
 {

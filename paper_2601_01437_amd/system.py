@@ -77,6 +77,12 @@ class System:
         Z, E = B.irl_nqs_evaluate(self.handle, V, H, theta, ws, ws_flags, grad=grad)
         return Z, E, grad
 
+    def adam_step(self, V, H, theta, m, v, t, ws_flags=B.IRL_WS_FP64, grad=None, **opts):
+        """One Adam step on theta (in place); returns (Z, E) before the update."""
+        P = V * H + H + V
+        self.workspace(P + 1, ws_flags)
+        return B.irl_adam_step(self.handle, V, H, theta, self.ws, ws_flags, m, v, t, grad=grad, **opts)
+
     def set_dtilde(self, D, ws_flags=B.IRL_WS_FP64):
         ws = self.workspace(D.shape[1], ws_flags)
         B.irl_dtilde_set(self.handle, D, ws, ws_flags)
