@@ -19,10 +19,21 @@ Readings (the paper is not explicit):
   (step length parity unpinned).
 * mode "G": the exact generalised problem H~' c = lambda S~ c, solved after
   canonical orthogonalisation of S~.
+* mode "C": mode A in the connected tangent basis, whose derivative columns are
+  projected against psi, d_i psi - psi (psi^T d_i psi) / Z (the connected
+  correlation form named after Eq. centered_hamiltonian).  With sigma =
+  D~[:, 1:]^T psi / Z, the linearised wavefunction c_0 psi + sum_i c_i (d_i psi
+  - sigma_i psi) is proportional to psi + sum_i dtheta_i d_i psi for dtheta =
+  c[1:] / (c_0 - sigma . c[1:]), which is the update taken.
 
 Pins: tests/test_oracle_lm.py (identities, D~ = I reduction to exact
 diagonalisation, zero update at an exact wavefunction, exact GEVP, ARPACK's
-implicitly restarted Lanczos, finite-difference gradient, predicted decrease).
+implicitly restarted Lanczos, finite-difference gradient, predicted decrease);
+tests/test_oracle_connected.py (mode C: orthogonality of the connected columns,
+invariance under d_i psi -> d_i psi + a_i psi, reduction to mode A when the
+derivatives are already orthogonal to psi, zero update at an exact
+wavefunction, and the exact generalised problem reaching the same eigenvalue
+and linearised wavefunction in either basis).
 """
 from __future__ import annotations
 
@@ -110,6 +121,11 @@ def solve(Dt: np.ndarray, Hmat: sp.spmatrix, mode: str = "A", e_core: float = 0.
         w, U = np.linalg.eigh(Hp[1:, 1:])
         gap = w[1] - w[0] if w.size > 1 else np.inf
         return LMResult(E, E_el, Z, w[0], U[:, 0], None, gap, Hp, St)
+    if mode == "C":
+        Dc, sigma = connected_basis(Dt)
+        res = solve(Dc, Hmat, mode="A", e_core=e_core)
+        res.dtheta = connected_update(res.c, sigma)
+        return res
     if mode == "G":
         s, Us = np.linalg.eigh(0.5 * (St + St.T))
         keep = s > s_cut * s.max()
@@ -120,6 +136,24 @@ def solve(Dt: np.ndarray, Hmat: sp.spmatrix, mode: str = "A", e_core: float = 0.
         gap = w[1] - w[0] if w.size > 1 else np.inf
         return LMResult(E, E_el, Z, w[0], c, dtheta, gap, Hp, St)
     raise ValueError(mode)
+
+
+def connected_basis(Dt: np.ndarray):
+    """(D_c, sigma): the columns d_i psi of D~ (i >= 1) replaced by their
+    components orthogonal to psi, d_i psi - sigma_i psi with sigma_i =
+    psi^T d_i psi / Z; column 0 (psi) is kept."""
+    psi = Dt[:, 0]
+    Z = exact_sum(psi * psi)
+    sigma = (Dt[:, 1:].T @ psi) / Z
+    Dc = Dt.copy()
+    Dc[:, 1:] = Dt[:, 1:] - np.outer(psi, sigma)
+    return Dc, sigma
+
+
+def connected_update(c: np.ndarray, sigma: np.ndarray):
+    """dtheta from an eigenvector c in the connected basis: the coefficient of
+    psi in the linearised wavefunction is c_0 - sigma . c[1:]."""
+    return c[1:] / (c[0] - sigma @ c[1:])
 
 
 def eigh_lowest(A: np.ndarray):
