@@ -67,8 +67,18 @@ enum irl_precision { IRL_FP64 = 0, IRL_FP32 = 1 };
  *  IRL_MODE_A: (P+1)-dimensional centred matrix H~' = H~ - E S~ with identity
  *              metric; the update is dtheta = c[1:] / c[0].
  *  IRL_MODE_P: the P x P matrix H_eff (Eq. heff) with identity metric; returns
- *              the direction only (no update is defined). */
-enum irl_mode { IRL_MODE_A = 0, IRL_MODE_P = 1 };
+ *              the direction only (no update is defined).
+ *  IRL_MODE_C: mode A in the connected tangent basis (Methods, "From SR to a
+ *              Stable Eigenvalue Problem": H_eff in connected-correlation
+ *              form): each derivative column d_i psi is replaced by its part
+ *              orthogonal to psi, d_i psi - sigma_i psi with sigma = D~[:, 1:]^T
+ *              psi / Z.  The centred matrix keeps mode A's psi row and column
+ *              (g / 2) and its H_eff block becomes H_eff - (g sigma^T + sigma
+ *              g^T) / 2.  The linearised wavefunction c_0 psi + sum_i c_i (d_i
+ *              psi - sigma_i psi) gives the update dtheta = c[1:] / (c_0 -
+ *              sigma . c[1:]).  FP64 solves with block 0 only; irl_step
+ *              computes sigma (one D~^T pass) before the solve. */
+enum irl_mode { IRL_MODE_A = 0, IRL_MODE_P = 1, IRL_MODE_C = 2 };
 
 /* workspace flags (irl_workspace_query) */
 enum irl_ws_flags {
@@ -169,7 +179,8 @@ typedef struct {
     double residual_est;    /* |beta_m e_m^T u_1| of the accepted cycle */
     double residual_explicit;  /* ||H~'y - lambda y|| with one more operator apply */
     double tol_used;        /* max(tol, 64 u_op ||T_m||) */
-    double c0;              /* first component of the unit Ritz vector (mode A) */
+    double c0;              /* first component of the unit Ritz vector (mode A);
+                               mode C: c_0 - sigma . c[1:], the coefficient of psi */
     double gap;             /* second-lowest minus lowest Ritz value */
     double norm_T;          /* max |Ritz value| of the last cycle */
     int32_t n_apply;        /* operator applies used by the solve */
@@ -310,14 +321,16 @@ int irl_apply_hamiltonian(irl_system *sys, const double *w, double *u, void *str
  *     (split form); if the workspace also holds the FP64 copy, the solve is
  *     then polished in FP64 from the FP32 Ritz vector (unless
  *     IRL_STEP_NO_POLISH), so the result meets the FP64 tolerance;
- *  3. mode A: dtheta = c[1:] / c[0]; unless IRL_STEP_NO_UPDATE theta += dtheta;
+ *  3. mode A: dtheta = c[1:] / c[0] (mode C: c[1:] / (c_0 - sigma . c[1:]));
+ *     unless IRL_STEP_NO_UPDATE theta += dtheta;
  *  4. unless IRL_STEP_NO_EVAL_AFTER: evaluate at the new theta (ws then holds
  *     D~ for the new theta, so the next call may pass IRL_STEP_WS_CURRENT).
  * nqs may be NULL when ws holds a D~ from irl_dtilde_set (no update then).
  * dtheta: device, P doubles, or NULL.  ritz: device, P+1 doubles (mode A) or
  * P doubles (mode P), unit-norm eigenvector, or NULL.
  * Returns IRL_OK, IRL_ENOTCONV (r filled with the last cycle's values),
- * IRL_ESTEP (|c_0| < 1e-8: theta unchanged) or an error. */
+ * IRL_ESTEP (|c_0| < 1e-8, mode C |c_0 - sigma . c[1:]| < 1e-8: theta
+ * unchanged) or an error (IRL_EINVAL for mode C with IRL_FP32 or block > 1). */
 int irl_step(irl_system *sys, irl_nqs_desc *nqs, const irl_solver_opts *opts, void *ws,
              size_t ws_bytes, uint32_t ws_flags, double *dtheta, double *ritz,
              irl_step_result *r, void *stream);

@@ -201,6 +201,22 @@ int energy_and_gradient(irl_system *s, void *ws, const WsLayout &L, hipStream_t 
     return IRL_OK;
 }
 
+// connected basis (mode C): sig = D~^T psi into ws (one backward product with psi)
+int connected_sigma(irl_system *s, void *ws, const WsLayout &L, hipStream_t st)
+{
+    const double *psi = ws_ptr<double>(ws, L.off_psi);
+    double *sig = ws_ptr<double>(ws, L.off_sig);
+    int nblk = 1;
+    if (L.flags & IRL_WS_FACTORED) {
+        nblk = fac_row_blocks(L);
+        TIMED(s, IRL_STAT_GEMV_T, st, launch_fac_vjp(s, L, ws, psi, nullptr, nullptr, 0, nblk, st));
+    } else {
+        TIMED(s, IRL_STAT_GEMV_T, st, launch_gemv_t2(L, ws, IRL_FP64, psi, psi, nullptr, nullptr, &nblk, st));
+    }
+    TIMED(s, IRL_STAT_REDUCE, st, launch_t2_reduce(L, ws, nblk, sig, nullptr, L.ncols, 1.0, nullptr, st));
+    return IRL_OK;
+}
+
 // the operator pair into ws yH/yS (internal, ldv long); zero_v0: apply to (0, v[1:])
 int apply_internal(irl_system *s, void *ws, const WsLayout &L, const double *v, double *yH,
                    double *yS, int prec, hipStream_t st, int zero_v0 = 0)
@@ -293,6 +309,7 @@ WsLayout make_layout(int64_t ns, int64_t ncols, uint32_t flags, int V)
     L.off_img1 = take((size_t)kBasisCols * ld * 8);
     L.off_hy = take((size_t)ld * 8);
     L.off_fac = take((flags & IRL_WS_FACTORED) ? (size_t)ns * (size_t)L.hfac * 8 : 0);
+    L.off_sig = take((size_t)ld * 8);
     L.total = off;
     return L;
 }
@@ -316,7 +333,7 @@ struct SolveOut {
 int irl_solve(irl_system *s, void *ws, const WsLayout &L, const irl_solver_opts &o, int prec,
               const double *start, SolveOut &out, hipStream_t st)
 {
-    const int64_t dim = (o.mode == IRL_MODE_A) ? L.ncols : L.ncols - 1;
+    const int64_t dim = (o.mode != IRL_MODE_P) ? L.ncols : L.ncols - 1;
     const int m = (int)std::min<int64_t>(o.m, dim);
     const int k = std::min(o.k_keep, m - 1);
     if (m < 2 || k < 1) return set_err(s, IRL_EINVAL, "problem dimension too small for the Krylov space");
@@ -922,9 +939,11 @@ int irl_step(irl_system *s, irl_nqs_desc *nqs, const irl_solver_opts *opts, void
     else
         irl_solver_opts_default(&o);
     if (o.m < 2 || o.m > kMaxKrylov || o.k_keep < 1 || o.k_keep >= o.m || !(o.tol > 0.0) ||
-        o.max_restarts < 0 || (o.mode != IRL_MODE_A && o.mode != IRL_MODE_P) || o.block < 0 ||
-        o.block > kMaxBlock)
+        o.max_restarts < 0 || (o.mode != IRL_MODE_A && o.mode != IRL_MODE_P && o.mode != IRL_MODE_C) ||
+        o.block < 0 || o.block > kMaxBlock)
         return set_err(s, IRL_EINVAL, "bad solver options");
+    if (o.mode == IRL_MODE_C && (o.precision != IRL_FP64 || o.block > 1))
+        return set_err(s, IRL_EINVAL, "the connected basis (mode C) needs an FP64 single-vector solve");
     hipStream_t st = (hipStream_t)stream;
     irl_step_result res;
     std::memset(&res, 0, sizeof(res));
@@ -948,6 +967,11 @@ int irl_step(irl_system *s, irl_nqs_desc *nqs, const irl_solver_opts *opts, void
     res.E_before = s->E_el + s->e_core;
     double t1 = now_ms();
     res.ms_eval = t1 - t0;
+
+    if (o.mode == IRL_MODE_C) {
+        rc = connected_sigma(s, ws, L, st);
+        if (rc) return rc;
+    }
 
     // ---- implicitly restarted Lanczos ----
     SolveOut so;
@@ -977,8 +1001,15 @@ int irl_step(irl_system *s, irl_nqs_desc *nqs, const irl_solver_opts *opts, void
     res.tol_used = so.tol_used;
     res.n_apply_lo = n_apply_lo;
     const bool converged = so.converged != 0;
+    if (o.mode == IRL_MODE_C) {
+        // coefficient of psi in the connected linearised wavefunction
+        CK(s, launch_connected_c0(L, ws, y, st));
+        rc = read_scalars(s, ws, L, st);
+        if (rc) return rc;
+        res.c0 = s->host_scal->c0;
+    }
     if (ritz) {
-        if (o.mode == IRL_MODE_A)
+        if (o.mode != IRL_MODE_P)
             CK(s, hipMemcpyAsync(ritz, y, L.ncols * 8, hipMemcpyDeviceToDevice, st));
         else
             CK(s, hipMemcpyAsync(ritz, y + 1, (L.ncols - 1) * 8, hipMemcpyDeviceToDevice, st));
@@ -986,7 +1017,7 @@ int irl_step(irl_system *s, irl_nqs_desc *nqs, const irl_solver_opts *opts, void
     double t2 = now_ms();
     res.ms_solve = t2 - t1;
     int status = converged ? IRL_OK : IRL_ENOTCONV;
-    if (o.mode == IRL_MODE_A) {
+    if (o.mode != IRL_MODE_P) {
         if (!(std::fabs(res.c0) >= 1e-8)) {
             status = IRL_ESTEP;
         } else {

@@ -61,7 +61,8 @@ struct WsLayout {
            off_u = 0, off_grad = 0, off_yh = 0, off_ys = 0, off_y = 0, off_r = 0,
            off_part = 0, off_part2 = 0, off_red = 0, off_kry0 = 0, off_kry1 = 0, off_vconv = 0,
            off_img0 = 0, off_img1 = 0, off_hy = 0,   // operator images of the basis; of y
-           off_fac = 0;                              // factored Jacobian d = 1 - t^2 (N_s x hfac)
+           off_fac = 0,                              // factored Jacobian d = 1 - t^2 (N_s x hfac)
+           off_sig = 0;                              // D~^T psi (connected basis, mode C)
     int hfac = 0;                                    // hidden units of the factored Jacobian
     size_t total = 0;
 };
@@ -317,6 +318,7 @@ hipError_t launch_ritz_vector(const WsLayout &L, void *ws, const double *V, cons
                               double *y, double *hy, hipStream_t st);
 hipError_t launch_residual_image(const WsLayout &L, void *ws, const double *y, const double *hy, double *r,
                                  int mode, hipStream_t st);
+hipError_t launch_connected_c0(const WsLayout &L, void *ws, const double *y, hipStream_t st);
 hipError_t launch_update(const WsLayout &L, void *ws, const double *y, double *dtheta,
                          double *theta, int64_t P, int mode, hipStream_t st);
 hipError_t launch_copy(double *dst, const double *src, int64_t n, hipStream_t st);

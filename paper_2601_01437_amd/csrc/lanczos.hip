@@ -156,10 +156,12 @@ hipError_t launch_start_vector(double *v, int64_t ncols, int64_t ldv, int mode, 
 // One Lanczos step j: w = H~' v_j from (yH, yS), recurrence, CGS2, normalise.
 // img (column j of the image basis): a copy of H~' v_j, so that the image of any
 // combination of basis vectors (a Ritz vector) is the same combination of images.
+// sig (mode C only, else null): D~^T psi.  The connected basis adds
+// -(g_i sigma.v + sigma_i g.v) / 2 to components i >= 1, sigma = sig / Z.
 __device__ void lanczos_step_body(
     const double *__restrict__ yH, const double *__restrict__ yS, const double *__restrict__ grad,
-    WsScalars *sc, double *V, double *img, int64_t ldv, int64_t ncols, int j, int mode, int split,
-    uint64_t seed)
+    const double *__restrict__ sig, WsScalars *sc, double *V, double *img, int64_t ldv, int64_t ncols,
+    int j, int mode, int split, uint64_t seed)
 {
     __shared__ double sh[kVecWaves * (kMaxKrylov + 1)];
     __shared__ double hsh[kMaxKrylov + 1];
@@ -167,11 +169,13 @@ __device__ void lanczos_step_body(
     const double *vj = V + (int64_t)j * ldv;
     double *w = V + (int64_t)(j + 1) * ldv;
     const int64_t L = ldv;
-    const double gdotv = split ? grad_dot(grad, vj, ncols, sh) : 0.0;
+    const double gdotv = (split || sig) ? grad_dot(grad, vj, ncols, sh) : 0.0;
+    const double sdotv = sig ? grad_dot(sig, vj, ncols, sh) / Z : 0.0;
     const double v0 = vj[0];
     double pa = 0.0;
     for (int64_t i = threadIdx.x; i < L; i += kVecThreads) {
         double x = (i < ncols) ? centred_component(i, yH, yS, grad, v0, gdotv, Z, E, split) : 0.0;
+        if (sig && i >= 1 && i < ncols) x -= 0.5 * (grad[i] * sdotv + (sig[i] / Z) * gdotv);
         if (mode == IRL_MODE_P && i == 0) x = 0.0;
         w[i] = x;
         img[(int64_t)j * ldv + i] = x;
@@ -207,17 +211,18 @@ __device__ void lanczos_step_body(
 
 __global__ __launch_bounds__(kVecThreads) void k_lanczos_step(
     const double *__restrict__ yH, const double *__restrict__ yS, const double *__restrict__ grad,
-    WsScalars *sc, double *V, double *img, int64_t ldv, int64_t ncols, int j, int mode, int split,
-    uint64_t seed)
+    const double *__restrict__ sig, WsScalars *sc, double *V, double *img, int64_t ldv, int64_t ncols,
+    int j, int mode, int split, uint64_t seed)
 {
-    lanczos_step_body(yH, yS, grad, sc, V, img, ldv, ncols, j, mode, split, seed);
+    lanczos_step_body(yH, yS, grad, sig, sc, V, img, ldv, ncols, j, mode, split, seed);
 }
 
 hipError_t launch_lanczos_step(const WsLayout &L, void *ws, double *V, double *img, int j, int mode,
                                int split, uint64_t seed, hipStream_t st)
 {
+    const double *sig = mode == IRL_MODE_C ? ws_ptr<double>(ws, L.off_sig) : nullptr;
     k_lanczos_step<<<1, kVecThreads, 0, st>>>(ws_ptr<double>(ws, L.off_yh), ws_ptr<double>(ws, L.off_ys),
-                                               ws_ptr<double>(ws, L.off_grad),
+                                               ws_ptr<double>(ws, L.off_grad), sig,
                                                ws_ptr<WsScalars>(ws, L.off_scal), V, img, L.ldv, L.ncols,
                                                j, mode, split, seed);
     return hipGetLastError();
@@ -505,10 +510,11 @@ hipError_t launch_residual_image(const WsLayout &L, void *ws, const double *y, c
     return hipGetLastError();
 }
 
-// dtheta = y[1:] / y[0]; theta += dtheta
-__global__ void k_update(const double *y, double *dtheta, double *theta, int64_t P)
+// dtheta = y[1:] / *c0p; theta += dtheta.  c0p is y[0] (mode A) or the connected
+// basis' coefficient of psi (mode C).
+__global__ void k_update(const double *y, const double *c0p, double *dtheta, double *theta, int64_t P)
 {
-    const double c0 = y[0];
+    const double c0 = *c0p;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < P;
          i += (int64_t)gridDim.x * blockDim.x) {
         double d = y[i + 1] / c0;
@@ -540,12 +546,30 @@ hipError_t launch_adam(double *theta, const double *g, double *m, double *v, int
     return hipGetLastError();
 }
 
-hipError_t launch_update(const WsLayout &, void *, const double *y, double *dtheta, double *theta,
-                         int64_t P, int, hipStream_t st)
+hipError_t launch_update(const WsLayout &L, void *ws, const double *y, double *dtheta, double *theta,
+                         int64_t P, int mode, hipStream_t st)
 {
     unsigned blocks = (unsigned)((P + 255) / 256);
     if (blocks > 1024) blocks = 1024;
-    k_update<<<blocks, 256, 0, st>>>(y, dtheta, theta, P);
+    const double *c0p = mode == IRL_MODE_C ? &ws_ptr<WsScalars>(ws, L.off_scal)->c0 : y;
+    k_update<<<blocks, 256, 0, st>>>(y, c0p, dtheta, theta, P);
+    return hipGetLastError();
+}
+
+// connected basis: the coefficient of psi in the linearised wavefunction,
+// c0 = y[0] - sum_{i >= 1} sig[i] y[i] / Z, into sc->c0 (one block, fixed order)
+__global__ __launch_bounds__(kVecThreads) void k_connected_c0(WsScalars *sc, const double *__restrict__ y,
+                                                             const double *__restrict__ sig, int64_t ncols)
+{
+    __shared__ double sh[kVecWaves];
+    const double s = grad_dot(sig, y, ncols, sh);
+    if (threadIdx.x == 0) sc->c0 = y[0] - s / sc->Z;
+}
+
+hipError_t launch_connected_c0(const WsLayout &L, void *ws, const double *y, hipStream_t st)
+{
+    k_connected_c0<<<1, kVecThreads, 0, st>>>(ws_ptr<WsScalars>(ws, L.off_scal), y,
+                                              ws_ptr<double>(ws, L.off_sig), L.ncols);
     return hipGetLastError();
 }
 
@@ -971,7 +995,7 @@ __global__ __launch_bounds__(kVecThreads) void k_lanczos_step_grouped(
     int split, uint64_t seed)
 {
     const Member &mb = M[items[blockIdx.x].m];
-    lanczos_step_body(mb.yH, mb.yS, mb.grad, mb.sc, mb.kry[cur], mb.img[cur], mb.ld, mb.ncols, j, mode,
+    lanczos_step_body(mb.yH, mb.yS, mb.grad, nullptr, mb.sc, mb.kry[cur], mb.img[cur], mb.ld, mb.ncols, j, mode,
                       split, seed);
 }
 

@@ -122,7 +122,7 @@ class System:
         dth = torch.empty(P, dtype=torch.float64, device=self.device) if want_dtheta else None
         ritz = None
         if want_ritz:
-            ritz = torch.empty(P + 1 if mode == B.IRL_MODE_A else P, dtype=torch.float64,
+            ritz = torch.empty(P + 1 if mode != B.IRL_MODE_P else P, dtype=torch.float64,
                                device=self.device)
         rc, res = B.irl_step(self.handle, o, ws, ws_flags, V=V, H=H, theta=theta, dtheta=dth,
                              ritz=ritz)

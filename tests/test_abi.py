@@ -60,3 +60,26 @@ def test_struct_layout_matches_c_compiler():
     sizes = _c_sizes()
     for name, size in sizes.items():
         assert ctypes.sizeof(getattr(B, name)) == size, name
+
+
+def test_enum_values_match_header():
+    """Every IRL_* enumerator the header defines has the same value in the binding."""
+    from paper_2601_01437_amd import binding
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    values = {}
+    for body in re.findall(r"enum\s+\w+\s*\{(.*?)\}", text, flags=re.S):
+        for name, val in re.findall(r"\b(IRL_[A-Z0-9_]+)\s*=\s*(-?\d+)u?", body):
+            values[name] = int(val)
+    assert values["IRL_MODE_C"] == 2
+    # the statistics kinds are the binding's STAT_KINDS, in enum order (the
+    # binding spells the reduced-precision kinds _LO as _fp32)
+    stats = {n: v for n, v in values.items() if n.startswith("IRL_STAT_")}
+    for n in stats:
+        del values[n]
+    assert stats.pop("IRL_STAT_KINDS") == len(binding.STAT_KINDS)
+    assert {n[len("IRL_STAT_"):].lower().replace("_lo", "_fp32"): v for n, v in stats.items()} == \
+        {k: i for i, k in enumerate(binding.STAT_KINDS)}
+    missing = [n for n in values if not hasattr(binding, n)]
+    assert not missing, missing
+    wrong = {n: (v, getattr(binding, n)) for n, v in values.items() if getattr(binding, n) != v}
+    assert not wrong, wrong
