@@ -330,7 +330,8 @@ int irl_apply_hamiltonian(irl_system *sys, const double *w, double *u, void *str
  * P doubles (mode P), unit-norm eigenvector, or NULL.
  * Returns IRL_OK, IRL_ENOTCONV (r filled with the last cycle's values),
  * IRL_ESTEP (|c_0| < 1e-8, mode C |c_0 - sigma . c[1:]| < 1e-8: theta
- * unchanged) or an error (IRL_EINVAL for mode C with IRL_FP32 or block > 1). */
+ * unchanged) or an error (IRL_EINVAL for mode C with IRL_FP32, block > 1 or
+ * sampled estimators). */
 int irl_step(irl_system *sys, irl_nqs_desc *nqs, const irl_solver_opts *opts, void *ws,
              size_t ws_bytes, uint32_t ws_flags, double *dtheta, double *ritz,
              irl_step_result *r, void *stream);
@@ -364,6 +365,52 @@ typedef struct {
 int irl_adam_step(irl_system *sys, const irl_nqs_desc *nqs, void *ws, size_t ws_bytes, uint32_t ws_flags,
                   const irl_adam_opts *opts, double *m, double *v, int64_t t, irl_eval_out *out,
                   void *stream);
+
+/* ---- sampled estimators (variational Monte Carlo) ----------------------- */
+
+/* Result of irl_vmc_sample. */
+typedef struct {
+    double E_sampled;       /* mean local energy over the draws (+ e_core) */
+    double E_exact;         /* psi^T H psi / Z on the set at the same theta (+ e_core) */
+    double E_loc_var;       /* variance of the local energy over the draws */
+    int64_t n_unique;       /* distinct determinants drawn */
+    int64_t n_samples;
+} irl_vmc_out;
+
+/* Draw n_samples configurations from |psi|^2 / Z on the determinant set and
+ * replace the workspace's exact estimators by the sampled ones.
+ *
+ * Sampling (Methods, "Autoregressive Modeling and Physical Constraints", Eqs.
+ * autoregressive_factorization and constraint): the spin-orbitals taken one at
+ * a time from the exact conditionals of |psi|^2 (most significant key bit
+ * first: beta orbital n-1 down to 0, then alpha n-1 down to 0), every draw
+ * inside the fixed (N_alpha, N_beta) set, one uniform number per sample.  This
+ * is the inverse transform of the cumulative |psi|^2 in ascending key order,
+ * which the library evaluates in 64-bit fixed point (psi^2 2^k rounded, the
+ * total below 2^62; determinants with psi^2 below 2^-62 Z are never drawn).
+ * u: device, n_samples doubles in [0, 1) (values outside are clamped into it);
+ * the caller supplies the random numbers.  rows (may be NULL): device,
+ * n_samples int64, the drawn row of each sample.  grad (may be NULL): device,
+ * P doubles, receives the sampled gradient F.
+ *
+ * Estimators (Methods, "From SR to a Stable Eigenvalue Problem", Eq.
+ * centered_hamiltonian; "Practical Matrix-Free Implementation", Eq.
+ * matrix_vec_prod), with E_loc(x) = (H psi)(x) / psi(x) on the set and O(x) =
+ * D~[x, :] / psi(x) (O_0 = 1): E = <E_loc>, F = 2 <O (E_loc - E)>, and the
+ * operator pair of irl_apply_lm_operator becomes (y_H, y_S) = Z (<O E_loc O^T> v,
+ * <O O^T> v), so the centred matrix (y_H - E y_S) / Z of irl_step is the sample
+ * mean of O (E_loc - E) O^T (mode A: P + 1 components; mode P: H_eff alone).
+ * Until the next irl_nqs_evaluate or irl_dtilde_set, applies and irl_step with
+ * IRL_STEP_WS_CURRENT use these (E_before then reports the sampled energy);
+ * an irl_step that evaluates, or evaluates after its update, returns to the
+ * exact estimators.  Mode C is not defined on sampled estimators (IRL_EINVAL).
+ *
+ * Requires an evaluated workspace with an FP64 D~ copy or the factored Jacobian
+ * (for F).  One synchronisation (the scalars of out).  Errors: IRL_ESTATE (no
+ * evaluation in ws), IRL_EINVAL (u NULL, n_samples outside [1, 2^31 - 1], no
+ * FP64 Jacobian), IRL_ENOMEM, IRL_EDEVICE. */
+int irl_vmc_sample(irl_system *sys, void *ws, size_t ws_bytes, const double *u, int64_t n_samples,
+                   int64_t *rows, double *grad, irl_vmc_out *out, void *stream);
 
 /* ---- batches of independent solves ------------------------------------- */
 
@@ -412,7 +459,8 @@ enum irl_stat_kind {
     IRL_STAT_RITZ = 7,           /* Ritz pairs, restart shifts, basis compression, Ritz vector */
     IRL_STAT_GEMV_LO = 8,        /* w = D~ v on the FP32 copy (IRL_STAT_GEMV: FP64 copy) */
     IRL_STAT_GEMV_T_LO = 9,      /* D~^T stream on the FP32 copy (IRL_STAT_GEMV_T: FP64 copy) */
-    IRL_STAT_KINDS = 10
+    IRL_STAT_VMC = 10,           /* sampling, sampled weights and the sampled operator's diagonal */
+    IRL_STAT_KINDS = 11
 };
 
 /* on != 0: from now on every kernel launch of this handle is bracketed by a

@@ -31,7 +31,7 @@ IRL_STEP_FULL_CYCLES = 16
 IRL_SYS_FORCE_HASH = 1
 IRL_SYS_FORCE_PULL = 2
 STAT_KINDS = ("dtilde_build", "ham_apply", "gemv", "gemv_t", "reduce", "energy", "lanczos", "ritz",
-              "gemv_fp32", "gemv_t_fp32")
+              "gemv_fp32", "gemv_t_fp32", "vmc")
 
 STATUS_NAMES = {0: "IRL_OK", 1: "IRL_ENOTCONV", 2: "IRL_ESTEP", -1: "IRL_EINVAL",
                 -2: "IRL_ENOMEM", -3: "IRL_EDEVICE", -4: "IRL_ESTATE"}
@@ -74,6 +74,14 @@ class irl_adam_opts(ctypes.Structure):
     _fields_ = [("lr", c_double), ("beta1", c_double), ("beta2", c_double), ("eps", c_double)]
 
 
+class irl_vmc_out(ctypes.Structure):
+    _fields_ = [("E_sampled", c_double), ("E_exact", c_double), ("E_loc_var", c_double),
+                ("n_unique", c_int64), ("n_samples", c_int64)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 class irl_step_result(ctypes.Structure):
     _fields_ = [("E_before", c_double), ("E_after", c_double), ("lambda_min", c_double),
                 ("residual_est", c_double), ("residual_explicit", c_double),
@@ -110,6 +118,8 @@ _sigs = {
     "irl_adam_step": (c_int32, [_SYS, POINTER(irl_nqs_desc), c_void_p, c_size_t, c_uint32,
                                 POINTER(irl_adam_opts), c_void_p, c_void_p, c_int64,
                                 POINTER(irl_eval_out), c_void_p]),
+    "irl_vmc_sample": (c_int32, [_SYS, c_void_p, c_size_t, c_void_p, c_int64, c_void_p, c_void_p,
+                                 POINTER(irl_vmc_out), c_void_p]),
     "irl_stats_enable": (c_int32, [_SYS, c_int32]),
     "irl_stats_get": (c_int32, [_SYS, c_void_p, c_void_p, c_void_p]),
     "irl_batch_create": (c_int32, [c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_uint32,
@@ -217,6 +227,15 @@ def irl_adam_step(sys, V, H, theta, ws, ws_flags, m, v, t, lr=1e-3, beta1=0.9, b
     _check(_lib.irl_adam_step(sys, ctypes.byref(nqs), _ptr(ws), ws.numel() * ws.element_size(), ws_flags,
                               ctypes.byref(o), _ptr(m), _ptr(v), t, ctypes.byref(out), _stream(stream)), sys)
     return out.Z, out.E
+
+
+def irl_vmc_sample(sys, ws, u, rows=None, grad=None, stream=None):
+    """u: device float64 tensor of uniforms; rows: optional device int64 tensor of
+    the same length; grad: optional device float64 tensor (P).  Returns irl_vmc_out."""
+    out = irl_vmc_out()
+    _check(_lib.irl_vmc_sample(sys, _ptr(ws), ws.numel() * ws.element_size(), _ptr(u), u.numel(),
+                               _ptr(rows), _ptr(grad), ctypes.byref(out), _stream(stream)), sys)
+    return out
 
 
 def irl_dtilde_set(sys, D, ws, ws_flags, stream=None):

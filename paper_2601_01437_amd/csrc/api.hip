@@ -225,14 +225,20 @@ int apply_internal(irl_system *s, void *ws, const WsLayout &L, const double *v, 
     if (prec == IRL_FP64 && (L.flags & IRL_WS_FACTORED)) {
         // factored Jacobian: forward product, H, both backward products in one pass
         TIMED(s, IRL_STAT_GEMV, st, launch_fac_jvp(s, L, ws, v, zero_v0, w, st));
-        TIMED(s, IRL_STAT_HAM_APPLY, st, launch_ham_apply(s, w, u, st));
+        if (s->vmc)
+            TIMED(s, IRL_STAT_VMC, st, launch_vmc_diag(L, ws, w, u, 1, st));
+        else
+            TIMED(s, IRL_STAT_HAM_APPLY, st, launch_ham_apply(s, w, u, st));
         const int nb = fac_row_blocks(L);
         TIMED(s, IRL_STAT_GEMV_T, st, launch_fac_vjp(s, L, ws, w, u, nullptr, 0, nb, st));
         TIMED(s, IRL_STAT_REDUCE, st, launch_t2_reduce(L, ws, nb, yS, yH, L.ncols, 1.0, nullptr, st));
         return IRL_OK;
     }
     TIMED(s, prec == IRL_FP64 ? IRL_STAT_GEMV : IRL_STAT_GEMV_LO, st, launch_gemv_rows(L, ws, prec, v, w, zero_v0, st));
-    TIMED(s, IRL_STAT_HAM_APPLY, st, launch_ham_apply(s, w, u, st));
+    if (s->vmc)
+        TIMED(s, IRL_STAT_VMC, st, launch_vmc_diag(L, ws, w, u, 1, st));
+    else
+        TIMED(s, IRL_STAT_HAM_APPLY, st, launch_ham_apply(s, w, u, st));
     int nblk = 1;
     TIMED(s, prec == IRL_FP64 ? IRL_STAT_GEMV_T : IRL_STAT_GEMV_T_LO, st, launch_gemv_t2(L, ws, prec, w, u, nullptr, nullptr, &nblk, st));
     TIMED(s, IRL_STAT_REDUCE, st, launch_t2_reduce(L, ws, nblk, yS, yH, L.ncols, 1.0, nullptr, st));
@@ -247,8 +253,12 @@ int apply_block_internal(irl_system *s, void *ws, const WsLayout &L, const doubl
     double *W = ws_ptr<double>(ws, L.off_w), *U = ws_ptr<double>(ws, L.off_u);
     TIMED(s, prec == IRL_FP64 ? IRL_STAT_GEMV : IRL_STAT_GEMV_LO, st,
           launch_gemv_rows_multi(L, ws, prec, V, ldv_in, nb, zero_v0, W, st));
-    for (int q = 0; q < nb; ++q)
-        TIMED(s, IRL_STAT_HAM_APPLY, st, launch_ham_apply(s, W + (int64_t)q * L.ns, U + (int64_t)q * L.ns, st));
+    if (s->vmc) {
+        TIMED(s, IRL_STAT_VMC, st, launch_vmc_diag(L, ws, W, U, nb, st));
+    } else {
+        for (int q = 0; q < nb; ++q)
+            TIMED(s, IRL_STAT_HAM_APPLY, st, launch_ham_apply(s, W + (int64_t)q * L.ns, U + (int64_t)q * L.ns, st));
+    }
     int nblk = 1;
     TIMED(s, prec == IRL_FP64 ? IRL_STAT_GEMV_T : IRL_STAT_GEMV_T_LO, st,
           launch_gemv_t2_multi(L, ws, prec, nb, W, U, &nblk, st));
@@ -310,6 +320,7 @@ WsLayout make_layout(int64_t ns, int64_t ncols, uint32_t flags, int V)
     L.off_hy = take((size_t)ld * 8);
     L.off_fac = take((flags & IRL_WS_FACTORED) ? (size_t)ns * (size_t)L.hfac * 8 : 0);
     L.off_sig = take((size_t)ld * 8);
+    L.off_q = take((size_t)ns * 8);
     L.total = off;
     return L;
 }
@@ -825,6 +836,7 @@ int irl_nqs_evaluate(irl_system *s, const irl_nqs_desc *nqs, void *ws, size_t ws
     int rc = check_ws(s, ws, ws_bytes, L);
     if (rc) return rc;
     s->ws_valid = false;
+    s->vmc = false;
     TIMED(s, IRL_STAT_DTILDE_BUILD, st, launch_nqs_dtilde(s, nqs->V, nqs->H, nqs->theta, L, ws, st));
     rc = energy_and_gradient(s, ws, L, st, nqs);
     if (rc) return rc;
@@ -867,6 +879,58 @@ int irl_adam_step(irl_system *s, const irl_nqs_desc *nqs, void *ws, size_t ws_by
     return IRL_OK;
 }
 
+int irl_vmc_sample(irl_system *s, void *ws, size_t ws_bytes, const double *u, int64_t n_samples,
+                   int64_t *rows, double *grad_out, irl_vmc_out *out, void *stream)
+{
+    if (!s) return IRL_EINVAL;
+    if (!s->ws_valid || s->ws != ws) return set_err(s, IRL_ESTATE, "workspace holds no evaluation for this system");
+    const WsLayout L = s->lay;
+    if (ws_bytes < L.total) return set_err(s, IRL_ENOMEM, "workspace too small");
+    if (!u || n_samples < 1 || n_samples > 0x7fffffffLL)
+        return set_err(s, IRL_EINVAL, "u is NULL or n_samples is outside [1, 2^31 - 1]");
+    if (!s->ws_has64) return set_err(s, IRL_EINVAL, "the sampled gradient needs an FP64 D~ copy or the factored Jacobian");
+    if ((vmc_scan_chunks(L.ns) + 1) * 8 > (int64_t)kStreamBlocks * 2 * L.ldv * 8)
+        return set_err(s, IRL_EINVAL, "determinant set too large for the sampling scan");
+    hipStream_t st = (hipStream_t)stream;
+    if (!s->vmc) s->E_exact = s->E_el;
+    const int k = 61 - std::ilogb(s->Z);
+    double *dout = ws_ptr<double>(ws, L.off_r);
+    s->vmc = false;
+    TIMED(s, IRL_STAT_VMC, st, launch_vmc_sample(L, ws, u, n_samples, k, s->Z, rows, dout, st));
+    // sampled gradient F = (2 / Z) D~^T (q (H psi - E psi)); the right-hand side is in the w region
+    const double *y = ws_ptr<double>(ws, L.off_w);
+    double *grad = ws_ptr<double>(ws, L.off_grad);
+    WsScalars *sc = ws_ptr<WsScalars>(ws, L.off_scal);
+    int nblk = 1;
+    if (L.flags & IRL_WS_FACTORED) {
+        nblk = fac_row_blocks(L);
+        TIMED(s, IRL_STAT_ENERGY, st, launch_fac_vjp(s, L, ws, y, nullptr, nullptr, 1, nblk, st));
+    } else {
+        TIMED(s, IRL_STAT_GEMV_T, st, launch_gemv_t2(L, ws, IRL_FP64, y, y, nullptr, nullptr, &nblk, st));
+    }
+    TIMED(s, IRL_STAT_REDUCE, st, launch_t2_reduce(L, ws, nblk, nullptr, grad, L.ncols, 2.0, &sc->Z, st));
+    if (grad_out) CK(s, hipMemcpyAsync(grad_out, grad + 1, (L.ncols - 1) * 8, hipMemcpyDeviceToDevice, st));
+    double h[3];
+    CK(s, hipMemcpyAsync(h, dout, sizeof(h), hipMemcpyDeviceToHost, st));
+    CK(s, hipStreamSynchronize(st));
+    int rc = stats_fold(s);
+    if (rc) return rc;
+    if (!std::isfinite(h[0])) {
+        s->ws_valid = false;   // the device energy is no longer the evaluated one
+        return set_err(s, IRL_EINVAL, "the sampled energy is not finite");
+    }
+    s->E_el = h[0];
+    s->vmc = true;
+    if (out) {
+        out->E_sampled = h[0] + s->e_core;
+        out->E_exact = s->E_exact + s->e_core;
+        out->E_loc_var = h[2];
+        out->n_unique = (int64_t)h[1];
+        out->n_samples = n_samples;
+    }
+    return IRL_OK;
+}
+
 int irl_dtilde_set(irl_system *s, const void *D, int64_t ld, int64_t ncols, int32_t dtype,
                    void *ws, size_t ws_bytes, uint32_t ws_flags, void *stream)
 {
@@ -880,6 +944,7 @@ int irl_dtilde_set(irl_system *s, const void *D, int64_t ld, int64_t ncols, int3
     int rc = check_ws(s, ws, ws_bytes, L);
     if (rc) return rc;
     s->ws_valid = false;
+    s->vmc = false;
     TIMED(s, IRL_STAT_DTILDE_BUILD, st, launch_dtilde_import(D, ld, ncols, dtype, L, ws, st));
     rc = energy_and_gradient(s, ws, L, st);
     if (rc) return rc;
@@ -944,6 +1009,8 @@ int irl_step(irl_system *s, irl_nqs_desc *nqs, const irl_solver_opts *opts, void
         return set_err(s, IRL_EINVAL, "bad solver options");
     if (o.mode == IRL_MODE_C && (o.precision != IRL_FP64 || o.block > 1))
         return set_err(s, IRL_EINVAL, "the connected basis (mode C) needs an FP64 single-vector solve");
+    if (o.mode == IRL_MODE_C && s->vmc && (o.flags & IRL_STEP_WS_CURRENT))
+        return set_err(s, IRL_EINVAL, "the connected basis (mode C) is not defined on sampled estimators");
     hipStream_t st = (hipStream_t)stream;
     irl_step_result res;
     std::memset(&res, 0, sizeof(res));
@@ -1446,6 +1513,7 @@ int batch_evaluate(irl_batch *b, const std::vector<int> &subset, hipStream_t st)
         s->ws = b->ws[m];
         s->lay = b->lay[m];
         s->ws_valid = true;
+        s->vmc = false;
         s->ws_has64 = (b->ws_flags & IRL_WS_FP64) != 0;
         s->ws_has32 = (b->ws_flags & IRL_WS_FP32) != 0;
         if (!(s->Z > 0.0) || !std::isfinite(s->E_el))

@@ -62,7 +62,8 @@ struct WsLayout {
            off_part = 0, off_part2 = 0, off_red = 0, off_kry0 = 0, off_kry1 = 0, off_vconv = 0,
            off_img0 = 0, off_img1 = 0, off_hy = 0,   // operator images of the basis; of y
            off_fac = 0,                              // factored Jacobian d = 1 - t^2 (N_s x hfac)
-           off_sig = 0;                              // D~^T psi (connected basis, mode C)
+           off_sig = 0,                              // D~^T psi (connected basis, mode C)
+           off_q = 0;                                // sampled row weights Z c_r / (N psi_r^2)
     int hfac = 0;                                    // hidden units of the factored Jacobian
     size_t total = 0;
 };
@@ -196,6 +197,9 @@ struct irl_system {
     bool ws_valid = false;
     bool ws_has64 = false, ws_has32 = false;
     double Z = 0.0, E_el = 0.0;   // host copies after the last evaluation
+    // sampled estimators (irl_vmc_sample) replace the exact ones until the next evaluation
+    bool vmc = false;
+    double E_exact = 0.0;
     // pinned host staging for small readbacks
     irl::WsScalars *host_scal = nullptr;
     // dense BLAS handle (rocblas_handle) for the same-spin doubles of a full space
@@ -319,6 +323,12 @@ hipError_t launch_ritz_vector(const WsLayout &L, void *ws, const double *V, cons
 hipError_t launch_residual_image(const WsLayout &L, void *ws, const double *y, const double *hy, double *r,
                                  int mode, hipStream_t st);
 hipError_t launch_connected_c0(const WsLayout &L, void *ws, const double *y, hipStream_t st);
+
+// vmc.hip
+int64_t vmc_scan_chunks(int64_t ns);
+hipError_t launch_vmc_sample(const WsLayout &L, void *ws, const double *u, int64_t nsamp, int k, double Z,
+                             int64_t *rows, double *out, hipStream_t st);
+hipError_t launch_vmc_diag(const WsLayout &L, void *ws, double *w, double *u, int nb, hipStream_t st);
 hipError_t launch_update(const WsLayout &L, void *ws, const double *y, double *dtheta,
                          double *theta, int64_t P, int mode, hipStream_t st);
 hipError_t launch_copy(double *dst, const double *src, int64_t n, hipStream_t st);

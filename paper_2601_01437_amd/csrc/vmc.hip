@@ -1,0 +1,322 @@
+// Sampled (variational Monte Carlo) estimators on the determinant set.
+//
+// Sampling (Methods, "Autoregressive Modeling and Physical Constraints", Eqs.
+// autoregressive_factorization and constraint): exact draws from |psi|^2 / Z
+// restricted to the fixed-(N_up, N_down) set.  Drawing the spin-orbitals one at
+// a time from exact conditionals with one uniform number per sample is the
+// inverse transform of the cumulative distribution in ascending key order, so
+// the kernels scan |psi|^2 once and binary-search each sample.  The scan runs
+// in 64-bit fixed point (psi^2 * 2^k rounded, k chosen so the total stays below
+// 2^62): integer sums are exact, so the distribution is monotone and identical
+// for any launch shape, and a determinant with psi = 0 is never drawn.
+//
+// Estimators (Methods, "From SR to a Stable Eigenvalue Problem", Eq.
+// centered_hamiltonian; "Practical Matrix-Free Implementation", Eq.
+// matrix_vec_prod): with c_r draws of row r out of N, O(x) = D~[x, :] / psi(x)
+// and E_loc(x) = (H psi)(x) / psi(x), every sample mean over the draws is a
+// weighted sum over rows with q_r = Z c_r / (N psi_r^2):
+//   E = (1/N) sum_r c_r E_loc,r
+//   F = (2/Z) D~^T (q (H psi - E psi))
+//   (y_H, y_S) = (D~^T (q E_loc w), D~^T (q w)),  w = D~ v,
+// so that (y_H - E y_S) / Z is the sample mean of O (E_loc - E) (O . v).
+
+#include "internal.h"
+
+namespace irl {
+
+namespace {
+
+constexpr int kScanThreads = 1024;
+constexpr int kScanWaves = kScanThreads / kWave;
+constexpr int kScanPer = 8;                          // consecutive rows per thread
+constexpr int64_t kScanChunk = (int64_t)kScanThreads * kScanPer;
+constexpr int kVmcThreads = 256;
+constexpr int kVmcBlocks = 1024;                     // row blocks of the weight passes
+
+__device__ __forceinline__ uint64_t fixed_weight(double p, int k)
+{
+    return (uint64_t)rint(ldexp(p * p, k));
+}
+
+// fixed-point weights of this thread's rows and their sum
+__device__ __forceinline__ uint64_t thread_weights(const double *__restrict__ psi, int64_t ns, int64_t base,
+                                                   int k, uint64_t *w)
+{
+    uint64_t s = 0;
+#pragma unroll
+    for (int e = 0; e < kScanPer; ++e) {
+        const int64_t i = base + e;
+        w[e] = i < ns ? fixed_weight(psi[i], k) : 0ull;
+        s += w[e];
+    }
+    return s;
+}
+
+// exclusive prefix of v over the block's threads and the block total (integer: exact)
+__device__ uint64_t block_exclusive(uint64_t v, uint64_t *sh, uint64_t *total)
+{
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+    uint64_t x = v;
+    for (int off = 1; off < kWave; off <<= 1) {
+        const uint64_t y = __shfl_up(x, off, kWave);
+        if (lane >= off) x += y;
+    }
+    if (lane == kWave - 1) sh[wv] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t acc = 0;
+        for (int i = 0; i < kScanWaves; ++i) {
+            const uint64_t t = sh[i];
+            sh[i] = acc;
+            acc += t;
+        }
+        sh[kScanWaves] = acc;
+    }
+    __syncthreads();
+    *total = sh[kScanWaves];
+    return sh[wv] + (x - v);
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_chunks(const double *__restrict__ psi, int64_t ns, int k,
+                                                             uint64_t *__restrict__ tot)
+{
+    __shared__ uint64_t sh[kScanWaves + 1];
+    uint64_t w[kScanPer];
+    const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanPer;
+    uint64_t total;
+    block_exclusive(thread_weights(psi, ns, base, k, w), sh, &total);
+    if (threadIdx.x == 0) tot[blockIdx.x] = total;
+}
+
+// exclusive offsets of the chunk totals, in place; the grand total into tot[nc]
+__global__ __launch_bounds__(kScanThreads) void k_scan_offsets(uint64_t *__restrict__ tot, int64_t nc)
+{
+    __shared__ uint64_t sh[kScanWaves + 1];
+    uint64_t carry = 0;
+    for (int64_t b = 0; b < nc; b += kScanThreads) {
+        const int64_t i = b + threadIdx.x;
+        const uint64_t v = i < nc ? tot[i] : 0ull;
+        uint64_t seg;
+        const uint64_t ex = block_exclusive(v, sh, &seg);
+        if (i < nc) tot[i] = carry + ex;
+        carry += seg;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) tot[nc] = carry;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_apply(const double *__restrict__ psi, int64_t ns, int k,
+                                                            const uint64_t *__restrict__ off,
+                                                            uint64_t *__restrict__ cum)
+{
+    __shared__ uint64_t sh[kScanWaves + 1];
+    uint64_t w[kScanPer];
+    const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanPer;
+    uint64_t total;
+    uint64_t acc = off[blockIdx.x] + block_exclusive(thread_weights(psi, ns, base, k, w), sh, &total);
+#pragma unroll
+    for (int e = 0; e < kScanPer; ++e) {
+        acc += w[e];
+        if (base + e < ns) cum[base + e] = acc;
+    }
+}
+
+// sample s: the first row whose cumulative weight exceeds floor(u_s T); u outside
+// [0, 1) (or NaN) is clamped into it
+__global__ __launch_bounds__(kVmcThreads) void k_vmc_draw(const double *__restrict__ u, int64_t nsamp,
+                                                         const uint64_t *__restrict__ cum, int64_t ns,
+                                                         const uint64_t *__restrict__ totp,
+                                                         uint32_t *__restrict__ counts, int64_t *__restrict__ rows)
+{
+    const int64_t s = (int64_t)blockIdx.x * kVmcThreads + threadIdx.x;
+    if (s >= nsamp) return;
+    const uint64_t T = *totp;
+    const double x = u[s] * (double)T;
+    uint64_t t = 0;
+    if (x > 0.0) t = x < (double)T ? (uint64_t)x : T - 1;
+    if (t >= T) t = T - 1;
+    int64_t lo = 0, hi = ns - 1;
+    while (lo < hi) {
+        const int64_t mid = lo + ((hi - lo) >> 1);
+        if (cum[mid] > t)
+            hi = mid;
+        else
+            lo = mid + 1;
+    }
+    atomicAdd(&counts[lo], 1u);
+    if (rows) rows[s] = lo;
+}
+
+__global__ void k_fill_u32(uint32_t *p, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+
+// fixed-order sum over a 256-thread block; result valid in thread 0
+__device__ double block_sum256(double v, double *sh)
+{
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, kWave);
+    if (lane == 0) sh[wv] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < kVmcThreads / kWave; ++i) s += sh[i];
+    __syncthreads();
+    return s;
+}
+
+// q_r = Z c_r / (N psi_r^2); per-block sums of c_r E_loc,r and of the distinct rows
+__global__ __launch_bounds__(kVmcThreads) void k_vmc_weights(const uint32_t *__restrict__ counts,
+                                                            const double *__restrict__ psi,
+                                                            const double *__restrict__ hpsi, int64_t ns,
+                                                            double zn, double *__restrict__ q,
+                                                            double *__restrict__ part)
+{
+    __shared__ double sh[kVmcThreads / kWave];
+    double se = 0.0, su = 0.0;
+    for (int64_t r = (int64_t)blockIdx.x * kVmcThreads + threadIdx.x; r < ns;
+         r += (int64_t)gridDim.x * kVmcThreads) {
+        const uint32_t c = counts[r];
+        double qr = 0.0;
+        if (c) {
+            const double p = psi[r];
+            qr = zn * (double)c / (p * p);
+            se += (double)c * (hpsi[r] / p);
+            su += 1.0;
+        }
+        q[r] = qr;
+    }
+    const double a = block_sum256(se, sh);
+    const double b = block_sum256(su, sh);
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = a;
+        part[2 * blockIdx.x + 1] = b;
+    }
+}
+
+// E = sum / N into sc->E_el and out[0]; distinct rows into out[1]
+__global__ __launch_bounds__(kWave) void k_vmc_energy(const double *__restrict__ part, int nblk, double inv_n,
+                                                     WsScalars *sc, double *out)
+{
+    if (threadIdx.x != 0) return;
+    double e = 0.0, un = 0.0;
+    for (int b = 0; b < nblk; ++b) {
+        e += part[2 * b];
+        un += part[2 * b + 1];
+    }
+    sc->E_el = e * inv_n;
+    out[0] = e * inv_n;
+    out[1] = un;
+}
+
+// right-hand side of the sampled gradient, y_r = q_r (H psi - E psi)_r, and
+// per-block sums of c_r (E_loc,r - E)^2
+__global__ __launch_bounds__(kVmcThreads) void k_vmc_rhs(const uint32_t *__restrict__ counts,
+                                                        const double *__restrict__ psi,
+                                                        const double *__restrict__ hpsi,
+                                                        const double *__restrict__ q, int64_t ns,
+                                                        const WsScalars *sc, double *__restrict__ y,
+                                                        double *__restrict__ part)
+{
+    __shared__ double sh[kVmcThreads / kWave];
+    const double E = sc->E_el;
+    double sv = 0.0;
+    for (int64_t r = (int64_t)blockIdx.x * kVmcThreads + threadIdx.x; r < ns;
+         r += (int64_t)gridDim.x * kVmcThreads) {
+        const double qr = q[r];
+        double yr = 0.0;
+        if (qr != 0.0) {
+            const double p = psi[r], h = hpsi[r];
+            yr = qr * (h - E * p);
+            const double d = h / p - E;
+            sv += (double)counts[r] * d * d;
+        }
+        y[r] = yr;
+    }
+    const double a = block_sum256(sv, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = a;
+}
+
+__global__ __launch_bounds__(kWave) void k_vmc_variance(const double *__restrict__ part, int nblk, double inv_n,
+                                                       double *out)
+{
+    if (threadIdx.x != 0) return;
+    double v = 0.0;
+    for (int b = 0; b < nblk; ++b) v += part[b];
+    out[2] = v * inv_n;
+}
+
+// the sampled operator's diagonal: w <- q w, u <- q E_loc w (nb columns of ns)
+__global__ __launch_bounds__(kVmcThreads) void k_vmc_diag(const double *__restrict__ q,
+                                                         const double *__restrict__ psi,
+                                                         const double *__restrict__ hpsi, int64_t ns, int nb,
+                                                         double *__restrict__ w, double *__restrict__ u)
+{
+    for (int64_t r = (int64_t)blockIdx.x * kVmcThreads + threadIdx.x; r < ns;
+         r += (int64_t)gridDim.x * kVmcThreads) {
+        const double qr = q[r];
+        const double el = qr != 0.0 ? hpsi[r] / psi[r] : 0.0;
+        for (int c = 0; c < nb; ++c) {
+            const double x = qr * w[(int64_t)c * ns + r];
+            w[(int64_t)c * ns + r] = x;
+            u[(int64_t)c * ns + r] = x * el;
+        }
+    }
+}
+
+unsigned row_blocks(int64_t ns)
+{
+    const int64_t b = (ns + kVmcThreads - 1) / kVmcThreads;
+    return (unsigned)(b < kVmcBlocks ? (b > 0 ? b : 1) : kVmcBlocks);
+}
+
+}  // namespace
+
+int64_t vmc_scan_chunks(int64_t ns)
+{
+    return (ns + kScanChunk - 1) / kScanChunk;
+}
+
+int vmc_weight_blocks(int64_t ns)
+{
+    return (int)row_blocks(ns);
+}
+
+hipError_t launch_vmc_sample(const WsLayout &L, void *ws, const double *u, int64_t nsamp, int k, double Z,
+                             int64_t *rows, double *out, hipStream_t st)
+{
+    const int64_t ns = L.ns;
+    const double *psi = ws_ptr<double>(ws, L.off_psi), *hpsi = ws_ptr<double>(ws, L.off_hpsi);
+    uint64_t *cum = ws_ptr<uint64_t>(ws, L.off_w);
+    uint32_t *counts = ws_ptr<uint32_t>(ws, L.off_u);
+    uint64_t *tot = ws_ptr<uint64_t>(ws, L.off_part);
+    double *part = ws_ptr<double>(ws, L.off_red);
+    double *q = ws_ptr<double>(ws, L.off_q);
+    double *y = ws_ptr<double>(ws, L.off_w);       // after the draws the scan is no longer needed
+    WsScalars *sc = ws_ptr<WsScalars>(ws, L.off_scal);
+    const int64_t nc = vmc_scan_chunks(ns);
+    const unsigned nb = row_blocks(ns);
+    k_scan_chunks<<<(unsigned)nc, kScanThreads, 0, st>>>(psi, ns, k, tot);
+    k_scan_offsets<<<1, kScanThreads, 0, st>>>(tot, nc);
+    k_scan_apply<<<(unsigned)nc, kScanThreads, 0, st>>>(psi, ns, k, tot, cum);
+    k_fill_u32<<<nb, kVmcThreads, 0, st>>>(counts, ns);
+    k_vmc_draw<<<(unsigned)((nsamp + kVmcThreads - 1) / kVmcThreads), kVmcThreads, 0, st>>>(
+        u, nsamp, cum, ns, tot + nc, counts, rows);
+    const double inv_n = 1.0 / (double)nsamp;
+    k_vmc_weights<<<nb, kVmcThreads, 0, st>>>(counts, psi, hpsi, ns, Z * inv_n, q, part);
+    k_vmc_energy<<<1, kWave, 0, st>>>(part, (int)nb, inv_n, sc, out);
+    k_vmc_rhs<<<nb, kVmcThreads, 0, st>>>(counts, psi, hpsi, q, ns, sc, y, part);
+    k_vmc_variance<<<1, kWave, 0, st>>>(part, (int)nb, inv_n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_vmc_diag(const WsLayout &L, void *ws, double *w, double *u, int nb, hipStream_t st)
+{
+    k_vmc_diag<<<row_blocks(L.ns), kVmcThreads, 0, st>>>(ws_ptr<double>(ws, L.off_q), ws_ptr<double>(ws, L.off_psi),
+                                                         ws_ptr<double>(ws, L.off_hpsi), L.ns, nb, w, u);
+    return hipGetLastError();
+}
+
+}  // namespace irl

@@ -83,6 +83,14 @@ class System:
         self.workspace(P + 1, ws_flags)
         return B.irl_adam_step(self.handle, V, H, theta, self.ws, ws_flags, m, v, t, grad=grad, **opts)
 
+    def vmc_sample(self, u, want_rows=False, want_grad=False):
+        """Draw len(u) samples (u: device float64 uniforms) and switch the workspace
+        to the sampled estimators; returns (irl_vmc_out, rows or None, F or None)."""
+        rows = torch.empty(u.numel(), dtype=torch.int64, device=self.device) if want_rows else None
+        grad = torch.empty(self.ncols - 1, dtype=torch.float64, device=self.device) if want_grad else None
+        out = B.irl_vmc_sample(self.handle, self.ws, u, rows=rows, grad=grad)
+        return out, rows, grad
+
     def set_dtilde(self, D, ws_flags=B.IRL_WS_FP64):
         ws = self.workspace(D.shape[1], ws_flags)
         B.irl_dtilde_set(self.handle, D, ws, ws_flags)

@@ -42,7 +42,7 @@ def _c_sizes():
     import subprocess
     import tempfile
     names = ["irl_system_desc", "irl_system_info", "irl_nqs_desc", "irl_eval_out",
-             "irl_solver_opts", "irl_step_result", "irl_adam_opts"]
+             "irl_solver_opts", "irl_step_result", "irl_adam_opts", "irl_vmc_out"]
     body = "".join(f'printf("%zu\\n", sizeof({n}));' for n in names)
     src = f'#include <stdio.h>\n#include "irlnqs.h"\nint main(void){{{body}return 0;}}\n'
     with tempfile.TemporaryDirectory() as d:
