@@ -452,8 +452,9 @@ def run_serving_bench(args):
 def run_ablation_bench(args):
     """Optimiser comparison (the shape of the paper's Fig. 2c): from the same theta_0
     on one workload, implicitly restarted Lanczos (IRL, m = 20, k = 1 by default), IRL
-    in the connected tangent basis (mode C), standard Lanczos (SL: one m = 20 Lanczos
-    process per step, no restart, Algorithm 2) and Adam (two step sizes).  E* is the energy where IRL's lowest eigenvalue reaches
+    in the connected tangent basis (mode C), IRL on the sampled (VMC) estimators,
+    standard Lanczos (SL: one m = 20 Lanczos process per step, no restart, Algorithm
+    2) and Adam (two step sizes).  E* is the energy where IRL's lowest eigenvalue reaches
     |lambda| <= 1e-12 (a stationary point of this network); each method reports the
     steps and seconds to E - E* <= 1e-3, 1e-6, 1e-9 and 1e-12 Ha, within its step
     and time caps (if IRL does not reach |lambda| <= 1e-12 within its cap, E* is the
@@ -497,6 +498,37 @@ def run_ablation_bench(args):
                     steps_not_converged=not_conv, last_lambda=lams[-1] if lams else None)
         return np.array(Es), np.array(ts), lams
 
+    def vmc_run(m, k, nsamp, cap, tcap, info):
+        """IRL on the sampled estimators: each step draws nsamp configurations from
+        |psi|^2 at the current theta (fresh seeded uniforms) and solves the sampled
+        centred matrix; the recorded energies are the exact ones on the set."""
+        th = theta0.clone()
+        rng = np.random.default_rng(wl.seed + 1)
+        Es, ts, lams = [], [], []
+        applies = not_conv = 0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for it in range(cap):
+            u = torch.tensor(rng.random(nsamp), dtype=torch.float64, device="cuda")
+            sysm.evaluate(wl.V, wl.H, th, ws_flags=fl, want_grad=False)
+            out, _, _ = sysm.vmc_sample(u)
+            rc, r, _, _ = sysm.step(th, wl.V, wl.H, m=m, k_keep=k, tol=1e-12, max_restarts=300,
+                                    flags=B.IRL_STEP_WS_CURRENT, ws_flags=fl, want_dtheta=False)
+            torch.cuda.synchronize()
+            if not Es:
+                Es.append(out.E_exact)
+                ts.append(0.0)
+            Es.append(r.E_after if np.isfinite(r.E_after) else Es[-1])
+            ts.append(time.perf_counter() - t0)
+            lams.append(r.lambda_min)
+            applies += r.n_apply
+            not_conv += rc == B.IRL_ENOTCONV
+            if rc == B.IRL_ESTEP or ts[-1] > tcap:
+                break
+        info.update(applies_per_step=applies / max(1, len(lams)), steps_not_converged=not_conv,
+                    last_lambda=lams[-1] if lams else None, samples_per_step=nsamp)
+        return np.array(Es), np.array(ts), lams
+
     def adam_run(lr, cap, tcap):
         th = theta0.clone()
         m = torch.zeros(wl.P, dtype=torch.float64, device="cuda")
@@ -529,6 +561,13 @@ def run_ablation_bench(args):
                                   mode=B.IRL_MODE_C)
     log(f"IRL mode C: {len(E_c) - 1} steps, E {E_c[-1]:.12f}, lambda {lam_c[-1]:.2e}, {info[conn_name]}")
     runs[conn_name] = (E_c, t_c)
+    if args.ablation_vmc_samples > 0:
+        vmc_name = f"IRL sampled estimators (VMC, {args.ablation_vmc_samples} draws, m={mk[0]}, k={mk[1]})"
+        info[vmc_name] = {}
+        E_v, t_v, lam_v = vmc_run(mk[0], mk[1], args.ablation_vmc_samples, args.irl_steps, args.irl_seconds,
+                                  info[vmc_name])
+        log(f"IRL VMC: {len(E_v) - 1} steps, E {E_v[-1]:.12f}, lambda {lam_v[-1]:.2e}, {info[vmc_name]}")
+        runs[vmc_name] = (E_v, t_v)
     for lr in args.adam_lr:
         E_a, t_a = adam_run(lr, args.adam_steps, args.adam_seconds)
         runs[f"Adam (lr={lr:g})"] = (E_a, t_a)
@@ -569,12 +608,157 @@ def run_ablation_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def vmc_cpu_baseline(wl, nsamp, applies_per_step, sample_draws=40, sample_rows=16384):
+    """The oracle's sampled step on the host, timed on bounded parts and scaled:
+    orbital-by-orbital draws (sample_draws of them), network rows, local energies
+    (oracle C Slater-Condon rows) and the sample-mean product of Eq.
+    matrix_vec_prod on sample_rows rows, scaled to nsamp draws and one product per
+    operator apply."""
+    import numpy as np
+
+    from oracle import capply, nqs, space, vmc
+    keys = wl.dets()
+    if keys is None:
+        keys = space.full_space(wl.n, wl.na, wl.nb)
+    h, g = wl.integrals()
+    theta = wl.theta()
+    rng = np.random.default_rng(0)
+    ns = keys.size
+    psi_all = rng.normal(size=ns)            # draw cost does not depend on the values
+    t = time.perf_counter()
+    vmc.sample_autoregressive(keys, wl.n, wl.na, wl.nb, psi_all, rng.random(sample_draws))
+    t_draw = (time.perf_counter() - t) / sample_draws
+    rows = np.sort(rng.choice(ns, size=min(sample_rows, ns), replace=False))
+    t = time.perf_counter()
+    D = nqs.dtilde(keys[rows], wl.n, wl.V, wl.H, theta)
+    t_rows = time.perf_counter() - t
+    t = time.perf_counter()
+    hpsi = capply.apply(wl.n, h, g, keys, psi_all, rows=rows)
+    t_eloc = time.perf_counter() - t
+    O = vmc.log_derivatives(D)
+    Eloc = hpsi / D[:, 0]
+    v = rng.normal(size=wl.P + 1)
+    r = np.arange(rows.size)
+    t = time.perf_counter()
+    vmc.sampled_mvp(r, O, Eloc, v)
+    t_mvp = time.perf_counter() - t
+    scale = nsamp / rows.size
+    per_step = nsamp * t_draw + (t_rows + t_eloc) * scale + applies_per_step * t_mvp * scale
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {
+        "value": 1.0 / per_step, "unit": "sampled IRL steps/s", "cores": cores, "kind": "oracle",
+        "sample": (f"{sample_draws} orbital-by-orbital draws over {ns} determinants "
+                   f"({t_draw * 1e3:.1f} ms each) and {rows.size} rows of network values, local "
+                   f"energies and the Eq. matrix_vec_prod product, scaled to {nsamp} draws and "
+                   f"{applies_per_step:.1f} products per step (apply count from the GPU run)"),
+        "ms_per_step": per_step * 1e3, "ms_per_draw": t_draw * 1e3,
+    }
+
+
+def run_vmc_bench(args):
+    """Sampled VMC step (Eq. matrix_vec_prod estimator) on one workload: each step
+    evaluates psi, d and H psi at theta on the set, draws N configurations from
+    |psi|^2 (irl_vmc_sample; uniforms from a seeded host generator, in HBM before
+    the timed region), and runs one IRL solve on the sampled centred matrix with
+    the update.  Reports sampled steps/s, draws/s and per-kernel rooflines."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2601_01437_amd import binding as B
+    from paper_2601_01437_amd import System
+
+    wl = synth.WORKLOADS[args.vmc_workload]
+    h, g = wl.integrals()
+    sysm = System(wl.n, wl.na, wl.nb, h, g, dets=wl.dets())
+    ns = sysm.ns
+    ws_flags = B.IRL_WS_FACTORED
+    theta0 = torch.tensor(wl.theta(), dtype=torch.float64, device="cuda")
+    theta = theta0.clone()
+    N = args.vmc_samples
+    rng = np.random.default_rng(wl.seed)
+    U = torch.tensor(rng.random((args.warmup + args.steps, N)), dtype=torch.float64, device="cuda")
+    log(f"vmc on {wl.name}: {ns} determinants, P={wl.P}, {N} draws per step, m={wl.m} k={wl.k}")
+
+    def one_step(i):
+        sysm.evaluate(wl.V, wl.H, theta, ws_flags=ws_flags, want_grad=False)
+        out, _, _ = sysm.vmc_sample(U[i])
+        rc, r, _, _ = sysm.step(theta, wl.V, wl.H, m=wl.m, k_keep=wl.k, tol=1e-12, ws_flags=ws_flags,
+                                flags=B.IRL_STEP_WS_CURRENT | B.IRL_STEP_NO_EVAL_AFTER, want_dtheta=False)
+        return out, rc, r
+
+    for i in range(args.warmup):
+        out, rc, r = one_step(i)
+        log(f"warmup {i}: E_sampled={out.E_sampled:.10f} E={out.E_exact:.10f} unique={out.n_unique} "
+            f"lambda={r.lambda_min:.3e} applies={r.n_apply}")
+    theta.copy_(theta0)
+    torch.cuda.synchronize()
+    B.irl_stats_enable(sysm.handle, True)
+    steps = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        out, rc, r = one_step(args.warmup + i)
+        steps.append({"E_sampled": out.E_sampled, "E": out.E_exact, "E_loc_var": out.E_loc_var,
+                      "unique": out.n_unique, "lambda_min": r.lambda_min, "applies": r.n_apply,
+                      "converged": r.converged})
+        log(f"step {i}: E_sampled={out.E_sampled:.10f} E={out.E_exact:.10f} unique={out.n_unique} "
+            f"lambda={r.lambda_min:.3e} applies={r.n_apply}")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    stats = B.irl_stats_get(sysm.handle)
+    B.irl_stats_enable(sysm.handle, False)
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    kern = {k: {"ms_total": v[0], "launches": v[1], "ms_avg": v[0] / v[1] if v[1] else None}
+            for k, v in stats.items() if v[1]}
+    rooflines = {}
+    for k, v in kern.items():
+        spec = kernel_roofline(k, ns, wl.P + 1, wl.H, True, 0, sysm.info, 0)
+        if spec is None:
+            continue
+        name, bound, work, unit, peak, src = spec
+        scale = 1e9 if unit == "GB/s" else 1e12
+        achieved = work / (v["ms_avg"] * 1e-3) / scale
+        src_hash = source_hash([os.path.join(CSRC, f) for f in src])
+        rooflines[name] = {"kernel": name, "bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
+                           "frac": achieved / peak, "traffic": None,
+                           ("bytes_per_launch" if unit == "GB/s" else "flops_per_launch"): work,
+                           "ms_avg": v["ms_avg"], "ms_total": v["ms_total"], "launches": v["launches"],
+                           "source_hash": src_hash}
+    roof = max(rooflines.values(), key=lambda r: r["ms_total"]) if rooflines else None
+    applies = sum(st["applies"] for st in steps) / len(steps)
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle sampled step, bounded sample)")
+        cpu = vmc_cpu_baseline(wl, N, applies)
+    out = {
+        "metric": "sampled VMC IRL steps/s", "value": args.steps / (t1 - t0), "unit": "steps/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": (f"sampled VMC step on {wl.name}: {wl.n} orbitals {wl.na}a+{wl.nb}b, "
+                                f"{ns} determinants, V={wl.V} H={wl.H} (P={wl.P}), {N} draws per step, "
+                                f"IRL m={wl.m} k={wl.k} tol=1e-12 on the sampled centred matrix, "
+                                f"factored Jacobian, exact evaluation of psi and H psi on the set")},
+        "draws_per_s": N * args.steps / (t1 - t0),
+        "roofline": {k: v for k, v in roof.items()} if roof else None,
+        "rooflines": rooflines,
+        "kernels": kern,
+        "steps_detail": steps,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c3s", "c4", "c5", "ablation"])
+    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c3s", "c4", "c5", "ablation", "vmc"])
+    ap.add_argument("--vmc-workload", default="c2", choices=["c1", "c2", "c3s"],
+                    help="vmc: workload of the sampled step")
+    ap.add_argument("--vmc-samples", type=int, default=1 << 17, help="vmc: draws per step")
     ap.add_argument("--ablation-workload", default="c1", choices=["c1", "c2", "c3s"],
                     help="ablation: workload of the optimiser comparison")
     ap.add_argument("--adam-lr", type=float, nargs="+", default=[1e-3, 1e-2], help="ablation: Adam step sizes")
@@ -583,6 +767,8 @@ def main():
     ap.add_argument("--sl-steps", type=int, default=400, help="ablation: standard Lanczos step cap")
     ap.add_argument("--irl-steps", type=int, default=400, help="ablation: IRL step cap")
     ap.add_argument("--irl-seconds", type=float, default=60.0, help="ablation: IRL and SL time cap")
+    ap.add_argument("--ablation-vmc-samples", type=int, default=4096,
+                    help="ablation: draws per step of the sampled-estimator IRL run (0: skip it)")
     ap.add_argument("--ablation-irl", type=int, nargs=2, default=[20, 1], metavar=("M", "K"),
                     help="ablation: IRL Krylov dimension and vectors kept per restart")
     ap.add_argument("--serve-seconds", type=float, default=20.0,
@@ -642,6 +828,9 @@ def main():
         return
     if args.config == "ablation":
         run_ablation_bench(args)
+        return
+    if args.config == "vmc":
+        run_vmc_bench(args)
         return
     wl = synth.WORKLOADS[args.config]
     h, g = wl.integrals()
