@@ -508,12 +508,13 @@ def run_ablation_bench(args):
         applies = not_conv = 0
         torch.cuda.synchronize()
         t0 = time.perf_counter()
+        flv = fl | B.IRL_WS_SAMPLED
         for it in range(cap):
             u = torch.tensor(rng.random(nsamp), dtype=torch.float64, device="cuda")
-            sysm.evaluate(wl.V, wl.H, th, ws_flags=fl, want_grad=False)
+            sysm.evaluate(wl.V, wl.H, th, ws_flags=flv, want_grad=False)
             out, _, _ = sysm.vmc_sample(u)
             rc, r, _, _ = sysm.step(th, wl.V, wl.H, m=m, k_keep=k, tol=1e-12, max_restarts=300,
-                                    flags=B.IRL_STEP_WS_CURRENT, ws_flags=fl, want_dtheta=False)
+                                    flags=B.IRL_STEP_WS_CURRENT, ws_flags=flv, want_dtheta=False)
             torch.cuda.synchronize()
             if not Es:
                 Es.append(out.E_exact)
@@ -672,7 +673,8 @@ def run_vmc_bench(args):
     h, g = wl.integrals()
     sysm = System(wl.n, wl.na, wl.nb, h, g, dets=wl.dets())
     ns = sysm.ns
-    ws_flags = B.IRL_WS_FACTORED
+    gathered = not args.vmc_all_rows
+    ws_flags = B.IRL_WS_FACTORED | (B.IRL_WS_SAMPLED if gathered else 0)
     theta0 = torch.tensor(wl.theta(), dtype=torch.float64, device="cuda")
     theta = theta0.clone()
     N = args.vmc_samples
@@ -712,8 +714,11 @@ def run_vmc_bench(args):
     kern = {k: {"ms_total": v[0], "launches": v[1], "ms_avg": v[0] / v[1] if v[1] else None}
             for k, v in stats.items() if v[1]}
     rooflines = {}
+    mean_unique = sum(st["unique"] for st in steps) / len(steps)
     for k, v in kern.items():
-        spec = kernel_roofline(k, ns, wl.P + 1, wl.H, True, 0, sysm.info, 0)
+        # the operator's products run over the drawn rows only when they are gathered
+        rows = mean_unique if gathered and k in ("gemv", "gemv_t") else ns
+        spec = kernel_roofline(k, rows, wl.P + 1, wl.H, True, 0, sysm.info, 0)
         if spec is None:
             continue
         name, bound, work, unit, peak, src = spec
@@ -739,7 +744,10 @@ def run_vmc_bench(args):
         "config": {"workload": (f"sampled VMC step on {wl.name}: {wl.n} orbitals {wl.na}a+{wl.nb}b, "
                                 f"{ns} determinants, V={wl.V} H={wl.H} (P={wl.P}), {N} draws per step, "
                                 f"IRL m={wl.m} k={wl.k} tol=1e-12 on the sampled centred matrix, "
-                                f"factored Jacobian, exact evaluation of psi and H psi on the set")},
+                                f"factored Jacobian, exact evaluation of psi and H psi on the set, "
+                                f"operator products over "
+                                f"{'the gathered drawn rows' if gathered else 'every row'}"),
+                   "mean_unique_rows": mean_unique},
         "draws_per_s": N * args.steps / (t1 - t0),
         "roofline": {k: v for k, v in roof.items()} if roof else None,
         "rooflines": rooflines,
@@ -759,6 +767,9 @@ def main():
     ap.add_argument("--vmc-workload", default="c2", choices=["c1", "c2", "c3s"],
                     help="vmc: workload of the sampled step")
     ap.add_argument("--vmc-samples", type=int, default=1 << 17, help="vmc: draws per step")
+    ap.add_argument("--vmc-all-rows", action="store_true",
+                    help="vmc: run the sampled operator's products over every row (zero weights "
+                         "outside the draws) instead of the gathered drawn rows")
     ap.add_argument("--ablation-workload", default="c1", choices=["c1", "c2", "c3s"],
                     help="ablation: workload of the optimiser comparison")
     ap.add_argument("--adam-lr", type=float, nargs="+", default=[1e-3, 1e-2], help="ablation: Adam step sizes")

@@ -87,13 +87,18 @@ enum irl_ws_flags {
     IRL_WS_BLOCK = 4u,  /* room for multi-vector applies and block solves of up to 8
                            vectors (8 vectors of n_dets for w and u, 8 of P+1 for the
                            outputs and larger reduction partials) */
-    IRL_WS_FACTORED = 8u  /* keep the Jacobian of the one-hidden-layer network in
+    IRL_WS_FACTORED = 8u,  /* keep the Jacobian of the one-hidden-layer network in
                            factored form (psi, d = 1 - t^2 of n_dets x H, and the
                            occupations) instead of, or beside, the D~ copies: IRL_FP64
                            applies and the gradient then use the network's forward and
                            backward products, about 8 H bytes per determinant instead
                            of 8 (P + 1).  Needs irl_nqs_evaluate (not irl_dtilde_set)
                            and V <= 64. */
+    IRL_WS_SAMPLED = 16u  /* with IRL_WS_FACTORED: room to gather the rows drawn by
+                           irl_vmc_sample contiguously (keys, psi, weights, local
+                           energies and d rows: about 8 (H + 5) bytes per
+                           determinant), so the sampled operator's products run
+                           over the drawn rows only */
 };
 
 /* irl_step flags */

@@ -25,7 +25,7 @@ IRL_OK, IRL_ENOTCONV, IRL_ESTEP = 0, 1, 2
 IRL_EINVAL, IRL_ENOMEM, IRL_EDEVICE, IRL_ESTATE = -1, -2, -3, -4
 IRL_FP64, IRL_FP32 = 0, 1
 IRL_MODE_A, IRL_MODE_P, IRL_MODE_C = 0, 1, 2
-IRL_WS_FP64, IRL_WS_FP32, IRL_WS_BLOCK, IRL_WS_FACTORED = 1, 2, 4, 8
+IRL_WS_FP64, IRL_WS_FP32, IRL_WS_BLOCK, IRL_WS_FACTORED, IRL_WS_SAMPLED = 1, 2, 4, 8, 16
 IRL_STEP_WS_CURRENT, IRL_STEP_NO_EVAL_AFTER, IRL_STEP_NO_UPDATE, IRL_STEP_NO_POLISH = 1, 2, 4, 8
 IRL_STEP_FULL_CYCLES = 16
 IRL_SYS_FORCE_HASH = 1

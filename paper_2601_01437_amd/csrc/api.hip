@@ -222,6 +222,17 @@ int apply_internal(irl_system *s, void *ws, const WsLayout &L, const double *v, 
                    double *yS, int prec, hipStream_t st, int zero_v0 = 0)
 {
     double *w = ws_ptr<double>(ws, L.off_w), *u = ws_ptr<double>(ws, L.off_u);
+    if (prec == IRL_FP64 && (L.flags & IRL_WS_FACTORED) && s->vmc && s->vmc_rows > 0) {
+        // sampled operator on the drawn rows only (gathered contiguously by irl_vmc_sample)
+        const FacRows R{ws_ptr<uint64_t>(ws, L.off_ckeys), s->vmc_rows, ws_ptr<double>(ws, L.off_cpsi),
+                        ws_ptr<double>(ws, L.off_cfac)};
+        TIMED(s, IRL_STAT_GEMV, st, launch_fac_jvp_rows(s, L, R, v, zero_v0, w, st));
+        TIMED(s, IRL_STAT_VMC, st, launch_vmc_diag_rows(L, ws, s->vmc_rows, w, u, st));
+        const int nb = fac_row_blocks_n(s->vmc_rows, L.hfac);
+        TIMED(s, IRL_STAT_GEMV_T, st, launch_fac_vjp_rows(s, L, ws, R, w, u, nullptr, 0, nb, st));
+        TIMED(s, IRL_STAT_REDUCE, st, launch_t2_reduce(L, ws, nb, yS, yH, L.ncols, 1.0, nullptr, st));
+        return IRL_OK;
+    }
     if (prec == IRL_FP64 && (L.flags & IRL_WS_FACTORED)) {
         // factored Jacobian: forward product, H, both backward products in one pass
         TIMED(s, IRL_STAT_GEMV, st, launch_fac_jvp(s, L, ws, v, zero_v0, w, st));
@@ -321,6 +332,13 @@ WsLayout make_layout(int64_t ns, int64_t ncols, uint32_t flags, int V)
     L.off_fac = take((flags & IRL_WS_FACTORED) ? (size_t)ns * (size_t)L.hfac * 8 : 0);
     L.off_sig = take((size_t)ld * 8);
     L.off_q = take((size_t)ns * 8);
+    const bool gather = (flags & IRL_WS_SAMPLED) && (flags & IRL_WS_FACTORED) && L.hfac > 0;
+    L.off_ckeys = take(gather ? (size_t)ns * 8 : 0);
+    L.off_cpsi = take(gather ? (size_t)ns * 8 : 0);
+    L.off_cq = take(gather ? (size_t)ns * 8 : 0);
+    L.off_cel = take(gather ? (size_t)ns * 8 : 0);
+    L.off_crow = take(gather ? (size_t)ns * 8 : 0);
+    L.off_cfac = take(gather ? (size_t)ns * (size_t)L.hfac * 8 : 0);
     L.total = off;
     return L;
 }
@@ -812,7 +830,7 @@ int irl_system_info_get(const irl_system *s, irl_system_info *o)
 int irl_workspace_query(const irl_system *s, int64_t ncols, uint32_t ws_flags, size_t *bytes)
 {
     if (!s || !bytes || ncols < 2 || !(ws_flags & (IRL_WS_FP64 | IRL_WS_FP32 | IRL_WS_FACTORED)) ||
-        (ws_flags & ~(uint32_t)(IRL_WS_FP64 | IRL_WS_FP32 | IRL_WS_BLOCK | IRL_WS_FACTORED)))
+        (ws_flags & ~(uint32_t)(IRL_WS_FP64 | IRL_WS_FP32 | IRL_WS_BLOCK | IRL_WS_FACTORED | IRL_WS_SAMPLED)))
         return IRL_EINVAL;
     const WsLayout L = make_layout(s->ns, ncols, ws_flags, 2 * s->n);
     if ((ws_flags & IRL_WS_FACTORED) && L.hfac < 1) return IRL_EINVAL;
@@ -837,6 +855,7 @@ int irl_nqs_evaluate(irl_system *s, const irl_nqs_desc *nqs, void *ws, size_t ws
     if (rc) return rc;
     s->ws_valid = false;
     s->vmc = false;
+    s->vmc_rows = 0;
     TIMED(s, IRL_STAT_DTILDE_BUILD, st, launch_nqs_dtilde(s, nqs->V, nqs->H, nqs->theta, L, ws, st));
     rc = energy_and_gradient(s, ws, L, st, nqs);
     if (rc) return rc;
@@ -896,6 +915,7 @@ int irl_vmc_sample(irl_system *s, void *ws, size_t ws_bytes, const double *u, in
     const int k = 61 - std::ilogb(s->Z);
     double *dout = ws_ptr<double>(ws, L.off_r);
     s->vmc = false;
+    s->vmc_rows = 0;
     TIMED(s, IRL_STAT_VMC, st, launch_vmc_sample(L, ws, u, n_samples, k, s->Z, rows, dout, st));
     // sampled gradient F = (2 / Z) D~^T (q (H psi - E psi)); the right-hand side is in the w region
     const double *y = ws_ptr<double>(ws, L.off_w);
@@ -909,6 +929,8 @@ int irl_vmc_sample(irl_system *s, void *ws, size_t ws_bytes, const double *u, in
         TIMED(s, IRL_STAT_GEMV_T, st, launch_gemv_t2(L, ws, IRL_FP64, y, y, nullptr, nullptr, &nblk, st));
     }
     TIMED(s, IRL_STAT_REDUCE, st, launch_t2_reduce(L, ws, nblk, nullptr, grad, L.ncols, 2.0, &sc->Z, st));
+    const bool gather = (L.flags & IRL_WS_SAMPLED) && (L.flags & IRL_WS_FACTORED) && L.hfac > 0;
+    if (gather) TIMED(s, IRL_STAT_VMC, st, launch_vmc_gather(L, ws, s->d.keys, L.hfac, st));
     if (grad_out) CK(s, hipMemcpyAsync(grad_out, grad + 1, (L.ncols - 1) * 8, hipMemcpyDeviceToDevice, st));
     double h[3];
     CK(s, hipMemcpyAsync(h, dout, sizeof(h), hipMemcpyDeviceToHost, st));
@@ -921,6 +943,7 @@ int irl_vmc_sample(irl_system *s, void *ws, size_t ws_bytes, const double *u, in
     }
     s->E_el = h[0];
     s->vmc = true;
+    s->vmc_rows = gather ? (int64_t)h[1] : 0;
     if (out) {
         out->E_sampled = h[0] + s->e_core;
         out->E_exact = s->E_exact + s->e_core;
@@ -945,6 +968,7 @@ int irl_dtilde_set(irl_system *s, const void *D, int64_t ld, int64_t ncols, int3
     if (rc) return rc;
     s->ws_valid = false;
     s->vmc = false;
+    s->vmc_rows = 0;
     TIMED(s, IRL_STAT_DTILDE_BUILD, st, launch_dtilde_import(D, ld, ncols, dtype, L, ws, st));
     rc = energy_and_gradient(s, ws, L, st);
     if (rc) return rc;
@@ -1514,6 +1538,7 @@ int batch_evaluate(irl_batch *b, const std::vector<int> &subset, hipStream_t st)
         s->lay = b->lay[m];
         s->ws_valid = true;
         s->vmc = false;
+        s->vmc_rows = 0;
         s->ws_has64 = (b->ws_flags & IRL_WS_FP64) != 0;
         s->ws_has32 = (b->ws_flags & IRL_WS_FP32) != 0;
         if (!(s->Z > 0.0) || !std::isfinite(s->E_el))

@@ -495,30 +495,29 @@ void forward_ks(const irl_system *s, const WsLayout &L, int V, int H, const doub
 }
 
 template <int KS>
-void jvp_ks(const irl_system *s, const WsLayout &L, int V, int H, const double *dfac, const double *psi,
-            const double *v, int zero_v0, double *w, hipStream_t st)
+void jvp_ks(const irl_system *s, const FacRows &R, int V, int H, const double *v, int zero_v0, double *w,
+            hipStream_t st)
 {
     constexpr int QT = KS <= 6 ? 4 : 2;
-    const int blocks = fac_tile_blocks(L.ns);
+    const int blocks = fac_tile_blocks(R.ns);
     if (H % QT == 0)
-        k_fac_jvp<KS, QT, true><<<blocks, 256, 0, st>>>(s->d.keys, L.ns, s->n, V, H, dfac, psi, v, zero_v0, w);
+        k_fac_jvp<KS, QT, true><<<blocks, 256, 0, st>>>(R.keys, R.ns, s->n, V, H, R.dfac, R.psi, v, zero_v0, w);
     else
-        k_fac_jvp<KS, QT, false><<<blocks, 256, 0, st>>>(s->d.keys, L.ns, s->n, V, H, dfac, psi, v, zero_v0, w);
+        k_fac_jvp<KS, QT, false><<<blocks, 256, 0, st>>>(R.keys, R.ns, s->n, V, H, R.dfac, R.psi, v, zero_v0, w);
 }
 
 // MT (hidden column tiles per wave) keeps NR MT NT <= 8 accumulator tiles per lane
 template <int NT, int NR>
-void vjp_nt(const irl_system *s, const WsLayout &L, int V, int H, const double *dfac, const double *psi,
-            const double *y0, const double *y1, const double *coefp, double *part, int nblk, int half,
-            hipStream_t st)
+void vjp_nt(const irl_system *s, const WsLayout &L, const FacRows &R, int V, int H, const double *y0,
+            const double *y1, const double *coefp, double *part, int nblk, int half, hipStream_t st)
 {
     constexpr int MT = (8 / (NR * NT)) >= 4 ? 4 : (8 / (NR * NT)) >= 2 ? 2 : 1;
     const dim3 grid((H + 16 * MT - 1) / (16 * MT), nblk);
     if (H % MT == 0)
-        k_fac_vjp<NT, NR, MT, true><<<grid, 256, 0, st>>>(s->d.keys, L.ns, s->n, V, H, dfac, psi, y0, y1,
+        k_fac_vjp<NT, NR, MT, true><<<grid, 256, 0, st>>>(R.keys, R.ns, s->n, V, H, R.dfac, R.psi, y0, y1,
                                                           coefp, part, L.ldv, nblk, half);
     else
-        k_fac_vjp<NT, NR, MT, false><<<grid, 256, 0, st>>>(s->d.keys, L.ns, s->n, V, H, dfac, psi, y0, y1,
+        k_fac_vjp<NT, NR, MT, false><<<grid, 256, 0, st>>>(R.keys, R.ns, s->n, V, H, R.dfac, R.psi, y0, y1,
                                                            coefp, part, L.ldv, nblk, half);
 }
 
@@ -550,58 +549,79 @@ hipError_t launch_fac_forward(const irl_system *s, const WsLayout &L, void *ws, 
     return hipGetLastError();
 }
 
-hipError_t launch_fac_jvp(const irl_system *s, const WsLayout &L, void *ws, const double *v, int zero_v0,
-                          double *w, hipStream_t st)
+FacRows fac_rows(const irl_system *s, const WsLayout &L, void *ws)
 {
-    if (!fac_shape_ok(s, L)) return hipErrorInvalidValue;
+    return FacRows{s->d.keys, L.ns, ws_ptr<double>(ws, L.off_psi), ws_ptr<double>(ws, L.off_fac)};
+}
+
+hipError_t launch_fac_jvp_rows(const irl_system *s, const WsLayout &L, const FacRows &R, const double *v,
+                               int zero_v0, double *w, hipStream_t st)
+{
+    if (!fac_shape_ok(s, L) || R.ns < 1) return hipErrorInvalidValue;
     const int V = 2 * s->n, H = L.hfac;
-    const double *psi = ws_ptr<double>(ws, L.off_psi), *dfac = ws_ptr<double>(ws, L.off_fac);
     switch ((V + 7) / 8) {
-    case 1: jvp_ks<2>(s, L, V, H, dfac, psi, v, zero_v0, w, st); break;
-    case 2: jvp_ks<4>(s, L, V, H, dfac, psi, v, zero_v0, w, st); break;
-    case 3: jvp_ks<6>(s, L, V, H, dfac, psi, v, zero_v0, w, st); break;
-    case 4: jvp_ks<8>(s, L, V, H, dfac, psi, v, zero_v0, w, st); break;
-    case 5: jvp_ks<10>(s, L, V, H, dfac, psi, v, zero_v0, w, st); break;
-    case 6: jvp_ks<12>(s, L, V, H, dfac, psi, v, zero_v0, w, st); break;
-    case 7: jvp_ks<14>(s, L, V, H, dfac, psi, v, zero_v0, w, st); break;
-    default: jvp_ks<16>(s, L, V, H, dfac, psi, v, zero_v0, w, st); break;
+    case 1: jvp_ks<2>(s, R, V, H, v, zero_v0, w, st); break;
+    case 2: jvp_ks<4>(s, R, V, H, v, zero_v0, w, st); break;
+    case 3: jvp_ks<6>(s, R, V, H, v, zero_v0, w, st); break;
+    case 4: jvp_ks<8>(s, R, V, H, v, zero_v0, w, st); break;
+    case 5: jvp_ks<10>(s, R, V, H, v, zero_v0, w, st); break;
+    case 6: jvp_ks<12>(s, R, V, H, v, zero_v0, w, st); break;
+    case 7: jvp_ks<14>(s, R, V, H, v, zero_v0, w, st); break;
+    default: jvp_ks<16>(s, R, V, H, v, zero_v0, w, st); break;
     }
     return hipGetLastError();
 }
 
-int fac_row_blocks(const WsLayout &L)
+hipError_t launch_fac_jvp(const irl_system *s, const WsLayout &L, void *ws, const double *v, int zero_v0,
+                          double *w, hipStream_t st)
 {
-    const int htiles = (L.hfac + 63) / 64;
+    return launch_fac_jvp_rows(s, L, fac_rows(s, L, ws), v, zero_v0, w, st);
+}
+
+int fac_row_blocks_n(int64_t ns, int hfac)
+{
+    const int htiles = (hfac + 63) / 64;
     int nblk = kStreamBlocks / (htiles > 0 ? htiles : 1);
     if (nblk < 1) nblk = 1;
-    if (nblk > (L.ns + 15) / 16) nblk = (int)((L.ns + 15) / 16);
+    if (nblk > (ns + 15) / 16) nblk = (int)((ns + 15) / 16);
     return nblk < 1 ? 1 : nblk;
+}
+
+int fac_row_blocks(const WsLayout &L)
+{
+    return fac_row_blocks_n(L.ns, L.hfac);
+}
+
+hipError_t launch_fac_vjp_rows(const irl_system *s, const WsLayout &L, void *ws, const FacRows &R,
+                               const double *y0, const double *y1, const double *coefp, int half, int nblk,
+                               hipStream_t st)
+{
+    if (!fac_shape_ok(s, L) || R.ns < 1 || nblk < 1 || nblk > kStreamBlocks || !y0) return hipErrorInvalidValue;
+    const int V = 2 * s->n, H = L.hfac;
+    double *part = ws_ptr<double>(ws, L.off_part);
+    const int nt = (V + 15) / 16;
+    if (y1) {
+        switch (nt) {
+        case 1: vjp_nt<1, 2>(s, L, R, V, H, y0, y1, coefp, part, nblk, 0, st); break;
+        case 2: vjp_nt<2, 2>(s, L, R, V, H, y0, y1, coefp, part, nblk, 0, st); break;
+        case 3: vjp_nt<3, 2>(s, L, R, V, H, y0, y1, coefp, part, nblk, 0, st); break;
+        default: vjp_nt<4, 2>(s, L, R, V, H, y0, y1, coefp, part, nblk, 0, st); break;
+        }
+    } else {
+        switch (nt) {
+        case 1: vjp_nt<1, 1>(s, L, R, V, H, y0, nullptr, coefp, part, nblk, half, st); break;
+        case 2: vjp_nt<2, 1>(s, L, R, V, H, y0, nullptr, coefp, part, nblk, half, st); break;
+        case 3: vjp_nt<3, 1>(s, L, R, V, H, y0, nullptr, coefp, part, nblk, half, st); break;
+        default: vjp_nt<4, 1>(s, L, R, V, H, y0, nullptr, coefp, part, nblk, half, st); break;
+        }
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_fac_vjp(const irl_system *s, const WsLayout &L, void *ws, const double *y0, const double *y1,
                           const double *coefp, int half, int nblk, hipStream_t st)
 {
-    if (!fac_shape_ok(s, L) || nblk < 1 || nblk > kStreamBlocks || !y0) return hipErrorInvalidValue;
-    const int V = 2 * s->n, H = L.hfac;
-    const double *psi = ws_ptr<double>(ws, L.off_psi), *dfac = ws_ptr<double>(ws, L.off_fac);
-    double *part = ws_ptr<double>(ws, L.off_part);
-    const int nt = (V + 15) / 16;
-    if (y1) {
-        switch (nt) {
-        case 1: vjp_nt<1, 2>(s, L, V, H, dfac, psi, y0, y1, coefp, part, nblk, 0, st); break;
-        case 2: vjp_nt<2, 2>(s, L, V, H, dfac, psi, y0, y1, coefp, part, nblk, 0, st); break;
-        case 3: vjp_nt<3, 2>(s, L, V, H, dfac, psi, y0, y1, coefp, part, nblk, 0, st); break;
-        default: vjp_nt<4, 2>(s, L, V, H, dfac, psi, y0, y1, coefp, part, nblk, 0, st); break;
-        }
-    } else {
-        switch (nt) {
-        case 1: vjp_nt<1, 1>(s, L, V, H, dfac, psi, y0, nullptr, coefp, part, nblk, half, st); break;
-        case 2: vjp_nt<2, 1>(s, L, V, H, dfac, psi, y0, nullptr, coefp, part, nblk, half, st); break;
-        case 3: vjp_nt<3, 1>(s, L, V, H, dfac, psi, y0, nullptr, coefp, part, nblk, half, st); break;
-        default: vjp_nt<4, 1>(s, L, V, H, dfac, psi, y0, nullptr, coefp, part, nblk, half, st); break;
-        }
-    }
-    return hipGetLastError();
+    return launch_fac_vjp_rows(s, L, ws, fac_rows(s, L, ws), y0, y1, coefp, half, nblk, st);
 }
 
 }  // namespace irl

@@ -63,7 +63,9 @@ struct WsLayout {
            off_img0 = 0, off_img1 = 0, off_hy = 0,   // operator images of the basis; of y
            off_fac = 0,                              // factored Jacobian d = 1 - t^2 (N_s x hfac)
            off_sig = 0,                              // D~^T psi (connected basis, mode C)
-           off_q = 0;                                // sampled row weights Z c_r / (N psi_r^2)
+           off_q = 0,                                // sampled row weights Z c_r / (N psi_r^2)
+           // drawn rows gathered contiguously (IRL_WS_SAMPLED with the factored Jacobian)
+           off_ckeys = 0, off_cpsi = 0, off_cq = 0, off_cel = 0, off_crow = 0, off_cfac = 0;
     int hfac = 0;                                    // hidden units of the factored Jacobian
     size_t total = 0;
 };
@@ -200,6 +202,7 @@ struct irl_system {
     // sampled estimators (irl_vmc_sample) replace the exact ones until the next evaluation
     bool vmc = false;
     double E_exact = 0.0;
+    int64_t vmc_rows = 0;     // drawn rows gathered contiguously (0: products run over every row)
     // pinned host staging for small readbacks
     irl::WsScalars *host_scal = nullptr;
     // dense BLAS handle (rocblas_handle) for the same-spin doubles of a full space
@@ -283,6 +286,20 @@ hipError_t launch_fac_jvp(const irl_system *s, const WsLayout &L, void *ws, cons
 hipError_t launch_fac_vjp(const irl_system *s, const WsLayout &L, void *ws, const double *y0, const double *y1,
                           const double *coefp, int half, int nblk, hipStream_t st);
 int fac_row_blocks(const WsLayout &L);
+// the same products over an explicit row set (keys, psi and d of ns rows), e.g. the
+// drawn rows of a sampled step gathered contiguously
+struct FacRows {
+    const uint64_t *keys;
+    int64_t ns;
+    const double *psi;
+    const double *dfac;
+};
+hipError_t launch_fac_jvp_rows(const irl_system *s, const WsLayout &L, const FacRows &R, const double *v,
+                               int zero_v0, double *w, hipStream_t st);
+hipError_t launch_fac_vjp_rows(const irl_system *s, const WsLayout &L, void *ws, const FacRows &R,
+                               const double *y0, const double *y1, const double *coefp, int half, int nblk,
+                               hipStream_t st);
+int fac_row_blocks_n(int64_t ns, int hfac);
 hipError_t launch_nqs_dtilde(const irl_system *s, int V, int H, const double *theta,
                              const WsLayout &L, void *ws, hipStream_t st);
 hipError_t launch_dtilde_import(const void *D, int64_t ld, int64_t ncols, int dtype,
@@ -329,6 +346,8 @@ int64_t vmc_scan_chunks(int64_t ns);
 hipError_t launch_vmc_sample(const WsLayout &L, void *ws, const double *u, int64_t nsamp, int k, double Z,
                              int64_t *rows, double *out, hipStream_t st);
 hipError_t launch_vmc_diag(const WsLayout &L, void *ws, double *w, double *u, int nb, hipStream_t st);
+hipError_t launch_vmc_gather(const WsLayout &L, void *ws, const uint64_t *keys, int hfac, hipStream_t st);
+hipError_t launch_vmc_diag_rows(const WsLayout &L, void *ws, int64_t nrows, double *w, double *u, hipStream_t st);
 hipError_t launch_update(const WsLayout &L, void *ws, const double *y, double *dtheta,
                          double *theta, int64_t P, int mode, hipStream_t st);
 hipError_t launch_copy(double *dst, const double *src, int64_t n, hipStream_t st);

@@ -38,15 +38,26 @@ __device__ __forceinline__ uint64_t fixed_weight(double p, int k)
     return (uint64_t)rint(ldexp(p * p, k));
 }
 
-// fixed-point weights of this thread's rows and their sum
-__device__ __forceinline__ uint64_t thread_weights(const double *__restrict__ psi, int64_t ns, int64_t base,
-                                                   int k, uint64_t *w)
+// values scanned: the fixed-point weight of a row, or whether it was drawn
+struct WeightVal {
+    const double *psi;
+    int k;
+    __device__ uint64_t operator()(int64_t i) const { return fixed_weight(psi[i], k); }
+};
+struct DrawnVal {
+    const uint32_t *counts;
+    __device__ uint64_t operator()(int64_t i) const { return counts[i] ? 1ull : 0ull; }
+};
+
+// this thread's values and their sum
+template <typename F>
+__device__ __forceinline__ uint64_t thread_values(const F &f, int64_t ns, int64_t base, uint64_t *w)
 {
     uint64_t s = 0;
 #pragma unroll
     for (int e = 0; e < kScanPer; ++e) {
         const int64_t i = base + e;
-        w[e] = i < ns ? fixed_weight(psi[i], k) : 0ull;
+        w[e] = i < ns ? f(i) : 0ull;
         s += w[e];
     }
     return s;
@@ -77,14 +88,14 @@ __device__ uint64_t block_exclusive(uint64_t v, uint64_t *sh, uint64_t *total)
     return sh[wv] + (x - v);
 }
 
-__global__ __launch_bounds__(kScanThreads) void k_scan_chunks(const double *__restrict__ psi, int64_t ns, int k,
-                                                             uint64_t *__restrict__ tot)
+template <typename F>
+__global__ __launch_bounds__(kScanThreads) void k_scan_chunks(F f, int64_t ns, uint64_t *__restrict__ tot)
 {
     __shared__ uint64_t sh[kScanWaves + 1];
     uint64_t w[kScanPer];
     const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanPer;
     uint64_t total;
-    block_exclusive(thread_weights(psi, ns, base, k, w), sh, &total);
+    block_exclusive(thread_values(f, ns, base, w), sh, &total);
     if (threadIdx.x == 0) tot[blockIdx.x] = total;
 }
 
@@ -105,15 +116,15 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_offsets(uint64_t *__restr
     if (threadIdx.x == 0) tot[nc] = carry;
 }
 
-__global__ __launch_bounds__(kScanThreads) void k_scan_apply(const double *__restrict__ psi, int64_t ns, int k,
-                                                            const uint64_t *__restrict__ off,
+template <typename F>
+__global__ __launch_bounds__(kScanThreads) void k_scan_apply(F f, int64_t ns, const uint64_t *__restrict__ off,
                                                             uint64_t *__restrict__ cum)
 {
     __shared__ uint64_t sh[kScanWaves + 1];
     uint64_t w[kScanPer];
     const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanPer;
     uint64_t total;
-    uint64_t acc = off[blockIdx.x] + block_exclusive(thread_weights(psi, ns, base, k, w), sh, &total);
+    uint64_t acc = off[blockIdx.x] + block_exclusive(thread_values(f, ns, base, w), sh, &total);
 #pragma unroll
     for (int e = 0; e < kScanPer; ++e) {
         acc += w[e];
@@ -266,6 +277,57 @@ __global__ __launch_bounds__(kVmcThreads) void k_vmc_diag(const double *__restri
     }
 }
 
+// compact slot of each drawn row: crow[cum_r - 1] = r (cum inclusive over drawn flags)
+__global__ __launch_bounds__(kVmcThreads) void k_vmc_index(const uint32_t *__restrict__ counts,
+                                                          const uint64_t *__restrict__ cum, int64_t ns,
+                                                          int64_t *__restrict__ crow)
+{
+    for (int64_t r = (int64_t)blockIdx.x * kVmcThreads + threadIdx.x; r < ns;
+         r += (int64_t)gridDim.x * kVmcThreads)
+        if (counts[r]) crow[cum[r] - 1] = r;
+}
+
+// one wavefront per drawn row j < *nup: key, psi, weight, local energy and the d row
+__global__ __launch_bounds__(kVmcThreads) void k_vmc_gather(const int64_t *__restrict__ crow,
+                                                           const uint64_t *__restrict__ nup, int64_t slots,
+                                                           const uint64_t *__restrict__ keys,
+                                                           const double *__restrict__ psi,
+                                                           const double *__restrict__ hpsi,
+                                                           const double *__restrict__ q,
+                                                           const double *__restrict__ dfac, int hfac,
+                                                           uint64_t *__restrict__ ckeys, double *__restrict__ cpsi,
+                                                           double *__restrict__ cq, double *__restrict__ cel,
+                                                           double *__restrict__ cfac)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t nu = (int64_t)*nup;
+    const int64_t waves = (int64_t)gridDim.x * (kVmcThreads / kWave);
+    for (int64_t j = (int64_t)blockIdx.x * (kVmcThreads / kWave) + threadIdx.x / kWave; j < nu && j < slots;
+         j += waves) {
+        const int64_t r = crow[j];
+        if (lane == 0) {
+            ckeys[j] = keys[r];
+            cpsi[j] = psi[r];
+            cq[j] = q[r];
+            cel[j] = hpsi[r] / psi[r];
+        }
+        for (int h = lane; h < hfac; h += kWave) cfac[j * hfac + h] = dfac[r * hfac + h];
+    }
+}
+
+// the sampled operator's diagonal on gathered rows: w <- q w, u <- q E_loc w
+__global__ __launch_bounds__(kVmcThreads) void k_vmc_diag_rows(const double *__restrict__ cq,
+                                                              const double *__restrict__ cel, int64_t nrows,
+                                                              double *__restrict__ w, double *__restrict__ u)
+{
+    for (int64_t j = (int64_t)blockIdx.x * kVmcThreads + threadIdx.x; j < nrows;
+         j += (int64_t)gridDim.x * kVmcThreads) {
+        const double x = cq[j] * w[j];
+        w[j] = x;
+        u[j] = x * cel[j];
+    }
+}
+
 unsigned row_blocks(int64_t ns)
 {
     const int64_t b = (ns + kVmcThreads - 1) / kVmcThreads;
@@ -298,9 +360,10 @@ hipError_t launch_vmc_sample(const WsLayout &L, void *ws, const double *u, int64
     WsScalars *sc = ws_ptr<WsScalars>(ws, L.off_scal);
     const int64_t nc = vmc_scan_chunks(ns);
     const unsigned nb = row_blocks(ns);
-    k_scan_chunks<<<(unsigned)nc, kScanThreads, 0, st>>>(psi, ns, k, tot);
+    const WeightVal wv{psi, k};
+    k_scan_chunks<<<(unsigned)nc, kScanThreads, 0, st>>>(wv, ns, tot);
     k_scan_offsets<<<1, kScanThreads, 0, st>>>(tot, nc);
-    k_scan_apply<<<(unsigned)nc, kScanThreads, 0, st>>>(psi, ns, k, tot, cum);
+    k_scan_apply<<<(unsigned)nc, kScanThreads, 0, st>>>(wv, ns, tot, cum);
     k_fill_u32<<<nb, kVmcThreads, 0, st>>>(counts, ns);
     k_vmc_draw<<<(unsigned)((nsamp + kVmcThreads - 1) / kVmcThreads), kVmcThreads, 0, st>>>(
         u, nsamp, cum, ns, tot + nc, counts, rows);
@@ -309,6 +372,37 @@ hipError_t launch_vmc_sample(const WsLayout &L, void *ws, const double *u, int64
     k_vmc_energy<<<1, kWave, 0, st>>>(part, (int)nb, inv_n, sc, out);
     k_vmc_rhs<<<nb, kVmcThreads, 0, st>>>(counts, psi, hpsi, q, ns, sc, y, part);
     k_vmc_variance<<<1, kWave, 0, st>>>(part, (int)nb, inv_n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_vmc_gather(const WsLayout &L, void *ws, const uint64_t *keys, int hfac, hipStream_t st)
+{
+    const int64_t ns = L.ns;
+    const uint32_t *counts = ws_ptr<uint32_t>(ws, L.off_u);
+    uint64_t *cum = ws_ptr<uint64_t>(ws, L.off_w);
+    uint64_t *tot = ws_ptr<uint64_t>(ws, L.off_part);
+    const int64_t nc = vmc_scan_chunks(ns);
+    const DrawnVal dv{counts};
+    k_scan_chunks<<<(unsigned)nc, kScanThreads, 0, st>>>(dv, ns, tot);
+    k_scan_offsets<<<1, kScanThreads, 0, st>>>(tot, nc);
+    k_scan_apply<<<(unsigned)nc, kScanThreads, 0, st>>>(dv, ns, tot, cum);
+    int64_t *crow = ws_ptr<int64_t>(ws, L.off_crow);
+    k_vmc_index<<<row_blocks(ns), kVmcThreads, 0, st>>>(counts, cum, ns, crow);
+    const int64_t waves_per_block = kVmcThreads / kWave;
+    int64_t blocks = (ns + waves_per_block - 1) / waves_per_block;
+    if (blocks > 16384) blocks = 16384;
+    k_vmc_gather<<<(unsigned)blocks, kVmcThreads, 0, st>>>(
+        crow, tot + nc, ns, keys, ws_ptr<double>(ws, L.off_psi), ws_ptr<double>(ws, L.off_hpsi),
+        ws_ptr<double>(ws, L.off_q), ws_ptr<double>(ws, L.off_fac), hfac, ws_ptr<uint64_t>(ws, L.off_ckeys),
+        ws_ptr<double>(ws, L.off_cpsi), ws_ptr<double>(ws, L.off_cq), ws_ptr<double>(ws, L.off_cel),
+        ws_ptr<double>(ws, L.off_cfac));
+    return hipGetLastError();
+}
+
+hipError_t launch_vmc_diag_rows(const WsLayout &L, void *ws, int64_t nrows, double *w, double *u, hipStream_t st)
+{
+    k_vmc_diag_rows<<<row_blocks(nrows), kVmcThreads, 0, st>>>(ws_ptr<double>(ws, L.off_cq),
+                                                               ws_ptr<double>(ws, L.off_cel), nrows, w, u);
     return hipGetLastError();
 }
 

@@ -97,12 +97,13 @@ def test_vmc_draws_and_estimators(vmc_case):
     assert rel_err(host(F), vmc.sampled_gradient(r, O, Eloc)) <= 1e-10
 
 
-@pytest.mark.parametrize("factored", [False, True])
+@pytest.mark.parametrize("factored", [False, True, "gathered"])
 def test_vmc_operator_pair(vmc_case, factored):
-    from paper_2601_01437_amd import IRL_WS_FACTORED, IRL_WS_FP64
+    from paper_2601_01437_amd import IRL_WS_FACTORED, IRL_WS_FP64, IRL_WS_SAMPLED
     p = vmc_case
     announce(f"vmc operator pair {p['name']} factored={factored}")
-    s, _ = _gpu_system(p, IRL_WS_FACTORED if factored else IRL_WS_FP64)
+    fl = {False: IRL_WS_FP64, True: IRL_WS_FACTORED, "gathered": IRL_WS_FACTORED | IRL_WS_SAMPLED}[factored]
+    s, _ = _gpu_system(p, fl)
     out, _, _ = s.vmc_sample(dev(p["u"]))
     Z, _, _ = lm.energy(p["psi"], p["Hm"])
     rng = np.random.default_rng(3)
@@ -113,7 +114,7 @@ def test_vmc_operator_pair(vmc_case, factored):
         assert rel_err(host(yH) / Z, rH) <= 1e-10 and rel_err(host(yS) / Z, rS) <= 1e-10
     # block apply of the sampled operator
     from paper_2601_01437_amd import IRL_WS_BLOCK
-    if not factored:
+    if factored is False:
         s2, _ = _gpu_system(p, IRL_WS_FP64 | IRL_WS_BLOCK)
         s2.vmc_sample(dev(p["u"]))
         Vb = rng.normal(size=(3, p["Dt"].shape[1]))
@@ -123,14 +124,14 @@ def test_vmc_operator_pair(vmc_case, factored):
             assert rel_err(host(YH[q]) / Z, rH) <= 1e-10 and rel_err(host(YS[q]) / Z, rS) <= 1e-10
 
 
-@pytest.mark.parametrize("variant", ["fp64", "factored", "fp32_polish", "mode_p"])
+@pytest.mark.parametrize("variant", ["fp64", "factored", "gathered", "fp32_polish", "mode_p"])
 def test_vmc_step(vmc_case, variant):
     from paper_2601_01437_amd import (IRL_FP32, IRL_FP64, IRL_MODE_A, IRL_MODE_P, IRL_STEP_WS_CURRENT,
-                                      IRL_WS_FACTORED, IRL_WS_FP32, IRL_WS_FP64)
+                                      IRL_WS_FACTORED, IRL_WS_FP32, IRL_WS_FP64, IRL_WS_SAMPLED)
     p = vmc_case
     announce(f"vmc step {p['name']} {variant}")
-    fl = {"fp64": IRL_WS_FP64, "factored": IRL_WS_FACTORED, "fp32_polish": IRL_WS_FP64 | IRL_WS_FP32,
-          "mode_p": IRL_WS_FACTORED}[variant]
+    fl = {"fp64": IRL_WS_FP64, "factored": IRL_WS_FACTORED, "gathered": IRL_WS_FACTORED | IRL_WS_SAMPLED,
+          "fp32_polish": IRL_WS_FP64 | IRL_WS_FP32, "mode_p": IRL_WS_FACTORED | IRL_WS_SAMPLED}[variant]
     mode = IRL_MODE_P if variant == "mode_p" else IRL_MODE_A
     s, theta = _gpu_system(p, fl)
     s.vmc_sample(dev(p["u"]))
@@ -174,26 +175,32 @@ def test_vmc_zero_variance_at_exact_eigenvector():
 def test_vmc_c2_scale_properties():
     """853,776 determinants, 2^17 draws: rows are monotone in u (inverse
     transform), the distinct rows match the reported count, the sampled energy is
-    within five standard errors of the exact one, and a sampled step converges."""
+    within five standard errors of the exact one, and a sampled step converges to
+    the same eigenvalue with the products over every row and over the gathered
+    drawn rows only."""
     import torch
-    from paper_2601_01437_amd import IRL_STEP_WS_CURRENT, IRL_WS_FACTORED, System
+    from paper_2601_01437_amd import IRL_STEP_WS_CURRENT, IRL_WS_FACTORED, IRL_WS_SAMPLED, System
     announce("vmc c2 scale")
     w = synth.WORKLOADS["c2"]
     h, g = w.integrals()
     s = System(w.n, w.na, w.nb, h, g)
-    theta = dev(w.theta())
-    s.evaluate(w.V, w.H, theta, ws_flags=IRL_WS_FACTORED)
     u = np.random.default_rng(9).random(1 << 17)
-    out, rows, F = s.vmc_sample(dev(u), want_rows=True, want_grad=True)
-    rows = host(rows)
-    order = np.argsort(u, kind="stable")
-    assert np.all(np.diff(rows[order]) >= 0)
-    assert out.n_unique == np.unique(rows).size
-    assert abs(out.E_sampled - out.E_exact) <= 5.0 * math.sqrt(out.E_loc_var / u.size)
-    assert np.all(np.isfinite(host(F)))
-    rc, r, _, _ = s.step(theta, w.V, w.H, m=40, k_keep=10, ws_flags=IRL_WS_FACTORED,
-                         flags=IRL_STEP_WS_CURRENT, want_dtheta=False)
-    assert r.converged == 1 and r.lambda_min <= 0.0 and np.isfinite(r.E_after)
+    lams = []
+    for fl in (IRL_WS_FACTORED, IRL_WS_FACTORED | IRL_WS_SAMPLED):
+        theta = dev(w.theta())
+        s.evaluate(w.V, w.H, theta, ws_flags=fl)
+        out, rows, F = s.vmc_sample(dev(u), want_rows=True, want_grad=True)
+        rows = host(rows)
+        order = np.argsort(u, kind="stable")
+        assert np.all(np.diff(rows[order]) >= 0)
+        assert out.n_unique == np.unique(rows).size
+        assert abs(out.E_sampled - out.E_exact) <= 5.0 * math.sqrt(out.E_loc_var / u.size)
+        assert np.all(np.isfinite(host(F)))
+        rc, r, _, _ = s.step(theta, w.V, w.H, m=40, k_keep=10, ws_flags=fl,
+                             flags=IRL_STEP_WS_CURRENT, want_dtheta=False)
+        assert r.converged == 1 and r.lambda_min <= 0.0 and np.isfinite(r.E_after)
+        lams.append((r.lambda_min, r.norm_T))
+    assert abs(lams[0][0] - lams[1][0]) <= 1e-10 * max(abs(lams[0][0]), lams[0][1])
     torch.cuda.synchronize()
 
 
