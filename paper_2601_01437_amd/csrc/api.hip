@@ -917,21 +917,8 @@ int irl_vmc_sample(irl_system *s, void *ws, size_t ws_bytes, const double *u, in
     s->vmc = false;
     s->vmc_rows = 0;
     TIMED(s, IRL_STAT_VMC, st, launch_vmc_sample(L, ws, u, n_samples, k, s->Z, rows, dout, st));
-    // sampled gradient F = (2 / Z) D~^T (q (H psi - E psi)); the right-hand side is in the w region
-    const double *y = ws_ptr<double>(ws, L.off_w);
-    double *grad = ws_ptr<double>(ws, L.off_grad);
-    WsScalars *sc = ws_ptr<WsScalars>(ws, L.off_scal);
-    int nblk = 1;
-    if (L.flags & IRL_WS_FACTORED) {
-        nblk = fac_row_blocks(L);
-        TIMED(s, IRL_STAT_ENERGY, st, launch_fac_vjp(s, L, ws, y, nullptr, nullptr, 1, nblk, st));
-    } else {
-        TIMED(s, IRL_STAT_GEMV_T, st, launch_gemv_t2(L, ws, IRL_FP64, y, y, nullptr, nullptr, &nblk, st));
-    }
-    TIMED(s, IRL_STAT_REDUCE, st, launch_t2_reduce(L, ws, nblk, nullptr, grad, L.ncols, 2.0, &sc->Z, st));
     const bool gather = (L.flags & IRL_WS_SAMPLED) && (L.flags & IRL_WS_FACTORED) && L.hfac > 0;
     if (gather) TIMED(s, IRL_STAT_VMC, st, launch_vmc_gather(L, ws, s->d.keys, L.hfac, st));
-    if (grad_out) CK(s, hipMemcpyAsync(grad_out, grad + 1, (L.ncols - 1) * 8, hipMemcpyDeviceToDevice, st));
     double h[3];
     CK(s, hipMemcpyAsync(h, dout, sizeof(h), hipMemcpyDeviceToHost, st));
     CK(s, hipStreamSynchronize(st));
@@ -941,6 +928,27 @@ int irl_vmc_sample(irl_system *s, void *ws, size_t ws_bytes, const double *u, in
         s->ws_valid = false;   // the device energy is no longer the evaluated one
         return set_err(s, IRL_EINVAL, "the sampled energy is not finite");
     }
+    const int64_t nu = (int64_t)h[1];
+    // sampled gradient F = (2 / Z) D~^T (q (H psi - E psi)), over the drawn rows when they
+    // are gathered, else over every row from the right-hand side in the w region
+    double *y = ws_ptr<double>(ws, L.off_w);
+    double *grad = ws_ptr<double>(ws, L.off_grad);
+    WsScalars *sc = ws_ptr<WsScalars>(ws, L.off_scal);
+    int nblk = 1;
+    if (gather) {
+        TIMED(s, IRL_STAT_VMC, st, launch_vmc_rhs_rows(L, ws, nu, y, st));
+        const FacRows R{ws_ptr<uint64_t>(ws, L.off_ckeys), nu, ws_ptr<double>(ws, L.off_cpsi),
+                        ws_ptr<double>(ws, L.off_cfac)};
+        nblk = fac_row_blocks_n(nu, L.hfac);
+        TIMED(s, IRL_STAT_ENERGY, st, launch_fac_vjp_rows(s, L, ws, R, y, nullptr, nullptr, 1, nblk, st));
+    } else if (L.flags & IRL_WS_FACTORED) {
+        nblk = fac_row_blocks(L);
+        TIMED(s, IRL_STAT_ENERGY, st, launch_fac_vjp(s, L, ws, y, nullptr, nullptr, 1, nblk, st));
+    } else {
+        TIMED(s, IRL_STAT_GEMV_T, st, launch_gemv_t2(L, ws, IRL_FP64, y, y, nullptr, nullptr, &nblk, st));
+    }
+    TIMED(s, IRL_STAT_REDUCE, st, launch_t2_reduce(L, ws, nblk, nullptr, grad, L.ncols, 2.0, &sc->Z, st));
+    if (grad_out) CK(s, hipMemcpyAsync(grad_out, grad + 1, (L.ncols - 1) * 8, hipMemcpyDeviceToDevice, st));
     s->E_el = h[0];
     s->vmc = true;
     s->vmc_rows = gather ? (int64_t)h[1] : 0;

@@ -348,6 +348,7 @@ hipError_t launch_vmc_sample(const WsLayout &L, void *ws, const double *u, int64
 hipError_t launch_vmc_diag(const WsLayout &L, void *ws, double *w, double *u, int nb, hipStream_t st);
 hipError_t launch_vmc_gather(const WsLayout &L, void *ws, const uint64_t *keys, int hfac, hipStream_t st);
 hipError_t launch_vmc_diag_rows(const WsLayout &L, void *ws, int64_t nrows, double *w, double *u, hipStream_t st);
+hipError_t launch_vmc_rhs_rows(const WsLayout &L, void *ws, int64_t nrows, double *y, hipStream_t st);
 hipError_t launch_update(const WsLayout &L, void *ws, const double *y, double *dtheta,
                          double *theta, int64_t P, int mode, hipStream_t st);
 hipError_t launch_copy(double *dst, const double *src, int64_t n, hipStream_t st);

@@ -207,19 +207,34 @@ __global__ __launch_bounds__(kVmcThreads) void k_vmc_weights(const uint32_t *__r
     }
 }
 
-// E = sum / N into sc->E_el and out[0]; distinct rows into out[1]
-__global__ __launch_bounds__(kWave) void k_vmc_energy(const double *__restrict__ part, int nblk, double inv_n,
-                                                     WsScalars *sc, double *out)
+// fixed-order sum of n <= kVmcBlocks partials (stride `stride`) over one
+// 1024-thread block; result valid in thread 0
+__device__ double partial_sum(const double *__restrict__ part, int n, int stride, double *sh)
 {
-    if (threadIdx.x != 0) return;
-    double e = 0.0, un = 0.0;
-    for (int b = 0; b < nblk; ++b) {
-        e += part[2 * b];
-        un += part[2 * b + 1];
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+    double v = (int)threadIdx.x < n ? part[(int64_t)threadIdx.x * stride] : 0.0;
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, kWave);
+    if (lane == 0) sh[wv] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < kVmcBlocks / kWave; ++i) s += sh[i];
+    __syncthreads();
+    return s;
+}
+
+// E = sum / N into sc->E_el and out[0]; distinct rows into out[1]
+__global__ __launch_bounds__(kVmcBlocks) void k_vmc_energy(const double *__restrict__ part, int nblk, double inv_n,
+                                                          WsScalars *sc, double *out)
+{
+    __shared__ double sh[kVmcBlocks / kWave];
+    const double e = partial_sum(part, nblk, 2, sh);
+    const double un = partial_sum(part + 1, nblk, 2, sh);
+    if (threadIdx.x == 0) {
+        sc->E_el = e * inv_n;
+        out[0] = e * inv_n;
+        out[1] = un;
     }
-    sc->E_el = e * inv_n;
-    out[0] = e * inv_n;
-    out[1] = un;
 }
 
 // right-hand side of the sampled gradient, y_r = q_r (H psi - E psi)_r, and
@@ -250,13 +265,24 @@ __global__ __launch_bounds__(kVmcThreads) void k_vmc_rhs(const uint32_t *__restr
     if (threadIdx.x == 0) part[blockIdx.x] = a;
 }
 
-__global__ __launch_bounds__(kWave) void k_vmc_variance(const double *__restrict__ part, int nblk, double inv_n,
-                                                       double *out)
+__global__ __launch_bounds__(kVmcBlocks) void k_vmc_variance(const double *__restrict__ part, int nblk,
+                                                            double inv_n, double *out)
 {
-    if (threadIdx.x != 0) return;
-    double v = 0.0;
-    for (int b = 0; b < nblk; ++b) v += part[b];
-    out[2] = v * inv_n;
+    __shared__ double sh[kVmcBlocks / kWave];
+    const double v = partial_sum(part, nblk, 1, sh);
+    if (threadIdx.x == 0) out[2] = v * inv_n;
+}
+
+// gradient right-hand side on the gathered rows: y_j = q_j psi_j (E_loc,j - E)
+__global__ __launch_bounds__(kVmcThreads) void k_vmc_rhs_rows(const double *__restrict__ cq,
+                                                             const double *__restrict__ cpsi,
+                                                             const double *__restrict__ cel, int64_t nrows,
+                                                             const WsScalars *sc, double *__restrict__ y)
+{
+    const double E = sc->E_el;
+    for (int64_t j = (int64_t)blockIdx.x * kVmcThreads + threadIdx.x; j < nrows;
+         j += (int64_t)gridDim.x * kVmcThreads)
+        y[j] = cq[j] * cpsi[j] * (cel[j] - E);
 }
 
 // the sampled operator's diagonal: w <- q w, u <- q E_loc w (nb columns of ns)
@@ -369,9 +395,9 @@ hipError_t launch_vmc_sample(const WsLayout &L, void *ws, const double *u, int64
         u, nsamp, cum, ns, tot + nc, counts, rows);
     const double inv_n = 1.0 / (double)nsamp;
     k_vmc_weights<<<nb, kVmcThreads, 0, st>>>(counts, psi, hpsi, ns, Z * inv_n, q, part);
-    k_vmc_energy<<<1, kWave, 0, st>>>(part, (int)nb, inv_n, sc, out);
+    k_vmc_energy<<<1, kVmcBlocks, 0, st>>>(part, (int)nb, inv_n, sc, out);
     k_vmc_rhs<<<nb, kVmcThreads, 0, st>>>(counts, psi, hpsi, q, ns, sc, y, part);
-    k_vmc_variance<<<1, kWave, 0, st>>>(part, (int)nb, inv_n, out);
+    k_vmc_variance<<<1, kVmcBlocks, 0, st>>>(part, (int)nb, inv_n, out);
     return hipGetLastError();
 }
 
@@ -396,6 +422,14 @@ hipError_t launch_vmc_gather(const WsLayout &L, void *ws, const uint64_t *keys, 
         ws_ptr<double>(ws, L.off_q), ws_ptr<double>(ws, L.off_fac), hfac, ws_ptr<uint64_t>(ws, L.off_ckeys),
         ws_ptr<double>(ws, L.off_cpsi), ws_ptr<double>(ws, L.off_cq), ws_ptr<double>(ws, L.off_cel),
         ws_ptr<double>(ws, L.off_cfac));
+    return hipGetLastError();
+}
+
+hipError_t launch_vmc_rhs_rows(const WsLayout &L, void *ws, int64_t nrows, double *y, hipStream_t st)
+{
+    k_vmc_rhs_rows<<<row_blocks(nrows), kVmcThreads, 0, st>>>(
+        ws_ptr<double>(ws, L.off_cq), ws_ptr<double>(ws, L.off_cpsi), ws_ptr<double>(ws, L.off_cel), nrows,
+        ws_ptr<WsScalars>(ws, L.off_scal), y);
     return hipGetLastError();
 }
 
