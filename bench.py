@@ -187,6 +187,35 @@ def cpu_baseline(wl, keys_fn, applies_per_step, sample_rows=1_000_000, chunk=20_
     }
 
 
+def measured_hbm_peak(torch, gib=4, reps=5):
+    """The achieved HBM rate of plain streaming on this GPU, next to the 8 TB/s
+    datasheet peak the rooflines use: a read-only reduction (torch sum of a
+    gib GiB FP64 tensor, bytes read / time) and a device-to-device copy
+    (gib / 2 GiB each way, bytes read + written / time); best of reps, timed with
+    HIP events on the current stream, outside the timed region of the bench."""
+    n = (gib << 30) // 8
+    x = torch.ones(n, dtype=torch.float64, device="cuda")
+    half = x[: n // 2]
+    y = torch.empty_like(half)
+    x.sum()
+    y.copy_(half)
+    read, copy = [], []
+    for _ in range(reps):
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        e0.record()
+        x.sum()
+        e1.record()
+        y.copy_(half)
+        e2.record()
+        e2.synchronize()
+        read.append(n * 8 / (e0.elapsed_time(e1) * 1e-3) / 1e9)
+        copy.append(2 * (n // 2) * 8 / (e1.elapsed_time(e2) * 1e-3) / 1e9)
+    del x, y, half
+    torch.cuda.empty_cache()
+    return {"read_GBps": max(read), "copy_GBps": max(copy), "bytes": n * 8,
+            "method": f"torch sum of {gib} GiB FP64 (read) and a {gib / 2:g} GiB device copy, best of {reps}"}
+
+
 def run_batch_bench(args):
     """64 independent solves (n ~ U{8..16}, half filled, full space capped at
     2^18 determinants, H ~ U{16..128}, FP64, m = 20, k = 1): one optimisation
@@ -986,6 +1015,9 @@ def main():
         log(f"fp64 reference step: {ms64:.1f} ms, dlambda {fp64_ref['dlambda']:.3e}, "
             f"dE_after {fp64_ref['dE_after']:.3e}")
 
+    hbm_ref = measured_hbm_peak(torch)
+    log(f"measured HBM reference: read {hbm_ref['read_GBps']:.0f} GB/s, copy {hbm_ref['copy_GBps']:.0f} GB/s")
+
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle on a row sample)")
@@ -1027,6 +1059,7 @@ def main():
         "applies_per_step": applies / args.steps,
         "setup_ms": setup_ms,
         "stored_rows": store,
+        "hbm_reference": hbm_ref,
         "fp64_reference": fp64_ref,
         "trajectory": steps,
         "E_final": Ef,
