@@ -220,7 +220,8 @@ def run_batch_bench(args):
     """64 independent solves (n ~ U{8..16}, half filled, full space capped at
     2^18 determinants, H ~ U{16..128}, FP64, m = 20, k = 1): one optimisation
     step each, (a) one after another with the solo path, (b) as batches of
-    grouped kernels admitted in waves by workspace footprint."""
+    grouped kernels admitted in waves by workspace footprint.  --jacobian picks
+    the factored Jacobian (default) or dense D~ copies for both."""
     import numpy as np
     import torch
 
@@ -235,7 +236,7 @@ def run_batch_bench(args):
         h, g = w.integrals()
         systems.append(System(w.n, w.na, w.nb, h, g, dets=w.dets()))
         thetas0.append(torch.tensor(w.theta(), dtype=torch.float64, device="cuda"))
-    fl = B.IRL_WS_FP64
+    fl = B.IRL_WS_FACTORED if args.jacobian == "factored" else B.IRL_WS_FP64
     sizes = [B.irl_workspace_query(s.handle, w.P + 1, fl) for s, w in zip(systems, wls)]
     for s, w in zip(systems, wls):
         s.workspace(w.P + 1, fl)
@@ -329,7 +330,8 @@ def run_batch_bench(args):
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": (f"c4: {len(wls)} independent solves, n ~ U{{8..16}} half filled, "
                                 f"full space capped at 2^18 determinants, H ~ U{{16..128}}, "
-                                f"seeds 0..{len(wls) - 1}, one IRL step each (m=20, k=1, tol=1e-12), FP64"),
+                                f"seeds 0..{len(wls) - 1}, one IRL step each (m=20, k=1, tol=1e-12), FP64, "
+                                + ("factored Jacobian" if args.jacobian == "factored" else "dense D~ copies")),
                    "waves": len(waves), "workspace_GB": sum(sizes) / 1e9,
                    "ham_kernels": {HAM_KERNELS[k]: kernels.count(k) for k in sorted(set(kernels))},
                    "stored_rows_GB": stored_bytes / 1e9},

@@ -1041,7 +1041,7 @@ int irl_step(irl_system *s, irl_nqs_desc *nqs, const irl_solver_opts *opts, void
         return set_err(s, IRL_EINVAL, "bad solver options");
     if (o.mode == IRL_MODE_C && (o.precision != IRL_FP64 || o.block > 1))
         return set_err(s, IRL_EINVAL, "the connected basis (mode C) needs an FP64 single-vector solve");
-    if (o.mode == IRL_MODE_C && s->vmc && (o.flags & IRL_STEP_WS_CURRENT))
+    if (o.mode == IRL_MODE_C && s->vmc && !(nqs && !(o.flags & IRL_STEP_WS_CURRENT)))
         return set_err(s, IRL_EINVAL, "the connected basis (mode C) is not defined on sampled estimators");
     hipStream_t st = (hipStream_t)stream;
     irl_step_result res;
@@ -1328,6 +1328,7 @@ struct ListSet {
     int region = 0;
     int off[LS_KINDS] = {0}, cnt[LS_KINDS] = {0};
     std::vector<int> product;   // members whose H apply is the solo string-product launch
+    std::vector<int> members;   // the subset the lists cover
     int64_t blocks[LS_KINDS] = {0};   // H-row kinds: blocks of the launch (one per 4-row group)
     size_t lds6 = 0;   // dynamic LDS of the grouped D~ v launch
     const WorkItem *ptr(const irl_batch *b, int kind) const { return b->ditems[region] + off[kind]; }
@@ -1365,6 +1366,7 @@ int build_lists(irl_batch *b, const std::vector<int> &subset, int region, int pr
     };
     ls.lds6 = 0;
     ls.product.clear();
+    ls.members = subset;
     // enumerating H rows: most expensive members first, in short items, so the
     // launch does not end on a few long work items
     std::vector<int> by_cost(subset);
@@ -1375,10 +1377,17 @@ int build_lists(irl_batch *b, const std::vector<int> &subset, int region, int pr
                binom_host(s->nb, 2) * binom_host((int)vb, 2);
     };
     std::stable_sort(by_cost.begin(), by_cost.end(), [&](int x, int y) { return row_cost(x) > row_cost(y); });
+    // D~ stream lists only for D~ copies (the factored products are solo launches)
+    const bool dense = !(b->ws_flags & IRL_WS_FACTORED);
     for (int kind = 0; kind < LS_KINDS; ++kind) {
         ls.off[kind] = (int)v.size();
         const bool hrows = kind == LS_ROWS4R || kind == LS_ROWS4H || kind == LS_ROWS4B;
         nblk = 0;
+        if (!dense && (kind == LS_ROWS6 || kind == LS_ROWS5 || kind == LS_T2 || kind == LS_RED)) {
+            ls.cnt[kind] = 0;
+            ls.blocks[kind] = 0;
+            continue;
+        }
         for (int m : (hrows ? by_cost : subset)) {
             const Member &mb = b->hm[m];
             // the stored rows a member uses are those in its view taken at batch create
@@ -1472,8 +1481,18 @@ int batch_apply(irl_batch *b, const ListSet &ls, int vsel, int j, int cur, int s
                 hipStream_t st)
 {
     irl_system *s0 = b->sys[0];
-    TIMED(s0, prec == IRL_FP64 ? IRL_STAT_GEMV : IRL_STAT_GEMV_LO, st, launch_gemv_rows_grouped(b->dm, ls.ptr(b, LS_ROWS6), ls.cnt[LS_ROWS6], prec, vsel, j, cur,
-                                    split, ls.lds6, st));
+    const bool factored = (b->ws_flags & IRL_WS_FACTORED) != 0;
+    if (factored) {
+        // each member's forward product is its solo launch (same kernel, same rows)
+        for (int m : ls.members) {
+            const Member &mb = b->hm[m];
+            const double *v = vsel ? mb.y : mb.kry[cur] + (int64_t)j * mb.ld;
+            TIMED(s0, IRL_STAT_GEMV, st, launch_fac_jvp(b->sys[m], b->lay[m], b->ws[m], v, split, mb.w, st));
+        }
+    } else {
+        TIMED(s0, prec == IRL_FP64 ? IRL_STAT_GEMV : IRL_STAT_GEMV_LO, st, launch_gemv_rows_grouped(b->dm, ls.ptr(b, LS_ROWS6), ls.cnt[LS_ROWS6], prec, vsel, j, cur,
+                                        split, ls.lds6, st));
+    }
     for (int k : {LS_ROWS4R, LS_ROWS4H, LS_ROWS4B})
         if (ls.cnt[k])
             TIMED(s0, IRL_STAT_HAM_APPLY, st,
@@ -1482,6 +1501,17 @@ int batch_apply(irl_batch *b, const ListSet &ls, int vsel, int j, int cur, int s
     if (ls.cnt[LS_ROWS4S])
         TIMED(s0, IRL_STAT_HAM_APPLY, st, launch_ham_stored_grouped(b->dm, ls.ptr(b, LS_ROWS4S), ls.cnt[LS_ROWS4S], ls.blocks[LS_ROWS4S], 0, st));
     for (int m : ls.product) TIMED(s0, IRL_STAT_HAM_APPLY, st, launch_ham_apply(b->sys[m], b->hm[m].w, b->hm[m].u, st));
+    if (factored) {
+        // both backward products in one pass and the fixed-order reduction, per member
+        for (int m : ls.members) {
+            const WsLayout &L = b->lay[m];
+            const Member &mb = b->hm[m];
+            const int nb = fac_row_blocks(L);
+            TIMED(s0, IRL_STAT_GEMV_T, st, launch_fac_vjp(b->sys[m], L, b->ws[m], mb.w, mb.u, nullptr, 0, nb, st));
+            TIMED(s0, IRL_STAT_REDUCE, st, launch_t2_reduce(L, b->ws[m], nb, mb.yS, mb.yH, L.ncols, 1.0, nullptr, st));
+        }
+        return IRL_OK;
+    }
     TIMED(s0, prec == IRL_FP64 ? IRL_STAT_GEMV_T : IRL_STAT_GEMV_T_LO, st, launch_gemv_t2_grouped(b->dm, ls.ptr(b, LS_T2), ls.cnt[LS_T2], prec, 0, st));
     TIMED(s0, IRL_STAT_REDUCE, st, launch_reduce_grouped(b->dm, ls.ptr(b, LS_RED), ls.cnt[LS_RED], 0, st));
     return IRL_OK;
@@ -1505,12 +1535,18 @@ int batch_evaluate(irl_batch *b, const std::vector<int> &subset, hipStream_t st)
 {
     irl_system *s0 = b->sys[0];
     ListSet ls;
-    const int prec = (b->ws_flags & IRL_WS_FP64) ? IRL_FP64 : IRL_FP32;
-    int rc = set_stream_precision(b, prec, st);
+    const bool factored = (b->ws_flags & IRL_WS_FACTORED) != 0;
+    const int prec = (b->ws_flags & (IRL_WS_FP64 | IRL_WS_FACTORED)) ? IRL_FP64 : IRL_FP32;
+    int rc = factored ? IRL_OK : set_stream_precision(b, prec, st);
     if (rc) return rc;
     rc = build_lists(b, subset, 0, prec, ls, st);
     if (rc) return rc;
-    TIMED(s0, IRL_STAT_DTILDE_BUILD, st, launch_nqs_dtilde_grouped(b->dm, ls.ptr(b, LS_ROWS5), ls.cnt[LS_ROWS5], 0, 0, st));
+    if (factored) {
+        for (int m : subset)
+            TIMED(s0, IRL_STAT_DTILDE_BUILD, st, launch_fac_forward(b->sys[m], b->lay[m], b->ws[m], b->nqs[m].theta, st));
+    } else {
+        TIMED(s0, IRL_STAT_DTILDE_BUILD, st, launch_nqs_dtilde_grouped(b->dm, ls.ptr(b, LS_ROWS5), ls.cnt[LS_ROWS5], 0, 0, st));
+    }
     for (int k : {LS_ROWS4R, LS_ROWS4H, LS_ROWS4B})
         if (ls.cnt[k])
             TIMED(s0, IRL_STAT_HAM_APPLY, st,
@@ -1521,7 +1557,16 @@ int batch_evaluate(irl_batch *b, const std::vector<int> &subset, hipStream_t st)
     for (int m : ls.product) TIMED(s0, IRL_STAT_HAM_APPLY, st, launch_ham_apply(b->sys[m], b->hm[m].psi, b->hm[m].hpsi, st));
     TIMED(s0, IRL_STAT_ENERGY, st, launch_energy_grouped(b->dm, ls.ptr(b, LS_E1), ls.cnt[LS_E1], 1, st));
     TIMED(s0, IRL_STAT_ENERGY, st, launch_energy_grouped(b->dm, ls.ptr(b, LS_VEC), ls.cnt[LS_VEC], 2, st));
-    if (prec == IRL_FP64) {
+    if (factored) {
+        // gradient: the solo backward product with c = H psi - E psi, per member
+        for (int m : subset) {
+            const WsLayout &L = b->lay[m];
+            const Member &mb = b->hm[m];
+            const int nb = fac_row_blocks(L);
+            TIMED(s0, IRL_STAT_ENERGY, st, launch_fac_vjp(b->sys[m], L, b->ws[m], mb.hpsi, nullptr, &mb.sc->E_el, 1, nb, st));
+            TIMED(s0, IRL_STAT_REDUCE, st, launch_t2_reduce(L, b->ws[m], nb, nullptr, mb.grad, L.ncols, 2.0, &mb.sc->Z, st));
+        }
+    } else if (prec == IRL_FP64) {
         TIMED(s0, IRL_STAT_GEMV_T, st, launch_gemv_t2_grouped(b->dm, ls.ptr(b, LS_T2), ls.cnt[LS_T2], prec, 1, st));
         TIMED(s0, IRL_STAT_REDUCE, st, launch_reduce_grouped(b->dm, ls.ptr(b, LS_RED), ls.cnt[LS_RED], 1, st));
     } else {
@@ -1547,7 +1592,7 @@ int batch_evaluate(irl_batch *b, const std::vector<int> &subset, hipStream_t st)
         s->ws_valid = true;
         s->vmc = false;
         s->vmc_rows = 0;
-        s->ws_has64 = (b->ws_flags & IRL_WS_FP64) != 0;
+        s->ws_has64 = (b->ws_flags & (IRL_WS_FP64 | IRL_WS_FACTORED)) != 0;
         s->ws_has32 = (b->ws_flags & IRL_WS_FP32) != 0;
         if (!(s->Z > 0.0) || !std::isfinite(s->E_el))
             return set_err(s0, IRL_EINVAL, "batch member " + std::to_string(m) + ": psi^T psi is zero or the energy is not finite");
@@ -1699,9 +1744,11 @@ int irl_batch_create(int32_t count, irl_system *const *systems, const irl_nqs_de
     if (!out) return IRL_EINVAL;
     *out = nullptr;
     if (count < 1 || !systems || !nqs || !ws || !ws_bytes) return set_err(nullptr, IRL_EINVAL, "bad batch arguments");
-    if (!(ws_flags & (IRL_WS_FP64 | IRL_WS_FP32))) return set_err(nullptr, IRL_EINVAL, "ws_flags names no D~ copy");
-    if (ws_flags & IRL_WS_FACTORED)
-        return set_err(nullptr, IRL_EINVAL, "batches stream D~ copies (IRL_WS_FACTORED is not supported)");
+    if (!(ws_flags & (IRL_WS_FP64 | IRL_WS_FP32 | IRL_WS_FACTORED)))
+        return set_err(nullptr, IRL_EINVAL, "ws_flags names no D~ copy and no factored Jacobian");
+    if ((ws_flags & IRL_WS_FACTORED) && (ws_flags & (IRL_WS_FP64 | IRL_WS_FP32)))
+        return set_err(nullptr, IRL_EINVAL, "batch workspaces hold either D~ copies or the factored Jacobian");
+    if (ws_flags & IRL_WS_SAMPLED) return set_err(nullptr, IRL_EINVAL, "batches use the exact estimators");
     irl_batch *b = new irl_batch();
     b->B = count;
     b->ws_flags = ws_flags;
@@ -1711,6 +1758,7 @@ int irl_batch_create(int32_t count, irl_system *const *systems, const irl_nqs_de
         for (int k = 0; k < i; ++k)
             if (systems[k] == s) { delete b; return set_err(nullptr, IRL_EINVAL, "a system appears twice in a batch"); }
         if (nqs[i].V != 2 * s->n || nqs[i].H < 1 || nqs[i].H > 1024) { delete b; return set_err(nullptr, IRL_EINVAL, "bad network size in batch member " + std::to_string(i)); }
+        if ((ws_flags & IRL_WS_FACTORED) && nqs[i].V > 64) { delete b; return set_err(nullptr, IRL_EINVAL, "the factored Jacobian needs V <= 64"); }
         const int64_t P = (int64_t)nqs[i].V * nqs[i].H + nqs[i].H + nqs[i].V;
         WsLayout L = make_layout(s->ns, P + 1, ws_flags, nqs[i].V);
         if (L.ldv > 8192) { delete b; return set_err(nullptr, IRL_EINVAL, "batch members need P + 1 <= 8192"); }
@@ -1796,9 +1844,9 @@ int irl_batch_step(irl_batch *b, const irl_solver_opts *opts, double *const *dth
         o.max_restarts < 0 || (o.mode != IRL_MODE_A && o.mode != IRL_MODE_P))
         return set_err(s0, IRL_EINVAL, "bad solver options");
     if (o.block > 1) return set_err(s0, IRL_EINVAL, "batches step with single-vector Lanczos (block must be 0 or 1)");
-    if ((o.precision == IRL_FP64 && !(b->ws_flags & IRL_WS_FP64)) ||
+    if ((o.precision == IRL_FP64 && !(b->ws_flags & (IRL_WS_FP64 | IRL_WS_FACTORED))) ||
         (o.precision == IRL_FP32 && !(b->ws_flags & IRL_WS_FP32)))
-        return set_err(s0, IRL_ESTATE, "batch workspaces hold no D~ copy for this precision");
+        return set_err(s0, IRL_ESTATE, "batch workspaces hold no D~ copy or factored Jacobian for this precision");
     hipStream_t st = (hipStream_t)stream;
     const int B = b->B;
     std::vector<int> all(B);

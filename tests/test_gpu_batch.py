@@ -81,6 +81,49 @@ def test_batch_equals_solo_bitwise(m, k, kernels):
     bt.close()
 
 
+@pytest.mark.parametrize("kernels", ["default", "stored"])
+def test_batch_factored_equals_solo_bitwise(kernels):
+    """Factored-Jacobian workspaces: each member's forward and backward products
+    are its solo launches inside the lockstep batch, so every member equals its
+    solo factored step bit for bit (string-product, beta-blocked and stored-row
+    Hamiltonians)."""
+    from paper_2601_01437_amd import IRL_WS_FACTORED, Batch
+    announce(f"batch factored vs solo kernels={kernels}")
+    flags_full, store, flags_sel = KERNELS[kernels]
+    solo = _build(flags_full, store, flags_sel)
+    ref = []
+    for s, theta, V, H, *_ in solo:
+        th = dev(theta)
+        rc, r, dth, _ = s.step(th, V, H, m=20, k_keep=2, ws_flags=IRL_WS_FACTORED)
+        ref.append((rc, r, host(dth), host(th)))
+    batch_sys = _build(flags_full, store, flags_sel)
+    thetas = [dev(t) for _, t, *_ in batch_sys]
+    bt = Batch([x[0] for x in batch_sys], thetas, [x[2] for x in batch_sys], [x[3] for x in batch_sys],
+               ws_flags=IRL_WS_FACTORED)
+    for step_no in range(2):
+        res, status, dth = bt.step(m=20, k_keep=2, want_dtheta=True)
+        if step_no == 0:
+            for i, (rc, r, d_ref, th_ref) in enumerate(ref):
+                assert status[i] == rc, i
+                assert _fields(res[i]) == _fields(r), (i, _fields(res[i]), _fields(r))
+                assert np.array_equal(host(dth[i]), d_ref), i
+                assert np.array_equal(host(thetas[i]), th_ref), i
+    # a second step of each solo system matches the batch's second step
+    for i, (s, theta, V, H, *_) in enumerate(solo):
+        th = dev(ref[i][3])
+        rc, r, _, _ = s.step(th, V, H, m=20, k_keep=2, ws_flags=IRL_WS_FACTORED)
+        assert _fields(res[i]) == _fields(r), i
+    bt.close()
+
+
+def test_batch_factored_rejects_mixed_flags():
+    from paper_2601_01437_amd import IRL_WS_FACTORED, IRL_WS_FP64, IrlError, Batch
+    mem = _build(0)[:2]
+    with pytest.raises(IrlError):
+        Batch([x[0] for x in mem], [dev(t) for _, t, *_ in mem], [x[2] for x in mem], [x[3] for x in mem],
+              ws_flags=IRL_WS_FACTORED | IRL_WS_FP64)
+
+
 def test_batch_matches_oracle():
     from paper_2601_01437_amd import Batch
     announce("batch vs oracle")
