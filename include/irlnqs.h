@@ -430,6 +430,10 @@ int irl_vmc_sample(irl_system *sys, void *ws, size_t ws_bytes, const double *u, 
  * kernel its system uses when the batch is created: string-product members
  * get their own launch, stored-row and per-determinant members share grouped
  * launches (rows stored after batch create are not used by the batch).
+ * ws_flags: D~ copies (IRL_WS_FP64 and/or IRL_WS_FP32; the D~ streams are
+ * grouped too) or IRL_WS_FACTORED alone (each member's network products are
+ * its solo launches, issued inside the lockstep loop; V <= 64); not
+ * IRL_WS_SAMPLED.
  * systems[i], nqs[i] and ws[i] (sized by irl_workspace_query for P_i + 1
  * columns and ws_flags) are borrowed and must stay alive while the batch
  * exists; a system must not be used by two members.  Requires
