@@ -352,8 +352,9 @@ def run_serving_bench(args):
     or c3 system) arrive as a Poisson process (20/s, seed 0) over about
     args.serve_seconds; the mix is chosen so the offered load is 0.7 of the
     measured one-at-a-time capacity.  Served with resident slots per class and
-    one lane per class (FP32 operator, FP64 solver), then against the plain
-    sequential FP64 schedule of the same arrivals."""
+    one lane per class (FP32 operator with the FP64 solver, or FP64 through the
+    factored Jacobian), then against the plain sequential FP64 schedule (dense
+    D~ copies) of the same arrivals."""
     import numpy as np
     import torch
 
@@ -369,14 +370,16 @@ def run_serving_bench(args):
     dets = {c: wl[c].dets() for c in names}
     slots = {"c1": 16, "c2": 8, "c3": 1}
 
-    def make_pools(precision, nslots):
+    factored = args.serve_operator == "fp64-factored"
+
+    def make_pools(precision, nslots, fac=False):
         pools = {}
         for c in names:
             w = wl[c]
             h, g = ints[c]
             pools[c] = ClassPool(ClassSpec(c, w.n, w.na, w.nb, w.V, w.H, h, g, dets=dets[c], m=w.m,
                                            k_keep=w.k, precision=precision, slots=nslots[c],
-                                           store_rows_bytes=32 << 30))
+                                           store_rows_bytes=32 << 30, factored=fac))
         torch.cuda.synchronize()
         return pools
 
@@ -394,11 +397,11 @@ def run_serving_bench(args):
         return out
 
     t_setup = time.perf_counter()
-    pools = make_pools(B.IRL_FP32, slots)
+    pools = make_pools(B.IRL_FP64 if factored else B.IRL_FP32, slots, factored)
     log(f"resident pools ready in {time.perf_counter() - t_setup:.1f} s: "
         + ", ".join(f"{c} {len(p.systems)} slots {p.device_bytes() / 1e9:.1f} GB" for c, p in pools.items()))
     svc = service_ms(pools, {"c1": 5, "c2": 3, "c3": 1})
-    log("one-at-a-time FP32 service ms: " + ", ".join(f"{c} {v:.1f}" for c, v in svc.items()))
+    log(f"one-at-a-time {args.serve_operator} service ms: " + ", ".join(f"{c} {v:.1f}" for c, v in svc.items()))
     # mix c1 : c2 : c3 = (1 - 6x) : 5x : x with offered load rate * E[service] = 0.7
     t1, t2, t3 = (svc[c] / 1e3 for c in names)
     x = (0.7 / rate - t1) / (5 * t2 + t3 - 6 * t1)
@@ -462,20 +465,21 @@ def run_serving_bench(args):
         "n_gpus": 1, "steps": n_req, "warmup": 1,
         "ms_per_step": lat["all"]["p50_ms"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32 operator, f64 solver", "data": "synthetic",
+        "dtype": "f64 (factored Jacobian)" if factored else "f32 operator, f64 solver", "data": "synthetic",
         "config": {"workload": (f"c5: Poisson arrivals {rate:g}/s seed 0, {n_req} requests, each one IRL "
                                 f"step of a fresh network (theta seed 1000 + request) on the c1 (4,900 "
                                 f"full), c2 (853,776 full) or c3 (2^20 selected, stored rows) system; "
-                                f"continuous admission into resident slots, one lane per class"),
+                                f"continuous admission into resident slots, one lane per class, "
+                                f"{'FP64 factored-Jacobian' if factored else 'FP32'} operator"),
                    "mix": mix, "offered_load": offered, "slots": slots,
-                   "service_ms_fp32": svc, "service_ms_fp64": svc64},
+                   "service_ms_served": svc, "service_ms_fp64_dense": svc64},
         "latency_ms": lat,
         "mean_batch_size": float(np.mean(batch_sizes)),
         "makespan_s": makespan,
         "sequential_fp64": {"solves_per_s": n_req / makespan64, "makespan_s": makespan64,
                             "latency_ms": lat64},
         "mix_equals_alone": {"checked": checked, "bitwise_equal": equal},
-        "max_abs_dE_after_fp32_vs_fp64": float(max(dE)) if dE else None,
+        "max_abs_dE_after_served_vs_fp64_dense": float(max(dE)) if dE else None,
     }
     print(json.dumps(out), flush=True)
 
@@ -813,6 +817,9 @@ def main():
                     help="ablation: draws per step of the sampled-estimator IRL run (0: skip it)")
     ap.add_argument("--ablation-irl", type=int, nargs=2, default=[20, 1], metavar=("M", "K"),
                     help="ablation: IRL Krylov dimension and vectors kept per restart")
+    ap.add_argument("--serve-operator", default="fp32", choices=["fp32", "fp64-factored"],
+                    help="c5: operator of the served classes (FP32 D~ copy with the FP64 solver, "
+                         "or FP64 through the factored Jacobian)")
     ap.add_argument("--serve-seconds", type=float, default=20.0,
                     help="c5: length of the arrival window in seconds")
     ap.add_argument("--solves", type=int, default=64, help="c4: number of independent solves")

@@ -61,6 +61,7 @@ class ClassSpec:
     precision: int = B.IRL_FP32
     slots: int = 1
     store_rows_bytes: int = 0     # device bytes allowed for stored H rows per slot
+    factored: bool = False        # FP64 through the factored Jacobian instead of a D~ copy
 
     @property
     def P(self) -> int:
@@ -68,7 +69,9 @@ class ClassSpec:
 
     @property
     def ws_flags(self) -> int:
-        return B.IRL_WS_FP64 if self.precision == B.IRL_FP64 else B.IRL_WS_FP32
+        if self.precision == B.IRL_FP64:
+            return B.IRL_WS_FACTORED if self.factored else B.IRL_WS_FP64
+        return B.IRL_WS_FP32
 
 
 class ClassPool:

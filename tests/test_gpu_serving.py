@@ -16,7 +16,7 @@ def _gpu():
     require_gpu()
 
 
-def _pools(precision):
+def _pools(precision, factored=False):
     from paper_2601_01437_amd.serving import ClassPool, ClassSpec
     specs = {}
     for name, (n, na, nb, H, sel) in {"a": (6, 3, 3, 8, None), "b": (8, 4, 4, 16, None),
@@ -25,16 +25,17 @@ def _pools(precision):
         dets = None if sel is None else synth.cisd_like_selected_set(n, na, nb, sel, seed=7)
         specs[name] = ClassPool(ClassSpec(name, n, na, nb, 2 * n, H, h, g, dets=dets, m=20, k_keep=1,
                                           precision=precision, slots=4,
-                                          store_rows_bytes=(1 << 30) if name == "s" else 0))
+                                          store_rows_bytes=(1 << 30) if name == "s" else 0,
+                                          factored=factored))
     return specs
 
 
-@pytest.mark.parametrize("fp32", [False, True])
-def test_serving_results_equal_alone(fp32):
+@pytest.mark.parametrize("fp32,factored", [(False, False), (True, False), (False, True)])
+def test_serving_results_equal_alone(fp32, factored):
     from paper_2601_01437_amd import IRL_FP32, IRL_FP64
     from paper_2601_01437_amd.serving import Request, Server
-    announce(f"serving lanes fp32={fp32}")
-    pools = _pools(IRL_FP32 if fp32 else IRL_FP64)
+    announce(f"serving lanes fp32={fp32} factored={factored}")
+    pools = _pools(IRL_FP32 if fp32 else IRL_FP64, factored)
     arr, picks = synth.serving_arrivals(60, 120.0, {"a": 0.5, "b": 0.3, "s": 0.2}, seed=1)
     reqs = [Request(i, picks[i], float(arr[i]),
                     synth.nqs_theta(pools[picks[i]].spec.V, pools[picks[i]].spec.H, 50 + i, scale=0.2))

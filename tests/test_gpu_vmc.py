@@ -224,3 +224,43 @@ def test_vmc_errors():
     s.vmc_sample(u)
     with pytest.raises(IrlError):                   # mode C on sampled estimators
         s.step(theta, 10, 4, m=16, k_keep=2, mode=IRL_MODE_C, ws_flags=IRL_WS_FP64, flags=IRL_STEP_WS_CURRENT)
+
+
+def test_vmc_edge_draws():
+    """One draw; u at the ends of [0, 1) and outside it (clamped: below 0 and NaN
+    act as 0, 1 and above as the largest u below 1); rows with psi = 0 are never
+    drawn, even where u lands exactly on their (empty) interval."""
+    from paper_2601_01437_amd import IRL_WS_FP64
+    announce("vmc edge draws")
+    n, na, nb = 5, 2, 2
+    s, h, g = _system(n, na, nb, seed=7)
+    keys = space.full_space(n, na, nb)
+    Hm = hamiltonian.build(keys, n, h, g)
+    rng = np.random.default_rng(8)
+    psi = rng.normal(size=keys.size)
+    zero = [0, 1, 17, keys.size - 1]          # first, last and interior rows with psi = 0
+    psi[zero] = 0.0
+    D = np.concatenate([psi[:, None], rng.normal(size=(keys.size, 12))], axis=1)
+    s.set_dtilde(dev(D), ws_flags=IRL_WS_FP64)
+    nz = np.nonzero(psi)[0]
+    below_one = np.nextafter(1.0, 0.0)
+    # one draw at u = 0: the first row with psi != 0, and E is its local energy
+    out, rows, _ = s.vmc_sample(dev(np.array([0.0])), want_rows=True)
+    Eloc = vmc.local_energy(psi, Hm)
+    assert host(rows)[0] == nz[0] and out.n_unique == 1
+    assert abs(out.E_sampled - Eloc[nz[0]]) <= 1e-12 * max(1.0, abs(Eloc[nz[0]]))
+    u = np.array([0.0, below_one, -0.25, np.nan, 1.0, 7.5, -np.inf, np.inf])
+    out, rows, _ = s.vmc_sample(dev(u), want_rows=True)
+    r = host(rows)
+    assert r[0] == nz[0]
+    assert r[1] == nz[-1]
+    assert r[2] == r[0] and r[3] == r[0] and r[6] == r[0]
+    assert r[4] == r[1] and r[5] == r[1] and r[7] == r[1]
+    # inner boundaries: u exactly at the cumulative weight of a zero row's start
+    c = np.cumsum(psi ** 2)
+    ub = np.array([c[16] / c[-1], c[17] / c[-1], 0.5])
+    out, rows, _ = s.vmc_sample(dev(ub), want_rows=True)
+    r = host(rows)
+    assert not np.isin(r, zero).any()
+    ref = vmc.sample_autoregressive(keys, n, na, nb, psi, ub)
+    assert _check_rows(r, ref, psi, ub) <= 3
