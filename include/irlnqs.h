@@ -107,8 +107,19 @@ enum irl_step_flags {
     IRL_STEP_NO_EVAL_AFTER = 2u, /* do not evaluate E(theta + dtheta) after the update */
     IRL_STEP_NO_UPDATE = 4u,     /* solve only; leave theta unchanged */
     IRL_STEP_NO_POLISH = 8u,     /* FP32 solve: skip the FP64 polish (see irl_step) */
-    IRL_STEP_FULL_CYCLES = 16u   /* test convergence only at the end of each m-step cycle
+    IRL_STEP_FULL_CYCLES = 16u,  /* test convergence only at the end of each m-step cycle
                                     (no early Ritz tests inside a cycle) */
+    IRL_STEP_GRAPH = 32u         /* single-vector solves that test only at the end of a
+                                    cycle (operators under 256 MB per apply, or
+                                    IRL_STEP_FULL_CYCLES): capture each cycle kind (the
+                                    first, a restart from either basis) once as a HIP
+                                    graph on a library stream and replay it on the
+                                    caller's stream; results equal the launched path bit
+                                    for bit.  The graphs are kept with the system, keyed
+                                    on the workspace, sizes, mode, precision, seed and the
+                                    Hamiltonian and sampling state, and rebuilt when any
+                                    changes; ignored while per-kernel timing is on; a
+                                    capture that fails falls back to launches. */
 };
 
 /* K4 variant selection (irl_system_desc.flags) */

@@ -64,9 +64,13 @@ int dev_alloc(irl_system *s, T **p, size_t count)
     return IRL_OK;
 }
 
+void free_cycle_graphs(irl_system *s);
+
 void free_system(irl_system *s)
 {
     if (!s) return;
+    free_cycle_graphs(s);
+    if (s->capture_stream) (void)hipStreamDestroy(s->capture_stream);
     free_dense_doubles(s);
     void *ptrs[] = {s->d.keys, s->d.h, s->d.g, s->d.diag, s->d.hkeys, s->d.hrows, s->d.rankA,
                     s->d.rankB, s->d.strA, s->d.strB, s->d.sglA, s->d.sglB, s->d.fA, s->d.fB,
@@ -359,6 +363,124 @@ struct SolveOut {
     int n_apply = 0, n_restart = 0, converged = 0;
 };
 
+// ---- captured Lanczos cycles -------------------------------------------------
+// On operators small enough that the solve is launch-bound (no in-cycle tests),
+// a whole cycle -- the m - j0 applies with their Lanczos steps and the Ritz /
+// restart-shift kernel, preceded by the basis restart for the restart cycles --
+// is captured once into a HIP graph and replayed: the first cycle (basis 0) and
+// the restart cycles from basis 0 and from basis 1.  The seeds of the captured
+// kernels are the solve's seed; the per-cycle seed is derived on the device from
+// the restart count, so a replay runs exactly the eager arithmetic.  The graphs
+// hold the workspace's pointers and every launch shape of the apply, so they are
+// keyed on all of them and rebuilt when any changes (one entry per precision).
+struct CycleKey {
+    void *ws = nullptr;
+    size_t total = 0;
+    int64_t ns = 0, ncols = 0;
+    uint32_t flags = 0;
+    int m = 0, k = 0, mode = 0, prec = 0, ham_kernel = -1;
+    uint64_t seed = 0;
+    bool vmc = false;
+    int64_t vmc_rows = 0;
+    const void *hptr = nullptr;
+    bool operator==(const CycleKey &o) const
+    {
+        return ws == o.ws && total == o.total && ns == o.ns && ncols == o.ncols && flags == o.flags && m == o.m &&
+               k == o.k && mode == o.mode && prec == o.prec && ham_kernel == o.ham_kernel && seed == o.seed &&
+               vmc == o.vmc && vmc_rows == o.vmc_rows && hptr == o.hptr;
+    }
+};
+
+struct CycleEntry {
+    CycleKey key;
+    bool valid = false, failed = false;
+    hipGraphExec_t exec[3] = {nullptr, nullptr, nullptr};   // first cycle, restart from basis 0, from basis 1
+};
+
+struct CycleGraphs {
+    CycleEntry e[2];   // by precision
+};
+
+void drop_entry(CycleEntry &c)
+{
+    for (auto &x : c.exec)
+        if (x) {
+            (void)hipGraphExecDestroy(x);
+            x = nullptr;
+        }
+    c.valid = false;
+    c.failed = false;
+}
+
+void free_cycle_graphs(irl_system *s)
+{
+    if (!s || !s->cycle_graphs) return;
+    CycleGraphs *g = static_cast<CycleGraphs *>(s->cycle_graphs);
+    for (auto &c : g->e) drop_entry(c);
+    delete g;
+    s->cycle_graphs = nullptr;
+}
+
+CycleEntry *cycle_entry(irl_system *s, const CycleKey &key)
+{
+    if (!s->cycle_graphs) s->cycle_graphs = new CycleGraphs();
+    CycleEntry &c = static_cast<CycleGraphs *>(s->cycle_graphs)->e[key.prec == IRL_FP64 ? 0 : 1];
+    if (!c.valid || !(c.key == key)) {
+        drop_entry(c);
+        c.key = key;
+        c.valid = true;
+    }
+    return c.failed ? nullptr : &c;
+}
+
+int apply_internal(irl_system *s, void *ws, const WsLayout &L, const double *v, double *yH, double *yS, int prec,
+                   hipStream_t st, int zero_v0);
+
+// capture cycle `kind` (0: first cycle from basis 0; 1, 2: restart from basis
+// kind - 1, then the cycle from k on the other basis) on the library's capture
+// stream; false if any launch or the capture itself fails (eager path then)
+bool capture_cycle(irl_system *s, void *ws, const WsLayout &L, const irl_solver_opts &o, int prec, int m,
+                   int k, int kind, hipGraphExec_t *out)
+{
+    if (!s->capture_stream && hipStreamCreateWithFlags(&s->capture_stream, hipStreamNonBlocking) != hipSuccess) {
+        s->capture_stream = nullptr;
+        return false;
+    }
+    hipStream_t cs = s->capture_stream;
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    const int split = (prec == IRL_FP32) ? 1 : 0;
+    double *Vb[2] = {ws_ptr<double>(ws, L.off_kry0), ws_ptr<double>(ws, L.off_kry1)};
+    double *Ib[2] = {ws_ptr<double>(ws, L.off_img0), ws_ptr<double>(ws, L.off_img1)};
+    double *yH = ws_ptr<double>(ws, L.off_yh), *yS = ws_ptr<double>(ws, L.off_ys);
+    bool ok = true;
+    int cur = 0, j0 = 0;
+    if (kind > 0) {
+        cur = kind - 1;
+        ok = launch_restart_basis(L, ws, Vb[cur], Vb[1 - cur], Ib[cur], Ib[1 - cur], m, k, o.mode, o.seed, cs) ==
+             hipSuccess;
+        cur = 1 - cur;
+        j0 = k;
+    }
+    for (int j = j0; ok && j < m; ++j) {
+        ok = apply_internal(s, ws, L, Vb[cur] + (int64_t)j * L.ldv, yH, yS, prec, cs, split) == IRL_OK &&
+             launch_lanczos_step(L, ws, Vb[cur], Ib[cur], j, o.mode, split, o.seed, cs) == hipSuccess;
+    }
+    if (ok) ok = launch_ritz(L, ws, m, k, cs) == hipSuccess;
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(cs, &g);
+    ok = ok && e == hipSuccess && g;
+    if (ok) ok = hipGraphInstantiate(out, g, nullptr, nullptr, 0) == hipSuccess;
+    if (g) (void)hipGraphDestroy(g);
+    if (!ok) {
+        *out = nullptr;
+        (void)hipGetLastError();
+    }
+    return ok;
+}
+
 int irl_solve(irl_system *s, void *ws, const WsLayout &L, const irl_solver_opts &o, int prec,
               const double *start, SolveOut &out, hipStream_t st)
 {
@@ -391,16 +513,54 @@ int irl_solve(irl_system *s, void *ws, const WsLayout &L, const irl_solver_opts 
     // stream synchronisation, negligible next to an apply that streams >= 256 MB.
     const double apply_bytes = 2.0 * (double)L.ns * (double)L.ldv * (prec == IRL_FP64 ? 8.0 : 4.0);
     const int stride = (o.flags & IRL_STEP_FULL_CYCLES) ? 0 : (apply_bytes >= 2.56e8 ? kCheckStride : 0);
+    // graph replay of whole cycles (launch-bound solves without in-cycle tests)
+    CycleEntry *cg = nullptr;
+    if ((o.flags & IRL_STEP_GRAPH) && stride == 0 && !s->stats_on) {
+        CycleKey key;
+        key.ws = ws;
+        key.total = L.total;
+        key.ns = L.ns;
+        key.ncols = L.ncols;
+        key.flags = L.flags;
+        key.m = m;
+        key.k = k;
+        key.mode = o.mode;
+        key.prec = prec;
+        key.ham_kernel = s->ham_kernel;
+        key.seed = o.seed;
+        key.vmc = s->vmc;
+        key.vmc_rows = s->vmc_rows;
+        key.hptr = s->d.hptr;
+        cg = cycle_entry(s, key);
+    }
+    int pending = -1;   // restart not yet launched: from basis `pending` (graph replay)
     for (;;) {
         int mc = m;   // size of the tridiagonal tested at the end of this pass
         bool early = false;
+        const int kind = pending >= 0 ? 1 + pending : (j0 == 0 && cur == 0 ? 0 : -1);
+        if (cg && kind >= 0 && !cg->exec[kind] && !capture_cycle(s, ws, L, o, prec, m, k, kind, &cg->exec[kind])) {
+            cg->failed = true;
+            cg = nullptr;
+        }
+        if (!cg && pending >= 0) {
+            // capture failed after a restart was deferred: launch it eagerly
+            TIMED(s, IRL_STAT_RITZ, st,
+                  launch_restart_basis(L, ws, Vb[pending], Vb[1 - pending], Ib[pending], Ib[1 - pending], m, k,
+                                       o.mode, o.seed, st));
+            pending = -1;
+        }
+        if (cg && kind >= 0) {
+            CK(s, hipGraphLaunch(cg->exec[kind], st));
+            n_apply += m - j0;
+            pending = -1;
+        } else {
         for (int j = j0; j < m; ++j) {
             rc = apply_internal(s, ws, L, Vb[cur] + (int64_t)j * L.ldv, yH, yS, prec, st, split);
             if (rc) return rc;
             ++n_apply;
             TIMED(s, IRL_STAT_LANCZOS, st,
                   launch_lanczos_step(L, ws, Vb[cur], Ib[cur], j, o.mode, split,
-                                      o.seed + 0x100000001b3ull * (uint64_t)(n_restart + 1), st));
+                                      o.seed, st));
             if (stride && j + 1 < m && j + 1 >= 2 && (j + 1 - j0) % stride == 0) {
                 TIMED(s, IRL_STAT_RITZ, st, launch_ritz(L, ws, j + 1, 0, st));
                 rc = read_scalars(s, ws, L, st);
@@ -414,6 +574,7 @@ int irl_solve(irl_system *s, void *ws, const WsLayout &L, const irl_solver_opts 
             }
         }
         if (!early) TIMED(s, IRL_STAT_RITZ, st, launch_ritz(L, ws, m, k, st));
+        }
         rc = read_scalars(s, ws, L, st);
         if (rc) return rc;
         const WsScalars &hs = *s->host_scal;
@@ -443,9 +604,13 @@ int irl_solve(irl_system *s, void *ws, const WsLayout &L, const irl_solver_opts 
             continue;
         }
         if (n_restart >= o.max_restarts) break;
-        TIMED(s, IRL_STAT_RITZ, st,
-              launch_restart_basis(L, ws, Vb[cur], Vb[1 - cur], Ib[cur], Ib[1 - cur], m, k, o.mode,
-                                   o.seed ^ (0x9e3779b97f4a7c15ull * (uint64_t)(n_restart + 7)), st));
+        if (cg) {
+            pending = cur;   // the restart opens the next captured cycle
+        } else {
+            TIMED(s, IRL_STAT_RITZ, st,
+                  launch_restart_basis(L, ws, Vb[cur], Vb[1 - cur], Ib[cur], Ib[1 - cur], m, k, o.mode,
+                                       o.seed, st));
+        }
         cur = 1 - cur;
         j0 = k;
         ++n_restart;
@@ -1699,7 +1864,7 @@ int batch_solve(irl_batch *b, const irl_solver_opts &o, int prec, bool from_y,
             if (rc) return rc;
             for (int i : active) out[i].n_apply += 1;
             TIMED(s0, IRL_STAT_LANCZOS, st, launch_lanczos_grouped(kGrpLanczos, b->dm, la.ptr(b, LS_VEC), la.cnt[LS_VEC], j, cur, o.mode, split,
-                                          o.seed + 0x100000001b3ull * (uint64_t)(n_restart + 1), nullptr, st));
+                                          o.seed, nullptr, st));
             if (j + 1 < m && j + 1 >= 2 && (j + 1 - j0) % kCheckStride == 0) {
                 std::vector<int> who;
                 for (int i : active)
@@ -1726,7 +1891,7 @@ int batch_solve(irl_batch *b, const irl_solver_opts &o, int prec, bool from_y,
             break;
         }
         TIMED(s0, IRL_STAT_RITZ, st, launch_lanczos_grouped(kGrpRestart, b->dm, la.ptr(b, LS_VEC), la.cnt[LS_VEC], cur, m, k, o.mode,
-                                      o.seed ^ (0x9e3779b97f4a7c15ull * (uint64_t)(n_restart + 7)), nullptr, st));
+                                      o.seed, nullptr, st));
         cur = 1 - cur;
         j0 = k;
         ++n_restart;

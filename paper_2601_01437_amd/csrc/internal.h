@@ -38,7 +38,7 @@ struct WsScalars {
     double gap;
     double c0;
     int32_t breakdowns;  // Lanczos breakdowns in the current solve
-    int32_t pad0;
+    int32_t restarts;    // implicit restarts done in the current solve (seeds derive from it)
     double alpha[kMaxKrylov];
     double beta[kMaxKrylov];
     double ritz[kMaxKrylov];
@@ -207,6 +207,9 @@ struct irl_system {
     irl::WsScalars *host_scal = nullptr;
     // dense BLAS handle (rocblas_handle) for the same-spin doubles of a full space
     void *blas = nullptr;
+    // captured Lanczos cycles (graph replay of small operators); owned by api.hip
+    void *cycle_graphs = nullptr;
+    hipStream_t capture_stream = nullptr;
     // per-kernel timing
     bool stats_on = false;
     std::vector<hipEvent_t> ev_pool;

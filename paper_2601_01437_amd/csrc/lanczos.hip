@@ -166,6 +166,8 @@ __device__ void lanczos_step_body(
     __shared__ double sh[kVecWaves * (kMaxKrylov + 1)];
     __shared__ double hsh[kMaxKrylov + 1];
     const double Z = sc->Z, E = sc->E_el;
+    // this cycle's seed: the solve's seed advanced by the restarts done so far
+    const uint64_t sd = seed + 0x100000001b3ull * (uint64_t)(sc->restarts + 1);
     const double *vj = V + (int64_t)j * ldv;
     double *w = V + (int64_t)(j + 1) * ldv;
     const int64_t L = ldv;
@@ -196,7 +198,7 @@ __device__ void lanczos_step_body(
     double normT = fmax(sc->normT, fmax(fabs(alpha), beta));
     if (beta <= 1e3 * 1.1102230246251565e-16 * normT) {
         // invariant subspace: continue with a fresh vector, T decouples
-        fresh_vector(V, ldv, j + 1, w, L, ncols, mode, seed ^ (0x5bd1e995ull * (uint64_t)(j + 1 + 64 * sc->breakdowns)), sh, hsh);
+        fresh_vector(V, ldv, j + 1, w, L, ncols, mode, sd ^ (0x5bd1e995ull * (uint64_t)(j + 1 + 64 * sc->breakdowns)), sh, hsh);
         beta = 0.0;
         if (threadIdx.x == 0) sc->breakdowns += 1;
     } else {
@@ -377,6 +379,7 @@ __device__ void restart_basis_body(WsScalars *sc, const double *Vold, double *Vn
     __shared__ double sh[kVecWaves * (kMaxKrylov + 1)];
     __shared__ double hsh[kMaxKrylov + 1];
     __shared__ double Qs[kMaxKrylov * (kMaxKrylov + 1)];
+    const uint64_t sd = seed ^ (0x9e3779b97f4a7c15ull * (uint64_t)(sc->restarts + 7));
     for (int i = threadIdx.x; i < m * (k + 1); i += kVecThreads) Qs[i] = sc->Q[i];
     __syncthreads();
     const double bk = sc->tbeta[k - 1];
@@ -408,7 +411,7 @@ __device__ void restart_basis_body(WsScalars *sc, const double *Vold, double *Vn
     for (int i = 0; i + 1 < k; ++i) normT = fmax(normT, fabs(sc->tbeta[i]));
     normT = fmax(normT, nrm);
     if (nrm <= 1e3 * 1.1102230246251565e-16 * normT) {
-        fresh_vector(Vnew, ldv, k, f, ldv, ncols, mode, seed ^ 0x27d4eb2f165667c5ull, sh, hsh);
+        fresh_vector(Vnew, ldv, k, f, ldv, ncols, mode, sd ^ 0x27d4eb2f165667c5ull, sh, hsh);
         nrm = 0.0;
     } else {
         for (int64_t c = threadIdx.x; c < ldv; c += kVecThreads) f[c] /= nrm;
@@ -419,6 +422,7 @@ __device__ void restart_basis_body(WsScalars *sc, const double *Vold, double *Vn
         for (int i = 0; i + 1 < k; ++i) sc->beta[i] = sc->tbeta[i];
         sc->beta[k - 1] = nrm;
         sc->normT = normT;
+        sc->restarts += 1;
     }
 }
 
@@ -598,6 +602,7 @@ __global__ void k_reset_solve(WsScalars *sc)
     if (threadIdx.x == 0) {
         sc->normT = 0.0;
         sc->breakdowns = 0;
+        sc->restarts = 0;
         sc->resid2 = 0.0;
     }
 }
@@ -972,6 +977,7 @@ __global__ void k_reset_grouped(const Member *__restrict__ M, const WorkItem *__
         WsScalars *sc = M[items[blockIdx.x].m].sc;
         sc->normT = 0.0;
         sc->breakdowns = 0;
+        sc->restarts = 0;
         sc->resid2 = 0.0;
     }
 }

@@ -163,5 +163,6 @@ def test_factored_errors():
     s.evaluate(10, 4, theta, ws_flags=_fl())
     with pytest.raises(IrlError):                   # multi-vector applies need a D~ copy
         s.apply_block(dev(np.ones((2, 55))))
-    with pytest.raises(IrlError):                   # batches stream D~ copies
-        Batch([s], [theta], [10], [4], ws_flags=_fl())
+    with pytest.raises(IrlError):                   # a batch holds D~ copies or the factored Jacobian
+        from paper_2601_01437_amd import IRL_WS_FP64
+        Batch([s], [theta], [10], [4], ws_flags=_fl() | IRL_WS_FP64)
