@@ -516,7 +516,8 @@ def run_ablation_bench(args):
         t0 = time.perf_counter()
         for it in range(cap):
             rc, r, _, _ = sysm.step(th, wl.V, wl.H, m=m, k_keep=k, tol=1e-12, max_restarts=restarts,
-                                    flags=flags, ws_flags=fl, want_dtheta=False, mode=mode)
+                                    flags=flags | (B.IRL_STEP_GRAPH if args.graph else 0), ws_flags=fl,
+                                    want_dtheta=False, mode=mode)
             torch.cuda.synchronize()
             if not Es:
                 Es.append(r.E_before)
@@ -549,7 +550,8 @@ def run_ablation_bench(args):
             sysm.evaluate(wl.V, wl.H, th, ws_flags=flv, want_grad=False)
             out, _, _ = sysm.vmc_sample(u)
             rc, r, _, _ = sysm.step(th, wl.V, wl.H, m=m, k_keep=k, tol=1e-12, max_restarts=300,
-                                    flags=B.IRL_STEP_WS_CURRENT, ws_flags=flv, want_dtheta=False)
+                                    flags=B.IRL_STEP_WS_CURRENT | (B.IRL_STEP_GRAPH if args.graph else 0),
+                                    ws_flags=flv, want_dtheta=False)
             torch.cuda.synchronize()
             if not Es:
                 Es.append(out.E_exact)
@@ -730,7 +732,10 @@ def run_vmc_bench(args):
             f"lambda={r.lambda_min:.3e} applies={r.n_apply}")
     theta.copy_(theta0)
     torch.cuda.synchronize()
-    B.irl_stats_enable(sysm.handle, True)
+    # per-kernel events in the timed region, except with graph replay (events would
+    # turn the replay off): then the kernel times come from an untimed rerun below
+    events = not (args.graph or args.no_events)
+    B.irl_stats_enable(sysm.handle, events)
     steps = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -743,6 +748,14 @@ def run_vmc_bench(args):
             f"lambda={r.lambda_min:.3e} applies={r.n_apply}")
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    if not events:
+        theta_end = theta.clone()
+        theta.copy_(theta0)
+        B.irl_stats_enable(sysm.handle, True)
+        for i in range(args.steps):
+            one_step()
+        torch.cuda.synchronize()
+        theta.copy_(theta_end)
     stats = B.irl_stats_get(sysm.handle)
     B.irl_stats_enable(sysm.handle, False)
     ms_per_step = (t1 - t0) * 1e3 / args.steps
@@ -833,6 +846,13 @@ def main():
                          "(default) or streams of the dense D~")
     ap.add_argument("--block", type=int, default=0,
                     help="vectors per operator pass: 0/1 implicitly restarted Lanczos, 2..8 block Lanczos")
+    ap.add_argument("--graph", action="store_true",
+                    help="replay captured Lanczos cycles (HIP graphs) where a solve tests only at the "
+                         "end of each cycle (operators under 256 MB per apply); the timed region "
+                         "then runs without per-kernel events")
+    ap.add_argument("--no-events", action="store_true",
+                    help="time the steps without per-kernel events (kernel times then come from an "
+                         "untimed rerun of the same steps)")
     ap.add_argument("--polish", action="store_true",
                     help="FP32 operator: keep an FP64 copy of D~ and refine the Ritz pair in FP64")
     ap.add_argument("--no-fp64-reference", dest="fp64_reference", action="store_false",
@@ -901,7 +921,8 @@ def main():
         ws_flags = B.IRL_WS_FACTORED if args.jacobian == "factored" else B.IRL_WS_FP64
     else:
         ws_flags = B.IRL_WS_FP32 | (B.IRL_WS_FP64 if args.polish else 0)
-    step_flags = B.IRL_STEP_NO_EVAL_AFTER | (0 if args.polish else B.IRL_STEP_NO_POLISH)
+    step_flags = (B.IRL_STEP_NO_EVAL_AFTER | (0 if args.polish else B.IRL_STEP_NO_POLISH)
+                  | (B.IRL_STEP_GRAPH if args.graph else 0))
     if args.block > 1:
         ws_flags |= B.IRL_WS_BLOCK
     sysm.workspace(wl.P + 1, ws_flags)
@@ -926,7 +947,10 @@ def main():
             f"restarts={r.n_restart} conv={r.converged} {r.ms_eval + r.ms_solve + r.ms_after:.1f} ms")
     theta.copy_(theta0)
     torch.cuda.synchronize()
-    B.irl_stats_enable(sysm.handle, True)
+    # per-kernel events in the timed region, except with graph replay (events would
+    # turn the replay off): then the kernel times come from an untimed rerun below
+    events = not (args.graph or args.no_events)
+    B.irl_stats_enable(sysm.handle, events)
     steps = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -943,6 +967,14 @@ def main():
             f"restarts={r.n_restart} conv={r.converged} {step_ms:.1f} ms")
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    if not events:
+        theta_end = theta.clone()
+        theta.copy_(theta0)
+        B.irl_stats_enable(sysm.handle, True)
+        for i in range(args.steps):
+            one_step()
+        torch.cuda.synchronize()
+        theta.copy_(theta_end)
     stats = B.irl_stats_get(sysm.handle)
     B.irl_stats_enable(sysm.handle, False)
     ms_per_step = (t1 - t0) * 1e3 / args.steps
@@ -1059,6 +1091,8 @@ def main():
                                 f"tol=1e-12" + (f", block Lanczos with {args.block} vectors per pass"
                                                 if args.block > 1 else "")),
                    "n_dets": ns, "P": wl.P, "m": wl.m, "k_keep": wl.k, "block": args.block,
+                   "graph_replay": bool(args.graph),
+                   "kernel_events_in_timed_region": events,
                    "ham_kernel": HAM_KERNELS[sysm.info.ham_kernel]},
         "roofline": roof,
         "rooflines": rooflines,

@@ -204,6 +204,8 @@ typedef struct {
     int32_t converged;      /* 1 if the residual test passed */
     int32_t n_apply_lo;     /* of n_apply, the reduced-precision (FP32) applies */
     double ms_eval, ms_solve, ms_after;   /* host wall time of each phase */
+    int32_t n_graph_cycles; /* cycles replayed from captured graphs (IRL_STEP_GRAPH) */
+    int32_t reserved;
 } irl_step_result;
 
 /* ---- system --------------------------------------------------------------- */

@@ -89,7 +89,8 @@ class irl_step_result(ctypes.Structure):
                 ("tol_used", c_double), ("c0", c_double), ("gap", c_double),
                 ("norm_T", c_double), ("n_apply", c_int32), ("n_restart", c_int32),
                 ("converged", c_int32), ("n_apply_lo", c_int32), ("ms_eval", c_double),
-                ("ms_solve", c_double), ("ms_after", c_double)]
+                ("ms_solve", c_double), ("ms_after", c_double), ("n_graph_cycles", c_int32),
+                ("reserved", c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

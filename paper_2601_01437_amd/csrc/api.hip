@@ -360,7 +360,7 @@ namespace {
 // return the unit Ritz vector is in ws y.
 struct SolveOut {
     double lam = 0, resid_est = 0, resid_explicit = 0, gap = 0, normT = 0, c0 = 0, tol_used = 0;
-    int n_apply = 0, n_restart = 0, converged = 0;
+    int n_apply = 0, n_restart = 0, converged = 0, n_graph = 0;
 };
 
 // ---- captured Lanczos cycles -------------------------------------------------
@@ -447,8 +447,10 @@ bool capture_cycle(irl_system *s, void *ws, const WsLayout &L, const irl_solver_
         return false;
     }
     hipStream_t cs = s->capture_stream;
-    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    hipError_t eb = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (eb != hipSuccess) {
         (void)hipGetLastError();
+        s->err = std::string("graph capture not started: ") + hipGetErrorString(eb);
         return false;
     }
     const int split = (prec == IRL_FP32) ? 1 : 0;
@@ -456,27 +458,47 @@ bool capture_cycle(irl_system *s, void *ws, const WsLayout &L, const irl_solver_
     double *Ib[2] = {ws_ptr<double>(ws, L.off_img0), ws_ptr<double>(ws, L.off_img1)};
     double *yH = ws_ptr<double>(ws, L.off_yh), *yS = ws_ptr<double>(ws, L.off_ys);
     bool ok = true;
+    std::string why;
     int cur = 0, j0 = 0;
     if (kind > 0) {
         cur = kind - 1;
         ok = launch_restart_basis(L, ws, Vb[cur], Vb[1 - cur], Ib[cur], Ib[1 - cur], m, k, o.mode, o.seed, cs) ==
              hipSuccess;
+        if (!ok) why = "restart kernel";
         cur = 1 - cur;
         j0 = k;
     }
     for (int j = j0; ok && j < m; ++j) {
-        ok = apply_internal(s, ws, L, Vb[cur] + (int64_t)j * L.ldv, yH, yS, prec, cs, split) == IRL_OK &&
-             launch_lanczos_step(L, ws, Vb[cur], Ib[cur], j, o.mode, split, o.seed, cs) == hipSuccess;
+        ok = apply_internal(s, ws, L, Vb[cur] + (int64_t)j * L.ldv, yH, yS, prec, cs, split) == IRL_OK;
+        if (!ok) {
+            why = "operator apply (" + s->err + ")";
+            break;
+        }
+        ok = launch_lanczos_step(L, ws, Vb[cur], Ib[cur], j, o.mode, split, o.seed, cs) == hipSuccess;
+        if (!ok) why = "Lanczos step";
     }
-    if (ok) ok = launch_ritz(L, ws, m, k, cs) == hipSuccess;
+    if (ok && launch_ritz(L, ws, m, k, cs) != hipSuccess) {
+        ok = false;
+        why = "Ritz kernel";
+    }
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(cs, &g);
-    ok = ok && e == hipSuccess && g;
-    if (ok) ok = hipGraphInstantiate(out, g, nullptr, nullptr, 0) == hipSuccess;
+    if (ok && (e != hipSuccess || !g)) {
+        ok = false;
+        why = std::string("end of capture: ") + hipGetErrorString(e);
+    }
+    if (ok) {
+        const hipError_t ei = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+        if (ei != hipSuccess) {
+            ok = false;
+            why = std::string("instantiation: ") + hipGetErrorString(ei);
+        }
+    }
     if (g) (void)hipGraphDestroy(g);
     if (!ok) {
         *out = nullptr;
         (void)hipGetLastError();
+        s->err = "graph capture failed (launching the cycle instead): " + why;
     }
     return ok;
 }
@@ -552,6 +574,7 @@ int irl_solve(irl_system *s, void *ws, const WsLayout &L, const irl_solver_opts 
         if (cg && kind >= 0) {
             CK(s, hipGraphLaunch(cg->exec[kind], st));
             n_apply += m - j0;
+            ++out.n_graph;
             pending = -1;
         } else {
         for (int j = j0; j < m; ++j) {
@@ -1250,6 +1273,7 @@ int irl_step(irl_system *s, irl_nqs_desc *nqs, const irl_solver_opts *opts, void
         if (rc) return rc;
         sp.n_apply += so.n_apply;
         sp.n_restart += so.n_restart;
+        sp.n_graph += so.n_graph;
         so = sp;
     }
     double *y = ws_ptr<double>(ws, L.off_y);
@@ -1264,6 +1288,7 @@ int irl_step(irl_system *s, irl_nqs_desc *nqs, const irl_solver_opts *opts, void
     res.converged = so.converged;
     res.tol_used = so.tol_used;
     res.n_apply_lo = n_apply_lo;
+    res.n_graph_cycles = so.n_graph;
     const bool converged = so.converged != 0;
     if (o.mode == IRL_MODE_C) {
         // coefficient of psi in the connected linearised wavefunction

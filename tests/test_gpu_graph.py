@@ -35,6 +35,12 @@ def _fields(r):
                                    r.residual_explicit, r.n_apply, r.n_restart, r.converged, r.norm_T))
 
 
+def _last_error(s):
+    from paper_2601_01437_amd import binding as B
+    msg = B._lib.irl_last_error(s.handle)
+    return msg.decode() if msg else ""
+
+
 def _run(s, theta, V, H, steps, graph, **kw):
     from paper_2601_01437_amd import IRL_STEP_GRAPH
     flags = kw.pop("flags", 0) | (IRL_STEP_GRAPH if graph else 0)
@@ -42,6 +48,8 @@ def _run(s, theta, V, H, steps, graph, **kw):
     out = []
     for _ in range(steps):
         rc, r, dth, _ = s.step(th, V, H, flags=flags, **kw)
+        # the replay is really used (not the launched fallback), and only when asked for
+        assert (r.n_graph_cycles > 0) == graph, (r.n_graph_cycles, _last_error(s))
         out.append((rc, _fields(r), None if dth is None else host(dth).tobytes(), host(th).tobytes()))
     return out
 
@@ -115,6 +123,7 @@ def test_graph_sampled_estimators_and_workspace_change():
             s.evaluate(16, 16, th, ws_flags=fl)
             s.vmc_sample(dev(np.random.default_rng(10 + it).random(3000)))
             rc, r, dth, _ = s.step(th, 16, 16, m=12, k_keep=2, ws_flags=fl, flags=IRL_STEP_WS_CURRENT | extra)
+            assert (r.n_graph_cycles > 0) == graph, _last_error(s)
             out.append((rc, _fields(r), host(dth).tobytes()))
         for fl2 in (IRL_WS_FP64, IRL_WS_FACTORED):
             rc, r, dth, _ = s.step(th, 16, 16, m=12, k_keep=2, ws_flags=fl2, flags=extra)
