@@ -900,7 +900,7 @@ __global__ __launch_bounds__(kProdThreads) void k_ham_product(ProdArgs P, const 
 // with no branch.  Rows of the next beta move are loaded into registers while
 // the current one is summed (two barriers per move).  TPB threads per block
 // (one thread per alpha string of the block's slice).
-constexpr int kProd2Threads = 256;
+constexpr int kProd2Threads = 512;
 constexpr int kProdLdsMaxA = 2048;
 
 template <int NSA, int TPB>
