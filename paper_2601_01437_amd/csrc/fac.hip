@@ -578,10 +578,15 @@ hipError_t launch_fac_jvp(const irl_system *s, const WsLayout &L, void *ws, cons
     return launch_fac_jvp_rows(s, L, fac_rows(s, L, ws), v, zero_v0, w, st);
 }
 
+// row blocks of the backward pass: 256 workgroups of 64 hidden units fill the
+// chip once at two waves per SIMD (512 left a second, partial round: 0.229
+// against 0.221 ms per c2 pass, and twice the partial rows to reduce)
+constexpr int kFacRowBlocks = 256;
+
 int fac_row_blocks_n(int64_t ns, int hfac)
 {
     const int htiles = (hfac + 63) / 64;
-    int nblk = kStreamBlocks / (htiles > 0 ? htiles : 1);
+    int nblk = kFacRowBlocks / (htiles > 0 ? htiles : 1);
     if (nblk < 1) nblk = 1;
     if (nblk > (ns + 15) / 16) nblk = (int)((ns + 15) / 16);
     return nblk < 1 ? 1 : nblk;
