@@ -578,9 +578,9 @@ hipError_t launch_fac_jvp(const irl_system *s, const WsLayout &L, void *ws, cons
     return launch_fac_jvp_rows(s, L, fac_rows(s, L, ws), v, zero_v0, w, st);
 }
 
-// row blocks of the backward pass: 256 workgroups of 64 hidden units fill the
-// chip once at two waves per SIMD (512 left a second, partial round: 0.229
-// against 0.221 ms per c2 pass, and twice the partial rows to reduce)
+// row blocks of the backward pass: at H = 64 the 256 row blocks x 2 hidden-unit
+// groups are 2048 waves, one round on the chip at two waves per SIMD (512 row
+// blocks took 0.229 against 0.221 ms per c2 pass, with twice the partial rows)
 constexpr int kFacRowBlocks = 256;
 
 int fac_row_blocks_n(int64_t ns, int hfac)
