@@ -476,8 +476,12 @@ namespace {
 
 int fac_tile_blocks(int64_t ns)
 {
-    int64_t blocks = (ns + 63) / 64;   // 4 waves x one 16-row tile each
-    if (blocks > 1024) blocks = 1024;
+    // 4 waves x one 16-row tile each; grid-stride beyond 512 blocks (two per
+    // compute unit: at 853,776 rows the forward takes 0.227 ms and the
+    // Jacobian-vector product 0.109 ms, against 0.236 and 0.113 at 1024
+    // blocks and 0.145 ms for the product at 256)
+    int64_t blocks = (ns + 63) / 64;
+    if (blocks > 512) blocks = 512;
     return (int)(blocks < 1 ? 1 : blocks);
 }
 
