@@ -693,6 +693,19 @@ def vmc_cpu_baseline(wl, nsamp, applies_per_step, sample_draws=40, sample_rows=1
     }
 
 
+def select_live_kinds(args, B, warm, has_roofline):
+    """Kernel classes bracketed by events inside the timed region: the one with a
+    roofline and the largest total time over the warm-up steps (each event pair
+    costs a few microseconds of queue time per launch); every class with
+    --all-events or without warm-up figures; none with --graph or --no-events."""
+    if args.graph or args.no_events:
+        return []
+    ranked = sorted((k for k, v in warm.items() if v[1] and has_roofline(k)), key=lambda k: -warm[k][0])
+    if args.all_events or not ranked:
+        return list(B.STAT_KINDS)
+    return ranked[:1]
+
+
 def run_vmc_bench(args):
     """Sampled VMC step (Eq. matrix_vec_prod estimator) on one workload: each step
     evaluates psi, d and H psi at theta on the set, draws N configurations from
@@ -726,16 +739,22 @@ def run_vmc_bench(args):
                                 flags=B.IRL_STEP_WS_CURRENT | B.IRL_STEP_NO_EVAL_AFTER, want_dtheta=False)
         return out, rc, r
 
+    B.irl_stats_select(sysm.handle, None)
+    B.irl_stats_enable(sysm.handle, args.warmup > 0 and not args.graph)
     for i in range(args.warmup):
         out, rc, r = one_step(i)
         log(f"warmup {i}: E_sampled={out.E_sampled:.10f} E={out.E_exact:.10f} unique={out.n_unique} "
             f"lambda={r.lambda_min:.3e} applies={r.n_apply}")
+    warm = B.irl_stats_get(sysm.handle)
+    B.irl_stats_enable(sysm.handle, False)
     theta.copy_(theta0)
     torch.cuda.synchronize()
-    # per-kernel events in the timed region, except with graph replay (events would
-    # turn the replay off): then the kernel times come from an untimed rerun below
-    events = not (args.graph or args.no_events)
-    B.irl_stats_enable(sysm.handle, events)
+    # events in the timed region around the dominant kernel class only (as in the
+    # main bench); every class's times from an untimed rerun below
+    live = select_live_kinds(args, B, warm, lambda k: kernel_roofline(k, ns, wl.P + 1, wl.H, True, 0,
+                                                                       sysm.info, 0) is not None)
+    B.irl_stats_select(sysm.handle, live or None)
+    B.irl_stats_enable(sysm.handle, bool(live))
     steps = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -748,18 +767,22 @@ def run_vmc_bench(args):
             f"lambda={r.lambda_min:.3e} applies={r.n_apply}")
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    if not events:
-        theta_end = theta.clone()
-        theta.copy_(theta0)
-        B.irl_stats_enable(sysm.handle, True)
-        for i in range(args.steps):
-            one_step()
-        torch.cuda.synchronize()
-        theta.copy_(theta_end)
     stats = B.irl_stats_get(sysm.handle)
     B.irl_stats_enable(sysm.handle, False)
+    if len(live) < len(B.STAT_KINDS):
+        theta_end = theta.clone()
+        theta.copy_(theta0)
+        B.irl_stats_select(sysm.handle, None)
+        B.irl_stats_enable(sysm.handle, True)
+        for i in range(args.steps):
+            one_step(args.warmup + i)
+        rerun = B.irl_stats_get(sysm.handle)
+        B.irl_stats_enable(sysm.handle, False)
+        theta.copy_(theta_end)
+        stats = {k: (stats[k] if k in live else rerun[k]) for k in rerun}
     ms_per_step = (t1 - t0) * 1e3 / args.steps
-    kern = {k: {"ms_total": v[0], "launches": v[1], "ms_avg": v[0] / v[1] if v[1] else None}
+    kern = {k: {"ms_total": v[0], "launches": v[1], "ms_avg": v[0] / v[1] if v[1] else None,
+                "timed_live": k in live}
             for k, v in stats.items() if v[1]}
     rooflines = {}
     mean_unique = sum(st["unique"] for st in steps) / len(steps)
@@ -779,6 +802,9 @@ def run_vmc_bench(args):
                            "ms_avg": v["ms_avg"], "ms_total": v["ms_total"], "launches": v["launches"],
                            "source_hash": src_hash}
     roof = max(rooflines.values(), key=lambda r: r["ms_total"]) if rooflines else None
+    if len(live) == 1 and live[0] in kern:
+        spec = kernel_roofline(live[0], ns, wl.P + 1, wl.H, True, 0, sysm.info, 0)
+        roof = rooflines.get(spec[0], roof) if spec else roof
     applies = sum(st["applies"] for st in steps) / len(steps)
     cpu = None
     if not args.no_cpu_baseline:
@@ -795,7 +821,8 @@ def run_vmc_bench(args):
                                 f"factored Jacobian, exact evaluation of psi and H psi on the set, "
                                 f"operator products over "
                                 f"{'the gathered drawn rows' if gathered else 'every row'}"),
-                   "mean_unique_rows": mean_unique},
+                   "mean_unique_rows": mean_unique,
+                   "kernel_events_in_timed_region": live if len(live) < len(B.STAT_KINDS) else "all"},
         "draws_per_s": N * args.steps / (t1 - t0),
         "roofline": {k: v for k, v in roof.items()} if roof else None,
         "rooflines": rooflines,
@@ -850,6 +877,9 @@ def main():
                     help="replay captured Lanczos cycles (HIP graphs) where a solve tests only at the "
                          "end of each cycle (operators under 256 MB per apply); the timed region "
                          "then runs without per-kernel events")
+    ap.add_argument("--all-events", action="store_true",
+                    help="bracket every kernel launch with events in the timed region (default: only "
+                         "the dominant kernel class, named by the warm-up steps)")
     ap.add_argument("--no-events", action="store_true",
                     help="time the steps without per-kernel events (kernel times then come from an "
                          "untimed rerun of the same steps)")
@@ -941,15 +971,31 @@ def main():
                                 ws_flags=ws_flags, want_dtheta=False, block=args.block)
         return rc, r
 
+    ncols = wl.P + 1
+    factored = bool(ws_flags & B.IRL_WS_FACTORED) and precision == B.IRL_FP64
+    s_build = (8 if ws_flags & B.IRL_WS_FP64 else 0) + (4 if ws_flags & B.IRL_WS_FP32 else 0)
+    stored_bytes = store["bytes"] if store and store["stored"] else 0
+
+    # events over the warm-up steps name the dominant kernel class
+    B.irl_stats_select(sysm.handle, None)
+    B.irl_stats_enable(sysm.handle, args.warmup > 0 and not args.graph)
     for i in range(args.warmup):
         rc, r = one_step()
         log(f"warmup {i}: E={r.E_before:.12f} lambda={r.lambda_min:.3e} applies={r.n_apply} "
             f"restarts={r.n_restart} conv={r.converged} {r.ms_eval + r.ms_solve + r.ms_after:.1f} ms")
+    warm = B.irl_stats_get(sysm.handle)
+    B.irl_stats_enable(sysm.handle, False)
     theta.copy_(theta0)
     torch.cuda.synchronize()
-    # per-kernel events in the timed region, except with graph replay (events would
-    # turn the replay off): then the kernel times come from an untimed rerun below
-    events = not (args.graph or args.no_events)
+    # Per-kernel events in the timed region: by default only around the dominant
+    # class (each event pair costs a few microseconds of queue time per launch);
+    # --all-events brackets every launch; none with graph replay (events would turn
+    # the replay off) or --no-events.  Every class's times then come from an untimed
+    # rerun of the same steps.
+    live = select_live_kinds(args, B, warm, lambda k: kernel_roofline(k, ns, ncols, wl.H, factored, s_build,
+                                                                       sysm.info, stored_bytes) is not None)
+    events = bool(live)
+    B.irl_stats_select(sysm.handle, live or None)
     B.irl_stats_enable(sysm.handle, events)
     steps = []
     torch.cuda.synchronize()
@@ -967,28 +1013,34 @@ def main():
             f"restarts={r.n_restart} conv={r.converged} {step_ms:.1f} ms")
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    if not events:
+    stats = B.irl_stats_get(sysm.handle)
+    B.irl_stats_enable(sysm.handle, False)
+    rerun = None
+    if len(live) < len(B.STAT_KINDS):
         theta_end = theta.clone()
         theta.copy_(theta0)
+        B.irl_stats_select(sysm.handle, None)
         B.irl_stats_enable(sysm.handle, True)
         for i in range(args.steps):
             one_step()
-        torch.cuda.synchronize()
+        rerun = B.irl_stats_get(sysm.handle)
+        B.irl_stats_enable(sysm.handle, False)
         theta.copy_(theta_end)
-    stats = B.irl_stats_get(sysm.handle)
-    B.irl_stats_enable(sysm.handle, False)
+        # live classes keep their timed-region figures
+        stats = {k: (stats[k] if k in live else rerun[k]) for k in rerun}
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     applies = sum(s["applies"] for s in steps)
     # final energy after the last update
     Zf, Ef, _ = sysm.evaluate(wl.V, wl.H, theta, ws_flags=ws_flags, want_grad=False)
 
     # dominant kernel and its roofline (every kernel kind's beside it)
-    ncols = wl.P + 1
-    kern = {k: {"ms_total": v[0], "launches": v[1], "ms_avg": v[0] / v[1] if v[1] else None}
+    kern = {k: {"ms_total": v[0], "launches": v[1], "ms_avg": v[0] / v[1] if v[1] else None,
+                "timed_live": k in live}
             for k, v in stats.items() if v[1]}
-    factored = bool(ws_flags & B.IRL_WS_FACTORED) and precision == B.IRL_FP64
-    s_build = (8 if ws_flags & B.IRL_WS_FP64 else 0) + (4 if ws_flags & B.IRL_WS_FP32 else 0)
-    stored_bytes = store["bytes"] if store and store["stored"] else 0
+    if rerun is not None:
+        for k in live:
+            if k in kern and rerun[k][1]:
+                kern[k]["ms_avg_untimed_rerun"] = rerun[k][0] / rerun[k][1]
     rooflines = {}
     for k, v in kern.items():
         spec = kernel_roofline(k, ns, ncols, wl.H, factored, s_build, sysm.info, stored_bytes)
@@ -1006,6 +1058,10 @@ def main():
                            "ms_avg": v["ms_avg"], "ms_total": v["ms_total"], "launches": v["launches"],
                            "source_hash": src_hash}
     roof = max(rooflines.values(), key=lambda r: r["ms_total"]) if rooflines else None
+    if len(live) == 1 and live[0] in kern:
+        # the kernel whose launches were bracketed live in the timed region
+        spec = kernel_roofline(live[0], ns, ncols, wl.H, factored, s_build, sysm.info, stored_bytes)
+        roof = rooflines.get(spec[0], roof) if spec else roof
     # whole operator apply, per D~ copy streamed: K6 + K4 + K7 + reduction averages
     operator = {}
     ham_avg = kern["ham_apply"]["ms_avg"]
@@ -1092,7 +1148,7 @@ def main():
                                                 if args.block > 1 else "")),
                    "n_dets": ns, "P": wl.P, "m": wl.m, "k_keep": wl.k, "block": args.block,
                    "graph_replay": bool(args.graph),
-                   "kernel_events_in_timed_region": events,
+                   "kernel_events_in_timed_region": live if len(live) < len(B.STAT_KINDS) else "all",
                    "ham_kernel": HAM_KERNELS[sysm.info.ham_kernel]},
         "roofline": roof,
         "rooflines": rooflines,

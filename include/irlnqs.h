@@ -491,6 +491,13 @@ enum irl_stat_kind {
  * (which cover all members) in the stats of the first member's system. */
 int irl_stats_enable(irl_system *sys, int32_t on);
 
+/* Restrict the timed launches to the kinds whose bits are set in `kinds`
+ * (bit k = irl_stat_kind k; all kinds by default).  Launches of the other kinds
+ * get no events and so none of their host and queue cost; their entries in
+ * irl_stats_get stay zero.  The choice persists across irl_stats_enable calls.
+ * IRL_EINVAL for a bit at or beyond IRL_STAT_KINDS. */
+int irl_stats_select(irl_system *sys, uint32_t kinds);
+
 /* Synchronise `stream` and return, per irl_stat_kind, the summed kernel time
  * in milliseconds (ms[IRL_STAT_KINDS]) and the launch count
  * (count[IRL_STAT_KINDS]) since the last irl_stats_enable(sys, 1). */

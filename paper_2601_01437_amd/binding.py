@@ -123,6 +123,7 @@ _sigs = {
     "irl_vmc_sample": (c_int32, [_SYS, c_void_p, c_size_t, c_void_p, c_int64, c_void_p, c_void_p,
                                  POINTER(irl_vmc_out), c_void_p]),
     "irl_stats_enable": (c_int32, [_SYS, c_int32]),
+    "irl_stats_select": (c_int32, [_SYS, c_uint32]),
     "irl_stats_get": (c_int32, [_SYS, c_void_p, c_void_p, c_void_p]),
     "irl_batch_create": (c_int32, [c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_uint32,
                                    POINTER(c_void_p)]),
@@ -289,6 +290,12 @@ def irl_step(sys, opts, ws, ws_flags, V=None, H=None, theta=None, dtheta=None, r
 
 def irl_stats_enable(sys, on=True):
     _check(_lib.irl_stats_enable(sys, 1 if on else 0), sys)
+
+
+def irl_stats_select(sys, kinds=None):
+    """Time only the named kinds (names of STAT_KINDS); None: every kind."""
+    mask = (1 << len(STAT_KINDS)) - 1 if kinds is None else sum(1 << STAT_KINDS.index(k) for k in kinds)
+    _check(_lib.irl_stats_select(sys, mask), sys)
 
 
 def irl_stats_get(sys, stream=None):

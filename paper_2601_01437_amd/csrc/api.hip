@@ -122,7 +122,8 @@ int stats_fold(irl_system *s)
 
 int stat_begin(irl_system *s, int kind, hipStream_t st)
 {
-    if (!s->stats_on) return IRL_OK;
+    s->ev_open = false;
+    if (!s->stats_on || !((s->stat_mask >> kind) & 1u)) return IRL_OK;
     const size_t cap = 4096;
     if (s->ev_used == cap) {
         int rc = stats_fold(s);
@@ -136,12 +137,14 @@ int stat_begin(irl_system *s, int kind, hipStream_t st)
     if (s->ev_kind.size() < s->ev_used + 1) s->ev_kind.resize(s->ev_used + 1);
     s->ev_kind[s->ev_used] = kind;
     CK(s, hipEventRecord(s->ev_pool[2 * s->ev_used], st));
+    s->ev_open = true;
     return IRL_OK;
 }
 
 int stat_end(irl_system *s, hipStream_t st)
 {
-    if (!s->stats_on) return IRL_OK;
+    if (!s->stats_on || !s->ev_open) return IRL_OK;
+    s->ev_open = false;
     CK(s, hipEventRecord(s->ev_pool[2 * s->ev_used + 1], st));
     s->ev_used += 1;
     return IRL_OK;
@@ -1334,11 +1337,20 @@ int irl_stats_enable(irl_system *s, int32_t on)
         if (rc) return rc;
     }
     s->stats_on = on != 0;
+    s->ev_open = false;
     s->ev_used = 0;
     for (int k = 0; k < IRL_STAT_KINDS; ++k) {
         s->stat_ms[k] = 0.0;
         s->stat_cnt[k] = 0;
     }
+    return IRL_OK;
+}
+
+int irl_stats_select(irl_system *s, uint32_t kinds)
+{
+    if (!s) return IRL_EINVAL;
+    if (kinds >> IRL_STAT_KINDS) return set_err(s, IRL_EINVAL, "kinds names a bit beyond the last irl_stat_kind");
+    s->stat_mask = kinds;
     return IRL_OK;
 }
 

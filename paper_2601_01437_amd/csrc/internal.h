@@ -212,6 +212,8 @@ struct irl_system {
     hipStream_t capture_stream = nullptr;
     // per-kernel timing
     bool stats_on = false;
+    bool ev_open = false;           // stat_begin recorded the first event of a pair
+    uint32_t stat_mask = (1u << IRL_STAT_KINDS) - 1u;   // kinds that get events
     std::vector<hipEvent_t> ev_pool;
     std::vector<int> ev_kind;       // kind of pending pair i (events 2i, 2i+1)
     size_t ev_used = 0;
