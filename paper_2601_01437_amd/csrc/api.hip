@@ -186,7 +186,7 @@ int energy_and_gradient(irl_system *s, void *ws, const WsLayout &L, hipStream_t 
     int nblk = 1;
     double *y = ws_ptr<double>(ws, L.off_y);
     if (L.flags & IRL_WS_FACTORED) {
-        nblk = fac_row_blocks(L);
+        nblk = fac_vjp_blocks(s, L);
         TIMED(s, IRL_STAT_ENERGY, st, launch_fac_vjp(s, L, ws, hpsi, nullptr, &sc->E_el, 1, nblk, st));
         y = nullptr;
     } else if (prec == IRL_FP32 && nqs) {
@@ -215,7 +215,7 @@ int connected_sigma(irl_system *s, void *ws, const WsLayout &L, hipStream_t st)
     double *sig = ws_ptr<double>(ws, L.off_sig);
     int nblk = 1;
     if (L.flags & IRL_WS_FACTORED) {
-        nblk = fac_row_blocks(L);
+        nblk = fac_vjp_blocks(s, L);
         TIMED(s, IRL_STAT_GEMV_T, st, launch_fac_vjp(s, L, ws, psi, nullptr, nullptr, 0, nblk, st));
     } else {
         TIMED(s, IRL_STAT_GEMV_T, st, launch_gemv_t2(L, ws, IRL_FP64, psi, psi, nullptr, nullptr, &nblk, st));
@@ -247,7 +247,7 @@ int apply_internal(irl_system *s, void *ws, const WsLayout &L, const double *v, 
             TIMED(s, IRL_STAT_VMC, st, launch_vmc_diag(L, ws, w, u, 1, st));
         else
             TIMED(s, IRL_STAT_HAM_APPLY, st, launch_ham_apply(s, w, u, st));
-        const int nb = fac_row_blocks(L);
+        const int nb = fac_vjp_blocks(s, L);
         TIMED(s, IRL_STAT_GEMV_T, st, launch_fac_vjp(s, L, ws, w, u, nullptr, 0, nb, st));
         TIMED(s, IRL_STAT_REDUCE, st, launch_t2_reduce(L, ws, nb, yS, yH, L.ncols, 1.0, nullptr, st));
         return IRL_OK;
@@ -298,7 +298,7 @@ int check_prec(irl_system *s, int prec)
 
 namespace irl {
 
-WsLayout make_layout(int64_t ns, int64_t ncols, uint32_t flags, int V)
+WsLayout make_layout(int64_t ns, int64_t ncols, uint32_t flags, int V, int64_t fullA, int64_t fullB)
 {
     WsLayout L;
     L.ns = ns;
@@ -346,6 +346,8 @@ WsLayout make_layout(int64_t ns, int64_t ncols, uint32_t flags, int V)
     L.off_cel = take(gather ? (size_t)ns * 8 : 0);
     L.off_crow = take(gather ? (size_t)ns * 8 : 0);
     L.off_cfac = take(gather ? (size_t)ns * (size_t)L.hfac * 8 : 0);
+    if ((flags & IRL_WS_FACTORED) && L.hfac > 0 && fullA > 0 && fullA * fullB == ns)
+        L.kf_S = fac_full_ranges(fullA, fullB, V / 2, L.hfac);
     L.total = off;
     return L;
 }
@@ -1023,7 +1025,7 @@ int irl_workspace_query(const irl_system *s, int64_t ncols, uint32_t ws_flags, s
     if (!s || !bytes || ncols < 2 || !(ws_flags & (IRL_WS_FP64 | IRL_WS_FP32 | IRL_WS_FACTORED)) ||
         (ws_flags & ~(uint32_t)(IRL_WS_FP64 | IRL_WS_FP32 | IRL_WS_BLOCK | IRL_WS_FACTORED | IRL_WS_SAMPLED)))
         return IRL_EINVAL;
-    const WsLayout L = make_layout(s->ns, ncols, ws_flags, 2 * s->n);
+    const WsLayout L = make_layout(s->ns, ncols, ws_flags, 2 * s->n, s->full ? s->nA : 0, s->full ? s->nB : 0);
     if ((ws_flags & IRL_WS_FACTORED) && L.hfac < 1) return IRL_EINVAL;
     *bytes = L.total;
     return IRL_OK;
@@ -1041,7 +1043,7 @@ int irl_nqs_evaluate(irl_system *s, const irl_nqs_desc *nqs, void *ws, size_t ws
     if ((ws_flags & IRL_WS_FACTORED) && nqs->V > 64) return set_err(s, IRL_EINVAL, "the factored Jacobian needs V <= 64");
     hipStream_t st = (hipStream_t)stream;
     const int64_t P = (int64_t)nqs->V * nqs->H + nqs->H + nqs->V;
-    WsLayout L = make_layout(s->ns, P + 1, ws_flags, nqs->V);
+    WsLayout L = make_layout(s->ns, P + 1, ws_flags, nqs->V, s->full ? s->nA : 0, s->full ? s->nB : 0);
     int rc = check_ws(s, ws, ws_bytes, L);
     if (rc) return rc;
     s->ws_valid = false;
@@ -1133,7 +1135,7 @@ int irl_vmc_sample(irl_system *s, void *ws, size_t ws_bytes, const double *u, in
         nblk = fac_row_blocks_n(nu, L.hfac);
         TIMED(s, IRL_STAT_ENERGY, st, launch_fac_vjp_rows(s, L, ws, R, y, nullptr, nullptr, 1, nblk, st));
     } else if (L.flags & IRL_WS_FACTORED) {
-        nblk = fac_row_blocks(L);
+        nblk = fac_vjp_blocks(s, L);
         TIMED(s, IRL_STAT_ENERGY, st, launch_fac_vjp(s, L, ws, y, nullptr, nullptr, 1, nblk, st));
     } else {
         TIMED(s, IRL_STAT_GEMV_T, st, launch_gemv_t2(L, ws, IRL_FP64, y, y, nullptr, nullptr, &nblk, st));
@@ -1162,7 +1164,7 @@ int irl_dtilde_set(irl_system *s, const void *D, int64_t ld, int64_t ncols, int3
     if (!(ws_flags & (IRL_WS_FP64 | IRL_WS_FP32))) return set_err(s, IRL_EINVAL, "ws_flags names no D~ copy");
     if (ws_flags & IRL_WS_FACTORED) return set_err(s, IRL_EINVAL, "a caller-set D~ has no factored form");
     hipStream_t st = (hipStream_t)stream;
-    WsLayout L = make_layout(s->ns, ncols, ws_flags, 2 * s->n);
+    WsLayout L = make_layout(s->ns, ncols, ws_flags, 2 * s->n, s->full ? s->nA : 0, s->full ? s->nB : 0);
     int rc = check_ws(s, ws, ws_bytes, L);
     if (rc) return rc;
     s->ws_valid = false;
@@ -1708,7 +1710,7 @@ int batch_apply(irl_batch *b, const ListSet &ls, int vsel, int j, int cur, int s
         for (int m : ls.members) {
             const WsLayout &L = b->lay[m];
             const Member &mb = b->hm[m];
-            const int nb = fac_row_blocks(L);
+            const int nb = fac_vjp_blocks(b->sys[m], L);
             TIMED(s0, IRL_STAT_GEMV_T, st, launch_fac_vjp(b->sys[m], L, b->ws[m], mb.w, mb.u, nullptr, 0, nb, st));
             TIMED(s0, IRL_STAT_REDUCE, st, launch_t2_reduce(L, b->ws[m], nb, mb.yS, mb.yH, L.ncols, 1.0, nullptr, st));
         }
@@ -1764,7 +1766,7 @@ int batch_evaluate(irl_batch *b, const std::vector<int> &subset, hipStream_t st)
         for (int m : subset) {
             const WsLayout &L = b->lay[m];
             const Member &mb = b->hm[m];
-            const int nb = fac_row_blocks(L);
+            const int nb = fac_vjp_blocks(b->sys[m], L);
             TIMED(s0, IRL_STAT_ENERGY, st, launch_fac_vjp(b->sys[m], L, b->ws[m], mb.hpsi, nullptr, &mb.sc->E_el, 1, nb, st));
             TIMED(s0, IRL_STAT_REDUCE, st, launch_t2_reduce(L, b->ws[m], nb, nullptr, mb.grad, L.ncols, 2.0, &mb.sc->Z, st));
         }
@@ -1962,7 +1964,7 @@ int irl_batch_create(int32_t count, irl_system *const *systems, const irl_nqs_de
         if (nqs[i].V != 2 * s->n || nqs[i].H < 1 || nqs[i].H > 1024) { delete b; return set_err(nullptr, IRL_EINVAL, "bad network size in batch member " + std::to_string(i)); }
         if ((ws_flags & IRL_WS_FACTORED) && nqs[i].V > 64) { delete b; return set_err(nullptr, IRL_EINVAL, "the factored Jacobian needs V <= 64"); }
         const int64_t P = (int64_t)nqs[i].V * nqs[i].H + nqs[i].H + nqs[i].V;
-        WsLayout L = make_layout(s->ns, P + 1, ws_flags, nqs[i].V);
+        WsLayout L = make_layout(s->ns, P + 1, ws_flags, nqs[i].V, s->full ? s->nA : 0, s->full ? s->nB : 0);
         if (L.ldv > 8192) { delete b; return set_err(nullptr, IRL_EINVAL, "batch members need P + 1 <= 8192"); }
         if (!ws[i] || reinterpret_cast<uintptr_t>(ws[i]) % 256 || ws_bytes[i] < L.total) { delete b; return set_err(nullptr, IRL_ENOMEM, "batch workspace missing or too small for member " + std::to_string(i)); }
         b->sys.push_back(s);

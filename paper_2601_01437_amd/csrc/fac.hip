@@ -468,6 +468,225 @@ __global__ __launch_bounds__(256) void k_fac_vjp(const uint64_t *__restrict__ ke
     }
 }
 
+
+// ---------------------------------------------------------------------------
+// Full space: the backward product split over alpha and beta strings.
+//
+// Row r = b nA + a of a full space pairs alpha string a with beta string b (keys
+// ascend beta-major), so x_r = [x(a), x(b)], and with t_r = c_r d_r (per hidden unit)
+//   sum_r t_r x_r,v = sum_a x(a)_v S_A[a]  (alpha v),   sum_b x(b)_v S_B[b]  (beta v),
+//   S_A[a] = sum_b t_(b,a),   S_B[b] = sum_a t_(b,a),
+// and likewise for the sums of c_r in X^T c.  The (c d)^T X contraction then needs
+// no matrix-core work and one pass streams d.  A workgroup takes a tile of kFullTB
+// beta strings and one of S alpha ranges; wave w walks the alpha strings lo + w,
+// lo + w + 4, ... (the next string's rows load while the current ones are summed): it
+// reads the tile's kFullTB rows (b, a) (a lane per hidden unit, one coalesced row per
+// load), sums them into S_A[a], which it folds into W_A[h][v] += x(a)_v S_A[a][h] at
+// once (n multiply-adds per kFullTB rows), and adds each row into S_B[b].  After a
+// fixed-order combination of the waves, the beta columns are W[h][n + v] = sum_b
+// x(b)_v S_B[b][h] over the tile, and the workgroup writes one complete partial row
+// of D~^T c, as the matrix-core kernel does per row block.
+
+constexpr int kFullTB = 8;                 // beta strings per tile
+constexpr int64_t kFullMinRows = 32768;    // smaller spaces keep the matrix-core kernel
+constexpr int kFullMaxN = 16;
+
+struct FullArgs {
+    const double *dfac, *psi, *y0, *y1, *coefp;
+    const uint32_t *strA, *strB;
+    int64_t nA, nB, aper, ldv;
+    int n, H, V, S, half;
+    double *part;
+};
+
+__device__ __forceinline__ double readlane_d(double x, int l)
+{
+    const unsigned long long u = (unsigned long long)__double_as_longlong(x);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, l);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), l);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// NR right-hand sides c_q = y_q - coef psi (coef = 0 without coefp).  NA >= n alpha
+// orbitals.  Grid: (hidden tiles of 64, tiles x S alpha ranges).
+template <int NR, int NA>
+__global__ __launch_bounds__(256) void k_fac_vjp_full(FullArgs F)
+{
+    constexpr int TB = kFullTB;
+    constexpr int kAcc = NR * TB + NR * NA + 3;   // doubles per lane in the wave combination
+    __shared__ double red[64 * kAcc];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int ht = blockIdx.x;
+    const int64_t wg = blockIdx.y;
+    const int64_t bt = wg / F.S;
+    const int sr = (int)(wg - bt * F.S);
+    const int64_t b0 = bt * TB;
+    const int nb = (int)(F.nB - b0 < TB ? F.nB - b0 : TB);
+    const int64_t alo = (int64_t)sr * F.aper;
+    const int64_t ahi = alo + F.aper < F.nA ? alo + F.aper : F.nA;
+    const int h = 64 * ht + lane;
+    const bool hv = h < F.H;
+    const double coef = F.coefp ? *F.coefp : 0.0;
+    // per-row scalars, one per lane: lanes 8 k + b hold y0 (k = 0), y1 (k = 1) and
+    // psi (k = 2) of row (b0 + b, a)
+    const int bl = lane & 7, kind = lane >> 3;
+    double sb[NR][TB], wa[NR][NA];
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+#pragma unroll
+        for (int b = 0; b < TB; ++b) sb[q][b] = 0.0;
+#pragma unroll
+        for (int v = 0; v < NA; ++v) wa[q][v] = 0.0;
+    }
+    double cb = 0.0, p0 = 0.0;   // lanes 8 q + b (q < NR): C_B[b] and sum psi c of c_q
+    double xc[NR];               // lane v < n: sum_a x(a)_v C_A[a] of c_q
+#pragma unroll
+    for (int q = 0; q < NR; ++q) xc[q] = 0.0;
+    double sc_n = 0.0, dv_n[TB];
+    auto fetch = [&](int64_t a) {
+        sc_n = 0.0;
+        if (a < ahi && bl < nb) {
+            const int64_t r = (b0 + bl) * F.nA + a;
+            if (kind == 0)
+                sc_n = F.y0[r];
+            else if (kind == 1 && NR == 2)
+                sc_n = F.y1[r];
+            else if (kind == 2)
+                sc_n = F.psi[r];
+        }
+#pragma unroll
+        for (int b = 0; b < TB; ++b)
+            dv_n[b] = (a < ahi && b < nb && hv) ? __builtin_nontemporal_load(F.dfac + ((b0 + b) * F.nA + a) * F.H + h)
+                                                : 0.0;
+    };
+    fetch(alo + wv);
+    for (int64_t a = alo + wv; a < ahi; a += 4) {
+        const double sc = sc_n;
+        double dv[TB];
+#pragma unroll
+        for (int b = 0; b < TB; ++b) dv[b] = dv_n[b];
+        fetch(a + 4);
+        const double ps = __shfl(sc, 16 + bl, 64);
+        const double cl = kind < 2 ? sc - coef * ps : sc;    // lanes 0..7: c_0, 8..15: c_1
+        double sa[NR];
+#pragma unroll
+        for (int q = 0; q < NR; ++q) sa[q] = 0.0;
+#pragma unroll
+        for (int b = 0; b < TB; ++b) {
+            if (b < nb) {
+#pragma unroll
+                for (int q = 0; q < NR; ++q) {
+                    const double t = readlane_d(cl, 8 * q + b) * dv[b];
+                    sa[q] += t;
+                    sb[q][b] += t;
+                }
+            }
+        }
+        const uint32_t xa = F.strA[a];
+#pragma unroll
+        for (int v = 0; v < NA; ++v) {
+            const double xv = ((xa >> v) & 1u) ? 1.0 : 0.0;
+#pragma unroll
+            for (int q = 0; q < NR; ++q) wa[q][v] = fma(xv, sa[q], wa[q][v]);
+        }
+        // C_A[a] over the tile's beta strings (fixed 8-lane tree), folded into lane v
+        double ca = kind < NR ? cl : 0.0;
+        ca += __shfl_xor(ca, 1, 64);
+        ca += __shfl_xor(ca, 2, 64);
+        ca += __shfl_xor(ca, 4, 64);
+        const double xl = ((xa >> (lane & 31)) & 1u) && lane < F.n ? 1.0 : 0.0;
+#pragma unroll
+        for (int q = 0; q < NR; ++q) xc[q] = fma(xl, readlane_d(ca, 8 * q), xc[q]);
+        if (kind < NR) {
+            cb += cl;
+            p0 = fma(cl, ps, p0);
+        }
+    }
+
+    // fixed-order combination of the 4 waves: ((w0 + w1) + w2) + w3
+    auto slot = [&](int k) -> double & { return red[64 * k + lane]; };
+    for (int src = 1; src < 4; ++src) {
+        __syncthreads();
+        if (wv == src) {
+            int k = 0;
+#pragma unroll
+            for (int q = 0; q < NR; ++q) {
+#pragma unroll
+                for (int b = 0; b < TB; ++b) slot(k++) = sb[q][b];
+#pragma unroll
+                for (int v = 0; v < NA; ++v) slot(k++) = wa[q][v];
+                slot(k++) = xc[q];
+            }
+            slot(k++) = cb;
+            slot(k++) = p0;
+        }
+        __syncthreads();
+        if (wv == 0) {
+            int k = 0;
+#pragma unroll
+            for (int q = 0; q < NR; ++q) {
+#pragma unroll
+                for (int b = 0; b < TB; ++b) sb[q][b] += slot(k++);
+#pragma unroll
+                for (int v = 0; v < NA; ++v) wa[q][v] += slot(k++);
+                xc[q] += slot(k++);
+            }
+            cb += slot(k++);
+            p0 += slot(k++);
+        }
+    }
+    if (wv != 0) return;
+    const int n = F.n, V = F.V;
+    const int64_t baseW = 1 + V + F.H, P1 = (int64_t)V * F.H + F.H + V + 1;
+    uint32_t xb[TB];
+#pragma unroll
+    for (int b = 0; b < TB; ++b) xb[b] = b < nb ? F.strB[b0 + b] : 0u;
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+        double *out = F.part + (wg * 2 + (NR == 2 ? q : F.half)) * F.ldv;
+        if (hv) {
+            double ds = 0.0;
+#pragma unroll
+            for (int b = 0; b < TB; ++b) ds += sb[q][b];
+            out[1 + V + h] = ds;
+            double *wrow = out + baseW + (int64_t)h * V;
+#pragma unroll
+            for (int v = 0; v < NA; ++v)
+                if (v < n) wrow[v] = wa[q][v];
+#pragma unroll
+            for (int v = 0; v < NA; ++v) {
+                if (v < n) {
+                    double wbv = 0.0;
+#pragma unroll
+                    for (int b = 0; b < TB; ++b) wbv = fma(((xb[b] >> v) & 1u) ? 1.0 : 0.0, sb[q][b], wbv);
+                    wrow[n + v] = wbv;
+                }
+            }
+        }
+        if (ht == 0) {
+            // psi^T c (8-lane tree of the lanes 8 q + b)
+            double p = p0;
+            p += __shfl_xor(p, 1, 64);
+            p += __shfl_xor(p, 2, 64);
+            p += __shfl_xor(p, 4, 64);
+            const double ptot = readlane_d(p, 8 * q);
+            // X^T c: alpha columns from lane v, beta columns sum_b x(b)_v C_B[b]
+            double xbv = 0.0;
+#pragma unroll
+            for (int b = 0; b < TB; ++b) {
+                const double cbb = readlane_d(cb, 8 * q + b);
+                xbv = fma(((xb[b] >> (lane & 31)) & 1u) ? 1.0 : 0.0, cbb, xbv);
+            }
+            if (lane == 0) out[0] = ptot;
+            if (lane < n) {
+                out[1 + lane] = xc[q];
+                out[1 + n + lane] = xbv;
+            }
+            for (int64_t col = P1 + lane; col < F.ldv; col += 64) out[col] = 0.0;
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // launchers: KS = k-steps of 4 visible units (even, V <= 4 KS), NT = column tiles of
 // 16 visible units (V <= 16 NT)
@@ -532,7 +751,66 @@ bool fac_shape_ok(const irl_system *s, const WsLayout &L)
            (int64_t)V * L.hfac + L.hfac + V + 1 <= L.ldv;
 }
 
+// the string-split backward product applies to these rows of this workspace
+bool fac_full_ok(const irl_system *s, const WsLayout &L, const FacRows &R)
+{
+    return L.kf_S > 0 && s->full && R.keys == s->d.keys && R.ns == s->ns && s->nA * s->nB == s->ns &&
+           s->d.strA && s->d.strB && L.hfac >= 1;
+}
+
+template <int NA>
+hipError_t vjp_full_na(const irl_system *s, const WsLayout &L, void *ws, const FacRows &R, const double *y0,
+                       const double *y1, const double *coefp, int half, int nblk, hipStream_t st)
+{
+    const int H = L.hfac, S = L.kf_S;
+    const int64_t nbt = (s->nB + kFullTB - 1) / kFullTB;
+    if (nblk != nbt * S) return hipErrorInvalidValue;
+    FullArgs F;
+    F.dfac = R.dfac;
+    F.psi = R.psi;
+    F.y0 = y0;
+    F.y1 = y1;
+    F.coefp = coefp;
+    F.strA = s->d.strA;
+    F.strB = s->d.strB;
+    F.nA = s->nA;
+    F.nB = s->nB;
+    F.aper = (s->nA + S - 1) / S;
+    F.ldv = L.ldv;
+    F.n = s->n;
+    F.H = H;
+    F.V = 2 * s->n;
+    F.S = S;
+    F.half = half;
+    F.part = ws_ptr<double>(ws, L.off_part);
+    const dim3 grid((unsigned)((H + 63) / 64), (unsigned)nblk);
+    if (y1)
+        k_fac_vjp_full<2, NA><<<grid, 256, 0, st>>>(F);
+    else
+        k_fac_vjp_full<1, NA><<<grid, 256, 0, st>>>(F);
+    return hipGetLastError();
+}
+
 }  // namespace
+
+int fac_full_ranges(int64_t nA, int64_t nB, int n, int H)
+{
+    // one partial row per workgroup: at most kStreamBlocks of them, at least 16
+    // alpha strings (4 per wave) per range
+    const int64_t nbt = (nB + kFullTB - 1) / kFullTB;
+    if (nA < 1 || nB < 1 || nA * nB < kFullMinRows || n < 1 || n > kFullMaxN || H < 1 || nbt > kStreamBlocks)
+        return 0;
+    int64_t S = kStreamBlocks / nbt;
+    const int64_t smax = (nA + 15) / 16;
+    if (S > smax) S = smax;
+    return (int)(S < 1 ? 1 : S);
+}
+
+int fac_vjp_blocks(const irl_system *s, const WsLayout &L)
+{
+    if (L.kf_S > 0 && s->full) return (int)(((s->nB + kFullTB - 1) / kFullTB) * L.kf_S);
+    return fac_row_blocks(L);
+}
 
 hipError_t launch_fac_forward(const irl_system *s, const WsLayout &L, void *ws, const double *theta,
                               hipStream_t st)
@@ -606,6 +884,14 @@ hipError_t launch_fac_vjp_rows(const irl_system *s, const WsLayout &L, void *ws,
                                hipStream_t st)
 {
     if (!fac_shape_ok(s, L) || R.ns < 1 || nblk < 1 || nblk > kStreamBlocks || !y0) return hipErrorInvalidValue;
+    if (fac_full_ok(s, L, R)) {
+        switch ((s->n + 3) / 4) {
+        case 1: return vjp_full_na<4>(s, L, ws, R, y0, y1, coefp, half, nblk, st);
+        case 2: return vjp_full_na<8>(s, L, ws, R, y0, y1, coefp, half, nblk, st);
+        case 3: return vjp_full_na<12>(s, L, ws, R, y0, y1, coefp, half, nblk, st);
+        default: return vjp_full_na<16>(s, L, ws, R, y0, y1, coefp, half, nblk, st);
+        }
+    }
     const int V = 2 * s->n, H = L.hfac;
     double *part = ws_ptr<double>(ws, L.off_part);
     const int nt = (V + 15) / 16;

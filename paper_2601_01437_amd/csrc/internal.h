@@ -67,12 +67,19 @@ struct WsLayout {
            // drawn rows gathered contiguously (IRL_WS_SAMPLED with the factored Jacobian)
            off_ckeys = 0, off_cpsi = 0, off_cq = 0, off_cel = 0, off_crow = 0, off_cfac = 0;
     int hfac = 0;                                    // hidden units of the factored Jacobian
+    int kf_S = 0;   // alpha ranges of the full-space backward product (0: the matrix-core kernel)
     size_t total = 0;
 };
 
 // V: visible units (2 n_orb); with IRL_WS_FACTORED the hidden width follows from
 // ncols = V H + H + V + 1 (hfac = 0 when ncols fits no network)
-WsLayout make_layout(int64_t ns, int64_t ncols, uint32_t flags, int V);
+// fullA, fullB: string counts of a full space (0 otherwise), which enable the
+// string-split backward product of the factored Jacobian
+WsLayout make_layout(int64_t ns, int64_t ncols, uint32_t flags, int V, int64_t fullA = 0, int64_t fullB = 0);
+
+// Full-space backward product of the factored Jacobian: alpha ranges S (0 when the
+// product keeps the matrix-core kernel)
+int fac_full_ranges(int64_t nA, int64_t nB, int n, int H);
 
 // vectors the w/u, yH/yS and conversion regions of a layout hold (1, or kMaxBlock with IRL_WS_BLOCK)
 inline int layout_vectors(const WsLayout &L) { return (L.flags & IRL_WS_BLOCK) ? kMaxBlock : 1; }
@@ -305,6 +312,8 @@ hipError_t launch_fac_vjp_rows(const irl_system *s, const WsLayout &L, void *ws,
                                const double *y0, const double *y1, const double *coefp, int half, int nblk,
                                hipStream_t st);
 int fac_row_blocks_n(int64_t ns, int hfac);
+// partial rows left by launch_fac_vjp over every row of ws
+int fac_vjp_blocks(const irl_system *s, const WsLayout &L);
 hipError_t launch_nqs_dtilde(const irl_system *s, int V, int H, const double *theta,
                              const WsLayout &L, void *ws, hipStream_t st);
 hipError_t launch_dtilde_import(const void *D, int64_t ld, int64_t ncols, int dtype,

@@ -72,6 +72,60 @@ def test_factored_matches_dense_fp64(n, na, nb, V, H, count, seed):
     assert rel_err(host(yH2), host(yH1)) <= 1e-12 and rel_err(host(yS2), host(yS1)) <= 1e-12
 
 
+@pytest.mark.parametrize("n,na,nb,H,seed", [
+    (10, 5, 5, 64, 3),    # 63,504 rows: 252 x 252 strings, one hidden tile
+    (10, 5, 4, 100, 4),   # 252 x 210 strings, a ragged second hidden tile
+    (10, 4, 5, 16, 5),    # 210 x 252, a quarter of the lanes per tile
+    (13, 6, 5, 8, 6),     # 1716 x 1287 strings (2.2 M rows), 13 alpha orbitals
+])
+def test_factored_full_space_string_split(n, na, nb, H, seed):
+    """Full spaces of 32,768 rows or more take the string-split backward product
+    (alpha/beta partial sums, no matrix-core work): the gradient, the operator pair,
+    the connected-basis sigma and a whole step equal the dense FP64 path to rounding."""
+    from paper_2601_01437_amd import IRL_MODE_C, IRL_WS_FP64
+    announce(f"factored full space n={n} {na}+{nb} H={H}")
+    V = 2 * n
+    theta = synth.nqs_theta(V, H, seed, scale=0.2)
+    out = {}
+    for fl in (IRL_WS_FP64, _fl()):
+        s, _, _ = _system(n, na, nb, seed=seed)
+        assert s.info.full_space
+        Z, E, g = s.evaluate(V, H, dev(theta), ws_flags=fl)
+        v = dev(np.random.default_rng(seed).normal(size=V * H + H + V + 1))
+        yH, yS = s.apply(v)
+        rc, r, dth, _ = s.step(dev(theta), V, H, m=12, k_keep=2, ws_flags=fl, mode=IRL_MODE_C)
+        out[fl] = (Z, E, host(g), host(yH), host(yS), r.lambda_min, r.E_after, r.norm_T, host(dth))
+    a, b = out[IRL_WS_FP64], out[_fl()]
+    assert abs(b[0] - a[0]) <= 1e-13 * a[0] and abs(b[1] - a[1]) <= 1e-12
+    for k in (2, 3, 4):
+        assert rel_err(b[k], a[k]) <= 1e-12, k
+    assert abs(b[5] - a[5]) <= 1e-10 * max(abs(a[5]), a[7])
+    assert abs(b[6] - a[6]) <= 1e-12 * max(1.0, abs(a[6]))
+    assert rel_err(b[8], a[8]) <= 1e-8
+
+
+def test_factored_full_space_string_split_vs_oracle():
+    """The string-split product on 63,504 rows against the oracle's dense D~ and
+    Slater-Condon rows: Z, E, the gradient and the operator pair."""
+    announce("factored full space vs oracle n=10 5+5 H=12")
+    from oracle import space
+    n, na, nb, H, seed = 10, 5, 5, 12, 8
+    V = 2 * n
+    s, h, g = _system(n, na, nb, seed=seed)
+    keys = space.full_space(n, na, nb)
+    Hm = capply.csr(n, h, g, keys)
+    th = synth.nqs_theta(V, H, seed, scale=0.3)
+    Dt = nqs.dtilde(keys, n, V, H, th)
+    Z, _, E = lm.energy(Dt[:, 0], Hm)
+    Zg, Eg, grad = s.evaluate(V, H, dev(th), ws_flags=_fl())
+    assert abs(Zg - Z) <= 1e-12 * Z and abs(Eg - E) <= 1e-12 * max(1.0, abs(E))
+    assert rel_err(host(grad), lm.gradient(Dt, Hm)) <= 1e-10
+    v = np.random.default_rng(seed).normal(size=V * H + H + V + 1)
+    yH, yS = s.apply(dev(v))
+    rH, rS = lm.apply_lm_operator(Dt, Hm, v)
+    assert rel_err(host(yH), rH) <= 1e-10 and rel_err(host(yS), rS) <= 1e-10
+
+
 @pytest.mark.parametrize("n,na,nb,H,count,seed", [
     (6, 3, 2, 5, 151, 3),       # V = 12 (one column tile, two k-steps padded), H = 5 (unaligned d rows)
     (8, 4, 3, 64, 1001, 4),     # V = 16, exactly one hidden chunk, ragged 16-row tail
