@@ -487,7 +487,11 @@ __global__ __launch_bounds__(256) void k_fac_vjp(const uint64_t *__restrict__ ke
 // x(b)_v S_B[b][h] over the tile, and the workgroup writes one complete partial row
 // of D~^T c, as the matrix-core kernel does per row block.
 
-constexpr int kFullTB = 8;                 // beta strings per tile
+// 16 beta strings per tile and one alpha string in flight per wave: 0.087 ms at
+// 853,776 rows, against 0.110 ms with 8 strings and 0.157 / 0.161 ms with 2 / 3
+// alpha strings in flight (the deeper rings halve the waves per SIMD)
+constexpr int kFullTB = 16;
+constexpr int kFullPD = 1;
 constexpr int64_t kFullMinRows = 32768;    // smaller spaces keep the matrix-core kernel
 constexpr int kFullMaxN = 16;
 
@@ -509,7 +513,7 @@ __device__ __forceinline__ double readlane_d(double x, int l)
 
 // NR right-hand sides c_q = y_q - coef psi (coef = 0 without coefp).  NA >= n alpha
 // orbitals.  Grid: (hidden tiles of 64, tiles x S alpha ranges).
-template <int NR, int NA>
+template <int NR, int NA, int PD>
 __global__ __launch_bounds__(256) void k_fac_vjp_full(FullArgs F)
 {
     constexpr int TB = kFullTB;
@@ -527,9 +531,10 @@ __global__ __launch_bounds__(256) void k_fac_vjp_full(FullArgs F)
     const int h = 64 * ht + lane;
     const bool hv = h < F.H;
     const double coef = F.coefp ? *F.coefp : 0.0;
-    // per-row scalars, one per lane: lanes 8 k + b hold y0 (k = 0), y1 (k = 1) and
+    // per-row scalars, one per lane: lanes TB k + b hold y0 (k = 0), y1 (k = 1) and
     // psi (k = 2) of row (b0 + b, a)
-    const int bl = lane & 7, kind = lane >> 3;
+    static_assert(3 * TB <= 64 && (TB & (TB - 1)) == 0, "three scalars per tile row in one wavefront");
+    const int bl = lane & (TB - 1), kind = lane / TB;
     double sb[NR][TB], wa[NR][NA];
 #pragma unroll
     for (int q = 0; q < NR; ++q) {
@@ -538,36 +543,36 @@ __global__ __launch_bounds__(256) void k_fac_vjp_full(FullArgs F)
 #pragma unroll
         for (int v = 0; v < NA; ++v) wa[q][v] = 0.0;
     }
-    double cb = 0.0, p0 = 0.0;   // lanes 8 q + b (q < NR): C_B[b] and sum psi c of c_q
+    double cb = 0.0, p0 = 0.0;   // lanes TB q + b (q < NR): C_B[b] and sum psi c of c_q
     double xc[NR];               // lane v < n: sum_a x(a)_v C_A[a] of c_q
 #pragma unroll
     for (int q = 0; q < NR; ++q) xc[q] = 0.0;
-    double sc_n = 0.0, dv_n[TB];
-    auto fetch = [&](int64_t a) {
-        sc_n = 0.0;
+    // ring of PD alpha strings in flight per wave: one is summed, then its slot is
+    // refilled with the string PD steps ahead (strings past the range load as zeros)
+    struct Stage {
+        double sc, dv[TB];
+    };
+    auto fetch = [&](int64_t a, Stage &g) {
+        g.sc = 0.0;
         if (a < ahi && bl < nb) {
             const int64_t r = (b0 + bl) * F.nA + a;
             if (kind == 0)
-                sc_n = F.y0[r];
+                g.sc = F.y0[r];
             else if (kind == 1 && NR == 2)
-                sc_n = F.y1[r];
+                g.sc = F.y1[r];
             else if (kind == 2)
-                sc_n = F.psi[r];
+                g.sc = F.psi[r];
         }
 #pragma unroll
         for (int b = 0; b < TB; ++b)
-            dv_n[b] = (a < ahi && b < nb && hv) ? __builtin_nontemporal_load(F.dfac + ((b0 + b) * F.nA + a) * F.H + h)
+            g.dv[b] = (a < ahi && b < nb && hv) ? __builtin_nontemporal_load(F.dfac + ((b0 + b) * F.nA + a) * F.H + h)
                                                 : 0.0;
     };
-    fetch(alo + wv);
-    for (int64_t a = alo + wv; a < ahi; a += 4) {
-        const double sc = sc_n;
-        double dv[TB];
-#pragma unroll
-        for (int b = 0; b < TB; ++b) dv[b] = dv_n[b];
-        fetch(a + 4);
-        const double ps = __shfl(sc, 16 + bl, 64);
-        const double cl = kind < 2 ? sc - coef * ps : sc;    // lanes 0..7: c_0, 8..15: c_1
+    auto consume = [&](int64_t a, const Stage &g) {
+        const double sc = g.sc;
+        const double *dv = g.dv;
+        const double ps = __shfl(sc, 2 * TB + bl, 64);
+        const double cl = kind < 2 ? sc - coef * ps : sc;    // lanes TB q + b: c_q of row b
         double sa[NR];
 #pragma unroll
         for (int q = 0; q < NR; ++q) sa[q] = 0.0;
@@ -576,7 +581,7 @@ __global__ __launch_bounds__(256) void k_fac_vjp_full(FullArgs F)
             if (b < nb) {
 #pragma unroll
                 for (int q = 0; q < NR; ++q) {
-                    const double t = readlane_d(cl, 8 * q + b) * dv[b];
+                    const double t = readlane_d(cl, TB * q + b) * dv[b];
                     sa[q] += t;
                     sb[q][b] += t;
                 }
@@ -589,17 +594,26 @@ __global__ __launch_bounds__(256) void k_fac_vjp_full(FullArgs F)
 #pragma unroll
             for (int q = 0; q < NR; ++q) wa[q][v] = fma(xv, sa[q], wa[q][v]);
         }
-        // C_A[a] over the tile's beta strings (fixed 8-lane tree), folded into lane v
+        // C_A[a] over the tile's beta strings (fixed TB-lane tree), folded into lane v
         double ca = kind < NR ? cl : 0.0;
-        ca += __shfl_xor(ca, 1, 64);
-        ca += __shfl_xor(ca, 2, 64);
-        ca += __shfl_xor(ca, 4, 64);
+#pragma unroll
+        for (int off = 1; off < TB; off <<= 1) ca += __shfl_xor(ca, off, 64);
         const double xl = ((xa >> (lane & 31)) & 1u) && lane < F.n ? 1.0 : 0.0;
 #pragma unroll
-        for (int q = 0; q < NR; ++q) xc[q] = fma(xl, readlane_d(ca, 8 * q), xc[q]);
+        for (int q = 0; q < NR; ++q) xc[q] = fma(xl, readlane_d(ca, TB * q), xc[q]);
         if (kind < NR) {
             cb += cl;
             p0 = fma(cl, ps, p0);
+        }
+    };
+    Stage ring[PD];
+#pragma unroll
+    for (int p = 0; p < PD; ++p) fetch(alo + wv + 4 * p, ring[p]);
+    for (int64_t a = alo + wv; a < ahi; a += 4 * PD) {
+#pragma unroll
+        for (int p = 0; p < PD; ++p) {
+            if (a + 4 * p < ahi) consume(a + 4 * p, ring[p]);
+            fetch(a + 4 * (p + PD), ring[p]);
         }
     }
 
@@ -664,17 +678,16 @@ __global__ __launch_bounds__(256) void k_fac_vjp_full(FullArgs F)
             }
         }
         if (ht == 0) {
-            // psi^T c (8-lane tree of the lanes 8 q + b)
+            // psi^T c (TB-lane tree of the lanes TB q + b)
             double p = p0;
-            p += __shfl_xor(p, 1, 64);
-            p += __shfl_xor(p, 2, 64);
-            p += __shfl_xor(p, 4, 64);
-            const double ptot = readlane_d(p, 8 * q);
+#pragma unroll
+            for (int off = 1; off < TB; off <<= 1) p += __shfl_xor(p, off, 64);
+            const double ptot = readlane_d(p, TB * q);
             // X^T c: alpha columns from lane v, beta columns sum_b x(b)_v C_B[b]
             double xbv = 0.0;
 #pragma unroll
             for (int b = 0; b < TB; ++b) {
-                const double cbb = readlane_d(cb, 8 * q + b);
+                const double cbb = readlane_d(cb, TB * q + b);
                 xbv = fma(((xb[b] >> (lane & 31)) & 1u) ? 1.0 : 0.0, cbb, xbv);
             }
             if (lane == 0) out[0] = ptot;
@@ -785,9 +798,9 @@ hipError_t vjp_full_na(const irl_system *s, const WsLayout &L, void *ws, const F
     F.part = ws_ptr<double>(ws, L.off_part);
     const dim3 grid((unsigned)((H + 63) / 64), (unsigned)nblk);
     if (y1)
-        k_fac_vjp_full<2, NA><<<grid, 256, 0, st>>>(F);
+        k_fac_vjp_full<2, NA, kFullPD><<<grid, 256, 0, st>>>(F);
     else
-        k_fac_vjp_full<1, NA><<<grid, 256, 0, st>>>(F);
+        k_fac_vjp_full<1, NA, kFullPD><<<grid, 256, 0, st>>>(F);
     return hipGetLastError();
 }
 
