@@ -700,6 +700,126 @@ __global__ __launch_bounds__(256) void k_fac_vjp_full(FullArgs F)
     }
 }
 
+
+// Full-space D~ v (H <= 64).  With the same split, (X V_W^T)_r = A[a] + B[b] and
+// x_r . v_a = PA[a] + PB[b], so
+//   w_r = psi_r v_0 + PA[a] + PB[b] + sum_h d_rh (v_b[h] + A[a][h] + B[b][h]).
+// A workgroup takes a tile of kFullTB beta strings and an alpha range: B of the tile
+// stays in registers (a lane per hidden unit), A[a] is n multiply-adds per alpha
+// string, each row costs one add and one multiply-add per lane, and the kFullTB row
+// sums over the 64 lanes finish in one transposed butterfly (row rho ends in lane
+// L(rho) = 32 rho_3 + 16 rho_2 + 8 rho_1 + 4 rho_0, summed in a fixed order).  Its d
+// loads go through the caches and the backward product's stream past them: per
+// apply at 853,776 rows, 0.093 + 0.089 ms, against 0.092 + 0.103 ms with both
+// streaming and 0.095 + 0.106 ms with both cached.
+static_assert(kFullTB == 16, "the butterfly below reduces 16 rows");
+
+__device__ __forceinline__ int full_row_lane(int rho)
+{
+    return 32 * ((rho >> 3) & 1) + 16 * ((rho >> 2) & 1) + 8 * ((rho >> 1) & 1) + 4 * (rho & 1);
+}
+
+constexpr int kJvpChunk = 64;   // alpha strings per write-back of w
+
+template <int HALF>
+__device__ __forceinline__ void full_fold(double *acc, int lane, int bit)
+{
+    const bool up = (lane & bit) != 0;
+#pragma unroll
+    for (int i = 0; i < HALF; ++i) {
+        const double keep = up ? acc[i + HALF] : acc[i];
+        const double send = up ? acc[i] : acc[i + HALF];
+        acc[i] = keep + __shfl_xor(send, bit, 64);
+    }
+}
+
+template <int NA>
+__global__ __launch_bounds__(256) void k_fac_jvp_full(FullArgs F, const double *__restrict__ v, int zero_v0,
+                                                      double *__restrict__ w)
+{
+    constexpr int TB = kFullTB;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t wg = blockIdx.x;
+    const int64_t bt = wg / F.S;
+    const int sr = (int)(wg - bt * F.S);
+    const int64_t b0 = bt * TB;
+    const int nb = (int)(F.nB - b0 < TB ? F.nB - b0 : TB);
+    const int64_t alo = (int64_t)sr * F.aper;
+    const int64_t ahi = alo + F.aper < F.nA ? alo + F.aper : F.nA;
+    const int n = F.n, V = F.V, H = F.H;
+    const bool hv = lane < H;
+    const double v0 = zero_v0 ? 0.0 : v[0];
+    // lane h: v_b[h], its V_W row (alpha part) and B[b][h] of the tile
+    const double vb = hv ? v[1 + V + lane] : 0.0;
+    const double *vw = v + 1 + V + H + (int64_t)lane * V;
+    double vwa[NA], bb[TB];
+#pragma unroll
+    for (int k = 0; k < NA; ++k) vwa[k] = (hv && k < n) ? vw[k] : 0.0;
+#pragma unroll
+    for (int b = 0; b < TB; ++b) bb[b] = 0.0;
+    if (hv)
+        for (int k = 0; k < n; ++k) {
+            const double x = vw[n + k];
+#pragma unroll
+            for (int b = 0; b < TB; ++b)
+                if (b < nb) bb[b] = fma(((F.strB[b0 + b] >> k) & 1u) ? 1.0 : 0.0, x, bb[b]);
+        }
+    // row rho = the row this lane writes (lanes 4 j), PB[b0 + rho] and v_a of alpha
+    int rho = 0;
+    {
+        const int l = lane;
+        rho = 8 * ((l >> 5) & 1) + 4 * ((l >> 4) & 1) + 2 * ((l >> 3) & 1) + ((l >> 2) & 1);
+    }
+    const bool writer = (lane & 3) == 0 && rho < nb;
+    double pb = 0.0;
+    if (writer) {
+        const uint32_t xb = F.strB[b0 + rho];
+        for (int k = 0; k < n; ++k) pb = fma(((xb >> k) & 1u) ? 1.0 : 0.0, v[1 + n + k], pb);
+    }
+    // lane k < n: v_a[k] (PA[a] is a wavefront sum)
+    const double vak = lane < n ? v[1 + lane] : 0.0;
+    // w of the tile's rows for kJvpChunk alpha strings at a time, written back as
+    // contiguous runs of each row block
+    __shared__ double wbuf[TB * kJvpChunk];
+    for (int64_t ac = alo; ac < ahi; ac += kJvpChunk) {
+    const int64_t ace = ac + kJvpChunk < ahi ? ac + kJvpChunk : ahi;
+    for (int64_t a = ac + wv; a < ace; a += 4) {
+        double dv[TB];
+#pragma unroll
+        for (int b = 0; b < TB; ++b)
+            dv[b] = (b < nb && hv) ? F.dfac[((b0 + b) * F.nA + a) * H + lane] : 0.0;
+        const double ps = writer ? F.psi[(b0 + rho) * F.nA + a] : 0.0;
+        const uint32_t xa = F.strA[a];
+        double ua = vb;
+#pragma unroll
+        for (int k = 0; k < NA; ++k) ua = fma(((xa >> k) & 1u) ? 1.0 : 0.0, vwa[k], ua);
+        double pa = ((xa >> (lane & 31)) & 1u) ? vak : 0.0;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) pa += __shfl_xor(pa, off, 64);
+        double *acc = dv;
+#pragma unroll
+        for (int b = 0; b < TB; ++b) acc[b] = dv[b] * (ua + bb[b]);
+        // transposed butterfly: at each step a lane keeps the half of its rows named
+        // by its lane bit and adds the partner's partials of those rows
+        full_fold<8>(acc, lane, 32);
+        full_fold<4>(acc, lane, 16);
+        full_fold<2>(acc, lane, 8);
+        full_fold<1>(acc, lane, 4);
+        double sum = acc[0];
+        sum += __shfl_xor(sum, 2, 64);
+        sum += __shfl_xor(sum, 1, 64);
+        if (writer) wbuf[rho * kJvpChunk + (int)(a - ac)] = ps * v0 + (pa + pb) + sum;
+    }
+    __syncthreads();
+    const int cnt = (int)(ace - ac);
+    for (int i = threadIdx.x; i < nb * kJvpChunk; i += 256) {
+        const int r = i / kJvpChunk, c = i - r * kJvpChunk;
+        if (c < cnt) w[(b0 + r) * F.nA + ac + c] = wbuf[i];
+    }
+    __syncthreads();
+    }
+}
+
 // ---------------------------------------------------------------------------
 // launchers: KS = k-steps of 4 visible units (even, V <= 4 KS), NT = column tiles of
 // 16 visible units (V <= 16 NT)
@@ -771,13 +891,10 @@ bool fac_full_ok(const irl_system *s, const WsLayout &L, const FacRows &R)
            s->d.strA && s->d.strB && L.hfac >= 1;
 }
 
-template <int NA>
-hipError_t vjp_full_na(const irl_system *s, const WsLayout &L, void *ws, const FacRows &R, const double *y0,
-                       const double *y1, const double *coefp, int half, int nblk, hipStream_t st)
+FullArgs full_args(const irl_system *s, const WsLayout &L, const FacRows &R, const double *y0, const double *y1,
+                   const double *coefp, int half, double *part)
 {
-    const int H = L.hfac, S = L.kf_S;
-    const int64_t nbt = (s->nB + kFullTB - 1) / kFullTB;
-    if (nblk != nbt * S) return hipErrorInvalidValue;
+    const int S = L.kf_S;
     FullArgs F;
     F.dfac = R.dfac;
     F.psi = R.psi;
@@ -791,11 +908,22 @@ hipError_t vjp_full_na(const irl_system *s, const WsLayout &L, void *ws, const F
     F.aper = (s->nA + S - 1) / S;
     F.ldv = L.ldv;
     F.n = s->n;
-    F.H = H;
+    F.H = L.hfac;
     F.V = 2 * s->n;
     F.S = S;
     F.half = half;
-    F.part = ws_ptr<double>(ws, L.off_part);
+    F.part = part;
+    return F;
+}
+
+template <int NA>
+hipError_t vjp_full_na(const irl_system *s, const WsLayout &L, void *ws, const FacRows &R, const double *y0,
+                       const double *y1, const double *coefp, int half, int nblk, hipStream_t st)
+{
+    const int H = L.hfac, S = L.kf_S;
+    const int64_t nbt = (s->nB + kFullTB - 1) / kFullTB;
+    if (nblk != nbt * S) return hipErrorInvalidValue;
+    const FullArgs F = full_args(s, L, R, y0, y1, coefp, half, ws_ptr<double>(ws, L.off_part));
     const dim3 grid((unsigned)((H + 63) / 64), (unsigned)nblk);
     if (y1)
         k_fac_vjp_full<2, NA, kFullPD><<<grid, 256, 0, st>>>(F);
@@ -854,6 +982,17 @@ hipError_t launch_fac_jvp_rows(const irl_system *s, const WsLayout &L, const Fac
 {
     if (!fac_shape_ok(s, L) || R.ns < 1) return hipErrorInvalidValue;
     const int V = 2 * s->n, H = L.hfac;
+    if (fac_full_ok(s, L, R) && H <= 64) {
+        FullArgs F = full_args(s, L, R, nullptr, nullptr, nullptr, 0, nullptr);
+        const unsigned grid = (unsigned)(((s->nB + kFullTB - 1) / kFullTB) * L.kf_S);
+        switch ((s->n + 3) / 4) {
+        case 1: k_fac_jvp_full<4><<<grid, 256, 0, st>>>(F, v, zero_v0, w); break;
+        case 2: k_fac_jvp_full<8><<<grid, 256, 0, st>>>(F, v, zero_v0, w); break;
+        case 3: k_fac_jvp_full<12><<<grid, 256, 0, st>>>(F, v, zero_v0, w); break;
+        default: k_fac_jvp_full<16><<<grid, 256, 0, st>>>(F, v, zero_v0, w); break;
+        }
+        return hipGetLastError();
+    }
     switch ((V + 7) / 8) {
     case 1: jvp_ks<2>(s, R, V, H, v, zero_v0, w, st); break;
     case 2: jvp_ks<4>(s, R, V, H, v, zero_v0, w, st); break;
