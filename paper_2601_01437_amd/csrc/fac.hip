@@ -820,6 +820,99 @@ __global__ __launch_bounds__(256) void k_fac_jvp_full(FullArgs F, const double *
     }
 }
 
+
+// Full-space forward pass (H <= 64).  z_r = Z_A[a] + Z_B[b] + bias with Z_A = X_A
+// W_A^T and Z_B = X_B W_B^T: the tile's Z_B (plus the bias) stays in registers, Z_A[a]
+// is n multiply-adds per alpha string, and each row costs one tanh per lane and a
+// coalesced store of its d; psi_r = PA[a] + PB[b] + sum_h t_h with the row sums
+// taken by a transposed butterfly over 8 rows at a time (16 rows of tanh in flight
+// take more than 256 registers) and psi written back in contiguous runs.
+template <int NA>
+__global__ __launch_bounds__(256) void k_fac_forward_full(FullArgs F, const double *__restrict__ theta,
+                                                          double *__restrict__ psi, double *__restrict__ dfac)
+{
+    constexpr int TB = kFullTB;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t wg = blockIdx.x;
+    const int64_t bt = wg / F.S;
+    const int sr = (int)(wg - bt * F.S);
+    const int64_t b0 = bt * TB;
+    const int nb = (int)(F.nB - b0 < TB ? F.nB - b0 : TB);
+    const int64_t alo = (int64_t)sr * F.aper;
+    const int64_t ahi = alo + F.aper < F.nA ? alo + F.aper : F.nA;
+    const int n = F.n, V = F.V, H = F.H;
+    const bool hv = lane < H;
+    const double *av = theta, *bias = theta + V, *W = theta + V + H;
+    // lane h: the alpha part of W row h, and Z_B[b][h] + bias[h] of the tile
+    const double *wrow = W + (int64_t)lane * V;
+    double wa[NA], zb[TB];
+#pragma unroll
+    for (int k = 0; k < NA; ++k) wa[k] = (hv && k < n) ? wrow[k] : 0.0;
+    const double bh = hv ? bias[lane] : 0.0;
+#pragma unroll
+    for (int b = 0; b < TB; ++b) zb[b] = bh;
+    if (hv)
+        for (int k = 0; k < n; ++k) {
+            const double x = wrow[n + k];
+#pragma unroll
+            for (int b = 0; b < TB; ++b)
+                if (b < nb) zb[b] = fma(((F.strB[b0 + b] >> k) & 1u) ? 1.0 : 0.0, x, zb[b]);
+        }
+    // rows are summed over the lanes 8 at a time: row 8 g + rho8 of group g ends in
+    // lane 32 rho8_2 + 16 rho8_1 + 8 rho8_0, which adds PB of both of its rows
+    const int rho8 = 4 * ((lane >> 5) & 1) + 2 * ((lane >> 4) & 1) + ((lane >> 3) & 1);
+    double pb[2] = {0.0, 0.0};
+    if ((lane & 7) == 0)
+#pragma unroll
+        for (int g = 0; g < 2; ++g)
+            if (8 * g + rho8 < nb) {
+                const uint32_t xb = F.strB[b0 + 8 * g + rho8];
+                for (int k = 0; k < n; ++k) pb[g] = fma(((xb >> k) & 1u) ? 1.0 : 0.0, av[n + k], pb[g]);
+            }
+    const double ak = lane < n ? av[lane] : 0.0;   // lane k < n: a_k (PA[a] is a wavefront sum)
+    __shared__ double pbuf[TB * kJvpChunk];
+    for (int64_t ac = alo; ac < ahi; ac += kJvpChunk) {
+        const int64_t ace = ac + kJvpChunk < ahi ? ac + kJvpChunk : ahi;
+        for (int64_t a = ac + wv; a < ace; a += 4) {
+            const uint32_t xa = F.strA[a];
+            double za = 0.0;
+#pragma unroll
+            for (int k = 0; k < NA; ++k) za = fma(((xa >> k) & 1u) ? 1.0 : 0.0, wa[k], za);
+            double pa = (((xa >> (lane & 31)) & 1u) && lane < n) ? ak : 0.0;
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) pa += __shfl_xor(pa, off, 64);
+#pragma unroll
+            for (int g = 0; g < 2; ++g) {
+                double ts[8];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const int b = 8 * g + i;
+                    double t, d;
+                    tanh_and_d(za + zb[b], t, d);
+                    if (b < nb && hv) dfac[((b0 + b) * F.nA + a) * H + lane] = d;
+                    ts[i] = hv ? t : 0.0;
+                }
+                full_fold<4>(ts, lane, 32);
+                full_fold<2>(ts, lane, 16);
+                full_fold<1>(ts, lane, 8);
+                double sum = ts[0];
+                sum += __shfl_xor(sum, 4, 64);
+                sum += __shfl_xor(sum, 2, 64);
+                sum += __shfl_xor(sum, 1, 64);
+                if ((lane & 7) == 0 && 8 * g + rho8 < nb)
+                    pbuf[(8 * g + rho8) * kJvpChunk + (int)(a - ac)] = (pa + pb[g]) + sum;
+            }
+        }
+        __syncthreads();
+        const int cnt = (int)(ace - ac);
+        for (int i = threadIdx.x; i < nb * kJvpChunk; i += 256) {
+            const int r = i / kJvpChunk, c = i - r * kJvpChunk;
+            if (c < cnt) psi[(b0 + r) * F.nA + ac + c] = pbuf[i];
+        }
+        __syncthreads();
+    }
+}
+
 // ---------------------------------------------------------------------------
 // launchers: KS = k-steps of 4 visible units (even, V <= 4 KS), NT = column tiles of
 // 16 visible units (V <= 16 NT)
@@ -953,12 +1046,29 @@ int fac_vjp_blocks(const irl_system *s, const WsLayout &L)
     return fac_row_blocks(L);
 }
 
+FacRows fac_rows(const irl_system *s, const WsLayout &L, void *ws)
+{
+    return FacRows{s->d.keys, L.ns, ws_ptr<double>(ws, L.off_psi), ws_ptr<double>(ws, L.off_fac)};
+}
+
 hipError_t launch_fac_forward(const irl_system *s, const WsLayout &L, void *ws, const double *theta,
                               hipStream_t st)
 {
     if (!fac_shape_ok(s, L)) return hipErrorInvalidValue;
     const int V = 2 * s->n, H = L.hfac;
     double *psi = ws_ptr<double>(ws, L.off_psi), *dfac = ws_ptr<double>(ws, L.off_fac);
+    const FacRows R = fac_rows(s, L, ws);
+    if (fac_full_ok(s, L, R) && H <= 64) {
+        const FullArgs F = full_args(s, L, R, nullptr, nullptr, nullptr, 0, nullptr);
+        const unsigned grid = (unsigned)(((s->nB + kFullTB - 1) / kFullTB) * L.kf_S);
+        switch ((s->n + 3) / 4) {
+        case 1: k_fac_forward_full<4><<<grid, 256, 0, st>>>(F, theta, psi, dfac); break;
+        case 2: k_fac_forward_full<8><<<grid, 256, 0, st>>>(F, theta, psi, dfac); break;
+        case 3: k_fac_forward_full<12><<<grid, 256, 0, st>>>(F, theta, psi, dfac); break;
+        default: k_fac_forward_full<16><<<grid, 256, 0, st>>>(F, theta, psi, dfac); break;
+        }
+        return hipGetLastError();
+    }
     switch ((V + 7) / 8) {
     case 1: forward_ks<2>(s, L, V, H, theta, psi, dfac, st); break;
     case 2: forward_ks<4>(s, L, V, H, theta, psi, dfac, st); break;
@@ -972,10 +1082,6 @@ hipError_t launch_fac_forward(const irl_system *s, const WsLayout &L, void *ws, 
     return hipGetLastError();
 }
 
-FacRows fac_rows(const irl_system *s, const WsLayout &L, void *ws)
-{
-    return FacRows{s->d.keys, L.ns, ws_ptr<double>(ws, L.off_psi), ws_ptr<double>(ws, L.off_fac)};
-}
 
 hipError_t launch_fac_jvp_rows(const irl_system *s, const WsLayout &L, const FacRows &R, const double *v,
                                int zero_v0, double *w, hipStream_t st)
