@@ -243,6 +243,8 @@ __global__ void k_reduce_stage1(const double *__restrict__ part, int nblk, int64
     const int per = (nblk + groups - 1) / groups;
     const int b0 = g * per, b1 = min(nblk, b0 + per);
     double s = 0.0;
+    // unrolled so that the loads of 8 partial rows are in flight together (same order)
+#pragma unroll 8
     for (int b = b0; b < b1; ++b) s += part[(int64_t)b * len + c];
     part2[(int64_t)g * len + c] = s;
 }
@@ -836,6 +838,7 @@ __global__ void k_reduce_grouped(const Member *__restrict__ M, const WorkItem *_
     for (int g = 0; g < groups; ++g) {
         const int b0 = g * per, b1 = min(nblk, b0 + per);
         double s = 0.0;
+#pragma unroll 8
         for (int b = b0; b < b1; ++b) s += mb.part[(int64_t)b * len + c];
         tot += s;
     }
