@@ -58,24 +58,40 @@ def kernel_bytes(kind, ns, ncols, s_build):
 CSRC = os.path.join(ROOT, "paper_2601_01437_amd", "csrc")
 
 
+FULL_MIN_ROWS = 32768     # full spaces from this size take the string-split factored kernels
+
+
+def fac_full_kernel(kind, info, rows, H):
+    """Whether the factored product of this kind runs as the full-space (string-split)
+    kernel: every row of a full space of at least FULL_MIN_ROWS rows, n <= 16, at most
+    512 tiles of 16 beta strings, and H <= 64 for the forward pass and D~ v."""
+    if not info.full_space or rows != info.n_dets or rows < FULL_MIN_ROWS or info.n_orb > 16:
+        return False
+    if (info.n_beta_strings + 15) // 16 > 512:
+        return False
+    return kind == "gemv_t" or H <= 64
+
+
 def kernel_roofline(kind, ns, ncols, H, factored, s_build, info, stored_bytes):
     """(name, bound, algorithmic work per launch, unit, peak, source files) of one
     timed kernel kind, or None.
 
     - Dense D~ streams and the dense build: HBM bytes (kernel_bytes).
     - Factored Jacobian (d = 1 - t^2 stored, N_s x H): the forward pass writes d and
-      psi and reads the keys; D~ v reads d, keys, psi and writes w; the apply's
-      backward pass D~^T [w, u] reads d, keys, psi, w and u.  HBM bytes (their FP64
-      matrix-core work, 2 N_s V H flops per product, is below the byte time at
-      8 TB/s for these shapes).
+      psi; D~ v reads d and psi and writes w; the apply's backward pass D~^T [w, u]
+      reads d, psi, w and u.  The matrix-core forms also read the keys (8 B per
+      row); the full-space forms read per-string tables instead (kilobytes).  HBM
+      bytes: the matrix-core work, 2 N_s V H flops per product, is below the byte
+      time at 8 TB/s for these shapes, and the full-space forms have none.
     - Hamiltonian apply: stored rows stream their bytes (HBM); the enumerating
       kernels do one FP64 multiply-add per candidate excitation (2 flops against
       the vector FP64 peak)."""
     P1 = ncols
     if kind in ("gemv", "gemv_t", "dtilde_build") and factored:
         name = {"gemv": "fac_jvp", "gemv_t": "fac_vjp", "dtilde_build": "fac_forward"}[kind]
-        nbytes = {"gemv": ns * (8 * H + 24) + 8 * P1, "gemv_t": ns * (8 * H + 32) + 16 * P1,
-                  "dtilde_build": ns * (8 * H + 16)}[kind]
+        keys = 0 if fac_full_kernel(kind, info, ns, H) else 8
+        nbytes = {"gemv": ns * (8 * H + 16 + keys) + 8 * P1, "gemv_t": ns * (8 * H + 24 + keys) + 16 * P1,
+                  "dtilde_build": ns * (8 * H + 8 + keys)}[kind]
         return name, "hbm", nbytes, "GB/s", HBM_PEAK_GBPS, ("fac.hip", "internal.h")
     if kind in ("gemv", "gemv_t", "gemv_fp32", "gemv_t_fp32", "dtilde_build"):
         src = ("dtilde.hip", "internal.h") if kind != "dtilde_build" else ("nqs.hip", "internal.h")
