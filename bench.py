@@ -3,7 +3,8 @@
 
 Workload (default): 12 spatial orbitals, 6 alpha + 6 beta electrons, the full
 853,776-determinant space; random molecule-like integrals (seed 0); network
-V = 24, H = 64 (P = 1624), so D~ is 853,776 x 1625 FP64 (11.1 GB); Krylov
+V = 24, H = 64 (P = 1624), so D~ would be 853,776 x 1625 FP64 (11.1 GB): the
+default factored Jacobian keeps d = 1 - tanh^2 (853,776 x 64) instead; Krylov
 dimension 40, 10 vectors kept per restart, tolerance 1e-12; FP64.
 
 A timed step is one optimisation step: network evaluation (D~, Z, E,

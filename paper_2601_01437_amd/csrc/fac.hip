@@ -479,7 +479,7 @@ __global__ __launch_bounds__(256) void k_fac_vjp(const uint64_t *__restrict__ ke
 // and likewise for the sums of c_r in X^T c.  The (c d)^T X contraction then needs
 // no matrix-core work and one pass streams d.  A workgroup takes a tile of kFullTB
 // beta strings and one of S alpha ranges; wave w walks the alpha strings lo + w,
-// lo + w + 4, ... (the next string's rows load while the current ones are summed): it
+// lo + w + 4, ... (a ring of kFullPD strings in flight per wave): it
 // reads the tile's kFullTB rows (b, a) (a lane per hidden unit, one coalesced row per
 // load), sums them into S_A[a], which it folds into W_A[h][v] += x(a)_v S_A[a][h] at
 // once (n multiply-adds per kFullTB rows), and adds each row into S_B[b].  After a
@@ -517,7 +517,9 @@ template <int NR, int NA, int PD>
 __global__ __launch_bounds__(256) void k_fac_vjp_full(FullArgs F)
 {
     constexpr int TB = kFullTB;
-    constexpr int kAcc = NR * TB + NR * NA + 3;   // doubles per lane in the wave combination
+    // doubles per lane in the wave combination: S_B, W_A and the X^T c sums of each
+    // right-hand side, then C_B and psi^T c
+    constexpr int kAcc = NR * (TB + NA + 1) + 2;
     __shared__ double red[64 * kAcc];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int ht = blockIdx.x;
