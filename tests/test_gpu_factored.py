@@ -77,6 +77,8 @@ def test_factored_matches_dense_fp64(n, na, nb, V, H, count, seed):
     (10, 5, 4, 100, 4),   # 252 x 210 strings, a ragged second hidden tile
     (10, 4, 5, 16, 5),    # 210 x 252, a quarter of the lanes per tile
     (13, 6, 5, 8, 6),     # 1716 x 1287 strings (2.2 M rows), 13 alpha orbitals
+    (14, 1, 6, 24, 7),    # 14 x 3003 strings: one alpha range, 188 tiles of beta strings
+    (14, 6, 1, 24, 8),    # 3003 x 14 strings: one partial tile, 188 alpha ranges
 ])
 def test_factored_full_space_string_split(n, na, nb, H, seed):
     """Full spaces of 32,768 rows or more take the string-split backward product
