@@ -160,3 +160,49 @@ def eigh_lowest(A: np.ndarray):
     """Lowest eigenpair of a dense symmetric matrix (scipy)."""
     w, U = sla.eigh(A, subset_by_index=[0, 0])
     return w[0], U[:, 0]
+
+
+def streamed_evaluation(keys, n, V, H, theta, h_apply, vs=(), chunk=20_000):
+    """Energy, gradient and operator pairs over a large set without holding D~.
+
+    The same definitions as ``energy``, ``gradient`` and ``apply_lm_operator``,
+    written for sets whose D~ does not fit in host memory: rows of D~ are
+    recomputed from theta (``nqs.dtilde``) chunk by chunk for each product, and
+    H is applied matrix-free by ``h_apply(w) -> H w`` over the whole set (the
+    plain C Slater-Condon apply).  Each product D~^T y is the sum over row
+    chunks of D~_chunk^T y_chunk.  Returns (Z, E_el, g, [(y_H, y_S) per v]).
+    Pinned against the dense functions in tests/test_oracle_lm.py.
+    """
+    from . import nqs
+
+    keys = np.asarray(keys, dtype=np.uint64)
+    ns = keys.size
+    P = V * H + H + V
+
+    def rows(c0):
+        return nqs.dtilde(keys[c0:c0 + chunk], n, V, H, theta)
+
+    psi = np.empty(ns)
+    ws = [np.empty(ns) for _ in vs]
+    for c0 in range(0, ns, chunk):
+        Dc = rows(c0)
+        psi[c0:c0 + chunk] = Dc[:, 0]
+        for w, v in zip(ws, vs):
+            w[c0:c0 + chunk] = Dc @ v
+    r = h_apply(psi)
+    Z = exact_sum(psi * psi)
+    E_el = exact_sum(psi * r) / Z
+    us = [h_apply(w) for w in ws]
+    resid = r - E_el * psi
+    g = np.zeros(P)
+    yH = [np.zeros(P + 1) for _ in vs]
+    yS = [np.zeros(P + 1) for _ in vs]
+    for c0 in range(0, ns, chunk):
+        Dc = rows(c0)
+        sl = slice(c0, c0 + chunk)
+        g += Dc[:, 1:].T @ resid[sl]
+        for j in range(len(vs)):
+            yH[j] += Dc.T @ us[j][sl]
+            yS[j] += Dc.T @ ws[j][sl]
+    g *= 2.0 / Z
+    return Z, E_el, g, list(zip(yH, yS))

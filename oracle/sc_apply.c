@@ -12,8 +12,11 @@
  *   h    : n*n doubles, g : n^4 doubles, g[((p*n+q)*n+r)*n+s] = (pq|rs)
  *   rows : optional list of rows to compute (NULL: all rows)
  *
- * Pinned against the Python oracle and the brute-force Fock-space Hamiltonian
- * in tests/test_oracle_hamiltonian.py.
+ * The apply is pinned against the Python oracle and the brute-force Fock-space
+ * Hamiltonian in tests/test_oracle_hamiltonian.py; the row extraction
+ * (oracle_sc_row, the CSR of capply.csr) element by element, pattern and sign,
+ * against the brute force and the Python rows in tests/test_oracle_sc_row.py,
+ * which also compiles copies of this file with planted mistakes.
  */
 #include <stdint.h>
 #include <stddef.h>

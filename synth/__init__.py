@@ -35,6 +35,7 @@ __all__ = [
     "integrals",
     "nqs_theta",
     "n_params",
+    "probe_vector",
     "cisd_like_selected_set",
     "capped_set",
     "Workload",
@@ -82,6 +83,11 @@ def nqs_theta(V: int, H: int, seed: int = 0, scale: float = 0.05) -> np.ndarray:
     """Random NQS parameters ``theta`` in the order ``[a, b, W]``."""
     rng = np.random.default_rng([seed, 1])
     return rng.normal(0.0, scale, size=n_params(V, H))
+
+
+def probe_vector(ncols: int, seed: int = 0) -> np.ndarray:
+    """A seeded N(0, 1) vector of length ncols (operator-apply test input)."""
+    return np.random.default_rng([seed, 7]).normal(size=ncols)
 
 
 def _strings_by_rank(n: int, ne: int, max_rank: int):

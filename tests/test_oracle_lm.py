@@ -174,3 +174,52 @@ def test_trajectory_towards_fci_small():
     assert energies[-1] < energies[0]
     assert energies[-1] - e_fci < 0.5 * (energies[0] - e_fci)
     assert np.all(lams <= 1e-12)                       # mode A: predicted decrease is never positive
+
+
+@pytest.mark.parametrize("chunk", [7, 333, 100_000])
+def test_streamed_evaluation_equals_dense(c1_problem, chunk):
+    """The row-chunked evaluation (used for sets whose D~ does not fit in host
+    memory) gives the dense definitions' Z, E, gradient and operator pairs on
+    c1, including chunk sizes that leave a ragged last chunk and one chunk."""
+    from oracle import capply
+    p = c1_problem
+    w = p["w"]
+    Dt = nqs.dtilde(p["keys"], w.n, w.V, w.H, p["theta"])
+    rng = np.random.default_rng(8)
+    vs = [rng.normal(size=w.P + 1) for _ in range(2)]
+    happ = lambda x: capply.apply(w.n, p["h"], p["g"], p["keys"], x)
+    Z, E_el, g, pairs = lm.streamed_evaluation(p["keys"], w.n, w.V, w.H, p["theta"], happ, vs,
+                                               chunk=chunk)
+    Zd, Ed, _ = lm.energy(Dt[:, 0], p["H"])
+    gd = lm.gradient(Dt, p["H"])
+    assert abs(Z - Zd) <= 1e-13 * Zd and abs(E_el - Ed) <= 1e-13
+    assert np.linalg.norm(g - gd) <= 1e-12 * np.linalg.norm(gd)
+    for v, (yH, yS) in zip(vs, pairs):
+        rH, rS = lm.apply_lm_operator(Dt, p["H"], v)
+        assert np.linalg.norm(yH - rH) <= 1e-12 * np.linalg.norm(rH)
+        assert np.linalg.norm(yS - rS) <= 1e-12 * np.linalg.norm(rS)
+
+
+def test_streamed_evaluation_identities_and_fd(small):
+    """Independent of the dense functions: v = e_0 gives y_S[0] = Z and
+    y_H[0] / y_S[0] = E; the gradient matches a central finite difference of
+    E(theta); v^T y_S = |D~ v|^2."""
+    n, V, H, keys, Hm, theta = (small[k] for k in ("n", "V", "H", "keys", "Hm", "theta"))
+    P = V * H + H + V
+    e0 = np.zeros(P + 1)
+    e0[0] = 1.0
+    v = np.random.default_rng(3).normal(size=P + 1)
+    Z, E_el, g, pairs = lm.streamed_evaluation(keys, n, V, H, theta, lambda x: Hm @ x, [e0, v], chunk=50)
+    (yH0, yS0), (yH, yS) = pairs
+    assert abs(yS0[0] - Z) <= 1e-13 * Z and abs(yH0[0] / yS0[0] - E_el) <= 1e-12
+    assert abs(v @ yS - np.linalg.norm(small["Dt"] @ v) ** 2) <= 1e-11 * abs(v @ yS)
+
+    def E(t):
+        return lm.streamed_evaluation(keys, n, V, H, t, lambda x: Hm @ x, [], chunk=50)[1]
+
+    hstep = 1e-5
+    for i in list(range(0, P, 11)) + [P - 1]:
+        tp, tm = theta.copy(), theta.copy()
+        tp[i] += hstep
+        tm[i] -= hstep
+        assert abs((E(tp) - E(tm)) / (2 * hstep) - g[i]) <= 1e-7 * max(1.0, np.abs(g).max())
