@@ -1,11 +1,17 @@
 #!/usr/bin/env python3
 """Benchmark of the IRL optimisation step on one MI355X.
 
-Workload (default): 12 spatial orbitals, 6 alpha + 6 beta electrons, the full
-853,776-determinant space; random molecule-like integrals (seed 0); network
-V = 24, H = 64 (P = 1624), so D~ would be 853,776 x 1625 FP64 (11.1 GB): the
-default factored Jacobian keeps d = 1 - tanh^2 (853,776 x 64) instead; Krylov
-dimension 40, 10 vectors kept per restart, tolerance 1e-12; FP64.
+Workload (default, --config c3): 20 spatial orbitals, 10 alpha + 10 beta
+electrons, the 2^20 determinants of the seeded CISD-like selection (excitation
+rank <= 4 from the aufbau determinant, top 2^20 by the seeded |c| model);
+random molecule-like integrals (seed 0); network V = 40, H = 256 (P = 10,536),
+so D~ would be 1,048,576 x 10,537 FP64 (88.4 GB): the exact FP64 path keeps the
+factored Jacobian d = 1 - tanh^2 (1,048,576 x 256) instead; Krylov dimension 20,
+one kept vector, tolerance 1e-12; the Hamiltonian's rows inside the set are
+stored once (setup) and streamed by every apply.  Secondary figures in the same
+line: the FP32-operator path of the same workload (FP32 D~ copy, FP64 energy,
+gradient and solver) against the FP64 steps, and the 853,776-determinant full
+space (12 orbitals, 6 alpha + 6 beta, V = 24, H = 64).
 
 A timed step is one optimisation step: network evaluation (D~, Z, E,
 gradient), the implicitly restarted Lanczos solve (operator applies,
@@ -127,9 +133,11 @@ def read_traffic(kernel, workload, src_hash):
     return float(m_val.group(1))
 
 
-def cpu_baseline(wl, keys_fn, applies_per_step, sample_rows=1_000_000, chunk=20_000):
+def cpu_baseline(wl, keys_fn, applies_per_step, sample_rows=1_000_000, chunk=None, budget_s=20.0):
     """The oracle's matrix-free apply (oracle.nqs rows, oracle C Slater-Condon
-    rows, numpy products) timed on a row sample and scaled to one step."""
+    rows, numpy products) timed on a row sample and scaled to one step.  The
+    sample is a seeded random row subset, processed in chunks until about
+    budget_s seconds of host time are spent (or sample_rows rows are done)."""
     import numpy as np
 
     from oracle import capply, nqs
@@ -138,12 +146,19 @@ def cpu_baseline(wl, keys_fn, applies_per_step, sample_rows=1_000_000, chunk=20_
     h, g = wl.integrals()
     theta = wl.theta()
     rng = np.random.default_rng(0)
-    rows = np.sort(rng.choice(ns, size=min(sample_rows, ns), replace=False))
+    order = rng.permutation(ns)[:min(sample_rows, ns)]
+    if chunk is None:
+        chunk = max(256, min(20_000, (1 << 28) // (8 * (wl.P + 1))))   # D~ chunks of <= 256 MiB
     v = rng.normal(size=wl.P + 1)
     wfull = rng.normal(size=ns)       # Slater-Condon cost does not depend on w's values
     t_build = t_dv = t_h = t_dt = 0.0
-    for c0 in range(0, rows.size, chunk):
-        rs = rows[c0:c0 + chunk]
+    done = 0
+    t_start = time.perf_counter()
+    for c0 in range(0, order.size, chunk):
+        if done and time.perf_counter() - t_start > budget_s:
+            break
+        rs = np.sort(order[c0:c0 + chunk])
+        done += rs.size
         t = time.perf_counter()
         D = nqs.dtilde(keys[rs], wl.n, wl.V, wl.H, theta)
         t_build += time.perf_counter() - t
@@ -157,6 +172,7 @@ def cpu_baseline(wl, keys_fn, applies_per_step, sample_rows=1_000_000, chunk=20_
         _ = D.T @ np.stack([w, u], axis=1)
         t_dt += time.perf_counter() - t
         del D
+    rows = np.sort(order[:done])
     scale = ns / rows.size
     per_apply = (t_dv + t_h + t_dt) * scale
     per_eval = (t_build + t_h + t_dt) * scale          # D~, H psi, gradient pass
@@ -166,7 +182,7 @@ def cpu_baseline(wl, keys_fn, applies_per_step, sample_rows=1_000_000, chunk=20_
     one = None
     try:
         from threadpoolctl import threadpool_limits
-        rs = rows[: max(1, min(rows.size, 20_000))]
+        rs = rows[: max(1, min(rows.size, chunk, max(64, rows.size // 16)))]
         with threadpool_limits(limits=1):
             t = time.perf_counter()
             D = nqs.dtilde(keys[rs], wl.n, wl.V, wl.H, theta)
@@ -850,12 +866,101 @@ def run_vmc_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def fp32_operator_comparison(args, B, sysm, wl, theta0, first64, torch):
+    """The FP32-operator path of the same workload beside the FP64 steps: an FP32
+    copy of D~ (FP32 products, FP32 accumulation inside a row block), FP64 energy,
+    gradient, Lanczos and QR; without and with the FP64 polish of the Ritz pair
+    (the polish restarts the FP64 factored solve from the FP32 Ritz vector, so the
+    step then meets the FP64 tolerances).  Each variant runs K steps from theta_0;
+    the first step's eigenvalue and energy after the update are compared with the
+    FP64 path's."""
+    out = {}
+    for name, fl, flags in (("fp32", B.IRL_WS_FP32, B.IRL_STEP_NO_POLISH),
+                            ("fp32_polished", B.IRL_WS_FP32 | B.IRL_WS_FACTORED, 0)):
+        sysm.ws = None
+        torch.cuda.empty_cache()
+        th = theta0.clone()
+        rs, ms = [], []
+        for i in range(args.warmup + args.steps):
+            if i == args.warmup:
+                th.copy_(theta0)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            rc, r, _, _ = sysm.step(th, wl.V, wl.H, m=wl.m, k_keep=wl.k, tol=1e-12, precision=B.IRL_FP32,
+                                    flags=flags, ws_flags=fl, want_dtheta=False)
+            torch.cuda.synchronize()
+            if i >= args.warmup:
+                ms.append((time.perf_counter() - t) * 1e3)
+                rs.append(r)
+        r0 = rs[0]
+        out[name] = {"ms_per_step": sum(ms) / len(ms), "applies_fp32": r0.n_apply_lo,
+                     "applies_fp64": r0.n_apply - r0.n_apply_lo, "lambda": r0.lambda_min,
+                     "E_after": r0.E_after, "converged": r0.converged}
+        if first64 is not None:
+            out[name]["dlambda_vs_fp64"] = r0.lambda_min - first64["lambda_min"]
+        log(f"{name}: {out[name]['ms_per_step']:.1f} ms per step, lambda {r0.lambda_min:.6e}")
+    sysm.ws = None
+    torch.cuda.empty_cache()
+    # the FP64 first step's energy after the update (the timed steps skip it)
+    th = theta0.clone()
+    rc, r64, _, _ = sysm.step(th, wl.V, wl.H, m=wl.m, k_keep=wl.k, tol=1e-12, precision=B.IRL_FP64,
+                              ws_flags=B.IRL_WS_FACTORED, want_dtheta=False)
+    for name in out:
+        out[name]["dE_after_vs_fp64"] = out[name]["E_after"] - r64.E_after
+    out["fp64_first_step"] = {"lambda": r64.lambda_min, "E_after": r64.E_after, "norm_T": r64.norm_T}
+    sysm.ws = None
+    torch.cuda.empty_cache()
+    return out
+
+
+def full_space_secondary(args, B, synth, System, torch):
+    """K steps of the exact FP64 path (factored Jacobian) on the 853,776-determinant
+    full space (12 orbitals, 6 alpha + 6 beta, V = 24, H = 64, m = 40, k = 10), with
+    per-kernel averages from events around every launch of an untimed rerun."""
+    wl = synth.WORKLOADS["c2"]
+    h, g = wl.integrals()
+    s = System(wl.n, wl.na, wl.nb, h, g)
+    theta0 = torch.tensor(wl.theta(), dtype=torch.float64, device="cuda")
+    th = theta0.clone()
+
+    def step():
+        return s.step(th, wl.V, wl.H, m=wl.m, k_keep=wl.k, tol=1e-12, ws_flags=B.IRL_WS_FACTORED,
+                      flags=B.IRL_STEP_NO_EVAL_AFTER, want_dtheta=False)
+    for _ in range(args.warmup):
+        step()
+    th.copy_(theta0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    applies = 0
+    for _ in range(args.steps):
+        rc, r, _, _ = step()
+        applies += r.n_apply
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    th.copy_(theta0)
+    B.irl_stats_select(s.handle, None)
+    B.irl_stats_enable(s.handle, True)
+    for _ in range(args.steps):
+        step()
+    st = B.irl_stats_get(s.handle)
+    B.irl_stats_enable(s.handle, False)
+    s.close()
+    kern = {k: v[0] / v[1] for k, v in st.items() if v[1]}
+    log(f"full space: {ms:.2f} ms per step, ham {kern.get('ham_apply', 0):.3f} ms per apply")
+    return {"workload": "12 orbitals 6a+6b full space (853,776 determinants), V=24 H=64 (P=1624), "
+                        "factored FP64, m=40 k_keep=10",
+            "steps": args.steps, "ms_per_step": ms, "steps_per_s": 1000.0 / ms,
+            "applies_per_step": applies / args.steps, "kernel_ms_avg": kern}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c3s", "c4", "c5", "ablation", "vmc"])
+    ap.add_argument("--config", default="c3", choices=["c1", "c2", "c3", "c3s", "c4", "c5", "ablation", "vmc"])
+    ap.add_argument("--no-secondary", dest="secondary", action="store_false",
+                    help="c3: skip the FP32-operator comparison and the full-space (12-orbital) steps")
     ap.add_argument("--vmc-workload", default="c2", choices=["c1", "c2", "c3s"],
                     help="vmc: workload of the sampled step")
     ap.add_argument("--vmc-samples", type=int, default=1 << 17, help="vmc: draws per step")
@@ -961,7 +1066,7 @@ def main():
     log(f"system ready: {ns} determinants, ham kernel {sysm.info.ham_kernel}, {setup_ms:.1f} ms")
     theta0 = torch.tensor(wl.theta(), dtype=torch.float64, device="cuda")
     theta = theta0.clone()
-    prec_name = args.precision or wl.precision
+    prec_name = args.precision or "fp64"
     precision = B.IRL_FP64 if prec_name == "fp64" else B.IRL_FP32
     # FP32 operator: FP32 copy of D~ only, unless the FP64 polish of the Ritz pair is asked for
     if precision == B.IRL_FP64:
@@ -1079,33 +1184,36 @@ def main():
         # the kernel whose launches were bracketed live in the timed region
         spec = kernel_roofline(live[0], ns, ncols, wl.H, factored, s_build, sysm.info, stored_bytes)
         roof = rooflines.get(spec[0], roof) if spec else roof
-    # whole operator apply, per D~ copy streamed: K6 + K4 + K7 + reduction averages
+    # whole operator apply: K6 + K4 + K7 + reduction averages, against the HBM bytes the
+    # kernels of one apply must move (the D~ copy streamed twice, or for the factored
+    # Jacobian d and psi twice with w and u; the Hamiltonian's stored rows or, when it
+    # enumerates, its input and output vectors)
     operator = {}
     ham_avg = kern["ham_apply"]["ms_avg"]
     red_avg = kern.get("reduce", {}).get("ms_avg") or 0.0
+    ham_bytes = (stored_bytes if stored_bytes else 0) + 2 * 8 * ns
     for tag, g6, g7, sDo in (("fp64", "gemv", "gemv_t", 8), ("fp32", "gemv_fp32", "gemv_t_fp32", 4)):
         if g6 not in kern or g7 not in kern:
             continue
-        # bytes of one apply as the dense method streams them (D~ read twice + vectors)
-        per_apply_bytes = 2 * ns * ncols * sDo + 6 * 8 * ns
+        apply_ms = kern[g6]["ms_avg"] + ham_avg + kern[g7]["ms_avg"] + red_avg
         if tag == "fp64" and factored:
-            # D~ v, H w, then D~^T [w, u] in one backward pass
-            apply_ms = kern[g6]["ms_avg"] + ham_avg + kern[g7]["ms_avg"] + red_avg
+            b6 = kernel_roofline(g6, ns, ncols, wl.H, True, s_build, sysm.info, stored_bytes)[2]
+            b7 = kernel_roofline(g7, ns, ncols, wl.H, True, s_build, sysm.info, stored_bytes)[2]
+            moved = b6 + b7 + ham_bytes
             operator["fp64_factored"] = {
                 "applies": kern[g6]["launches"], "ms_per_apply": apply_ms,
-                "dense_stream_ms_at_peak": per_apply_bytes / (HBM_PEAK_GBPS * 1e9) * 1e3,
-                "dense_equivalent_GBps": per_apply_bytes / (apply_ms * 1e-3) / 1e9,
-                "vs_dense_stream_roofline": per_apply_bytes / (apply_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS,
-                "factored_bytes_per_apply": ns * (8 * wl.H + 24) + ns * (8 * wl.H + 32) + 2 * 8 * ns,
-                "bytes_per_apply_dense": per_apply_bytes}
+                "bytes_per_apply": moved, "GBps": moved / (apply_ms * 1e-3) / 1e9,
+                "frac_hbm": moved / (apply_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS,
+                "network_products_frac_hbm": (b6 + b7) / ((kern[g6]["ms_avg"] + kern[g7]["ms_avg"]) * 1e-3)
+                / 1e9 / HBM_PEAK_GBPS,
+                "dense_method_bytes_per_apply": 2 * ns * ncols * 8 + 6 * 8 * ns}
             continue
-        apply_ms = kern[g6]["ms_avg"] + ham_avg + kern[g7]["ms_avg"] + red_avg
+        moved = 2 * ns * ncols * sDo + 2 * 8 * ns + ham_bytes
         operator[tag] = {"applies": kern[g6]["launches"], "ms_per_apply": apply_ms,
-                         "GBps": per_apply_bytes / (apply_ms * 1e-3) / 1e9,
-                         "frac_hbm": per_apply_bytes / (apply_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS,
+                         "bytes_per_apply": moved, "GBps": moved / (apply_ms * 1e-3) / 1e9,
+                         "frac_hbm": moved / (apply_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS,
                          "stream_frac_hbm": (2 * ns * ncols * sDo) / ((kern[g6]["ms_avg"] + kern[g7]["ms_avg"]) * 1e-3)
-                         / 1e9 / HBM_PEAK_GBPS,
-                         "bytes_per_apply": per_apply_bytes}
+                         / 1e9 / HBM_PEAK_GBPS}
     operator["ham_ms_per_apply"] = ham_avg
     operator["ham_candidates_per_s"] = ns * sysm.info.max_connections / (ham_avg * 1e-3)
 
@@ -1128,6 +1236,15 @@ def main():
                     "dlambda": r32.lambda_min - r64.lambda_min, "dE_after": r32.E_after - r64.E_after}
         log(f"fp64 reference step: {ms64:.1f} ms, dlambda {fp64_ref['dlambda']:.3e}, "
             f"dE_after {fp64_ref['dE_after']:.3e}")
+
+    fp32_op = None
+    if precision == B.IRL_FP64 and args.config == "c3" and args.secondary:
+        fp32_op = fp32_operator_comparison(args, B, sysm, wl, theta0, steps[0] if steps else None, torch)
+    full_space = None
+    if args.config == "c3" and args.secondary:
+        sysm.ws = None
+        torch.cuda.empty_cache()
+        full_space = full_space_secondary(args, B, synth, System, torch)
 
     hbm_ref = measured_hbm_peak(torch)
     log(f"measured HBM reference: read {hbm_ref['read_GBps']:.0f} GB/s, copy {hbm_ref['copy_GBps']:.0f} GB/s")
@@ -1177,6 +1294,8 @@ def main():
         "stored_rows": store,
         "hbm_reference": hbm_ref,
         "fp64_reference": fp64_ref,
+        "fp32_operator": fp32_op,
+        "full_space_12_orbitals": full_space,
         "trajectory": steps,
         "E_final": Ef,
     }

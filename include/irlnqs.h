@@ -127,8 +127,11 @@ enum irl_system_flags {
     IRL_SYS_FORCE_HASH = 1u,     /* use the general hashed per-determinant Hamiltonian
                                     apply for every set (full spaces and selected sets
                                     that would otherwise take the beta-blocked kernel) */
-    IRL_SYS_FORCE_PULL = 2u      /* full space: per-determinant kernel with string-rank
+    IRL_SYS_FORCE_PULL = 2u,     /* full space: per-determinant kernel with string-rank
                                     lookup instead of the string-product kernel */
+    IRL_SYS_STORE_SLICED = 4u    /* irl_system_store_hamiltonian uses the LDS-sliced
+                                    layout for any set size (by default only sets of
+                                    more than 2^18 determinants do) */
 };
 
 typedef struct irl_system irl_system;
@@ -216,7 +219,8 @@ typedef struct {
  * key -> row lookup, the integrals and the diagonal H_xx.  Inputs are copied;
  * the library owns the device tables until irl_system_destroy.
  * Errors: IRL_EINVAL (n out of range, wrong popcount or orbital outside n,
- * duplicate keys, non-symmetric h or g beyond 1e-12, empty set), IRL_ENOMEM,
+ * duplicate keys, the reserved key 2^64 - 1, non-symmetric h or g beyond
+ * 1e-12, empty set), IRL_ENOMEM,
  * IRL_EDEVICE.  *out is NULL on error. */
 int irl_system_create(const irl_system_desc *desc, void *stream, irl_system **out);
 
@@ -229,17 +233,24 @@ int irl_system_info_get(const irl_system *sys, irl_system_info *out);
 /* Store the off-diagonal elements of H inside the set (Methods, "Wave Function
  * Ansatz": the second-quantised electronic Hamiltonian, whose elements between
  * determinants follow from the Slater-Condon rules) as
- * compressed rows split into column blocks: the targets of block b are rows
- * [b 2^s, (b + 1) 2^s), a slice of the amplitude vector of about 2 MiB (at most 8
- * blocks), so the gathers of one block stay in the L2 cache.  Layout: row offsets
- * int64[blocks][n_dets + 1] (block-major), targets int32[nnz], values FP64[nnz],
- * device memory owned by the system.  Later applies stream these rows one block
- * at a time instead of enumerating excitations (ham_kernel becomes 4,
- * stored_col_blocks reports the block count); results agree with the enumerating
- * kernels to rounding (summation order differs) and are reproducible.  Two
- * enumeration passes count and fill the rows; the call synchronises stream.
+ * compressed rows split into column blocks.  Sets of up to 2^18 determinants:
+ * the targets of block b are rows [b 2^s, (b + 1) 2^s), a slice of the amplitude
+ * vector of about 2 MiB (at most 8 blocks), so the gathers of one block stay in
+ * the L2 cache; layout: row offsets int64[blocks][n_dets + 1] (block-major),
+ * targets int32[nnz], values FP64[nnz]; bytes_needed = blocks * (n_dets + 1) * 8
+ * + nnz * 12.  Larger sets (or IRL_SYS_STORE_SLICED): slices of 2^14 target rows,
+ * whose 128 KiB of amplitudes one workgroup stages in LDS, at most 256 slices;
+ * layout per slice b: offsets uint32[n_dets + 1] relative to the slice's first
+ * element, the slice's base offset int64, then each row's elements ordered by
+ * target with 16-bit targets (row - b 2^14) and FP64 values; bytes_needed =
+ * slices * (n_dets + 1) * 4 + slices * 8 + nnz * 10.  Device memory is owned by
+ * the system.  Later applies stream these rows instead of enumerating
+ * excitations (ham_kernel becomes 4, stored_col_blocks reports the block or
+ * slice count); results agree with the enumerating kernels to rounding
+ * (summation order differs) and are reproducible.  Enumeration passes count and
+ * fill the rows; the call synchronises stream.
  * max_bytes: device bytes the caller allows for the stored rows.
- * bytes_needed (may be NULL): receives blocks * (n_dets + 1) * 8 + nnz * 12.
+ * bytes_needed (may be NULL): receives the byte count above.
  * Errors: IRL_ENOMEM when the rows need more than max_bytes or allocation
  * fails (the system is unchanged and stays usable), IRL_EDEVICE, IRL_EINVAL.
  * Calling it again after success does nothing. */
@@ -521,6 +532,17 @@ int irl_debug_diagonal(const irl_system *sys, double *out);
  * number of connections; IRL_EINVAL if it exceeds cap. */
 int irl_debug_excitations(const irl_system *sys, int64_t row, int32_t *target, int8_t *sign,
                           uint8_t *kind, double *hval, int64_t cap, int64_t *count);
+
+/* Copy rows [row0, row0 + nrows) of the current evaluation's tangent basis
+ * (Methods, "From SR to a Stable Eigenvalue Problem": chi_0 = psi and the
+ * parameter derivatives) to host memory.  psi: FP64[nrows].  rows: with the
+ * factored Jacobian (IRL_WS_FACTORED) d = 1 - tanh^2(z) as FP64[nrows x H]
+ * (*kind = 0, *ncols_out = H); else the rows of the FP64 D~ copy as
+ * FP64[nrows x (P+1)] (*kind = 1) or of the FP32 copy as FP32[nrows x (P+1)]
+ * (*kind = 2), *ncols_out = P+1.  Either pointer may be NULL.  IRL_ESTATE when
+ * ws holds no evaluation, IRL_EINVAL for a row range outside [0, N_s). */
+int irl_debug_jacobian(irl_system *sys, void *ws, size_t ws_bytes, int64_t row0, int64_t nrows,
+                       double *psi_host, void *rows_host, int32_t *kind, int64_t *ncols_out);
 
 /* Run j_end Lanczos steps of the centred mode-A (or mode-P) operator from the
  * unit vector v1 (device), no restart, and copy to host: the basis

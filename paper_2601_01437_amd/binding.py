@@ -31,6 +31,7 @@ IRL_STEP_FULL_CYCLES = 16
 IRL_STEP_GRAPH = 32
 IRL_SYS_FORCE_HASH = 1
 IRL_SYS_FORCE_PULL = 2
+IRL_SYS_STORE_SLICED = 4
 STAT_KINDS = ("dtilde_build", "ham_apply", "gemv", "gemv_t", "reduce", "energy", "lanczos", "ritz",
               "gemv_fp32", "gemv_t_fp32", "vmc")
 
@@ -135,6 +136,8 @@ _sigs = {
     "irl_debug_diagonal": (c_int32, [_SYS, c_void_p]),
     "irl_debug_excitations": (c_int32, [_SYS, c_int64, c_void_p, c_void_p, c_void_p, c_void_p,
                                         c_int64, POINTER(c_int64)]),
+    "irl_debug_jacobian": (c_int32, [_SYS, c_void_p, c_size_t, c_int64, c_int64, c_void_p, c_void_p,
+                                     POINTER(c_int32), POINTER(c_int64)]),
     "irl_debug_lanczos": (c_int32, [_SYS, c_void_p, c_size_t, c_void_p, c_int32, c_int32, c_int32,
                                     c_void_p, c_void_p, c_void_p, c_void_p]),
 }
@@ -352,6 +355,19 @@ def irl_debug_diagonal(sys, n_dets):
     out = np.empty(n_dets, dtype=np.float64)
     _check(_lib.irl_debug_diagonal(sys, out.ctypes.data), sys)
     return out
+
+
+def irl_debug_jacobian(sys, ws, row0, nrows):
+    """(psi, rows, kind): psi FP64[nrows]; rows d (kind 0, FP64 nrows x H) or
+    D~ rows (kind 1 FP64, kind 2 FP32; nrows x (P+1))."""
+    kind, nc = c_int32(0), c_int64(0)
+    _check(_lib.irl_debug_jacobian(sys, _ptr(ws), ws.numel(), row0, 0, None, None, ctypes.byref(kind),
+                                   ctypes.byref(nc)), sys)
+    psi = np.empty(nrows, dtype=np.float64)
+    rows = np.empty((nrows, nc.value), dtype=np.float32 if kind.value == 2 else np.float64)
+    _check(_lib.irl_debug_jacobian(sys, _ptr(ws), ws.numel(), row0, nrows, psi.ctypes.data, rows.ctypes.data,
+                                   ctypes.byref(kind), ctypes.byref(nc)), sys)
+    return psi, rows, kind.value
 
 
 def irl_debug_excitations(sys, row, cap=70000):

@@ -2,8 +2,7 @@
 
 Every HIP source is compiled for gfx950 only, with packed FP32 instructions
 disabled, then linked into one shared library exporting the C ABI of
-``include/irlnqs.h`` (linked against rocBLAS, used for the dense DGEMMs of the
-same-spin doubles of small full spaces).  Run ``python paper_2601_01437_amd/build.py`` (by path: importing the package
+``include/irlnqs.h`` (HIP runtime only: every kernel is in ``csrc/``).  Run ``python paper_2601_01437_amd/build.py`` (by path: importing the package
 itself loads the library).
 """
 from __future__ import annotations
@@ -58,8 +57,7 @@ def build(verbose: bool = True) -> str:
     with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
         objs = list(ex.map(_compile, srcs))
     tmp = LIB + f".tmp{os.getpid()}"
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs, "-L/opt/rocm/lib", "-lrocblas",
-           "-Wl,-rpath,/opt/rocm/lib"]
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
     proc = subprocess.run(cmd, capture_output=True, text=True)
     if proc.returncode != 0:
         raise RuntimeError(f"link failed:\n{proc.stdout}\n{proc.stderr}")

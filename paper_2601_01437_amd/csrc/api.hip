@@ -76,7 +76,7 @@ void free_system(irl_system *s)
                     s->d.rankB, s->d.strA, s->d.strB, s->d.sglA, s->d.sglB, s->d.fA, s->d.fB,
                     s->d.dblA_rank, s->d.dblA_val, s->d.dblB_rank, s->d.dblB_val, s->d.jA,
                     s->d.jB, s->d.sglA_ia, s->d.sglB_ia, s->d.hfilter, s->d.bidx, s->d.bstart,
-                    s->d.hptr, s->d.hcol, s->d.hval};
+                    s->d.hptr, s->d.hcol, s->d.hval, s->d.sptr, s->d.sbase, s->d.scol, s->d.sval};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (s->host_scal) (void)hipHostFree(s->host_scal);
@@ -557,7 +557,7 @@ int irl_solve(irl_system *s, void *ws, const WsLayout &L, const irl_solver_opts 
         key.seed = o.seed;
         key.vmc = s->vmc;
         key.vmc_rows = s->vmc_rows;
-        key.hptr = s->d.hptr;
+        key.hptr = s->d.scb ? (const void *)s->d.sval : (const void *)s->d.hptr;
         cg = cycle_entry(s, key);
     }
     int pending = -1;   // restart not yet launched: from basis `pending` (graph replay)
@@ -806,6 +806,7 @@ int irl_system_create(const irl_system_desc *d, void *stream, irl_system **out)
     s->na = na;
     s->nb = nb;
     s->e_core = d->e_core;
+    s->sys_flags = d->flags;
     hipStream_t st = (hipStream_t)stream;
     (void)hipGetDevice(&s->device);
     const int64_t cA = binom_host(n, na), cB = binom_host(n, nb);
@@ -818,6 +819,7 @@ int irl_system_create(const irl_system_desc *d, void *stream, irl_system **out)
         for (size_t i = 0; i < keys.size(); ++i) {
             uint32_t al = (uint32_t)keys[i], be = (uint32_t)(keys[i] >> 32);
             if (i > 0 && keys[i] == keys[i - 1]) { free_system(s); return set_err(nullptr, IRL_EINVAL, "duplicate determinant keys"); }
+            if (keys[i] == kEmptyKey) { free_system(s); return set_err(nullptr, IRL_EINVAL, "key 2^64 - 1 is reserved"); }
             if ((n < 32 && ((al >> n) || (be >> n))) || __builtin_popcount(al) != na ||
                 __builtin_popcount(be) != nb) {
                 free_system(s);
@@ -920,14 +922,105 @@ int irl_system_create(const irl_system_desc *d, void *stream, irl_system **out)
 
 void irl_system_destroy(irl_system *sys) { free_system(sys); }
 
+}  // extern "C"
+
+namespace {
+
+size_t sliced_bytes(int scb, int64_t ns, int64_t nnz)
+{
+    return (size_t)scb * (ns + 1) * 4 + (size_t)scb * 8 + (size_t)nnz * 10;
+}
+
+// Stored rows in the LDS-sliced layout (sets of at least kSlicedMinRows rows): count
+// the connections of every row per slice, offsets on the host, fill and order.
+int store_sliced(irl_system *s, size_t max_bytes, size_t *bytes_needed, hipStream_t st)
+{
+    const int64_t ns = s->ns;
+    const int scs = kSliceLog;
+    const int scb = (int)((ns + ((int64_t)1 << scs) - 1) >> scs);
+    uint32_t *dcount = nullptr;
+    CK(s, hipMalloc((void **)&dcount, (size_t)scb * ns * 4));
+    std::vector<uint32_t> count((size_t)scb * ns);
+    hipError_t e = launch_ham_count_sliced(s, scs, scb, dcount, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(count.data(), dcount, (size_t)scb * ns * 4, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipFree(dcount);
+    if (e != hipSuccess) return set_err(s, IRL_EDEVICE, std::string("row counts: ") + hipGetErrorString(e));
+    // per slice: offsets relative to the slice's first element (32-bit), slice bases
+    std::vector<uint32_t> ptr((size_t)scb * (ns + 1));
+    std::vector<int64_t> base(scb);
+    int64_t nnz = 0;
+    for (int b = 0; b < scb; ++b) {
+        uint32_t *pb = ptr.data() + (size_t)b * (ns + 1);
+        const uint32_t *cb = count.data() + (size_t)b * ns;
+        base[b] = nnz;
+        uint64_t run = 0;
+        pb[0] = 0;
+        for (int64_t r = 0; r < ns; ++r) {
+            run += cb[r];
+            if (run > 0xffffffffull) return set_err(s, IRL_EINVAL, "a slice holds more than 2^32 - 1 elements");
+            pb[r + 1] = (uint32_t)run;
+        }
+        nnz += (int64_t)run;
+    }
+    const size_t bytes = sliced_bytes(scb, ns, nnz);
+    if (bytes_needed) *bytes_needed = bytes;
+    if (bytes > max_bytes)
+        return set_err(s, IRL_ENOMEM, "stored rows need " + std::to_string(bytes) +
+                                          " bytes, more than max_bytes = " + std::to_string(max_bytes));
+    const size_t bytes_before = s->dev_bytes;
+    auto release = [&]() {
+        s->dev_bytes = bytes_before;
+        for (void *p : {(void *)s->d.sptr, (void *)s->d.sbase, (void *)s->d.scol, (void *)s->d.sval})
+            if (p) (void)hipFree(p);
+        s->d.sptr = nullptr;
+        s->d.sbase = nullptr;
+        s->d.scol = nullptr;
+        s->d.sval = nullptr;
+    };
+    int rc;
+    if ((rc = dev_alloc(s, &s->d.sptr, (size_t)scb * (ns + 1))) != IRL_OK ||
+        (rc = dev_alloc(s, &s->d.sbase, (size_t)scb)) != IRL_OK ||
+        (rc = dev_alloc(s, &s->d.scol, (size_t)std::max<int64_t>(nnz, 1))) != IRL_OK ||
+        (rc = dev_alloc(s, &s->d.sval, (size_t)std::max<int64_t>(nnz, 1))) != IRL_OK) {
+        release();
+        return rc;
+    }
+    e = hipMemcpyAsync(s->d.sptr, ptr.data(), ptr.size() * 4, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(s->d.sbase, base.data(), base.size() * 8, hipMemcpyHostToDevice, st);
+    // slots the fill does not reach (none, if the two enumerations agree) gather in bounds
+    if (e == hipSuccess) e = hipMemsetAsync(s->d.scol, 0, (size_t)std::max<int64_t>(nnz, 1) * 2, st);
+    if (e == hipSuccess) e = hipMemsetAsync(s->d.sval, 0, (size_t)std::max<int64_t>(nnz, 1) * 8, st);
+    if (e == hipSuccess) e = launch_ham_fill_sliced(s, scs, scb, s->d.sbase, s->d.sptr, s->d.scol, s->d.sval, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        release();
+        return set_err(s, IRL_EDEVICE, std::string("stored rows: ") + hipGetErrorString(e));
+    }
+    s->d.scb = scb;
+    s->d.scs = scs;
+    s->d.hnnz = nnz;
+    s->ham_kernel = 4;
+    return IRL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 int irl_system_store_hamiltonian(irl_system *s, size_t max_bytes, size_t *bytes_needed, void *stream)
 {
     if (!s) return set_err(nullptr, IRL_EINVAL, "system is NULL");
     const int64_t ns = s->ns;
     if (s->ham_kernel == 4) {
-        if (bytes_needed) *bytes_needed = (size_t)s->d.hcb * (ns + 1) * 8 + (size_t)s->d.hnnz * 12;
+        if (bytes_needed)
+            *bytes_needed = s->d.scb ? sliced_bytes(s->d.scb, ns, s->d.hnnz)
+                                     : (size_t)s->d.hcb * (ns + 1) * 8 + (size_t)s->d.hnnz * 12;
         return IRL_OK;
     }
+    if ((ns >= kSlicedMinRows || (s->sys_flags & IRL_SYS_STORE_SLICED)) &&
+        ((ns + ((int64_t)1 << kSliceLog) - 1) >> kSliceLog) <= kMaxSlices)
+        return store_sliced(s, max_bytes, bytes_needed, (hipStream_t)stream);
     // column blocks: slices of w of about kColSliceBytes, a power of two rows wide
     int hcs = 0;
     while (hcs < 40 && ((int64_t)8 << hcs) < kColSliceBytes) ++hcs;
@@ -1016,7 +1109,7 @@ int irl_system_info_get(const irl_system *s, irl_system_info *o)
                          (int64_t)s->na * va * s->nb * vb;
     o->device_bytes = s->dev_bytes;
     o->ham_kernel = s->ham_kernel;
-    o->stored_col_blocks = s->ham_kernel == 4 ? s->d.hcb : 0;
+    o->stored_col_blocks = s->ham_kernel == 4 ? (s->d.scb ? s->d.scb : s->d.hcb) : 0;
     return IRL_OK;
 }
 
@@ -1461,6 +1554,43 @@ int irl_debug_excitations(const irl_system *cs, int64_t row, int32_t *target, in
     return rc;
 }
 
+int irl_debug_jacobian(irl_system *s, void *ws, size_t ws_bytes, int64_t row0, int64_t nrows,
+                       double *psi_host, void *rows_host, int32_t *kind, int64_t *ncols_out)
+{
+    if (!s) return IRL_EINVAL;
+    if (!s->ws_valid || ws != s->ws) return set_err(s, IRL_ESTATE, "workspace holds no evaluation");
+    const WsLayout &L = s->lay;
+    if (ws_bytes < L.total) return set_err(s, IRL_ENOMEM, "workspace too small");
+    if (row0 < 0 || nrows < 0 || row0 + nrows > L.ns) return set_err(s, IRL_EINVAL, "row range outside the set");
+    CK(s, hipDeviceSynchronize());
+    if (psi_host && nrows)
+        CK(s, hipMemcpy(psi_host, ws_ptr<double>(ws, L.off_psi) + row0, (size_t)nrows * 8, hipMemcpyDeviceToHost));
+    int32_t kd;
+    int64_t nc;
+    if ((L.flags & IRL_WS_FACTORED) && L.hfac > 0) {
+        kd = 0;
+        nc = L.hfac;
+        if (rows_host && nrows)
+            CK(s, hipMemcpy(rows_host, ws_ptr<double>(ws, L.off_fac) + row0 * (int64_t)L.hfac,
+                            (size_t)nrows * L.hfac * 8, hipMemcpyDeviceToHost));
+    } else if (L.flags & IRL_WS_FP64) {
+        kd = 1;
+        nc = L.ncols;
+        if (rows_host && nrows)
+            CK(s, hipMemcpy2D(rows_host, (size_t)L.ncols * 8, ws_ptr<double>(ws, L.off_d64) + row0 * L.ld64,
+                              (size_t)L.ld64 * 8, (size_t)L.ncols * 8, (size_t)nrows, hipMemcpyDeviceToHost));
+    } else {
+        kd = 2;
+        nc = L.ncols;
+        if (rows_host && nrows)
+            CK(s, hipMemcpy2D(rows_host, (size_t)L.ncols * 4, ws_ptr<float>(ws, L.off_d32) + row0 * L.ld32,
+                              (size_t)L.ld32 * 4, (size_t)L.ncols * 4, (size_t)nrows, hipMemcpyDeviceToHost));
+    }
+    if (kind) *kind = kd;
+    if (ncols_out) *ncols_out = nc;
+    return IRL_OK;
+}
+
 int irl_debug_lanczos(irl_system *s, void *ws, size_t ws_bytes, const double *v1, int32_t j_end,
                       int32_t precision, int32_t mode, double *V_host, double *alpha_host,
                       double *beta_host, void *stream)
@@ -1595,8 +1725,9 @@ int build_lists(irl_batch *b, const std::vector<int> &subset, int region, int pr
         for (int m : (hrows ? by_cost : subset)) {
             const Member &mb = b->hm[m];
             // the stored rows a member uses are those in its view taken at batch create
+            // LDS-sliced stored rows run their solo launch (as the string product does)
             const bool stored = mb.ham.hptr != nullptr;
-            const bool product = !stored && b->sys[m]->ham_kernel == 2;
+            const bool product = (!stored && b->sys[m]->ham_kernel == 2) || mb.ham.sval != nullptr;
             switch (kind) {
             case LS_ROWS6: rows(m, 512); ls.lds6 = std::max(ls.lds6, (size_t)mb.ld * (prec == IRL_FP64 ? 8 : 4)); break;
             case LS_ROWS4R:

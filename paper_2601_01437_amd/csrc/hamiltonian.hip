@@ -20,7 +20,6 @@
 // reproducible.
 #include "internal.h"
 
-#include <rocblas/rocblas.h>
 
 namespace irl {
 
@@ -509,6 +508,220 @@ __global__ __launch_bounds__(256) void k_ham_fill(HamArgs A, const int64_t *__re
     }
 }
 
+// ---- stored rows, LDS-sliced layout ---------------------------------------------
+// For sets larger than an L2-resident slice of w, the targets are split into
+// slices of 2^scs rows whose w (128 KiB) one workgroup stages in LDS, so the
+// random gathers of w become LDS reads and HBM streams only the elements.  Per
+// slice b: row offsets sptr[b][row] relative to the slice's first element
+// sbase[b], then each row's elements ordered by target, targets as 16-bit
+// indices inside the slice and FP64 values (10 bytes per element).
+
+// first pass: connections of each row inside each slice (count[b ns + row])
+template <int LK>
+__global__ __launch_bounds__(256) void k_ham_count_sliced(HamArgs A, int scs, int scb, uint32_t *__restrict__ count)
+{
+    __shared__ WaveLists lists[4];
+    __shared__ uint32_t cnt[4][kMaxSlices];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t nwaves = (int64_t)gridDim.x * 4;
+    for (int64_t row = (int64_t)blockIdx.x * 4 + wv; row < A.ns; row += nwaves) {
+        for (int b = lane; b < scb; b += kWave) cnt[wv][b] = 0u;
+        const uint64_t key = A.keys[row];
+        const uint32_t al = (uint32_t)key, be = (uint32_t)(key >> 32);
+        prepare_row<LK>(A, lists[wv], al, be, lane);
+        visit_row<LK>(A, lists[wv], al, be, lane, kWave, [&](int64_t r, int, int, double) {
+            atomicAdd(&cnt[wv][(int)(r >> scs)], 1u);
+        });
+        end_row();
+        for (int b = lane; b < scb; b += kWave) count[(int64_t)b * A.ns + row] = cnt[wv][b];
+        end_row();
+    }
+}
+
+// second pass: each connection takes the next free slot of its row's slice segment
+// (LDS cursors; slot order is arbitrary), written only inside the segment
+template <int LK>
+__global__ __launch_bounds__(256) void k_ham_fill_sliced(HamArgs A, int scs, int scb, const int64_t *__restrict__ sbase,
+                                                         const uint32_t *__restrict__ sptr,
+                                                         uint16_t *__restrict__ scol, double *__restrict__ sval)
+{
+    __shared__ WaveLists lists[4];
+    __shared__ uint32_t cur[4][kMaxSlices];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t nwaves = (int64_t)gridDim.x * 4;
+    const uint32_t mask = (1u << scs) - 1u;
+    for (int64_t row = (int64_t)blockIdx.x * 4 + wv; row < A.ns; row += nwaves) {
+        for (int b = lane; b < scb; b += kWave) cur[wv][b] = 0u;
+        const uint64_t key = A.keys[row];
+        const uint32_t al = (uint32_t)key, be = (uint32_t)(key >> 32);
+        prepare_row<LK>(A, lists[wv], al, be, lane);
+        visit_row<LK>(A, lists[wv], al, be, lane, kWave, [&](int64_t r, int, int, double v) {
+            const int b = (int)(r >> scs);
+            const uint32_t *pb = sptr + (int64_t)b * (A.ns + 1);
+            const uint32_t k = atomicAdd(&cur[wv][b], 1u);
+            const uint32_t q = pb[row] + k;
+            if (q < pb[row + 1]) {
+                scol[sbase[b] + q] = (uint16_t)((uint32_t)r & mask);
+                sval[sbase[b] + q] = v;
+            }
+        });
+        end_row();
+    }
+}
+
+// third pass: order every (slice, row) segment by target (insertion sort, one
+// thread per segment), so the stored layout and the apply's summation order do
+// not depend on the fill's slot order
+__global__ __launch_bounds__(256) void k_ham_sort_sliced(int64_t ns, int scb, const int64_t *__restrict__ sbase,
+                                                         const uint32_t *__restrict__ sptr,
+                                                         uint16_t *__restrict__ scol, double *__restrict__ sval)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ns * scb) return;
+    const int b = (int)(t / ns);
+    const int64_t row = t - (int64_t)b * ns;
+    const uint32_t *pb = sptr + (int64_t)b * (ns + 1);
+    uint16_t *c = scol + sbase[b];
+    double *v = sval + sbase[b];
+    const uint32_t p0 = pb[row], p1 = pb[row + 1];
+    for (uint32_t i = p0 + 1; i < p1; ++i) {
+        const uint16_t ci = c[i];
+        const double vi = v[i];
+        uint32_t j = i;
+        while (j > p0 && c[j - 1] > ci) {
+            c[j] = c[j - 1];
+            v[j] = v[j - 1];
+            --j;
+        }
+        c[j] = ci;
+        v[j] = vi;
+    }
+}
+
+hipError_t launch_ham_count_sliced(const irl_system *s, int scs, int scb, uint32_t *count, hipStream_t st)
+{
+    HamArgs A = ham_view(s);
+    int64_t blocks = (s->ns + 3) / 4;
+    if (blocks > 65536) blocks = 65536;
+    if (s->lookup == kLkBlocks)
+        k_ham_count_sliced<kLkBlocks><<<(unsigned)blocks, 256, 0, st>>>(A, scs, scb, count);
+    else if (s->lookup == kLkHash)
+        k_ham_count_sliced<kLkHash><<<(unsigned)blocks, 256, 0, st>>>(A, scs, scb, count);
+    else
+        k_ham_count_sliced<kLkRanks><<<(unsigned)blocks, 256, 0, st>>>(A, scs, scb, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_ham_fill_sliced(const irl_system *s, int scs, int scb, const int64_t *sbase,
+                                  const uint32_t *sptr, uint16_t *scol, double *sval, hipStream_t st)
+{
+    HamArgs A = ham_view(s);
+    int64_t blocks = (s->ns + 3) / 4;
+    if (blocks > 65536) blocks = 65536;
+    if (s->lookup == kLkBlocks)
+        k_ham_fill_sliced<kLkBlocks><<<(unsigned)blocks, 256, 0, st>>>(A, scs, scb, sbase, sptr, scol, sval);
+    else if (s->lookup == kLkHash)
+        k_ham_fill_sliced<kLkHash><<<(unsigned)blocks, 256, 0, st>>>(A, scs, scb, sbase, sptr, scol, sval);
+    else
+        k_ham_fill_sliced<kLkRanks><<<(unsigned)blocks, 256, 0, st>>>(A, scs, scb, sbase, sptr, scol, sval);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t segs = s->ns * scb;
+    k_ham_sort_sliced<<<(unsigned)((segs + 255) / 256), 256, 0, st>>>(s->ns, scb, sbase, sptr, scol, sval);
+    return hipGetLastError();
+}
+
+// Apply: a workgroup owns kSlcRows rows and walks the slices in order.  Per slice
+// it stages w (2^scs rows) and its rows' offsets in LDS; groups of G lanes take one
+// row each (rows grp, grp + NG, ...), every lane loading kSlcUnroll elements of the
+// segment at once (stride G), so most segments need one pass; the G partial sums
+// are combined by a fixed butterfly and added to the row's LDS accumulator in slice
+// order.  Finally u = H_rr w + accumulator.
+constexpr int kSlcThreads = 512;
+constexpr int kSlcRows = 2048;
+constexpr int kSlcUnroll = 4;
+
+template <int G>
+__global__ __launch_bounds__(kSlcThreads) void k_ham_sliced(HamArgs A, const double *__restrict__ w,
+                                                            double *__restrict__ u, int64_t r0, int64_t r1)
+{
+    __shared__ double wl[1 << kSliceLog];
+    __shared__ double acc[kSlcRows];
+    __shared__ uint32_t pl[kSlcRows + 1];
+    constexpr int NG = kSlcThreads / G;
+    const int t = threadIdx.x, grp = t / G, l = t % G;
+    const int64_t rb = r0 + (int64_t)blockIdx.x * kSlcRows;
+    const int nr = (int)min((int64_t)kSlcRows, r1 - rb);
+    for (int i = t; i < nr; i += kSlcThreads) acc[i] = 0.0;
+    for (int b = 0; b < A.scb; ++b) {
+        const int64_t c0 = (int64_t)b << A.scs;
+        const int nc = (int)min((int64_t)1 << A.scs, A.ns - c0);
+        __syncthreads();   // the previous slice is consumed
+        for (int i = 2 * t; i < nc; i += 2 * kSlcThreads) {
+            if (i + 1 < nc) {
+                const double2 x = *reinterpret_cast<const double2 *>(w + c0 + i);
+                wl[i] = x.x;
+                wl[i + 1] = x.y;
+            } else {
+                wl[i] = w[c0 + i];
+            }
+        }
+        const uint32_t *pb = A.sptr + (int64_t)b * (A.ns + 1) + rb;
+        for (int i = t; i <= nr; i += kSlcThreads) pl[i] = pb[i];
+        __syncthreads();
+        const uint16_t *col = A.scol + A.sbase[b];
+        const double *val = A.sval + A.sbase[b];
+        for (int i = grp; i < nr; i += NG) {
+            const uint32_t p0 = pl[i], p1 = pl[i + 1];
+            double sum = 0.0;
+            for (uint32_t p = p0 + l; p < p1; p += kSlcUnroll * G) {
+                double v[kSlcUnroll];
+                uint32_t c[kSlcUnroll];
+#pragma unroll
+                for (int q = 0; q < kSlcUnroll; ++q) {
+                    const uint32_t pq = p + q * G;
+                    v[q] = pq < p1 ? __builtin_nontemporal_load(val + pq) : 0.0;
+                    c[q] = pq < p1 ? (uint32_t)__builtin_nontemporal_load(col + pq) : 0u;
+                }
+#pragma unroll
+                for (int q = 0; q < kSlcUnroll; ++q) sum += v[q] * wl[c[q]];
+            }
+#pragma unroll
+            for (int off = G / 2; off > 0; off >>= 1) sum += __shfl_xor(sum, off, G);
+            if (l == 0) acc[i] += sum;
+        }
+    }
+    __syncthreads();
+    for (int i = t; i < nr; i += kSlcThreads) {
+        const int64_t row = rb + i;
+        u[row] = fma(A.diag[row], w[row], acc[i]);
+    }
+}
+
+// lanes per row: the smallest group whose one pass (kSlcUnroll G elements) covers
+// 5/4 of the mean segment length of a (slice, row) pair
+static int sliced_group(const irl_system *s)
+{
+    const double mean = (double)s->d.hnnz / ((double)s->ns * (double)(s->d.scb ? s->d.scb : 1));
+    if (kSlcUnroll * 4 >= 1.25 * mean) return 4;
+    if (kSlcUnroll * 8 >= 1.25 * mean) return 8;
+    if (kSlcUnroll * 16 >= 1.25 * mean) return 16;
+    return 32;
+}
+
+static hipError_t launch_ham_sliced(const irl_system *s, const HamArgs &A, const double *w, double *u, int64_t r0,
+                                    int64_t r1, hipStream_t st)
+{
+    const unsigned blocks = (unsigned)((r1 - r0 + kSlcRows - 1) / kSlcRows);
+    switch (sliced_group(s)) {
+    case 4: k_ham_sliced<4><<<blocks, kSlcThreads, 0, st>>>(A, w, u, r0, r1); break;
+    case 8: k_ham_sliced<8><<<blocks, kSlcThreads, 0, st>>>(A, w, u, r0, r1); break;
+    case 16: k_ham_sliced<16><<<blocks, kSlcThreads, 0, st>>>(A, w, u, r0, r1); break;
+    default: k_ham_sliced<32><<<blocks, kSlcThreads, 0, st>>>(A, w, u, r0, r1); break;
+    }
+    return hipGetLastError();
+}
+
 // Grouped H rows: one block per 4-row group, as in the solo launch.  Item k
 // = (member m, first block a, b row groups); the items are in ascending a, and
 // each block finds its item by a binary search (uniform, scalar loads).
@@ -597,6 +810,12 @@ HamView ham_view(const irl_system *s)
     A.hval = s->ham_kernel == 4 ? s->d.hval : nullptr;
     A.hcb = s->d.hcb;
     A.hcs = s->d.hcs;
+    A.sptr = s->ham_kernel == 4 ? s->d.sptr : nullptr;
+    A.sbase = s->ham_kernel == 4 ? s->d.sbase : nullptr;
+    A.scol = s->ham_kernel == 4 ? s->d.scol : nullptr;
+    A.sval = s->ham_kernel == 4 ? s->d.sval : nullptr;
+    A.scb = s->d.scb;
+    A.scs = s->d.scs;
     A.rankA = s->d.rankA;
     A.rankB = s->d.rankB;
     return A;
@@ -620,6 +839,7 @@ hipError_t launch_ham_apply_rows(const irl_system *s, const double *w, double *u
     HamArgs A = ham_view(s);
     int64_t blocks = (r1 - r0 + 3) / 4;
     if (blocks > 65536) blocks = 65536;
+    if (s->ham_kernel == 4 && A.sval) return launch_ham_sliced(s, A, w, u, r0, r1, st);
     if (s->ham_kernel == 4) {
         for (int b = 0; b < A.hcb; ++b) {
             k_ham_stored<<<(unsigned)blocks, 256, 0, st>>>(A, w, u, r0, r1, b);
@@ -1056,8 +1276,6 @@ constexpr int64_t kDenseDoublesMax = 2048;
 
 void free_dense_doubles(irl_system *s)
 {
-    if (s->blas) (void)rocblas_destroy_handle((rocblas_handle)s->blas);
-    s->blas = nullptr;
     for (double **p : {&s->d.denseA, &s->d.denseB}) {
         if (*p) (void)hipFree(*p);
         *p = nullptr;
@@ -1080,15 +1298,138 @@ static hipError_t build_dense_doubles(irl_system *s, int nda, int ndb, hipStream
                                                                      s->d.denseA);
     k_dense_doubles<<<(unsigned)((s->nB + 127) / 128), 128, 0, st>>>(s->d.dblB_rank, s->d.dblB_val, s->nB, ndb,
                                                                      s->d.denseB);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    rocblas_handle hb = nullptr;
-    if (rocblas_create_handle(&hb) != rocblas_status_success) return hipErrorUnknown;
-    s->blas = hb;
-    // reproducible results: no split reductions with atomics
-    if (rocblas_set_atomics_mode(hb, rocblas_atomics_not_allowed) != rocblas_status_success ||
-        rocblas_set_pointer_mode(hb, rocblas_pointer_mode_host) != rocblas_status_success)
-        return hipErrorUnknown;
-    return hipSuccess;
+    return hipGetLastError();
+}
+
+// ---- same-spin doubles as one FP64 matrix-core product ------------------------
+// With w as the column-major nA x nB matrix X (column = beta string) and D_A, D_B
+// the symmetric same-spin double matrices of each spin,
+//     U[:, b0:b1] += D_A X[:, b0:b1] + X D_B[:, b0:b1],
+// computed as a single product over the concatenated inner index (the nA alpha
+// strings of the first term, then the nB beta strings of the second), so each
+// 64 x 64 tile of U is read and written once, in a fixed summation order.
+// Workgroup: 4 wavefronts, each owning a 32 x 32 quarter of the tile as 2 x 2
+// blocks of v_mfma_f64_16x16x4f64; inner tiles of 32 are staged through LDS
+// (double-buffered, one barrier per inner tile) and loaded from memory two tiles
+// ahead into registers, so an L2/MALL round trip overlaps two tiles of matrix-core
+// work.  Operand layout of the instruction (lane l): A[l % 16][l / 16],
+// B[l / 16][l % 16]; result register r holds D[4 r + l / 16][l % 16].
+namespace {
+constexpr int kDblTM = 64, kDblTN = 64, kDblTK = 32, kDblThreads = 256;
+constexpr int kDblLdB = kDblTN + 1;   // padded rows of the B tile (conflict-free column stores)
+constexpr int kDblPer = kDblTM * kDblTK / kDblThreads;   // tile elements per thread (8)
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+struct DblArgs {
+    const double *DA, *DB, *X;   // nA x nA, nB x nB, nA x nB (column-major)
+    double *U;                   // nA x nB, columns [b0, b1) updated
+    int64_t nA, nB, b0, nbeta;
+};
+
+struct DblRegs {
+    double a[kDblPer], b[kDblPer];
+};
+}  // namespace
+
+__global__ void __launch_bounds__(kDblThreads) k_same_spin_doubles(DblArgs a)
+{
+    __shared__ double As[2][kDblTK][kDblTM];
+    __shared__ double Bs[2][kDblTK][kDblLdB];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int64_t m0 = (int64_t)blockIdx.x * kDblTM, n0 = (int64_t)blockIdx.y * kDblTN;
+    const int64_t M = a.nA, N = a.nbeta;
+    const int nk1 = (int)((a.nA + kDblTK - 1) / kDblTK), nk2 = (int)((a.nB + kDblTK - 1) / kDblTK);
+    const int nkt = nk1 + nk2;
+    // A tile element (row m0 + t % 64, inner k0 + t / 64 + 4 j); B tile element
+    // (inner k0 + t % 32, column n0 + t / 32 + 8 j)
+    const int ar = t & 63, ak = t >> 6, bk = t & 31, bn = t >> 5;
+    auto load = [&](int kt, DblRegs &R) {
+        if (kt >= nkt) return;
+        const bool first = kt < nk1;
+        const int64_t k0 = (int64_t)(first ? kt : kt - nk1) * kDblTK;
+        const int64_t K = first ? a.nA : a.nB;
+        // first term: A = D_A (ld nA), B = X[:, b0 + n] (ld nA);
+        // second term: A = X (ld nA), B = D_B[:, b0 + n] (ld nB)
+        const double *A = first ? a.DA : a.X;
+        const double *Bm = first ? a.X : a.DB;
+        const int64_t ldb = first ? a.nA : a.nB;
+        const int64_t m = m0 + ar;
+#pragma unroll
+        for (int j = 0; j < kDblPer; ++j) {
+            const int64_t k = k0 + ak + 4 * j;
+            R.a[j] = (m < M && k < K) ? A[k * a.nA + m] : 0.0;
+        }
+        const int64_t kb = k0 + bk;
+#pragma unroll
+        for (int j = 0; j < kDblPer; ++j) {
+            const int64_t n = n0 + bn + 8 * j;
+            R.b[j] = (n < N && kb < K) ? Bm[(a.b0 + n) * ldb + kb] : 0.0;
+        }
+    };
+    auto store = [&](int buf, const DblRegs &R) {
+#pragma unroll
+        for (int j = 0; j < kDblPer; ++j) As[buf][ak + 4 * j][ar] = R.a[j];
+#pragma unroll
+        for (int j = 0; j < kDblPer; ++j) Bs[buf][bk][bn + 8 * j] = R.b[j];
+    };
+    dbl4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+    const int wm = (wv & 1) * 32, wn = (wv >> 1) * 32;
+    const int lr = lane & 15, lk = lane >> 4;
+    DblRegs r0, r1;
+    load(0, r0);
+    store(0, r0);
+    load(1, r0);   // tile kt + 1, stored at the end of iteration kt
+    load(2, r1);   // tile kt + 2, in flight across two iterations
+    __syncthreads();
+    for (int kt = 0; kt < nkt; ++kt) {
+        const int buf = kt & 1;
+#pragma unroll
+        for (int ks = 0; ks < kDblTK; ks += 4) {
+            double fa[2], fb[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) fa[i] = As[buf][ks + lk][wm + 16 * i + lr];
+#pragma unroll
+            for (int j = 0; j < 2; ++j) fb[j] = Bs[buf][ks + lk][wn + 16 * j + lr];
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[i], fb[j], acc[i][j], 0, 0, 0);
+        }
+        if (kt + 1 < nkt) store(buf ^ 1, r0);
+        r0 = r1;
+        load(kt + 3, r1);
+        __syncthreads();
+    }
+    // U tile += acc (row m0 + wm + 16 i + 4 r + l / 16, column n0 + wn + 16 j + l % 16)
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int64_t n = n0 + wn + 16 * j + lr;
+            if (n >= N) continue;
+            double *col = a.U + (a.b0 + n) * a.nA;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t m = m0 + wm + 16 * i + 4 * r + lk;
+                if (m < M) col[m] += acc[i][j][r];
+            }
+        }
+}
+
+static hipError_t launch_same_spin_doubles(const irl_system *s, const double *w, double *u, int64_t b0,
+                                           int64_t nbeta, hipStream_t st)
+{
+    if (nbeta <= 0) return hipSuccess;
+    DblArgs a{s->d.denseA, s->d.denseB, w, u, s->nA, s->nB, b0, nbeta};
+    dim3 grid((unsigned)((s->nA + kDblTM - 1) / kDblTM), (unsigned)((nbeta + kDblTN - 1) / kDblTN));
+    k_same_spin_doubles<<<grid, kDblThreads, 0, st>>>(a);
+    return hipGetLastError();
 }
 
 hipError_t launch_product_tables(irl_system *s, hipStream_t st)
@@ -1164,7 +1505,7 @@ static hipError_t launch_ham_product(const irl_system *s, const double *w, doubl
 {
     ProdArgs P;
     P.rb0 = b0;
-    P.dense = s->d.denseA != nullptr && s->blas != nullptr;
+    P.dense = s->d.denseA != nullptr && s->d.denseB != nullptr;
     const int64_t nbeta = b1 - b0;
     product_fits(s, P.nsa, P.nsb, P.nda, P.ndb);
     P.n = s->n;
@@ -1195,18 +1536,7 @@ static hipError_t launch_ham_product(const irl_system *s, const double *w, doubl
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !P.dense) return e;
-    // same-spin doubles: with w as the column-major nA x nB matrix X (column = beta
-    // string), U[:, b0:b1] += D_A X[:, b0:b1] + X D_B[:, b0:b1] (D_A, D_B symmetric)
-    rocblas_handle hb = (rocblas_handle)s->blas;
-    const double one = 1.0;
-    const rocblas_int mA = (rocblas_int)s->nA, kB = (rocblas_int)s->nB, nb = (rocblas_int)nbeta;
-    if (rocblas_set_stream(hb, st) != rocblas_status_success ||
-        rocblas_dgemm(hb, rocblas_operation_none, rocblas_operation_none, mA, nb, mA, &one, s->d.denseA, mA,
-                      w + b0 * s->nA, mA, &one, u + b0 * s->nA, mA) != rocblas_status_success ||
-        rocblas_dgemm(hb, rocblas_operation_none, rocblas_operation_none, mA, nb, kB, &one, w, mA,
-                      s->d.denseB + b0 * s->nB, kB, &one, u + b0 * s->nA, mA) != rocblas_status_success)
-        return hipErrorUnknown;
-    return hipSuccess;
+    return launch_same_spin_doubles(s, w, u, b0, nbeta, st);
 }
 
 }  // namespace irl

@@ -110,6 +110,15 @@ struct SystemDev {
     int64_t hnnz = 0;
     int32_t hcb = 0;              // column blocks of the stored rows
     int32_t hcs = 0;              // log2 of the target rows per column block
+    // stored rows, LDS-sliced layout (large sets): column slices of 2^scs target rows
+    // (a slice of w staged in LDS); per slice, row offsets relative to the slice's
+    // first element, targets as 16-bit indices inside the slice, values FP64
+    uint32_t *sptr = nullptr;     // scb blocks of n_dets + 1 offsets
+    int64_t *sbase = nullptr;     // scb element offsets of the slices
+    uint16_t *scol = nullptr;     // nnz targets (row - slice start)
+    double *sval = nullptr;       // nnz values
+    int32_t scb = 0;              // slices (0: the L2-block layout above, if any)
+    int32_t scs = 0;
     // string tables (full space)
     int32_t *rankA = nullptr;   // 2^n, -1 for strings not of popcount n_alpha
     int32_t *rankB = nullptr;
@@ -150,6 +159,11 @@ struct HamView {
     const int32_t *hcol;     // stored rows: targets
     const double *hval;      // stored rows: values
     int hcb, hcs;            // stored rows: column blocks, log2 of their width in rows
+    const uint32_t *sptr;    // stored rows, LDS-sliced layout (or nullptr)
+    const int64_t *sbase;
+    const uint16_t *scol;
+    const double *sval;
+    int scb, scs;
 };
 
 // key -> row lookup used when excitations are enumerated
@@ -193,6 +207,7 @@ struct irl_system {
     int64_t ns = 0;
     int64_t nA = 0, nB = 0;   // string counts (full space) or distinct counts
     bool full = false;
+    uint32_t sys_flags = 0;   // irl_system_flags given at create
     int ham_kernel = 0;       // 0 hashed pull, 1 rank pull, 2 string product, 3 blocked pull,
                               // 4 stored rows
     int lookup = 0;           // irl::LookupMode of the excitation enumeration
@@ -212,8 +227,6 @@ struct irl_system {
     int64_t vmc_rows = 0;     // drawn rows gathered contiguously (0: products run over every row)
     // pinned host staging for small readbacks
     irl::WsScalars *host_scal = nullptr;
-    // dense BLAS handle (rocblas_handle) for the same-spin doubles of a full space
-    void *blas = nullptr;
     // captured Lanczos cycles (graph replay of small operators); owned by api.hip
     void *cycle_graphs = nullptr;
     hipStream_t capture_stream = nullptr;
@@ -241,6 +254,15 @@ hipError_t launch_hash_lookup(const uint64_t *hkeys, const int32_t *hrows, uint6
                               const uint64_t *q, int64_t nq, int32_t *rows, hipStream_t st);
 hipError_t launch_diagonal(const uint64_t *keys, int64_t ns, int n, const double *h,
                            const double *g, double *diag, hipStream_t st);
+// stored rows, LDS-sliced layout (hamiltonian.hip): count[b n_dets + row] = connections of
+// row inside slice b; fill writes targets and values at sbase[b] + sptr[b][row] + k and
+// orders each row's slice segment by target
+constexpr int kSliceLog = 14;            // 2^14 target rows (128 KiB of w) per slice
+constexpr int kMaxSlices = 256;          // sets of up to 2^22 determinants
+constexpr int64_t kSlicedMinRows = ((int64_t)1 << 18) + 1;   // up to 2^18 rows: the L2-block layout
+hipError_t launch_ham_count_sliced(const irl_system *s, int scs, int scb, uint32_t *count, hipStream_t st);
+hipError_t launch_ham_fill_sliced(const irl_system *s, int scs, int scb, const int64_t *sbase,
+                                  const uint32_t *sptr, uint16_t *scol, double *sval, hipStream_t st);
 hipError_t launch_lookup_any(const irl_system *s, const uint64_t *q, int64_t nq, int32_t *rows,
                              hipStream_t st);
 

@@ -124,6 +124,7 @@ hipError_t launch_hash_build(const uint64_t *keys, int64_t ns, uint64_t *hkeys, 
 __device__ __forceinline__ int32_t hash_find(const uint64_t *hkeys, const int32_t *hrows,
                                              uint64_t mask, uint64_t key)
 {
+    if (key == kEmptyKey) return -1;   // the empty-slot marker is never a member
     uint64_t slot = mix64(key) & mask;
     for (uint64_t probe = 0; probe <= mask; ++probe) {
         uint64_t k = hkeys[slot];

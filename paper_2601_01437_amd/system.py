@@ -70,6 +70,10 @@ class System:
     def excitations(self, row):
         return B.irl_debug_excitations(self.handle, row)
 
+    def jacobian_rows(self, row0, nrows):
+        """(psi, rows, kind) of the current evaluation (see irl_debug_jacobian)."""
+        return B.irl_debug_jacobian(self.handle, self.ws, row0, nrows)
+
     def evaluate(self, V, H, theta, ws_flags=B.IRL_WS_FP64, want_grad=True):
         P = V * H + H + V
         ws = self.workspace(P + 1, ws_flags)

@@ -60,24 +60,88 @@ def test_stored_rows_count_and_apply(n, na, nb, count, seed, flags):
     assert again and need2 == need
 
 
-def test_stored_rows_column_blocks_match_enumeration():
-    """300,000 determinants: the stored rows split into two column blocks (2^18
-    target rows each, the second ragged).  The blocked apply equals the
-    enumerating kernel of the same system (itself pinned to the oracle) to FP64
-    rounding, and is bitwise reproducible."""
-    announce("stored rows: two column blocks")
-    keys = synth.cisd_like_selected_set(14, 7, 7, 300000, seed=3)
-    s, _, _ = _system(14, 7, 7, 3, keys)
-    w = dev(np.random.default_rng(7).normal(size=keys.size))
+SLICED_CASES = [  # (n, na, nb, selected count or None, seed, system flags)
+    (10, 5, 5, None, 0, 2),         # full space (63,504 rows): 4 slices, the last ragged
+    (10, 5, 5, 20000, 2, 0),        # selected, beta-blocked lookup: 2 slices
+    (10, 5, 5, 16384, 2, 1),        # selected, hashed lookup: exactly one slice
+    (9, 5, 4, 1, 5, 0),             # one determinant: no off-diagonal elements
+]
+
+
+@pytest.mark.parametrize("n,na,nb,count,seed,flags", SLICED_CASES)
+def test_stored_rows_lds_slices_count_and_apply(n, na, nb, count, seed, flags):
+    """LDS-sliced layout (slices of 2^14 target rows, forced by
+    IRL_SYS_STORE_SLICED on sets this small): the byte size fixes the element
+    count, which must equal the oracle's number of connections inside the set;
+    the apply matches the oracle to FP64 rounding, repeats bitwise, and a second
+    system built from the same set stores the same rows (segments ordered by
+    target)."""
+    from paper_2601_01437_amd import IRL_SYS_STORE_SLICED
+    announce(f"stored rows, LDS slices: n={n} count={count} flags={flags}")
+    keys = (space.full_space(n, na, nb) if count is None
+            else synth.cisd_like_selected_set(n, na, nb, count, seed=seed))
+    fl = flags | IRL_SYS_STORE_SLICED
+    s, h, g = _system(n, na, nb, seed, None if count is None else keys, fl)
+    Href = capply.csr(n, h, g, np.sort(keys))
+    nnz_off = Href.nnz - keys.size
+    stored, need = s.store_hamiltonian(1 << 40)
+    nsl = -(-keys.size // (1 << 14))
+    assert stored and s.info.ham_kernel == 4 and s.info.stored_col_blocks == nsl
+    assert need == nsl * (keys.size + 1) * 4 + nsl * 8 + 10 * nnz_off
+    w_h = np.random.default_rng(4).normal(size=keys.size)
+    w = dev(w_h)
+    u1 = host(s.apply_hamiltonian(w))
+    assert rel_err(u1, Href @ w_h) <= 1e-12
+    assert np.array_equal(host(s.apply_hamiltonian(w)), u1)
+    s2, _, _ = _system(n, na, nb, seed, None if count is None else keys, fl)
+    assert s2.store_hamiltonian(1 << 40) == (True, need)
+    assert np.array_equal(host(s2.apply_hamiltonian(w)), u1)
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("count", [300000, (1 << 18) + 1])
+def test_stored_rows_lds_slices_large(count):
+    """Sets above 2^18 determinants take the LDS-sliced layout by default: 300,000
+    rows give 19 slices (the last ragged), 2^18 + 1 rows 17 (the last holds one
+    row).  The apply equals the enumerating kernel of the same system (pinned to
+    the oracle) to FP64 rounding and the oracle's rows on a sample, and is
+    bitwise reproducible across two systems built from the same set."""
+    announce(f"stored rows: LDS slices, {count} rows")
+    keys = synth.cisd_like_selected_set(14, 7, 7, count, seed=3)
+    s, h, g = _system(14, 7, 7, 3, keys)
+    w_h = np.random.default_rng(7).normal(size=keys.size)
+    w = dev(w_h)
     u_enum = host(s.apply_hamiltonian(w))
     stored, need = s.store_hamiltonian(1 << 40)
-    assert stored and s.info.ham_kernel == 4 and s.info.stored_col_blocks == 2
+    nsl = -(-keys.size // (1 << 14))
+    assert stored and s.info.ham_kernel == 4 and s.info.stored_col_blocks == nsl
+    assert (need - nsl * (keys.size + 1) * 4 - nsl * 8) % 10 == 0
     u1 = host(s.apply_hamiltonian(w))
     assert rel_err(u1, u_enum) <= 1e-12
+    sk = np.sort(keys)
+    rows = np.concatenate([np.random.default_rng(8).choice(keys.size, 400, replace=False),
+                           [0, keys.size - 1, (1 << 14) - 1, 1 << 14]])
+    ref = capply.apply(14, h, g, sk, w_h, rows=rows)
+    assert np.max(np.abs(u1[rows] - ref)) <= 1e-12 * np.abs(ref).max()
     assert np.array_equal(host(s.apply_hamiltonian(w)), u1)
     s2, _, _ = _system(14, 7, 7, 3, keys)
     assert s2.store_hamiltonian(1 << 40) == (True, need)
     assert np.array_equal(host(s2.apply_hamiltonian(w)), u1)
+
+
+def test_stored_rows_largest_l2_block_set():
+    """2^18 determinants exactly (the largest set of the L2-block layout): one
+    column block of 2^18 target rows; apply against the enumerating kernel."""
+    announce("stored rows: L2 column block at 2^18 rows")
+    keys = synth.cisd_like_selected_set(14, 7, 7, 1 << 18, seed=3)
+    s, _, _ = _system(14, 7, 7, 3, keys)
+    w = dev(np.random.default_rng(7).normal(size=keys.size))
+    u_enum = host(s.apply_hamiltonian(w))
+    stored, need = s.store_hamiltonian(1 << 40)
+    assert stored and s.info.ham_kernel == 4 and s.info.stored_col_blocks == 1
+    u1 = host(s.apply_hamiltonian(w))
+    assert rel_err(u1, u_enum) <= 1e-12
+    assert np.array_equal(host(s.apply_hamiltonian(w)), u1)
 
 
 def test_stored_rows_over_budget_leaves_system_unchanged():
