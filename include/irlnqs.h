@@ -161,6 +161,8 @@ typedef struct {
                                per-determinant (selected sets with n_orb <= 24),
                                4: stored rows (irl_system_store_hamiltonian) */
     int32_t stored_col_blocks;  /* column blocks of the stored rows (0 unless ham_kernel == 4) */
+    int64_t stored_elements;    /* off-diagonal elements stored (padding excluded; 0 unless
+                                   ham_kernel == 4) */
 } irl_system_info;
 
 typedef struct {
@@ -239,11 +241,21 @@ int irl_system_info_get(const irl_system *sys, irl_system_info *out);
  * the L2 cache; layout: row offsets int64[blocks][n_dets + 1] (block-major),
  * targets int32[nnz], values FP64[nnz]; bytes_needed = blocks * (n_dets + 1) * 8
  * + nnz * 12.  Larger sets (or IRL_SYS_STORE_SLICED): slices of 2^14 target rows,
- * whose 128 KiB of amplitudes one workgroup stages in LDS, at most 256 slices;
- * layout per slice b: offsets uint32[n_dets + 1] relative to the slice's first
- * element, the slice's base offset int64, then each row's elements ordered by
- * target with 16-bit targets (row - b 2^14) and FP64 values; bytes_needed =
- * slices * (n_dets + 1) * 4 + slices * 8 + nnz * 10.  Device memory is owned by
+ * whose 128 KiB of amplitudes one workgroup stages in LDS, at most 256 slices.
+ * Inside a slice the rows are taken in windows of 4096; a window's rows are
+ * ordered by their number of elements in the slice (descending, ties by row)
+ * and grouped 64 at a time, one row per lane of a wavefront; a group stores
+ * L x 64 slots (L = its longest row), slot (j, lane) holding the lane row's
+ * j-th element (zero padding past the row's end) as a 16-bit target (row - b
+ * 2^14) and an FP64 value, so every element load of a wavefront is 512
+ * contiguous bytes.  Per slice and group: the slot offset (uint32) and L
+ * (uint16); per lane of a group: the lane's row inside its window (uint16,
+ * 0xffff for an empty lane); per slice: the slot base (int64) and one FP64
+ * partial sum per row,
+ * which each apply writes and then sums in slice order.  bytes_needed = groups
+ * * slices * 6 + groups * 64 * slices * 2 + slices * 8 + slots * 10 + slices *
+ * n_dets * 8 (groups = ceil(n_dets / 64); slots counts the padding).  Device
+ * memory is owned by
  * the system.  Later applies stream these rows instead of enumerating
  * excitations (ham_kernel becomes 4, stored_col_blocks reports the block or
  * slice count); results agree with the enumerating kernels to rounding

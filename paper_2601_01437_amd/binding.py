@@ -55,7 +55,8 @@ class irl_system_info(ctypes.Structure):
     _fields_ = [("n_dets", c_int64), ("n_orb", c_int32), ("n_alpha", c_int32),
                 ("n_beta", c_int32), ("full_space", c_int32), ("n_alpha_strings", c_int64),
                 ("n_beta_strings", c_int64), ("max_connections", c_int64),
-                ("device_bytes", c_size_t), ("ham_kernel", c_int32), ("stored_col_blocks", c_int32)]
+                ("device_bytes", c_size_t), ("ham_kernel", c_int32), ("stored_col_blocks", c_int32),
+                ("stored_elements", c_int64)]
 
 
 class irl_nqs_desc(ctypes.Structure):

@@ -76,7 +76,8 @@ void free_system(irl_system *s)
                     s->d.rankB, s->d.strA, s->d.strB, s->d.sglA, s->d.sglB, s->d.fA, s->d.fB,
                     s->d.dblA_rank, s->d.dblA_val, s->d.dblB_rank, s->d.dblB_val, s->d.jA,
                     s->d.jB, s->d.sglA_ia, s->d.sglB_ia, s->d.hfilter, s->d.bidx, s->d.bstart,
-                    s->d.hptr, s->d.hcol, s->d.hval, s->d.sptr, s->d.sbase, s->d.scol, s->d.sval};
+                    s->d.hptr, s->d.hcol, s->d.hval, s->d.sbase, s->d.sgbase, s->d.sglen, s->d.sperm,
+                    s->d.scol, s->d.sval, s->d.spart};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (s->host_scal) (void)hipHostFree(s->host_scal);
@@ -235,7 +236,7 @@ int apply_internal(irl_system *s, void *ws, const WsLayout &L, const double *v, 
                         ws_ptr<double>(ws, L.off_cfac)};
         TIMED(s, IRL_STAT_GEMV, st, launch_fac_jvp_rows(s, L, R, v, zero_v0, w, st));
         TIMED(s, IRL_STAT_VMC, st, launch_vmc_diag_rows(L, ws, s->vmc_rows, w, u, st));
-        const int nb = fac_row_blocks_n(s->vmc_rows, L.hfac);
+        const int nb = fac_row_blocks_n(s, s->vmc_rows, L.hfac);
         TIMED(s, IRL_STAT_GEMV_T, st, launch_fac_vjp_rows(s, L, ws, R, w, u, nullptr, 0, nb, st));
         TIMED(s, IRL_STAT_REDUCE, st, launch_t2_reduce(L, ws, nb, yS, yH, L.ncols, 1.0, nullptr, st));
         return IRL_OK;
@@ -926,73 +927,121 @@ void irl_system_destroy(irl_system *sys) { free_system(sys); }
 
 namespace {
 
-size_t sliced_bytes(int scb, int64_t ns, int64_t nnz)
+size_t sliced_bytes(int scb, int64_t ns, int64_t slots)
 {
-    return (size_t)scb * (ns + 1) * 4 + (size_t)scb * 8 + (size_t)nnz * 10;
+    const int64_t groups = (ns + kWave - 1) / kWave;
+    return (size_t)groups * scb * 6 + (size_t)groups * kWave * scb * 2 + (size_t)scb * 8 + (size_t)slots * 10 +
+           (size_t)scb * ns * 8;
 }
 
-// Stored rows in the LDS-sliced layout (sets of at least kSlicedMinRows rows): count
-// the connections of every row per slice, offsets on the host, fill and order.
+// Stored rows in the LDS-sliced layout (sets of at least kSlicedMinRows rows, or
+// IRL_SYS_STORE_SLICED): count the connections of every row per slice, order each
+// window's rows by count (descending, ties by row) and group them 64 at a time
+// (host), then fill the slots.
 int store_sliced(irl_system *s, size_t max_bytes, size_t *bytes_needed, hipStream_t st)
 {
     const int64_t ns = s->ns;
     const int scs = kSliceLog;
     const int scb = (int)((ns + ((int64_t)1 << scs) - 1) >> scs);
+    const int64_t G = (ns + kWave - 1) / kWave;
     uint32_t *dcount = nullptr;
     CK(s, hipMalloc((void **)&dcount, (size_t)scb * ns * 4));
     std::vector<uint32_t> count((size_t)scb * ns);
     hipError_t e = launch_ham_count_sliced(s, scs, scb, dcount, st);
     if (e == hipSuccess) e = hipMemcpyAsync(count.data(), dcount, (size_t)scb * ns * 4, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
-    (void)hipFree(dcount);
-    if (e != hipSuccess) return set_err(s, IRL_EDEVICE, std::string("row counts: ") + hipGetErrorString(e));
-    // per slice: offsets relative to the slice's first element (32-bit), slice bases
-    std::vector<uint32_t> ptr((size_t)scb * (ns + 1));
-    std::vector<int64_t> base(scb);
-    int64_t nnz = 0;
-    for (int b = 0; b < scb; ++b) {
-        uint32_t *pb = ptr.data() + (size_t)b * (ns + 1);
-        const uint32_t *cb = count.data() + (size_t)b * ns;
-        base[b] = nnz;
-        uint64_t run = 0;
-        pb[0] = 0;
-        for (int64_t r = 0; r < ns; ++r) {
-            run += cb[r];
-            if (run > 0xffffffffull) return set_err(s, IRL_EINVAL, "a slice holds more than 2^32 - 1 elements");
-            pb[r + 1] = (uint32_t)run;
-        }
-        nnz += (int64_t)run;
+    if (e != hipSuccess) {
+        (void)hipFree(dcount);
+        return set_err(s, IRL_EDEVICE, std::string("row counts: ") + hipGetErrorString(e));
     }
-    const size_t bytes = sliced_bytes(scb, ns, nnz);
+    // per slice and window: rows by count (counting sort, descending, ties by row),
+    // groups of 64 lanes, slot offsets; slot[b][row] = group * 64 + lane
+    std::vector<int64_t> base(scb);
+    std::vector<uint32_t> gbase((size_t)scb * G), slot((size_t)scb * ns);
+    std::vector<uint16_t> glen((size_t)scb * G), perm((size_t)scb * G * kWave, 0xffff);
+    int64_t slots = 0, nnz = 0;
+    std::vector<uint32_t> order, bucket;
+    for (int b = 0; b < scb; ++b) {
+        base[b] = slots;
+        const uint32_t *cb = count.data() + (size_t)b * ns;
+        uint64_t run = 0;
+        for (int64_t w0 = 0; w0 < ns; w0 += kSellWindow) {
+            const int nr = (int)std::min<int64_t>(kSellWindow, ns - w0);
+            uint32_t cmax = 0;
+            for (int i = 0; i < nr; ++i) cmax = std::max(cmax, cb[w0 + i]);
+            bucket.assign((size_t)cmax + 2, 0u);
+            for (int i = 0; i < nr; ++i) ++bucket[cmax - cb[w0 + i] + 1];
+            for (uint32_t c = 1; c < cmax + 2; ++c) bucket[c] += bucket[c - 1];
+            order.assign(nr, 0u);
+            for (int i = 0; i < nr; ++i) order[bucket[cmax - cb[w0 + i]]++] = (uint32_t)i;
+            const int64_t g0 = w0 / kWave;
+            for (int k = 0; k * kWave < nr; ++k) {
+                const int64_t g = g0 + k;
+                const uint32_t L = cb[w0 + order[(size_t)k * kWave]];
+                if (L > 0xffffu) return (void)hipFree(dcount), set_err(s, IRL_EINVAL, "a row holds more than 65535 elements in one slice");
+                gbase[(size_t)b * G + g] = (uint32_t)run;
+                glen[(size_t)b * G + g] = (uint16_t)L;
+                for (int l = 0; l < kWave && k * kWave + l < nr; ++l) {
+                    const uint32_t i = order[(size_t)k * kWave + l];
+                    perm[((size_t)b * G + g) * kWave + l] = (uint16_t)i;
+                    slot[(size_t)b * ns + w0 + i] = (uint32_t)(k * kWave + l) + (uint32_t)(g0 * kWave);
+                    nnz += cb[w0 + i];
+                }
+                run += (uint64_t)L * kWave;
+                if (run > 0xffffffffull)
+                    return (void)hipFree(dcount), set_err(s, IRL_EINVAL, "a slice holds more than 2^32 - 1 slots");
+            }
+        }
+        slots += (int64_t)run;
+    }
+    const size_t bytes = sliced_bytes(scb, ns, slots);
     if (bytes_needed) *bytes_needed = bytes;
-    if (bytes > max_bytes)
+    if (bytes > max_bytes) {
+        (void)hipFree(dcount);
         return set_err(s, IRL_ENOMEM, "stored rows need " + std::to_string(bytes) +
                                           " bytes, more than max_bytes = " + std::to_string(max_bytes));
+    }
     const size_t bytes_before = s->dev_bytes;
     auto release = [&]() {
         s->dev_bytes = bytes_before;
-        for (void *p : {(void *)s->d.sptr, (void *)s->d.sbase, (void *)s->d.scol, (void *)s->d.sval})
+        for (void *p : {(void *)s->d.sbase, (void *)s->d.sgbase, (void *)s->d.sglen, (void *)s->d.sperm,
+                        (void *)s->d.scol, (void *)s->d.sval, (void *)s->d.spart})
             if (p) (void)hipFree(p);
-        s->d.sptr = nullptr;
         s->d.sbase = nullptr;
+        s->d.sgbase = nullptr;
+        s->d.sglen = nullptr;
+        s->d.sperm = nullptr;
         s->d.scol = nullptr;
         s->d.sval = nullptr;
+        s->d.spart = nullptr;
+        s->d.sgroups = 0;
     };
     int rc;
-    if ((rc = dev_alloc(s, &s->d.sptr, (size_t)scb * (ns + 1))) != IRL_OK ||
-        (rc = dev_alloc(s, &s->d.sbase, (size_t)scb)) != IRL_OK ||
-        (rc = dev_alloc(s, &s->d.scol, (size_t)std::max<int64_t>(nnz, 1))) != IRL_OK ||
-        (rc = dev_alloc(s, &s->d.sval, (size_t)std::max<int64_t>(nnz, 1))) != IRL_OK) {
+    if ((rc = dev_alloc(s, &s->d.sbase, (size_t)scb)) != IRL_OK ||
+        (rc = dev_alloc(s, &s->d.sgbase, (size_t)scb * G)) != IRL_OK ||
+        (rc = dev_alloc(s, &s->d.sglen, (size_t)scb * G)) != IRL_OK ||
+        (rc = dev_alloc(s, &s->d.sperm, (size_t)scb * G * kWave)) != IRL_OK ||
+        (rc = dev_alloc(s, &s->d.scol, (size_t)std::max<int64_t>(slots, 1))) != IRL_OK ||
+        (rc = dev_alloc(s, &s->d.sval, (size_t)std::max<int64_t>(slots, 1))) != IRL_OK ||
+        (rc = dev_alloc(s, &s->d.spart, (size_t)scb * ns)) != IRL_OK) {
+        (void)hipFree(dcount);
         release();
         return rc;
     }
-    e = hipMemcpyAsync(s->d.sptr, ptr.data(), ptr.size() * 4, hipMemcpyHostToDevice, st);
+    s->d.sgroups = (int32_t)G;
+    // the slot map reuses the count buffer (scb x ns uint32)
+    uint32_t *dslot = dcount;
+    e = hipMemcpyAsync(dslot, slot.data(), slot.size() * 4, hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipMemcpyAsync(s->d.sbase, base.data(), base.size() * 8, hipMemcpyHostToDevice, st);
-    // slots the fill does not reach (none, if the two enumerations agree) gather in bounds
-    if (e == hipSuccess) e = hipMemsetAsync(s->d.scol, 0, (size_t)std::max<int64_t>(nnz, 1) * 2, st);
-    if (e == hipSuccess) e = hipMemsetAsync(s->d.sval, 0, (size_t)std::max<int64_t>(nnz, 1) * 8, st);
-    if (e == hipSuccess) e = launch_ham_fill_sliced(s, scs, scb, s->d.sbase, s->d.sptr, s->d.scol, s->d.sval, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(s->d.sgbase, gbase.data(), gbase.size() * 4, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(s->d.sglen, glen.data(), glen.size() * 2, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(s->d.sperm, perm.data(), perm.size() * 2, hipMemcpyHostToDevice, st);
+    // padding slots: target 0 (inside every slice), value 0
+    if (e == hipSuccess) e = hipMemsetAsync(s->d.scol, 0, (size_t)std::max<int64_t>(slots, 1) * 2, st);
+    if (e == hipSuccess) e = hipMemsetAsync(s->d.sval, 0, (size_t)std::max<int64_t>(slots, 1) * 8, st);
+    if (e == hipSuccess) e = launch_ham_fill_sliced(s, scs, scb, dslot, s->d.scol, s->d.sval, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipFree(dcount);
     if (e != hipSuccess) {
         release();
         return set_err(s, IRL_EDEVICE, std::string("stored rows: ") + hipGetErrorString(e));
@@ -1000,6 +1049,7 @@ int store_sliced(irl_system *s, size_t max_bytes, size_t *bytes_needed, hipStrea
     s->d.scb = scb;
     s->d.scs = scs;
     s->d.hnnz = nnz;
+    s->d.sslots = slots;
     s->ham_kernel = 4;
     return IRL_OK;
 }
@@ -1014,7 +1064,7 @@ int irl_system_store_hamiltonian(irl_system *s, size_t max_bytes, size_t *bytes_
     const int64_t ns = s->ns;
     if (s->ham_kernel == 4) {
         if (bytes_needed)
-            *bytes_needed = s->d.scb ? sliced_bytes(s->d.scb, ns, s->d.hnnz)
+            *bytes_needed = s->d.scb ? sliced_bytes(s->d.scb, ns, s->d.sslots)
                                      : (size_t)s->d.hcb * (ns + 1) * 8 + (size_t)s->d.hnnz * 12;
         return IRL_OK;
     }
@@ -1110,6 +1160,7 @@ int irl_system_info_get(const irl_system *s, irl_system_info *o)
     o->device_bytes = s->dev_bytes;
     o->ham_kernel = s->ham_kernel;
     o->stored_col_blocks = s->ham_kernel == 4 ? (s->d.scb ? s->d.scb : s->d.hcb) : 0;
+    o->stored_elements = s->ham_kernel == 4 ? s->d.hnnz : 0;
     return IRL_OK;
 }
 
@@ -1225,7 +1276,7 @@ int irl_vmc_sample(irl_system *s, void *ws, size_t ws_bytes, const double *u, in
         TIMED(s, IRL_STAT_VMC, st, launch_vmc_rhs_rows(L, ws, nu, y, st));
         const FacRows R{ws_ptr<uint64_t>(ws, L.off_ckeys), nu, ws_ptr<double>(ws, L.off_cpsi),
                         ws_ptr<double>(ws, L.off_cfac)};
-        nblk = fac_row_blocks_n(nu, L.hfac);
+        nblk = fac_row_blocks_n(s, nu, L.hfac);
         TIMED(s, IRL_STAT_ENERGY, st, launch_fac_vjp_rows(s, L, ws, R, y, nullptr, nullptr, 1, nblk, st));
     } else if (L.flags & IRL_WS_FACTORED) {
         nblk = fac_vjp_blocks(s, L);

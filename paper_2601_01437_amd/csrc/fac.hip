@@ -972,6 +972,239 @@ void vjp_nt(const irl_system *s, const WsLayout &L, const FacRows &R, int V, int
                                                            coefp, part, L.ldv, nblk, half);
 }
 
+// ---------------------------------------------------------------------------
+// Backward product of selected sets on the vector units.
+//
+// The matrix-core form (k_fac_vjp) contracts (c d)^T with X through dense 16 x 16
+// x 4 tiles: N_s V H multiply-adds per right-hand side on an X that is 0/1 with
+// N_alpha + N_beta ones per row (at V = 40, H = 256 that is twice the time of
+// streaming d).  Here a workgroup owns a block of rows and every hidden unit
+// (thread t = hidden unit t, H <= 256) and walks its rows in order: a row's
+// occupation bits are the same for every thread, so its alpha part is one FMA per
+// orbital with the bit as a scalar 0.0 / 1.0 operand, and its beta part is folded
+// once per run of rows that share a beta string (keys ascend beta-major, so such
+// runs are contiguous; any order is still correct).  d streams once per pass with
+// coalesced row loads, PD rows in flight per thread; row data (keys, psi,
+// right-hand sides) are staged in LDS per batch of kBitsRB rows.  (The same scheme
+// for the forward pass and D~ v measured slower than the matrix-core forms, whose
+// contraction there is a single 16-wide product per tile.)
+
+#ifndef IRL_BITS_PD
+#define IRL_BITS_PD 8
+#endif
+#ifndef IRL_BITS_BLOCKS
+#define IRL_BITS_BLOCKS 512
+#endif
+constexpr int kBitsRB = 256;   // rows staged per batch
+constexpr int kBitsPD = IRL_BITS_PD;   // d rows in flight per thread (8 or 16)
+constexpr int kBitsMaxN = 24;  // alpha (and beta) orbitals of the register accumulators
+constexpr int kBitsMinH = 48;  // narrower networks keep the matrix-core forms
+constexpr int kBitsMaxH = 256;
+constexpr int kBitsBlocks = IRL_BITS_BLOCKS;
+
+struct BitsArgs {
+    const uint64_t *keys;
+    const double *psi, *dfac;
+    int64_t ns;
+    int n, V, H;
+};
+
+__device__ __forceinline__ uint32_t uniform_u32(uint32_t x) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)x); }
+
+// bit k of a wavefront-uniform mask as the double 0.0 or 1.0 (scalar arithmetic:
+// 1.0 is 0x3ff0 << 48), so a conditional add becomes one FMA with a scalar operand;
+// fma(bit, y, x) equals x or x + y exactly
+__device__ __forceinline__ double bit_d(uint32_t bits, int k)
+{
+    const uint32_t hi = ((bits >> k) & 1u) * 0x3ff00000u;
+    return __hiloint2double((int)hi, 0);
+}
+
+// rows [r0, r1) of row block rb of nblk
+__device__ __forceinline__ void bits_block(int64_t ns, int nblk, int rb, int64_t &r0, int64_t &r1)
+{
+    const int64_t per = (ns + nblk - 1) / nblk;
+    r0 = (int64_t)rb * per;
+    r1 = r0 + per < ns ? r0 + per : ns;
+    if (r0 > ns) r0 = ns;
+}
+
+// Partial rows of D~^T c for NR right-hand sides c_q = y_q - coef psi over row block
+// blockIdx.x (layout of k_fac_vjp: NR = 2 writes rows (rb, 0) and (rb, 1), NR = 1 row
+// (rb, half)).  Thread h accumulates W[h][v] for the alpha orbitals v < n per row
+// and, for the beta orbitals, the run sum S of c d_h that it folds into W[h][n + v]
+// (and into the b entry) when the beta string changes.  Wave 0 also sums c over
+// each orbital (the a entries, lane v) and c psi (the psi entry).
+template <int NR, int NA>
+__global__ __launch_bounds__(256) void k_fac_vjp_bits(BitsArgs A, const double *__restrict__ y0,
+                                                      const double *__restrict__ y1, const double *__restrict__ coefp,
+                                                      double *__restrict__ part, int64_t ldv, int nblk, int half)
+{
+    constexpr int RB = kBitsRB, PD = kBitsPD;
+    __shared__ uint64_t skey[RB];
+    __shared__ double sps[RB], sc[NR][RB];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int H = A.H, n = A.n, V = A.V;
+    const bool hv = t < H;
+    int64_t r0, r1;
+    bits_block(A.ns, nblk, blockIdx.x, r0, r1);
+    const double coef = coefp ? *coefp : 0.0;
+    const double *ys[2] = {y0, y1};
+    double wa[NR][NA], wb[NR][NA], sb[NR], bp[NR], ax[NR], a0[NR];
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+        sb[q] = bp[q] = ax[q] = a0[q] = 0.0;
+#pragma unroll
+        for (int k = 0; k < NA; ++k) wa[q][k] = wb[q][k] = 0.0;
+    }
+    uint32_t cur = 0u;
+    bool run = false;
+    double dr[PD];
+#pragma unroll
+    for (int p = 0; p < PD; ++p) dr[p] = (hv && r0 + p < r1) ? A.dfac[(r0 + p) * H + t] : 0.0;
+    for (int64_t bs = r0; bs < r1; bs += RB) {
+        const int nbt = (int)(r1 - bs < RB ? r1 - bs : RB);
+        __syncthreads();
+        for (int i = t; i < nbt; i += blockDim.x) {
+            const int64_t r = bs + i;
+            const double ps = A.psi[r];
+            skey[i] = A.keys[r];
+            sps[i] = ps;
+#pragma unroll
+            for (int q = 0; q < NR; ++q) sc[q][i] = ys[q][r] - coef * ps;
+        }
+        __syncthreads();
+        for (int j0 = 0; j0 < nbt; j0 += PD) {
+#pragma unroll
+            for (int p = 0; p < PD; ++p) {
+                const int j = j0 + p;
+                if (j < nbt) {
+                    const uint64_t key = skey[j];
+                    const uint32_t al = uniform_u32((uint32_t)key), be = uniform_u32((uint32_t)(key >> 32));
+                    if (!run || be != cur) {
+                        if (run) {
+#pragma unroll
+                            for (int k = 0; k < NA; ++k) {
+                                const double bk = bit_d(cur, k);
+#pragma unroll
+                                for (int q = 0; q < NR; ++q) wb[q][k] = fma(bk, sb[q], wb[q][k]);
+                            }
+#pragma unroll
+                            for (int q = 0; q < NR; ++q) {
+                                bp[q] += sb[q];
+                                sb[q] = 0.0;
+                            }
+                        }
+                        cur = be;
+                        run = true;
+                    }
+                    const double d = dr[p];
+                    double c[NR], tq[NR];
+#pragma unroll
+                    for (int q = 0; q < NR; ++q) {
+                        c[q] = sc[q][j];
+                        tq[q] = c[q] * d;
+                        sb[q] += tq[q];
+                    }
+#pragma unroll
+                    for (int k = 0; k < NA; ++k) {
+                        const double bk = bit_d(al, k);
+#pragma unroll
+                        for (int q = 0; q < NR; ++q) wa[q][k] = fma(bk, tq[q], wa[q][k]);
+                    }
+                    if (wv == 0) {
+                        const uint32_t bits = lane < n ? al : be;
+                        const int sh = lane < n ? lane : lane - n;
+                        const bool on = lane < V && ((bits >> (sh & 31)) & 1u);
+                        const double ps = sps[j];
+#pragma unroll
+                        for (int q = 0; q < NR; ++q) {
+                            ax[q] += on ? c[q] : 0.0;
+                            a0[q] = fma(c[q], ps, a0[q]);
+                        }
+                    }
+                }
+                const int64_t rn = bs + j0 + p + PD;
+                dr[p] = (hv && rn < r1) ? A.dfac[rn * H + t] : 0.0;
+            }
+        }
+    }
+    if (run) {
+#pragma unroll
+        for (int k = 0; k < NA; ++k) {
+            const double bk = bit_d(cur, k);
+#pragma unroll
+            for (int q = 0; q < NR; ++q) wb[q][k] = fma(bk, sb[q], wb[q][k]);
+        }
+#pragma unroll
+        for (int q = 0; q < NR; ++q) bp[q] += sb[q];
+    }
+    const int64_t P1 = (int64_t)V * H + H + V + 1;
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+        double *out = part + ((int64_t)blockIdx.x * 2 + (NR == 2 ? q : half)) * ldv;
+        if (hv) {
+            double *wrow = out + 1 + V + H + (int64_t)t * V;
+#pragma unroll
+            for (int k = 0; k < NA; ++k)
+                if (k < n) {
+                    wrow[k] = wa[q][k];
+                    wrow[n + k] = wb[q][k];
+                }
+            out[1 + V + t] = bp[q];
+        }
+        if (wv == 0) {
+            if (lane < V) out[1 + lane] = ax[q];
+            if (lane == 0) out[0] = a0[q];
+            for (int64_t col = P1 + lane; col < ldv; col += 64) out[col] = 0.0;
+        }
+    }
+}
+
+// the vector-unit forms apply to these rows: not the full-space kernels, n <= 24,
+// 48 <= H <= 256
+bool fac_bits_ok(const irl_system *s, int H)
+{
+#ifdef IRL_FAC_NO_BITS
+    return false;
+#endif
+    return s->n <= kBitsMaxN && H >= kBitsMinH && H <= kBitsMaxH;
+}
+
+int fac_bits_blocks(int64_t ns)
+{
+    int64_t per = (ns + kBitsBlocks - 1) / kBitsBlocks;
+    if (per < 64) per = 64;
+    const int64_t nb = (ns + per - 1) / per;
+    return (int)(nb < 1 ? 1 : nb);
+}
+
+template <int NA>
+static void launch_bits_na(const BitsArgs &B, int nblk, const double *y0, const double *y1, const double *coefp,
+                           double *part, int64_t ldv, int half, hipStream_t st)
+{
+    const unsigned threads = (unsigned)(64 * ((B.H + 63) / 64));
+    if (y1)
+        k_fac_vjp_bits<2, NA><<<nblk, threads, 0, st>>>(B, y0, y1, coefp, part, ldv, nblk, 0);
+    else
+        k_fac_vjp_bits<1, NA><<<nblk, threads, 0, st>>>(B, y0, nullptr, coefp, part, ldv, nblk, half);
+}
+
+// D~^T [y0, y1] (y1 == nullptr: D~^T y0 into half `half`) on the vector units
+static hipError_t launch_vjp_bits(const irl_system *s, const BitsArgs &B, int nblk, const double *y0,
+                                  const double *y1, const double *coefp, double *part, int64_t ldv, int half,
+                                  hipStream_t st)
+{
+    switch ((s->n + 3) / 4) {
+    case 0: case 1: case 2: launch_bits_na<8>(B, nblk, y0, y1, coefp, part, ldv, half, st); break;
+    case 3: launch_bits_na<12>(B, nblk, y0, y1, coefp, part, ldv, half, st); break;
+    case 4: launch_bits_na<16>(B, nblk, y0, y1, coefp, part, ldv, half, st); break;
+    case 5: launch_bits_na<20>(B, nblk, y0, y1, coefp, part, ldv, half, st); break;
+    default: launch_bits_na<24>(B, nblk, y0, y1, coefp, part, ldv, half, st); break;
+    }
+    return hipGetLastError();
+}
+
 bool fac_shape_ok(const irl_system *s, const WsLayout &L)
 {
     const int V = 2 * s->n;
@@ -1045,7 +1278,7 @@ int fac_full_ranges(int64_t nA, int64_t nB, int n, int H)
 int fac_vjp_blocks(const irl_system *s, const WsLayout &L)
 {
     if (L.kf_S > 0 && s->full) return (int)(((s->nB + kFullTB - 1) / kFullTB) * L.kf_S);
-    return fac_row_blocks(L);
+    return fac_row_blocks(s, L);
 }
 
 FacRows fac_rows(const irl_system *s, const WsLayout &L, void *ws)
@@ -1125,8 +1358,9 @@ hipError_t launch_fac_jvp(const irl_system *s, const WsLayout &L, void *ws, cons
 // blocks took 0.229 against 0.221 ms per c2 pass, with twice the partial rows)
 constexpr int kFacRowBlocks = 256;
 
-int fac_row_blocks_n(int64_t ns, int hfac)
+int fac_row_blocks_n(const irl_system *s, int64_t ns, int hfac)
 {
+    if (fac_bits_ok(s, hfac)) return fac_bits_blocks(ns);
     const int htiles = (hfac + 63) / 64;
     int nblk = kFacRowBlocks / (htiles > 0 ? htiles : 1);
     if (nblk < 1) nblk = 1;
@@ -1134,9 +1368,9 @@ int fac_row_blocks_n(int64_t ns, int hfac)
     return nblk < 1 ? 1 : nblk;
 }
 
-int fac_row_blocks(const WsLayout &L)
+int fac_row_blocks(const irl_system *s, const WsLayout &L)
 {
-    return fac_row_blocks_n(L.ns, L.hfac);
+    return fac_row_blocks_n(s, L.ns, L.hfac);
 }
 
 hipError_t launch_fac_vjp_rows(const irl_system *s, const WsLayout &L, void *ws, const FacRows &R,
@@ -1154,6 +1388,10 @@ hipError_t launch_fac_vjp_rows(const irl_system *s, const WsLayout &L, void *ws,
     }
     const int V = 2 * s->n, H = L.hfac;
     double *part = ws_ptr<double>(ws, L.off_part);
+    if (fac_bits_ok(s, H)) {
+        const BitsArgs B{R.keys, R.psi, R.dfac, R.ns, s->n, V, H};
+        return launch_vjp_bits(s, B, nblk, y0, y1, coefp, part, L.ldv, half, st);
+    }
     const int nt = (V + 15) / 16;
     if (y1) {
         switch (nt) {

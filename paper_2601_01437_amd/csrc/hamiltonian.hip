@@ -511,10 +511,11 @@ __global__ __launch_bounds__(256) void k_ham_fill(HamArgs A, const int64_t *__re
 // ---- stored rows, LDS-sliced layout ---------------------------------------------
 // For sets larger than an L2-resident slice of w, the targets are split into
 // slices of 2^scs rows whose w (128 KiB) one workgroup stages in LDS, so the
-// random gathers of w become LDS reads and HBM streams only the elements.  Per
-// slice b: row offsets sptr[b][row] relative to the slice's first element
-// sbase[b], then each row's elements ordered by target, targets as 16-bit
-// indices inside the slice and FP64 values (10 bytes per element).
+// random gathers of w become LDS reads and HBM streams only the elements.  Inside
+// a slice, rows are ordered by their element count within windows of kSellWindow
+// rows and grouped 64 per wavefront (one row per lane); a group of longest row L
+// holds L x 64 slots, slot (j, lane) the j-th element of the lane's row (zero
+// padding past its end), as a 16-bit target inside the slice and an FP64 value.
 
 // first pass: connections of each row inside each slice (count[b ns + row])
 template <int LK>
@@ -538,63 +539,54 @@ __global__ __launch_bounds__(256) void k_ham_count_sliced(HamArgs A, int scs, in
     }
 }
 
-// second pass: each connection takes the next free slot of its row's slice segment
-// (LDS cursors; slot order is arbitrary), written only inside the segment
+// second pass, one wavefront per workgroup: each lane counts its own connections
+// per slice (LDS table [lane][slice]), an exclusive scan over the lanes gives each
+// lane's first position j in the row's run of each slice, and a second enumeration
+// writes element j of (slice b, row) to slot base + j * 64 + lane of the row's group
+// and lane (slot[b][row] = group * 64 + lane): the layout, and so the apply's
+// summation order, are fixed by the set.
 template <int LK>
-__global__ __launch_bounds__(256) void k_ham_fill_sliced(HamArgs A, int scs, int scb, const int64_t *__restrict__ sbase,
-                                                         const uint32_t *__restrict__ sptr,
-                                                         uint16_t *__restrict__ scol, double *__restrict__ sval)
+__global__ __launch_bounds__(64) void k_ham_fill_sliced(HamArgs A, int scs, int scb, const int64_t *__restrict__ sbase,
+                                                        const uint32_t *__restrict__ sgbase, int sgroups,
+                                                        const uint16_t *__restrict__ sglen,
+                                                        const uint32_t *__restrict__ slot,
+                                                        uint16_t *__restrict__ scol, double *__restrict__ sval)
 {
-    __shared__ WaveLists lists[4];
-    __shared__ uint32_t cur[4][kMaxSlices];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int64_t nwaves = (int64_t)gridDim.x * 4;
+    __shared__ WaveLists lists;
+    __shared__ uint32_t cnt[kWave][kMaxSlices];
+    const int lane = threadIdx.x;
     const uint32_t mask = (1u << scs) - 1u;
-    for (int64_t row = (int64_t)blockIdx.x * 4 + wv; row < A.ns; row += nwaves) {
-        for (int b = lane; b < scb; b += kWave) cur[wv][b] = 0u;
+    for (int64_t row = blockIdx.x; row < A.ns; row += gridDim.x) {
+        for (int b = 0; b < scb; ++b) cnt[lane][b] = 0u;
         const uint64_t key = A.keys[row];
         const uint32_t al = (uint32_t)key, be = (uint32_t)(key >> 32);
-        prepare_row<LK>(A, lists[wv], al, be, lane);
-        visit_row<LK>(A, lists[wv], al, be, lane, kWave, [&](int64_t r, int, int, double v) {
+        prepare_row<LK>(A, lists, al, be, lane);
+        visit_row<LK>(A, lists, al, be, lane, kWave, [&](int64_t r, int, int, double) {
+            ++cnt[lane][(int)(r >> scs)];
+        });
+        end_row();
+        // lane b (and b + 64, ...) turns column b of the table into first positions
+        for (int b = lane; b < scb; b += kWave) {
+            uint32_t run = 0u;
+            for (int l = 0; l < kWave; ++l) {
+                const uint32_t c = cnt[l][b];
+                cnt[l][b] = run;
+                run += c;
+            }
+        }
+        end_row();
+        visit_row<LK>(A, lists, al, be, lane, kWave, [&](int64_t r, int, int, double v) {
             const int b = (int)(r >> scs);
-            const uint32_t *pb = sptr + (int64_t)b * (A.ns + 1);
-            const uint32_t k = atomicAdd(&cur[wv][b], 1u);
-            const uint32_t q = pb[row] + k;
-            if (q < pb[row + 1]) {
-                scol[sbase[b] + q] = (uint16_t)((uint32_t)r & mask);
-                sval[sbase[b] + q] = v;
+            const uint32_t j = cnt[lane][b]++;
+            const uint32_t sl = slot[(int64_t)b * A.ns + row];
+            const int64_t g = (int64_t)b * sgroups + (sl >> 6);
+            if (j < sglen[g]) {
+                const int64_t p = sbase[b] + sgbase[g] + (int64_t)j * kWave + (sl & 63u);
+                scol[p] = (uint16_t)((uint32_t)r & mask);
+                sval[p] = v;
             }
         });
         end_row();
-    }
-}
-
-// third pass: order every (slice, row) segment by target (insertion sort, one
-// thread per segment), so the stored layout and the apply's summation order do
-// not depend on the fill's slot order
-__global__ __launch_bounds__(256) void k_ham_sort_sliced(int64_t ns, int scb, const int64_t *__restrict__ sbase,
-                                                         const uint32_t *__restrict__ sptr,
-                                                         uint16_t *__restrict__ scol, double *__restrict__ sval)
-{
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= ns * scb) return;
-    const int b = (int)(t / ns);
-    const int64_t row = t - (int64_t)b * ns;
-    const uint32_t *pb = sptr + (int64_t)b * (ns + 1);
-    uint16_t *c = scol + sbase[b];
-    double *v = sval + sbase[b];
-    const uint32_t p0 = pb[row], p1 = pb[row + 1];
-    for (uint32_t i = p0 + 1; i < p1; ++i) {
-        const uint16_t ci = c[i];
-        const double vi = v[i];
-        uint32_t j = i;
-        while (j > p0 && c[j - 1] > ci) {
-            c[j] = c[j - 1];
-            v[j] = v[j - 1];
-            --j;
-        }
-        c[j] = ci;
-        v[j] = vi;
     }
 }
 
@@ -612,113 +604,125 @@ hipError_t launch_ham_count_sliced(const irl_system *s, int scs, int scb, uint32
     return hipGetLastError();
 }
 
-hipError_t launch_ham_fill_sliced(const irl_system *s, int scs, int scb, const int64_t *sbase,
-                                  const uint32_t *sptr, uint16_t *scol, double *sval, hipStream_t st)
+hipError_t launch_ham_fill_sliced(const irl_system *s, int scs, int scb, const uint32_t *slot, uint16_t *scol,
+                                  double *sval, hipStream_t st)
 {
     HamArgs A = ham_view(s);
-    int64_t blocks = (s->ns + 3) / 4;
-    if (blocks > 65536) blocks = 65536;
+    int64_t blocks = s->ns;
+    if (blocks > 262144) blocks = 262144;
+    const int G = s->d.sgroups;
     if (s->lookup == kLkBlocks)
-        k_ham_fill_sliced<kLkBlocks><<<(unsigned)blocks, 256, 0, st>>>(A, scs, scb, sbase, sptr, scol, sval);
+        k_ham_fill_sliced<kLkBlocks><<<(unsigned)blocks, 64, 0, st>>>(A, scs, scb, s->d.sbase, s->d.sgbase, G,
+                                                                     s->d.sglen, slot, scol, sval);
     else if (s->lookup == kLkHash)
-        k_ham_fill_sliced<kLkHash><<<(unsigned)blocks, 256, 0, st>>>(A, scs, scb, sbase, sptr, scol, sval);
+        k_ham_fill_sliced<kLkHash><<<(unsigned)blocks, 64, 0, st>>>(A, scs, scb, s->d.sbase, s->d.sgbase, G,
+                                                                   s->d.sglen, slot, scol, sval);
     else
-        k_ham_fill_sliced<kLkRanks><<<(unsigned)blocks, 256, 0, st>>>(A, scs, scb, sbase, sptr, scol, sval);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    const int64_t segs = s->ns * scb;
-    k_ham_sort_sliced<<<(unsigned)((segs + 255) / 256), 256, 0, st>>>(s->ns, scb, sbase, sptr, scol, sval);
+        k_ham_fill_sliced<kLkRanks><<<(unsigned)blocks, 64, 0, st>>>(A, scs, scb, s->d.sbase, s->d.sgbase, G,
+                                                                    s->d.sglen, slot, scol, sval);
     return hipGetLastError();
 }
 
-// Apply: a workgroup owns kSlcRows rows and walks the slices in order.  Per slice
-// it stages w (2^scs rows) and its rows' offsets in LDS; groups of G lanes take one
-// row each (rows grp, grp + NG, ...), every lane loading kSlcUnroll elements of the
-// segment at once (stride G), so most segments need one pass; the G partial sums
-// are combined by a fixed butterfly and added to the row's LDS accumulator in slice
-// order.  Finally u = H_rr w + accumulator.
-constexpr int kSlcThreads = 512;
-constexpr int kSlcRows = 2048;
-constexpr int kSlcUnroll = 4;
+// Apply, two kernels.  (1) k_ham_sell: a workgroup owns one slice b and a range of
+// groups; it stages the slice's w (128 KiB) in LDS once, then each wavefront takes
+// groups in turn: lane l sums its row's elements over the group's slots (j, l),
+// kSellUnroll slots in flight (every load of the wavefront is 512 contiguous bytes
+// of values and 128 of targets; the targets index the LDS copy of w), and writes
+// the sum to part[b][row].  (2) k_ham_sliced_sum: u[row] = H_rr w[row] + sum_b
+// part[b][row] in slice order.
+#ifndef IRL_SELL_THREADS
+#define IRL_SELL_THREADS 1024
+#endif
+#ifndef IRL_SELL_UNROLL
+#define IRL_SELL_UNROLL 16
+#endif
+constexpr int kSellThreads = IRL_SELL_THREADS;
+constexpr int kSellUnroll = IRL_SELL_UNROLL;
+#ifndef IRL_SELL_WGS
+#define IRL_SELL_WGS 4096
+#endif
+constexpr int kSellWaveGoal = IRL_SELL_WGS;   // workgroups per launch (slices x group ranges), about
 
-template <int G>
-__global__ __launch_bounds__(kSlcThreads) void k_ham_sliced(HamArgs A, const double *__restrict__ w,
-                                                            double *__restrict__ u, int64_t r0, int64_t r1)
+__global__ __launch_bounds__(kSellThreads) void k_ham_sell(HamArgs A, const double *__restrict__ w, int64_t r0,
+                                                           int64_t r1, int64_t ga, int64_t gz, int64_t grange)
 {
-    __shared__ double wl[1 << kSliceLog];
-    __shared__ double acc[kSlcRows];
-    __shared__ uint32_t pl[kSlcRows + 1];
-    constexpr int NG = kSlcThreads / G;
-    const int t = threadIdx.x, grp = t / G, l = t % G;
-    const int64_t rb = r0 + (int64_t)blockIdx.x * kSlcRows;
-    const int nr = (int)min((int64_t)kSlcRows, r1 - rb);
-    for (int i = t; i < nr; i += kSlcThreads) acc[i] = 0.0;
-    for (int b = 0; b < A.scb; ++b) {
-        const int64_t c0 = (int64_t)b << A.scs;
-        const int nc = (int)min((int64_t)1 << A.scs, A.ns - c0);
-        __syncthreads();   // the previous slice is consumed
-        for (int i = 2 * t; i < nc; i += 2 * kSlcThreads) {
-            if (i + 1 < nc) {
-                const double2 x = *reinterpret_cast<const double2 *>(w + c0 + i);
-                wl[i] = x.x;
-                wl[i + 1] = x.y;
-            } else {
-                wl[i] = w[c0 + i];
-            }
+    constexpr int SL = 1 << kSliceLog, PER = SL / (2 * kSellThreads), K = kSellUnroll;
+    __shared__ double wl[SL];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int b = blockIdx.x;
+    const int64_t c0 = (int64_t)b << A.scs;
+    const int nc = (int)min((int64_t)SL, A.ns - c0);
+    // stage the slice: every thread's loads are issued before any is stored
+    if (nc == SL) {
+        double2 x[PER];
+#pragma unroll
+        for (int j = 0; j < PER; ++j) x[j] = *reinterpret_cast<const double2 *>(w + c0 + 2 * (t + j * kSellThreads));
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            wl[2 * (t + j * kSellThreads)] = x[j].x;
+            wl[2 * (t + j * kSellThreads) + 1] = x[j].y;
         }
-        const uint32_t *pb = A.sptr + (int64_t)b * (A.ns + 1) + rb;
-        for (int i = t; i <= nr; i += kSlcThreads) pl[i] = pb[i];
-        __syncthreads();
-        const uint16_t *col = A.scol + A.sbase[b];
-        const double *val = A.sval + A.sbase[b];
-        for (int i = grp; i < nr; i += NG) {
-            const uint32_t p0 = pl[i], p1 = pl[i + 1];
-            double sum = 0.0;
-            for (uint32_t p = p0 + l; p < p1; p += kSlcUnroll * G) {
-                double v[kSlcUnroll];
-                uint32_t c[kSlcUnroll];
-#pragma unroll
-                for (int q = 0; q < kSlcUnroll; ++q) {
-                    const uint32_t pq = p + q * G;
-                    v[q] = pq < p1 ? __builtin_nontemporal_load(val + pq) : 0.0;
-                    c[q] = pq < p1 ? (uint32_t)__builtin_nontemporal_load(col + pq) : 0u;
-                }
-#pragma unroll
-                for (int q = 0; q < kSlcUnroll; ++q) sum += v[q] * wl[c[q]];
-            }
-#pragma unroll
-            for (int off = G / 2; off > 0; off >>= 1) sum += __shfl_xor(sum, off, G);
-            if (l == 0) acc[i] += sum;
-        }
+    } else {
+        for (int i = t; i < nc; i += kSellThreads) wl[i] = w[c0 + i];
     }
     __syncthreads();
-    for (int i = t; i < nr; i += kSlcThreads) {
-        const int64_t row = rb + i;
-        u[row] = fma(A.diag[row], w[row], acc[i]);
+    const int64_t g0 = ga + (int64_t)blockIdx.y * grange;
+    const int64_t g1 = min(gz, g0 + grange);
+    const int64_t gb = (int64_t)b * A.sgroups;
+    const uint16_t *col = A.scol + A.sbase[b];
+    const double *val = A.sval + A.sbase[b];
+    double *part = A.spart + (int64_t)b * A.ns;
+    for (int64_t g = g0 + wv; g < g1; g += kSellThreads / kWave) {
+        const int L = A.sglen[gb + g];
+        const int64_t base = (int64_t)A.sgbase[gb + g] + lane;
+        double acc = 0.0;
+        for (int j0 = 0; j0 < L; j0 += K) {
+            double v[K];
+            uint32_t c[K];
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const bool in = j0 + k < L;   // the same for the whole wavefront
+                const int64_t p = base + (int64_t)(in ? j0 + k : 0) * kWave;
+                v[k] = val[p];
+                c[k] = col[p];
+                v[k] = in ? v[k] : 0.0;
+            }
+#pragma unroll
+            for (int k = 0; k < K; ++k) acc += v[k] * wl[c[k]];
+        }
+        const uint32_t lr = A.sperm[(gb + g) * kWave + lane];
+        const int64_t row = (g / (kSellWindow / kWave)) * kSellWindow + lr;
+        if (lr != 0xffffu && row >= r0 && row < r1) part[row] = acc;
     }
 }
 
-// lanes per row: the smallest group whose one pass (kSlcUnroll G elements) covers
-// 5/4 of the mean segment length of a (slice, row) pair
-static int sliced_group(const irl_system *s)
+__global__ __launch_bounds__(256) void k_ham_sliced_sum(HamArgs A, const double *__restrict__ w,
+                                                        double *__restrict__ u, int64_t r0, int64_t r1)
 {
-    const double mean = (double)s->d.hnnz / ((double)s->ns * (double)(s->d.scb ? s->d.scb : 1));
-    if (kSlcUnroll * 4 >= 1.25 * mean) return 4;
-    if (kSlcUnroll * 8 >= 1.25 * mean) return 8;
-    if (kSlcUnroll * 16 >= 1.25 * mean) return 16;
-    return 32;
+    const int64_t row = r0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (row >= r1) return;
+    double acc = 0.0;
+    for (int b = 0; b < A.scb; ++b) acc += A.spart[(int64_t)b * A.ns + row];
+    u[row] = fma(A.diag[row], w[row], acc);
 }
 
 static hipError_t launch_ham_sliced(const irl_system *s, const HamArgs &A, const double *w, double *u, int64_t r0,
                                     int64_t r1, hipStream_t st)
 {
-    const unsigned blocks = (unsigned)((r1 - r0 + kSlcRows - 1) / kSlcRows);
-    switch (sliced_group(s)) {
-    case 4: k_ham_sliced<4><<<blocks, kSlcThreads, 0, st>>>(A, w, u, r0, r1); break;
-    case 8: k_ham_sliced<8><<<blocks, kSlcThreads, 0, st>>>(A, w, u, r0, r1); break;
-    case 16: k_ham_sliced<16><<<blocks, kSlcThreads, 0, st>>>(A, w, u, r0, r1); break;
-    default: k_ham_sliced<32><<<blocks, kSlcThreads, 0, st>>>(A, w, u, r0, r1); break;
-    }
+    // the groups of the windows that hold rows [r0, r1)
+    constexpr int64_t GPW = kSellWindow / kWave;
+    const int64_t ga = (r0 / kSellWindow) * GPW;
+    int64_t gz = ((r1 + kSellWindow - 1) / kSellWindow) * GPW;
+    if (gz > A.sgroups) gz = A.sgroups;
+    int64_t nrange = (kSellWaveGoal + A.scb - 1) / A.scb;
+    int64_t grange = (gz - ga + nrange - 1) / nrange;
+    if (grange < 16) grange = 16;
+    nrange = (gz - ga + grange - 1) / grange;
+    const dim3 grid((unsigned)A.scb, (unsigned)nrange);
+    k_ham_sell<<<grid, kSellThreads, 0, st>>>(A, w, r0, r1, ga, gz, grange);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_ham_sliced_sum<<<(unsigned)((r1 - r0 + 255) / 256), 256, 0, st>>>(A, w, u, r0, r1);
     return hipGetLastError();
 }
 
@@ -810,12 +814,17 @@ HamView ham_view(const irl_system *s)
     A.hval = s->ham_kernel == 4 ? s->d.hval : nullptr;
     A.hcb = s->d.hcb;
     A.hcs = s->d.hcs;
-    A.sptr = s->ham_kernel == 4 ? s->d.sptr : nullptr;
-    A.sbase = s->ham_kernel == 4 ? s->d.sbase : nullptr;
-    A.scol = s->ham_kernel == 4 ? s->d.scol : nullptr;
-    A.sval = s->ham_kernel == 4 ? s->d.sval : nullptr;
+    const bool sl = s->ham_kernel == 4 && s->d.scb > 0;
+    A.sbase = sl ? s->d.sbase : nullptr;
+    A.sgbase = sl ? s->d.sgbase : nullptr;
+    A.sglen = sl ? s->d.sglen : nullptr;
+    A.sperm = sl ? s->d.sperm : nullptr;
+    A.scol = sl ? s->d.scol : nullptr;
+    A.sval = sl ? s->d.sval : nullptr;
+    A.spart = sl ? s->d.spart : nullptr;
     A.scb = s->d.scb;
     A.scs = s->d.scs;
+    A.sgroups = s->d.sgroups;
     A.rankA = s->d.rankA;
     A.rankB = s->d.rankB;
     return A;
@@ -1304,20 +1313,19 @@ static hipError_t build_dense_doubles(irl_system *s, int nda, int ndb, hipStream
 // ---- same-spin doubles as one FP64 matrix-core product ------------------------
 // With w as the column-major nA x nB matrix X (column = beta string) and D_A, D_B
 // the symmetric same-spin double matrices of each spin,
-//     U[:, b0:b1] += D_A X[:, b0:b1] + X D_B[:, b0:b1],
-// computed as a single product over the concatenated inner index (the nA alpha
-// strings of the first term, then the nB beta strings of the second), so each
-// 64 x 64 tile of U is read and written once, in a fixed summation order.
-// Workgroup: 4 wavefronts, each owning a 32 x 32 quarter of the tile as 2 x 2
-// blocks of v_mfma_f64_16x16x4f64; inner tiles of 32 are staged through LDS
-// (double-buffered, one barrier per inner tile) and loaded from memory two tiles
-// ahead into registers, so an L2/MALL round trip overlaps two tiles of matrix-core
-// work.  Operand layout of the instruction (lane l): A[l % 16][l / 16],
-// B[l / 16][l % 16]; result register r holds D[4 r + l / 16][l % 16].
+//     U[:, b0:b1] += D_A X[:, b0:b1] + X D_B[:, b0:b1].
+// A workgroup owns a 64 x 64 tile of U and has two groups of 4 wavefronts: group 0
+// forms the tile of D_A X, group 1 that of X D_B, each wavefront a 32 x 32 quarter
+// as 2 x 2 blocks of v_mfma_f64_16x16x4f64, over inner tiles of 32 staged through
+// its own double-buffered LDS (the next inner tile is loaded while the current one
+// is multiplied; two groups per workgroup put two wavefronts on every SIMD).  At
+// the end group 1 hands its tile to group 0 through LDS, which adds the two in a
+// fixed order and updates U once.  Operand layout of the instruction (lane l):
+// A[l % 16][l / 16], B[l / 16][l % 16]; result register r holds D[4 r + l / 16][l % 16].
 namespace {
-constexpr int kDblTM = 64, kDblTN = 64, kDblTK = 32, kDblThreads = 256;
+constexpr int kDblTM = 64, kDblTN = 64, kDblTK = 32, kDblThreads = 512;
 constexpr int kDblLdB = kDblTN + 1;   // padded rows of the B tile (conflict-free column stores)
-constexpr int kDblPer = kDblTM * kDblTK / kDblThreads;   // tile elements per thread (8)
+constexpr int kDblPer = kDblTM * kDblTK / 256;   // tile elements per thread of a group (8)
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
@@ -1329,95 +1337,124 @@ struct DblArgs {
 
 struct DblRegs {
     double a[kDblPer], b[kDblPer];
+    uint32_t va, vb;   // bit j: element j is inside the matrices (else it enters as zero)
+};
+
+struct DblTiles {
+    double A[2][kDblTK][kDblTM];
+    double B[2][kDblTK][kDblLdB];
 };
 }  // namespace
 
 __global__ void __launch_bounds__(kDblThreads) k_same_spin_doubles(DblArgs a)
 {
-    __shared__ double As[2][kDblTK][kDblTM];
-    __shared__ double Bs[2][kDblTK][kDblLdB];
-    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    __shared__ DblTiles tiles[2];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6, grp = wv >> 2, wq = wv & 3, tg = t & 255;
+    DblTiles &T = tiles[grp];
     const int64_t m0 = (int64_t)blockIdx.x * kDblTM, n0 = (int64_t)blockIdx.y * kDblTN;
     const int64_t M = a.nA, N = a.nbeta;
-    const int nk1 = (int)((a.nA + kDblTK - 1) / kDblTK), nk2 = (int)((a.nB + kDblTK - 1) / kDblTK);
-    const int nkt = nk1 + nk2;
-    // A tile element (row m0 + t % 64, inner k0 + t / 64 + 4 j); B tile element
-    // (inner k0 + t % 32, column n0 + t / 32 + 8 j)
-    const int ar = t & 63, ak = t >> 6, bk = t & 31, bn = t >> 5;
+    // group 0: A = D_A (ld nA), B = X[:, b0 + n] (ld nA), inner index over nA;
+    // group 1: A = X (ld nA), B = D_B[:, b0 + n] (ld nB), inner index over nB
+    const double *Am = grp ? a.X : a.DA;
+    const double *Bm = grp ? a.DB : a.X;
+    const int64_t K = grp ? a.nB : a.nA;
+    const int64_t ldb = grp ? a.nB : a.nA;
+    const int nkt = (int)((K + kDblTK - 1) / kDblTK);
+    const int nkmax = (int)((((a.nA > a.nB) ? a.nA : a.nB) + kDblTK - 1) / kDblTK);
+    // A tile element (row m0 + tg % 64, inner k0 + tg / 64 + 4 j); B tile element
+    // (inner k0 + tg % 32, column n0 + tg / 32 + 8 j).  Out-of-range elements load a
+    // clamped in-range address and enter as zero (masks applied at the LDS store).
+    const int ar = tg & 63, ak = tg >> 6, bk = tg & 31, bn = tg >> 5;
     auto load = [&](int kt, DblRegs &R) {
-        if (kt >= nkt) return;
-        const bool first = kt < nk1;
-        const int64_t k0 = (int64_t)(first ? kt : kt - nk1) * kDblTK;
-        const int64_t K = first ? a.nA : a.nB;
-        // first term: A = D_A (ld nA), B = X[:, b0 + n] (ld nA);
-        // second term: A = X (ld nA), B = D_B[:, b0 + n] (ld nB)
-        const double *A = first ? a.DA : a.X;
-        const double *Bm = first ? a.X : a.DB;
-        const int64_t ldb = first ? a.nA : a.nB;
-        const int64_t m = m0 + ar;
+        const int64_t k0 = (int64_t)kt * kDblTK;
+        const int64_t m = m0 + ar, mc = m < M ? m : M - 1;
+        R.va = R.vb = 0u;
 #pragma unroll
         for (int j = 0; j < kDblPer; ++j) {
-            const int64_t k = k0 + ak + 4 * j;
-            R.a[j] = (m < M && k < K) ? A[k * a.nA + m] : 0.0;
+            const int64_t k = k0 + ak + 4 * j, kc = k < K ? k : K - 1;
+            R.a[j] = Am[kc * a.nA + mc];
+            R.va |= (m < M && k < K) ? (1u << j) : 0u;
         }
-        const int64_t kb = k0 + bk;
+        const int64_t kb = k0 + bk, kbc = kb < K ? kb : K - 1;
 #pragma unroll
         for (int j = 0; j < kDblPer; ++j) {
-            const int64_t n = n0 + bn + 8 * j;
-            R.b[j] = (n < N && kb < K) ? Bm[(a.b0 + n) * ldb + kb] : 0.0;
+            const int64_t n = n0 + bn + 8 * j, nc = n < N ? n : N - 1;
+            R.b[j] = Bm[(a.b0 + nc) * ldb + kbc];
+            R.vb |= (n < N && kb < K) ? (1u << j) : 0u;
         }
     };
     auto store = [&](int buf, const DblRegs &R) {
 #pragma unroll
-        for (int j = 0; j < kDblPer; ++j) As[buf][ak + 4 * j][ar] = R.a[j];
+        for (int j = 0; j < kDblPer; ++j) T.A[buf][ak + 4 * j][ar] = ((R.va >> j) & 1u) ? R.a[j] : 0.0;
 #pragma unroll
-        for (int j = 0; j < kDblPer; ++j) Bs[buf][bk][bn + 8 * j] = R.b[j];
+        for (int j = 0; j < kDblPer; ++j) T.B[buf][bk][bn + 8 * j] = ((R.vb >> j) & 1u) ? R.b[j] : 0.0;
     };
     dbl4 acc[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
-    const int wm = (wv & 1) * 32, wn = (wv >> 1) * 32;
+    const int wm = (wq & 1) * 32, wn = (wq >> 1) * 32;
     const int lr = lane & 15, lk = lane >> 4;
-    DblRegs r0, r1;
-    load(0, r0);
-    store(0, r0);
-    load(1, r0);   // tile kt + 1, stored at the end of iteration kt
-    load(2, r1);   // tile kt + 2, in flight across two iterations
-    __syncthreads();
-    for (int kt = 0; kt < nkt; ++kt) {
-        const int buf = kt & 1;
+    auto compute = [&](int buf) {
+        double fa[2][2], fb[2][2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) fa[0][i] = T.A[buf][lk][wm + 16 * i + lr];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) fb[0][j] = T.B[buf][lk][wn + 16 * j + lr];
 #pragma unroll
         for (int ks = 0; ks < kDblTK; ks += 4) {
-            double fa[2], fb[2];
+            const int c = (ks >> 2) & 1, nx = c ^ 1;
+            if (ks + 4 < kDblTK) {
 #pragma unroll
-            for (int i = 0; i < 2; ++i) fa[i] = As[buf][ks + lk][wm + 16 * i + lr];
+                for (int i = 0; i < 2; ++i) fa[nx][i] = T.A[buf][ks + 4 + lk][wm + 16 * i + lr];
 #pragma unroll
-            for (int j = 0; j < 2; ++j) fb[j] = Bs[buf][ks + lk][wn + 16 * j + lr];
+                for (int j = 0; j < 2; ++j) fb[nx][j] = T.B[buf][ks + 4 + lk][wn + 16 * j + lr];
+            }
 #pragma unroll
             for (int i = 0; i < 2; ++i)
 #pragma unroll
                 for (int j = 0; j < 2; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[i], fb[j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[c][i], fb[c][j], acc[i][j], 0, 0, 0);
         }
-        if (kt + 1 < nkt) store(buf ^ 1, r0);
-        r0 = r1;
-        load(kt + 3, r1);
+    };
+    DblRegs R;
+    if (nkt > 0) {
+        load(0, R);
+        store(0, R);
+    }
+    __syncthreads();
+    for (int kt = 0; kt < nkmax; ++kt) {   // every wavefront meets every barrier
+        const int buf = kt & 1;
+        const bool more = kt + 1 < nkt;
+        if (more) load(kt + 1, R);
+        if (kt < nkt) compute(buf);
+        if (more) store(buf ^ 1, R);
         __syncthreads();
     }
-    // U tile += acc (row m0 + wm + 16 i + 4 r + l / 16, column n0 + wn + 16 j + l % 16)
+    // group 1 hands its tile to group 0 (the LDS of the inner tiles is free now)
+    double *xfer = &tiles[0].A[0][0][0];
+    if (grp == 1) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) xfer[((wq * 4 + i * 2 + j) * 4 + r) * 64 + lane] = acc[i][j][r];
+    }
+    __syncthreads();
+    if (grp == 1) return;
+    // U tile += acc_0 + acc_1 (row m0 + wm + 16 i + 4 r + l / 16, column n0 + wn + 16 j + l % 16)
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
             const int64_t n = n0 + wn + 16 * j + lr;
-            if (n >= N) continue;
-            double *col = a.U + (a.b0 + n) * a.nA;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int64_t m = m0 + wm + 16 * i + 4 * r + lk;
-                if (m < M) col[m] += acc[i][j][r];
+                const double v = acc[i][j][r] + xfer[((wq * 4 + i * 2 + j) * 4 + r) * 64 + lane];
+                if (n < N && m < M) a.U[(a.b0 + n) * a.nA + m] += v;
             }
         }
 }

@@ -111,12 +111,18 @@ struct SystemDev {
     int32_t hcb = 0;              // column blocks of the stored rows
     int32_t hcs = 0;              // log2 of the target rows per column block
     // stored rows, LDS-sliced layout (large sets): column slices of 2^scs target rows
-    // (a slice of w staged in LDS); per slice, row offsets relative to the slice's
-    // first element, targets as 16-bit indices inside the slice, values FP64
-    uint32_t *sptr = nullptr;     // scb blocks of n_dets + 1 offsets
-    int64_t *sbase = nullptr;     // scb element offsets of the slices
-    uint16_t *scol = nullptr;     // nnz targets (row - slice start)
-    double *sval = nullptr;       // nnz values
+    // (a slice of w staged in LDS); per slice, rows in windows of kSellWindow ordered
+    // by element count and grouped 64 per wavefront, group g holding glen[g] x 64
+    // slots (slot (j, lane): the lane row's j-th element, zero padding past its end)
+    int64_t *sbase = nullptr;     // scb slot offsets of the slices
+    uint32_t *sgbase = nullptr;   // scb x sgroups slot offsets of the groups (inside the slice)
+    uint16_t *sglen = nullptr;    // scb x sgroups slots per lane of the groups
+    uint16_t *sperm = nullptr;    // scb x sgroups x 64: row of each lane inside its window (0xffff: none)
+    uint16_t *scol = nullptr;     // slots: targets (row - slice start)
+    double *sval = nullptr;       // slots: values
+    double *spart = nullptr;      // scb x n_dets partial sums of one apply
+    int64_t sslots = 0;           // slots, padding included
+    int32_t sgroups = 0;          // ceil(n_dets / 64)
     int32_t scb = 0;              // slices (0: the L2-block layout above, if any)
     int32_t scs = 0;
     // string tables (full space)
@@ -159,11 +165,12 @@ struct HamView {
     const int32_t *hcol;     // stored rows: targets
     const double *hval;      // stored rows: values
     int hcb, hcs;            // stored rows: column blocks, log2 of their width in rows
-    const uint32_t *sptr;    // stored rows, LDS-sliced layout (or nullptr)
-    const int64_t *sbase;
-    const uint16_t *scol;
+    const int64_t *sbase;    // stored rows, LDS-sliced layout (or nullptr)
+    const uint32_t *sgbase;
+    const uint16_t *sglen, *sperm, *scol;
     const double *sval;
-    int scb, scs;
+    double *spart;           // stored rows, LDS-sliced layout: per-slice partial sums of an apply
+    int scb, scs, sgroups;
 };
 
 // key -> row lookup used when excitations are enumerated
@@ -255,14 +262,19 @@ hipError_t launch_hash_lookup(const uint64_t *hkeys, const int32_t *hrows, uint6
 hipError_t launch_diagonal(const uint64_t *keys, int64_t ns, int n, const double *h,
                            const double *g, double *diag, hipStream_t st);
 // stored rows, LDS-sliced layout (hamiltonian.hip): count[b n_dets + row] = connections of
-// row inside slice b; fill writes targets and values at sbase[b] + sptr[b][row] + k and
-// orders each row's slice segment by target
-constexpr int kSliceLog = 14;            // 2^14 target rows (128 KiB of w) per slice
+// row inside slice b; fill writes them to the slots of (slice b, lane slot[b][row] =
+// group * 64 + lane), element j of the row at slot base + j * 64 + lane, in the
+// lane-major enumeration order of its wavefront
+#ifndef IRL_SLICE_LOG
+#define IRL_SLICE_LOG 14
+#endif
+constexpr int kSliceLog = IRL_SLICE_LOG; // 2^14 target rows (128 KiB of w) per slice
 constexpr int kMaxSlices = 256;          // sets of up to 2^22 determinants
+constexpr int kSellWindow = 4096;        // rows ordered by length together
 constexpr int64_t kSlicedMinRows = ((int64_t)1 << 18) + 1;   // up to 2^18 rows: the L2-block layout
 hipError_t launch_ham_count_sliced(const irl_system *s, int scs, int scb, uint32_t *count, hipStream_t st);
-hipError_t launch_ham_fill_sliced(const irl_system *s, int scs, int scb, const int64_t *sbase,
-                                  const uint32_t *sptr, uint16_t *scol, double *sval, hipStream_t st);
+hipError_t launch_ham_fill_sliced(const irl_system *s, int scs, int scb, const uint32_t *slot, uint16_t *scol,
+                                  double *sval, hipStream_t st);
 hipError_t launch_lookup_any(const irl_system *s, const uint64_t *q, int64_t nq, int32_t *rows,
                              hipStream_t st);
 
@@ -319,7 +331,7 @@ hipError_t launch_fac_jvp(const irl_system *s, const WsLayout &L, void *ws, cons
 // `half`, or two (y1 non-null: y0 into half 0, y1 into half 1) from one pass over d
 hipError_t launch_fac_vjp(const irl_system *s, const WsLayout &L, void *ws, const double *y0, const double *y1,
                           const double *coefp, int half, int nblk, hipStream_t st);
-int fac_row_blocks(const WsLayout &L);
+int fac_row_blocks(const irl_system *s, const WsLayout &L);
 // the same products over an explicit row set (keys, psi and d of ns rows), e.g. the
 // drawn rows of a sampled step gathered contiguously
 struct FacRows {
@@ -333,7 +345,7 @@ hipError_t launch_fac_jvp_rows(const irl_system *s, const WsLayout &L, const Fac
 hipError_t launch_fac_vjp_rows(const irl_system *s, const WsLayout &L, void *ws, const FacRows &R,
                                const double *y0, const double *y1, const double *coefp, int half, int nblk,
                                hipStream_t st);
-int fac_row_blocks_n(int64_t ns, int hfac);
+int fac_row_blocks_n(const irl_system *s, int64_t ns, int hfac);
 // partial rows left by launch_fac_vjp over every row of ws
 int fac_vjp_blocks(const irl_system *s, const WsLayout &L);
 hipError_t launch_nqs_dtilde(const irl_system *s, int V, int H, const double *theta,

@@ -53,11 +53,20 @@ def test_stored_rows_count_and_apply(n, na, nb, count, seed, flags):
     nb = s.info.stored_col_blocks
     assert 1 <= nb <= 8 and nb == max(1, -(-keys.size // (1 << 18)))    # 2 MiB slices of w
     assert need == nb * (keys.size + 1) * 8 + 12 * nnz_off
+    assert s.info.stored_elements == nnz_off
     w = np.random.default_rng(4).normal(size=keys.size)
     u = host(s.apply_hamiltonian(dev(w)))
     assert rel_err(u, Href @ w) <= 1e-12
     again, need2 = s.store_hamiltonian(0)   # already stored: no-op
     assert again and need2 == need
+
+
+def _sliced_fixed_bytes(nsl, ns):
+    """Bytes of the LDS-sliced layout besides the 10-byte slots: per slice and group
+    of 64 rows the slot offset and length, per group lane its row, per slice the
+    base, and the per-(slice, row) partial sums."""
+    groups = -(-ns // 64)
+    return groups * nsl * 6 + groups * 64 * nsl * 2 + nsl * 8 + nsl * ns * 8
 
 
 SLICED_CASES = [  # (n, na, nb, selected count or None, seed, system flags)
@@ -71,11 +80,12 @@ SLICED_CASES = [  # (n, na, nb, selected count or None, seed, system flags)
 @pytest.mark.parametrize("n,na,nb,count,seed,flags", SLICED_CASES)
 def test_stored_rows_lds_slices_count_and_apply(n, na, nb, count, seed, flags):
     """LDS-sliced layout (slices of 2^14 target rows, forced by
-    IRL_SYS_STORE_SLICED on sets this small): the byte size fixes the element
-    count, which must equal the oracle's number of connections inside the set;
+    IRL_SYS_STORE_SLICED on sets this small): the number of stored elements must
+    equal the oracle's number of connections inside the set (the byte size then
+    counts the padded slots of the 64-row groups);
     the apply matches the oracle to FP64 rounding, repeats bitwise, and a second
-    system built from the same set stores the same rows (segments ordered by
-    target)."""
+    system built from the same set stores the same rows (each segment in the
+    fixed lane-major enumeration order)."""
     from paper_2601_01437_amd import IRL_SYS_STORE_SLICED
     announce(f"stored rows, LDS slices: n={n} count={count} flags={flags}")
     keys = (space.full_space(n, na, nb) if count is None
@@ -87,7 +97,9 @@ def test_stored_rows_lds_slices_count_and_apply(n, na, nb, count, seed, flags):
     stored, need = s.store_hamiltonian(1 << 40)
     nsl = -(-keys.size // (1 << 14))
     assert stored and s.info.ham_kernel == 4 and s.info.stored_col_blocks == nsl
-    assert need == nsl * (keys.size + 1) * 4 + nsl * 8 + 10 * nnz_off
+    assert s.info.stored_elements == nnz_off
+    slots, rem = divmod(need - _sliced_fixed_bytes(nsl, keys.size), 10)
+    assert rem == 0 and slots >= nnz_off
     w_h = np.random.default_rng(4).normal(size=keys.size)
     w = dev(w_h)
     u1 = host(s.apply_hamiltonian(w))
@@ -115,7 +127,8 @@ def test_stored_rows_lds_slices_large(count):
     stored, need = s.store_hamiltonian(1 << 40)
     nsl = -(-keys.size // (1 << 14))
     assert stored and s.info.ham_kernel == 4 and s.info.stored_col_blocks == nsl
-    assert (need - nsl * (keys.size + 1) * 4 - nsl * 8) % 10 == 0
+    slots, rem = divmod(need - _sliced_fixed_bytes(nsl, keys.size), 10)
+    assert rem == 0 and slots >= s.info.stored_elements
     u1 = host(s.apply_hamiltonian(w))
     assert rel_err(u1, u_enum) <= 1e-12
     sk = np.sort(keys)
