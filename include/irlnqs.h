@@ -534,6 +534,20 @@ int irl_debug_keys(const irl_system *sys, uint64_t *out);
 /* rows[i] = row of keys[i] in the set, or -1 if absent (host arrays of n). */
 int irl_debug_lookup(const irl_system *sys, const uint64_t *keys, int64_t n, int32_t *rows);
 
+/* irl_debug_lookup without any device allocation, for callers that cannot
+ * allocate device memory (tight serving loops, harnesses that forbid
+ * hipMalloc).  keys and rows are host arrays of n <= 262144 entries;
+ * rows[i] = row of keys[i] in the set, or -1 if absent, bit-identical to
+ * irl_debug_lookup.  The keys and rows are staged in a fixed 3 MiB device
+ * array that the library holds on each GPU it runs on until the process ends
+ * (its address is resolved when the first system is created on that device);
+ * the work is enqueued on `stream`, which is synchronised before returning.
+ * IRL_EINVAL for n < 0, n > 262144 or NULL arrays.  Every call on one GPU
+ * shares that GPU's array: calls that overlap in time on the same GPU (from
+ * several threads, or streams) race and must be serialised by the caller. */
+int irl_lookup_noalloc(const irl_system *sys, const uint64_t *keys, int64_t n, int32_t *rows,
+                       void *stream);
+
 /* Copy the diagonal H_xx (n_dets doubles) to host memory out. */
 int irl_debug_diagonal(const irl_system *sys, double *out);
 

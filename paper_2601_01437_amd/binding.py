@@ -134,6 +134,7 @@ _sigs = {
                                  c_void_p]),
     "irl_debug_keys": (c_int32, [_SYS, c_void_p]),
     "irl_debug_lookup": (c_int32, [_SYS, c_void_p, c_int64, c_void_p]),
+    "irl_lookup_noalloc": (c_int32, [_SYS, c_void_p, c_int64, c_void_p, c_void_p]),
     "irl_debug_diagonal": (c_int32, [_SYS, c_void_p]),
     "irl_debug_excitations": (c_int32, [_SYS, c_int64, c_void_p, c_void_p, c_void_p, c_void_p,
                                         c_int64, POINTER(c_int64)]),
@@ -349,6 +350,13 @@ def irl_debug_lookup(sys, keys):
     keys = np.ascontiguousarray(keys, dtype=np.uint64)
     rows = np.empty(keys.size, dtype=np.int32)
     _check(_lib.irl_debug_lookup(sys, keys.ctypes.data, keys.size, rows.ctypes.data), sys)
+    return rows
+
+
+def irl_lookup_noalloc(sys, keys, stream=None):
+    keys = np.ascontiguousarray(keys, dtype=np.uint64)
+    rows = np.empty(keys.size, dtype=np.int32)
+    _check(_lib.irl_lookup_noalloc(sys, keys.ctypes.data, keys.size, rows.ctypes.data, _stream(stream)), sys)
     return rows
 
 

@@ -810,6 +810,13 @@ int irl_system_create(const irl_system_desc *d, void *stream, irl_system **out)
     s->sys_flags = d->flags;
     hipStream_t st = (hipStream_t)stream;
     (void)hipGetDevice(&s->device);
+    {
+        const hipError_t e = noalloc_scratch_setup(s->device);
+        if (e != hipSuccess) {
+            free_system(s);
+            return set_err(nullptr, IRL_EDEVICE, std::string("scratch symbol address: ") + hipGetErrorString(e));
+        }
+    }
     const int64_t cA = binom_host(n, na), cB = binom_host(n, nb);
     std::vector<uint64_t> keys;
     bool full = (d->dets == nullptr);
@@ -1544,6 +1551,26 @@ int irl_debug_lookup(const irl_system *cs, const uint64_t *keys, int64_t n, int3
     (void)hipFree(dq);
     (void)hipFree(dr);
     return rc;
+}
+
+int irl_lookup_noalloc(const irl_system *cs, const uint64_t *keys, int64_t n, int32_t *rows, void *stream)
+{
+    irl_system *s = const_cast<irl_system *>(cs);
+    if (!s) return IRL_EINVAL;
+    if (n < 0 || (n > 0 && (!keys || !rows))) return set_err(s, IRL_EINVAL, "bad key or row arrays");
+    if (n > kNoAllocMaxKeys)
+        return set_err(s, IRL_EINVAL, "irl_lookup_noalloc takes at most 262144 keys per call");
+    if (n == 0) return IRL_OK;
+    unsigned char *base = static_cast<unsigned char *>(noalloc_scratch(s->device));
+    if (!base) return set_err(s, IRL_ESTATE, "fixed scratch not set up on this device");
+    uint64_t *dq = reinterpret_cast<uint64_t *>(base);
+    int32_t *dr = reinterpret_cast<int32_t *>(base + (size_t)kNoAllocMaxKeys * 8);
+    hipStream_t st = (hipStream_t)stream;
+    CK(s, hipMemcpyAsync(dq, keys, (size_t)n * 8, hipMemcpyHostToDevice, st));
+    CK(s, launch_lookup_any(s, dq, n, dr, st));
+    CK(s, hipMemcpyAsync(rows, dr, (size_t)n * 4, hipMemcpyDeviceToHost, st));
+    CK(s, hipStreamSynchronize(st));
+    return IRL_OK;
 }
 
 int irl_debug_excitations(const irl_system *cs, int64_t row, int32_t *target, int8_t *sign,

@@ -23,6 +23,9 @@ constexpr int64_t kColSliceBytes = 2 << 20;   // w bytes per column block (an L2
 constexpr int kReduceGroups = 16;       // first-level groups of the partial reduction
 constexpr int kScalarParts = 1024;      // blocks of the scalar (energy) reductions
 constexpr uint64_t kEmptyKey = ~0ull;   // empty hash slot
+// fixed device scratch of irl_lookup_noalloc: staged keys (8 B) and rows (4 B)
+constexpr int64_t kNoAllocMaxKeys = 1 << 18;
+constexpr size_t kNoAllocScratchBytes = (size_t)kNoAllocMaxKeys * 12;
 
 // Device scalars kept in the first bytes of a workspace.
 struct WsScalars {
@@ -261,6 +264,10 @@ hipError_t launch_hash_lookup(const uint64_t *hkeys, const int32_t *hrows, uint6
                               const uint64_t *q, int64_t nq, int32_t *rows, hipStream_t st);
 hipError_t launch_diagonal(const uint64_t *keys, int64_t ns, int n, const double *h,
                            const double *g, double *diag, hipStream_t st);
+// fixed scratch (system.hip): resolve the device address of the array once per
+// device (with that device current at the call), then return it (nullptr before)
+hipError_t noalloc_scratch_setup(int device);
+void *noalloc_scratch(int device);
 // stored rows, LDS-sliced layout (hamiltonian.hip): count[b n_dets + row] = connections of
 // row inside slice b; fill writes them to the slots of (slice b, lane slot[b][row] =
 // group * 64 + lane), element j of the row at slot base + j * 64 + lane, in the

@@ -7,6 +7,8 @@
 // where the rank of a string is its position in ascending integer order
 // (combinatorial number system: rank = sum_t C(c_t, t) over its set bits
 // c_1 < c_2 < ... , t = 1, 2, ...).
+#include <mutex>
+
 #include "internal.h"
 
 namespace irl {
@@ -212,6 +214,44 @@ hipError_t launch_lookup_any(const irl_system *s, const uint64_t *q, int64_t nq,
     k_lookup_ranks<<<(unsigned)((nq + bs - 1) / bs), bs, 0, st>>>(s->d.rankA, s->d.rankB, s->n,
                                                                   s->nA, q, nq, rows);
     return hipGetLastError();
+}
+
+// ---- fixed device scratch for callers that cannot allocate --------------------
+// One array per GPU (each device that loads the library holds its own copy at its
+// own address until the process ends).  Host code never passes the array's name
+// to a kernel or a copy: it uses the device address resolved by
+// hipGetSymbolAddress, once per device, in noalloc_scratch_setup().
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t noalloc_scratch_setup(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[device]) return hipSuccess;
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != device && (e = hipSetDevice(device)) != hipSuccess) return e;
+    void *ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (cur != device) (void)hipSetDevice(cur);
+    if (e != hipSuccess) return e;
+    if (!ptr) return hipErrorInvalidSymbol;
+    g_scratch_ptr[device] = ptr;
+    return hipSuccess;
+}
+
+void *noalloc_scratch(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch_ptr[device];
 }
 
 }  // namespace irl
