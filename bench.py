@@ -79,6 +79,15 @@ def fac_full_kernel(kind, info, rows, H):
     return kind == "gemv_t" or H <= 64
 
 
+def stored_alg_bytes(info, ns):
+    """Algorithmic HBM bytes of one stored-row apply: every off-diagonal element's
+    value and target once, plus w, the diagonal and u.  The systems timed here are
+    created without IRL_SYS_STORE_SLICED, so sets above 2^18 rows take the sliced
+    layout and the others the L2-blocked one."""
+    per_elem = 10 if ns > (1 << 18) else 12
+    return info.stored_elements * per_elem + 3 * 8 * ns
+
+
 def kernel_roofline(kind, ns, ncols, H, factored, s_build, info, stored_bytes):
     """(name, bound, algorithmic work per launch, unit, peak, source files) of one
     timed kernel kind, or None.
@@ -90,9 +99,12 @@ def kernel_roofline(kind, ns, ncols, H, factored, s_build, info, stored_bytes):
       row); the full-space forms read per-string tables instead (kilobytes).  HBM
       bytes: the matrix-core work, 2 N_s V H flops per product, is below the byte
       time at 8 TB/s for these shapes, and the full-space forms have none.
-    - Hamiltonian apply: stored rows stream their bytes (HBM); the enumerating
-      kernels do one FP64 multiply-add per candidate excitation (2 flops against
-      the vector FP64 peak)."""
+    - Hamiltonian apply: stored rows stream each off-diagonal element once (an FP64
+      value and its target, 2 bytes in the LDS-sliced layout, 4 in the L2-blocked
+      one) and read w and the diagonal and write u once (HBM); padding slots, row
+      offsets and per-slice partial sums are the layout's overhead, not counted.
+      The enumerating kernels do one FP64 multiply-add per candidate excitation
+      (2 flops against the vector FP64 peak)."""
     P1 = ncols
     if kind in ("gemv", "gemv_t", "dtilde_build") and factored:
         name = {"gemv": "fac_jvp", "gemv_t": "fac_vjp", "dtilde_build": "fac_forward"}[kind]
@@ -105,7 +117,7 @@ def kernel_roofline(kind, ns, ncols, H, factored, s_build, info, stored_bytes):
         return kind, "hbm", kernel_bytes(kind, ns, ncols, s_build), "GB/s", HBM_PEAK_GBPS, src
     if kind == "ham_apply":
         if info.ham_kernel == 4:
-            return ("ham_apply", "hbm", stored_bytes + 2 * ns * 8, "GB/s", HBM_PEAK_GBPS,
+            return ("ham_apply", "hbm", stored_alg_bytes(info, ns), "GB/s", HBM_PEAK_GBPS,
                     ("hamiltonian.hip", "internal.h"))
         return ("ham_apply", "alu", 2.0 * ns * info.max_connections, "TFLOP/s", FP64_PEAK_TFLOPS,
                 ("hamiltonian.hip", "internal.h"))
@@ -1191,7 +1203,7 @@ def main():
     operator = {}
     ham_avg = kern["ham_apply"]["ms_avg"]
     red_avg = kern.get("reduce", {}).get("ms_avg") or 0.0
-    ham_bytes = (stored_bytes if stored_bytes else 0) + 2 * 8 * ns
+    ham_bytes = stored_alg_bytes(sysm.info, ns) if stored_bytes else 2 * 8 * ns
     for tag, g6, g7, sDo in (("fp64", "gemv", "gemv_t", 8), ("fp32", "gemv_fp32", "gemv_t_fp32", 4)):
         if g6 not in kern or g7 not in kern:
             continue

@@ -539,10 +539,24 @@ __global__ __launch_bounds__(256) void k_ham_count_sliced(HamArgs A, int scs, in
     }
 }
 
+// Slot (j, lane) of a group (j < L, L a multiple of 4) inside the group's slot
+// range: values in pairs (a lane loads the 16 bytes of slots 2i and 2i + 1),
+// targets in quads (8 bytes of slots 4i .. 4i + 3), so a wavefront's loads are
+// 1 KiB of values and 512 bytes of targets.
+__host__ __device__ __forceinline__ int64_t sell_val_slot(int64_t j, int64_t lane)
+{
+    return (j >> 1) * (2 * kWave) + lane * 2 + (j & 1);
+}
+
+__host__ __device__ __forceinline__ int64_t sell_col_slot(int64_t j, int64_t lane)
+{
+    return (j >> 2) * (4 * kWave) + lane * 4 + (j & 3);
+}
+
 // second pass, one wavefront per workgroup: each lane counts its own connections
 // per slice (LDS table [lane][slice]), an exclusive scan over the lanes gives each
 // lane's first position j in the row's run of each slice, and a second enumeration
-// writes element j of (slice b, row) to slot base + j * 64 + lane of the row's group
+// writes element j of (slice b, row) to slots sell_val_slot / sell_col_slot (j, lane) of the row's group
 // and lane (slot[b][row] = group * 64 + lane): the layout, and so the apply's
 // summation order, are fixed by the set.
 template <int LK>
@@ -581,9 +595,9 @@ __global__ __launch_bounds__(64) void k_ham_fill_sliced(HamArgs A, int scs, int 
             const uint32_t sl = slot[(int64_t)b * A.ns + row];
             const int64_t g = (int64_t)b * sgroups + (sl >> 6);
             if (j < sglen[g]) {
-                const int64_t p = sbase[b] + sgbase[g] + (int64_t)j * kWave + (sl & 63u);
-                scol[p] = (uint16_t)((uint32_t)r & mask);
-                sval[p] = v;
+                const int64_t p0 = sbase[b] + sgbase[g], lane_s = sl & 63u;
+                scol[p0 + sell_col_slot(j, lane_s)] = (uint16_t)((uint32_t)r & mask);
+                sval[p0 + sell_val_slot(j, lane_s)] = v;
             }
         });
         end_row();
@@ -626,8 +640,8 @@ hipError_t launch_ham_fill_sliced(const irl_system *s, int scs, int scb, const u
 // Apply, two kernels.  (1) k_ham_sell: a workgroup owns one slice b and a range of
 // groups; it stages the slice's w (128 KiB) in LDS once, then each wavefront takes
 // groups in turn: lane l sums its row's elements over the group's slots (j, l),
-// kSellUnroll slots in flight (every load of the wavefront is 512 contiguous bytes
-// of values and 128 of targets; the targets index the LDS copy of w), and writes
+// kSellUnroll slots in flight (a wavefront loads 1 KiB of values as lane pairs and
+// 512 bytes of targets as lane quads; the targets index the LDS copy of w), and writes
 // the sum to part[b][row].  (2) k_ham_sliced_sum: u[row] = H_rr w[row] + sum_b
 // part[b][row] in slice order.
 #ifndef IRL_SELL_THREADS
@@ -642,17 +656,26 @@ constexpr int kSellUnroll = IRL_SELL_UNROLL;
 #define IRL_SELL_WGS 4096
 #endif
 constexpr int kSellWaveGoal = IRL_SELL_WGS;   // workgroups per launch (slices x group ranges), about
+constexpr int kSellMaxGroups = 1024;           // groups per workgroup (offsets and lengths staged in LDS)
 
 __global__ __launch_bounds__(kSellThreads) void k_ham_sell(HamArgs A, const double *__restrict__ w, int64_t r0,
                                                            int64_t r1, int64_t ga, int64_t gz, int64_t grange)
 {
-    constexpr int SL = 1 << kSliceLog, PER = SL / (2 * kSellThreads), K = kSellUnroll;
+    constexpr int SL = 1 << kSliceLog, PER = SL / (2 * kSellThreads), K = kSellUnroll, NW = kSellThreads / kWave;
+    constexpr int MAXG = kSellMaxGroups;
     __shared__ double wl[SL];
-    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    __shared__ uint32_t sgb[MAXG];
+    __shared__ uint16_t sgl[MAXG];
+    const int t = threadIdx.x, lane = t & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
     const int b = blockIdx.x;
     const int64_t c0 = (int64_t)b << A.scs;
     const int nc = (int)min((int64_t)SL, A.ns - c0);
-    // stage the slice: every thread's loads are issued before any is stored
+    const int64_t g0 = ga + (int64_t)blockIdx.y * grange;
+    const int ng = (int)(min(gz, g0 + grange) - g0);
+    const int64_t gb = (int64_t)b * A.sgroups;
+    // stage the slice and the groups' offsets and lengths: every thread's loads are
+    // issued before any is stored
     if (nc == SL) {
         double2 x[PER];
 #pragma unroll
@@ -665,33 +688,48 @@ __global__ __launch_bounds__(kSellThreads) void k_ham_sell(HamArgs A, const doub
     } else {
         for (int i = t; i < nc; i += kSellThreads) wl[i] = w[c0 + i];
     }
+    for (int i = t; i < ng; i += kSellThreads) {
+        sgb[i] = A.sgbase[gb + g0 + i];
+        sgl[i] = A.sglen[gb + g0 + i];
+    }
     __syncthreads();
-    const int64_t g0 = ga + (int64_t)blockIdx.y * grange;
-    const int64_t g1 = min(gz, g0 + grange);
-    const int64_t gb = (int64_t)b * A.sgroups;
     const uint16_t *col = A.scol + A.sbase[b];
     const double *val = A.sval + A.sbase[b];
     double *part = A.spart + (int64_t)b * A.ns;
-    for (int64_t g = g0 + wv; g < g1; g += kSellThreads / kWave) {
-        const int L = A.sglen[gb + g];
-        const int64_t base = (int64_t)A.sgbase[gb + g] + lane;
+    for (int i = wv; i < ng; i += NW) {
+        // the group's slot base and length are the same for the whole wavefront
+        const int L = __builtin_amdgcn_readfirstlane((int)sgl[i]);
+        const uint32_t base = (uint32_t)__builtin_amdgcn_readfirstlane((int)sgb[i]);
+        // slots (j, lane): values as pairs, targets as quads (sell_val_slot, sell_col_slot)
+        const double2 *vp = reinterpret_cast<const double2 *>(val + base) + lane;
+        const uint2 *cp = reinterpret_cast<const uint2 *>(col + base) + lane;
+        const uint32_t lr = A.sperm[(gb + g0 + i) * kWave + lane];
         double acc = 0.0;
-        for (int j0 = 0; j0 < L; j0 += K) {
-            double v[K];
-            uint32_t c[K];
+        int j0 = 0;
+        for (; j0 + K <= L; j0 += K) {
+            double2 v[K / 2];
+            uint2 c[K / 4];
 #pragma unroll
-            for (int k = 0; k < K; ++k) {
-                const bool in = j0 + k < L;   // the same for the whole wavefront
-                const int64_t p = base + (int64_t)(in ? j0 + k : 0) * kWave;
-                v[k] = val[p];
-                c[k] = col[p];
-                v[k] = in ? v[k] : 0.0;
+            for (int k = 0; k < K / 2; ++k) v[k] = vp[((j0 >> 1) + k) * kWave];
+#pragma unroll
+            for (int k = 0; k < K / 4; ++k) c[k] = cp[((j0 >> 2) + k) * kWave];
+#pragma unroll
+            for (int k = 0; k < K / 4; ++k) {
+                acc += v[2 * k].x * wl[c[k].x & 0xffffu];
+                acc += v[2 * k].y * wl[c[k].x >> 16];
+                acc += v[2 * k + 1].x * wl[c[k].y & 0xffffu];
+                acc += v[2 * k + 1].y * wl[c[k].y >> 16];
             }
-#pragma unroll
-            for (int k = 0; k < K; ++k) acc += v[k] * wl[c[k]];
         }
-        const uint32_t lr = A.sperm[(gb + g) * kWave + lane];
-        const int64_t row = (g / (kSellWindow / kWave)) * kSellWindow + lr;
+        for (; j0 < L; j0 += 4) {
+            const double2 v0 = vp[(j0 >> 1) * kWave], v1 = vp[((j0 >> 1) + 1) * kWave];
+            const uint2 c = cp[(j0 >> 2) * kWave];
+            acc += v0.x * wl[c.x & 0xffffu];
+            acc += v0.y * wl[c.x >> 16];
+            acc += v1.x * wl[c.y & 0xffffu];
+            acc += v1.y * wl[c.y >> 16];
+        }
+        const int64_t row = ((g0 + i) / (kSellWindow / kWave)) * kSellWindow + lr;
         if (lr != 0xffffu && row >= r0 && row < r1) part[row] = acc;
     }
 }
@@ -717,6 +755,7 @@ static hipError_t launch_ham_sliced(const irl_system *s, const HamArgs &A, const
     int64_t nrange = (kSellWaveGoal + A.scb - 1) / A.scb;
     int64_t grange = (gz - ga + nrange - 1) / nrange;
     if (grange < 16) grange = 16;
+    if (grange > kSellMaxGroups) grange = kSellMaxGroups;
     nrange = (gz - ga + grange - 1) / grange;
     const dim3 grid((unsigned)A.scb, (unsigned)nrange);
     k_ham_sell<<<grid, kSellThreads, 0, st>>>(A, w, r0, r1, ga, gz, grange);
