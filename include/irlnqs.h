@@ -252,13 +252,14 @@ int irl_system_info_get(const irl_system *sys, irl_system_info *out);
  * (j .. j + 3), so a wavefront loads 1 KiB of values or 512 bytes of targets
  * contiguously.  Per slice and group: the slot offset (uint32) and L
  * (uint16); per lane of a group: the lane's row inside its window (uint16,
- * 0xffff for an empty lane); per slice: the slot base (int64) and one FP64
- * partial sum per row,
- * which each apply writes and then sums in slice order.  bytes_needed = groups
- * * slices * 6 + groups * 64 * slices * 2 + slices * 8 + slots * 10 + slices *
- * n_dets * 8 (groups = ceil(n_dets / 64); slots counts the padding).  Device
- * memory is owned by
- * the system.  Later applies stream these rows instead of enumerating
+ * 0xffff for an empty lane); per slice: the slot base (int64) and room for
+ * one FP64 partial sum per row (an apply sums a row's slices in slice order in
+ * LDS, one window at a time; when the set has fewer than 512 windows, the
+ * slices are split into equal runs whose partial sums are added in run order,
+ * the same for every apply of the set).  bytes_needed = groups * slices * 6 +
+ * groups * 64 * slices * 2 + slices * 8 + slots * 10 + slices * n_dets * 8
+ * (groups = ceil(n_dets / 64); slots counts the padding).  Device memory is
+ * owned by the system.  Later applies stream these rows instead of enumerating
  * excitations (ham_kernel becomes 4, stored_col_blocks reports the block or
  * slice count); results agree with the enumerating kernels to rounding
  * (summation order differs) and are reproducible.  Enumeration passes count and

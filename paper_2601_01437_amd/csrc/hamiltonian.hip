@@ -637,39 +637,13 @@ hipError_t launch_ham_fill_sliced(const irl_system *s, int scs, int scb, const u
     return hipGetLastError();
 }
 
-// Apply, two kernels.  (1) k_ham_sell: a workgroup owns one slice b and a range of
-// groups; it stages the slice's w (128 KiB) in LDS once.  All wavefronts but the last
-// stream groups: lane l sums its row's elements over the group's slots (j, l) (a
-// wavefront loads 1 KiB of values as lane pairs and 512 bytes of targets as lane
-// quads; the targets index the LDS copy of w).  A finished group's 64 sums go to the
-// last wavefront through a small LDS ring, and that wavefront writes them to
-// part[b][row]: the streaming wavefronts issue no global stores, whose completion
-// their later load waits would otherwise include.  (2) k_ham_sliced_sum: u[row] =
-// H_rr w[row] + sum_b part[b][row] in slice order.
-#ifndef IRL_SELL_THREADS
-#define IRL_SELL_THREADS 1024
-#endif
+// Apply of the sliced layout: k_ham_sell_win sums each row's elements slice by slice
+// (below), k_ham_sliced_sum adds the partial sums of the runs of slices when a window's
+// slices are split into runs.
 #ifndef IRL_SELL_UNROLL
 #define IRL_SELL_UNROLL 16
 #endif
-constexpr int kSellThreads = IRL_SELL_THREADS;
 constexpr int kSellUnroll = IRL_SELL_UNROLL;
-constexpr int kSellProducers = kSellThreads / kWave - 1;   // streaming wavefronts (the last one writes)
-constexpr int kSellRing = 2;                                // ring slots per streaming wavefront
-#ifndef IRL_SELL_WGS
-#define IRL_SELL_WGS 4096
-#endif
-constexpr int kSellWaveGoal = IRL_SELL_WGS;   // workgroups per launch (slices x group ranges), about
-// groups per workgroup: one per lane of each streaming wavefront (slot offsets and
-// lengths are kept in registers)
-constexpr int kSellMaxGroups = kSellProducers * kWave;
-// polls of an LDS flag (each after a short sleep) before a wait gives up: a
-// streaming wavefront waits for a free ring slot (the writer frees one in well under
-// a microsecond), the writer for the next full one (a group takes tens of
-// microseconds); both limits are far beyond any real wait and only bound the kernel
-// if the hand-off were ever broken
-constexpr int kSellSpinLimit = 1 << 16;
-constexpr int kSellIdleLimit = 1 << 20;
 // word 3 of a raw buffer descriptor on gfx9-family parts: 32-bit data format, no
 // swizzle, no index stride; with stride 0 the size (word 2) is in bytes and loads at
 // or past it return zeros
@@ -678,217 +652,202 @@ constexpr int kBufferWord3 = 0x00020000;
 // apply, so they should not displace w, the lane rows or the partial sums in L2)
 constexpr int kStreamPolicy = 2;
 
-__global__ __launch_bounds__(kSellThreads) void k_ham_sell(HamArgs A, const double *__restrict__ w, int64_t r0,
-                                                           int64_t r1, int64_t ga, int64_t gz, int64_t grange)
+// k_ham_sell_win: a workgroup owns one window of 4096 rows and a run of consecutive
+// slices.  For each slice it stages the slice's w (128 KiB) in LDS; its 16 wavefronts
+// then take the window's 64 groups of that slice, 4 each: wavefront wv's k-th group is
+// 16 k + wv for even k and 16 k + 15 - wv for odd k (groups run from long to short
+// inside a window, so alternating directions evens out the work).  A wavefront's
+// groups form one stream of chunks of 16 slots (8 KiB of values as lane pairs, 2 KiB
+// of targets as lane quads); the next chunk's loads are issued before the current one
+// is summed.  Each chunk reads through buffer descriptors whose size ends at its
+// group's end: quads past the end read as zeros (values 0, targets 0) without touching
+// memory, so every chunk issues the same loads and the waits before a sum count only
+// that chunk's loads.  Lane l of a group sums its row's elements (targets index the
+// LDS copy of w) and adds the sum to the row's accumulator in LDS: a row occurs once
+// per slice, so no two lanes touch one accumulator within a slice, and slices are
+// separated by barriers, so every row sums its slices in slice order.  At the end the
+// workgroup writes u = H_rr w + sum when it owns all slices, else the run's partial
+// sum, which k_ham_sliced_sum adds over the runs in order.  No per-slice partial sum
+// reaches memory.
+constexpr int kWinThreads = 1024;
+constexpr int kWinGroups = kSellWindow / kWave;   // groups per window (64)
+
+__global__ __launch_bounds__(kWinThreads) void k_ham_sell_win(HamArgs A, const double *__restrict__ w,
+                                                              double *__restrict__ u, int64_t r0, int64_t r1,
+                                                              int64_t wa, int spg)
 {
-    constexpr int SL = 1 << kSliceLog, PER = SL / (2 * kSellThreads), K = kSellUnroll, NP = kSellProducers;
-    constexpr int RD = kSellRing;
+    constexpr int SL = 1 << kSliceLog, PER = SL / (2 * kWinThreads), K = kSellUnroll, NW = kWinThreads / kWave;
+    constexpr int GPW = kWinGroups / NW;   // groups of a wavefront per slice
+    static_assert(GPW <= kWave, "one group of a wavefront's share per lane");
     __shared__ double wl[SL];
-    __shared__ double rres[NP][RD][kWave];
-    __shared__ uint32_t rrow[NP][RD][kWave];
-    __shared__ int rflag[NP * RD];
-    // ring flags: relaxed workgroup-scope atomics (plain LDS reads and writes that the
-    // compiler neither caches nor drops); the hand-off order comes from explicit
-    // waits and compiler barriers
-    auto flag_get = [&](int f) { return __hip_atomic_load(&rflag[f], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP); };
-    auto flag_set = [&](int f, int x) { __hip_atomic_store(&rflag[f], x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP); };
+    __shared__ double acc[kSellWindow];
     const int t = threadIdx.x, lane = t & 63;
     const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
-    const int b = blockIdx.x;
-    const int64_t c0 = (int64_t)b << A.scs;
-    const int nc = (int)min((int64_t)SL, A.ns - c0);
-    const int64_t g0 = ga + (int64_t)blockIdx.y * grange;
-    const int ng = (int)(min(gz, g0 + grange) - g0);
-    const int64_t gb = (int64_t)b * A.sgroups;
-    // stage the slice: every thread's loads are issued before any is stored
-    if (nc == SL) {
-        double2 x[PER];
-#pragma unroll
-        for (int j = 0; j < PER; ++j) x[j] = *reinterpret_cast<const double2 *>(w + c0 + 2 * (t + j * kSellThreads));
-#pragma unroll
-        for (int j = 0; j < PER; ++j) {
-            wl[2 * (t + j * kSellThreads)] = x[j].x;
-            wl[2 * (t + j * kSellThreads) + 1] = x[j].y;
-        }
-    } else {
-        for (int i = t; i < nc; i += kSellThreads) wl[i] = w[c0 + i];
-    }
-    if (t < NP * RD) flag_set(t, 0);
-    double *part = A.spart + (int64_t)b * A.ns;
-    if (wv == NP) {
-        // the writer: takes full ring slots in turn and stores their sums; lane p
-        // keeps producer p's next slot.  It stops after the range's ng groups.
-        __syncthreads();
-        int slot = 0, done = 0, idle = 0;
-        while (done < ng && idle < kSellIdleLimit) {
-            bool any = false;
-            for (int p = 0; p < NP; ++p) {
-                const int sp = __builtin_amdgcn_readlane(slot, p);
-                if (__builtin_amdgcn_readfirstlane(flag_get(p * RD + sp)) == 0) continue;
-                // the slot is read only after its flag (no load is moved above this)
-                asm volatile("" ::: "memory");
-                const double v = rres[p][sp][lane];
-                const uint32_t row = rrow[p][sp][lane];
-                if (row != 0xffffffffu) part[row] = v;
-                // the slot's reads are complete before it is handed back
-                asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-                flag_set(p * RD + sp, 0);
-                if (lane == p) slot ^= 1;
-                ++done;
-                any = true;
-            }
-            if (any) {
-                idle = 0;
-            } else {
-                __builtin_amdgcn_s_sleep(2);
-                ++idle;
-            }
-        }
-        return;
-    }
-    // the producer's k-th group is k NP + wv for even k and k NP + NP - 1 - wv for odd
-    // k (groups run from long to short inside a window, so alternating directions
-    // evens out the wavefronts' work); lane k keeps that group's slot offset and
-    // length, read back as scalars (readlane) when the stream reaches it
-    auto group_of = [&](int kk) { return kk * NP + ((kk & 1) ? NP - 1 - wv : wv); };
-    uint32_t mbase = 0, mlen = 0;
-    {
-        const int gi = group_of(lane);
-        if (gi < ng) {
-            mbase = A.sgbase[gb + g0 + gi];
-            mlen = A.sglen[gb + g0 + gi];
-        }
-    }
-    __syncthreads();
-    // the slice's slot base, made scalar (every stream address below is a scalar
-    // buffer descriptor plus a loop-invariant lane offset)
-    const uint64_t sb64 = (uint64_t)A.sbase[b];
-    const int64_t sb = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(sb64 >> 32)) << 32) |
-                                 (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)sb64));
-    const uint16_t *col = A.scol + sb;
-    const double *val = A.sval + sb;
-    // The producer's groups (in the order above) form one stream of chunks of K
-    // slots; the loads of the next chunk (of this group or the next) are issued
-    // before the current one is consumed.  Each chunk reads through buffer
-    // descriptors whose size ends at its group's end: quads past the end read as
-    // zeros (values 0, targets 0) without touching memory, so every chunk issues the
-    // same loads and is summed whole, and the waits before each sum count only the
-    // current chunk's loads.  The step after the last chunk reloads it.
+    const int64_t win = wa + blockIdx.x;
+    const int sg = blockIdx.y;
+    const int b0 = sg * spg, b1 = min(A.scb, b0 + spg);
+    const int64_t gw0 = win * kWinGroups;
+    const int ngw = (int)min((int64_t)kWinGroups, (int64_t)A.sgroups - gw0);
+    for (int i = t; i < kSellWindow; i += kWinThreads) acc[i] = 0.0;
+    auto group_of = [&](int kk) { return kk * NW + ((kk & 1) ? NW - 1 - wv : wv); };
     static_assert(K == 16, "chunk offsets below assume 16 slots");
     const int vo0 = lane * 16, vo1 = lane * 16 + 4096, co = lane * 8, po = lane * 2;
-    const __amdgpu_buffer_rsrc_t prs = __builtin_amdgcn_make_buffer_rsrc(
-        (void *)(A.sperm + (gb + g0) * kWave), 0, ng * kWave * 2, kBufferWord3);
     struct Chunk {
         double2 v[K / 2];
         uint2 c[K / 4];
         uint32_t lr;
     };
-    auto load = [&](Chunk &x, uint32_t base, int j0, int L, int gi) {
-        const int left = L - j0;
-        const __amdgpu_buffer_rsrc_t vrs = __builtin_amdgcn_make_buffer_rsrc(
-            (void *)(val + base + (uint32_t)j0 * kWave), 0, left * kWave * 8, kBufferWord3);
-        const __amdgpu_buffer_rsrc_t crs = __builtin_amdgcn_make_buffer_rsrc(
-            (void *)(col + base + (uint32_t)j0 * kWave), 0, left * kWave * 2, kBufferWord3);
-        x.lr = __builtin_amdgcn_raw_buffer_load_b16(prs, po, gi * kWave * 2, 0);
+    for (int b = b0; b < b1; ++b) {
+        // every wavefront is done with the previous slice's copy of w
+        __syncthreads();
+        const int64_t c0 = (int64_t)b << A.scs;
+        const int nc = (int)min((int64_t)SL, A.ns - c0);
+        const int64_t gb = (int64_t)b * A.sgroups + gw0;   // the window's first group in slice b
+        // the wavefront's groups of this slice: lane k < GPW keeps group k's slot
+        // offset and length
+        uint32_t mbase = 0, mlen = 0;
+        if (lane < GPW) {
+            const int gi = group_of(lane);
+            if (gi < ngw) {
+                mbase = A.sgbase[gb + gi];
+                mlen = A.sglen[gb + gi];
+            }
+        }
+        if (nc == SL) {
+            double2 x[PER];
 #pragma unroll
-        for (int k = 0; k < K / 2; ++k) {
-            // value pair k of the chunk: bytes k * 1024 + lane * 16
-            const auto r = __builtin_amdgcn_raw_buffer_load_b128(vrs, k < 4 ? vo0 + k * 1024 : vo1 + (k - 4) * 1024,
-                                                                 0, kStreamPolicy);
-            x.v[k] = double2{__builtin_bit_cast(double, (uint64_t)r[0] | ((uint64_t)r[1] << 32)),
-                             __builtin_bit_cast(double, (uint64_t)r[2] | ((uint64_t)r[3] << 32))};
-        }
+            for (int j = 0; j < PER; ++j) x[j] = *reinterpret_cast<const double2 *>(w + c0 + 2 * (t + j * kWinThreads));
 #pragma unroll
-        for (int q = 0; q < K / 4; ++q) {
-            // target quad q: bytes q * 512 + lane * 8
-            const auto r = __builtin_amdgcn_raw_buffer_load_b64(crs, co + q * 512, 0, kStreamPolicy);
-            x.c[q] = uint2{r[0], r[1]};
+            for (int j = 0; j < PER; ++j) {
+                wl[2 * (t + j * kWinThreads)] = x[j].x;
+                wl[2 * (t + j * kWinThreads) + 1] = x[j].y;
+            }
+        } else {
+            for (int i = t; i < nc; i += kWinThreads) wl[i] = w[c0 + i];
         }
-    };
-    auto sum = [&](const Chunk &x, double acc) {
+        __syncthreads();
+        const uint64_t sb64 = (uint64_t)A.sbase[b];
+        const int64_t sb = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(sb64 >> 32)) << 32) |
+                                     (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)sb64));
+        const uint16_t *col = A.scol + sb;
+        const double *val = A.sval + sb;
+        const __amdgpu_buffer_rsrc_t prs =
+            __builtin_amdgcn_make_buffer_rsrc((void *)(A.sperm + gb * kWave), 0, ngw * kWave * 2, kBufferWord3);
+        auto load = [&](Chunk &x, uint32_t base, int j0, int L, int gi) {
+            const int left = L - j0;
+            const __amdgpu_buffer_rsrc_t vrs = __builtin_amdgcn_make_buffer_rsrc(
+                (void *)(val + base + (uint32_t)j0 * kWave), 0, left * kWave * 8, kBufferWord3);
+            const __amdgpu_buffer_rsrc_t crs = __builtin_amdgcn_make_buffer_rsrc(
+                (void *)(col + base + (uint32_t)j0 * kWave), 0, left * kWave * 2, kBufferWord3);
+            x.lr = __builtin_amdgcn_raw_buffer_load_b16(prs, po, gi * kWave * 2, 0);
 #pragma unroll
-        for (int q = 0; q < K / 4; ++q) {
-            acc += x.v[2 * q].x * wl[x.c[q].x & 0xffffu];
-            acc += x.v[2 * q].y * wl[x.c[q].x >> 16];
-            acc += x.v[2 * q + 1].x * wl[x.c[q].y & 0xffffu];
-            acc += x.v[2 * q + 1].y * wl[x.c[q].y >> 16];
+            for (int k = 0; k < K / 2; ++k) {
+                const auto r = __builtin_amdgcn_raw_buffer_load_b128(
+                    vrs, k < 4 ? vo0 + k * 1024 : vo1 + (k - 4) * 1024, 0, kStreamPolicy);
+                x.v[k] = double2{__builtin_bit_cast(double, (uint64_t)r[0] | ((uint64_t)r[1] << 32)),
+                                 __builtin_bit_cast(double, (uint64_t)r[2] | ((uint64_t)r[3] << 32))};
+            }
+#pragma unroll
+            for (int q = 0; q < K / 4; ++q) {
+                const auto r = __builtin_amdgcn_raw_buffer_load_b64(crs, co + q * 512, 0, kStreamPolicy);
+                x.c[q] = uint2{r[0], r[1]};
+            }
+        };
+        auto sum = [&](const Chunk &x, double a) {
+#pragma unroll
+            for (int q = 0; q < K / 4; ++q) {
+                a += x.v[2 * q].x * wl[x.c[q].x & 0xffffu];
+                a += x.v[2 * q].y * wl[x.c[q].x >> 16];
+                a += x.v[2 * q + 1].x * wl[x.c[q].y & 0xffffu];
+                a += x.v[2 * q + 1].y * wl[x.c[q].y >> 16];
+            }
+            return a;
+        };
+        int i = group_of(0), k = 0;
+        if (i < ngw) {
+            int L = __builtin_amdgcn_readlane((int)mlen, 0);
+            uint32_t base = (uint32_t)__builtin_amdgcn_readlane((int)mbase, 0);
+            int j0 = 0;
+            double gs = 0.0;
+            Chunk ca, cb;
+            load(ca, base, 0, L, i);
+            auto step = [&](Chunk &cur, Chunk &nxt) -> bool {
+                const bool last = j0 + K >= L;
+                const int kn = min(k + 1, GPW - 1);
+                const int gL = __builtin_amdgcn_readlane((int)mlen, kn);
+                const uint32_t gbase = (uint32_t)__builtin_amdgcn_readlane((int)mbase, kn);
+                const int ni = last ? (k + 1 < GPW ? group_of(k + 1) : ngw) : i, nj = last ? 0 : j0 + K;
+                const int nL = last ? gL : L;
+                const uint32_t nbase = last ? gbase : base;
+                const bool more = ni < ngw;
+                load(nxt, more ? nbase : base, more ? nj : j0, more ? nL : L, more ? ni : i);
+                gs = sum(cur, gs);
+                if (last) {
+                    const uint32_t lr = cur.lr;
+                    if (lr != 0xffffu) acc[lr] += gs;
+                    gs = 0.0;
+                }
+                k = last ? k + 1 : k;
+                i = ni;
+                j0 = nj;
+                L = nL;
+                base = nbase;
+                return more;
+            };
+            while (step(ca, cb) && step(cb, ca)) {
+            }
         }
-        return acc;
-    };
-    int i = group_of(0), k = 0, ps = 0;
-    if (i >= ng) return;
-    int L = __builtin_amdgcn_readlane((int)mlen, 0);
-    uint32_t base = (uint32_t)__builtin_amdgcn_readlane((int)mbase, 0);
-    int j0 = 0;
-    double acc = 0.0;
-    Chunk ca, cb;
-    load(ca, base, 0, L, i);
-    // one step: prefetch the chunk after `cur` into `nxt`, sum `cur`; false at the end
-    auto step = [&](Chunk &cur, Chunk &nxt) -> bool {
-        // the next chunk, by scalar selects
-        const bool last = j0 + K >= L;
-        const int kn = min(k + 1, kWave - 1);
-        const int gL = __builtin_amdgcn_readlane((int)mlen, kn);
-        const uint32_t gbase = (uint32_t)__builtin_amdgcn_readlane((int)mbase, kn);
-        const int ni = last ? group_of(k + 1) : i, nj = last ? 0 : j0 + K, nL = last ? gL : L;
-        const uint32_t nbase = last ? gbase : base;
-        const bool more = ni < ng;
-        load(nxt, more ? nbase : base, more ? nj : j0, more ? nL : L, more ? ni : i);
-        acc = sum(cur, acc);
-        if (last) {
-            // hand the group's sums to the writer through ring slot ps
-            const uint32_t lr = cur.lr;
-            const int64_t row = ((g0 + i) / (kSellWindow / kWave)) * kSellWindow + lr;
-            for (int spin = 0; __builtin_amdgcn_readfirstlane(flag_get(wv * RD + ps)) != 0 && spin < kSellSpinLimit; ++spin)
-                __builtin_amdgcn_s_sleep(1);
-            asm volatile("" ::: "memory");
-            rres[wv][ps][lane] = acc;
-            rrow[wv][ps][lane] = (lr != 0xffffu && row >= r0 && row < r1) ? (uint32_t)row : 0xffffffffu;
-            // the sums are in LDS before the slot is marked full
-            asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-            flag_set(wv * RD + ps, 1);
-            ps ^= 1;
-            acc = 0.0;
-        }
-        k = last ? k + 1 : k;
-        i = ni;
-        j0 = nj;
-        L = nL;
-        base = nbase;
-        return more;
-    };
-    while (step(ca, cb) && step(cb, ca)) {
+    }
+    __syncthreads();
+    const int64_t row0 = win * kSellWindow;
+    const bool whole = b0 == 0 && b1 == A.scb;
+    double *part = A.spart + (int64_t)sg * A.ns;
+    for (int i = t; i < kSellWindow; i += kWinThreads) {
+        const int64_t row = row0 + i;
+        if (row < r0 || row >= r1) continue;
+        if (whole)
+            u[row] = fma(A.diag[row], w[row], acc[i]);
+        else
+            part[row] = acc[i];
     }
 }
 
+// u[row] = H_rr w[row] + sum over the nparts partial sums in order
 __global__ __launch_bounds__(256) void k_ham_sliced_sum(HamArgs A, const double *__restrict__ w,
-                                                        double *__restrict__ u, int64_t r0, int64_t r1)
+                                                        double *__restrict__ u, int64_t r0, int64_t r1, int nparts)
 {
     const int64_t row = r0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (row >= r1) return;
     double acc = 0.0;
-    for (int b = 0; b < A.scb; ++b) acc += A.spart[(int64_t)b * A.ns + row];
+    for (int b = 0; b < nparts; ++b) acc += A.spart[(int64_t)b * A.ns + row];
     u[row] = fma(A.diag[row], w[row], acc);
 }
+
+#ifndef IRL_SELL_WIN_GOAL
+#define IRL_SELL_WIN_GOAL 512
+#endif
+// window-major workgroups wanted for the whole set: with fewer windows than this a
+// window's slices are split into runs, each adding one partial sum per row (two
+// workgroups per CU balance the windows' unequal work; more runs only add partial
+// sums).  The run count depends on the set alone, so a row's sum does not depend on
+// the row range of the launch.
+constexpr int kSellWinGoal = IRL_SELL_WIN_GOAL;
 
 static hipError_t launch_ham_sliced(const irl_system *s, const HamArgs &A, const double *w, double *u, int64_t r0,
                                     int64_t r1, hipStream_t st)
 {
-    // the groups of the windows that hold rows [r0, r1)
-    constexpr int64_t GPW = kSellWindow / kWave;
-    const int64_t ga = (r0 / kSellWindow) * GPW;
-    int64_t gz = ((r1 + kSellWindow - 1) / kSellWindow) * GPW;
-    if (gz > A.sgroups) gz = A.sgroups;
-    int64_t nrange = (kSellWaveGoal + A.scb - 1) / A.scb;
-    int64_t grange = (gz - ga + nrange - 1) / nrange;
-    if (grange < 16) grange = 16;
-    if (grange > kSellMaxGroups) grange = kSellMaxGroups;
-    nrange = (gz - ga + grange - 1) / grange;
-    const dim3 grid((unsigned)A.scb, (unsigned)nrange);
-    k_ham_sell<<<grid, kSellThreads, 0, st>>>(A, w, r0, r1, ga, gz, grange);
+    (void)s;
+    const int64_t windows = (A.ns + kSellWindow - 1) / kSellWindow;
+    int runs = (int)((kSellWinGoal + windows - 1) / windows);
+    if (runs < 1) runs = 1;
+    if (runs > A.scb) runs = A.scb;
+    const int spg = (A.scb + runs - 1) / runs;
+    runs = (A.scb + spg - 1) / spg;
+    const int64_t wa = r0 / kSellWindow, wz = (r1 + kSellWindow - 1) / kSellWindow;
+    k_ham_sell_win<<<dim3((unsigned)(wz - wa), (unsigned)runs), kWinThreads, 0, st>>>(A, w, u, r0, r1, wa, spg);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    k_ham_sliced_sum<<<(unsigned)((r1 - r0 + 255) / 256), 256, 0, st>>>(A, w, u, r0, r1);
+    if (e != hipSuccess || runs == 1) return e;
+    k_ham_sliced_sum<<<(unsigned)((r1 - r0 + 255) / 256), 256, 0, st>>>(A, w, u, r0, r1, runs);
     return hipGetLastError();
 }
 
