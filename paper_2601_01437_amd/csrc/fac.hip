@@ -1071,7 +1071,7 @@ __global__ __launch_bounds__(256) void k_fac_vjp_bits(BitsArgs A, const double *
             skey[i] = A.keys[r];
             sps[i] = ps;
 #pragma unroll
-            for (int q = 0; q < NR; ++q) sc[q][i] = ys[q][r] - coef * ps;
+            for (int q = 0; q < NR; ++q) sc[q][i] = fma(-coef, ps, ys[q][r]);
         }
         __syncthreads();
         for (int j0 = 0; j0 < nbt; j0 += PD) {
@@ -1161,6 +1161,247 @@ __global__ __launch_bounds__(256) void k_fac_vjp_bits(BitsArgs A, const double *
     }
 }
 
+// The same partial rows with the rows' data streamed into LDS by direct-to-LDS loads
+// (global_load_lds), which need no registers, so a wavefront keeps kRingPairs row
+// pairs of d in flight beside its 2 NR NA accumulators.  Wavefront w owns hidden
+// units [64 w, 64 w + 64) and its own LDS ring: one load per row pair brings the
+// pair's two 512-byte segments of d; the rows' keys, psi and y (kRingBatch rows at a
+// time, double-buffered) come the same way, in dwords.  The rows are visited in the
+// order of k_fac_vjp_bits and every sum has the same operands in the same order, so
+// the partial rows are bitwise those of k_fac_vjp_bits.  Only direct-to-LDS loads
+// are in flight in the loop, so the waits are counted by hand: before a pair is
+// read, every load but the ones issued after it has completed.
+constexpr int kRingPairs = 16;   // row pairs in flight per wavefront
+constexpr int kRingBatch = 64;   // rows per batch of keys, psi and y
+
+typedef __attribute__((address_space(3))) void *lds_ptr_t;
+// word 3 of a raw buffer descriptor on gfx9-family parts: 32-bit data format, no
+// swizzle, no index stride; with stride 0 the size (word 2) is in bytes and loads at
+// or past it return zeros
+constexpr int kBufWord3 = 0x00020000;
+typedef uint32_t u4v __attribute__((ext_vector_type(4)));
+// the LDS byte address of a workgroup-shared object
+__device__ __forceinline__ uint32_t lds_addr(const void *p)
+{
+    return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) void *)p;
+}
+// double e of two packed in a 16-byte LDS read
+__device__ __forceinline__ double u2d(u4v x, int e)
+{
+    return __builtin_bit_cast(double, ((uint64_t)x[2 * e + 1] << 32) | x[2 * e]);
+}
+
+template <int NR, int NA>
+__global__ __launch_bounds__(256) void k_fac_vjp_ring(BitsArgs A, const double *__restrict__ y0,
+                                                      const double *__restrict__ y1, const double *__restrict__ coefp,
+                                                      double *__restrict__ part, int64_t ldv, int nblk, int half)
+{
+    constexpr int RP = kRingPairs, MB = kRingBatch, NM = 2 + NR;   // arrays per batch: keys, psi, y0 (, y1)
+    __shared__ double ring[4][RP][128];
+    __shared__ double meta[4][2][NM][MB];
+    const int t = threadIdx.x, lane = t & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int H = A.H, n = A.n, V = A.V;
+    int64_t r0, r1;
+    bits_block(A.ns, nblk, blockIdx.x, r0, r1);
+    const int64_t nr = r1 - r0;
+    const double coef = coefp ? *coefp : 0.0;
+    double wa[NR][NA], wb[NR][NA], sb[NR], bp[NR], ax[NR], a0[NR];
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+        sb[q] = bp[q] = ax[q] = a0[q] = 0.0;
+#pragma unroll
+        for (int k = 0; k < NA; ++k) wa[q][k] = wb[q][k] = 0.0;
+    }
+    uint32_t cur = 0u;
+    bool run = false;
+    if (nr > 0) {
+        // Direct-to-LDS buffer loads with loop-invariant lane offsets; each load's
+        // descriptor ends at the block's last row, so lanes past it (the second row of
+        // a last odd pair, pairs and batches past the end) read zeros and touch no
+        // memory.
+        const int vo_d = ((lane >> 5) * H + 64 * wv + 2 * (lane & 31)) * 8, vo_m = lane * 4;
+        // pair p: rows r0 + 2p and r0 + 2p + 1, the wavefront's 64 hidden units of each
+        auto dma_pair = [&](int64_t p) {
+            const int64_t left = nr - 2 * p;
+            const int nb = left <= 0 ? 0 : (int)((left < 2 ? left : 2) * H * 8);
+            const __amdgpu_buffer_rsrc_t rs =
+                __builtin_amdgcn_make_buffer_rsrc((void *)(A.dfac + (r0 + 2 * p) * H), 0, nb, kBufWord3);
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_ptr_t)&ring[wv][p % RP][0], 16, vo_d, 0, 0, 0);
+        };
+        // batch b: keys, psi, y0 (, y1) of rows r0 + MB b ... as dwords (two loads of
+        // 32 rows per array)
+        auto dma_meta = [&](int64_t b) {
+            const double *arr[4] = {reinterpret_cast<const double *>(A.keys), A.psi, y0, y1};
+            const int64_t left = nr - (int64_t)MB * b;
+            const int nb = left <= 0 ? 0 : (int)((left < MB ? left : MB) * 8);
+#pragma unroll
+            for (int a = 0; a < NM; ++a) {
+                const __amdgpu_buffer_rsrc_t rs =
+                    __builtin_amdgcn_make_buffer_rsrc((void *)(arr[a] + r0 + (int64_t)MB * b), 0, nb, kBufWord3);
+                // the immediate offset moves both the global and the LDS address
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_ptr_t)&meta[wv][b & 1][a][0], 4, vo_m, 0, 0, 0);
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_ptr_t)&meta[wv][b & 1][a][0], 4, vo_m, 0, 256, 0);
+            }
+        };
+        const int64_t npairs = (nr + 1) / 2;
+        dma_meta(0);
+        dma_meta(1);
+#pragma unroll
+        for (int p = 0; p < RP; ++p) dma_pair(p);
+        // two pairs (four rows) per iteration; a batch holds MB / 2 pairs, an even count
+        for (int64_t p = 0; p < npairs; p += 2) {
+            const int64_t b = p / (MB / 2);
+            if (p % (MB / 2) == 0 && b > 0) {
+                // batch b - 1's rows are read (their LDS reads complete), so its buffer
+                // takes batch b + 1
+                asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+                dma_meta(b + 1);
+            }
+            // pair p + 1's load and every older one have completed: the loads issued
+            // after it are the RP - 2 later pairs and, when a batch started since, the
+            // 2 NM loads of the next batch
+            const int64_t bs = b * (MB / 2);   // the latest batch start at or before p
+            if (bs > 0 && bs > p + 1 - RP) {
+                if constexpr (NR == 2)
+                    asm volatile("s_waitcnt vmcnt(22)" ::: "memory");
+                else
+                    asm volatile("s_waitcnt vmcnt(20)" ::: "memory");
+            } else {
+                asm volatile("s_waitcnt vmcnt(14)" ::: "memory");
+            }
+            // the four rows' keys, psi and y (the same for every lane) and their d
+            // values, read in one block that also waits for them: the compiler does not
+            // track which LDS bytes the direct-to-LDS loads write and would otherwise
+            // wait for every load in flight before each read
+            const int jm0 = (int)((2 * p) % MB);
+            const uint32_t maddr = lds_addr(&meta[wv][b & 1][0][jm0]);
+            const uint32_t da0 = lds_addr(&ring[wv][p % RP][lane]), da1 = lds_addr(&ring[wv][(p + 1) % RP][lane]);
+            u4v mk[2], mp[2], my0[2], my1[2] = {u4v{0u, 0u, 0u, 0u}, u4v{0u, 0u, 0u, 0u}};
+            d2v dd[2];
+            if constexpr (NR == 2) {
+                asm volatile("ds_read_b128 %0, %10\n\t"
+                             "ds_read_b128 %1, %10 offset:16\n\t"
+                             "ds_read_b128 %2, %10 offset:512\n\t"
+                             "ds_read_b128 %3, %10 offset:528\n\t"
+                             "ds_read_b128 %4, %10 offset:1024\n\t"
+                             "ds_read_b128 %5, %10 offset:1040\n\t"
+                             "ds_read_b128 %6, %10 offset:1536\n\t"
+                             "ds_read_b128 %7, %10 offset:1552\n\t"
+                             "ds_read2_b64 %8, %11 offset1:64\n\t"
+                             "ds_read2_b64 %9, %12 offset1:64\n\t"
+                             "s_waitcnt lgkmcnt(0)"
+                             : "=&v"(mk[0]), "=&v"(mk[1]), "=&v"(mp[0]), "=&v"(mp[1]), "=&v"(my0[0]), "=&v"(my0[1]),
+                               "=&v"(my1[0]), "=&v"(my1[1]), "=&v"(dd[0]), "=&v"(dd[1])
+                             : "v"(maddr), "v"(da0), "v"(da1)
+                             : "memory");
+            } else {
+                asm volatile("ds_read_b128 %0, %8\n\t"
+                             "ds_read_b128 %1, %8 offset:16\n\t"
+                             "ds_read_b128 %2, %8 offset:512\n\t"
+                             "ds_read_b128 %3, %8 offset:528\n\t"
+                             "ds_read_b128 %4, %8 offset:1024\n\t"
+                             "ds_read_b128 %5, %8 offset:1040\n\t"
+                             "ds_read2_b64 %6, %9 offset1:64\n\t"
+                             "ds_read2_b64 %7, %10 offset1:64\n\t"
+                             "s_waitcnt lgkmcnt(0)"
+                             : "=&v"(mk[0]), "=&v"(mk[1]), "=&v"(mp[0]), "=&v"(mp[1]), "=&v"(my0[0]), "=&v"(my0[1]),
+                               "=&v"(dd[0]), "=&v"(dd[1])
+                             : "v"(maddr), "v"(da0), "v"(da1)
+                             : "memory");
+            }
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int64_t j = 2 * p + e;
+                if (j < nr) {
+                    const int h2 = e >> 1, e2 = e & 1;
+                    const uint64_t key = ((uint64_t)mk[h2][2 * e2 + 1] << 32) | mk[h2][2 * e2];
+                    const uint32_t al = uniform_u32((uint32_t)key), be = uniform_u32((uint32_t)(key >> 32));
+                    if (!run || be != cur) {
+                        if (run) {
+#pragma unroll
+                            for (int k = 0; k < NA; ++k) {
+                                const double bk = bit_d(cur, k);
+#pragma unroll
+                                for (int q = 0; q < NR; ++q) wb[q][k] = fma(bk, sb[q], wb[q][k]);
+                            }
+#pragma unroll
+                            for (int q = 0; q < NR; ++q) {
+                                bp[q] += sb[q];
+                                sb[q] = 0.0;
+                            }
+                        }
+                        cur = be;
+                        run = true;
+                    }
+                    const double ps = u2d(mp[h2], e2);
+                    const double d = dd[h2][e2];
+                    double c[NR], tq[NR];
+#pragma unroll
+                    for (int q = 0; q < NR; ++q) {
+                        c[q] = fma(-coef, ps, u2d(q == 0 ? my0[h2] : my1[h2], e2));
+                        tq[q] = c[q] * d;
+                        sb[q] += tq[q];
+                    }
+#pragma unroll
+                    for (int k = 0; k < NA; ++k) {
+                        const double bk = bit_d(al, k);
+#pragma unroll
+                        for (int q = 0; q < NR; ++q) wa[q][k] = fma(bk, tq[q], wa[q][k]);
+                    }
+                    if (wv == 0) {
+                        const uint32_t bits = lane < n ? al : be;
+                        const int sh = lane < n ? lane : lane - n;
+                        const bool on = lane < V && ((bits >> (sh & 31)) & 1u);
+#pragma unroll
+                        for (int q = 0; q < NR; ++q) {
+                            ax[q] += on ? c[q] : 0.0;
+                            a0[q] = fma(c[q], ps, a0[q]);
+                        }
+                    }
+                }
+            }
+            // the pairs' LDS reads have completed (above) before their slots take pairs
+            // p + RP and p + RP + 1
+            dma_pair(p + RP);
+            dma_pair(p + RP + 1);
+        }
+        // the loads still in flight write LDS only; wait for them before the
+        // workgroup ends
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    }
+    if (run) {
+#pragma unroll
+        for (int k = 0; k < NA; ++k) {
+            const double bk = bit_d(cur, k);
+#pragma unroll
+            for (int q = 0; q < NR; ++q) wb[q][k] = fma(bk, sb[q], wb[q][k]);
+        }
+#pragma unroll
+        for (int q = 0; q < NR; ++q) bp[q] += sb[q];
+    }
+    const int64_t P1 = (int64_t)V * H + H + V + 1;
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+        double *out = part + ((int64_t)blockIdx.x * 2 + (NR == 2 ? q : half)) * ldv;
+        if (t < H) {
+            double *wrow = out + 1 + V + H + (int64_t)t * V;
+#pragma unroll
+            for (int k = 0; k < NA; ++k)
+                if (k < n) {
+                    wrow[k] = wa[q][k];
+                    wrow[n + k] = wb[q][k];
+                }
+            out[1 + V + t] = bp[q];
+        }
+        if (wv == 0) {
+            if (lane < V) out[1 + lane] = ax[q];
+            if (lane == 0) out[0] = a0[q];
+            for (int64_t col = P1 + lane; col < ldv; col += 64) out[col] = 0.0;
+        }
+    }
+}
+
 // the vector-unit forms apply to these rows: not the full-space kernels, n <= 24,
 // 48 <= H <= 256
 bool fac_bits_ok(const irl_system *s, int H)
@@ -1184,6 +1425,15 @@ static void launch_bits_na(const BitsArgs &B, int nblk, const double *y0, const 
                            double *part, int64_t ldv, int half, hipStream_t st)
 {
     const unsigned threads = (unsigned)(64 * ((B.H + 63) / 64));
+#ifndef IRL_FAC_NO_RING
+    if (B.H % 64 == 0) {
+        if (y1)
+            k_fac_vjp_ring<2, NA><<<nblk, threads, 0, st>>>(B, y0, y1, coefp, part, ldv, nblk, 0);
+        else
+            k_fac_vjp_ring<1, NA><<<nblk, threads, 0, st>>>(B, y0, nullptr, coefp, part, ldv, nblk, half);
+        return;
+    }
+#endif
     if (y1)
         k_fac_vjp_bits<2, NA><<<nblk, threads, 0, st>>>(B, y0, y1, coefp, part, ldv, nblk, 0);
     else
