@@ -503,6 +503,7 @@ def run_serving_bench(args):
     dE = [abs(a.E_after - b_.E_after) for a, b_ in zip(served, seq) if np.isfinite(a.E_after)]
     for p in pools64.values():
         p.close()
+    foot = footprint_leg(args)
     out = {
         "metric": METRIC,
         "value": n_req / makespan,
@@ -525,8 +526,63 @@ def run_serving_bench(args):
                             "latency_ms": lat64},
         "mix_equals_alone": {"checked": checked, "bitwise_equal": equal},
         "max_abs_dE_after_served_vs_fp64_dense": float(max(dE)) if dE else None,
+        "footprint_admission": foot,
     }
     print(json.dumps(out), flush=True)
+
+
+def footprint_leg(args):
+    """Admission by footprint: requests of classes that no pool holds in advance
+    (random full spaces of 6 to 12 orbitals and selected sets of 2^12 to 2^17
+    determinants of 16 to 20 orbitals, hidden widths 16 to 128; FP64 through the
+    factored Jacobian, stored rows for the selected sets), Poisson arrivals 40/s for
+    args.serve_seconds / 2, admitted whenever their slot's bytes fit a 3 GiB budget (about two
+    of the largest classes, so slots are evicted and requests wait)."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2601_01437_amd import binding as B
+    from paper_2601_01437_amd.serving import ClassSpec, FootprintServer, Request, latency_summary
+
+    rng = np.random.default_rng(7)
+    specs = []
+    for i in range(10):
+        if i % 2 == 0:
+            n = int(rng.integers(6, 13))
+            na = nb = n // 2
+            dets = None
+        else:
+            n = int(rng.integers(16, 21))
+            na = nb = n // 2
+            dets = synth.cisd_like_selected_set(n, na, nb, int(2 ** rng.integers(12, 18)), seed=100 + i)
+        H = int(2 ** rng.integers(4, 8))
+        h, g = synth.integrals(n, 100 + i)
+        specs.append(ClassSpec(f"f{i}", n, na, nb, 2 * n, H, h, g, dets=dets, m=20, k_keep=1,
+                               precision=B.IRL_FP64, slots=1, store_rows_bytes=(8 << 30) if dets is not None else 0,
+                               factored=True))
+    rate, secs = 40.0, max(args.serve_seconds / 2, 2.0)
+    n_req = int(rate * secs)
+    arr = np.cumsum(rng.exponential(1 / rate, size=n_req))
+    picks = rng.integers(0, len(specs), size=n_req)
+    reqs = [Request(i, specs[p].name, float(arr[i]), synth.nqs_theta(specs[p].V, specs[p].H, 2000 + i, scale=0.1),
+                    spec=specs[p]) for i, p in enumerate(picks)]
+    budget = 3 << 30
+    srv = FootprintServer(budget, lanes=4, max_batch=8)
+    try:
+        makespan = srv.run(reqs)
+        adm = srv.adm
+        stats = {"created": adm.created, "evicted": adm.evicted, "reused": adm.reused,
+                 "peak_bytes": adm.peak, "budget_bytes": budget}
+    finally:
+        srv.close()
+    torch.cuda.empty_cache()
+    lat = latency_summary(reqs)
+    log(f"footprint admission: {n_req} requests of {len(specs)} classes in {makespan:.1f} s, "
+        f"p50 {lat['p50_ms']:.1f} ms, p99 {lat['p99_ms']:.1f} ms, {stats}")
+    return {"requests": n_req, "classes": len(specs), "rate_per_s": rate, "makespan_s": makespan,
+            "solves_per_s": n_req / makespan, "latency_ms": lat, **stats,
+            "ok": sum(1 for r in reqs if r.status in (0, 2))}
 
 
 def run_ablation_bench(args):
