@@ -81,10 +81,10 @@ def fac_full_kernel(kind, info, rows, H):
 
 def stored_alg_bytes(info, ns):
     """Algorithmic HBM bytes of one stored-row apply: every off-diagonal element's
-    value and target once, plus w, the diagonal and u.  The systems timed here are
-    created without IRL_SYS_STORE_SLICED, so sets above 2^18 rows take the sliced
-    layout and the others the L2-blocked one."""
-    per_elem = 10 if ns > (1 << 18) else 12
+    value and target once, plus w, the diagonal and u.  The systems timed here take
+    the default layout: LDS-sliced (16-bit targets) up to 256 slices of 2^14 rows,
+    L2-blocked (32-bit targets) beyond."""
+    per_elem = 10 if ns <= 256 * (1 << 14) else 12
     return info.stored_elements * per_elem + 3 * 8 * ns
 
 
@@ -279,7 +279,8 @@ def run_batch_bench(args):
     systems, thetas0 = [], []
     for w in wls:
         h, g = w.integrals()
-        systems.append(System(w.n, w.na, w.nb, h, g, dets=w.dets()))
+        systems.append(System(w.n, w.na, w.nb, h, g, dets=w.dets(),
+                              flags=B.IRL_SYS_STORE_BLOCKS if args.store_blocks else 0))
         thetas0.append(torch.tensor(w.theta(), dtype=torch.float64, device="cuda"))
     fl = B.IRL_WS_FACTORED if args.jacobian == "factored" else B.IRL_WS_FP64
     sizes = [B.irl_workspace_query(s.handle, w.P + 1, fl) for s, w in zip(systems, wls)]
@@ -1058,6 +1059,8 @@ def main():
     ap.add_argument("--precision", default=None, choices=["fp64", "fp32"],
                     help="operator precision (default: the workload's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--store-blocks", action="store_true",
+                    help="c4: store the selected sets' rows in the L2-blocked layout")
     ap.add_argument("--jacobian", default="factored", choices=["dense", "factored"],
                     help="FP64 operator: products with the factored Jacobian of the network "
                          "(default) or streams of the dense D~")

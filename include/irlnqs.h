@@ -129,9 +129,12 @@ enum irl_system_flags {
                                     that would otherwise take the beta-blocked kernel) */
     IRL_SYS_FORCE_PULL = 2u,     /* full space: per-determinant kernel with string-rank
                                     lookup instead of the string-product kernel */
-    IRL_SYS_STORE_SLICED = 4u    /* irl_system_store_hamiltonian uses the LDS-sliced
-                                    layout for any set size (by default only sets of
-                                    more than 2^18 determinants do) */
+    IRL_SYS_STORE_SLICED = 4u,   /* irl_system_store_hamiltonian uses the LDS-sliced
+                                    layout (the default for sets of at most 256
+                                    slices of 2^14 determinants) */
+    IRL_SYS_STORE_BLOCKS = 8u    /* irl_system_store_hamiltonian uses the L2-blocked
+                                    layout at any set size (the default only beyond
+                                    256 slices) */
 };
 
 typedef struct irl_system irl_system;
@@ -234,14 +237,15 @@ int irl_system_info_get(const irl_system *sys, irl_system_info *out);
 
 /* Store the off-diagonal elements of H inside the set (Methods, "Wave Function
  * Ansatz": the second-quantised electronic Hamiltonian, whose elements between
- * determinants follow from the Slater-Condon rules) as
- * compressed rows split into column blocks.  Sets of up to 2^18 determinants:
- * the targets of block b are rows [b 2^s, (b + 1) 2^s), a slice of the amplitude
- * vector of about 2 MiB (at most 8 blocks), so the gathers of one block stay in
- * the L2 cache; layout: row offsets int64[blocks][n_dets + 1] (block-major),
- * targets int32[nnz], values FP64[nnz]; bytes_needed = blocks * (n_dets + 1) * 8
- * + nnz * 12.  Larger sets (or IRL_SYS_STORE_SLICED): slices of 2^14 target rows,
- * whose 128 KiB of amplitudes one workgroup stages in LDS, at most 256 slices.
+ * determinants follow from the Slater-Condon rules) in one of two layouts.
+ * L2-blocked (IRL_SYS_STORE_BLOCKS, or sets of more than 256 slices): compressed
+ * rows split into column blocks; the targets of block b are rows [b 2^s,
+ * (b + 1) 2^s), a slice of the amplitude vector of about 2 MiB (at most 8
+ * blocks, wider for larger sets), so the gathers of one block stay in the L2
+ * cache; layout: row offsets int64[blocks][n_dets + 1] (block-major), targets
+ * int32[nnz], values FP64[nnz]; bytes_needed = blocks * (n_dets + 1) * 8 + nnz *
+ * 12.  LDS-sliced (the default): slices of 2^14 target rows, whose 128 KiB of
+ * amplitudes one workgroup stages in LDS, at most 256 slices.
  * Inside a slice the rows are taken in windows of 4096; a window's rows are
  * ordered by their number of elements in the slice (descending, ties by row)
  * and grouped 64 at a time, one row per lane of a wavefront; a group stores

@@ -32,6 +32,7 @@ IRL_STEP_GRAPH = 32
 IRL_SYS_FORCE_HASH = 1
 IRL_SYS_FORCE_PULL = 2
 IRL_SYS_STORE_SLICED = 4
+IRL_SYS_STORE_BLOCKS = 8
 STAT_KINDS = ("dtilde_build", "ham_apply", "gemv", "gemv_t", "reduce", "energy", "lanczos", "ritz",
               "gemv_fp32", "gemv_t_fp32", "vmc")
 

@@ -941,8 +941,8 @@ size_t sliced_bytes(int scb, int64_t ns, int64_t slots)
            (size_t)scb * ns * 8;
 }
 
-// Stored rows in the LDS-sliced layout (sets of at least kSlicedMinRows rows, or
-// IRL_SYS_STORE_SLICED): count the connections of every row per slice, order each
+// Stored rows in the LDS-sliced layout (every set of at most kMaxSlices slices unless
+// IRL_SYS_STORE_BLOCKS): count the connections of every row per slice, order each
 // window's rows by count (descending, ties by row) and group them 64 at a time
 // (host), then fill the slots.
 int store_sliced(irl_system *s, size_t max_bytes, size_t *bytes_needed, hipStream_t st)
@@ -1076,8 +1076,7 @@ int irl_system_store_hamiltonian(irl_system *s, size_t max_bytes, size_t *bytes_
                                      : (size_t)s->d.hcb * (ns + 1) * 8 + (size_t)s->d.hnnz * 12;
         return IRL_OK;
     }
-    if ((ns >= kSlicedMinRows || (s->sys_flags & IRL_SYS_STORE_SLICED)) &&
-        ((ns + ((int64_t)1 << kSliceLog) - 1) >> kSliceLog) <= kMaxSlices)
+    if (!(s->sys_flags & IRL_SYS_STORE_BLOCKS) && ((ns + ((int64_t)1 << kSliceLog) - 1) >> kSliceLog) <= kMaxSlices)
         return store_sliced(s, max_bytes, bytes_needed, (hipStream_t)stream);
     // column blocks: slices of w of about kColSliceBytes, a power of two rows wide
     int hcs = 0;

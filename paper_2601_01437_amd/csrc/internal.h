@@ -278,7 +278,6 @@ void *noalloc_scratch(int device);
 constexpr int kSliceLog = IRL_SLICE_LOG; // 2^14 target rows (128 KiB of w) per slice
 constexpr int kMaxSlices = 256;          // sets of up to 2^22 determinants
 constexpr int kSellWindow = 4096;        // rows ordered by length together
-constexpr int64_t kSlicedMinRows = ((int64_t)1 << 18) + 1;   // up to 2^18 rows: the L2-block layout
 hipError_t launch_ham_count_sliced(const irl_system *s, int scs, int scb, uint32_t *count, hipStream_t st);
 hipError_t launch_ham_fill_sliced(const irl_system *s, int scs, int scb, const uint32_t *slot, uint16_t *scol,
                                   double *sval, hipStream_t st);

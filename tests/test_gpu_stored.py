@@ -42,10 +42,13 @@ CASES = [  # (n, na, nb, selected count or None, seed, system flags)
 
 @pytest.mark.parametrize("n,na,nb,count,seed,flags", CASES)
 def test_stored_rows_count_and_apply(n, na, nb, count, seed, flags):
+    """L2-blocked layout (IRL_SYS_STORE_BLOCKS): the byte size is exact and the
+    apply matches the oracle."""
+    from paper_2601_01437_amd import IRL_SYS_STORE_BLOCKS
     announce(f"stored rows n={n} count={count} flags={flags}")
     keys = (space.full_space(n, na, nb) if count is None
             else synth.cisd_like_selected_set(n, na, nb, count, seed=seed))
-    s, h, g = _system(n, na, nb, seed, None if count is None else keys, flags)
+    s, h, g = _system(n, na, nb, seed, None if count is None else keys, flags | IRL_SYS_STORE_BLOCKS)
     Href = capply.csr(n, h, g, keys)
     nnz_off = Href.nnz - keys.size        # the oracle emits the diagonal once per row
     stored, need = s.store_hamiltonian(1 << 40)
@@ -79,8 +82,8 @@ SLICED_CASES = [  # (n, na, nb, selected count or None, seed, system flags)
 
 @pytest.mark.parametrize("n,na,nb,count,seed,flags", SLICED_CASES)
 def test_stored_rows_lds_slices_count_and_apply(n, na, nb, count, seed, flags):
-    """LDS-sliced layout (slices of 2^14 target rows, forced by
-    IRL_SYS_STORE_SLICED on sets this small): the number of stored elements must
+    """LDS-sliced layout (slices of 2^14 target rows, the default; also requested
+    with IRL_SYS_STORE_SLICED): the number of stored elements must
     equal the oracle's number of connections inside the set (the byte size then
     counts the padded slots of the 64-row groups);
     the apply matches the oracle to FP64 rounding, repeats bitwise, and a second
@@ -113,7 +116,7 @@ def test_stored_rows_lds_slices_count_and_apply(n, na, nb, count, seed, flags):
 @pytest.mark.timeout(600)
 @pytest.mark.parametrize("count", [300000, (1 << 18) + 1])
 def test_stored_rows_lds_slices_large(count):
-    """Sets above 2^18 determinants take the LDS-sliced layout by default: 300,000
+    """Sets above 2^18 determinants (the old L2-block range) in the LDS-sliced layout: 300,000
     rows give 19 slices (the last ragged), 2^18 + 1 rows 17 (the last holds one
     row).  The apply equals the enumerating kernel of the same system (pinned to
     the oracle) to FP64 rounding and the oracle's rows on a sample, and is
@@ -143,11 +146,13 @@ def test_stored_rows_lds_slices_large(count):
 
 
 def test_stored_rows_largest_l2_block_set():
-    """2^18 determinants exactly (the largest set of the L2-block layout): one
-    column block of 2^18 target rows; apply against the enumerating kernel."""
+    """2^18 determinants exactly (the largest set of one 2 MiB column block in the
+    L2-blocked layout): one column block of 2^18 target rows; apply against the
+    enumerating kernel."""
+    from paper_2601_01437_amd import IRL_SYS_STORE_BLOCKS
     announce("stored rows: L2 column block at 2^18 rows")
     keys = synth.cisd_like_selected_set(14, 7, 7, 1 << 18, seed=3)
-    s, _, _ = _system(14, 7, 7, 3, keys)
+    s, _, _ = _system(14, 7, 7, 3, keys, IRL_SYS_STORE_BLOCKS)
     w = dev(np.random.default_rng(7).normal(size=keys.size))
     u_enum = host(s.apply_hamiltonian(w))
     stored, need = s.store_hamiltonian(1 << 40)
