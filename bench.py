@@ -1022,6 +1022,35 @@ def full_space_secondary(args, B, synth, System, torch):
             "applies_per_step": applies / args.steps, "kernel_ms_avg": kern}
 
 
+def warm_start_leg(args, B, sysm, wl, theta, theta0, precision, step_flags, ws_flags, cold, torch):
+    """The timed steps again from theta0 with each Lanczos process after the first
+    started at the previous step's Ritz vector (IRL_STEP_WARM_START, an option:
+    Algorithm 1 and the headline steps start from a random unit vector).  Reports
+    the rate, the applies and the largest energy and eigenvalue differences from
+    the cold-started trajectory; theta is left as the timed steps left it."""
+    if args.block > 1 or not cold:
+        return None
+    theta_end = theta.clone()
+    theta.copy_(theta0)
+    rows = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        flags = step_flags | (B.IRL_STEP_WARM_START if i else 0)
+        rc, r, _, _ = sysm.step(theta, wl.V, wl.H, m=wl.m, k_keep=wl.k, tol=1e-12, precision=precision,
+                                flags=flags, ws_flags=ws_flags, want_dtheta=False)
+        rows.append((r.E_before, r.lambda_min, r.n_apply, r.converged))
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    theta.copy_(theta_end)
+    log(f"warm start: {ms:.1f} ms per step, applies {[a for _, _, a, _ in rows]}")
+    return {"value": 1000.0 / ms, "unit": "IRL steps/s", "ms_per_step": ms,
+            "applies_per_step": sum(a for _, _, a, _ in rows) / len(rows),
+            "all_converged": all(c == 1 for _, _, _, c in rows),
+            "max_abs_dE_vs_cold": max(abs(e - c["E"]) for (e, _, _, _), c in zip(rows, cold)),
+            "max_abs_dlambda_vs_cold": max(abs(l - c["lambda_min"]) for (_, l, _, _), c in zip(rows, cold))}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -1225,6 +1254,7 @@ def main():
     applies = sum(s["applies"] for s in steps)
     # final energy after the last update
     Zf, Ef, _ = sysm.evaluate(wl.V, wl.H, theta, ws_flags=ws_flags, want_grad=False)
+    warm_leg = warm_start_leg(args, B, sysm, wl, theta, theta0, precision, step_flags, ws_flags, steps, torch)
 
     # dominant kernel and its roofline (every kernel kind's beside it)
     kern = {k: {"ms_total": v[0], "launches": v[1], "ms_avg": v[0] / v[1] if v[1] else None,
@@ -1369,6 +1399,7 @@ def main():
         "full_space_12_orbitals": full_space,
         "trajectory": steps,
         "E_final": Ef,
+        "warm_start": warm_leg,
     }
     print(json.dumps(out), flush=True)
 

@@ -109,7 +109,7 @@ enum irl_step_flags {
     IRL_STEP_NO_POLISH = 8u,     /* FP32 solve: skip the FP64 polish (see irl_step) */
     IRL_STEP_FULL_CYCLES = 16u,  /* test convergence only at the end of each m-step cycle
                                     (no early Ritz tests inside a cycle) */
-    IRL_STEP_GRAPH = 32u         /* single-vector solves that test only at the end of a
+    IRL_STEP_GRAPH = 32u,        /* single-vector solves that test only at the end of a
                                     cycle (operators under 256 MB per apply, or
                                     IRL_STEP_FULL_CYCLES): capture each cycle kind (the
                                     first, a restart from either basis) once as a HIP
@@ -120,6 +120,17 @@ enum irl_step_flags {
                                     Hamiltonian and sampling state, and rebuilt when any
                                     changes; ignored while per-kernel timing is on; a
                                     capture that fails falls back to launches. */
+    IRL_STEP_WARM_START = 64u    /* single-vector solves: start the Lanczos process from
+                                    the Ritz vector of this system's previous converged
+                                    solve in the same workspace, with the same dimension,
+                                    layout and mode (in an optimisation loop, the last
+                                    step's eigenvector), instead of the seeded random
+                                    vector; otherwise the random vector.  Every converged
+                                    single-vector solve keeps a copy of its Ritz vector in the workspace
+                                    for this (ncols doubles); any other system that
+                                    steps in the same workspace in between overwrites it,
+                                    which changes only the start.  The converged pair
+                                    meets the same tolerances either way. */
 };
 
 /* K4 variant selection (irl_system_desc.flags) */

@@ -29,6 +29,7 @@ IRL_WS_FP64, IRL_WS_FP32, IRL_WS_BLOCK, IRL_WS_FACTORED, IRL_WS_SAMPLED = 1, 2, 
 IRL_STEP_WS_CURRENT, IRL_STEP_NO_EVAL_AFTER, IRL_STEP_NO_UPDATE, IRL_STEP_NO_POLISH = 1, 2, 4, 8
 IRL_STEP_FULL_CYCLES = 16
 IRL_STEP_GRAPH = 32
+IRL_STEP_WARM_START = 64
 IRL_SYS_FORCE_HASH = 1
 IRL_SYS_FORCE_PULL = 2
 IRL_SYS_STORE_SLICED = 4

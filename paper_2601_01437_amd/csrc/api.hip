@@ -340,6 +340,7 @@ WsLayout make_layout(int64_t ns, int64_t ncols, uint32_t flags, int V, int64_t f
     L.off_fac = take((flags & IRL_WS_FACTORED) ? (size_t)ns * (size_t)L.hfac * 8 : 0);
     L.off_sig = take((size_t)ld * 8);
     L.off_q = take((size_t)ns * 8);
+    L.off_warm = take((size_t)ld * 8);
     const bool gather = (flags & IRL_WS_SAMPLED) && (flags & IRL_WS_FACTORED) && L.hfac > 0;
     L.off_ckeys = take(gather ? (size_t)ns * 8 : 0);
     L.off_cpsi = take(gather ? (size_t)ns * 8 : 0);
@@ -1418,8 +1419,15 @@ int irl_step(irl_system *s, irl_nqs_desc *nqs, const irl_solver_opts *opts, void
 
     // ---- implicitly restarted Lanczos ----
     SolveOut so;
+    // warm start: the copy of the last converged Ritz vector, kept in its own
+    // region because the evaluation at the start of a step reuses y
+    const double *start = nullptr;
+    if ((o.flags & IRL_STEP_WARM_START) && o.block <= 1 && s->warm_ws == ws && s->warm_ncols == L.ncols &&
+        s->warm_off == L.off_warm && s->warm_mode == o.mode)
+        start = ws_ptr<double>(ws, L.off_warm);
+    s->warm_ws = nullptr;
     rc = o.block > 1 ? irl_solve_block(s, ws, L, o, o.precision, so, st)
-                     : irl_solve(s, ws, L, o, o.precision, nullptr, so, st);
+                     : irl_solve(s, ws, L, o, o.precision, start, so, st);
     if (rc) return rc;
     const int n_apply_lo = o.precision == IRL_FP32 ? so.n_apply : 0;
     if (o.precision == IRL_FP32 && s->ws_has64 && !(o.flags & IRL_STEP_NO_POLISH)) {
@@ -1433,6 +1441,13 @@ int irl_step(irl_system *s, irl_nqs_desc *nqs, const irl_solver_opts *opts, void
         so = sp;
     }
     double *y = ws_ptr<double>(ws, L.off_y);
+    if (o.block <= 1 && so.converged) {
+        CK(s, hipMemcpyAsync(ws_ptr<double>(ws, L.off_warm), y, L.ldv * 8, hipMemcpyDeviceToDevice, st));
+        s->warm_ws = ws;
+        s->warm_ncols = L.ncols;
+        s->warm_off = L.off_warm;
+        s->warm_mode = o.mode;
+    }
     res.lambda_min = so.lam;
     res.residual_est = so.resid_est;
     res.residual_explicit = so.resid_explicit;

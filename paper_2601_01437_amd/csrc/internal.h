@@ -67,6 +67,7 @@ struct WsLayout {
            off_fac = 0,                              // factored Jacobian d = 1 - t^2 (N_s x hfac)
            off_sig = 0,                              // D~^T psi (connected basis, mode C)
            off_q = 0,                                // sampled row weights Z c_r / (N psi_r^2)
+           off_warm = 0,                             // Ritz vector of the last converged solve
            // drawn rows gathered contiguously (IRL_WS_SAMPLED with the factored Jacobian)
            off_ckeys = 0, off_cpsi = 0, off_cq = 0, off_cel = 0, off_crow = 0, off_cfac = 0;
     int hfac = 0;                                    // hidden units of the factored Jacobian
@@ -231,6 +232,12 @@ struct irl_system {
     bool ws_valid = false;
     bool ws_has64 = false, ws_has32 = false;
     double Z = 0.0, E_el = 0.0;   // host copies after the last evaluation
+    // the last converged single-vector solve (IRL_STEP_WARM_START): its workspace,
+    // dimension, mode and the offset of the copy of its Ritz vector in that workspace
+    void *warm_ws = nullptr;
+    int64_t warm_ncols = 0;
+    size_t warm_off = 0;
+    int warm_mode = -1;
     // sampled estimators (irl_vmc_sample) replace the exact ones until the next evaluation
     bool vmc = false;
     double E_exact = 0.0;

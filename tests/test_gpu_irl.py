@@ -166,3 +166,62 @@ def test_trajectory_c1_matches_oracle(c1_problem, block):
         assert abs(r.lambda_min - lams[t]) <= 1e-9 * max(1.0, abs(lams[t])), t
         assert abs(r.E_after - energies[t + 1]) <= 1e-9, t
     assert rel_err(host(theta), thetas[-1]) <= 1e-8
+
+
+def test_warm_start_trajectory_c1(c1_problem):
+    """IRL_STEP_WARM_START: four optimisation steps that start each Lanczos
+    process from the previous step's Ritz vector follow the oracle's trajectory
+    to the tolerances of the cold-started trajectory, and need no more operator
+    applies than the cold start.  The Krylov space (m = 8, 3 kept) is small
+    enough that a cold solve restarts; a solve repeated on the same operator
+    (theta not updated) starts at its own converged eigenvector, so it converges
+    in its first cycle with the same eigenvalue; a block solve in between, or a
+    change of mode, drops the saved vector (a cold start again, bit for bit)."""
+    from paper_2601_01437_amd import (IRL_MODE_P, IRL_STEP_NO_UPDATE, IRL_STEP_WARM_START, IRL_WS_BLOCK,
+                                      IRL_WS_FP64)
+    announce("warm-start trajectory c1")
+    p = c1_problem
+    w = p["w"]
+    energies, lams, thetas = step.trajectory(p["keys"], w.n, w.V, w.H, p["theta"], p["H"], steps=4)
+    applies = {}
+    for warm in (False, True):
+        s, _, _ = make_system(8, 4, 4)
+        theta = dev(p["theta"])
+        fl = IRL_STEP_WARM_START if warm else 0
+        applies[warm] = []
+        for t in range(4):
+            rc, r, _, _ = s.step(theta, w.V, w.H, m=8, k_keep=3, ws_flags=IRL_WS_FP64, flags=fl)
+            assert r.converged == 1
+            assert abs(r.E_before - energies[t]) <= (1e-12 if t == 0 else 1e-9), (warm, t)
+            assert abs(r.lambda_min - lams[t]) <= 1e-9 * max(1.0, abs(lams[t])), (warm, t)
+            assert abs(r.E_after - energies[t + 1]) <= 1e-9, (warm, t)
+            applies[warm].append(r.n_apply)
+        assert rel_err(host(theta), thetas[-1]) <= 1e-8
+    print("applies cold", applies[False], "warm", applies[True])
+    assert applies[True][0] == applies[False][0]
+    assert sum(applies[True][1:]) <= sum(applies[False][1:])
+
+    # the same operator twice: the second solve starts at the first's eigenvector
+    s, _, _ = make_system(8, 4, 4)
+    theta = dev(p["theta"])
+    kw = dict(m=8, k_keep=3, ws_flags=IRL_WS_FP64 | IRL_WS_BLOCK)
+    _, r0, d0, _ = s.step(theta, w.V, w.H, flags=IRL_STEP_NO_UPDATE | IRL_STEP_WARM_START, **kw)
+    _, r1, d1, _ = s.step(theta, w.V, w.H, flags=IRL_STEP_NO_UPDATE | IRL_STEP_WARM_START, **kw)
+    print("cold", r0.n_apply, r0.n_restart, "repeated warm", r1.n_apply, r1.n_restart)
+    assert r0.converged == 1 and r0.n_restart > 0
+    assert r1.converged == 1 and r1.n_restart == 0
+    assert r1.n_apply < r0.n_apply
+    assert abs(r1.lambda_min - r0.lambda_min) <= 1e-10 * max(abs(r0.lambda_min), r0.norm_T)
+    assert rel_err(host(d1), host(d0)) <= 1e-8
+    # a block solve, then a mode change, each drop the saved vector: cold start bit for bit
+    _, rb, _, _ = s.step(theta, w.V, w.H, flags=IRL_STEP_NO_UPDATE | IRL_STEP_WARM_START, block=4, m=20,
+                         k_keep=4, ws_flags=kw["ws_flags"])
+    assert rb.converged == 1
+    _, r2, d2, _ = s.step(theta, w.V, w.H, flags=IRL_STEP_NO_UPDATE | IRL_STEP_WARM_START, **kw)
+    assert r2.n_apply == r0.n_apply and r2.lambda_min == r0.lambda_min
+    assert np.array_equal(host(d2), host(d0))
+    _, rp, _, _ = s.step(theta, w.V, w.H, flags=IRL_STEP_NO_UPDATE | IRL_STEP_WARM_START, mode=IRL_MODE_P,
+                         **kw)
+    _, r3, d3, _ = s.step(theta, w.V, w.H, flags=IRL_STEP_NO_UPDATE | IRL_STEP_WARM_START, **kw)
+    assert r3.n_apply == r0.n_apply and r3.lambda_min == r0.lambda_min
+    assert np.array_equal(host(d3), host(d0))
