@@ -940,12 +940,14 @@ def fp32_operator_comparison(args, B, sysm, wl, theta0, first64, torch):
     copy of D~ (FP32 products, FP32 accumulation inside a row block), FP64 energy,
     gradient, Lanczos and QR; without and with the FP64 polish of the Ritz pair
     (the polish restarts the FP64 factored solve from the FP32 Ritz vector, so the
-    step then meets the FP64 tolerances).  Each variant runs K steps from theta_0;
-    the first step's eigenvalue and energy after the update are compared with the
-    FP64 path's."""
+    step then meets the FP64 tolerances); and the plain FP64 form, which streams an
+    FP64 copy of D~ (twice the FP32 copy's bytes).  Each variant runs K steps from
+    theta_0; the first step's eigenvalue and energy after the update are compared
+    with the factored FP64 path's."""
     out = {}
-    for name, fl, flags in (("fp32", B.IRL_WS_FP32, B.IRL_STEP_NO_POLISH),
-                            ("fp32_polished", B.IRL_WS_FP32 | B.IRL_WS_FACTORED, 0)):
+    for name, fl, prec, flags in (("fp32", B.IRL_WS_FP32, B.IRL_FP32, B.IRL_STEP_NO_POLISH),
+                                  ("fp32_polished", B.IRL_WS_FP32 | B.IRL_WS_FACTORED, B.IRL_FP32, 0),
+                                  ("fp64_dense", B.IRL_WS_FP64, B.IRL_FP64, 0)):
         sysm.ws = None
         torch.cuda.empty_cache()
         th = theta0.clone()
@@ -955,7 +957,7 @@ def fp32_operator_comparison(args, B, sysm, wl, theta0, first64, torch):
                 th.copy_(theta0)
             torch.cuda.synchronize()
             t = time.perf_counter()
-            rc, r, _, _ = sysm.step(th, wl.V, wl.H, m=wl.m, k_keep=wl.k, tol=1e-12, precision=B.IRL_FP32,
+            rc, r, _, _ = sysm.step(th, wl.V, wl.H, m=wl.m, k_keep=wl.k, tol=1e-12, precision=prec,
                                     flags=flags, ws_flags=fl, want_dtheta=False)
             torch.cuda.synchronize()
             if i >= args.warmup:

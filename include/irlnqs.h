@@ -352,9 +352,11 @@ int irl_apply_lm_operator(irl_system *sys, void *ws, size_t ws_bytes, const doub
  * V: device, nb columns of ncols = P + 1 doubles, column q at V + q * ldv
  * (ldv >= ncols).  YH, YS: device, nb columns at stride ldy >= ncols (entries
  * >= ncols are not written).  Needs a workspace evaluated with IRL_WS_BLOCK.
- * Bytes per call are those of one vector; each column equals
- * irl_apply_lm_operator on that column to rounding (the D~^T partial sums use
- * other row blocks).  Asynchronous on stream.  Errors: IRL_ESTATE, IRL_EINVAL,
+ * With a D~ copy, the D~ bytes per call are those of one vector and each column
+ * equals irl_apply_lm_operator on that column to rounding (the D~^T partial sums
+ * use other row blocks).  FP64 with IRL_WS_FACTORED takes the factored products
+ * one vector at a time, and each column equals irl_apply_lm_operator on it bit
+ * for bit.  Asynchronous on stream.  Errors: IRL_ESTATE, IRL_EINVAL,
  * IRL_ENOMEM, IRL_EDEVICE. */
 int irl_apply_lm_operator_block(irl_system *sys, void *ws, size_t ws_bytes, const double *V, int64_t ldv,
                                 int32_t nb, double *YH, double *YS, int64_t ldy, int32_t precision,

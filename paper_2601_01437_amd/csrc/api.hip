@@ -269,6 +269,17 @@ int apply_internal(irl_system *s, void *ws, const WsLayout &L, const double *v, 
 int apply_block_internal(irl_system *s, void *ws, const WsLayout &L, const double *V, int64_t ldv_in, int nb,
                          double *YH, double *YS, int64_t ldy, int prec, hipStream_t st, int zero_v0 = 0)
 {
+    if (prec == IRL_FP64 && (L.flags & IRL_WS_FACTORED)) {
+        // factored Jacobian: the products read d (H values per row) instead of a
+        // D~ row, and H is applied per vector anyway, so the block is nb
+        // single-vector applies (d read twice per vector)
+        for (int q = 0; q < nb; ++q) {
+            const int rc = apply_internal(s, ws, L, V + (int64_t)q * ldv_in, YH + (int64_t)q * ldy,
+                                          YS + (int64_t)q * ldy, prec, st, zero_v0);
+            if (rc) return rc;
+        }
+        return IRL_OK;
+    }
     double *W = ws_ptr<double>(ws, L.off_w), *U = ws_ptr<double>(ws, L.off_u);
     TIMED(s, prec == IRL_FP64 ? IRL_STAT_GEMV : IRL_STAT_GEMV_LO, st,
           launch_gemv_rows_multi(L, ws, prec, V, ldv_in, nb, zero_v0, W, st));
@@ -669,8 +680,6 @@ int irl_solve_block(irl_system *s, void *ws, const WsLayout &L, const irl_solver
 {
     const int nb = o.block;
     if (!(L.flags & IRL_WS_BLOCK)) return set_err(s, IRL_EINVAL, "block solves need a workspace with IRL_WS_BLOCK");
-    if (prec == IRL_FP64 && !(L.flags & IRL_WS_FP64))
-        return set_err(s, IRL_EINVAL, "block solves stream a D~ copy (IRL_WS_FP64 for FP64)");
     if (nb < 2 || nb > kMaxBlock) return set_err(s, IRL_EINVAL, "block must be in [2, 8]");
     const int64_t dim = (o.mode == IRL_MODE_A) ? L.ncols : L.ncols - 1;
     const int m = (int)std::min<int64_t>(std::min(o.m, kMaxKrylov), dim);
@@ -1357,8 +1366,6 @@ int irl_apply_lm_operator_block(irl_system *s, void *ws, size_t ws_bytes, const 
     if (!V || !YH || !YS || ldv_in < L.ncols || ldy < L.ncols) return set_err(s, IRL_EINVAL, "bad vector arguments");
     int rc = check_prec(s, precision);
     if (rc) return rc;
-    if (precision == IRL_FP64 && !(L.flags & IRL_WS_FP64))
-        return set_err(s, IRL_EINVAL, "multi-vector applies stream a D~ copy (IRL_WS_FP64 for FP64)");
     hipStream_t st = (hipStream_t)stream;
     return apply_block_internal(s, ws, L, V, ldv_in, nb, YH, YS, ldy, precision, st);
 }

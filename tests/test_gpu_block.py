@@ -4,8 +4,9 @@ The multi-vector apply returns, per column, the same raw operator pair as the
 oracle's matrix-free apply (||y - y_ref|| <= 1e-10 ||y_ref||, FP64).  The block
 solve converges to the oracle's lowest eigenpair of the centred matrix with the
 same tolerances as the single-vector step (eigenvalue 1e-10 max(|lambda|,
-||H~'||), energies 1e-12 Ha); the pins that do not depend on the Krylov method
-(D~ = I is exact diagonalisation, an exact psi gives a zero update) hold too."""
+||H~'||), energies 1e-12 Ha), with an FP64 D~ copy and with the factored
+Jacobian; the pins that do not depend on the Krylov method (D~ = I is exact
+diagonalisation, an exact psi gives a zero update) hold too."""
 import json
 import os
 
@@ -25,8 +26,10 @@ def _gpu():
     require_gpu()
 
 
-def _flags(fp32=False):
-    from paper_2601_01437_amd import IRL_WS_BLOCK, IRL_WS_FP32, IRL_WS_FP64
+def _flags(fp32=False, factored=False):
+    from paper_2601_01437_amd import IRL_WS_BLOCK, IRL_WS_FACTORED, IRL_WS_FP32, IRL_WS_FP64
+    if factored:
+        return IRL_WS_FACTORED | IRL_WS_BLOCK
     return IRL_WS_FP64 | IRL_WS_BLOCK | (IRL_WS_FP32 if fp32 else 0)
 
 
@@ -45,14 +48,18 @@ def c1_oracle(c1_problem):
     return Dt, res, th_new, E_after
 
 
+@pytest.mark.parametrize("factored", [False, True])
 @pytest.mark.parametrize("nb", [1, 2, 3, 4, 5, 8])
-def test_multi_vector_apply_c1(c1_problem, c1_oracle, nb):
-    announce(f"multi-vector apply c1 nb={nb}")
+def test_multi_vector_apply_c1(c1_problem, c1_oracle, nb, factored):
+    """Per column: the oracle's operator pair; the single-vector apply to
+    rounding with a D~ copy, bit for bit with the factored Jacobian (whose block
+    apply is one single-vector apply per column)."""
+    announce(f"multi-vector apply c1 nb={nb} factored={factored}")
     p = c1_problem
     w = p["w"]
     Dt = c1_oracle[0]
     s, _, _ = _system(8, 4, 4)
-    s.evaluate(w.V, w.H, dev(p["theta"]), ws_flags=_flags())
+    s.evaluate(w.V, w.H, dev(p["theta"]), ws_flags=_flags(factored=factored))
     V = np.random.default_rng(10 + nb).normal(size=(nb, w.P + 1))
     YH, YS = s.apply_block(dev(V))
     YH, YS = host(YH), host(YS)
@@ -63,6 +70,8 @@ def test_multi_vector_apply_c1(c1_problem, c1_oracle, nb):
         # the same column through the single-vector apply
         y1H, y1S = s.apply(dev(V[q]))
         assert rel_err(YH[q], host(y1H)) <= 1e-13 and rel_err(YS[q], host(y1S)) <= 1e-13
+        if factored:
+            assert np.array_equal(YH[q], host(y1H)) and np.array_equal(YS[q], host(y1S))
 
 
 @pytest.mark.parametrize("nb", [2, 4, 8])
@@ -86,16 +95,17 @@ def test_multi_vector_apply_selected_fp32(nb):
         assert rel_err(host(YH64[q]), host(y1H)) <= 1e-13 and rel_err(host(YS64[q]), host(y1S)) <= 1e-13
 
 
+@pytest.mark.parametrize("factored", [False, True])
 @pytest.mark.parametrize("nb,m,k", [(2, 20, 4), (4, 20, 4), (4, 40, 10), (2, 8, 2), (8, 24, 8)])
-def test_block_step_c1(c1_problem, c1_oracle, nb, m, k):
-    announce(f"block step c1 nb={nb} m={m} k={k}")
+def test_block_step_c1(c1_problem, c1_oracle, nb, m, k, factored):
+    announce(f"block step c1 nb={nb} m={m} k={k} factored={factored}")
     p = c1_problem
     w = p["w"]
     _, res, th_new, E_after = c1_oracle
     s, _, _ = _system(8, 4, 4)
     theta = dev(p["theta"])
     rc, r, dth, ritz = s.step(theta, w.V, w.H, m=m, k_keep=k, want_ritz=True, block=nb,
-                              ws_flags=_flags())
+                              ws_flags=_flags(factored=factored))
     normH = np.linalg.norm(res.Hp, 2)
     announce(f"block nb={nb}: applies {r.n_apply} restarts {r.n_restart} "
              f"dlambda {r.lambda_min - res.lam:.2e}")
@@ -175,17 +185,20 @@ def test_block_invariant_subspace_breakdown():
     assert abs(r.lambda_min - lam_ref) <= 1e-10 * max(1.0, np.abs(np.linalg.eigvalsh(Hp)).max())
 
 
-def test_block_c3s_step_matches_oracle():
-    """2^14-determinant, 20-orbital selected set with P = 10,536, FP64, block 4."""
+@pytest.mark.parametrize("factored", [False, True])
+def test_block_c3s_step_matches_oracle(factored):
+    """2^14-determinant, 20-orbital selected set with P = 10,536, FP64, block 4,
+    with the FP64 D~ copy and with the factored Jacobian."""
     if not os.path.exists(GOLDEN):
         pytest.skip("tests/golden/c3s_step.json not generated")
     from paper_2601_01437_amd import System
-    announce("block c3s step")
+    announce(f"block c3s step factored={factored}")
     G = json.load(open(GOLDEN))
     w = synth.WORKLOADS["c3s"]
     h, g = w.integrals()
     s = System(w.n, w.na, w.nb, h, g, dets=w.dets())
-    rc, r, dth, _ = s.step(dev(w.theta()), w.V, w.H, m=40, k_keep=8, block=4, ws_flags=_flags())
+    rc, r, dth, _ = s.step(dev(w.theta()), w.V, w.H, m=40, k_keep=8, block=4,
+                           ws_flags=_flags(factored=factored))
     announce(f"block c3s: applies {r.n_apply} restarts {r.n_restart}")
     assert r.converged == 1
     assert abs(r.E_before - G["E"]) <= 1e-12
