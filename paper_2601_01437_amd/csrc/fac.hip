@@ -1180,6 +1180,7 @@ typedef __attribute__((address_space(3))) void *lds_ptr_t;
 // or past it return zeros
 constexpr int kBufWord3 = 0x00020000;
 typedef uint32_t u4v __attribute__((ext_vector_type(4)));
+typedef uint32_t u2v __attribute__((vector_size(8)));
 // the LDS byte address of a workgroup-shared object
 __device__ __forceinline__ uint32_t lds_addr(const void *p)
 {
@@ -1402,6 +1403,276 @@ __global__ __launch_bounds__(256) void k_fac_vjp_ring(BitsArgs A, const double *
     }
 }
 
+// ---------------------------------------------------------------------------
+// D~ v on selected sets on the vector units, with the occupation sums read from
+// tables.  Row r needs t_r[h] = v_b[h] + sum over its occupied orbitals of
+// V_W[h][v]; the matrix-core form multiplies the whole 0/1 row of X, half of it
+// zeros, on FP64 matrix cores that are no faster than the vector units on this
+// part.  Here the alpha and the beta orbitals are each split into groups of 4,
+// and for each group and each of its 16 occupation patterns a workgroup tabulates
+// the pattern's sum of V_W[h][v] (orbitals in increasing order) for the 64 hidden
+// units of a chunk in LDS, so t_r is one table read per group.  A workgroup owns
+// a block of rows and walks the hidden chunks in order; each wave owns a
+// contiguous part of the block and walks it in 16-row batches (lane l = hidden
+// unit 64 c + l, one coalesced 512-byte d segment per row), loads the next
+// batch's d, keys and psi while the current one is summed, and forms the 16 row
+// sums of d t with one transposed butterfly.  Chunk 0 adds psi_r v_0 and x_r . v_a
+// (tables of v_a, read at a uniform address); later chunks add to w in chunk
+// order, so the sum is fixed by the launch shape.
+#ifndef IRL_LUT_THREADS
+#define IRL_LUT_THREADS 1024
+#endif
+#ifndef IRL_LUT_BLOCKS
+#define IRL_LUT_BLOCKS 256
+#endif
+constexpr int kLutRB = 16;        // rows per batch (one transposed butterfly)
+constexpr int kLutThreads = IRL_LUT_THREADS;
+constexpr int kLutMaxG = 6;       // groups of 4 orbitals per spin (n <= 24)
+constexpr int kLutBlocks = IRL_LUT_BLOCKS;
+
+// row sums of p[0..16) over the wavefront (p is consumed): on return lane l holds
+// the sum of row (l >> 2) & 15, the same value in the 4 lanes of a row
+__device__ __forceinline__ double rows16_sum(double (&p)[kLutRB], int lane)
+{
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const int o = 32 >> s, half = 8 >> s;
+        // the choice by bit mask: a select between two elements would become an
+        // indexed access and put p in scratch memory
+        const uint64_t m = (lane & o) ? ~0ull : 0ull;
+#pragma unroll
+        for (int k = 0; k < half; ++k) {
+            const uint64_t lo = __builtin_bit_cast(uint64_t, p[k]), hi = __builtin_bit_cast(uint64_t, p[k + half]);
+            const double send = __builtin_bit_cast(double, (lo & m) | (hi & ~m));
+            const double keep = __builtin_bit_cast(double, (hi & m) | (lo & ~m));
+            p[k] = keep + __shfl_xor(send, o, kWave);
+        }
+    }
+    double r = p[0];
+    r += __shfl_xor(r, 1, kWave);
+    r += __shfl_xor(r, 2, kWave);
+    return r;
+}
+
+// tables of one hidden chunk, shared by the workgroup: spin s (0 alpha, 1 beta),
+// group g, pattern p at [s][g][p]
+template <int NG>
+struct LutShared {
+    double lut[2][NG][16][64];   // pattern sums of V_W[64 c + lane][s n + 4 g + j]
+    double xlut[2][NG][16];      // pattern sums of v_a[s n + 4 g + j]
+};
+
+// the 16 pattern sums of x[0..4) (entries past n are zero), each in increasing
+// orbital order: the pattern without its highest bit, plus that bit's entry
+__device__ __forceinline__ void pattern_sums(const double (&x)[4], double (&out)[16])
+{
+    out[0] = 0.0;
+#pragma unroll
+    for (int p = 1; p < 16; ++p) {
+        const int top = p >= 8 ? 3 : p >= 4 ? 2 : p >= 2 ? 1 : 0;
+        out[p] = p == (1 << top) ? x[top] : out[p - (1 << top)] + x[top];
+    }
+}
+
+// one wave's rows [r0, r1) for hidden chunk c (lane = unit 64 c + lane).
+// D~ v (FWD false): out = w; FIRST (chunk 0) writes psi v_0 + x . v_a + the chunk's
+// sum of d t, later chunks add theirs.  Forward pass (FWD true): t is z = b + W x,
+// the chunk's d = 1 - tanh^2 z goes to dout and out = psi gets x . a + the sum of
+// tanh z in the same way.
+template <int NG, bool FIRST, bool FWD>
+__device__ __forceinline__ void lut_rows(const BitsArgs &A, const LutShared<NG> &T, int64_t r0, int64_t r1, int h,
+                                         int lane, double bh, double v0, double *__restrict__ out,
+                                         double *__restrict__ dout)
+{
+    const int H = A.H;
+    const int nbatch = (int)((r1 - r0 + kLutRB - 1) / kLutRB);
+    uint32_t cur = 0xffffffffu;   // beta string of tb (none yet: strings are < 2^n)
+    double tb = 0.0;
+    for (int b = 0; b < nbatch; ++b) {
+        const int64_t rb = r0 + (int64_t)b * kLutRB;
+        const int cnt = r1 - rb < kLutRB ? (int)(r1 - rb) : kLutRB;
+        // the batch's d segments, keys and psi through buffer descriptors bounded
+        // at its last row (rows past it read as zeros, stores past it are dropped);
+        // the 16 rows' loads are in flight together, and the other waves of the
+        // SIMD (four per SIMD) keep it busy meanwhile
+        const auto rs = __builtin_amdgcn_make_buffer_rsrc((void *)((FWD ? dout : A.dfac) + rb * H), 0,
+                                                          cnt * H * 8, kBufWord3);
+        double d[kLutRB];
+        if (!FWD) {
+#pragma unroll
+            for (int i = 0; i < kLutRB; ++i)
+                d[i] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, h * 8, i * H * 8, 0));
+        }
+        const auto rk = __builtin_amdgcn_make_buffer_rsrc((void *)(A.keys + rb), 0, cnt * 8, kBufWord3);
+        const uint64_t kl = __builtin_bit_cast(uint64_t, __builtin_amdgcn_raw_buffer_load_b64(rk, lane * 8, 0, 0));
+        double pl = 0.0;
+        if (FIRST && !FWD) {
+            const auto rp = __builtin_amdgcn_make_buffer_rsrc((void *)(A.psi + rb), 0, cnt * 8, kBufWord3);
+            pl = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rp, lane * 8, 0, 0));
+        }
+        // row i's t: bh + its beta part + its alpha part (t0: the first two)
+        auto finish = [&](int i, double t) {
+            if (FWD) {
+                double th, dd;
+                tanh_and_d(t, th, dd);
+                __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2v, dd), rs, h * 8, i * H * 8, 0);
+                d[i] = th;
+            } else {
+                d[i] *= t;
+            }
+        };
+        // one beta string for the whole batch (the usual case: rows ascend
+        // beta-major): its part of t is read once; otherwise per row
+        const uint32_t khi = (uint32_t)(kl >> 32);
+        const uint32_t b0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)khi);
+        const bool one_beta = __ballot(lane < cnt && khi != b0) == 0;
+        if (one_beta) {
+            if (b0 != cur) {
+                cur = b0;
+                tb = 0.0;
+#pragma unroll
+                for (int g = 0; g < NG; ++g) tb += T.lut[1][g][(b0 >> (4 * g)) & 15u][lane];
+            }
+            const double tb0 = bh + tb;
+#pragma unroll
+            for (int i = 0; i < kLutRB; ++i) {
+                const uint32_t oa = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)kl, i);
+                double t = tb0;
+#pragma unroll
+                for (int g = 0; g < NG; ++g) t += T.lut[0][g][(oa >> (4 * g)) & 15u][lane];
+                finish(i, t);
+            }
+        } else {
+            cur = 0xffffffffu;
+#pragma unroll
+            for (int i = 0; i < kLutRB; ++i) {
+                const uint32_t occ[2] = {(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)kl, i),
+                                         (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(kl >> 32), i)};
+                double t = bh;
+#pragma unroll
+                for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+                    for (int g = 0; g < NG; ++g) t += T.lut[sp][g][(occ[sp] >> (4 * g)) & 15u][lane];
+                finish(i, t);
+            }
+        }
+        double sum = rows16_sum(d, lane);
+        const int j = lane >> 2;
+        if (FIRST) {
+            // x_j . a (or psi_j v_0 + x_j . v_a) for row j, the (spin, group)
+            // tables split over the row's 4 lanes and summed in a fixed order
+            const uint64_t kj = __shfl(kl, j, kWave);
+            double x = 0.0;
+#pragma unroll
+            for (int m = 0; m < (2 * NG + 3) / 4; ++m) {
+                const int k = 4 * m + (lane & 3);
+                const bool beta = k >= NG;
+                const int g = beta ? k - NG : k;
+                const uint32_t o = beta ? (uint32_t)(kj >> 32) : (uint32_t)kj;
+                if (k < 2 * NG) x += T.xlut[beta ? 1 : 0][g][(o >> (4 * g)) & 15u];
+            }
+            x += __shfl_xor(x, 1, kWave);
+            x += __shfl_xor(x, 2, kWave);
+            if (FWD)
+                sum += x;
+            else
+                sum += fma(__shfl(pl, j, kWave), v0, x);
+        }
+        if ((lane & 3) == 0 && j < cnt) {
+            const int64_t row = rb + j;
+            out[row] = FIRST ? sum : out[row] + sum;
+        }
+    }
+}
+
+// the workgroup's tables for hidden chunk c of M (H x V, row-major) and of the
+// visible vector a (xlut, built once by the caller's first call)
+template <int NG>
+__device__ __forceinline__ void lut_build(LutShared<NG> &T, const double *__restrict__ M, const double *__restrict__ a,
+                                          int n, int V, int c, int lane, int wv, int nwv)
+{
+    if (c == 0 && threadIdx.x < 2 * NG) {
+        const int sp = threadIdx.x / NG, g = threadIdx.x % NG;
+        double x[4], o[16];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) x[j] = 4 * g + j < n ? a[sp * n + 4 * g + j] : 0.0;
+        pattern_sums(x, o);
+#pragma unroll
+        for (int p = 0; p < 16; ++p) T.xlut[sp][g][p] = o[p];
+    }
+    // pattern sums of M for unit h: wave wv takes (spin, group) pairs wv, wv + nwv, ...
+    const int h = 64 * c + lane;
+    for (int q = wv; q < 2 * NG; q += nwv) {
+        const int sp = q / NG, g = q % NG;
+        double x[4], o[16];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) x[j] = 4 * g + j < n ? M[(size_t)h * V + sp * n + 4 * g + j] : 0.0;
+        pattern_sums(x, o);
+#pragma unroll
+        for (int p = 0; p < 16; ++p) T.lut[sp][g][p][lane] = o[p];
+    }
+}
+
+// this wave's part of the workgroup's block of rows: whole batches, in wave order
+__device__ __forceinline__ void lut_wave_rows(int64_t ns, int wv, int nwv, int64_t &r0, int64_t &r1)
+{
+    bits_block(ns, gridDim.x, blockIdx.x, r0, r1);
+    const int64_t nb = (r1 - r0 + kLutRB - 1) / kLutRB, per = (nb + nwv - 1) / nwv;
+    const int64_t q0 = r0 + (int64_t)wv * per * kLutRB, q1 = q0 + per * kLutRB;
+    r1 = q1 < r1 ? q1 : r1;
+    r0 = q0 < r1 ? q0 : r1;
+}
+
+template <int NG>
+__global__ __launch_bounds__(kLutThreads) void k_fac_jvp_lut(BitsArgs A, const double *__restrict__ v, int zero_v0,
+                                                             double *__restrict__ w)
+{
+    static_assert(NG >= 1 && NG <= kLutMaxG, "orbital groups");
+    __shared__ LutShared<NG> T;
+    const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    constexpr int nwv = kLutThreads / 64;
+    const int V = A.V, H = A.H;
+    int64_t r0, r1;
+    lut_wave_rows(A.ns, wv, nwv, r0, r1);
+    const double *va = v + 1, *vb = v + 1 + V, *vW = v + 1 + V + H;
+    const double v0 = zero_v0 ? 0.0 : v[0];
+    for (int c = 0; c < H / 64; ++c) {
+        __syncthreads();   // the previous chunk's tables are no longer read
+        lut_build(T, vW, va, A.n, V, c, lane, wv, nwv);
+        __syncthreads();
+        const int h = 64 * c + lane;
+        if (c == 0)
+            lut_rows<NG, true, false>(A, T, r0, r1, h, lane, vb[h], v0, w, nullptr);
+        else
+            lut_rows<NG, false, false>(A, T, r0, r1, h, lane, vb[h], v0, w, nullptr);
+    }
+}
+
+// forward pass on selected sets with the same tables (of W and a): psi and d
+template <int NG>
+__global__ __launch_bounds__(kLutThreads) void k_fac_forward_lut(BitsArgs A, const double *__restrict__ theta,
+                                                                 double *__restrict__ psi, double *__restrict__ dfac)
+{
+    static_assert(NG >= 1 && NG <= kLutMaxG, "orbital groups");
+    __shared__ LutShared<NG> T;
+    const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    constexpr int nwv = kLutThreads / 64;
+    const int V = A.V, H = A.H;
+    int64_t r0, r1;
+    lut_wave_rows(A.ns, wv, nwv, r0, r1);
+    const double *a = theta, *bb = theta + V, *W = theta + V + H;
+    for (int c = 0; c < H / 64; ++c) {
+        __syncthreads();
+        lut_build(T, W, a, A.n, V, c, lane, wv, nwv);
+        __syncthreads();
+        const int h = 64 * c + lane;
+        if (c == 0)
+            lut_rows<NG, true, true>(A, T, r0, r1, h, lane, bb[h], 0.0, psi, dfac);
+        else
+            lut_rows<NG, false, true>(A, T, r0, r1, h, lane, bb[h], 0.0, psi, dfac);
+    }
+}
+
 // the vector-unit forms apply to these rows: not the full-space kernels, n <= 24,
 // 48 <= H <= 256
 bool fac_bits_ok(const irl_system *s, int H)
@@ -1410,6 +1681,24 @@ bool fac_bits_ok(const irl_system *s, int H)
     return false;
 #endif
     return s->n <= kBitsMaxN && H >= kBitsMinH && H <= kBitsMaxH;
+}
+
+// the table-driven D~ v applies to these rows: not the full-space kernels, n <= 24,
+// H a multiple of 64
+bool fac_lut_ok(const irl_system *s, int H)
+{
+#ifdef IRL_FAC_NO_LUT
+    return false;
+#endif
+    return s->n <= kBitsMaxN && H >= 64 && H % 64 == 0;
+}
+
+// row blocks of the table-driven kernels: at most kLutBlocks, at least 128 rows each
+unsigned lut_blocks(int64_t ns)
+{
+    int64_t per = (ns + kLutBlocks - 1) / kLutBlocks;
+    if (per < 128) per = 128;
+    return (unsigned)((ns + per - 1) / per);
 }
 
 int fac_bits_blocks(int64_t ns)
@@ -1554,6 +1843,21 @@ hipError_t launch_fac_forward(const irl_system *s, const WsLayout &L, void *ws, 
         }
         return hipGetLastError();
     }
+#ifndef IRL_FAC_NO_LUT_FWD
+    if (fac_lut_ok(s, H)) {
+        const BitsArgs B{R.keys, R.psi, R.dfac, R.ns, s->n, V, H};
+        const unsigned nblk = lut_blocks(R.ns);
+        switch ((s->n + 3) / 4) {
+        case 1: k_fac_forward_lut<1><<<nblk, kLutThreads, 0, st>>>(B, theta, psi, dfac); break;
+        case 2: k_fac_forward_lut<2><<<nblk, kLutThreads, 0, st>>>(B, theta, psi, dfac); break;
+        case 3: k_fac_forward_lut<3><<<nblk, kLutThreads, 0, st>>>(B, theta, psi, dfac); break;
+        case 4: k_fac_forward_lut<4><<<nblk, kLutThreads, 0, st>>>(B, theta, psi, dfac); break;
+        case 5: k_fac_forward_lut<5><<<nblk, kLutThreads, 0, st>>>(B, theta, psi, dfac); break;
+        default: k_fac_forward_lut<6><<<nblk, kLutThreads, 0, st>>>(B, theta, psi, dfac); break;
+        }
+        return hipGetLastError();
+    }
+#endif
     switch ((V + 7) / 8) {
     case 1: forward_ks<2>(s, L, V, H, theta, psi, dfac, st); break;
     case 2: forward_ks<4>(s, L, V, H, theta, psi, dfac, st); break;
@@ -1581,6 +1885,19 @@ hipError_t launch_fac_jvp_rows(const irl_system *s, const WsLayout &L, const Fac
         case 2: k_fac_jvp_full<8><<<grid, 256, 0, st>>>(F, v, zero_v0, w); break;
         case 3: k_fac_jvp_full<12><<<grid, 256, 0, st>>>(F, v, zero_v0, w); break;
         default: k_fac_jvp_full<16><<<grid, 256, 0, st>>>(F, v, zero_v0, w); break;
+        }
+        return hipGetLastError();
+    }
+    if (fac_lut_ok(s, H)) {
+        const BitsArgs B{R.keys, R.psi, R.dfac, R.ns, s->n, V, H};
+        const unsigned nblk = lut_blocks(R.ns);
+        switch ((s->n + 3) / 4) {
+        case 1: k_fac_jvp_lut<1><<<nblk, kLutThreads, 0, st>>>(B, v, zero_v0, w); break;
+        case 2: k_fac_jvp_lut<2><<<nblk, kLutThreads, 0, st>>>(B, v, zero_v0, w); break;
+        case 3: k_fac_jvp_lut<3><<<nblk, kLutThreads, 0, st>>>(B, v, zero_v0, w); break;
+        case 4: k_fac_jvp_lut<4><<<nblk, kLutThreads, 0, st>>>(B, v, zero_v0, w); break;
+        case 5: k_fac_jvp_lut<5><<<nblk, kLutThreads, 0, st>>>(B, v, zero_v0, w); break;
+        default: k_fac_jvp_lut<6><<<nblk, kLutThreads, 0, st>>>(B, v, zero_v0, w); break;
         }
         return hipGetLastError();
     }

@@ -134,6 +134,11 @@ def test_factored_full_space_string_split_vs_oracle():
     (10, 5, 4, 130, 2047, 5),   # three hidden chunks (the last one 2 wide), H % 4 != 0
     (11, 3, 3, 33, 17, 6),      # 17 rows: one full tile plus one row
     (9, 5, 4, 7, 1, 7),         # one determinant
+    # the table-driven D~ v (H a multiple of 64): one group of 4 orbitals per spin
+    # with two hidden chunks, six groups (n = 24), three chunks with a ragged batch
+    (3, 2, 1, 128, 9, 8),
+    (24, 3, 3, 64, 3001, 9),
+    (12, 4, 4, 192, 4097, 10),
 ])
 def test_factored_shapes_vs_oracle(n, na, nb, H, count, seed):
     """Tile edges of the matrix-core kernels against the oracle's dense D~:
