@@ -1016,8 +1016,10 @@ __device__ __forceinline__ uint32_t uniform_u32(uint32_t x) { return (uint32_t)_
 // fma(bit, y, x) equals x or x + y exactly
 __device__ __forceinline__ double bit_d(uint32_t bits, int k)
 {
-    const uint32_t hi = ((bits >> k) & 1u) * 0x3ff00000u;
-    return __hiloint2double((int)hi, 0);
+    // the bit spread over all 64 bits (0 or -1) masks 1.0 as one 64-bit value: two
+    // scalar instructions, with no separate move for the low word
+    const int64_t m = (int64_t)((uint64_t)bits << (63 - k)) >> 63;
+    return __builtin_bit_cast(double, (uint64_t)m & 0x3ff0000000000000ull);
 }
 
 // rows [r0, r1) of row block rb of nblk
