@@ -14,7 +14,9 @@
 * 2^20-determinant selected set (20 orbitals, 10 alpha + 10 beta, V = 40,
   H = 256, P = 10,536): the FP32 operator's step against the FP64 step
   (precision report, Methods "Practical Matrix-Free Implementation"), and with
-  the FP64 polish at the FP64 tolerances.
+  the FP64 polish at the FP64 tolerances; psi and d on sampled rows; the exact
+  operator's symmetry, positivity and overlap entry (properties that hold at
+  any size).
 
 Tolerances: energies 1e-12 Ha; gradient and operator outputs 1e-10 relative;
 eigenvalues 1e-10 max(|lambda|, ||H~'||).
@@ -253,5 +255,38 @@ def test_c3_fp32_step_against_fp64_step(c3_system):
     assert rc == 0 and rp.converged == 1
     assert abs(rp.lambda_min - r64.lambda_min) <= 1e-10 * max(abs(r64.lambda_min), normH)
     assert abs(rp.E_after - r64.E_after) <= 1e-12
+    s.ws = None
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.timeout(600)
+def test_c3_operator_properties(c3_system):
+    """The exact factored operator at the full 2^20-row shape (table-driven D~ v,
+    stored rows, backward product), through properties that hold at any size:
+    D~^T D~ and D~^T H D~ are symmetric (u . y(v) = v . y(u); a forward product
+    that does not match the backward one breaks this), D~^T D~ is positive, and
+    applied to e_0 (D~ e_0 = psi) the overlap entry is Z = psi . psi from the
+    evaluation."""
+    import torch
+    from paper_2601_01437_amd import IRL_WS_FACTORED
+    w, keys, s = c3_system
+    announce("c3 operator properties")
+    Z, _, _ = s.evaluate(w.V, w.H, dev(w.theta()), ws_flags=IRL_WS_FACTORED)
+    rng = np.random.default_rng(33)
+    u = rng.normal(size=w.P + 1)
+    v = rng.normal(size=w.P + 1)
+    yHu, ySu = (host(x) for x in s.apply(dev(u)))
+    yHv, ySv = (host(x) for x in s.apply(dev(v)))
+    nu, nv = float(u @ ySu), float(v @ ySv)
+    assert nu > 0 and nv > 0
+    a, b = float(u @ ySv), float(v @ ySu)
+    assert abs(a - b) <= 1e-10 * np.sqrt(nu * nv), (a, b)
+    a, b = float(u @ yHv), float(v @ yHu)
+    scale = np.linalg.norm(yHv) * np.linalg.norm(u) + np.linalg.norm(yHu) * np.linalg.norm(v)
+    assert abs(a - b) <= 1e-10 * scale, (a, b, scale)
+    e0 = np.zeros(w.P + 1)
+    e0[0] = 1.0
+    _, yS0 = s.apply(dev(e0))
+    assert abs(float(host(yS0)[0]) - Z) <= 1e-12 * Z
     s.ws = None
     torch.cuda.empty_cache()
