@@ -18,6 +18,8 @@
 // QT units per lane where the operands of 64 units would not fit the registers).
 #include "internal.h"
 
+#include <utility>
+
 namespace irl {
 
 typedef double d4v __attribute__((ext_vector_type(4)));
@@ -1194,6 +1196,44 @@ __device__ __forceinline__ double u2d(u4v x, int e)
     return __builtin_bit_cast(double, ((uint64_t)x[2 * e + 1] << 32) | x[2 * e]);
 }
 
+// acc[q][k] += bit_k * t[q] for the alpha bits k < NA of a row, one FP64 FMA per
+// (k, q) and no scalar instruction: lane l of every 16-lane row holds the 0/1
+// factor of bit l (flo) and of bit 16 + l (fhi), and each FMA reads the factor of
+// bit k through a row broadcast (DPP row_newbcast).  The sums are those of
+// fma(bit_d(bits, k), t, acc) bit for bit.  A VALU write of a VGPR needs two wait
+// states before a DPP read of it: the factors pass through an s_nop after they are
+// formed, and every broadcast FMA takes them from its output.
+template <int K>
+__device__ __forceinline__ void fmac_bcast(double &acc, double f, double y)
+{
+    asm("v_fmac_f64_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
+        : "+v"(acc)
+        : "v"(f), "v"(y), "n"(K & 15));
+}
+
+template <int NR, int NA, int... K>
+__device__ __forceinline__ void bits_fma_seq(double (&acc)[NR][NA], double flo, double fhi, const double (&t)[NR],
+                                             std::integer_sequence<int, K...>)
+{
+    (
+        [&] {
+#pragma unroll
+            for (int q = 0; q < NR; ++q) fmac_bcast<K>(acc[q][K], K < 16 ? flo : fhi, t[q]);
+        }(),
+        ...);
+}
+
+template <int NR, int NA>
+__device__ __forceinline__ void bits_fma(double (&acc)[NR][NA], uint32_t bits, int lane, const double (&t)[NR])
+{
+    static_assert(NA <= 32, "two factor registers hold 32 bits");
+    const uint32_t sh = (uint32_t)lane & 15u;
+    double flo = __hiloint2double(((bits >> sh) & 1u) ? 0x3ff00000 : 0, 0);
+    double fhi = NA > 16 ? __hiloint2double(((bits >> (16u + sh)) & 1u) ? 0x3ff00000 : 0, 0) : 0.0;
+    asm("s_nop 1" : "+v"(flo), "+v"(fhi));
+    bits_fma_seq<NR, NA>(acc, flo, fhi, t, std::make_integer_sequence<int, NA>{});
+}
+
 template <int NR, int NA>
 __global__ __launch_bounds__(256) void k_fac_vjp_ring(BitsArgs A, const double *__restrict__ y0,
                                                       const double *__restrict__ y1, const double *__restrict__ coefp,
@@ -1316,10 +1356,17 @@ __global__ __launch_bounds__(256) void k_fac_vjp_ring(BitsArgs A, const double *
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int64_t j = 2 * p + e;
+                // a row past the block adds zeros to the alpha sums (no branch around
+                // them: the accumulators then need no copies across it)
+                uint32_t al = 0u;
+                double tq[NR];
+#pragma unroll
+                for (int q = 0; q < NR; ++q) tq[q] = 0.0;
                 if (j < nr) {
                     const int h2 = e >> 1, e2 = e & 1;
                     const uint64_t key = ((uint64_t)mk[h2][2 * e2 + 1] << 32) | mk[h2][2 * e2];
-                    const uint32_t al = uniform_u32((uint32_t)key), be = uniform_u32((uint32_t)(key >> 32));
+                    al = uniform_u32((uint32_t)key);
+                    const uint32_t be = uniform_u32((uint32_t)(key >> 32));
                     if (!run || be != cur) {
                         if (run) {
 #pragma unroll
@@ -1339,19 +1386,21 @@ __global__ __launch_bounds__(256) void k_fac_vjp_ring(BitsArgs A, const double *
                     }
                     const double ps = u2d(mp[h2], e2);
                     const double d = dd[h2][e2];
-                    double c[NR], tq[NR];
+                    double c[NR];
 #pragma unroll
                     for (int q = 0; q < NR; ++q) {
                         c[q] = fma(-coef, ps, u2d(q == 0 ? my0[h2] : my1[h2], e2));
                         tq[q] = c[q] * d;
                         sb[q] += tq[q];
                     }
+#ifdef IRL_VJP_NO_DPP
 #pragma unroll
                     for (int k = 0; k < NA; ++k) {
                         const double bk = bit_d(al, k);
 #pragma unroll
                         for (int q = 0; q < NR; ++q) wa[q][k] = fma(bk, tq[q], wa[q][k]);
                     }
+#endif
                     if (wv == 0) {
                         const uint32_t bits = lane < n ? al : be;
                         const int sh = lane < n ? lane : lane - n;
@@ -1363,6 +1412,9 @@ __global__ __launch_bounds__(256) void k_fac_vjp_ring(BitsArgs A, const double *
                         }
                     }
                 }
+#ifndef IRL_VJP_NO_DPP
+                bits_fma<NR, NA>(wa, al, lane, tq);
+#endif
             }
             // the pairs' LDS reads have completed (above) before their slots take pairs
             // p + RP and p + RP + 1
