@@ -139,6 +139,7 @@ def test_factored_full_space_string_split_vs_oracle():
     (3, 2, 1, 128, 9, 8),
     (24, 3, 3, 64, 3001, 9),
     (12, 4, 4, 192, 4097, 10),
+    (5, 2, 2, 64, 1, 11),       # one determinant through the table-driven kernels
 ])
 def test_factored_shapes_vs_oracle(n, na, nb, H, count, seed):
     """Tile edges of the matrix-core kernels against the oracle's dense D~:
