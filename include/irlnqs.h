@@ -260,12 +260,11 @@ int irl_system_info_get(const irl_system *sys, irl_system_info *out);
  * Inside a slice the rows are taken in windows of 4096; a window's rows are
  * ordered by their number of elements in the slice (descending, ties by row)
  * and grouped 64 at a time, one row per lane of a wavefront; a group stores
- * L x 64 slots (L = its longest row rounded up to a multiple of 4), slot
+ * L x 64 slots (L = its longest row rounded up to an even number), slot
  * (j, lane) holding the lane row's j-th element (zero padding past the row's
- * end) as a 16-bit target (row - b 2^14) and an FP64 value; values sit in
- * lane-interleaved pairs (j, j + 1) and targets in lane-interleaved quads
- * (j .. j + 3), so a wavefront loads 1 KiB of values or 512 bytes of targets
- * contiguously.  Per slice and group: the slot offset (uint32) and L
+ * end) as a 16-bit target (row - b 2^14) and an FP64 value; values and targets
+ * sit in lane-interleaved pairs (j, j + 1), so a wavefront loads 1 KiB of
+ * values or 256 bytes of targets contiguously.  Per slice and group: the slot offset (uint32) and L
  * (uint16); per lane of a group: the lane's row inside its window (uint16,
  * 0xffff for an empty lane); per slice: the slot base (int64) and room for
  * one FP64 partial sum per row (an apply sums a row's slices in slice order in

@@ -994,8 +994,9 @@ int store_sliced(irl_system *s, size_t max_bytes, size_t *bytes_needed, hipStrea
             const int64_t g0 = w0 / kWave;
             for (int k = 0; k * kWave < nr; ++k) {
                 const int64_t g = g0 + k;
-                // slots per lane: the longest row rounded up to 4 (four targets per load)
-                const uint32_t L = (cb[w0 + order[(size_t)k * kWave]] + 3u) & ~3u;
+                // slots per lane: the longest row rounded up to 2 (two values or two
+                // targets per lane and load)
+                const uint32_t L = (cb[w0 + order[(size_t)k * kWave]] + 1u) & ~1u;
                 if (L > 0xffffu) return (void)hipFree(dcount), set_err(s, IRL_EINVAL, "a row holds more than 65535 elements in one slice");
                 gbase[(size_t)b * G + g] = (uint32_t)run;
                 glen[(size_t)b * G + g] = (uint16_t)L;

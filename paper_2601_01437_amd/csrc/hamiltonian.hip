@@ -539,10 +539,10 @@ __global__ __launch_bounds__(256) void k_ham_count_sliced(HamArgs A, int scs, in
     }
 }
 
-// Slot (j, lane) of a group (j < L, L a multiple of 4) inside the group's slot
-// range: values in pairs (a lane loads the 16 bytes of slots 2i and 2i + 1),
-// targets in quads (8 bytes of slots 4i .. 4i + 3), so a wavefront's loads are
-// 1 KiB of values and 512 bytes of targets.
+// Slot (j, lane) of a group (j < L, L even) inside the group's slot range: values
+// and targets in lane-interleaved pairs (a lane loads the 16 bytes of values or
+// the 4 bytes of targets of slots 2i and 2i + 1), so a wavefront's loads are 1 KiB
+// of values and 256 bytes of targets.
 __host__ __device__ __forceinline__ int64_t sell_val_slot(int64_t j, int64_t lane)
 {
     return (j >> 1) * (2 * kWave) + lane * 2 + (j & 1);
@@ -550,7 +550,7 @@ __host__ __device__ __forceinline__ int64_t sell_val_slot(int64_t j, int64_t lan
 
 __host__ __device__ __forceinline__ int64_t sell_col_slot(int64_t j, int64_t lane)
 {
-    return (j >> 2) * (4 * kWave) + lane * 4 + (j & 3);
+    return (j >> 1) * (2 * kWave) + lane * 2 + (j & 1);
 }
 
 // second pass, one wavefront per workgroup: each lane counts its own connections
@@ -657,10 +657,10 @@ constexpr int kStreamPolicy = 2;
 // then take the window's 64 groups of that slice, 4 each: wavefront wv's k-th group is
 // 16 k + wv for even k and 16 k + 15 - wv for odd k (groups run from long to short
 // inside a window, so alternating directions evens out the work).  A wavefront's
-// groups form one stream of chunks of 16 slots (8 KiB of values as lane pairs, 2 KiB
-// of targets as lane quads); the next chunk's loads are issued before the current one
+// groups form one stream of chunks of 16 slots (8 KiB of values and 2 KiB of targets,
+// both as lane pairs); the next chunk's loads are issued before the current one
 // is summed.  Each chunk reads through buffer descriptors whose size ends at its
-// group's end: quads past the end read as zeros (values 0, targets 0) without touching
+// group's end: pairs past the end read as zeros (values 0, targets 0) without touching
 // memory, so every chunk issues the same loads and the waits before a sum count only
 // that chunk's loads.  Lane l of a group sums its row's elements (targets index the
 // LDS copy of w) and adds the sum to the row's accumulator in LDS: a row occurs once
@@ -691,10 +691,10 @@ __global__ __launch_bounds__(kWinThreads) void k_ham_sell_win(HamArgs A, const d
     for (int i = t; i < kSellWindow; i += kWinThreads) acc[i] = 0.0;
     auto group_of = [&](int kk) { return kk * NW + ((kk & 1) ? NW - 1 - wv : wv); };
     static_assert(K == 16, "chunk offsets below assume 16 slots");
-    const int vo0 = lane * 16, vo1 = lane * 16 + 4096, co = lane * 8, po = lane * 2;
+    const int vo0 = lane * 16, vo1 = lane * 16 + 4096, co = lane * 4, po = lane * 2;
     struct Chunk {
         double2 v[K / 2];
-        uint2 c[K / 4];
+        uint32_t c[K / 2];
         uint32_t lr;
     };
     for (int b = b0; b < b1; ++b) {
@@ -748,18 +748,14 @@ __global__ __launch_bounds__(kWinThreads) void k_ham_sell_win(HamArgs A, const d
                                  __builtin_bit_cast(double, (uint64_t)r[2] | ((uint64_t)r[3] << 32))};
             }
 #pragma unroll
-            for (int q = 0; q < K / 4; ++q) {
-                const auto r = __builtin_amdgcn_raw_buffer_load_b64(crs, co + q * 512, 0, kStreamPolicy);
-                x.c[q] = uint2{r[0], r[1]};
-            }
+            for (int q = 0; q < K / 2; ++q)
+                x.c[q] = __builtin_amdgcn_raw_buffer_load_b32(crs, co + q * 256, 0, kStreamPolicy);
         };
         auto sum = [&](const Chunk &x, double a) {
 #pragma unroll
-            for (int q = 0; q < K / 4; ++q) {
-                a += x.v[2 * q].x * wl[x.c[q].x & 0xffffu];
-                a += x.v[2 * q].y * wl[x.c[q].x >> 16];
-                a += x.v[2 * q + 1].x * wl[x.c[q].y & 0xffffu];
-                a += x.v[2 * q + 1].y * wl[x.c[q].y >> 16];
+            for (int q = 0; q < K / 2; ++q) {
+                a += x.v[q].x * wl[x.c[q] & 0xffffu];
+                a += x.v[q].y * wl[x.c[q] >> 16];
             }
             return a;
         };
