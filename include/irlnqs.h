@@ -130,7 +130,10 @@ enum irl_step_flags {
                                     for this (ncols doubles); any other system that
                                     steps in the same workspace in between overwrites it,
                                     which changes only the start.  The converged pair
-                                    meets the same tolerances either way. */
+                                    meets the same tolerances either way.  The saved
+                                    vector is known by the workspace's address: a caller
+                                    that frees a workspace and steps in a new one at the
+                                    same address omits the flag for that first step. */
 };
 
 /* K4 variant selection (irl_system_desc.flags) */
