@@ -1039,6 +1039,44 @@ __device__ __forceinline__ void bits_block(int64_t ns, int nblk, int rb, int64_t
 // and, for the beta orbitals, the run sum S of c d_h that it folds into W[h][n + v]
 // (and into the b entry) when the beta string changes.  Wave 0 also sums c over
 // each orbital (the a entries, lane v) and c psi (the psi entry).
+// acc[q][k] += bit_k * t[q] for the alpha bits k < NA of a row, one FP64 FMA per
+// (k, q) and no scalar instruction: lane l of every 16-lane row holds the 0/1
+// factor of bit l (flo) and of bit 16 + l (fhi), and each FMA reads the factor of
+// bit k through a row broadcast (DPP row_newbcast).  The sums are those of
+// fma(bit_d(bits, k), t, acc) bit for bit.  A VALU write of a VGPR needs two wait
+// states before a DPP read of it: the factors pass through an s_nop after they are
+// formed, and every broadcast FMA takes them from its output.
+template <int K>
+__device__ __forceinline__ void fmac_bcast(double &acc, double f, double y)
+{
+    asm("v_fmac_f64_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
+        : "+v"(acc)
+        : "v"(f), "v"(y), "n"(K & 15));
+}
+
+template <int NR, int NA, int... K>
+__device__ __forceinline__ void bits_fma_seq(double (&acc)[NR][NA], double flo, double fhi, const double (&t)[NR],
+                                             std::integer_sequence<int, K...>)
+{
+    (
+        [&] {
+#pragma unroll
+            for (int q = 0; q < NR; ++q) fmac_bcast<K>(acc[q][K], K < 16 ? flo : fhi, t[q]);
+        }(),
+        ...);
+}
+
+template <int NR, int NA>
+__device__ __forceinline__ void bits_fma(double (&acc)[NR][NA], uint32_t bits, int lane, const double (&t)[NR])
+{
+    static_assert(NA <= 32, "two factor registers hold 32 bits");
+    const uint32_t sh = (uint32_t)lane & 15u;
+    double flo = __hiloint2double(((bits >> sh) & 1u) ? 0x3ff00000 : 0, 0);
+    double fhi = NA > 16 ? __hiloint2double(((bits >> (16u + sh)) & 1u) ? 0x3ff00000 : 0, 0) : 0.0;
+    asm("s_nop 1" : "+v"(flo), "+v"(fhi));
+    bits_fma_seq<NR, NA>(acc, flo, fhi, t, std::make_integer_sequence<int, NA>{});
+}
+
 template <int NR, int NA>
 __global__ __launch_bounds__(256) void k_fac_vjp_bits(BitsArgs A, const double *__restrict__ y0,
                                                       const double *__restrict__ y1, const double *__restrict__ coefp,
@@ -1082,9 +1120,16 @@ __global__ __launch_bounds__(256) void k_fac_vjp_bits(BitsArgs A, const double *
 #pragma unroll
             for (int p = 0; p < PD; ++p) {
                 const int j = j0 + p;
+                // a row past the batch adds zeros to the alpha sums (no branch around
+                // them: the accumulators then need no copies across it)
+                uint32_t al = 0u;
+                double tq[NR];
+#pragma unroll
+                for (int q = 0; q < NR; ++q) tq[q] = 0.0;
                 if (j < nbt) {
                     const uint64_t key = skey[j];
-                    const uint32_t al = uniform_u32((uint32_t)key), be = uniform_u32((uint32_t)(key >> 32));
+                    al = uniform_u32((uint32_t)key);
+                    const uint32_t be = uniform_u32((uint32_t)(key >> 32));
                     if (!run || be != cur) {
                         if (run) {
 #pragma unroll
@@ -1103,19 +1148,21 @@ __global__ __launch_bounds__(256) void k_fac_vjp_bits(BitsArgs A, const double *
                         run = true;
                     }
                     const double d = dr[p];
-                    double c[NR], tq[NR];
+                    double c[NR];
 #pragma unroll
                     for (int q = 0; q < NR; ++q) {
                         c[q] = sc[q][j];
                         tq[q] = c[q] * d;
                         sb[q] += tq[q];
                     }
+#ifdef IRL_VJP_NO_DPP
 #pragma unroll
                     for (int k = 0; k < NA; ++k) {
                         const double bk = bit_d(al, k);
 #pragma unroll
                         for (int q = 0; q < NR; ++q) wa[q][k] = fma(bk, tq[q], wa[q][k]);
                     }
+#endif
                     if (wv == 0) {
                         const uint32_t bits = lane < n ? al : be;
                         const int sh = lane < n ? lane : lane - n;
@@ -1128,6 +1175,9 @@ __global__ __launch_bounds__(256) void k_fac_vjp_bits(BitsArgs A, const double *
                         }
                     }
                 }
+#ifndef IRL_VJP_NO_DPP
+                bits_fma<NR, NA>(wa, al, lane, tq);
+#endif
                 const int64_t rn = bs + j0 + p + PD;
                 dr[p] = (hv && rn < r1) ? A.dfac[rn * H + t] : 0.0;
             }
@@ -1194,44 +1244,6 @@ __device__ __forceinline__ uint32_t lds_addr(const void *p)
 __device__ __forceinline__ double u2d(u4v x, int e)
 {
     return __builtin_bit_cast(double, ((uint64_t)x[2 * e + 1] << 32) | x[2 * e]);
-}
-
-// acc[q][k] += bit_k * t[q] for the alpha bits k < NA of a row, one FP64 FMA per
-// (k, q) and no scalar instruction: lane l of every 16-lane row holds the 0/1
-// factor of bit l (flo) and of bit 16 + l (fhi), and each FMA reads the factor of
-// bit k through a row broadcast (DPP row_newbcast).  The sums are those of
-// fma(bit_d(bits, k), t, acc) bit for bit.  A VALU write of a VGPR needs two wait
-// states before a DPP read of it: the factors pass through an s_nop after they are
-// formed, and every broadcast FMA takes them from its output.
-template <int K>
-__device__ __forceinline__ void fmac_bcast(double &acc, double f, double y)
-{
-    asm("v_fmac_f64_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
-        : "+v"(acc)
-        : "v"(f), "v"(y), "n"(K & 15));
-}
-
-template <int NR, int NA, int... K>
-__device__ __forceinline__ void bits_fma_seq(double (&acc)[NR][NA], double flo, double fhi, const double (&t)[NR],
-                                             std::integer_sequence<int, K...>)
-{
-    (
-        [&] {
-#pragma unroll
-            for (int q = 0; q < NR; ++q) fmac_bcast<K>(acc[q][K], K < 16 ? flo : fhi, t[q]);
-        }(),
-        ...);
-}
-
-template <int NR, int NA>
-__device__ __forceinline__ void bits_fma(double (&acc)[NR][NA], uint32_t bits, int lane, const double (&t)[NR])
-{
-    static_assert(NA <= 32, "two factor registers hold 32 bits");
-    const uint32_t sh = (uint32_t)lane & 15u;
-    double flo = __hiloint2double(((bits >> sh) & 1u) ? 0x3ff00000 : 0, 0);
-    double fhi = NA > 16 ? __hiloint2double(((bits >> (16u + sh)) & 1u) ? 0x3ff00000 : 0, 0) : 0.0;
-    asm("s_nop 1" : "+v"(flo), "+v"(fhi));
-    bits_fma_seq<NR, NA>(acc, flo, fhi, t, std::make_integer_sequence<int, NA>{});
 }
 
 template <int NR, int NA>
