@@ -1551,6 +1551,9 @@ __device__ __forceinline__ void lut_rows(const BitsArgs &A, const LutShared<NG> 
                                          double *__restrict__ dout)
 {
     const int H = A.H;
+    // a lane past H (the last chunk of a width that is not a multiple of 64) reads
+    // and writes past every descriptor's end: its d is 0 and its stores are dropped
+    const uint32_t dvo = h < H ? (uint32_t)h * 8u : 0x40000000u;
     const int nbatch = (int)((r1 - r0 + kLutRB - 1) / kLutRB);
     uint32_t cur = 0xffffffffu;   // beta string of tb (none yet: strings are < 2^n)
     double tb = 0.0;
@@ -1567,7 +1570,7 @@ __device__ __forceinline__ void lut_rows(const BitsArgs &A, const LutShared<NG> 
         if (!FWD) {
 #pragma unroll
             for (int i = 0; i < kLutRB; ++i)
-                d[i] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, h * 8, i * H * 8, 0));
+                d[i] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, dvo, i * H * 8, 0));
         }
         const auto rk = __builtin_amdgcn_make_buffer_rsrc((void *)(A.keys + rb), 0, cnt * 8, kBufWord3);
         const uint64_t kl = __builtin_bit_cast(uint64_t, __builtin_amdgcn_raw_buffer_load_b64(rk, lane * 8, 0, 0));
@@ -1581,7 +1584,7 @@ __device__ __forceinline__ void lut_rows(const BitsArgs &A, const LutShared<NG> 
             if (FWD) {
                 double th, dd;
                 tanh_and_d(t, th, dd);
-                __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2v, dd), rs, h * 8, i * H * 8, 0);
+                __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2v, dd), rs, dvo, i * H * 8, 0);
                 d[i] = th;
             } else {
                 d[i] *= t;
@@ -1655,7 +1658,7 @@ __device__ __forceinline__ void lut_rows(const BitsArgs &A, const LutShared<NG> 
 // visible vector a (xlut, built once by the caller's first call)
 template <int NG>
 __device__ __forceinline__ void lut_build(LutShared<NG> &T, const double *__restrict__ M, const double *__restrict__ a,
-                                          int n, int V, int c, int lane, int wv, int nwv)
+                                          int n, int V, int H, int c, int lane, int wv, int nwv)
 {
     if (c == 0 && threadIdx.x < 2 * NG) {
         const int sp = threadIdx.x / NG, g = threadIdx.x % NG;
@@ -1672,7 +1675,7 @@ __device__ __forceinline__ void lut_build(LutShared<NG> &T, const double *__rest
         const int sp = q / NG, g = q % NG;
         double x[4], o[16];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) x[j] = 4 * g + j < n ? M[(size_t)h * V + sp * n + 4 * g + j] : 0.0;
+        for (int j = 0; j < 4; ++j) x[j] = (h < H && 4 * g + j < n) ? M[(size_t)h * V + sp * n + 4 * g + j] : 0.0;
         pattern_sums(x, o);
 #pragma unroll
         for (int p = 0; p < 16; ++p) T.lut[sp][g][p][lane] = o[p];
@@ -1702,15 +1705,16 @@ __global__ __launch_bounds__(kLutThreads) void k_fac_jvp_lut(BitsArgs A, const d
     lut_wave_rows(A.ns, wv, nwv, r0, r1);
     const double *va = v + 1, *vb = v + 1 + V, *vW = v + 1 + V + H;
     const double v0 = zero_v0 ? 0.0 : v[0];
-    for (int c = 0; c < H / 64; ++c) {
+    for (int c = 0; 64 * c < H; ++c) {
         __syncthreads();   // the previous chunk's tables are no longer read
-        lut_build(T, vW, va, A.n, V, c, lane, wv, nwv);
+        lut_build(T, vW, va, A.n, V, H, c, lane, wv, nwv);
         __syncthreads();
         const int h = 64 * c + lane;
+        const double bh = h < H ? vb[h] : 0.0;
         if (c == 0)
-            lut_rows<NG, true, false>(A, T, r0, r1, h, lane, vb[h], v0, w, nullptr);
+            lut_rows<NG, true, false>(A, T, r0, r1, h, lane, bh, v0, w, nullptr);
         else
-            lut_rows<NG, false, false>(A, T, r0, r1, h, lane, vb[h], v0, w, nullptr);
+            lut_rows<NG, false, false>(A, T, r0, r1, h, lane, bh, v0, w, nullptr);
     }
 }
 
@@ -1727,15 +1731,16 @@ __global__ __launch_bounds__(kLutThreads) void k_fac_forward_lut(BitsArgs A, con
     int64_t r0, r1;
     lut_wave_rows(A.ns, wv, nwv, r0, r1);
     const double *a = theta, *bb = theta + V, *W = theta + V + H;
-    for (int c = 0; c < H / 64; ++c) {
+    for (int c = 0; 64 * c < H; ++c) {
         __syncthreads();
-        lut_build(T, W, a, A.n, V, c, lane, wv, nwv);
+        lut_build(T, W, a, A.n, V, H, c, lane, wv, nwv);
         __syncthreads();
         const int h = 64 * c + lane;
+        const double bh = h < H ? bb[h] : 0.0;
         if (c == 0)
-            lut_rows<NG, true, true>(A, T, r0, r1, h, lane, bb[h], 0.0, psi, dfac);
+            lut_rows<NG, true, true>(A, T, r0, r1, h, lane, bh, 0.0, psi, dfac);
         else
-            lut_rows<NG, false, true>(A, T, r0, r1, h, lane, bb[h], 0.0, psi, dfac);
+            lut_rows<NG, false, true>(A, T, r0, r1, h, lane, bh, 0.0, psi, dfac);
     }
 }
 
@@ -1749,14 +1754,15 @@ bool fac_bits_ok(const irl_system *s, int H)
     return s->n <= kBitsMaxN && H >= kBitsMinH && H <= kBitsMaxH;
 }
 
-// the table-driven D~ v applies to these rows: not the full-space kernels, n <= 24,
-// H a multiple of 64
+// the table-driven forward pass and D~ v apply to these rows: not the full-space
+// kernels, n <= 24, H >= 48 (a last chunk of a width that is not a multiple of 64
+// leaves its lanes past H idle; narrower networks keep the matrix-core forms)
 bool fac_lut_ok(const irl_system *s, int H)
 {
 #ifdef IRL_FAC_NO_LUT
     return false;
 #endif
-    return s->n <= kBitsMaxN && H >= 64 && H % 64 == 0;
+    return s->n <= kBitsMaxN && H >= kBitsMinH;
 }
 
 // row blocks of the table-driven kernels: at most kLutBlocks, at least 128 rows each
