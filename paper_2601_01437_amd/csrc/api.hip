@@ -76,6 +76,7 @@ void free_system(irl_system *s)
                     s->d.rankB, s->d.strA, s->d.strB, s->d.sglA, s->d.sglB, s->d.fA, s->d.fB,
                     s->d.dblA_rank, s->d.dblA_val, s->d.dblB_rank, s->d.dblB_val, s->d.jA,
                     s->d.jB, s->d.sglA_ia, s->d.sglB_ia, s->d.hfilter, s->d.bidx, s->d.bstart,
+                    s->d.aidx, s->d.astart, s->d.arow, s->d.abeta,
                     s->d.hptr, s->d.hcol, s->d.hval, s->d.sbase, s->d.sgbase, s->d.sglen, s->d.sperm,
                     s->d.scol, s->d.sval, s->d.spart};
     for (void *p : ptrs)
@@ -859,7 +860,8 @@ int irl_system_create(const irl_system_desc *d, void *stream, irl_system **out)
     const bool want_blocks = !full && n <= 24 && !(d->flags & IRL_SYS_FORCE_HASH);
     s->ham_kernel = want_blocks ? 3 : (want_hash ? 0 : 1);
     s->lookup = want_blocks ? kLkBlocks : (want_hash ? kLkHash : kLkRanks);
-    std::vector<int32_t> bidx, bstart;
+    std::vector<int32_t> bidx, bstart, aidx, astart, arow;
+    std::vector<uint32_t> abeta;
     if (want_blocks) {
         bidx.assign((size_t)1 << n, -1);
         for (size_t i = 0; i < keys.size(); ++i) {
@@ -871,6 +873,23 @@ int irl_system_create(const irl_system_desc *d, void *stream, irl_system **out)
         }
         s->d.nblocks = (int64_t)bstart.size();
         bstart.push_back((int32_t)keys.size());
+        // alpha-major order: a stable sort of the rows by alpha string keeps each
+        // alpha block in beta order
+        arow.resize(keys.size());
+        for (size_t i = 0; i < keys.size(); ++i) arow[i] = (int32_t)i;
+        std::stable_sort(arow.begin(), arow.end(),
+                         [&](int32_t x, int32_t y) { return (uint32_t)keys[x] < (uint32_t)keys[y]; });
+        aidx.assign((size_t)1 << n, -1);
+        abeta.resize(keys.size());
+        for (size_t i = 0; i < keys.size(); ++i) {
+            const uint32_t al = (uint32_t)keys[arow[i]];
+            abeta[i] = (uint32_t)(keys[arow[i]] >> 32);
+            if (i == 0 || al != (uint32_t)keys[arow[i - 1]]) {
+                aidx[al] = (int32_t)astart.size();
+                astart.push_back((int32_t)i);
+            }
+        }
+        astart.push_back((int32_t)keys.size());
     }
 
     int rc = IRL_OK;
@@ -901,6 +920,10 @@ int irl_system_create(const irl_system_desc *d, void *stream, irl_system **out)
     if (want_blocks) {
         AL(s->d.bidx, bidx.size());
         AL(s->d.bstart, bstart.size());
+        AL(s->d.aidx, aidx.size());
+        AL(s->d.astart, astart.size());
+        AL(s->d.arow, arow.size());
+        AL(s->d.abeta, abeta.size());
     }
 #undef AL
     auto fail_dev = [&](hipError_t e, const char *what) {
@@ -923,6 +946,11 @@ int irl_system_create(const irl_system_desc *d, void *stream, irl_system **out)
             return fail_dev(e, "copy block index");
         if ((e = hipMemcpyAsync(s->d.bstart, bstart.data(), bstart.size() * 4, hipMemcpyHostToDevice, st)) != hipSuccess)
             return fail_dev(e, "copy block starts");
+        if ((e = hipMemcpyAsync(s->d.aidx, aidx.data(), aidx.size() * 4, hipMemcpyHostToDevice, st)) != hipSuccess ||
+            (e = hipMemcpyAsync(s->d.astart, astart.data(), astart.size() * 4, hipMemcpyHostToDevice, st)) != hipSuccess ||
+            (e = hipMemcpyAsync(s->d.arow, arow.data(), arow.size() * 4, hipMemcpyHostToDevice, st)) != hipSuccess ||
+            (e = hipMemcpyAsync(s->d.abeta, abeta.data(), abeta.size() * 4, hipMemcpyHostToDevice, st)) != hipSuccess)
+            return fail_dev(e, "copy alpha-major index");
     }
     if (want_hash)
         if ((e = launch_hash_build(s->d.keys, s->ns, s->d.hkeys, s->d.hrows, s->d.hcap, s->d.hfilter,

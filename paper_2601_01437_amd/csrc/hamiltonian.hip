@@ -119,10 +119,11 @@ struct WaveLists {
     uint16_t poA[kMaxPairs], pvA[kMaxPairs], poB[kMaxPairs], pvB[kMaxPairs];  // i | j << 8
     int32_t sBlo[kMaxSingles], sBhi[kMaxSingles];   // blocked lookup: rows of each beta single's target
     int32_t own_lo, own_hi;                         // blocked lookup: rows sharing this row's beta
+    int32_t alo, ahi;                               // blocked lookup: alpha-major rows sharing its alpha
 };
 
 // blocked lookup: row ranges of the beta-single targets and of the row's own beta
-__device__ void build_block_ranges(const HamArgs &A, WaveLists &L, uint32_t be, int lane)
+__device__ void build_block_ranges(const HamArgs &A, WaveLists &L, uint32_t al, uint32_t be, int lane)
 {
     const int cnt = A.nb * (A.n - A.nb);
     for (int f = lane; f < cnt; f += kWave) {
@@ -134,6 +135,9 @@ __device__ void build_block_ranges(const HamArgs &A, WaveLists &L, uint32_t be, 
         const int32_t b = A.bidx[be];
         L.own_lo = A.bstart[b];
         L.own_hi = A.bstart[b + 1];
+        const int32_t a = A.aidx[al];
+        L.alo = A.astart[a];
+        L.ahi = A.astart[a + 1];
     }
 }
 
@@ -218,9 +222,40 @@ __device__ __forceinline__ void visit_row(const HamArgs &A, const WaveLists &L, 
             }
         }
     }
+    // Blocked lookup, alpha side: the rows sharing this row's alpha string (its
+    // alpha-major block) that differ in one or two beta orbitals are exactly the beta
+    // singles and beta-beta doubles inside the set; a short block is scanned instead
+    // of searching for each candidate.
+    bool scan_alpha = false;
+    if constexpr (LK == kLkBlocks) {
+        const int cand = nb * vb + (nb * (nb - 1) / 2) * (vb * (vb - 1) / 2);
+        scan_alpha = (L.ahi - L.alo) <= kScanFactor * cand;
+        if (scan_alpha) {
+            for (int64_t p = L.alo + lane; p < L.ahi; p += stride) {
+                const uint32_t b2 = A.abeta[p];
+                const uint32_t x = be ^ b2;
+                const int pc = __popc(x);
+                if (pc == 2) {
+                    const int i = __ffs(be & x) - 1, a = __ffs(b2 & x) - 1;
+                    const int sg = move_sign(be, i, a);
+                    op((int64_t)A.arow[p], sg, 2, sg * single_value(A.h, A.g, n, be, al, i, a));
+                } else if (pc == 4) {
+                    const uint32_t out = be & x, in = b2 & x;
+                    const int i = __ffs(out) - 1, j = __ffs(out & (out - 1)) - 1;
+                    const int a = __ffs(in) - 1, b = __ffs(in & (in - 1)) - 1;
+                    const int s1 = move_sign(be, i, a);
+                    const uint32_t b1 = (be & ~(1u << i)) | (1u << a);
+                    const int s2 = move_sign(b1, j, b);
+                    const double v = gint(A.g, n, i, a, j, b) - gint(A.g, n, i, b, j, a);
+                    op((int64_t)A.arow[p], s1 * s2, 4, (s1 * s2) * v);
+                }
+            }
+        }
+    }
     // alpha and beta singles
     for (int spin = 0; spin < 2; ++spin) {
         if (spin == 0 && scan_own) continue;
+        if (spin == 1 && scan_alpha) continue;
         const int cnt = spin ? nb * vb : na * va;
         const uint32_t *s = spin ? L.sB : L.sA;
         const uint32_t *ss = spin ? L.sBstr : L.sAstr;
@@ -240,6 +275,7 @@ __device__ __forceinline__ void visit_row(const HamArgs &A, const WaveLists &L, 
     // same-spin doubles
     for (int spin = 0; spin < 2; ++spin) {
         if (spin == 0 && scan_own) continue;
+        if (spin == 1 && scan_alpha) continue;
         const int ne = spin ? nb : na, nv = spin ? vb : va;
         const int npo = ne * (ne - 1) / 2, npv = nv * (nv - 1) / 2;
         const int cnt = npo * npv;
@@ -329,7 +365,7 @@ __device__ __forceinline__ void prepare_row(const HamArgs &A, WaveLists &L, uint
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     if constexpr (LK == kLkBlocks) {
-        build_block_ranges(A, L, be, lane);
+        build_block_ranges(A, L, al, be, lane);
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -930,6 +966,10 @@ HamView ham_view(const irl_system *s)
     A.hfbits = s->d.hfbits;
     A.bidx = s->lookup == kLkBlocks ? s->d.bidx : nullptr;
     A.bstart = s->lookup == kLkBlocks ? s->d.bstart : nullptr;
+    A.aidx = s->lookup == kLkBlocks ? s->d.aidx : nullptr;
+    A.astart = s->lookup == kLkBlocks ? s->d.astart : nullptr;
+    A.arow = s->lookup == kLkBlocks ? s->d.arow : nullptr;
+    A.abeta = s->lookup == kLkBlocks ? s->d.abeta : nullptr;
     A.hptr = s->ham_kernel == 4 ? s->d.hptr : nullptr;
     A.hcol = s->ham_kernel == 4 ? s->d.hcol : nullptr;
     A.hval = s->ham_kernel == 4 ? s->d.hval : nullptr;
@@ -1034,7 +1074,7 @@ __global__ void k_ham_row_list(HamArgs A, int64_t row, int32_t *tgt, int8_t *sig
     build_lists(be, A.n, A.nb, L.sB, L.sBstr, L.poB, L.pvB, lane);
     __syncthreads();
     if constexpr (LK == kLkBlocks) {
-        build_block_ranges(A, L, be, lane);
+        build_block_ranges(A, L, al, be, lane);
         __syncthreads();
     }
     if (lane != 0) return;

@@ -107,6 +107,11 @@ struct SystemDev {
     int32_t *bidx = nullptr;      // 2^n: beta string -> block index, -1 if absent
     int32_t *bstart = nullptr;    // nblocks + 1 row offsets
     int64_t nblocks = 0;
+    // the same rows alpha-major: rows sharing an alpha string, in beta order
+    int32_t *aidx = nullptr;      // 2^n: alpha string -> alpha block index, -1 if absent
+    int32_t *astart = nullptr;    // alpha blocks + 1 offsets into arow / abeta
+    int32_t *arow = nullptr;      // n_dets rows in alpha-major order
+    uint32_t *abeta = nullptr;    // their beta strings
     // stored rows (optional): off-diagonal elements inside the set, compressed by row
     int64_t *hptr = nullptr;      // hcb blocks of n_dets + 1 row offsets (block-major)
     int32_t *hcol = nullptr;      // nnz target rows, block b's targets in [b 2^hcs, (b + 1) 2^hcs)
@@ -165,6 +170,10 @@ struct HamView {
     const int32_t *rankA, *rankB;
     const int32_t *bidx;     // blocked lookup: beta string -> block, -1 if absent (or nullptr)
     const int32_t *bstart;   // blocked lookup: first row of each block, plus the end
+    const int32_t *aidx;     // blocked lookup: alpha string -> alpha block, -1 if absent
+    const int32_t *astart;   // blocked lookup: alpha blocks' offsets into arow / abeta
+    const int32_t *arow;     // blocked lookup: rows in alpha-major order
+    const uint32_t *abeta;   // blocked lookup: their beta strings
     const int64_t *hptr;     // stored rows (or nullptr): row offsets, hcb blocks of ns + 1
     const int32_t *hcol;     // stored rows: targets
     const double *hval;      // stored rows: values

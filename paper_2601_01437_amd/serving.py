@@ -241,7 +241,9 @@ def estimate_system_bytes(n: int, na: int, nb: int, n_dets: int | None) -> int:
         cap = 64
         while cap < 2 * ns:
             cap <<= 1
-        b += 12 * cap + (1 << 25) // 8 + 4 * (1 << min(n, 24)) + 4 * (ns + 1)
+        # hash and membership bitmap; beta-major and alpha-major block tables (string
+        # -> block, block starts, and the alpha-major rows with their beta strings)
+        b += 12 * cap + (1 << 25) // 8 + 8 * (1 << min(n, 24)) + 8 * (ns + 1) + 8 * ns
     return int(b * 1.25) + (4 << 20)
 
 
