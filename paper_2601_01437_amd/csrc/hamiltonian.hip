@@ -108,7 +108,10 @@ __device__ __forceinline__ int64_t find_row(const HamArgs &A, uint32_t al, uint3
 }
 
 constexpr int kMaxSingles = 256;   // n <= 32: na * (n - na) <= 256
-constexpr int kScanFactor = 8;     // scan a block when it holds <= 8x the candidates it replaces
+#ifndef IRL_SCAN_FACTOR
+#define IRL_SCAN_FACTOR 8
+#endif
+constexpr int kScanFactor = IRL_SCAN_FACTOR;   // scan a block when it holds <= this many times the candidates it replaces
 constexpr int kMaxPairs = 496;     // C(32, 2)
 
 struct WaveLists {
