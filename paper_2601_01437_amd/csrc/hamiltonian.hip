@@ -68,17 +68,21 @@ __device__ __forceinline__ double single_value(const double *h, const double *g,
 //   kLkHash    any set: membership bitmap, then open-addressing hash
 //   kLkBlocks  selected set: beta -> contiguous row block, binary search on alpha
 
-// row of alpha string `al` inside the rows [lo, hi) that share one beta string
+// row of alpha string `al` inside the rows [lo, hi) that share one beta string: a
+// search of fixed length (ceil(log2(hi - lo)) halvings, the same for every lane that
+// searches the same block) over the keys' low words, then one equality test
 __device__ __forceinline__ int64_t search_block(const uint64_t *keys, int64_t lo, int64_t hi,
                                                 uint32_t al)
 {
-    while (lo < hi) {
-        const int64_t mid = (lo + hi) >> 1;
-        const uint32_t a = (uint32_t)keys[mid];
-        if (a == al) return mid;
-        if (a < al) lo = mid + 1; else hi = mid;
+    const uint32_t *alpha = reinterpret_cast<const uint32_t *>(keys);   // low word of key r at 2 r
+    int32_t base = (int32_t)lo, len = (int32_t)(hi - lo);
+    if (len <= 0) return -1;
+    while (len > 1) {
+        const int32_t half = len >> 1;
+        base = alpha[2 * (int64_t)(base + half)] <= al ? base + half : base;
+        len -= half;
     }
-    return -1;
+    return alpha[2 * (int64_t)base] == al ? (int64_t)base : -1;
 }
 
 template <int LK>
