@@ -195,6 +195,24 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
+// Visits p = lo + lane, lo + lane + stride, ... < hi with key(p) loaded four at a
+// time, so that four loads are in flight before the first one is used; past hi the
+// key is `none`, which the callers choose so that it matches no excitation.
+template <typename LD, typename FN>
+__device__ __forceinline__ void scan4(int64_t lo, int64_t hi, int lane, int stride, uint32_t none, LD key, FN fn)
+{
+    for (int64_t p0 = lo + lane; p0 < hi; p0 += 4 * (int64_t)stride) {
+        uint32_t k[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t p = p0 + (int64_t)u * stride;
+            k[u] = p < hi ? key(p) : none;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) fn(p0 + (int64_t)u * stride, k[u]);
+    }
+}
+
 // Evaluate the candidates of one determinant on one lane (stride 64).  OP is
 // called with (target row, sign, kind, value) for every target inside the set.
 template <int LK, typename OP>
@@ -202,6 +220,8 @@ __device__ __forceinline__ void visit_row(const HamArgs &A, const WaveLists &L, 
                                           uint32_t be, int lane, int stride, OP op)
 {
     const int n = A.n, na = A.na, nb = A.nb, va = n - na, vb = n - nb;
+    const uint32_t *alpha32 = reinterpret_cast<const uint32_t *>(A.keys);   // low word of key r at 2 r
+    (void)alpha32;
     // Blocked lookup: a short own-beta block is scanned (its members that differ
     // from the row's alpha string by one or two orbitals are exactly the alpha
     // singles and alpha-alpha doubles inside the set) instead of probing every
@@ -211,8 +231,8 @@ __device__ __forceinline__ void visit_row(const HamArgs &A, const WaveLists &L, 
         const int cand = na * va + (na * (na - 1) / 2) * (va * (va - 1) / 2);
         scan_own = (L.own_hi - L.own_lo) <= kScanFactor * cand;
         if (scan_own) {
-            for (int64_t p = L.own_lo + lane; p < L.own_hi; p += stride) {
-                const uint32_t a2 = (uint32_t)A.keys[p];
+            scan4(L.own_lo, L.own_hi, lane, stride, al, [&](int64_t p) { return alpha32[2 * p]; },
+                  [&](int64_t p, uint32_t a2) {
                 const uint32_t x = al ^ a2;
                 const int pc = __popc(x);
                 if (pc == 2) {
@@ -229,7 +249,7 @@ __device__ __forceinline__ void visit_row(const HamArgs &A, const WaveLists &L, 
                     const double v = gint(A.g, n, i, a, j, b) - gint(A.g, n, i, b, j, a);
                     op(p, s1 * s2, 3, (s1 * s2) * v);
                 }
-            }
+            });
         }
     }
     // Blocked lookup, alpha side: the rows sharing this row's alpha string (its
@@ -241,8 +261,8 @@ __device__ __forceinline__ void visit_row(const HamArgs &A, const WaveLists &L, 
         const int cand = nb * vb + (nb * (nb - 1) / 2) * (vb * (vb - 1) / 2);
         scan_alpha = (L.ahi - L.alo) <= kScanFactor * cand;
         if (scan_alpha) {
-            for (int64_t p = L.alo + lane; p < L.ahi; p += stride) {
-                const uint32_t b2 = A.abeta[p];
+            scan4(L.alo, L.ahi, lane, stride, be, [&](int64_t p) { return A.abeta[p]; },
+                  [&](int64_t p, uint32_t b2) {
                 const uint32_t x = be ^ b2;
                 const int pc = __popc(x);
                 if (pc == 2) {
@@ -259,7 +279,7 @@ __device__ __forceinline__ void visit_row(const HamArgs &A, const WaveLists &L, 
                     const double v = gint(A.g, n, i, a, j, b) - gint(A.g, n, i, b, j, a);
                     op((int64_t)A.arow[p], s1 * s2, 4, (s1 * s2) * v);
                 }
-            }
+            });
         }
     }
     // alpha and beta singles
@@ -323,14 +343,14 @@ __device__ __forceinline__ void visit_row(const HamArgs &A, const WaveLists &L, 
             const uint32_t pb = L.sB[f];
             const int j = pb & 31, b = (pb >> 5) & 31, sgb = (pb >> 10) & 1 ? -1 : 1;
             if (hi - lo <= kScanFactor * cA) {
-                for (int64_t p = lo + lane; p < hi; p += stride) {
-                    const uint32_t a2 = (uint32_t)A.keys[p];
+                scan4(lo, hi, lane, stride, al, [&](int64_t p) { return alpha32[2 * p]; },
+                      [&](int64_t p, uint32_t a2) {
                     const uint32_t x = al ^ a2;
-                    if (__popc(x) != 2) continue;
+                    if (__popc(x) != 2) return;
                     const int i = __ffs(al & x) - 1, a = __ffs(a2 & x) - 1;
                     const int sg = move_sign(al, i, a) * sgb;
                     op(p, sg, 5, sg * gint(A.g, n, i, a, j, b));
-                }
+                });
             } else {
                 for (int xa = lane; xa < cA; xa += stride) {
                     const int64_t r = search_block(A.keys, lo, hi, L.sAstr[xa]);
