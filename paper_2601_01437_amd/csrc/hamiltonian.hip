@@ -88,6 +88,26 @@ __device__ __forceinline__ int64_t search_block(const uint64_t *keys, int64_t lo
     return alpha[2 * (int64_t)base] == al ? (int64_t)base : -1;
 }
 
+// two searches of the same block in lockstep (two loads in flight per halving)
+__device__ __forceinline__ void search_block2(const uint64_t *keys, int64_t lo, int64_t hi, uint32_t a0, uint32_t a1,
+                                              int64_t &r0, int64_t &r1)
+{
+    const uint32_t *alpha = reinterpret_cast<const uint32_t *>(keys);
+    int32_t b0 = (int32_t)lo, b1 = (int32_t)lo, len = (int32_t)(hi - lo);
+    r0 = r1 = -1;
+    if (len <= 0) return;
+    while (len > 1) {
+        const int32_t half = len >> 1;
+        const uint32_t k0 = alpha[2 * (int64_t)(b0 + half)], k1 = alpha[2 * (int64_t)(b1 + half)];
+        b0 = k0 <= a0 ? b0 + half : b0;
+        b1 = k1 <= a1 ? b1 + half : b1;
+        len -= half;
+    }
+    const uint32_t k0 = alpha[2 * (int64_t)b0], k1 = alpha[2 * (int64_t)b1];
+    r0 = k0 == a0 ? (int64_t)b0 : -1;
+    r1 = k1 == a1 ? (int64_t)b1 : -1;
+}
+
 template <int LK>
 __device__ __forceinline__ int64_t find_row(const HamArgs &A, uint32_t al, uint32_t be)
 {
@@ -352,13 +372,23 @@ __device__ __forceinline__ void visit_row(const HamArgs &A, const WaveLists &L, 
                     op(p, sg, 5, sg * gint(A.g, n, i, a, j, b));
                 });
             } else {
-                for (int xa = lane; xa < cA; xa += stride) {
-                    const int64_t r = search_block(A.keys, lo, hi, L.sAstr[xa]);
-                    if (r >= 0) {
+                // two alpha singles per lane and pass, searched together; the second
+                // of a pair past cA searches the first's string and is not used
+                for (int xa = lane; xa < cA; xa += 2 * stride) {
+                    const int xb = xa + stride < cA ? xa + stride : xa;
+                    int64_t ra, rb;
+                    search_block2(A.keys, lo, hi, L.sAstr[xa], L.sAstr[xb], ra, rb);
+                    if (ra >= 0) {
                         const uint32_t pa = L.sA[xa];
                         const int i = pa & 31, a = (pa >> 5) & 31;
                         const int sg = ((pa >> 10) & 1 ? -1 : 1) * sgb;
-                        op(r, sg, 5, sg * gint(A.g, n, i, a, j, b));
+                        op(ra, sg, 5, sg * gint(A.g, n, i, a, j, b));
+                    }
+                    if (xa + stride < cA && rb >= 0) {
+                        const uint32_t pa = L.sA[xb];
+                        const int i = pa & 31, a = (pa >> 5) & 31;
+                        const int sg = ((pa >> 10) & 1 ? -1 : 1) * sgb;
+                        op(rb, sg, 5, sg * gint(A.g, n, i, a, j, b));
                     }
                 }
             }
