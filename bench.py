@@ -302,6 +302,39 @@ def run_batch_bench(args):
         f"{(time.perf_counter() - t) * 1e3:.0f} ms")
     kernels = [s.info.ham_kernel for s in systems]
     opts = dict(m=20, k_keep=1, tol=1e-12)
+    tune_report = None
+    if args.autotune:
+        # launch shapes per member from the autotuner (bit-neutral; outside the
+        # timed passes, like the stored-row build); the untuned sequential pass
+        # is timed first for comparison
+        from paper_2601_01437_amd import autotune
+        for s, w, th0 in zip(systems, wls, thetas0):
+            s.step(th0.clone(), w.V, w.H, ws_flags=fl, want_dtheta=False, **opts)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s, w, th0 in zip(systems, wls, thetas0):
+            s.step(th0.clone(), w.V, w.H, ws_flags=fl, want_dtheta=False, **opts)
+        torch.cuda.synchronize()
+        t_untuned = time.perf_counter() - t0
+        cache = autotune.TuneCache(args.tune_cache)
+        t0 = time.perf_counter()
+        choices = []
+        for s, w, th0 in zip(systems, wls, thetas0):
+            s.evaluate(w.V, w.H, th0.clone(), ws_flags=fl, want_grad=False)
+            choices.append(autotune.tune_system(s, w.H, cache=cache))
+        torch.cuda.synchronize()
+        t_tune = time.perf_counter() - t0
+        tuned = {}
+        for c in choices:
+            for name, e in c.items():
+                d = tuned.setdefault(name, {"members": 0, "changed": 0, "cached": 0})
+                d["members"] += 1
+                d["changed"] += e["value"] != 0
+                d["cached"] += e["cached"]
+        tune_report = {"sequential_untuned_ms": t_untuned * 1e3, "tuning_s": t_tune,
+                       "knobs": tuned, "cache": args.tune_cache,
+                       "values": [{k: e["value"] for k, e in c.items()} for c in choices]}
+        log(f"autotune: {t_tune:.1f} s, {tuned}; untuned sequential {t_untuned * 1e3:.1f} ms")
 
     def solo_pass():
         out = []
@@ -389,6 +422,7 @@ def run_batch_bench(args):
         "kernels_batched": k_batch,
         "applies": [r[3] for r in r_batch],
         "converged": sum(1 for r in r_batch if r[0] in (0, 2)),
+        "autotune": tune_report,
     }
     print(json.dumps(out), flush=True)
 
@@ -1085,6 +1119,10 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=20.0,
                     help="c5: length of the arrival window in seconds")
     ap.add_argument("--solves", type=int, default=64, help="c4: number of independent solves")
+    ap.add_argument("--no-autotune", dest="autotune", action="store_false",
+                    help="c4: keep the built-in launch shapes (default: per-member autotuned shapes)")
+    ap.add_argument("--tune-cache", default=None, metavar="JSON",
+                    help="c4: autotuner cache file (read if present, written after tuning)")
     ap.add_argument("--hbm-budget-gb", type=float, default=240.0,
                     help="c4: device memory admitted per wave of batched solves")
     ap.add_argument("--precision", default=None, choices=["fp64", "fp32"],

@@ -548,6 +548,35 @@ int irl_stats_select(irl_system *sys, uint32_t kinds);
  * (count[IRL_STAT_KINDS]) since the last irl_stats_enable(sys, 1). */
 int irl_stats_get(irl_system *sys, double *ms, int64_t *count, void *stream);
 
+/* ---- launch-shape tuning ------------------------------------------------- */
+
+/* Launch shapes that a caller (the package's autotuner) may choose per system.
+ * Each one only moves rows between workgroups: every row's sums are formed by
+ * one wavefront in a fixed order, so results are bit-for-bit the same for every
+ * value.  The operator's cost per matrix-vector product (Methods, "Practical
+ * Matrix-Free Implementation") is what the choice changes. */
+enum irl_tune_knob {
+    IRL_TUNE_LUT_BLOCKS = 0,    /* workgroups of the table-driven forward pass and D~ v
+                                   (selected sets, n <= 24, H >= 48); default 256,
+                                   at least 128 rows each */
+    IRL_TUNE_PULL_BLOCKS = 1    /* workgroup cap of the enumerating Hamiltonian apply
+                                   (hashed, rank or beta-blocked pull, 4 rows per
+                                   workgroup in grid strides); default 65536 */
+};
+
+/* Set `knob` of `sys` to `value` (0 restores the default).  Takes effect at the
+ * next launch; captured Lanczos cycles are recaptured.  IRL_EINVAL for an
+ * unknown knob, a negative value, or a value above 65536 (LUT) or 2^20 (pull). */
+int irl_tune_set(irl_system *sys, int32_t knob, int32_t value);
+
+/* Current value of `knob` (0 = default) in *value, and in *applies 1 when the
+ * system's kernels use it: for IRL_TUNE_LUT_BLOCKS, D~ v over the whole set with
+ * a network of `hidden` units runs the table-driven kernel; for
+ * IRL_TUNE_PULL_BLOCKS, the Hamiltonian apply enumerates excitations (no stored
+ * rows, not the string product).  Host pointers; IRL_EINVAL for an unknown knob
+ * or hidden < 1 with IRL_TUNE_LUT_BLOCKS. */
+int irl_tune_get(irl_system *sys, int32_t knob, int32_t hidden, int32_t *value, int32_t *applies);
+
 /* ---- bit-exact test surface ----------------------------------------------- */
 
 /* Copy the ascending key array (n_dets uint64) to host memory out. */

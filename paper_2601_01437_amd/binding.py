@@ -14,6 +14,12 @@ from ctypes import POINTER, c_char_p, c_double, c_int8, c_int32, c_int64, c_size
 from ctypes import c_uint32, c_uint64, c_void_p
 
 import numpy as np
+# torch owns the device memory and streams the library works on, so both must run
+# on one HIP runtime.  torch ships its own libamdhip64.so.7 (same soname as the
+# system's), and whichever is loaded first serves the process: load torch before
+# the library so the library's HIP and HSA dependencies resolve to torch's copies.
+# (Loaded the other way round, the library's first device call found no device.)
+import torch  # noqa: F401
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "lib", "libirlnqs.so")
 if not os.path.exists(LIB_PATH):
@@ -34,6 +40,7 @@ IRL_SYS_FORCE_HASH = 1
 IRL_SYS_FORCE_PULL = 2
 IRL_SYS_STORE_SLICED = 4
 IRL_SYS_STORE_BLOCKS = 8
+IRL_TUNE_LUT_BLOCKS, IRL_TUNE_PULL_BLOCKS = 0, 1
 STAT_KINDS = ("dtilde_build", "ham_apply", "gemv", "gemv_t", "reduce", "energy", "lanczos", "ritz",
               "gemv_fp32", "gemv_t_fp32", "vmc")
 
@@ -129,6 +136,8 @@ _sigs = {
     "irl_stats_enable": (c_int32, [_SYS, c_int32]),
     "irl_stats_select": (c_int32, [_SYS, c_uint32]),
     "irl_stats_get": (c_int32, [_SYS, c_void_p, c_void_p, c_void_p]),
+    "irl_tune_set": (c_int32, [_SYS, c_int32, c_int32]),
+    "irl_tune_get": (c_int32, [_SYS, c_int32, c_int32, POINTER(c_int32), POINTER(c_int32)]),
     "irl_batch_create": (c_int32, [c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_uint32,
                                    POINTER(c_void_p)]),
     "irl_batch_destroy": (None, [c_void_p]),
@@ -311,6 +320,17 @@ def irl_stats_get(sys, stream=None):
     cnt = np.zeros(len(STAT_KINDS), dtype=np.int64)
     _check(_lib.irl_stats_get(sys, ms.ctypes.data, cnt.ctypes.data, _stream(stream)), sys)
     return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(STAT_KINDS)}
+
+
+def irl_tune_set(sys, knob, value):
+    _check(_lib.irl_tune_set(sys, int(knob), int(value)), sys)
+
+
+def irl_tune_get(sys, knob, hidden=1):
+    """(value, applies): the knob's value (0 = default) and whether the system uses it."""
+    value, applies = c_int32(0), c_int32(0)
+    _check(_lib.irl_tune_get(sys, int(knob), int(hidden), ctypes.byref(value), ctypes.byref(applies)), sys)
+    return int(value.value), bool(applies.value)
 
 
 def irl_batch_create(systems, nqs, ws, ws_flags):

@@ -402,11 +402,13 @@ struct CycleKey {
     bool vmc = false;
     int64_t vmc_rows = 0;
     const void *hptr = nullptr;
+    int32_t tune_lut = 0, tune_pull = 0;   // launch shapes recorded in the graph
     bool operator==(const CycleKey &o) const
     {
         return ws == o.ws && total == o.total && ns == o.ns && ncols == o.ncols && flags == o.flags && m == o.m &&
                k == o.k && mode == o.mode && prec == o.prec && ham_kernel == o.ham_kernel && seed == o.seed &&
-               vmc == o.vmc && vmc_rows == o.vmc_rows && hptr == o.hptr;
+               vmc == o.vmc && vmc_rows == o.vmc_rows && hptr == o.hptr && tune_lut == o.tune_lut &&
+               tune_pull == o.tune_pull;
     }
 };
 
@@ -572,6 +574,8 @@ int irl_solve(irl_system *s, void *ws, const WsLayout &L, const irl_solver_opts 
         key.vmc = s->vmc;
         key.vmc_rows = s->vmc_rows;
         key.hptr = s->d.scb ? (const void *)s->d.sval : (const void *)s->d.hptr;
+        key.tune_lut = s->tune_lut_blocks;
+        key.tune_pull = s->tune_pull_blocks;
         cg = cycle_entry(s, key);
     }
     int pending = -1;   // restart not yet launched: from basis `pending` (graph replay)
@@ -1556,6 +1560,42 @@ int irl_stats_select(irl_system *s, uint32_t kinds)
     if (kinds >> IRL_STAT_KINDS) return set_err(s, IRL_EINVAL, "kinds names a bit beyond the last irl_stat_kind");
     s->stat_mask = kinds;
     return IRL_OK;
+}
+
+int irl_tune_set(irl_system *s, int32_t knob, int32_t value)
+{
+    if (!s) return IRL_EINVAL;
+    if (value < 0) return set_err(s, IRL_EINVAL, "tuning value must be 0 (default) or positive");
+    switch (knob) {
+    case IRL_TUNE_LUT_BLOCKS:
+        if (value > 65536) return set_err(s, IRL_EINVAL, "IRL_TUNE_LUT_BLOCKS above 65536");
+        s->tune_lut_blocks = value;
+        return IRL_OK;
+    case IRL_TUNE_PULL_BLOCKS:
+        if (value > (1 << 20)) return set_err(s, IRL_EINVAL, "IRL_TUNE_PULL_BLOCKS above 2^20");
+        s->tune_pull_blocks = value;
+        return IRL_OK;
+    default:
+        return set_err(s, IRL_EINVAL, "unknown tuning knob");
+    }
+}
+
+int irl_tune_get(irl_system *s, int32_t knob, int32_t hidden, int32_t *value, int32_t *applies)
+{
+    if (!s || !value || !applies) return IRL_EINVAL;
+    switch (knob) {
+    case IRL_TUNE_LUT_BLOCKS:
+        if (hidden < 1) return set_err(s, IRL_EINVAL, "hidden width must be positive");
+        *value = s->tune_lut_blocks;
+        *applies = irl::fac_jvp_uses_lut(s, s->ns, hidden);
+        return IRL_OK;
+    case IRL_TUNE_PULL_BLOCKS:
+        *value = s->tune_pull_blocks;
+        *applies = (s->ham_kernel == 0 || s->ham_kernel == 1 || s->ham_kernel == 3) ? 1 : 0;
+        return IRL_OK;
+    default:
+        return set_err(s, IRL_EINVAL, "unknown tuning knob");
+    }
 }
 
 int irl_stats_get(irl_system *s, double *ms, int64_t *count, void *stream)

@@ -1682,10 +1682,16 @@ __device__ __forceinline__ void lut_build(LutShared<NG> &T, const double *__rest
     }
 }
 
-// this wave's part of the workgroup's block of rows: whole batches, in wave order
+// this wave's part of the workgroup's block of rows: whole batches, in wave order.
+// Blocks hold a multiple of kLutRB rows, so every batch starts at a multiple of
+// kLutRB and a row's place in the butterfly (row mod kLutRB) does not depend on the
+// workgroup count: the sums are the same for any grid.
 __device__ __forceinline__ void lut_wave_rows(int64_t ns, int wv, int nwv, int64_t &r0, int64_t &r1)
 {
-    bits_block(ns, gridDim.x, blockIdx.x, r0, r1);
+    const int64_t bper = ((ns + gridDim.x - 1) / gridDim.x + kLutRB - 1) / kLutRB * kLutRB;
+    r0 = (int64_t)blockIdx.x * bper;
+    r1 = r0 + bper < ns ? r0 + bper : ns;
+    if (r0 > ns) r0 = ns;
     const int64_t nb = (r1 - r0 + kLutRB - 1) / kLutRB, per = (nb + nwv - 1) / nwv;
     const int64_t q0 = r0 + (int64_t)wv * per * kLutRB, q1 = q0 + per * kLutRB;
     r1 = q1 < r1 ? q1 : r1;
@@ -1765,10 +1771,13 @@ bool fac_lut_ok(const irl_system *s, int H)
     return s->n <= kBitsMaxN && H >= kBitsMinH;
 }
 
-// row blocks of the table-driven kernels: at most kLutBlocks, at least 128 rows each
-unsigned lut_blocks(int64_t ns)
+// row blocks of the table-driven kernels: at most kLutBlocks (or the system's
+// tuned count), at least 128 rows each.  Each row's sums are formed by one wave in
+// a fixed order, so the count moves rows between workgroups and nothing else.
+unsigned lut_blocks(const irl_system *s, int64_t ns)
 {
-    int64_t per = (ns + kLutBlocks - 1) / kLutBlocks;
+    const int64_t cap = s->tune_lut_blocks > 0 ? s->tune_lut_blocks : kLutBlocks;
+    int64_t per = (ns + cap - 1) / cap;
     if (per < 128) per = 128;
     return (unsigned)((ns + per - 1) / per);
 }
@@ -1886,6 +1895,13 @@ int fac_full_ranges(int64_t nA, int64_t nB, int n, int H)
     return (int)(S < 1 ? 1 : S);
 }
 
+int fac_jvp_uses_lut(const irl_system *s, int64_t ns, int H)
+{
+    const bool full = s->full && ns == s->ns && s->nA * s->nB == s->ns && s->d.strA && s->d.strB &&
+                      fac_full_ranges(s->nA, s->nB, s->n, H) > 0;
+    return (!(full && H <= 64) && fac_lut_ok(s, H)) ? 1 : 0;
+}
+
 int fac_vjp_blocks(const irl_system *s, const WsLayout &L)
 {
     if (L.kf_S > 0 && s->full) return (int)(((s->nB + kFullTB - 1) / kFullTB) * L.kf_S);
@@ -1918,7 +1934,7 @@ hipError_t launch_fac_forward(const irl_system *s, const WsLayout &L, void *ws, 
 #ifndef IRL_FAC_NO_LUT_FWD
     if (fac_lut_ok(s, H)) {
         const BitsArgs B{R.keys, R.psi, R.dfac, R.ns, s->n, V, H};
-        const unsigned nblk = lut_blocks(R.ns);
+        const unsigned nblk = lut_blocks(s, R.ns);
         switch ((s->n + 3) / 4) {
         case 1: k_fac_forward_lut<1><<<nblk, kLutThreads, 0, st>>>(B, theta, psi, dfac); break;
         case 2: k_fac_forward_lut<2><<<nblk, kLutThreads, 0, st>>>(B, theta, psi, dfac); break;
@@ -1962,7 +1978,7 @@ hipError_t launch_fac_jvp_rows(const irl_system *s, const WsLayout &L, const Fac
     }
     if (fac_lut_ok(s, H)) {
         const BitsArgs B{R.keys, R.psi, R.dfac, R.ns, s->n, V, H};
-        const unsigned nblk = lut_blocks(R.ns);
+        const unsigned nblk = lut_blocks(s, R.ns);
         switch ((s->n + 3) / 4) {
         case 1: k_fac_jvp_lut<1><<<nblk, kLutThreads, 0, st>>>(B, v, zero_v0, w); break;
         case 2: k_fac_jvp_lut<2><<<nblk, kLutThreads, 0, st>>>(B, v, zero_v0, w); break;

@@ -1068,7 +1068,10 @@ hipError_t launch_ham_apply_rows(const irl_system *s, const double *w, double *u
     }
     HamArgs A = ham_view(s);
     int64_t blocks = (r1 - r0 + 3) / 4;
-    if (blocks > 65536) blocks = 65536;
+    // the enumerating kernels take rows in grid strides and sum each row on one
+    // wavefront, so the cap (tunable) only moves rows between workgroups
+    const int64_t cap = (s->ham_kernel != 4 && s->tune_pull_blocks > 0) ? s->tune_pull_blocks : 65536;
+    if (blocks > cap) blocks = cap;
     if (s->ham_kernel == 4 && A.sval) return launch_ham_sliced(s, A, w, u, r0, r1, st);
     if (s->ham_kernel == 4) {
         for (int b = 0; b < A.hcb; ++b) {

@@ -231,6 +231,10 @@ struct irl_system {
     int ham_kernel = 0;       // 0 hashed pull, 1 rank pull, 2 string product, 3 blocked pull,
                               // 4 stored rows
     int lookup = 0;           // irl::LookupMode of the excitation enumeration
+    // launch shapes set by irl_tune_set (0: the built-in default); both only move
+    // rows between workgroups, so results do not depend on them
+    int32_t tune_lut_blocks = 0;    // workgroups of the table-driven forward pass and D~ v
+    int32_t tune_pull_blocks = 0;   // workgroup cap of the enumerating Hamiltonian apply
     int device = 0;
     size_t dev_bytes = 0;
     irl::SystemDev d;
@@ -370,6 +374,9 @@ hipError_t launch_fac_vjp_rows(const irl_system *s, const WsLayout &L, void *ws,
 int fac_row_blocks_n(const irl_system *s, int64_t ns, int hfac);
 // partial rows left by launch_fac_vjp over every row of ws
 int fac_vjp_blocks(const irl_system *s, const WsLayout &L);
+// 1 when D~ v on `ns` rows of this system with hidden width H runs the
+// table-driven kernel (the one IRL_TUNE_LUT_BLOCKS shapes)
+int fac_jvp_uses_lut(const irl_system *s, int64_t ns, int H);
 hipError_t launch_nqs_dtilde(const irl_system *s, int V, int H, const double *theta,
                              const WsLayout &L, void *ws, hipStream_t st);
 hipError_t launch_dtilde_import(const void *D, int64_t ld, int64_t ncols, int dtype,
