@@ -103,7 +103,10 @@ def tune_system(system, hidden, cache=None, reps=5, seed=0, device_name=None):
     import torch
 
     cache = cache if cache is not None else TuneCache(None)
-    dev = device_name or torch.cuda.get_device_name(system.device)
+    if device_name is None:
+        props = torch.cuda.get_device_properties(system.device)
+        device_name = f"{props.name} {getattr(props, 'gcnArchName', '')}".strip()
+    dev = device_name
     info = B.irl_system_info_get(system.handle)
     gen = torch.Generator(device="cpu").manual_seed(seed)
     v = torch.randn(system.ncols, generator=gen, dtype=torch.float64).to(system.device)

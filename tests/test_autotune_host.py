@@ -39,3 +39,29 @@ def test_cache_round_trip(tmp_path):
     c2 = autotune.TuneCache(str(path))
     assert c2.get("k") == 512
     autotune.TuneCache(None).save()   # no path: nothing written
+
+
+def test_binding_loads_torch_before_the_library():
+    """The library must share torch's HIP runtime, so the binding imports torch
+    before it loads the library (checked in a fresh interpreter)."""
+    import subprocess
+    import sys
+    code = ("import sys, builtins\n"
+            "order = []\n"
+            "real = builtins.__import__\n"
+            "def imp(name, *a, **k):\n"
+            "    if name in ('torch', 'ctypes') and name not in order: order.append(name)\n"
+            "    return real(name, *a, **k)\n"
+            "builtins.__import__ = imp\n"
+            "import ctypes\n"
+            "real_cdll = ctypes.CDLL\n"
+            "def cdll(path, *a, **k):\n"
+            "    if 'libirlnqs' in str(path): order.append('lib:' + str('torch' in sys.modules))\n"
+            "    return real_cdll(path, *a, **k)\n"
+            "ctypes.CDLL = cdll\n"
+            "import paper_2601_01437_amd.binding\n"
+            "print([o for o in order if o.startswith('lib:')])\n")
+    root = __import__("os").path.dirname(__import__("os").path.dirname(__import__("os").path.abspath(__file__)))
+    out = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip().splitlines()[-1] == "['lib:True']"
