@@ -561,7 +561,7 @@ enum irl_tune_knob {
                                    at least 128 rows each */
     IRL_TUNE_PULL_BLOCKS = 1    /* workgroup cap of the enumerating Hamiltonian apply
                                    (hashed, rank or beta-blocked pull, 4 rows per
-                                   workgroup in grid strides); default 65536 */
+                                   workgroup in grid strides); default 2^20 */
 };
 
 /* Set `knob` of `sys` to `value` (0 restores the default).  Takes effect at the

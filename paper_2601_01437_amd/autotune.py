@@ -26,7 +26,7 @@ from . import binding as B
 # knob -> (name, kernel class timed by irl_stats, candidate values; 0 is the built-in default)
 KNOBS = {
     B.IRL_TUNE_LUT_BLOCKS: ("lut_blocks", "gemv", (0, 128, 512, 1024, 2048)),
-    B.IRL_TUNE_PULL_BLOCKS: ("pull_blocks", "ham_apply", (0, 8192, 16384, 32768, 131072, 262144)),
+    B.IRL_TUNE_PULL_BLOCKS: ("pull_blocks", "ham_apply", (0, 8192, 32768, 131072)),
 }
 
 
