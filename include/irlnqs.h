@@ -559,21 +559,24 @@ enum irl_tune_knob {
     IRL_TUNE_LUT_BLOCKS = 0,    /* workgroups of the table-driven forward pass and D~ v
                                    (selected sets, n <= 24, H >= 48); default 256,
                                    at least 128 rows each */
-    IRL_TUNE_PULL_BLOCKS = 1    /* workgroup cap of the enumerating Hamiltonian apply
-                                   (hashed, rank or beta-blocked pull, 4 rows per
-                                   workgroup in grid strides); default 2^20 */
+    IRL_TUNE_PULL_BLOCKS = 1,   /* workgroup cap of the enumerating Hamiltonian apply
+                                   (hashed, rank or beta-blocked pull, one row per
+                                   wavefront in grid strides); default 2^20 */
+    IRL_TUNE_PULL_WAVES = 2     /* wavefronts (rows) per workgroup of that apply: 1, 2
+                                   or 4; default 4 */
 };
 
 /* Set `knob` of `sys` to `value` (0 restores the default).  Takes effect at the
  * next launch; captured Lanczos cycles are recaptured.  IRL_EINVAL for an
- * unknown knob, a negative value, or a value above 65536 (LUT) or 2^20 (pull). */
+ * unknown knob, a negative value, a value above 65536 (LUT) or 2^20 (pull cap),
+ * or a wavefront count other than 0, 1, 2 or 4. */
 int irl_tune_set(irl_system *sys, int32_t knob, int32_t value);
 
 /* Current value of `knob` (0 = default) in *value, and in *applies 1 when the
  * system's kernels use it: for IRL_TUNE_LUT_BLOCKS, D~ v over the whole set with
  * a network of `hidden` units runs the table-driven kernel; for
- * IRL_TUNE_PULL_BLOCKS, the Hamiltonian apply enumerates excitations (no stored
- * rows, not the string product).  Host pointers; IRL_EINVAL for an unknown knob
+ * IRL_TUNE_PULL_BLOCKS and IRL_TUNE_PULL_WAVES, the Hamiltonian apply enumerates
+ * excitations (no stored rows, not the string product).  Host pointers; IRL_EINVAL for an unknown knob
  * or hidden < 1 with IRL_TUNE_LUT_BLOCKS. */
 int irl_tune_get(irl_system *sys, int32_t knob, int32_t hidden, int32_t *value, int32_t *applies);
 

@@ -40,7 +40,7 @@ IRL_SYS_FORCE_HASH = 1
 IRL_SYS_FORCE_PULL = 2
 IRL_SYS_STORE_SLICED = 4
 IRL_SYS_STORE_BLOCKS = 8
-IRL_TUNE_LUT_BLOCKS, IRL_TUNE_PULL_BLOCKS = 0, 1
+IRL_TUNE_LUT_BLOCKS, IRL_TUNE_PULL_BLOCKS, IRL_TUNE_PULL_WAVES = 0, 1, 2
 STAT_KINDS = ("dtilde_build", "ham_apply", "gemv", "gemv_t", "reduce", "energy", "lanczos", "ritz",
               "gemv_fp32", "gemv_t_fp32", "vmc")
 

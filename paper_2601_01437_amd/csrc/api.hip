@@ -402,13 +402,13 @@ struct CycleKey {
     bool vmc = false;
     int64_t vmc_rows = 0;
     const void *hptr = nullptr;
-    int32_t tune_lut = 0, tune_pull = 0;   // launch shapes recorded in the graph
+    int32_t tune_lut = 0, tune_pull = 0, tune_waves = 0;   // launch shapes recorded in the graph
     bool operator==(const CycleKey &o) const
     {
         return ws == o.ws && total == o.total && ns == o.ns && ncols == o.ncols && flags == o.flags && m == o.m &&
                k == o.k && mode == o.mode && prec == o.prec && ham_kernel == o.ham_kernel && seed == o.seed &&
                vmc == o.vmc && vmc_rows == o.vmc_rows && hptr == o.hptr && tune_lut == o.tune_lut &&
-               tune_pull == o.tune_pull;
+               tune_pull == o.tune_pull && tune_waves == o.tune_waves;
     }
 };
 
@@ -576,6 +576,7 @@ int irl_solve(irl_system *s, void *ws, const WsLayout &L, const irl_solver_opts 
         key.hptr = s->d.scb ? (const void *)s->d.sval : (const void *)s->d.hptr;
         key.tune_lut = s->tune_lut_blocks;
         key.tune_pull = s->tune_pull_blocks;
+        key.tune_waves = s->tune_pull_waves;
         cg = cycle_entry(s, key);
     }
     int pending = -1;   // restart not yet launched: from basis `pending` (graph replay)
@@ -1575,6 +1576,11 @@ int irl_tune_set(irl_system *s, int32_t knob, int32_t value)
         if (value > (1 << 20)) return set_err(s, IRL_EINVAL, "IRL_TUNE_PULL_BLOCKS above 2^20");
         s->tune_pull_blocks = value;
         return IRL_OK;
+    case IRL_TUNE_PULL_WAVES:
+        if (value != 0 && value != 1 && value != 2 && value != 4)
+            return set_err(s, IRL_EINVAL, "IRL_TUNE_PULL_WAVES must be 0, 1, 2 or 4");
+        s->tune_pull_waves = value;
+        return IRL_OK;
     default:
         return set_err(s, IRL_EINVAL, "unknown tuning knob");
     }
@@ -1590,7 +1596,8 @@ int irl_tune_get(irl_system *s, int32_t knob, int32_t hidden, int32_t *value, in
         *applies = irl::fac_jvp_uses_lut(s, s->ns, hidden);
         return IRL_OK;
     case IRL_TUNE_PULL_BLOCKS:
-        *value = s->tune_pull_blocks;
+    case IRL_TUNE_PULL_WAVES:
+        *value = knob == IRL_TUNE_PULL_BLOCKS ? s->tune_pull_blocks : s->tune_pull_waves;
         *applies = (s->ham_kernel == 0 || s->ham_kernel == 1 || s->ham_kernel == 3) ? 1 : 0;
         return IRL_OK;
     default:

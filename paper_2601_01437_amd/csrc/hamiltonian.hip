@@ -454,16 +454,30 @@ __device__ __forceinline__ void pull_row(const HamArgs &A, WaveLists &L, int64_t
     end_row();
 }
 
-// rows [r0, r1), one wavefront per row, grid-stride
-template <int LK>
-__global__ __launch_bounds__(256) void k_ham_pull(HamArgs A, const double *__restrict__ w,
-                                                  double *__restrict__ u, int64_t r0, int64_t r1)
+// rows [r0, r1), one wavefront per row, NW wavefronts per workgroup, grid-stride
+template <int LK, int NW = 4>
+__global__ __launch_bounds__(64 * NW) void k_ham_pull(HamArgs A, const double *__restrict__ w,
+                                                      double *__restrict__ u, int64_t r0, int64_t r1)
 {
-    __shared__ WaveLists lists[4];
+    __shared__ WaveLists lists[NW];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int64_t nwaves = (int64_t)gridDim.x * 4;
-    for (int64_t row = r0 + (int64_t)blockIdx.x * 4 + wv; row < r1; row += nwaves)
+    const int64_t nwaves = (int64_t)gridDim.x * NW;
+    for (int64_t row = r0 + (int64_t)blockIdx.x * NW + wv; row < r1; row += nwaves)
         pull_row<LK>(A, lists[wv], row, lane, w, u);
+}
+
+template <int LK>
+static void launch_pull(const HamArgs &A, const double *w, double *u, int64_t r0, int64_t r1, int nw, int64_t cap,
+                        hipStream_t st)
+{
+    int64_t blocks = (r1 - r0 + nw - 1) / nw;
+    if (blocks > cap) blocks = cap;
+    if (nw == 1)
+        k_ham_pull<LK, 1><<<(unsigned)blocks, 64, 0, st>>>(A, w, u, r0, r1);
+    else if (nw == 2)
+        k_ham_pull<LK, 2><<<(unsigned)blocks, 128, 0, st>>>(A, w, u, r0, r1);
+    else
+        k_ham_pull<LK, 4><<<(unsigned)blocks, 256, 0, st>>>(A, w, u, r0, r1);
 }
 
 // Stored rows: u[row] = diag * w[row] + sum_p val[p] w[col[p]], one wave per row.
@@ -1069,11 +1083,11 @@ hipError_t launch_ham_apply_rows(const irl_system *s, const double *w, double *u
     HamArgs A = ham_view(s);
     int64_t blocks = (r1 - r0 + 3) / 4;
     // the enumerating kernels take rows in grid strides and sum each row on one
-    // wavefront, so the cap (tunable) only moves rows between workgroups.  By default
-    // every 4-row group gets its own workgroup up to 2^20 of them (c3: 72.7 ms per
-    // apply against 83.7 ms with a cap of 65,536 and four groups per workgroup: the
-    // rows' costs vary, and the hardware's workgroup dispatch balances them better
-    // than a fixed stride does)
+    // wavefront, so the cap and the wavefronts per workgroup (both tunable) only move
+    // rows between workgroups.  By default every group of rows gets its own workgroup
+    // up to 2^20 of them (c3: 72.7 ms per apply against 83.7 ms with a cap of 65,536
+    // and four groups per workgroup: the rows' costs vary, and the hardware's dispatch
+    // of waiting workgroups balances them better than a fixed stride does)
     const int64_t cap = s->ham_kernel == 4 ? 65536 : (s->tune_pull_blocks > 0 ? s->tune_pull_blocks : (1 << 20));
     if (blocks > cap) blocks = cap;
     if (s->ham_kernel == 4 && A.sval) return launch_ham_sliced(s, A, w, u, r0, r1, st);
@@ -1084,12 +1098,16 @@ hipError_t launch_ham_apply_rows(const irl_system *s, const double *w, double *u
             if (e != hipSuccess) return e;
         }
         return hipSuccess;
-    } else if (s->lookup == kLkBlocks)
-        k_ham_pull<kLkBlocks><<<(unsigned)blocks, 256, 0, st>>>(A, w, u, r0, r1);
+    }
+    // wavefronts (rows) per workgroup of the enumerating kernels (tunable; one row
+    // per wavefront whatever the count)
+    const int nw = s->tune_pull_waves > 0 ? s->tune_pull_waves : 4;
+    if (s->lookup == kLkBlocks)
+        launch_pull<kLkBlocks>(A, w, u, r0, r1, nw, cap, st);
     else if (s->lookup == kLkHash)
-        k_ham_pull<kLkHash><<<(unsigned)blocks, 256, 0, st>>>(A, w, u, r0, r1);
+        launch_pull<kLkHash>(A, w, u, r0, r1, nw, cap, st);
     else
-        k_ham_pull<kLkRanks><<<(unsigned)blocks, 256, 0, st>>>(A, w, u, r0, r1);
+        launch_pull<kLkRanks>(A, w, u, r0, r1, nw, cap, st);
     return hipGetLastError();
 }
 

@@ -235,6 +235,7 @@ struct irl_system {
     // rows between workgroups, so results do not depend on them
     int32_t tune_lut_blocks = 0;    // workgroups of the table-driven forward pass and D~ v
     int32_t tune_pull_blocks = 0;   // workgroup cap of the enumerating Hamiltonian apply
+    int32_t tune_pull_waves = 0;    // wavefronts (rows) per workgroup of that apply: 1, 2 or 4
     int device = 0;
     size_t dev_bytes = 0;
     irl::SystemDev d;

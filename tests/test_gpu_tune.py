@@ -47,7 +47,8 @@ def test_knobs_are_bit_neutral():
     g0 = host(g0)
     yH0, yS0 = (host(t) for t in s.apply(v))
     for knob, (name, _, cands) in autotune.KNOBS.items():
-        for c in cands + (1, 7, 157):
+        extra = (4,) if knob == B.IRL_TUNE_PULL_WAVES else (1, 7, 157)
+        for c in cands + extra:
             announce(f"knob {name} = {c}")
             B.irl_tune_set(s.handle, knob, c)
             assert B.irl_tune_get(s.handle, knob, H)[0] == c
@@ -60,6 +61,8 @@ def test_knobs_are_bit_neutral():
         B.irl_tune_set(s.handle, 99, 1)
     with pytest.raises(B.IrlError):
         B.irl_tune_set(s.handle, B.IRL_TUNE_LUT_BLOCKS, -1)
+    with pytest.raises(B.IrlError):
+        B.irl_tune_set(s.handle, B.IRL_TUNE_PULL_WAVES, 3)
 
 
 def test_tuned_step_equals_default_step():
@@ -67,11 +70,12 @@ def test_tuned_step_equals_default_step():
     s, V, H, theta = _selected(n_dets=1 << 14, H=256)
     res = []
     full, graph = B.IRL_STEP_FULL_CYCLES, B.IRL_STEP_FULL_CYCLES | B.IRL_STEP_GRAPH
-    for lut, pull, flags in [(0, 0, full), (1024, 8192, full), (0, 0, graph), (128, 262144, graph),
-                             (0, 0, graph)]:
-        announce(f"step lut={lut} pull={pull} flags={flags}")
+    for lut, pull, waves, flags in [(0, 0, 0, full), (1024, 8192, 1, full), (0, 0, 0, graph),
+                                    (128, 262144, 2, graph), (0, 0, 0, graph)]:
+        announce(f"step lut={lut} pull={pull} waves={waves} flags={flags}")
         B.irl_tune_set(s.handle, B.IRL_TUNE_LUT_BLOCKS, lut)
         B.irl_tune_set(s.handle, B.IRL_TUNE_PULL_BLOCKS, pull)
+        B.irl_tune_set(s.handle, B.IRL_TUNE_PULL_WAVES, waves)
         rc, r, dth, _ = s.step(theta.clone(), V, H, ws_flags=B.IRL_WS_FACTORED, flags=flags)
         res.append((rc, r.lambda_min, r.E_after, r.n_apply, host(dth)))
         if flags & B.IRL_STEP_GRAPH:
@@ -89,10 +93,12 @@ def test_autotune_cache(tmp_path):
     cache = autotune.TuneCache(path)
     first = autotune.tune_system(s, H, cache=cache, reps=3)
     announce(f"tuned {first}")
-    assert set(first) == {"lut_blocks", "pull_blocks"}
+    names = (("lut_blocks", B.IRL_TUNE_LUT_BLOCKS), ("pull_blocks", B.IRL_TUNE_PULL_BLOCKS),
+             ("pull_waves", B.IRL_TUNE_PULL_WAVES))
+    assert set(first) == {n for n, _ in names}
     data = json.load(open(path))
-    assert len(data) == 2
-    for name, knob in (("lut_blocks", B.IRL_TUNE_LUT_BLOCKS), ("pull_blocks", B.IRL_TUNE_PULL_BLOCKS)):
+    assert len(data) == 3
+    for name, knob in names:
         assert not first[name]["cached"]
         assert B.irl_tune_get(s.handle, knob, H)[0] == first[name]["value"]
         cands = autotune.KNOBS[knob][2]
@@ -101,10 +107,11 @@ def test_autotune_cache(tmp_path):
     # second system of the same shape: values from the cache, no timing
     s2, _, _, _ = _selected(n_dets=1 << 14, H=256)
     again = autotune.tune_system(s2, H, cache=autotune.TuneCache(path), reps=3)
-    for name, knob in (("lut_blocks", B.IRL_TUNE_LUT_BLOCKS), ("pull_blocks", B.IRL_TUNE_PULL_BLOCKS)):
+    for name, knob in names:
         assert again[name]["cached"] and again[name]["value"] == first[name]["value"]
         assert B.irl_tune_get(s2.handle, knob, H)[0] == first[name]["value"]
     # stored rows: the pull knob no longer applies and is not tuned
     s2.store_hamiltonian(1 << 34)
     assert not B.irl_tune_get(s2.handle, B.IRL_TUNE_PULL_BLOCKS)[1]
+    assert not B.irl_tune_get(s2.handle, B.IRL_TUNE_PULL_WAVES)[1]
     assert set(autotune.tune_system(s2, H, cache=autotune.TuneCache(path), reps=3)) == {"lut_blocks"}
