@@ -141,19 +141,28 @@ constexpr int kMaxSingles = 256;   // n <= 32: na * (n - na) <= 256
 constexpr int kScanFactor = IRL_SCAN_FACTOR;   // scan a block when it holds <= this many times the candidates it replaces
 constexpr int kMaxPairs = 496;     // C(32, 2)
 
-struct WaveLists {
-    uint32_t sA[kMaxSingles];      // i | a << 5 | (sign < 0) << 10
-    uint32_t sAstr[kMaxSingles];
-    uint32_t sB[kMaxSingles];
-    uint32_t sBstr[kMaxSingles];
-    uint16_t poA[kMaxPairs], pvA[kMaxPairs], poB[kMaxPairs], pvB[kMaxPairs];  // i | j << 8
-    int32_t sBlo[kMaxSingles], sBhi[kMaxSingles];   // blocked lookup: rows of each beta single's target
-    int32_t own_lo, own_hi;                         // blocked lookup: rows sharing this row's beta
-    int32_t alo, ahi;                               // blocked lookup: alpha-major rows sharing its alpha
+// one wavefront's lists in LDS, for at most MS single moves and MP orbital pairs per spin
+template <int MS, int MP>
+struct WaveListsT {
+    uint32_t sA[MS];      // i | a << 5 | (sign < 0) << 10
+    uint32_t sAstr[MS];
+    uint32_t sB[MS];
+    uint32_t sBstr[MS];
+    uint16_t poA[MP], pvA[MP], poB[MP], pvB[MP];  // i | j << 8
+    int32_t sBlo[MS], sBhi[MS];   // blocked lookup: rows of each beta single's target
+    int32_t own_lo, own_hi;       // blocked lookup: rows sharing this row's beta
+    int32_t alo, ahi;             // blocked lookup: alpha-major rows sharing its alpha
 };
+using WaveLists = WaveListsT<kMaxSingles, kMaxPairs>;   // any n <= 32 (10 KiB)
+// n <= 20: na (n - na) <= 100 single moves and C(n, 2) <= 190 pairs.  At 4.5 KiB
+// per wavefront the enumerating kernel's LDS no longer limits it to 4 wavefronts
+// per SIMD.
+constexpr int kSmallListsMaxN = 20;
+using WaveListsSmall = WaveListsT<128, 192>;
 
 // blocked lookup: row ranges of the beta-single targets and of the row's own beta
-__device__ void build_block_ranges(const HamArgs &A, WaveLists &L, uint32_t al, uint32_t be, int lane)
+template <class WL>
+__device__ void build_block_ranges(const HamArgs &A, WL &L, uint32_t al, uint32_t be, int lane)
 {
     const int cnt = A.nb * (A.n - A.nb);
     for (int f = lane; f < cnt; f += kWave) {
@@ -235,8 +244,8 @@ __device__ __forceinline__ void scan4(int64_t lo, int64_t hi, int lane, int stri
 
 // Evaluate the candidates of one determinant on one lane (stride 64).  OP is
 // called with (target row, sign, kind, value) for every target inside the set.
-template <int LK, typename OP>
-__device__ __forceinline__ void visit_row(const HamArgs &A, const WaveLists &L, uint32_t al,
+template <int LK, typename OP, class WL>
+__device__ __forceinline__ void visit_row(const HamArgs &A, const WL &L, uint32_t al,
                                           uint32_t be, int lane, int stride, OP op)
 {
     const int n = A.n, na = A.na, nb = A.nb, va = n - na, vb = n - nb;
@@ -415,8 +424,8 @@ __device__ __forceinline__ void visit_row(const HamArgs &A, const WaveLists &L, 
 // one determinant row on one wavefront: u[row] = H_rr w[row] + sum of the row's connections
 // lists of one row's single moves and pairs (and, for the blocked lookup, the
 // row ranges of its beta-single targets), written by the 64 lanes of its wave
-template <int LK>
-__device__ __forceinline__ void prepare_row(const HamArgs &A, WaveLists &L, uint32_t al, uint32_t be,
+template <int LK, class WL>
+__device__ __forceinline__ void prepare_row(const HamArgs &A, WL &L, uint32_t al, uint32_t be,
                                             int lane)
 {
     build_lists(al, A.n, A.na, L.sA, L.sAstr, L.poA, L.pvA, lane);
@@ -439,8 +448,8 @@ __device__ __forceinline__ void end_row()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <int LK>
-__device__ __forceinline__ void pull_row(const HamArgs &A, WaveLists &L, int64_t row, int lane,
+template <int LK, class WL>
+__device__ __forceinline__ void pull_row(const HamArgs &A, WL &L, int64_t row, int lane,
                                          const double *__restrict__ w, double *__restrict__ u)
 {
     uint64_t key = A.keys[row];
@@ -455,29 +464,39 @@ __device__ __forceinline__ void pull_row(const HamArgs &A, WaveLists &L, int64_t
 }
 
 // rows [r0, r1), one wavefront per row, NW wavefronts per workgroup, grid-stride
-template <int LK, int NW = 4>
+template <int LK, int NW = 4, class WL = WaveLists>
 __global__ __launch_bounds__(64 * NW) void k_ham_pull(HamArgs A, const double *__restrict__ w,
                                                       double *__restrict__ u, int64_t r0, int64_t r1)
 {
-    __shared__ WaveLists lists[NW];
+    __shared__ WL lists[NW];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t nwaves = (int64_t)gridDim.x * NW;
     for (int64_t row = r0 + (int64_t)blockIdx.x * NW + wv; row < r1; row += nwaves)
         pull_row<LK>(A, lists[wv], row, lane, w, u);
 }
 
-template <int LK>
-static void launch_pull(const HamArgs &A, const double *w, double *u, int64_t r0, int64_t r1, int nw, int64_t cap,
-                        hipStream_t st)
+template <int LK, class WL>
+static void launch_pull_lists(const HamArgs &A, const double *w, double *u, int64_t r0, int64_t r1, int nw,
+                              int64_t cap, hipStream_t st)
 {
     int64_t blocks = (r1 - r0 + nw - 1) / nw;
     if (blocks > cap) blocks = cap;
     if (nw == 1)
-        k_ham_pull<LK, 1><<<(unsigned)blocks, 64, 0, st>>>(A, w, u, r0, r1);
+        k_ham_pull<LK, 1, WL><<<(unsigned)blocks, 64, 0, st>>>(A, w, u, r0, r1);
     else if (nw == 2)
-        k_ham_pull<LK, 2><<<(unsigned)blocks, 128, 0, st>>>(A, w, u, r0, r1);
+        k_ham_pull<LK, 2, WL><<<(unsigned)blocks, 128, 0, st>>>(A, w, u, r0, r1);
     else
-        k_ham_pull<LK, 4><<<(unsigned)blocks, 256, 0, st>>>(A, w, u, r0, r1);
+        k_ham_pull<LK, 4, WL><<<(unsigned)blocks, 256, 0, st>>>(A, w, u, r0, r1);
+}
+
+template <int LK>
+static void launch_pull(const HamArgs &A, const double *w, double *u, int64_t r0, int64_t r1, int nw, int64_t cap,
+                        hipStream_t st)
+{
+    if (A.n <= kSmallListsMaxN)
+        launch_pull_lists<LK, WaveListsSmall>(A, w, u, r0, r1, nw, cap, st);
+    else
+        launch_pull_lists<LK, WaveLists>(A, w, u, r0, r1, nw, cap, st);
 }
 
 // Stored rows: u[row] = diag * w[row] + sum_p val[p] w[col[p]], one wave per row.
