@@ -647,10 +647,10 @@ __global__ __launch_bounds__(256) void k_ham_fill(HamArgs A, const int64_t *__re
 // padding past its end), as a 16-bit target inside the slice and an FP64 value.
 
 // first pass: connections of each row inside each slice (count[b ns + row])
-template <int LK>
+template <int LK, class WL>
 __global__ __launch_bounds__(256) void k_ham_count_sliced(HamArgs A, int scs, int scb, uint32_t *__restrict__ count)
 {
-    __shared__ WaveLists lists[4];
+    __shared__ WL lists[4];
     __shared__ uint32_t cnt[4][kMaxSlices];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t nwaves = (int64_t)gridDim.x * 4;
@@ -683,44 +683,48 @@ __host__ __device__ __forceinline__ int64_t sell_col_slot(int64_t j, int64_t lan
 }
 
 // second pass, one wavefront per workgroup: each lane counts its own connections
-// per slice (LDS table [lane][slice]), an exclusive scan over the lanes gives each
+// per slice (LDS table [lane][slice], sized for the set's slices at launch, with an
+// odd row stride so that the lanes' entries of one slice fall in distinct banks),
+// an exclusive scan over the lanes gives each
 // lane's first position j in the row's run of each slice, and a second enumeration
 // writes element j of (slice b, row) to slots sell_val_slot / sell_col_slot (j, lane) of the row's group
 // and lane (slot[b][row] = group * 64 + lane): the layout, and so the apply's
 // summation order, are fixed by the set.
-template <int LK>
-__global__ __launch_bounds__(64) void k_ham_fill_sliced(HamArgs A, int scs, int scb, const int64_t *__restrict__ sbase,
+template <int LK, class WL>
+__global__ __launch_bounds__(64) void k_ham_fill_sliced(HamArgs A, int scs, int scb, int cs,
+                                                        const int64_t *__restrict__ sbase,
                                                         const uint32_t *__restrict__ sgbase, int sgroups,
                                                         const uint16_t *__restrict__ sglen,
                                                         const uint32_t *__restrict__ slot,
                                                         uint16_t *__restrict__ scol, double *__restrict__ sval)
 {
-    __shared__ WaveLists lists;
-    __shared__ uint32_t cnt[kWave][kMaxSlices];
+    __shared__ WL lists;
+    extern __shared__ uint32_t cnt_tab[];   // [kWave][cs], cs >= scb
+    auto cnt = [&](int l, int b) -> uint32_t & { return cnt_tab[l * cs + b]; };
     const int lane = threadIdx.x;
     const uint32_t mask = (1u << scs) - 1u;
     for (int64_t row = blockIdx.x; row < A.ns; row += gridDim.x) {
-        for (int b = 0; b < scb; ++b) cnt[lane][b] = 0u;
+        for (int b = 0; b < scb; ++b) cnt(lane, b) = 0u;
         const uint64_t key = A.keys[row];
         const uint32_t al = (uint32_t)key, be = (uint32_t)(key >> 32);
         prepare_row<LK>(A, lists, al, be, lane);
         visit_row<LK>(A, lists, al, be, lane, kWave, [&](int64_t r, int, int, double) {
-            ++cnt[lane][(int)(r >> scs)];
+            ++cnt(lane, (int)(r >> scs));
         });
         end_row();
         // lane b (and b + 64, ...) turns column b of the table into first positions
         for (int b = lane; b < scb; b += kWave) {
             uint32_t run = 0u;
             for (int l = 0; l < kWave; ++l) {
-                const uint32_t c = cnt[l][b];
-                cnt[l][b] = run;
+                const uint32_t c = cnt(l, b);
+                cnt(l, b) = run;
                 run += c;
             }
         }
         end_row();
         visit_row<LK>(A, lists, al, be, lane, kWave, [&](int64_t r, int, int, double v) {
             const int b = (int)(r >> scs);
-            const uint32_t j = cnt[lane][b]++;
+            const uint32_t j = cnt(lane, b)++;
             const uint32_t sl = slot[(int64_t)b * A.ns + row];
             const int64_t g = (int64_t)b * sgroups + (sl >> 6);
             if (j < sglen[g]) {
@@ -738,13 +742,28 @@ hipError_t launch_ham_count_sliced(const irl_system *s, int scs, int scb, uint32
     HamArgs A = ham_view(s);
     int64_t blocks = (s->ns + 3) / 4;
     if (blocks > 65536) blocks = 65536;
-    if (s->lookup == kLkBlocks)
-        k_ham_count_sliced<kLkBlocks><<<(unsigned)blocks, 256, 0, st>>>(A, scs, scb, count);
-    else if (s->lookup == kLkHash)
-        k_ham_count_sliced<kLkHash><<<(unsigned)blocks, 256, 0, st>>>(A, scs, scb, count);
-    else
-        k_ham_count_sliced<kLkRanks><<<(unsigned)blocks, 256, 0, st>>>(A, scs, scb, count);
+    if (scb < 1 || scb > kMaxSlices) return hipErrorInvalidValue;
+    const bool small = s->n <= kSmallListsMaxN;
+    if (s->lookup == kLkBlocks) {
+        if (small) k_ham_count_sliced<kLkBlocks, WaveListsSmall><<<(unsigned)blocks, 256, 0, st>>>(A, scs, scb, count);
+        else k_ham_count_sliced<kLkBlocks, WaveLists><<<(unsigned)blocks, 256, 0, st>>>(A, scs, scb, count);
+    } else if (s->lookup == kLkHash) {
+        if (small) k_ham_count_sliced<kLkHash, WaveListsSmall><<<(unsigned)blocks, 256, 0, st>>>(A, scs, scb, count);
+        else k_ham_count_sliced<kLkHash, WaveLists><<<(unsigned)blocks, 256, 0, st>>>(A, scs, scb, count);
+    } else {
+        if (small) k_ham_count_sliced<kLkRanks, WaveListsSmall><<<(unsigned)blocks, 256, 0, st>>>(A, scs, scb, count);
+        else k_ham_count_sliced<kLkRanks, WaveLists><<<(unsigned)blocks, 256, 0, st>>>(A, scs, scb, count);
+    }
     return hipGetLastError();
+}
+
+template <int LK, class WL>
+static void launch_fill_sliced_lists(const irl_system *s, const HamArgs &A, int64_t blocks, int scs, int scb, int cs,
+                                     const uint32_t *slot, uint16_t *scol, double *sval, hipStream_t st)
+{
+    const size_t lds = (size_t)kWave * cs * sizeof(uint32_t);
+    k_ham_fill_sliced<LK, WL><<<(unsigned)blocks, 64, lds, st>>>(A, scs, scb, cs, s->d.sbase, s->d.sgbase,
+                                                                 s->d.sgroups, s->d.sglen, slot, scol, sval);
 }
 
 hipError_t launch_ham_fill_sliced(const irl_system *s, int scs, int scb, const uint32_t *slot, uint16_t *scol,
@@ -753,16 +772,20 @@ hipError_t launch_ham_fill_sliced(const irl_system *s, int scs, int scb, const u
     HamArgs A = ham_view(s);
     int64_t blocks = s->ns;
     if (blocks > 262144) blocks = 262144;
-    const int G = s->d.sgroups;
-    if (s->lookup == kLkBlocks)
-        k_ham_fill_sliced<kLkBlocks><<<(unsigned)blocks, 64, 0, st>>>(A, scs, scb, s->d.sbase, s->d.sgbase, G,
-                                                                     s->d.sglen, slot, scol, sval);
-    else if (s->lookup == kLkHash)
-        k_ham_fill_sliced<kLkHash><<<(unsigned)blocks, 64, 0, st>>>(A, scs, scb, s->d.sbase, s->d.sgbase, G,
-                                                                   s->d.sglen, slot, scol, sval);
-    else
-        k_ham_fill_sliced<kLkRanks><<<(unsigned)blocks, 64, 0, st>>>(A, scs, scb, s->d.sbase, s->d.sgbase, G,
-                                                                    s->d.sglen, slot, scol, sval);
+    if (scb < 1 || scb > kMaxSlices) return hipErrorInvalidValue;
+    // odd row stride of the per-lane count table while it stays within 64 KiB
+    const int cs = (scb | 1) * kWave * 4 <= 65536 ? (scb | 1) : scb;
+    const bool small = s->n <= kSmallListsMaxN;
+    if (s->lookup == kLkBlocks) {
+        if (small) launch_fill_sliced_lists<kLkBlocks, WaveListsSmall>(s, A, blocks, scs, scb, cs, slot, scol, sval, st);
+        else launch_fill_sliced_lists<kLkBlocks, WaveLists>(s, A, blocks, scs, scb, cs, slot, scol, sval, st);
+    } else if (s->lookup == kLkHash) {
+        if (small) launch_fill_sliced_lists<kLkHash, WaveListsSmall>(s, A, blocks, scs, scb, cs, slot, scol, sval, st);
+        else launch_fill_sliced_lists<kLkHash, WaveLists>(s, A, blocks, scs, scb, cs, slot, scol, sval, st);
+    } else {
+        if (small) launch_fill_sliced_lists<kLkRanks, WaveListsSmall>(s, A, blocks, scs, scb, cs, slot, scol, sval, st);
+        else launch_fill_sliced_lists<kLkRanks, WaveLists>(s, A, blocks, scs, scb, cs, slot, scol, sval, st);
+    }
     return hipGetLastError();
 }
 
