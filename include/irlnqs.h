@@ -563,7 +563,7 @@ enum irl_tune_knob {
                                    (hashed, rank or beta-blocked pull, one row per
                                    wavefront in grid strides); default 2^20 */
     IRL_TUNE_PULL_WAVES = 2     /* wavefronts (rows) per workgroup of that apply: 1, 2
-                                   or 4; default 4 */
+                                   or 4; default 1 for n <= 20, else 4 */
 };
 
 /* Set `knob` of `sys` to `value` (0 restores the default).  Takes effect at the

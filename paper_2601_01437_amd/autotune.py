@@ -27,7 +27,7 @@ from . import binding as B
 KNOBS = {
     B.IRL_TUNE_LUT_BLOCKS: ("lut_blocks", "gemv", (0, 128, 512, 1024, 2048)),
     B.IRL_TUNE_PULL_BLOCKS: ("pull_blocks", "ham_apply", (0, 8192, 32768, 131072)),
-    B.IRL_TUNE_PULL_WAVES: ("pull_waves", "ham_apply", (0, 1, 2)),
+    B.IRL_TUNE_PULL_WAVES: ("pull_waves", "ham_apply", (0, 1, 2, 4)),
 }
 
 

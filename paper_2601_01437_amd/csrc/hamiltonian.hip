@@ -463,9 +463,11 @@ __device__ __forceinline__ void pull_row(const HamArgs &A, WL &L, int64_t row, i
     end_row();
 }
 
-// rows [r0, r1), one wavefront per row, NW wavefronts per workgroup, grid-stride
+// rows [r0, r1), one wavefront per row, NW wavefronts per workgroup, grid-stride.
+// With the small lists, LDS allows 8 wavefronts per SIMD; the launch bound asks the
+// compiler for registers to match (some scalar registers then live in vector lanes).
 template <int LK, int NW = 4, class WL = WaveLists>
-__global__ __launch_bounds__(64 * NW) void k_ham_pull(HamArgs A, const double *__restrict__ w,
+__global__ __launch_bounds__(64 * NW, sizeof(WL) <= 8192 ? 8 : 4) void k_ham_pull(HamArgs A, const double *__restrict__ w,
                                                       double *__restrict__ u, int64_t r0, int64_t r1)
 {
     __shared__ WL lists[NW];
@@ -1142,8 +1144,9 @@ hipError_t launch_ham_apply_rows(const irl_system *s, const double *w, double *u
         return hipSuccess;
     }
     // wavefronts (rows) per workgroup of the enumerating kernels (tunable; one row
-    // per wavefront whatever the count)
-    const int nw = s->tune_pull_waves > 0 ? s->tune_pull_waves : 4;
+    // per wavefront whatever the count).  Default: one with the small lists (c3:
+    // 57.2 ms against 59.3 with four), four with the large ones
+    const int nw = s->tune_pull_waves > 0 ? s->tune_pull_waves : (s->n <= kSmallListsMaxN ? 1 : 4);
     if (s->lookup == kLkBlocks)
         launch_pull<kLkBlocks>(A, w, u, r0, r1, nw, cap, st);
     else if (s->lookup == kLkHash)

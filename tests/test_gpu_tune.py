@@ -47,7 +47,7 @@ def test_knobs_are_bit_neutral():
     g0 = host(g0)
     yH0, yS0 = (host(t) for t in s.apply(v))
     for knob, (name, _, cands) in autotune.KNOBS.items():
-        extra = (4,) if knob == B.IRL_TUNE_PULL_WAVES else (1, 7, 157)
+        extra = () if knob == B.IRL_TUNE_PULL_WAVES else (1, 7, 157)
         for c in cands + extra:
             announce(f"knob {name} = {c}")
             B.irl_tune_set(s.handle, knob, c)
