@@ -100,7 +100,9 @@ def _time_applies(system, v, kind, reps):
 def tune_system(system, hidden, cache=None, reps=5, seed=0, device_name=None):
     """Choose every applicable knob of `system` (a System whose workspace holds an
     evaluation of a network with `hidden` units).  Returns {knob name: {"value",
-    "cached", "timings"}}; knobs the system's kernels do not use are left unset."""
+    "cached", "timings"}}; knobs the system's kernels do not use are left unset.
+    Timing uses the system's kernel statistics: they are cleared, and left off and
+    selecting every kind, when the call returns."""
     import torch
 
     cache = cache if cache is not None else TuneCache(None)
