@@ -1824,6 +1824,7 @@ struct irl_batch {
     WorkItem *hitems = nullptr;   // pinned staging
     size_t hcap = 0;
     MemberScalars *dscal = nullptr, *hscal = nullptr;
+    int max_n = 0;   // largest orbital count among the members
 };
 
 namespace {
@@ -2008,7 +2009,7 @@ int batch_apply(irl_batch *b, const ListSet &ls, int vsel, int j, int cur, int s
         if (ls.cnt[k])
             TIMED(s0, IRL_STAT_HAM_APPLY, st,
                   launch_ham_pull_grouped(b->dm, ls.ptr(b, k), ls.cnt[k], ls.blocks[k], 0,
-                                          k == LS_ROWS4R ? kLkRanks : (k == LS_ROWS4H ? kLkHash : kLkBlocks), st));
+                                          k == LS_ROWS4R ? kLkRanks : (k == LS_ROWS4H ? kLkHash : kLkBlocks), b->max_n, st));
     if (ls.cnt[LS_ROWS4S])
         TIMED(s0, IRL_STAT_HAM_APPLY, st, launch_ham_stored_grouped(b->dm, ls.ptr(b, LS_ROWS4S), ls.cnt[LS_ROWS4S], ls.blocks[LS_ROWS4S], 0, st));
     for (int m : ls.product) TIMED(s0, IRL_STAT_HAM_APPLY, st, launch_ham_apply(b->sys[m], b->hm[m].w, b->hm[m].u, st));
@@ -2062,7 +2063,7 @@ int batch_evaluate(irl_batch *b, const std::vector<int> &subset, hipStream_t st)
         if (ls.cnt[k])
             TIMED(s0, IRL_STAT_HAM_APPLY, st,
                   launch_ham_pull_grouped(b->dm, ls.ptr(b, k), ls.cnt[k], ls.blocks[k], 1,
-                                          k == LS_ROWS4R ? kLkRanks : (k == LS_ROWS4H ? kLkHash : kLkBlocks), st));
+                                          k == LS_ROWS4R ? kLkRanks : (k == LS_ROWS4H ? kLkHash : kLkBlocks), b->max_n, st));
     if (ls.cnt[LS_ROWS4S])
         TIMED(s0, IRL_STAT_HAM_APPLY, st, launch_ham_stored_grouped(b->dm, ls.ptr(b, LS_ROWS4S), ls.cnt[LS_ROWS4S], ls.blocks[LS_ROWS4S], 1, st));
     for (int m : ls.product) TIMED(s0, IRL_STAT_HAM_APPLY, st, launch_ham_apply(b->sys[m], b->hm[m].psi, b->hm[m].hpsi, st));
@@ -2275,6 +2276,7 @@ int irl_batch_create(int32_t count, irl_system *const *systems, const irl_nqs_de
         if (L.ldv > 8192) { delete b; return set_err(nullptr, IRL_EINVAL, "batch members need P + 1 <= 8192"); }
         if (!ws[i] || reinterpret_cast<uintptr_t>(ws[i]) % 256 || ws_bytes[i] < L.total) { delete b; return set_err(nullptr, IRL_ENOMEM, "batch workspace missing or too small for member " + std::to_string(i)); }
         b->sys.push_back(s);
+        b->max_n = std::max(b->max_n, (int)s->n);
         b->lay.push_back(L);
         b->ws.push_back(ws[i]);
         b->ws_bytes.push_back(ws_bytes[i]);

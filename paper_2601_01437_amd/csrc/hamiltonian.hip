@@ -1015,12 +1015,11 @@ __device__ __forceinline__ int find_item(const WorkItem *__restrict__ items, int
     return lo;
 }
 
-template <int LK>
-__global__ __launch_bounds__(256) void k_ham_pull_grouped(const Member *__restrict__ M,
-                                                          const WorkItem *__restrict__ items,
-                                                          int nitems, int which)
+template <int LK, class WL>
+__global__ __launch_bounds__(256, sizeof(WL) <= 8192 ? 8 : 4) void k_ham_pull_grouped(
+    const Member *__restrict__ M, const WorkItem *__restrict__ items, int nitems, int which)
 {
-    __shared__ WaveLists lists[4];
+    __shared__ WL lists[4];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const WorkItem it = items[find_item(items, nitems, (int)blockIdx.x)];
     const Member &mb = M[it.m];
@@ -1052,15 +1051,26 @@ hipError_t launch_ham_stored_grouped(const Member *M, const WorkItem *items, int
 }
 
 hipError_t launch_ham_pull_grouped(const Member *M, const WorkItem *items, int nitems,
-                                   int64_t nblocks, int which, int lookup, hipStream_t st)
+                                   int64_t nblocks, int which, int lookup, int max_n, hipStream_t st)
 {
     if (nitems <= 0 || nblocks <= 0) return hipSuccess;
-    if (lookup == kLkBlocks)
-        k_ham_pull_grouped<kLkBlocks><<<(unsigned)nblocks, 256, 0, st>>>(M, items, nitems, which);
-    else if (lookup == kLkHash)
-        k_ham_pull_grouped<kLkHash><<<(unsigned)nblocks, 256, 0, st>>>(M, items, nitems, which);
-    else
-        k_ham_pull_grouped<kLkRanks><<<(unsigned)nblocks, 256, 0, st>>>(M, items, nitems, which);
+    // small lists when every member has n <= 20 (the same sums: only LDS sizes differ)
+    if (lookup == kLkBlocks) {
+        if (max_n <= kSmallListsMaxN)
+            k_ham_pull_grouped<kLkBlocks, WaveListsSmall><<<(unsigned)nblocks, 256, 0, st>>>(M, items, nitems, which);
+        else
+            k_ham_pull_grouped<kLkBlocks, WaveLists><<<(unsigned)nblocks, 256, 0, st>>>(M, items, nitems, which);
+    } else if (lookup == kLkHash) {
+        if (max_n <= kSmallListsMaxN)
+            k_ham_pull_grouped<kLkHash, WaveListsSmall><<<(unsigned)nblocks, 256, 0, st>>>(M, items, nitems, which);
+        else
+            k_ham_pull_grouped<kLkHash, WaveLists><<<(unsigned)nblocks, 256, 0, st>>>(M, items, nitems, which);
+    } else {
+        if (max_n <= kSmallListsMaxN)
+            k_ham_pull_grouped<kLkRanks, WaveListsSmall><<<(unsigned)nblocks, 256, 0, st>>>(M, items, nitems, which);
+        else
+            k_ham_pull_grouped<kLkRanks, WaveLists><<<(unsigned)nblocks, 256, 0, st>>>(M, items, nitems, which);
+    }
     return hipGetLastError();
 }
 

@@ -312,8 +312,9 @@ void free_dense_doubles(irl_system *s);
 HamView ham_view(const irl_system *s);
 hipError_t launch_ham_stored_grouped(const Member *M, const WorkItem *items, int nitems,
                                      int64_t nblocks, int which, hipStream_t st);
+// max_n: the largest orbital count among the members the items cover
 hipError_t launch_ham_pull_grouped(const Member *M, const WorkItem *items, int nitems,
-                                   int64_t nblocks, int which, int lookup, hipStream_t st);
+                                   int64_t nblocks, int which, int lookup, int max_n, hipStream_t st);
 hipError_t launch_ham_apply(const irl_system *s, const double *w, double *u, hipStream_t st);
 // rows [r0, r1) of u = H w (r0, r1 multiples of ham_row_quantum: whole beta strings
 // for the string-product kernel)
